@@ -1,0 +1,421 @@
+/*
+ * FP64 CPU oracle for the finite-difference acoustic propagation path.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may call, link or
+ * load this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline do. It shares no code with the HIP library.
+ *
+ * What it computes (paper: section 2.1 eq. 1-2, section 2.2 eq. 5-12b,
+ * section 2.3 eq. 13-15). The paper states the continuous equations only;
+ * the discrete scheme written out here is this project's reading of them:
+ *
+ *   padded grid   NZ = nz + 2 nb, NX = wnx + 2 nb per shot window, zero
+ *                 values outside the padded box (Dirichlet halo);
+ *   model         V = Pad(v): edge replication of the shot's window;
+ *   Laplacian     L8 u = h^-2 (2 c0 u + sum_k c_k (u[i+-k][j] + u[i][j+-k])),
+ *                 c = (-205/72, 8/5, -1/5, 8/315, -1/560);
+ *   sponge        sigma = smax (dz^2 + dx^2), dz = distance into the sponge
+ *                 / nb, smax = 3 v_ref ln(1/R) / (2 nb h);
+ *                 a = 1/(1 + sigma dt/2), b = (1 - sigma dt/2) a;
+ *   source        s^n = w[n] / h^2 at the source cell;
+ *   time step     u^{n+1} = a (2 u^n + V^2 dt^2 (L8 u^n + s^n)) - b u^{n-1},
+ *                 u^{-1} = u^0 = 0  (eq. 1, leapfrog, damped in the sponge);
+ *   receivers     d[r][n] = u^{n+1}[rz][rx];
+ *   misfit        phi = 1/2 sum (d - d_obs)^2   (eq. 2).
+ *
+ *   Born (eq. 9-11, solved jointly as the paper notes; velocity
+ *   parametrisation, exact derivative of the discrete forward map):
+ *                 rho = 2 Pad(dv) / V,
+ *                 du^{n+1} = a (2 du^n + V^2 dt^2 (L8 du^n + rho (L8 u^n + s^n)))
+ *                            - b du^{n-1},  dd[r][n] = du^{n+1}[rz][rx].
+ *
+ *   Adjoint (eq. 13; exact transpose of the Born map):
+ *                 lam^n = a (2 lam^{n+1} + V^2 dt^2 (L8 lam^{n+1} + R^T r^n))
+ *                         - b lam^{n+2},  n = nt-1 .. 0, lam^{nt} = lam^{nt+1} = 0,
+ *                 img = sum_shots Pad^T( (2/V) sum_n lam^n (L8 u^n + s^n) ),
+ *                 where R^T adds r[r][n] at receiver cells and Pad^T sums
+ *                 every sponge cell onto the edge cell it replicates.
+ *
+ * Every function below works on one shot at a time; shots are independent
+ * and run in an OpenMP loop, and per-shot images are summed in shot order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int nz, nx, nb;
+    double h, dt, v_ref, R;
+} og_grid;
+
+typedef struct {
+    int nshots;
+    const int *src_z, *src_x;
+    const int *win_x0, *win_nx; /* NULL: full width */
+    const int *nt;              /* NULL: nt_max for every shot */
+    int nt_max;
+    const int64_t *rec_ptr;
+    const int *rec_z, *rec_x;
+    const double *wavelet;      /* [nt_max] shared, or [nshots][nt_max] */
+    int wavelet_shared;
+} og_geom;
+
+/* 8th-order central second-derivative weights (Fornberg 1988). */
+static const double C8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0,
+                             8.0 / 315.0, -1.0 / 560.0};
+
+/* ------------------------------------------------------------------ */
+/* per-shot padded domain                                              */
+
+typedef struct {
+    int NZ, NX, x0, wnx;
+    double *V;   /* padded velocity */
+    double *c;   /* V^2 dt^2 */
+    double *a, *b;
+} shot_dom;
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+static void shot_window(const og_grid *g, const og_geom *geo, int s, int *x0, int *wnx)
+{
+    if (geo->win_x0) { *x0 = geo->win_x0[s]; *wnx = geo->win_nx[s]; }
+    else { *x0 = 0; *wnx = g->nx; }
+}
+
+static int shot_nt(const og_geom *geo, int s) { return geo->nt ? geo->nt[s] : geo->nt_max; }
+
+static const double *shot_wavelet(const og_geom *geo, int s)
+{
+    return geo->wavelet_shared ? geo->wavelet : geo->wavelet + (int64_t)s * geo->nt_max;
+}
+
+/* Pad: edge replication of the window [x0, x0+wnx) of the nz x nx model. */
+static void pad_model(const og_grid *g, int x0, int wnx, const double *v, double *V)
+{
+    int NZ = g->nz + 2 * g->nb, NX = wnx + 2 * g->nb;
+    for (int i = 0; i < NZ; i++)
+        for (int j = 0; j < NX; j++) {
+            int pi = clampi(i - g->nb, 0, g->nz - 1);
+            int pj = x0 + clampi(j - g->nb, 0, wnx - 1);
+            V[(int64_t)i * NX + j] = v[(int64_t)pi * g->nx + pj];
+        }
+}
+
+/* Pad^T: every padded cell adds onto the physical cell it was copied from. */
+static void pad_adjoint_add(const og_grid *g, int x0, int wnx, const double *P, double *img)
+{
+    int NZ = g->nz + 2 * g->nb, NX = wnx + 2 * g->nb;
+    for (int i = 0; i < NZ; i++)
+        for (int j = 0; j < NX; j++) {
+            int pi = clampi(i - g->nb, 0, g->nz - 1);
+            int pj = x0 + clampi(j - g->nb, 0, wnx - 1);
+            img[(int64_t)pi * g->nx + pj] += P[(int64_t)i * NX + j];
+        }
+}
+
+static double sponge_depth(int i, int n, int nb)
+{
+    /* distance (in cells, / nb) into the sponge along one axis */
+    int d = 0;
+    if (i < nb) d = nb - i;
+    if (i > n - 1 - nb) d = i - (n - 1 - nb);
+    return nb > 0 ? (double)d / (double)nb : 0.0;
+}
+
+static int dom_init(shot_dom *D, const og_grid *g, const og_geom *geo, int s, const double *v)
+{
+    shot_window(g, geo, s, &D->x0, &D->wnx);
+    D->NZ = g->nz + 2 * g->nb;
+    D->NX = D->wnx + 2 * g->nb;
+    int64_t n = (int64_t)D->NZ * D->NX;
+    D->V = malloc(n * sizeof(double));
+    D->c = malloc(n * sizeof(double));
+    D->a = malloc(n * sizeof(double));
+    D->b = malloc(n * sizeof(double));
+    if (!D->V || !D->c || !D->a || !D->b) return -1;
+    pad_model(g, D->x0, D->wnx, v, D->V);
+    double smax = g->nb > 0 ? 3.0 * g->v_ref * log(1.0 / g->R) / (2.0 * g->nb * g->h) : 0.0;
+    for (int i = 0; i < D->NZ; i++)
+        for (int j = 0; j < D->NX; j++) {
+            int64_t k = (int64_t)i * D->NX + j;
+            double dz = sponge_depth(i, D->NZ, g->nb), dx = sponge_depth(j, D->NX, g->nb);
+            double sig = smax * (dz * dz + dx * dx);
+            D->a[k] = 1.0 / (1.0 + 0.5 * sig * g->dt);
+            D->b[k] = (1.0 - 0.5 * sig * g->dt) / (1.0 + 0.5 * sig * g->dt);
+            D->c[k] = D->V[k] * D->V[k] * g->dt * g->dt;
+        }
+    return 0;
+}
+
+static void dom_free(shot_dom *D)
+{
+    free(D->V); free(D->c); free(D->a); free(D->b);
+}
+
+/* L8 u with zero values outside the NZ x NX box. */
+static void laplacian8(const double *u, int NZ, int NX, double h, double *out)
+{
+    double ih2 = 1.0 / (h * h);
+    for (int i = 0; i < NZ; i++)
+        for (int j = 0; j < NX; j++) {
+            double acc = 2.0 * C8[0] * u[(int64_t)i * NX + j];
+            for (int k = 1; k <= 4; k++) {
+                if (i - k >= 0) acc += C8[k] * u[(int64_t)(i - k) * NX + j];
+                if (i + k < NZ) acc += C8[k] * u[(int64_t)(i + k) * NX + j];
+                if (j - k >= 0) acc += C8[k] * u[(int64_t)i * NX + j - k];
+                if (j + k < NX) acc += C8[k] * u[(int64_t)i * NX + j + k];
+            }
+            out[(int64_t)i * NX + j] = acc * ih2;
+        }
+}
+
+/* padded index of a physical cell (z, x) of shot s */
+static int64_t cell_index(const og_grid *g, const shot_dom *D, int z, int x)
+{
+    return (int64_t)(z + g->nb) * D->NX + (x - D->x0 + g->nb);
+}
+
+/* ------------------------------------------------------------------ */
+/* one shot                                                            */
+
+/* Forward modelling of shot s. d_shot is [nrec][nt]. If hist != NULL it
+ * receives u^n for n = 0 .. nt ([nt+1][NZ][NX]). */
+static int forward_shot(const og_grid *g, const og_geom *geo, int s, const shot_dom *D,
+                        double *d_shot, double *hist)
+{
+    int nt = shot_nt(geo, s);
+    int64_t n = (int64_t)D->NZ * D->NX;
+    double *um = calloc(n, sizeof(double)), *u0 = calloc(n, sizeof(double));
+    double *up = calloc(n, sizeof(double)), *lap = malloc(n * sizeof(double));
+    if (!um || !u0 || !up || !lap) { free(um); free(u0); free(up); free(lap); return -1; }
+    const double *w = shot_wavelet(geo, s);
+    int64_t src = cell_index(g, D, geo->src_z[s], geo->src_x[s]);
+    int64_t r0 = geo->rec_ptr[s], nrec = geo->rec_ptr[s + 1] - r0;
+    double ih2 = 1.0 / (g->h * g->h);
+    for (int t = 0; t < nt; t++) {
+        if (hist) memcpy(hist + (int64_t)t * n, u0, n * sizeof(double));
+        laplacian8(u0, D->NZ, D->NX, g->h, lap);
+        lap[src] += w[t] * ih2;
+        for (int64_t k = 0; k < n; k++)
+            up[k] = D->a[k] * (2.0 * u0[k] + D->c[k] * lap[k]) - D->b[k] * um[k];
+        for (int64_t r = 0; r < nrec; r++)
+            d_shot[r * nt + t] = up[cell_index(g, D, geo->rec_z[r0 + r], geo->rec_x[r0 + r])];
+        double *tmp = um; um = u0; u0 = up; up = tmp;
+    }
+    if (hist) memcpy(hist + (int64_t)nt * n, u0, n * sizeof(double));
+    free(um); free(u0); free(up); free(lap);
+    return 0;
+}
+
+/* Born modelling of shot s: dd_shot = J_s dv, [nrec][nt]. */
+static int born_shot(const og_grid *g, const og_geom *geo, int s, const shot_dom *D,
+                     const double *dv, double *dd_shot)
+{
+    int nt = shot_nt(geo, s);
+    int64_t n = (int64_t)D->NZ * D->NX;
+    double *um = calloc(n, sizeof(double)), *u0 = calloc(n, sizeof(double));
+    double *up = calloc(n, sizeof(double)), *lap = malloc(n * sizeof(double));
+    double *dm = calloc(n, sizeof(double)), *d0 = calloc(n, sizeof(double));
+    double *dp = calloc(n, sizeof(double)), *dlap = malloc(n * sizeof(double));
+    double *rho = malloc(n * sizeof(double));
+    int ok = um && u0 && up && lap && dm && d0 && dp && dlap && rho;
+    if (ok) {
+        pad_model(g, D->x0, D->wnx, dv, rho);            /* Pad(dv) */
+        for (int64_t k = 0; k < n; k++) rho[k] = 2.0 * rho[k] / D->V[k];
+        const double *w = shot_wavelet(geo, s);
+        int64_t src = cell_index(g, D, geo->src_z[s], geo->src_x[s]);
+        int64_t r0 = geo->rec_ptr[s], nrec = geo->rec_ptr[s + 1] - r0;
+        double ih2 = 1.0 / (g->h * g->h);
+        for (int t = 0; t < nt; t++) {
+            laplacian8(u0, D->NZ, D->NX, g->h, lap);
+            lap[src] += w[t] * ih2;                       /* L8 u^n + s^n */
+            laplacian8(d0, D->NZ, D->NX, g->h, dlap);
+            for (int64_t k = 0; k < n; k++) {
+                dp[k] = D->a[k] * (2.0 * d0[k] + D->c[k] * (dlap[k] + rho[k] * lap[k]))
+                        - D->b[k] * dm[k];
+                up[k] = D->a[k] * (2.0 * u0[k] + D->c[k] * lap[k]) - D->b[k] * um[k];
+            }
+            for (int64_t r = 0; r < nrec; r++)
+                dd_shot[r * nt + t] = dp[cell_index(g, D, geo->rec_z[r0 + r], geo->rec_x[r0 + r])];
+            double *tmp = um; um = u0; u0 = up; up = tmp;
+            tmp = dm; dm = d0; d0 = dp; dp = tmp;
+        }
+    }
+    free(um); free(u0); free(up); free(lap); free(dm); free(d0); free(dp); free(dlap); free(rho);
+    return ok ? 0 : -1;
+}
+
+/* Adjoint of shot s: adds Pad^T((2/V) sum_n lam^n (L8 u^n + s^n)) to img.
+ * res_shot is [nrec][nt]. If lam_hist != NULL it receives lam^n for
+ * n = 0..nt-1 ([nt][NZ][NX]). */
+static int adjoint_shot(const og_grid *g, const og_geom *geo, int s, const shot_dom *D,
+                        const double *res_shot, double *img, double *lam_hist)
+{
+    int nt = shot_nt(geo, s);
+    int64_t n = (int64_t)D->NZ * D->NX;
+    double *hist = malloc((size_t)(nt + 1) * n * sizeof(double));
+    double *dummy = malloc(((geo->rec_ptr[s + 1] - geo->rec_ptr[s]) * (int64_t)nt + 1) * sizeof(double));
+    double *l1 = calloc(n, sizeof(double)), *l2 = calloc(n, sizeof(double));
+    double *l0 = calloc(n, sizeof(double)), *lap = malloc(n * sizeof(double));
+    double *lu = malloc(n * sizeof(double)), *G = calloc(n, sizeof(double));
+    int ok = hist && dummy && l1 && l2 && l0 && lap && lu && G;
+    if (ok) ok = forward_shot(g, geo, s, D, dummy, hist) == 0;
+    if (ok) {
+        const double *w = shot_wavelet(geo, s);
+        int64_t src = cell_index(g, D, geo->src_z[s], geo->src_x[s]);
+        int64_t r0 = geo->rec_ptr[s], nrec = geo->rec_ptr[s + 1] - r0;
+        double ih2 = 1.0 / (g->h * g->h);
+        for (int t = nt - 1; t >= 0; t--) {
+            laplacian8(l1, D->NZ, D->NX, g->h, lap);    /* L8 lam^{n+1} */
+            for (int64_t r = 0; r < nrec; r++)            /* + R^T r^n */
+                lap[cell_index(g, D, geo->rec_z[r0 + r], geo->rec_x[r0 + r])] += res_shot[r * nt + t];
+            for (int64_t k = 0; k < n; k++)
+                l0[k] = D->a[k] * (2.0 * l1[k] + D->c[k] * lap[k]) - D->b[k] * l2[k];
+            if (lam_hist) memcpy(lam_hist + (int64_t)t * n, l0, n * sizeof(double));
+            laplacian8(hist + (int64_t)t * n, D->NZ, D->NX, g->h, lu);
+            lu[src] += w[t] * ih2;                        /* L8 u^n + s^n */
+            for (int64_t k = 0; k < n; k++) G[k] += l0[k] * lu[k];
+            double *tmp = l2; l2 = l1; l1 = l0; l0 = tmp;
+        }
+        for (int64_t k = 0; k < n; k++) G[k] *= 2.0 / D->V[k];
+        pad_adjoint_add(g, D->x0, D->wnx, G, img);
+    }
+    free(hist); free(dummy); free(l1); free(l2); free(l0); free(lap); free(lu); free(G);
+    return ok ? 0 : -1;
+}
+
+/* ------------------------------------------------------------------ */
+/* public entry points (ctypes)                                        */
+
+static int64_t shot_data_offset(const og_geom *geo, int s)
+{
+    int64_t off = 0;
+    for (int q = 0; q < s; q++) off += (geo->rec_ptr[q + 1] - geo->rec_ptr[q]) * (int64_t)shot_nt(geo, q);
+    return off;
+}
+
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+/* d = F(v), packed traces. */
+int oracle_forward(const og_grid *g, const og_geom *geo, const double *v, double *d)
+{
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int s = 0; s < geo->nshots; s++) {
+        shot_dom D;
+        if (dom_init(&D, g, geo, s, v)) { err |= 1; dom_free(&D); continue; }
+        err |= forward_shot(g, geo, s, &D, d + shot_data_offset(geo, s), NULL) ? 1 : 0;
+        dom_free(&D);
+    }
+    return err ? -1 : 0;
+}
+
+/* dd = J dv. */
+int oracle_born_demig(const og_grid *g, const og_geom *geo, const double *v, const double *dv, double *dd)
+{
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int s = 0; s < geo->nshots; s++) {
+        shot_dom D;
+        if (dom_init(&D, g, geo, s, v)) { err |= 1; dom_free(&D); continue; }
+        err |= born_shot(g, geo, s, &D, dv, dd + shot_data_offset(geo, s)) ? 1 : 0;
+        dom_free(&D);
+    }
+    return err ? -1 : 0;
+}
+
+/* img = J^T r (shot images summed in shot order). */
+int oracle_born_mig(const og_grid *g, const og_geom *geo, const double *v, const double *r, double *img)
+{
+    int64_t npix = (int64_t)g->nz * g->nx;
+    double *per = calloc((size_t)geo->nshots * npix + 1, sizeof(double));
+    if (!per) return -1;
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int s = 0; s < geo->nshots; s++) {
+        shot_dom D;
+        if (dom_init(&D, g, geo, s, v)) { err |= 1; dom_free(&D); continue; }
+        err |= adjoint_shot(g, geo, s, &D, r + shot_data_offset(geo, s), per + s * npix, NULL) ? 1 : 0;
+        dom_free(&D);
+    }
+    memset(img, 0, npix * sizeof(double));
+    for (int s = 0; s < geo->nshots; s++)
+        for (int64_t k = 0; k < npix; k++) img[k] += per[s * npix + k];
+    free(per);
+    return err ? -1 : 0;
+}
+
+/* g = J^T (F(v) - d_obs), misfit = 1/2 ||F(v) - d_obs||^2; d_syn optional. */
+int oracle_gradient(const og_grid *g, const og_geom *geo, const double *v, const double *d_obs,
+                    double *grad, double *misfit, double *d_syn)
+{
+    int64_t nd = shot_data_offset(geo, geo->nshots);
+    double *d = malloc((nd + 1) * sizeof(double));
+    if (!d) return -1;
+    int err = oracle_forward(g, geo, v, d);
+    double phi = 0.0;
+    for (int64_t k = 0; k < nd; k++) {
+        d[k] -= d_obs[k];
+        phi += 0.5 * d[k] * d[k];
+    }
+    if (misfit) *misfit = phi;
+    if (d_syn)
+        for (int64_t k = 0; k < nd; k++) d_syn[k] = d[k] + d_obs[k];
+    if (!err) err = oracle_born_mig(g, geo, v, d, grad);
+    free(d);
+    return err;
+}
+
+/* Wavefield histories of one shot, for identity tests:
+ * u_hist [nt+1][NZ][NX] receives u^0 .. u^nt; lam_hist (nullable)
+ * [nt][NZ][NX] receives lam^0 .. lam^{nt-1} for the residual res_shot
+ * ([nrec][nt]); a_out, b_out, c_out (nullable) receive the padded sponge
+ * coefficients and V^2 dt^2. */
+int oracle_shot_fields(const og_grid *g, const og_geom *geo, int s, const double *v,
+                       const double *res_shot, double *u_hist, double *lam_hist,
+                       double *a_out, double *b_out, double *c_out)
+{
+    shot_dom D;
+    if (dom_init(&D, g, geo, s, v)) { dom_free(&D); return -1; }
+    int nt = shot_nt(geo, s);
+    int64_t n = (int64_t)D.NZ * D.NX;
+    int64_t nrec = geo->rec_ptr[s + 1] - geo->rec_ptr[s];
+    double *d = malloc((nrec * nt + 1) * sizeof(double));
+    double *img = calloc((int64_t)g->nz * g->nx, sizeof(double));
+    int err = (!d || !img) ? -1 : 0;
+    if (!err) err = forward_shot(g, geo, s, &D, d, u_hist);
+    if (!err && lam_hist) err = adjoint_shot(g, geo, s, &D, res_shot, img, lam_hist);
+    if (a_out) memcpy(a_out, D.a, n * sizeof(double));
+    if (b_out) memcpy(b_out, D.b, n * sizeof(double));
+    if (c_out) memcpy(c_out, D.c, n * sizeof(double));
+    free(d); free(img);
+    dom_free(&D);
+    return err;
+}
+
+/* Pad and Pad^T of one window, exported so that tests can check the
+ * adjoint pair <Pad x, y> = <x, Pad^T y> directly. P is [nz+2nb][wnx+2nb]. */
+void oracle_pad(const og_grid *g, int x0, int wnx, const double *v, double *P)
+{
+    pad_model(g, x0, wnx, v, P);
+}
+
+void oracle_pad_adjoint(const og_grid *g, int x0, int wnx, const double *P, double *img)
+{
+    memset(img, 0, (size_t)g->nz * g->nx * sizeof(double));
+    pad_adjoint_add(g, x0, wnx, P, img);
+}
