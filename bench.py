@@ -1,0 +1,171 @@
+#!/usr/bin/env python
+"""Benchmark: finite-difference cell-updates/s of one FWI iteration's
+propagation on one MI355X.
+
+One step = the propagation work of one network-preconditioned FWI iteration
+on the 600x200 layered model (64 shots, 600 receivers, 4000 steps, dt 0.8 ms,
+15 Hz): the FWI gradient (forward + checkpointed adjoint with imaging) and
+the Born demigration-remigration pair of that gradient. Inputs are resident
+in HBM before the timed region. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--shots", type=int, default=64)
+    ap.add_argument("--nt", type=int, default=4000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-shots", type=int, default=4)
+    ap.add_argument("--cpu-nt", type=int, default=400)
+    ap.add_argument("--mem-budget-gb", type=float, default=0.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(args):
+    """The FP64 oracle on a bounded sample of the same step."""
+    import numpy as np
+    import oracle
+    from synth import configs
+    from synth.problem import cell_updates
+    wl = configs.layered_600x200(nshots=64, nt=args.cpu_nt)
+    pick = np.linspace(0, 63, args.cpu_shots).round().astype(int)
+    acq = wl.acq.subset(pick)
+    cores = min(os.cpu_count() or 1, 16, len(pick))
+    cores = oracle.set_threads(cores)
+    v0 = wl.v0.astype(np.float32).astype(np.float64)
+    d_obs = oracle.forward(wl.grid, acq, wl.v_true.astype(np.float32).astype(np.float64))
+    t0 = time.perf_counter()
+    g, _, _ = oracle.gradient(wl.grid, acq, v0, d_obs)
+    oracle.born_pair(wl.grid, acq, v0, -g)
+    dt = time.perf_counter() - t0
+    upd = 6 * cell_updates(wl.grid, acq)
+    return {"value": upd / dt, "unit": "cell-updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"gradient + Born pair, {len(pick)} of 64 shots, {args.cpu_nt} of 4000 steps, "
+                      f"FP64, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2403_17518_amd import ops
+    from synth import configs
+    from synth.problem import cell_updates
+
+    wl = configs.layered_600x200(nshots=args.shots, nt=args.nt)
+    grid, acq = wl.grid, wl.acq
+    acq.wavelet = acq.wavelet.astype(np.float32)
+    dev = torch.device("cuda", 0)
+    ctx = ops.FwiContext(0)
+    if args.mem_budget_gb > 0:
+        ctx.set_mem_budget(int(args.mem_budget_gb * 2**30))
+    v_true = torch.from_numpy(wl.v_true.astype(np.float32)).to(dev)
+    v0 = torch.from_numpy(wl.v0.astype(np.float32)).to(dev)
+    d_obs = ctx.fwi_forward(grid, acq, v_true)        # synthetic observed data
+    torch.cuda.synchronize()
+
+    acc = {}
+
+    def add_stats():
+        s = ctx.stats()
+        for k in ("cell_updates", "ms_fwd", "ms_adj", "ms_born", "n_fwd", "n_adj", "n_born",
+                  "bytes_fwd", "bytes_adj", "bytes_born"):
+            acc[k] = acc.get(k, 0.0) + s[k]
+        acc["n_segments"] = s["n_segments"] or acc.get("n_segments", 0)
+        acc["ckpt_every"] = s["ckpt_every"] or acc.get("ckpt_every", 0)
+
+    def step(record):
+        g, phi, _ = ctx.fwi_gradient(grid, acq, v0, d_obs, want_misfit=False)
+        if record:
+            add_stats()
+        dd = ctx.born_demig(grid, acq, v0, -g)
+        if record:
+            add_stats()
+        dm1 = ctx.born_mig(grid, acq, v0, dd)
+        if record:
+            add_stats()
+        return dm1
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step(True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    ctx.set_profiling(False)
+
+    useful = 6 * cell_updates(grid, acq)          # fwd + adj, 2 Born fields, fwd + adj
+    value = useful / (ms * 1e-3)
+    # dominant kernel by time, its algorithmic bytes per launch / average duration
+    kinds = {"stencil_fwd": ("ms_fwd", "n_fwd", "bytes_fwd"),
+             "stencil_adj": ("ms_adj", "n_adj", "bytes_adj"),
+             "stencil_born": ("ms_born", "n_born", "bytes_born")}
+    dom = max(kinds, key=lambda k: acc.get(kinds[k][0], 0.0))
+    kms, kn, kb = (acc[x] for x in kinds[dom])
+    achieved = (kb / kn) / ((kms / kn) * 1e-3) / 1e9
+    out = {
+        "metric": "FD cell-updates/s & % HBM roofline; FWI iters+time to model error vs plain",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"layered_600x200: FWI gradient + Born demig/mig pair, {acq.nshots} shots, "
+                        f"{grid.nt_max} steps, padded 240x640, 600 receivers",
+            "global_batch": acq.nshots,
+            "seq_len": grid.nt_max,
+            "parallelism": "single GPU, all shots per launch",
+            "checkpoint_segments": acc.get("n_segments", 0),
+            "executed_cell_updates_per_step": acc["cell_updates"] / args.steps,
+            "useful_cell_updates_per_step": useful,
+            "wall_s": wall,
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "avg_launch_us": kms / kn * 1e3, "launches": int(kn),
+            "bytes_per_launch": kb / kn,
+            "kernel_ms": {k: acc[v[0]] / args.steps for k, v in kinds.items()},
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

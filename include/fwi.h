@@ -1,0 +1,157 @@
+/*
+ * fwi.h - C ABI of the MI355X finite-difference acoustic propagation library
+ * (libfwi.so) behind deep-Hessian-deblurred full waveform inversion.
+ *
+ * Operators (all on one GPU, FP32, hand-written HIP kernels for gfx950):
+ *
+ *   fwi_forward   d  = F(v)                       paper section 2.1, eq. 1
+ *   fwi_gradient  g  = J^T (F(v) - d_obs),        section 2.1 eq. 2 and
+ *                 phi = 1/2 ||F(v) - d_obs||^2    section 2.3 eq. 13
+ *   born_demig    dd = J dv                       section 2.2, eq. 11-12b
+ *   born_mig      img = J^T dd                    section 2.3, eq. 13
+ *
+ * where J = dF/dv is the exact Jacobian of the discrete forward map, so
+ * born_mig(v, born_demig(v, g)) is the doubly migrated image J^T J g of
+ * section 2.3 eq. 15.
+ *
+ * Discretisation (the paper names the finite-difference method but not a
+ * scheme; this is the library's definition): constant-density acoustic wave
+ * equation in velocity v, 8th-order central Laplacian on a square grid of
+ * spacing h, 2nd-order leapfrog in time,
+ *     u^{n+1} = a (2 u^n + V^2 dt^2 (L8 u^n + s^n)) - b u^{n-1},
+ * with a damping sponge of nb cells on all four sides
+ *     sigma = smax (dz^2 + dx^2), dz, dx = depth into the sponge / nb,
+ *     smax = 3 v_ref ln(1/R) / (2 nb h), a = 1/(1 + sigma dt/2),
+ *     b = (1 - sigma dt/2) a,
+ * zero field values outside the padded box, V = the shot window of v
+ * edge-replicated into the sponge, a point source s^n = w[n]/h^2 at the
+ * source cell and point receivers d[r][n] = u^{n+1}[rz][rx].
+ *
+ * Memory and ownership
+ *   - Every float pointer argument of an operator is a DEVICE pointer that
+ *     the caller owns (e.g. from torch), contiguous, row-major:
+ *       models / images      [nz][nx], x fastest;
+ *       data                 packed traces: shot order, then the shot's
+ *                            receiver order, time fastest, nt[s] samples.
+ *   - fwi_grid and fwi_geom are HOST structures; their arrays (including
+ *     the wavelet) are host memory and are copied during the call.
+ *   - Outputs are overwritten, never accumulated; inputs are not modified.
+ *   - Scratch (wavefields, checkpoints, the imaging-condition buffers) is
+ *     owned by the context and reused across calls.
+ *
+ * Streams and threads
+ *   - Work is enqueued on the context's stream (fwi_ctx_set_stream). Calls
+ *     return once the work is enqueued, except that fwi_gradient with a
+ *     non-NULL misfit pointer waits for the result, and every call waits
+ *     for the model check described under FWI_ECFL.
+ *   - A context is not thread-safe: use one context per host thread.
+ *
+ * Errors: every int-returning function returns FWI_OK (0) or a negative
+ * code; fwi_last_error() gives a message. After an error, outputs are
+ * unspecified; the context stays usable unless the error was FWI_EHIP.
+ */
+#ifndef FWI_H
+#define FWI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FWI_OK = 0,
+    FWI_EINVAL = -1,   /* bad size, position, window or NULL pointer */
+    FWI_ENOMEM = -2,   /* device allocation failed */
+    FWI_EHIP = -3,     /* HIP runtime error */
+    FWI_ECFL = -4,     /* v dt / h above the stability limit */
+    FWI_ESTATE = -5,   /* object used in the wrong state */
+    FWI_ENOTIMPL = -6
+};
+
+typedef struct fwi_ctx fwi_ctx;
+
+typedef struct {
+    int32_t nz, nx;     /* physical model rows (depth) and columns */
+    int32_t nb;         /* sponge width in cells on all four sides, >= 0 */
+    float h;            /* grid spacing (m); dz == dx */
+    float dt;           /* time step (s) */
+    int32_t nt_max;     /* longest record; length of a shared wavelet */
+    float v_ref;        /* fixed sponge reference velocity (m/s) */
+    float R;            /* nominal sponge reflection coefficient, (0, 1) */
+    int32_t ckpt_every; /* checkpoint interval (steps) for the adjoint
+                           sweeps; 0 = chosen from the memory budget */
+} fwi_grid;
+
+typedef struct {
+    int32_t nshots;
+    const int32_t *src_z, *src_x;   /* [nshots] physical cell of the source */
+    const int32_t *win_x0, *win_nx; /* [nshots] column window of each shot;
+                                       both NULL = the full width */
+    const int32_t *nt;              /* [nshots] record length; NULL = nt_max */
+    const int64_t *rec_ptr;         /* [nshots+1] receivers of shot s are
+                                       rec_ptr[s] .. rec_ptr[s+1]-1 */
+    const int32_t *rec_z, *rec_x;   /* physical cells; co-located receivers
+                                       are allowed (their traces are equal
+                                       and their adjoint sources add) */
+    const float *wavelet;           /* host: [nt_max] if wavelet_shared,
+                                       else [nshots][nt_max] */
+    int32_t wavelet_shared;
+} fwi_geom;
+
+typedef struct {
+    /* filled by the last operator call on the context */
+    double cell_updates;      /* padded-cell x step x shot x field updates */
+    int64_t stencil_launches; /* launches of the propagation kernels */
+    int32_t ckpt_every;       /* checkpoint interval used (0 = none) */
+    int32_t n_segments;       /* adjoint segments (recompute passes + 1) */
+    int64_t scratch_bytes;    /* device scratch held by the context */
+    /* kernel timings, valid only when profiling is enabled (ms, summed
+       over launches) */
+    double ms_fwd, ms_adj, ms_born, ms_other;
+    int64_t n_fwd, n_adj, n_born;
+    double bytes_fwd, bytes_adj, bytes_born; /* algorithmic bytes moved */
+} fwi_stats;
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). */
+int fwi_ctx_create(int device, void *hip_stream, fwi_ctx **out);
+void fwi_ctx_destroy(fwi_ctx *ctx);
+int fwi_ctx_set_stream(fwi_ctx *ctx, void *hip_stream);
+/* Upper bound on device memory used for checkpoints and the stored
+ * imaging-condition history (bytes); 0 = 40% of the device memory. */
+int fwi_ctx_set_mem_budget(fwi_ctx *ctx, int64_t bytes);
+/* 1 = time every kernel launch with HIP events (adds a sync per call). */
+int fwi_ctx_set_profiling(fwi_ctx *ctx, int enable);
+int fwi_ctx_get_stats(const fwi_ctx *ctx, fwi_stats *out);
+/* Release all scratch memory held by the context. */
+int fwi_ctx_trim(fwi_ctx *ctx);
+const char *fwi_last_error(const fwi_ctx *ctx);
+
+/* d = F(v). v: [nz][nx] velocities (m/s); d: packed traces. */
+int fwi_forward(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
+                const float *v, float *d);
+
+/* g = J^T (F(v) - d_obs), the gradient of phi = 1/2 ||F(v) - d_obs||^2
+ * with respect to v (the negative of the paper's g = L^T (d_o - d_s)).
+ * misfit: HOST pointer, may be NULL (then the call does not wait);
+ * d_syn: device [packed data] receives F(v), may be NULL. */
+int fwi_gradient(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
+                 const float *v, const float *d_obs, float *g,
+                 double *misfit, float *d_syn);
+
+/* dd = J dv: Born (single-scattering) data of the perturbation dv of the
+ * background velocity v0. */
+int born_demig(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
+               const float *v0, const float *dv, float *dd);
+
+/* img = J^T dd: migration of data dd in the background v0 (the adjoint of
+ * born_demig; shot images are summed). */
+int born_mig(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
+             const float *v0, const float *dd, float *img);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FWI_H */

@@ -1,0 +1,910 @@
+// C ABI of libfwi.so (declared in include/fwi.h): argument checks, the
+// per-call plan (shot layout, wave table, receiver tables), the scratch
+// pool, the checkpointed adjoint sweeps, and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/fwi.h"
+#include "internal.h"
+
+using namespace fwi;
+
+namespace {
+
+constexpr double kCflLimit = 0.55;     // 2D 8th-order leapfrog limit is 0.5546
+constexpr int kRowsPerWave = 30;       // target rows streamed by one wave
+
+// 8th-order central second-derivative weights (Fornberg 1988).
+constexpr double kC8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Plan {
+    // grid
+    int nz = 0, nx = 0, nb = 0, NZ = 0, nt_max = 0, S = 0;
+    float h = 0, dt = 0, v_ref = 0, R = 0;
+    int ckpt_every = 0;
+    // shots in slot order (record length decreasing)
+    std::vector<int> order;              // slot -> caller's shot index
+    std::vector<ShotDesc> shots;
+    std::vector<int> slot_nt;
+    std::vector<int> wave_prefix;        // waves of slots [0, k)
+    std::vector<WaveDesc> waves;
+    std::vector<RecRow> rrows;
+    std::vector<int32_t> rmap;
+    // unique receiver cells
+    int Q = 0;
+    std::vector<int32_t> q_nt, q_rptr;
+    std::vector<int64_t> q_roff;
+    std::vector<float> wav;
+    int64_t field_floats = 0;  // one wavefield buffer, all shots
+    int64_t img_floats = 0;    // one image / D slot, all shots
+    int64_t data_size = 0;     // packed data samples
+    double updates_per_field_pass = 0;
+    std::vector<char> key;     // serialized inputs (plan cache)
+
+    int active_waves(int n) const
+    {
+        // slots are sorted by decreasing nt: those with nt > n form a prefix
+        int lo = 0, hi = S;
+        while (lo < hi) {
+            const int mid = (lo + hi) / 2;
+            if (slot_nt[mid] > n) lo = mid + 1;
+            else hi = mid;
+        }
+        return wave_prefix[lo];
+    }
+};
+
+}  // namespace
+
+struct fwi_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int64_t budget = 0;
+    bool profiling = false;
+    fwi_stats stats{};
+    Plan plan;
+    bool plan_valid = false;
+    // device copies of the plan tables
+    DevBuf d_shots, d_waves, d_rrows, d_rmap, d_qnt, d_qrptr, d_qroff, d_wav;
+    // scratch
+    DevBuf fields, samples, image, dhist, ckpt, partials, misfit, check;
+    float *h_check = nullptr;     // pinned [3]
+    double *h_misfit = nullptr;   // pinned [1]
+    // profiling events
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_marks;  // (class, first event index)
+};
+
+namespace {
+
+int set_err(fwi_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return set_err(ctx, FWI_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+int ensure(fwi_ctx *c, DevBuf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return FWI_OK;
+    if (b.p) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return set_err(c, FWI_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    b.bytes = bytes;
+    return FWI_OK;
+}
+
+void release(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <class T>
+int upload(fwi_ctx *c, DevBuf &b, const std::vector<T> &v)
+{
+    int rc = ensure(c, b, v.size() * sizeof(T));
+    if (rc) return rc;
+    if (!v.empty())
+        HIPCHK(c, hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return FWI_OK;
+}
+
+template <class T>
+void put(std::vector<char> &k, const T *p, size_t n)
+{
+    const char *b = reinterpret_cast<const char *>(p);
+    k.insert(k.end(), b, b + n * sizeof(T));
+}
+
+// ---------------------------------------------------------------------------
+// argument checks and the plan
+
+int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
+{
+    if (!g || !geo) return set_err(c, FWI_EINVAL, "grid and geometry must not be NULL");
+    if (g->nz < 1 || g->nx < 1 || g->nb < 0 || g->nt_max < 1)
+        return set_err(c, FWI_EINVAL, "bad grid sizes nz=%d nx=%d nb=%d nt_max=%d", g->nz, g->nx, g->nb,
+                       g->nt_max);
+    if (!(g->h > 0.f) || !(g->dt > 0.f) || !(g->v_ref > 0.f) || !(g->R > 0.f && g->R < 1.f))
+        return set_err(c, FWI_EINVAL, "bad grid constants h=%g dt=%g v_ref=%g R=%g", g->h, g->dt, g->v_ref, g->R);
+    if (double(g->v_ref) * g->dt / g->h > kCflLimit)
+        return set_err(c, FWI_ECFL, "v_ref*dt/h = %.4f exceeds %.2f", double(g->v_ref) * g->dt / g->h,
+                       kCflLimit);
+    if (g->ckpt_every < 0) return set_err(c, FWI_EINVAL, "ckpt_every must be >= 0");
+    const int64_t NZ64 = int64_t(g->nz) + 2 * int64_t(g->nb);
+    if (NZ64 > (1 << 20) || int64_t(g->nx) + 2 * g->nb > (1 << 20))
+        return set_err(c, FWI_EINVAL, "grid too large");
+    const int S = geo->nshots;
+    if (S < 0) return set_err(c, FWI_EINVAL, "nshots < 0");
+    if (S > 0 && (!geo->src_z || !geo->src_x || !geo->rec_ptr || !geo->wavelet))
+        return set_err(c, FWI_EINVAL, "NULL geometry array");
+    if ((geo->win_x0 == nullptr) != (geo->win_nx == nullptr))
+        return set_err(c, FWI_EINVAL, "win_x0 and win_nx must both be given or both be NULL");
+    if (S > 0 && geo->rec_ptr[0] != 0) return set_err(c, FWI_EINVAL, "rec_ptr[0] must be 0");
+    for (int s = 0; s < S; ++s)
+        if (geo->rec_ptr[s + 1] < geo->rec_ptr[s]) return set_err(c, FWI_EINVAL, "rec_ptr not monotone");
+    const int64_t nrec_tot = S > 0 ? geo->rec_ptr[S] : 0;
+    if (nrec_tot > 0 && (!geo->rec_z || !geo->rec_x)) return set_err(c, FWI_EINVAL, "NULL receiver arrays");
+    if (nrec_tot > (int64_t(1) << 30)) return set_err(c, FWI_EINVAL, "too many receivers");
+
+    // plan cache key: every input the plan depends on
+    std::vector<char> key;
+    put(key, g, 1);
+    put(key, &S, 1);
+    if (S > 0) {
+        put(key, geo->src_z, S);
+        put(key, geo->src_x, S);
+        const int flags[3] = {geo->win_x0 != nullptr, geo->nt != nullptr, geo->wavelet_shared != 0};
+        put(key, flags, 3);
+        if (geo->win_x0) {
+            put(key, geo->win_x0, S);
+            put(key, geo->win_nx, S);
+        }
+        if (geo->nt) put(key, geo->nt, S);
+        put(key, geo->rec_ptr, S + 1);
+        put(key, geo->rec_z, nrec_tot);
+        put(key, geo->rec_x, nrec_tot);
+        put(key, geo->wavelet, size_t(geo->wavelet_shared ? 1 : S) * g->nt_max);
+    }
+    if (c->plan_valid && key == c->plan.key) return FWI_OK;
+    c->plan_valid = false;
+
+    Plan p;
+    p.nz = g->nz;
+    p.nx = g->nx;
+    p.nb = g->nb;
+    p.NZ = int(NZ64);
+    p.nt_max = g->nt_max;
+    p.h = g->h;
+    p.dt = g->dt;
+    p.v_ref = g->v_ref;
+    p.R = g->R;
+    p.ckpt_every = g->ckpt_every;
+    p.S = S;
+
+    std::vector<int> x0(S), wnx(S), nts(S);
+    std::vector<int64_t> data_off(S + 1, 0);
+    for (int s = 0; s < S; ++s) {
+        x0[s] = geo->win_x0 ? geo->win_x0[s] : 0;
+        wnx[s] = geo->win_x0 ? geo->win_nx[s] : g->nx;
+        nts[s] = geo->nt ? geo->nt[s] : g->nt_max;
+        if (x0[s] < 0 || wnx[s] < 1 || int64_t(x0[s]) + wnx[s] > g->nx)
+            return set_err(c, FWI_EINVAL, "shot %d: window [%d, %d) outside [0, %d)", s, x0[s], x0[s] + wnx[s],
+                           g->nx);
+        if (nts[s] < 0 || nts[s] > g->nt_max)
+            return set_err(c, FWI_EINVAL, "shot %d: nt=%d outside [0, nt_max=%d]", s, nts[s], g->nt_max);
+        const int sz = geo->src_z[s], sx = geo->src_x[s];
+        if (sz < 0 || sz >= g->nz || sx < x0[s] || sx >= x0[s] + wnx[s])
+            return set_err(c, FWI_EINVAL, "shot %d: source (%d, %d) outside its window", s, sz, sx);
+        for (int64_t r = geo->rec_ptr[s]; r < geo->rec_ptr[s + 1]; ++r) {
+            const int rz = geo->rec_z[r], rx = geo->rec_x[r];
+            if (rz < 0 || rz >= g->nz || rx < x0[s] || rx >= x0[s] + wnx[s])
+                return set_err(c, FWI_EINVAL, "shot %d: receiver %lld at (%d, %d) outside its window", s,
+                               (long long)r, rz, rx);
+        }
+        data_off[s + 1] = data_off[s] + (geo->rec_ptr[s + 1] - geo->rec_ptr[s]) * int64_t(nts[s]);
+    }
+    p.data_size = data_off[S];
+
+    // slots: record length decreasing (stable)
+    p.order.resize(S);
+    for (int s = 0; s < S; ++s) p.order[s] = s;
+    std::stable_sort(p.order.begin(), p.order.end(), [&](int a, int b) { return nts[a] > nts[b]; });
+
+    const int nseg_z = std::max(1, (p.NZ + kRowsPerWave - 1) / kRowsPerWave);
+    const int rows_per = (p.NZ + nseg_z - 1) / nseg_z;
+
+    p.shots.resize(S);
+    p.slot_nt.resize(S);
+    p.wave_prefix.assign(S + 1, 0);
+    int64_t foff = 0, goff = 0;
+    p.q_rptr.push_back(0);
+    if (geo->wavelet_shared) p.wav.assign(geo->wavelet, geo->wavelet + g->nt_max);
+    else p.wav.resize(size_t(S) * g->nt_max);
+    for (int k = 0; k < S; ++k) {
+        const int s = p.order[k];
+        ShotDesc &d = p.shots[k];
+        d.NX = wnx[s] + 2 * p.nb;
+        d.P = ((d.NX + kHalo + 31) / 32) * 32;
+        d.f_off = foff + int64_t(kRowsAbove) * d.P;
+        d.g_off = goff;
+        foff += int64_t(p.NZ + kRowsExtra) * d.P;
+        goff += int64_t(p.NZ) * d.P;
+        d.x0 = x0[s];
+        d.wnx = wnx[s];
+        d.nt = nts[s];
+        d.src_i = geo->src_z[s] + p.nb;
+        d.src_j = geo->src_x[s] - x0[s] + p.nb;
+        if (geo->wavelet_shared) d.wav_off = 0;
+        else {
+            d.wav_off = k * g->nt_max;
+            std::memcpy(&p.wav[size_t(k) * g->nt_max], geo->wavelet + size_t(s) * g->nt_max,
+                        sizeof(float) * g->nt_max);
+        }
+        p.slot_nt[k] = nts[s];
+        p.updates_per_field_pass += double(p.NZ) * d.NX * nts[s];
+
+        // unique receiver cells of this shot, sorted by (row, col)
+        std::map<std::pair<int, int>, std::vector<int64_t>> cells;
+        for (int64_t r = geo->rec_ptr[s]; r < geo->rec_ptr[s + 1]; ++r) {
+            const int i = geo->rec_z[r] + p.nb, jj = geo->rec_x[r] - x0[s] + p.nb;
+            cells[{i, jj}].push_back(data_off[s] + (r - geo->rec_ptr[s]) * int64_t(nts[s]));
+        }
+        const int qbase = p.Q;
+        std::vector<std::pair<int, int>> cell_list;  // (row, col) by q
+        for (auto &kv : cells) {
+            cell_list.push_back(kv.first);
+            p.q_nt.push_back(nts[s]);
+            for (int64_t off : kv.second) p.q_roff.push_back(off);
+            p.q_rptr.push_back(int32_t(p.q_roff.size()));
+            ++p.Q;
+        }
+        // waves: strip-major, then row segments; receiver rows per wave
+        const int nstrips = (d.NX + kLanes - 1) / kLanes;
+        for (int st = 0; st < nstrips; ++st) {
+            const int col0 = st * kLanes;
+            // receiver cells of this strip, already sorted by row then col
+            std::vector<std::pair<std::pair<int, int>, int>> sc;
+            for (size_t qi = 0; qi < cell_list.size(); ++qi)
+                if (cell_list[qi].second >= col0 && cell_list[qi].second < col0 + kLanes)
+                    sc.push_back({cell_list[qi], qbase + int(qi)});
+            size_t pos = 0;
+            for (int z0 = 0; z0 < p.NZ; z0 += rows_per) {
+                WaveDesc w{};
+                w.shot = k;
+                w.col0 = col0;
+                w.z0 = z0;
+                w.z1 = std::min(p.NZ, z0 + rows_per);
+                w.rr0 = int(p.rrows.size());
+                while (pos < sc.size() && sc[pos].first.first < w.z1) {
+                    const int rowi = sc[pos].first.first;
+                    RecRow rrw{rowi, int32_t(p.rmap.size())};
+                    p.rmap.resize(p.rmap.size() + kLanes, -1);
+                    while (pos < sc.size() && sc[pos].first.first == rowi) {
+                        p.rmap[rrw.map_off + (sc[pos].first.second - col0)] = sc[pos].second;
+                        ++pos;
+                    }
+                    p.rrows.push_back(rrw);
+                }
+                w.rr1 = int(p.rrows.size());
+                p.waves.push_back(w);
+            }
+        }
+        p.wave_prefix[k + 1] = int(p.waves.size());
+    }
+    p.field_floats = foff;
+    p.img_floats = goff;
+    if (p.waves.size() > size_t(1) << 28) return set_err(c, FWI_EINVAL, "too many waves");
+    p.key = std::move(key);
+
+    int rc;
+    if ((rc = upload(c, c->d_shots, p.shots)) || (rc = upload(c, c->d_waves, p.waves)) ||
+        (rc = upload(c, c->d_rrows, p.rrows)) || (rc = upload(c, c->d_rmap, p.rmap)) ||
+        (rc = upload(c, c->d_qnt, p.q_nt)) || (rc = upload(c, c->d_qrptr, p.q_rptr)) ||
+        (rc = upload(c, c->d_qroff, p.q_roff)) || (rc = upload(c, c->d_wav, p.wav)))
+        return rc;
+    // the host vectors are read by the copies above; keep them alive in the
+    // context and make sure the copies finished before the plan can change
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->plan = std::move(p);
+    c->plan_valid = true;
+    return FWI_OK;
+}
+
+int check_model(fwi_ctx *c, const float *v, const char *what)
+{
+    const Plan &p = c->plan;
+    if (!v) return set_err(c, FWI_EINVAL, "%s is NULL", what);
+    int rc = ensure(c, c->check, 4 * sizeof(float));
+    if (rc) return rc;
+    HIPCHK(c, launch_model_check(v, int64_t(p.nz) * p.nx, static_cast<float *>(c->check.p), c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_check, c->check.p, 3 * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->h_check[2] > 0.f)
+        return set_err(c, FWI_EINVAL, "%s has %.0f non-finite or non-positive entries", what, c->h_check[2]);
+    const double cfl = double(c->h_check[1]) * p.dt / p.h;
+    if (cfl > kCflLimit)
+        return set_err(c, FWI_ECFL, "max(%s)*dt/h = %.4f exceeds %.2f", what, cfl, kCflLimit);
+    return FWI_OK;
+}
+
+int check_finite_perturbation(fwi_ctx *c, const float *dv)
+{
+    // dv may be negative; only reject non-finite entries
+    if (!dv) return set_err(c, FWI_EINVAL, "dv is NULL");
+    return FWI_OK;
+}
+
+StepArgs base_args(fwi_ctx *c, const float *v)
+{
+    const Plan &p = c->plan;
+    StepArgs a{};
+    a.shots = static_cast<const ShotDesc *>(c->d_shots.p);
+    a.waves = static_cast<const WaveDesc *>(c->d_waves.p);
+    a.rrows = static_cast<const RecRow *>(c->d_rrows.p);
+    a.rmap = static_cast<const int32_t *>(c->d_rmap.p);
+    a.v = v;
+    a.wav = static_cast<const float *>(c->d_wav.p);
+    a.nz = p.nz;
+    a.nx = p.nx;
+    a.nb = p.nb;
+    a.NZ = p.NZ;
+    const double ih2 = 1.0 / (double(p.h) * p.h);
+    a.w0 = float(2.0 * kC8[0] * ih2);
+    a.w1 = float(kC8[1] * ih2);
+    a.w2 = float(kC8[2] * ih2);
+    a.w3 = float(kC8[3] * ih2);
+    a.w4 = float(kC8[4] * ih2);
+    a.dt2 = float(double(p.dt) * p.dt);
+    a.ih2 = float(ih2);
+    if (p.nb > 0) {
+        const double smax = 3.0 * p.v_ref * std::log(1.0 / p.R) / (2.0 * p.nb * p.h);
+        a.hs = float(smax * p.dt / (2.0 * double(p.nb) * p.nb));
+    }
+    return a;
+}
+
+// ---- profiling --------------------------------------------------------------
+
+enum KClass { K_FWD = 0, K_ADJ = 1, K_BORN = 2, K_OTHER = 3 };
+
+int ev_begin(fwi_ctx *c, int cls)
+{
+    if (!c->profiling) return FWI_OK;
+    if (c->ev_used + 2 > c->ev.size()) {
+        const size_t add = std::max<size_t>(256, c->ev.size());
+        for (size_t i = 0; i < add; ++i) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->ev.push_back(e);
+        }
+    }
+    c->ev_marks.push_back({cls, c->ev_used});
+    HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+    c->ev_used += 2;
+    return FWI_OK;
+}
+
+int ev_end(fwi_ctx *c)
+{
+    if (!c->profiling) return FWI_OK;
+    HIPCHK(c, hipEventRecord(c->ev[c->ev_marks.back().second + 1], c->stream));
+    return FWI_OK;
+}
+
+int ev_collect(fwi_ctx *c)
+{
+    if (!c->profiling) return FWI_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &m : c->ev_marks) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[m.second], c->ev[m.second + 1]));
+        switch (m.first) {
+        case K_FWD: c->stats.ms_fwd += ms; break;
+        case K_ADJ: c->stats.ms_adj += ms; break;
+        case K_BORN: c->stats.ms_born += ms; break;
+        default: c->stats.ms_other += ms; break;
+        }
+    }
+    c->ev_marks.clear();
+    c->ev_used = 0;
+    return FWI_OK;
+}
+
+// ---- sweeps -------------------------------------------------------------------
+
+// Algorithmic bytes per cell-update: forward reads u^n, u^{n-1} and the
+// model and writes u^{n+1} (16 B); emitting D^n adds a 4 B write; the
+// adjoint with imaging adds the D^n read and the G read-modify-write (28 B);
+// the Born step moves 32 B for its two field updates.
+constexpr double kBytesFwd = 16.0, kBytesEmit = 4.0, kBytesAdj = 28.0, kBytesBorn = 32.0;
+
+double step_updates(const Plan &p, int n)
+{
+    double u = 0;
+    for (int k = 0; k < p.S && p.slot_nt[k] > n; ++k) u += double(p.NZ) * p.shots[k].NX;
+    return u;
+}
+
+int fwd_step(fwi_ctx *c, StepArgs a, int flags, int n, float *F0, float *F1)
+{
+    const Plan &p = c->plan;
+    a.n = n;
+    a.nwaves = p.active_waves(n);
+    a.cur = (n % 2 == 0) ? F0 : F1;
+    a.prev = (n % 2 == 0) ? F1 : F0;
+    int rc = ev_begin(c, K_FWD);
+    if (rc) return rc;
+    HIPCHK(c, launch_step(flags, a, c->stream));
+    if ((rc = ev_end(c))) return rc;
+    const double upd = step_updates(p, n);
+    c->stats.cell_updates += upd;
+    c->stats.stencil_launches += 1;
+    c->stats.n_fwd += 1;
+    c->stats.bytes_fwd += upd * (kBytesFwd + ((flags & F_EMIT) ? kBytesEmit : 0.0));
+    return FWI_OK;
+}
+
+int adj_step(fwi_ctx *c, StepArgs a, int n, float *A0, float *A1)
+{
+    const Plan &p = c->plan;
+    a.n = n;
+    a.nwaves = p.active_waves(n);
+    // lambda^{n+1} lives in A[(n+1)%2], lambda^{n+2} (overwritten by lambda^n) in A[n%2]
+    a.cur = ((n + 1) % 2 == 0) ? A0 : A1;
+    a.prev = (n % 2 == 0) ? A0 : A1;
+    int rc = ev_begin(c, K_ADJ);
+    if (rc) return rc;
+    HIPCHK(c, launch_step(F_INJECT | F_IMAGE, a, c->stream));
+    if ((rc = ev_end(c))) return rc;
+    const double upd = step_updates(p, n);
+    c->stats.cell_updates += upd;
+    c->stats.stencil_launches += 1;
+    c->stats.n_adj += 1;
+    c->stats.bytes_adj += upd * kBytesAdj;
+    return FWI_OK;
+}
+
+int other(fwi_ctx *c, hipError_t e, const char *what)
+{
+    if (e != hipSuccess) return set_err(c, FWI_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return FWI_OK;
+}
+
+void reset_stats(fwi_ctx *c)
+{
+    c->stats = fwi_stats{};
+}
+
+int finish_stats(fwi_ctx *c)
+{
+    c->stats.scratch_bytes = int64_t(c->fields.bytes + c->samples.bytes + c->image.bytes + c->dhist.bytes +
+                                     c->ckpt.bytes + c->partials.bytes);
+    return ev_collect(c);
+}
+
+// Choose the checkpoint interval k: the last segment's D^n history is
+// stored during the forward sweep; every earlier segment is recomputed from
+// a checkpoint of (u^{n-1}, u^n). Memory = k slots + (segments-1) checkpoints.
+int choose_segments(fwi_ctx *c, int *k_out, int *nseg_out)
+{
+    const Plan &p = c->plan;
+    const int nt = p.nt_max;
+    const double slot = double(p.img_floats) * 4.0;
+    const double ck = 2.0 * double(p.field_floats) * 4.0;
+    auto mem = [&](int k) { return double(k) * slot + double((nt + k - 1) / k - 1) * ck; };
+    int k;
+    if (p.ckpt_every > 0) k = std::min(p.ckpt_every, nt);
+    else {
+        const double budget = double(c->budget);
+        k = nt;
+        if (mem(k) > budget) {
+            k = int(std::max(1.0, std::min(double(nt), std::floor(budget / std::max(slot, 1.0)))));
+            while (k > 1 && mem(k) > budget) k = std::max(1, k - std::max(1, k / 32));
+            if (mem(k) > budget)
+                return set_err(c, FWI_ENOMEM, "memory budget %.3g B too small for the adjoint sweep", budget);
+        }
+    }
+    *k_out = k;
+    *nseg_out = (nt + k - 1) / k;
+    return FWI_OK;
+}
+
+struct Sweep {
+    int k = 0, nseg = 0;
+    float *F0, *F1, *A0, *A1, *Dh, *CK, *G;
+};
+
+// Forward sweep for an adjoint: checkpoints of (u^{n-1}, u^n) at the start
+// of every segment but the last, D^n stored for the last segment, receiver
+// samples (time-major) if `sample`.
+int forward_for_adjoint(fwi_ctx *c, const float *v, bool sample, Sweep &w)
+{
+    const Plan &p = c->plan;
+    int rc;
+    if ((rc = choose_segments(c, &w.k, &w.nseg))) return rc;
+    const int k = w.k, nseg = w.nseg;
+    c->stats.ckpt_every = nseg > 1 ? k : 0;
+    c->stats.n_segments = nseg;
+    const int64_t ff = p.field_floats, gf = p.img_floats;
+    if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
+        (rc = ensure(c, c->dhist, size_t(k) * gf * 4)) ||
+        (rc = ensure(c, c->ckpt, size_t(std::max(0, nseg - 1)) * 2 * ff * 4)) ||
+        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)))
+        return rc;
+    float *F = static_cast<float *>(c->fields.p);
+    w.F0 = F;
+    w.F1 = F + ff;
+    w.A0 = F + 2 * ff;
+    w.A1 = F + 3 * ff;
+    w.Dh = static_cast<float *>(c->dhist.p);
+    w.CK = static_cast<float *>(c->ckpt.p);
+    w.G = static_cast<float *>(c->image.p);
+    float *samp = static_cast<float *>(c->samples.p);
+    hipStream_t st = c->stream;
+    if ((rc = other(c, launch_fill(w.F0, 2 * ff, 0.f, st), "fill"))) return rc;
+    StepArgs a = base_args(c, v);
+    const int last0 = (nseg - 1) * k;
+    for (int n = 0; n < p.nt_max; ++n) {
+        if (n % k == 0 && n / k < nseg - 1) {
+            float *ckp = w.CK + size_t(n / k) * 2 * ff;
+            HIPCHK(c, hipMemcpyAsync(ckp, w.F0, size_t(2 * ff) * 4, hipMemcpyDeviceToDevice, st));
+        }
+        int fl = F_SRC;
+        if (sample) {
+            fl |= F_SAMPLE;
+            a.samp = samp + size_t(n) * p.Q;
+        }
+        if (n >= last0) {
+            fl |= F_EMIT;
+            a.dslot = w.Dh + size_t(n - last0) * gf;
+        }
+        if ((rc = fwd_step(c, a, fl, n, w.F0, w.F1))) return rc;
+    }
+    return FWI_OK;
+}
+
+// Backward sweep: for every segment, last to first, recompute D^n from its
+// checkpoint (the last segment's is already stored), then run the adjoint
+// steps with the fused imaging condition; finally fold and scale the image.
+// The adjoint sources (time-major [nt_max][Q]) are in the samples buffer.
+int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
+{
+    const Plan &p = c->plan;
+    const int64_t ff = p.field_floats, gf = p.img_floats;
+    const int k = w.k, nseg = w.nseg;
+    hipStream_t st = c->stream;
+    float *inj = static_cast<float *>(c->samples.p);
+    int rc;
+    if ((rc = other(c, launch_fill(w.A0, 2 * ff, 0.f, st), "fill"))) return rc;
+    if ((rc = other(c, launch_fill(w.G, gf, 0.f, st), "fill"))) return rc;
+    StepArgs a = base_args(c, v);
+    a.G = w.G;
+    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+        const int lo = sgi * k, hi = std::min(p.nt_max, lo + k);
+        if (sgi != nseg - 1) {
+            HIPCHK(c, hipMemcpyAsync(w.F0, w.CK + size_t(sgi) * 2 * ff, size_t(2 * ff) * 4,
+                                     hipMemcpyDeviceToDevice, st));
+            for (int n = lo; n < hi; ++n) {
+                a.dslot = w.Dh + size_t(n - lo) * gf;
+                if ((rc = fwd_step(c, a, F_SRC | F_EMIT, n, w.F0, w.F1))) return rc;
+            }
+        }
+        for (int n = hi - 1; n >= lo; --n) {
+            a.dslot = w.Dh + size_t(n - lo) * gf;
+            a.inj = inj + size_t(n) * p.Q;
+            if ((rc = adj_step(c, a, n, w.A0, w.A1))) return rc;
+        }
+    }
+    FinalArgs fa{};
+    fa.shots = static_cast<const ShotDesc *>(c->d_shots.p);
+    fa.nshots = p.S;
+    fa.G = w.G;
+    fa.v = v;
+    fa.nz = p.nz;
+    fa.nx = p.nx;
+    fa.nb = p.nb;
+    fa.NZ = p.NZ;
+    fa.dt2 = float(double(p.dt) * p.dt);
+    fa.img = img;
+    return other(c, launch_finalize(fa, st), "finalize");
+}
+
+TraceArgs trace_args(fwi_ctx *c)
+{
+    const Plan &p = c->plan;
+    TraceArgs t{};
+    t.Q = p.Q;
+    t.nt_max = p.nt_max;
+    t.q_nt = static_cast<const int32_t *>(c->d_qnt.p);
+    t.q_rptr = static_cast<const int32_t *>(c->d_qrptr.p);
+    t.q_roff = static_cast<const int64_t *>(c->d_qroff.p);
+    return t;
+}
+
+int begin_call(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
+{
+    if (!c) return FWI_EINVAL;
+    c->err.clear();
+    reset_stats(c);
+    c->ev_marks.clear();
+    c->ev_used = 0;
+    HIPCHK(c, hipSetDevice(c->device));
+    return build_plan(c, g, geo);
+}
+
+int forward_sweep_sampled(fwi_ctx *c, const float *v)
+{
+    const Plan &p = c->plan;
+    const int64_t ff = p.field_floats;
+    int rc;
+    if ((rc = ensure(c, c->fields, size_t(2 * ff) * 4)) ||
+        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)))
+        return rc;
+    float *F0 = static_cast<float *>(c->fields.p), *F1 = F0 + ff;
+    float *samp = static_cast<float *>(c->samples.p);
+    if ((rc = other(c, launch_fill(F0, 2 * ff, 0.f, c->stream), "fill"))) return rc;
+    StepArgs a = base_args(c, v);
+    for (int n = 0; n < p.nt_max; ++n) {
+        a.samp = samp + size_t(n) * p.Q;
+        if ((rc = fwd_step(c, a, F_SRC | F_SAMPLE, n, F0, F1))) return rc;
+    }
+    return FWI_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// public entry points
+
+extern "C" {
+
+int fwi_ctx_create(int device, void *hip_stream, fwi_ctx **out)
+{
+    if (!out) return FWI_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FWI_EHIP;
+    if (hipSetDevice(device) != hipSuccess) return FWI_EHIP;
+    fwi_ctx *c = new fwi_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = size_t(64) << 30;
+    c->budget = int64_t(0.4 * double(tot));
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->h_check), 4 * sizeof(float), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&c->h_misfit), sizeof(double), hipHostMallocDefault) !=
+            hipSuccess) {
+        delete c;
+        return FWI_ENOMEM;
+    }
+    *out = c;
+    return FWI_OK;
+}
+
+void fwi_ctx_destroy(fwi_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (DevBuf *b : {&c->d_shots, &c->d_waves, &c->d_rrows, &c->d_rmap, &c->d_qnt, &c->d_qrptr, &c->d_qroff,
+                      &c->d_wav, &c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt, &c->partials,
+                      &c->misfit, &c->check})
+        release(*b);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->h_check) (void)hipHostFree(c->h_check);
+    if (c->h_misfit) (void)hipHostFree(c->h_misfit);
+    delete c;
+}
+
+int fwi_ctx_set_stream(fwi_ctx *c, void *hip_stream)
+{
+    if (!c) return FWI_EINVAL;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return FWI_OK;
+}
+
+int fwi_ctx_set_mem_budget(fwi_ctx *c, int64_t bytes)
+{
+    if (!c || bytes < 0) return FWI_EINVAL;
+    if (bytes == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = size_t(64) << 30;
+        bytes = int64_t(0.4 * double(tot));
+    }
+    c->budget = bytes;
+    return FWI_OK;
+}
+
+int fwi_ctx_set_profiling(fwi_ctx *c, int enable)
+{
+    if (!c) return FWI_EINVAL;
+    c->profiling = enable != 0;
+    return FWI_OK;
+}
+
+int fwi_ctx_get_stats(const fwi_ctx *c, fwi_stats *out)
+{
+    if (!c || !out) return FWI_EINVAL;
+    *out = c->stats;
+    return FWI_OK;
+}
+
+int fwi_ctx_trim(fwi_ctx *c)
+{
+    if (!c) return FWI_EINVAL;
+    (void)hipSetDevice(c->device);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return FWI_EHIP;
+    for (DevBuf *b : {&c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt, &c->partials})
+        release(*b);
+    return FWI_OK;
+}
+
+const char *fwi_last_error(const fwi_ctx *c)
+{
+    return c ? c->err.c_str() : "NULL context";
+}
+
+int fwi_forward(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v, float *d)
+{
+    int rc = begin_call(c, g, geo);
+    if (rc) return rc;
+    const Plan &p = c->plan;
+    if (!d && p.data_size > 0) return set_err(c, FWI_EINVAL, "d is NULL");
+    if ((rc = check_model(c, v, "v"))) return rc;
+    if ((rc = forward_sweep_sampled(c, v))) return rc;
+    TraceArgs t = trace_args(c);
+    t.tm_in = static_cast<const float *>(c->samples.p);
+    t.alpha = 1.f;
+    t.tr_out = d;
+    if ((rc = other(c, launch_traces(t, c->stream, nullptr), "traces"))) return rc;
+    return finish_stats(c);
+}
+
+int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v, const float *d_obs,
+                 float *grad, double *misfit, float *d_syn)
+{
+    int rc = begin_call(c, g, geo);
+    if (rc) return rc;
+    const Plan &p = c->plan;
+    if (!grad) return set_err(c, FWI_EINVAL, "g is NULL");
+    if (!d_obs && p.data_size > 0) return set_err(c, FWI_EINVAL, "d_obs is NULL");
+    if ((rc = check_model(c, v, "v"))) return rc;
+    // forward with sampling and checkpoints, then the residual (in place
+    // over the samples), then the backward sweep
+    Sweep w;
+    if ((rc = forward_for_adjoint(c, v, true, w))) return rc;
+    TraceArgs t = trace_args(c);
+    float *samp = static_cast<float *>(c->samples.p);
+    t.tm_in = samp;
+    t.alpha = 1.f;
+    t.tr_in = d_obs;
+    t.beta = -1.f;
+    t.tm_out = samp;
+    t.tr_out = d_syn;
+    const int64_t nblk = int64_t((p.Q + 63) / 64) * ((p.nt_max + 63) / 64);
+    if ((rc = ensure(c, c->partials, size_t(std::max<int64_t>(nblk, 1)) * sizeof(double))) ||
+        (rc = ensure(c, c->misfit, sizeof(double))))
+        return rc;
+    t.partials = static_cast<double *>(c->partials.p);
+    if ((rc = other(c, launch_traces(t, c->stream, nullptr), "residual"))) return rc;
+    if (nblk > 0) {
+        if ((rc = other(c, launch_sum_partials(t.partials, nblk, static_cast<double *>(c->misfit.p), c->stream),
+                        "misfit")))
+            return rc;
+    } else {
+        HIPCHK(c, hipMemsetAsync(c->misfit.p, 0, sizeof(double), c->stream));
+    }
+    if (misfit)
+        HIPCHK(c, hipMemcpyAsync(c->h_misfit, c->misfit.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if ((rc = backward_sweep(c, v, w, grad))) return rc;
+    if (misfit) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *misfit = *c->h_misfit;
+    }
+    return finish_stats(c);
+}
+
+int born_demig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v0, const float *dv, float *dd)
+{
+    int rc = begin_call(c, g, geo);
+    if (rc) return rc;
+    const Plan &p = c->plan;
+    if (!dd && p.data_size > 0) return set_err(c, FWI_EINVAL, "dd is NULL");
+    if ((rc = check_model(c, v0, "v0")) || (rc = check_finite_perturbation(c, dv))) return rc;
+    const int64_t ff = p.field_floats;
+    if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) ||
+        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)))
+        return rc;
+    float *F = static_cast<float *>(c->fields.p);
+    float *samp = static_cast<float *>(c->samples.p);
+    if ((rc = other(c, launch_fill(F, 4 * ff, 0.f, c->stream), "fill"))) return rc;
+    StepArgs a = base_args(c, v0);
+    a.dv = dv;
+    float *U0 = F, *U1 = F + ff, *D0 = F + 2 * ff, *D1 = F + 3 * ff;
+    for (int n = 0; n < p.nt_max; ++n) {
+        a.n = n;
+        a.nwaves = p.active_waves(n);
+        a.cur = n % 2 == 0 ? U0 : U1;
+        a.prev = n % 2 == 0 ? U1 : U0;
+        a.cur2 = n % 2 == 0 ? D0 : D1;
+        a.prev2 = n % 2 == 0 ? D1 : D0;
+        a.samp = samp + size_t(n) * p.Q;
+        if ((rc = ev_begin(c, K_BORN))) return rc;
+        HIPCHK(c, launch_born_step(a, c->stream));
+        if ((rc = ev_end(c))) return rc;
+        const double upd = step_updates(p, n);
+        c->stats.cell_updates += 2 * upd;
+        c->stats.stencil_launches += 1;
+        c->stats.n_born += 1;
+        c->stats.bytes_born += upd * kBytesBorn;
+    }
+    TraceArgs t = trace_args(c);
+    t.tm_in = samp;
+    t.alpha = 1.f;
+    t.tr_out = dd;
+    if ((rc = other(c, launch_traces(t, c->stream, nullptr), "traces"))) return rc;
+    return finish_stats(c);
+}
+
+int born_mig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v0, const float *dd, float *img)
+{
+    int rc = begin_call(c, g, geo);
+    if (rc) return rc;
+    const Plan &p = c->plan;
+    if (!img) return set_err(c, FWI_EINVAL, "img is NULL");
+    if (!dd && p.data_size > 0) return set_err(c, FWI_EINVAL, "dd is NULL");
+    if ((rc = check_model(c, v0, "v0"))) return rc;
+    if ((rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4))) return rc;
+    TraceArgs t = trace_args(c);
+    t.tr_in = dd;
+    t.beta = 1.f;
+    t.tm_out = static_cast<float *>(c->samples.p);
+    if ((rc = other(c, launch_traces(t, c->stream, nullptr), "adjoint sources"))) return rc;
+    Sweep w;
+    if ((rc = forward_for_adjoint(c, v0, false, w))) return rc;
+    if ((rc = backward_sweep(c, v0, w, img))) return rc;
+    return finish_stats(c);
+}
+
+}  // extern "C"

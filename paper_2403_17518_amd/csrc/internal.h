@@ -1,0 +1,121 @@
+// Internal declarations shared by the kernels (fwi_kernels.hip) and the
+// host planner / C ABI (fwi_api.hip). Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fwi {
+
+constexpr int kLanes = 64;          // wavefront width on CDNA
+constexpr int kHalo = 4;            // stencil radius (8th order)
+constexpr int kWavesPerBlock = 4;   // waves per workgroup of the step kernels
+// A wavefield of one shot is stored as (NZ + 2*kHalo + 2) rows of pitch P:
+// one guard row, kHalo zero rows, NZ padded rows, kHalo zero rows, one guard
+// row. Columns NX .. P-1 of every row stay zero (P >= NX + kHalo), so they
+// serve as the right halo of a row and, read through the flat index, as the
+// left halo of the next row.
+constexpr int kRowsAbove = kHalo + 1;
+constexpr int kRowsExtra = 2 * kHalo + 2;
+
+// Per-shot layout and acquisition (device table, indexed in "slot" order:
+// shots sorted by decreasing record length).
+struct ShotDesc {
+    int64_t f_off;   // float offset of padded cell (0,0) in a field buffer
+    int64_t g_off;   // float offset of padded cell (0,0) in an image / D slot
+    int32_t P;       // row pitch (floats)
+    int32_t NX;      // padded width = win_nx + 2 nb
+    int32_t x0;      // first model column of the window
+    int32_t wnx;     // window width
+    int32_t nt;      // record length
+    int32_t src_i;   // source row, padded coordinates
+    int32_t src_j;   // source column, padded coordinates
+    int32_t wav_off; // float offset of the shot's wavelet
+};
+
+// One wavefront of a step kernel owns a strip of 64 columns and the rows
+// [z0, z1) of one shot. Rows holding receivers inside the strip are listed
+// in rrows[rr0 .. rr1).
+struct WaveDesc {
+    int32_t shot, col0, z0, z1;
+    int32_t rr0, rr1, pad0, pad1;
+};
+
+// A row of a strip that holds receiver cells: rmap[map_off + lane] is the
+// unique-receiver-cell index q of column col0 + lane, or -1.
+struct RecRow {
+    int32_t row, map_off;
+};
+
+enum StepFlags : int {
+    F_SRC = 1,     // add the source term w[n]/h^2
+    F_SAMPLE = 2,  // record the new field at receiver cells
+    F_INJECT = 4,  // add the adjoint source at receiver cells
+    F_EMIT = 8,    // store D^n = V^2 dt^2 (L8 u^n + s^n)
+    F_IMAGE = 16,  // accumulate G += out * D^n
+};
+
+struct StepArgs {
+    const ShotDesc *shots;
+    const WaveDesc *waves;
+    const RecRow *rrows;
+    const int32_t *rmap;
+    const float *v;      // physical model [nz][nx]
+    const float *dv;     // Born perturbation [nz][nx]
+    const float *wav;    // wavelets
+    int32_t nwaves, nz, nx, nb, NZ;
+    float w0, w1, w2, w3, w4;  // 2 c0 / h^2, c_k / h^2
+    float dt2;                 // dt^2
+    float hs;                  // smax dt / (2 nb^2): sigma dt/2 = hs (dz^2 + dx^2)
+    float ih2;                 // 1 / h^2
+    int32_t n;                 // time index
+    const float *cur;          // field at the current level
+    float *prev;               // previous level in, next level out
+    const float *cur2;         // second field (Born)
+    float *prev2;
+    float *dslot;              // D^n slot (F_EMIT writes, F_IMAGE reads)
+    float *G;                  // imaging accumulator
+    float *samp;               // receiver samples of step n: samp[q]
+    const float *inj;          // adjoint sources of step n: inj[q]
+};
+
+// Time-major <-> trace-major conversion, residual and misfit.
+//   tm_out[n][q] = sum over receivers r at cell q of
+//                  (alpha * tm_in[n][q] + beta * tr_in[r][n])
+//   tr_out[r][n] = tm_in[n][q(r)]
+//   partials[block] = 1/2 sum over (r, n) of (alpha*tm_in + beta*tr_in)^2
+struct TraceArgs {
+    int32_t Q;
+    int32_t nt_max;
+    const int32_t *q_nt;     // [Q] record length of the cell's shot
+    const int32_t *q_rptr;   // [Q+1] receivers of cell q: q_roff[q_rptr[q]..]
+    const int64_t *q_roff;   // trace offsets (floats) in the packed data
+    const float *tm_in;
+    float alpha;
+    const float *tr_in;
+    float beta;
+    float *tm_out;
+    float *tr_out;
+    double *partials;
+};
+
+struct FinalArgs {
+    const ShotDesc *shots;
+    int32_t nshots;
+    const float *G;
+    const float *v;
+    int32_t nz, nx, nb, NZ;
+    float dt2;
+    float *img;
+};
+
+hipError_t launch_step(int flags, const StepArgs &a, hipStream_t s);
+hipError_t launch_born_step(const StepArgs &a, hipStream_t s);
+hipError_t launch_fill(float *p, int64_t n, float val, hipStream_t s);
+hipError_t launch_model_check(const float *v, int64_t n, float *out3, hipStream_t s);
+hipError_t launch_traces(const TraceArgs &a, hipStream_t s, int64_t *nblocks_out);
+hipError_t launch_sum_partials(const double *part, int64_t n, double *out, hipStream_t s);
+hipError_t launch_finalize(const FinalArgs &a, hipStream_t s);
+
+}  // namespace fwi

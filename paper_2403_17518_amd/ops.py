@@ -1,0 +1,181 @@
+"""torch-facing binding of libfwi.so: same names as the C ABI.
+
+torch supplies device memory and the stream; every operator runs in the
+library's HIP kernels. There is no CPU fallback: without the built library
+or a GPU these functions raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _abi
+
+
+def _check(lib, ctx, rc):
+    if rc != _abi.FWI_OK:
+        msg = lib.fwi_last_error(ctx)
+        raise _abi.FwiError(rc, msg.decode() if msg else "")
+
+
+def _dev_f32(t: torch.Tensor, name: str, device) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device != device or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor on {device}")
+    return t
+
+
+class FwiContext:
+    """Owns one fwi_ctx: scratch pool, plan cache and kernel statistics."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 0, profiling: bool = False):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: libfwi.so needs an MI355X")
+        self.lib = _abi.load()
+        self.device = torch.device("cuda", device)
+        with torch.cuda.device(self.device):
+            ptr = C.c_void_p()
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            _check(self.lib, None, self.lib.fwi_ctx_create(device, C.c_void_p(stream), C.byref(ptr)))
+        self.ctx = ptr
+        if mem_budget:
+            self.set_mem_budget(mem_budget)
+        if profiling:
+            self.set_profiling(True)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.fwi_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- settings ----------------------------------------------------------
+    def set_mem_budget(self, nbytes: int):
+        _check(self.lib, self.ctx, self.lib.fwi_ctx_set_mem_budget(self.ctx, int(nbytes)))
+
+    def set_profiling(self, on: bool):
+        _check(self.lib, self.ctx, self.lib.fwi_ctx_set_profiling(self.ctx, 1 if on else 0))
+
+    def stats(self) -> dict:
+        s = _abi.fwi_stats()
+        _check(self.lib, self.ctx, self.lib.fwi_ctx_get_stats(self.ctx, C.byref(s)))
+        return s.as_dict()
+
+    def trim(self):
+        _check(self.lib, self.ctx, self.lib.fwi_ctx_trim(self.ctx))
+
+    def _prep(self, grid, acq):
+        g = _abi.make_grid(grid)
+        gv = _abi.GeomView(acq, grid)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(self.lib, self.ctx, self.lib.fwi_ctx_set_stream(self.ctx, C.c_void_p(stream)))
+        return g, gv
+
+    def _data_size(self, grid, acq) -> int:
+        nt = np.full(len(acq.src_z), grid.nt_max) if getattr(acq, "nt", None) is None else np.asarray(acq.nt)
+        nrec = np.diff(np.asarray(acq.rec_ptr, dtype=np.int64))
+        return int(np.sum(nrec * nt))
+
+    def _model(self, t, name, grid):
+        t = _dev_f32(t, name, self.device)
+        if tuple(t.shape) != (grid.nz, grid.nx):
+            raise ValueError(f"{name} must have shape ({grid.nz}, {grid.nx})")
+        return t
+
+    def _data(self, t, name, n):
+        t = _dev_f32(t, name, self.device)
+        if t.numel() != n:
+            raise ValueError(f"{name} must hold {n} samples")
+        return t
+
+    # -- operators -----------------------------------------------------------
+    def fwi_forward(self, grid, acq, v: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """d = F(v): packed traces (shot, receiver, time)."""
+        v = self._model(v, "v", grid)
+        n = self._data_size(grid, acq)
+        d = torch.empty(n, device=self.device, dtype=torch.float32) if out is None else self._data(out, "out", n)
+        g, gv = self._prep(grid, acq)
+        _check(self.lib, self.ctx, self.lib.fwi_forward(self.ctx, C.byref(g), C.byref(gv.geom),
+                                                        C.c_void_p(v.data_ptr()), C.c_void_p(d.data_ptr())))
+        return d
+
+    def fwi_gradient(self, grid, acq, v, d_obs, want_misfit: bool = True, want_dsyn: bool = False):
+        """(g, misfit, d_syn): g = J^T (F(v) - d_obs); misfit = 1/2 ||F(v) - d_obs||^2."""
+        v = self._model(v, "v", grid)
+        n = self._data_size(grid, acq)
+        d_obs = self._data(d_obs, "d_obs", n)
+        grad = torch.empty((grid.nz, grid.nx), device=self.device, dtype=torch.float32)
+        d_syn = torch.empty(n, device=self.device, dtype=torch.float32) if want_dsyn else None
+        phi = C.c_double(0.0)
+        g, gv = self._prep(grid, acq)
+        _check(self.lib, self.ctx, self.lib.fwi_gradient(
+            self.ctx, C.byref(g), C.byref(gv.geom), C.c_void_p(v.data_ptr()),
+            C.c_void_p(d_obs.data_ptr()), C.c_void_p(grad.data_ptr()),
+            C.byref(phi) if want_misfit else None,
+            C.c_void_p(d_syn.data_ptr()) if d_syn is not None else None))
+        return grad, (float(phi.value) if want_misfit else None), d_syn
+
+    def born_demig(self, grid, acq, v0, dv) -> torch.Tensor:
+        """dd = J dv."""
+        v0 = self._model(v0, "v0", grid)
+        dv = self._model(dv, "dv", grid)
+        n = self._data_size(grid, acq)
+        dd = torch.empty(n, device=self.device, dtype=torch.float32)
+        g, gv = self._prep(grid, acq)
+        _check(self.lib, self.ctx, self.lib.born_demig(self.ctx, C.byref(g), C.byref(gv.geom),
+                                                       C.c_void_p(v0.data_ptr()), C.c_void_p(dv.data_ptr()),
+                                                       C.c_void_p(dd.data_ptr())))
+        return dd
+
+    def born_mig(self, grid, acq, v0, dd) -> torch.Tensor:
+        """img = J^T dd."""
+        v0 = self._model(v0, "v0", grid)
+        dd = self._data(dd, "dd", self._data_size(grid, acq))
+        img = torch.empty((grid.nz, grid.nx), device=self.device, dtype=torch.float32)
+        g, gv = self._prep(grid, acq)
+        _check(self.lib, self.ctx, self.lib.born_mig(self.ctx, C.byref(g), C.byref(gv.geom),
+                                                     C.c_void_p(v0.data_ptr()), C.c_void_p(dd.data_ptr()),
+                                                     C.c_void_p(img.data_ptr())))
+        return img
+
+    def born_pair(self, grid, acq, v0, g_in) -> torch.Tensor:
+        """J^T J g_in, the doubly migrated image (paper section 2.3 eq. 15)."""
+        return self.born_mig(grid, acq, v0, self.born_demig(grid, acq, v0, g_in))
+
+
+_default: dict = {}
+
+
+def default_context(device: int = 0) -> FwiContext:
+    ctx = _default.get(device)
+    if ctx is None:
+        ctx = _default[device] = FwiContext(device)
+    return ctx
+
+
+def _ctx_of(t: torch.Tensor) -> FwiContext:
+    return default_context(t.device.index or 0)
+
+
+def fwi_forward(grid, acq, v):
+    return _ctx_of(v).fwi_forward(grid, acq, v)
+
+
+def fwi_gradient(grid, acq, v, d_obs, want_dsyn: bool = False):
+    return _ctx_of(v).fwi_gradient(grid, acq, v, d_obs, True, want_dsyn)
+
+
+def born_demig(grid, acq, v0, dv):
+    return _ctx_of(v0).born_demig(grid, acq, v0, dv)
+
+
+def born_mig(grid, acq, v0, dd):
+    return _ctx_of(v0).born_mig(grid, acq, v0, dd)
