@@ -111,6 +111,9 @@ typedef struct {
     double ms_fwd, ms_adj, ms_born, ms_other;
     int64_t n_fwd, n_adj, n_born;
     double bytes_fwd, bytes_adj, bytes_born; /* algorithmic bytes moved */
+    /* tiling used by the forward, adjoint and Born kernels: columns per
+       lane (strip width 64 * cols) and rows streamed per wave */
+    int32_t tile_cw[3], tile_rows[3];
 } fwi_stats;
 
 /* Create a context on HIP device `device`, enqueueing on `hip_stream`
@@ -123,6 +126,13 @@ int fwi_ctx_set_stream(fwi_ctx *ctx, void *hip_stream);
 int fwi_ctx_set_mem_budget(fwi_ctx *ctx, int64_t bytes);
 /* 1 = time every kernel launch with HIP events (adds a sync per call). */
 int fwi_ctx_set_profiling(fwi_ctx *ctx, int enable);
+/* Tiling of the step kernels. kernel: 0 forward, 1 adjoint, 2 Born, -1 all;
+ * cols_per_lane 1 or 2 and rows_per_wave >= 1 force a tiling; (0, 0)
+ * returns the kernel to the autotuner. */
+int fwi_ctx_set_tiling(fwi_ctx *ctx, int kernel, int cols_per_lane, int rows_per_wave);
+/* 1 (default): pick each kernel's tiling by timing candidates once per
+ * geometry; 0: use a fixed default tiling. */
+int fwi_ctx_set_autotune(fwi_ctx *ctx, int enable);
 int fwi_ctx_get_stats(const fwi_ctx *ctx, fwi_stats *out);
 /* Release all scratch memory held by the context. */
 int fwi_ctx_trim(fwi_ctx *ctx);

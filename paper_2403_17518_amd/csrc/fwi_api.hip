@@ -21,7 +21,8 @@ using namespace fwi;
 namespace {
 
 constexpr double kCflLimit = 0.55;     // 2D 8th-order leapfrog limit is 0.5546
-constexpr int kRowsPerWave = 30;       // target rows streamed by one wave
+constexpr int kDefaultCw = 2;          // tiling used when autotuning is off
+constexpr int kDefaultRows = 16;
 
 // 8th-order central second-derivative weights (Fornberg 1988).
 constexpr double kC8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
@@ -40,10 +41,8 @@ struct Plan {
     std::vector<int> order;              // slot -> caller's shot index
     std::vector<ShotDesc> shots;
     std::vector<int> slot_nt;
-    std::vector<int> wave_prefix;        // waves of slots [0, k)
-    std::vector<WaveDesc> waves;
-    std::vector<RecRow> rrows;
-    std::vector<int32_t> rmap;
+    // receiver cells of every slot: ((row, col), q), sorted by row then col
+    std::vector<std::vector<std::pair<std::pair<int, int>, int>>> slot_cells;
     // unique receiver cells
     int Q = 0;
     std::vector<int32_t> q_nt, q_rptr;
@@ -55,7 +54,7 @@ struct Plan {
     double updates_per_field_pass = 0;
     std::vector<char> key;     // serialized inputs (plan cache)
 
-    int active_waves(int n) const
+    int active_slots(int n) const
     {
         // slots are sorted by decreasing nt: those with nt > n form a prefix
         int lo = 0, hi = S;
@@ -64,9 +63,21 @@ struct Plan {
             if (slot_nt[mid] > n) lo = mid + 1;
             else hi = mid;
         }
-        return wave_prefix[lo];
+        return lo;
     }
 };
+
+// Wave table of one tiling: strips of 64*cw columns, runs of `rows` rows.
+struct Tiling {
+    int cw = 0, rows = 0;
+    std::vector<WaveDesc> waves;
+    std::vector<RecRow> rrows;
+    std::vector<int32_t> rmap;
+    std::vector<int> prefix;  // waves of slots [0, k)
+    DevBuf d_waves, d_rrows, d_rmap;
+};
+
+enum KClass { K_FWD = 0, K_ADJ = 1, K_BORN = 2, K_OTHER = 3 };
 
 }  // namespace
 
@@ -80,7 +91,12 @@ struct fwi_ctx {
     Plan plan;
     bool plan_valid = false;
     // device copies of the plan tables
-    DevBuf d_shots, d_waves, d_rrows, d_rmap, d_qnt, d_qrptr, d_qroff, d_wav;
+    DevBuf d_shots, d_qnt, d_qrptr, d_qroff, d_wav;
+    // one tiling per kernel class (forward, adjoint, Born), picked by the
+    // autotuner or forced by fwi_ctx_set_tiling
+    Tiling tile[3];
+    int force_cw[3] = {0, 0, 0}, force_rows[3] = {0, 0, 0};
+    bool autotune = true;
     // scratch
     DevBuf fields, samples, image, dhist, ckpt, partials, misfit, check;
     float *h_check = nullptr;     // pinned [3]
@@ -250,12 +266,9 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
     for (int s = 0; s < S; ++s) p.order[s] = s;
     std::stable_sort(p.order.begin(), p.order.end(), [&](int a, int b) { return nts[a] > nts[b]; });
 
-    const int nseg_z = std::max(1, (p.NZ + kRowsPerWave - 1) / kRowsPerWave);
-    const int rows_per = (p.NZ + nseg_z - 1) / nseg_z;
-
     p.shots.resize(S);
     p.slot_nt.resize(S);
-    p.wave_prefix.assign(S + 1, 0);
+    p.slot_cells.resize(S);
     int64_t foff = 0, goff = 0;
     p.q_rptr.push_back(0);
     if (geo->wavelet_shared) p.wav.assign(geo->wavelet, geo->wavelet + g->nt_max);
@@ -289,64 +302,87 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
             const int i = geo->rec_z[r] + p.nb, jj = geo->rec_x[r] - x0[s] + p.nb;
             cells[{i, jj}].push_back(data_off[s] + (r - geo->rec_ptr[s]) * int64_t(nts[s]));
         }
-        const int qbase = p.Q;
-        std::vector<std::pair<int, int>> cell_list;  // (row, col) by q
         for (auto &kv : cells) {
-            cell_list.push_back(kv.first);
+            p.slot_cells[k].push_back({kv.first, p.Q});
             p.q_nt.push_back(nts[s]);
             for (int64_t off : kv.second) p.q_roff.push_back(off);
             p.q_rptr.push_back(int32_t(p.q_roff.size()));
             ++p.Q;
         }
-        // waves: strip-major, then row segments; receiver rows per wave
-        const int nstrips = (d.NX + kLanes - 1) / kLanes;
-        for (int st = 0; st < nstrips; ++st) {
-            const int col0 = st * kLanes;
-            // receiver cells of this strip, already sorted by row then col
-            std::vector<std::pair<std::pair<int, int>, int>> sc;
-            for (size_t qi = 0; qi < cell_list.size(); ++qi)
-                if (cell_list[qi].second >= col0 && cell_list[qi].second < col0 + kLanes)
-                    sc.push_back({cell_list[qi], qbase + int(qi)});
-            size_t pos = 0;
-            for (int z0 = 0; z0 < p.NZ; z0 += rows_per) {
-                WaveDesc w{};
-                w.shot = k;
-                w.col0 = col0;
-                w.z0 = z0;
-                w.z1 = std::min(p.NZ, z0 + rows_per);
-                w.rr0 = int(p.rrows.size());
-                while (pos < sc.size() && sc[pos].first.first < w.z1) {
-                    const int rowi = sc[pos].first.first;
-                    RecRow rrw{rowi, int32_t(p.rmap.size())};
-                    p.rmap.resize(p.rmap.size() + kLanes, -1);
-                    while (pos < sc.size() && sc[pos].first.first == rowi) {
-                        p.rmap[rrw.map_off + (sc[pos].first.second - col0)] = sc[pos].second;
-                        ++pos;
-                    }
-                    p.rrows.push_back(rrw);
-                }
-                w.rr1 = int(p.rrows.size());
-                p.waves.push_back(w);
-            }
-        }
-        p.wave_prefix[k + 1] = int(p.waves.size());
     }
     p.field_floats = foff;
     p.img_floats = goff;
-    if (p.waves.size() > size_t(1) << 28) return set_err(c, FWI_EINVAL, "too many waves");
+    for (int k = 0; k < S; ++k)
+        if (int64_t(p.NZ + kRowsExtra) * p.shots[k].P >= (int64_t(1) << 31))
+            return set_err(c, FWI_EINVAL, "shot %d: padded field too large", k);
     p.key = std::move(key);
 
     int rc;
-    if ((rc = upload(c, c->d_shots, p.shots)) || (rc = upload(c, c->d_waves, p.waves)) ||
-        (rc = upload(c, c->d_rrows, p.rrows)) || (rc = upload(c, c->d_rmap, p.rmap)) ||
-        (rc = upload(c, c->d_qnt, p.q_nt)) || (rc = upload(c, c->d_qrptr, p.q_rptr)) ||
+    if ((rc = upload(c, c->d_shots, p.shots)) || (rc = upload(c, c->d_qnt, p.q_nt)) || (rc = upload(c, c->d_qrptr, p.q_rptr)) ||
         (rc = upload(c, c->d_qroff, p.q_roff)) || (rc = upload(c, c->d_wav, p.wav)))
         return rc;
     // the host vectors are read by the copies above; keep them alive in the
     // context and make sure the copies finished before the plan can change
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->plan = std::move(p);
+    for (Tiling &t : c->tile) t.cw = t.rows = 0;  // stale for the new plan
     c->plan_valid = true;
+    return FWI_OK;
+}
+
+void build_tiling(const Plan &p, int cw, int rows_target, Tiling &t)
+{
+    t.cw = cw;
+    t.rows = rows_target;
+    t.waves.clear();
+    t.rrows.clear();
+    t.rmap.clear();
+    t.prefix.assign(p.S + 1, 0);
+    const int SW = kLanes * cw;
+    const int nseg = std::max(1, (p.NZ + rows_target - 1) / rows_target);
+    const int rows = (p.NZ + nseg - 1) / nseg;
+    for (int k = 0; k < p.S; ++k) {
+        const auto &cells = p.slot_cells[k];
+        const int nstrips = (p.shots[k].NX + SW - 1) / SW;
+        for (int st = 0; st < nstrips; ++st) {
+            const int col0 = st * SW;
+            std::vector<std::pair<std::pair<int, int>, int>> sc;
+            for (const auto &cq : cells)
+                if (cq.first.second >= col0 && cq.first.second < col0 + SW) sc.push_back(cq);
+            size_t pos = 0;
+            for (int z0 = 0; z0 < p.NZ; z0 += rows) {
+                WaveDesc w{};
+                w.shot = k;
+                w.col0 = col0;
+                w.z0 = z0;
+                w.z1 = std::min(p.NZ, z0 + rows);
+                w.rr0 = int(t.rrows.size());
+                while (pos < sc.size() && sc[pos].first.first < w.z1) {
+                    const int rowi = sc[pos].first.first;
+                    RecRow rrw{rowi, int32_t(t.rmap.size())};
+                    t.rmap.resize(t.rmap.size() + SW, -1);
+                    while (pos < sc.size() && sc[pos].first.first == rowi) {
+                        t.rmap[rrw.map_off + (sc[pos].first.second - col0)] = sc[pos].second;
+                        ++pos;
+                    }
+                    t.rrows.push_back(rrw);
+                }
+                w.rr1 = int(t.rrows.size());
+                t.waves.push_back(w);
+            }
+        }
+        t.prefix[k + 1] = int(t.waves.size());
+    }
+}
+
+int upload_tiling(fwi_ctx *c, Tiling &t)
+{
+    int rc;
+    if ((rc = upload(c, t.d_waves, t.waves)) || (rc = upload(c, t.d_rrows, t.rrows)) ||
+        (rc = upload(c, t.d_rmap, t.rmap)))
+        return rc;
+    // pageable sources: make sure the copies have consumed them
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return FWI_OK;
 }
 
@@ -374,14 +410,16 @@ int check_finite_perturbation(fwi_ctx *c, const float *dv)
     return FWI_OK;
 }
 
-StepArgs base_args(fwi_ctx *c, const float *v)
+StepArgs base_args(fwi_ctx *c, const float *v, int cls)
 {
     const Plan &p = c->plan;
+    const Tiling &t = c->tile[cls];
     StepArgs a{};
     a.shots = static_cast<const ShotDesc *>(c->d_shots.p);
-    a.waves = static_cast<const WaveDesc *>(c->d_waves.p);
-    a.rrows = static_cast<const RecRow *>(c->d_rrows.p);
-    a.rmap = static_cast<const int32_t *>(c->d_rmap.p);
+    a.waves = static_cast<const WaveDesc *>(t.d_waves.p);
+    a.rrows = static_cast<const RecRow *>(t.d_rrows.p);
+    a.rmap = static_cast<const int32_t *>(t.d_rmap.p);
+    a.cw = t.cw;
     a.v = v;
     a.wav = static_cast<const float *>(c->d_wav.p);
     a.nz = p.nz;
@@ -404,8 +442,6 @@ StepArgs base_args(fwi_ctx *c, const float *v)
 }
 
 // ---- profiling --------------------------------------------------------------
-
-enum KClass { K_FWD = 0, K_ADJ = 1, K_BORN = 2, K_OTHER = 3 };
 
 int ev_begin(fwi_ctx *c, int cls)
 {
@@ -469,7 +505,7 @@ int fwd_step(fwi_ctx *c, StepArgs a, int flags, int n, float *F0, float *F1)
 {
     const Plan &p = c->plan;
     a.n = n;
-    a.nwaves = p.active_waves(n);
+    a.nwaves = c->tile[K_FWD].prefix[p.active_slots(n)];
     a.cur = (n % 2 == 0) ? F0 : F1;
     a.prev = (n % 2 == 0) ? F1 : F0;
     int rc = ev_begin(c, K_FWD);
@@ -488,7 +524,7 @@ int adj_step(fwi_ctx *c, StepArgs a, int n, float *A0, float *A1)
 {
     const Plan &p = c->plan;
     a.n = n;
-    a.nwaves = p.active_waves(n);
+    a.nwaves = c->tile[K_ADJ].prefix[p.active_slots(n)];
     // lambda^{n+1} lives in A[(n+1)%2], lambda^{n+2} (overwritten by lambda^n) in A[n%2]
     a.cur = ((n + 1) % 2 == 0) ? A0 : A1;
     a.prev = (n % 2 == 0) ? A0 : A1;
@@ -582,7 +618,7 @@ int forward_for_adjoint(fwi_ctx *c, const float *v, bool sample, Sweep &w)
     float *samp = static_cast<float *>(c->samples.p);
     hipStream_t st = c->stream;
     if ((rc = other(c, launch_fill(w.F0, 2 * ff, 0.f, st), "fill"))) return rc;
-    StepArgs a = base_args(c, v);
+    StepArgs a = base_args(c, v, K_FWD);
     const int last0 = (nseg - 1) * k;
     for (int n = 0; n < p.nt_max; ++n) {
         if (n % k == 0 && n / k < nseg - 1) {
@@ -617,7 +653,8 @@ int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
     int rc;
     if ((rc = other(c, launch_fill(w.A0, 2 * ff, 0.f, st), "fill"))) return rc;
     if ((rc = other(c, launch_fill(w.G, gf, 0.f, st), "fill"))) return rc;
-    StepArgs a = base_args(c, v);
+    StepArgs af = base_args(c, v, K_FWD);
+    StepArgs a = base_args(c, v, K_ADJ);
     a.G = w.G;
     for (int sgi = nseg - 1; sgi >= 0; --sgi) {
         const int lo = sgi * k, hi = std::min(p.nt_max, lo + k);
@@ -625,8 +662,8 @@ int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
             HIPCHK(c, hipMemcpyAsync(w.F0, w.CK + size_t(sgi) * 2 * ff, size_t(2 * ff) * 4,
                                      hipMemcpyDeviceToDevice, st));
             for (int n = lo; n < hi; ++n) {
-                a.dslot = w.Dh + size_t(n - lo) * gf;
-                if ((rc = fwd_step(c, a, F_SRC | F_EMIT, n, w.F0, w.F1))) return rc;
+                af.dslot = w.Dh + size_t(n - lo) * gf;
+                if ((rc = fwd_step(c, af, F_SRC | F_EMIT, n, w.F0, w.F1))) return rc;
             }
         }
         for (int n = hi - 1; n >= lo; --n) {
@@ -661,6 +698,131 @@ TraceArgs trace_args(fwi_ctx *c)
     return t;
 }
 
+// ---- autotuner ----------------------------------------------------------------
+//
+// Picks, per kernel class, the strip width (64 or 128 columns: 1 or 2
+// columns per lane) and the rows one wave streams, by timing a few launches
+// of each candidate on the plan's real shapes. Runs once per plan (the
+// plan cache keeps the result) on zeroed scratch fields; timings do not
+// depend on the field values.
+
+const int kTuneCw[] = {1, 2};
+const int kTuneRows[] = {8, 12, 16, 24, 32, 48};
+
+int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_out)
+{
+    const Plan &p = c->plan;
+    const int64_t ff = p.field_floats;
+    float *F = static_cast<float *>(c->fields.p);
+    StepArgs a{};
+    a.shots = static_cast<const ShotDesc *>(c->d_shots.p);
+    a.waves = static_cast<const WaveDesc *>(t.d_waves.p);
+    a.rrows = static_cast<const RecRow *>(t.d_rrows.p);
+    a.rmap = static_cast<const int32_t *>(t.d_rmap.p);
+    a.cw = t.cw;
+    StepArgs b = base_args(c, v, cls);
+    b.shots = a.shots;
+    b.waves = a.waves;
+    b.rrows = a.rrows;
+    b.rmap = a.rmap;
+    b.cw = a.cw;
+    b.n = 0;
+    b.nwaves = t.prefix[p.active_slots(0)];
+    b.cur = F;
+    b.prev = F + ff;
+    b.cur2 = F + 2 * ff;
+    b.prev2 = F + 3 * ff;
+    b.dv = v;
+    b.dslot = static_cast<float *>(c->dhist.p);
+    b.G = static_cast<float *>(c->image.p);
+    b.samp = static_cast<float *>(c->samples.p);
+    b.inj = b.samp;
+    auto launch = [&]() -> hipError_t {
+        if (cls == K_FWD) return launch_step(F_SRC | F_SAMPLE, b, c->stream);
+        if (cls == K_ADJ) return launch_step(F_INJECT | F_IMAGE, b, c->stream);
+        return launch_born_step(b, c->stream);
+    };
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    hipError_t err = launch();
+    if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
+    for (int i = 0; i < 4 && err == hipSuccess; ++i) err = launch();
+    if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return set_err(c, FWI_EHIP, "autotune launch: %s", hipGetErrorString(err));
+    *ms_out = ms;
+    return FWI_OK;
+}
+
+int ensure_tilings(fwi_ctx *c, const float *v)
+{
+    const Plan &p = c->plan;
+    bool need_tune = false;
+    for (int k = 0; k < 3; ++k) {
+        Tiling &t = c->tile[k];
+        const int want_cw = c->force_cw[k] ? c->force_cw[k] : (c->autotune ? 0 : kDefaultCw);
+        const int want_rows = c->force_rows[k] ? c->force_rows[k] : (c->autotune ? 0 : kDefaultRows);
+        if (want_cw && want_rows) {
+            if (t.cw == want_cw && t.rows == want_rows) continue;
+            build_tiling(p, want_cw, want_rows, t);
+            int rc = upload_tiling(c, t);
+            if (rc) return rc;
+        } else if (t.cw == 0) {
+            need_tune = true;
+        }
+    }
+    if (!need_tune) return FWI_OK;
+    // scratch for the trial launches
+    const int64_t ff = p.field_floats, gf = p.img_floats;
+    int rc;
+    if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
+        (rc = ensure(c, c->dhist, size_t(gf) * 4)) || (rc = ensure(c, c->samples, size_t(std::max(p.Q, 1)) * 4)))
+        return rc;
+    if ((rc = other(c, launch_fill(static_cast<float *>(c->fields.p), 4 * ff, 0.f, c->stream), "fill")) ||
+        (rc = other(c, launch_fill(static_cast<float *>(c->image.p), gf, 0.f, c->stream), "fill")) ||
+        (rc = other(c, launch_fill(static_cast<float *>(c->dhist.p), gf, 0.f, c->stream), "fill")) ||
+        (rc = other(c, launch_fill(static_cast<float *>(c->samples.p), std::max(p.Q, 1), 0.f, c->stream), "fill")))
+        return rc;
+    float best[3] = {1e30f, 1e30f, 1e30f};
+    int bcw[3] = {kDefaultCw, kDefaultCw, kDefaultCw}, brows[3] = {kDefaultRows, kDefaultRows, kDefaultRows};
+    Tiling trial;
+    for (int cw : kTuneCw)
+        for (int rows : kTuneRows) {
+            build_tiling(p, cw, rows, trial);
+            if ((rc = upload_tiling(c, trial))) return rc;
+            for (int k = 0; k < 3; ++k) {
+                if (c->tile[k].cw != 0) continue;
+                float ms = 0.f;
+                if ((rc = time_class(c, k, trial, v, &ms))) {
+                    release(trial.d_waves);
+                    release(trial.d_rrows);
+                    release(trial.d_rmap);
+                    return rc;
+                }
+                if (ms < best[k]) {
+                    best[k] = ms;
+                    bcw[k] = cw;
+                    brows[k] = rows;
+                }
+            }
+        }
+    release(trial.d_waves);
+    release(trial.d_rrows);
+    release(trial.d_rmap);
+    for (int k = 0; k < 3; ++k) {
+        Tiling &t = c->tile[k];
+        if (t.cw != 0) continue;
+        build_tiling(p, bcw[k], brows[k], t);
+        if ((rc = upload_tiling(c, t))) return rc;
+    }
+    return FWI_OK;
+}
+
 int begin_call(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
 {
     if (!c) return FWI_EINVAL;
@@ -670,6 +832,19 @@ int begin_call(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
     c->ev_used = 0;
     HIPCHK(c, hipSetDevice(c->device));
     return build_plan(c, g, geo);
+}
+
+// Tilings are (re)built after the model check, which the trial launches
+// need (they read the model).
+int prepare(fwi_ctx *c, const float *v)
+{
+    int rc = ensure_tilings(c, v);
+    if (rc) return rc;
+    for (int k = 0; k < 3; ++k) {
+        c->stats.tile_cw[k] = c->tile[k].cw;
+        c->stats.tile_rows[k] = c->tile[k].rows;
+    }
+    return FWI_OK;
 }
 
 int forward_sweep_sampled(fwi_ctx *c, const float *v)
@@ -683,7 +858,7 @@ int forward_sweep_sampled(fwi_ctx *c, const float *v)
     float *F0 = static_cast<float *>(c->fields.p), *F1 = F0 + ff;
     float *samp = static_cast<float *>(c->samples.p);
     if ((rc = other(c, launch_fill(F0, 2 * ff, 0.f, c->stream), "fill"))) return rc;
-    StepArgs a = base_args(c, v);
+    StepArgs a = base_args(c, v, K_FWD);
     for (int n = 0; n < p.nt_max; ++n) {
         a.samp = samp + size_t(n) * p.Q;
         if ((rc = fwd_step(c, a, F_SRC | F_SAMPLE, n, F0, F1))) return rc;
@@ -727,8 +902,9 @@ void fwi_ctx_destroy(fwi_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf *b : {&c->d_shots, &c->d_waves, &c->d_rrows, &c->d_rmap, &c->d_qnt, &c->d_qrptr, &c->d_qroff,
-                      &c->d_wav, &c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt, &c->partials,
+    for (Tiling &t : c->tile)
+        for (DevBuf *b : {&t.d_waves, &t.d_rrows, &t.d_rmap}) release(*b);
+    for (DevBuf *b : {&c->d_shots, &c->d_qnt, &c->d_qrptr, &c->d_qroff, &c->d_wav, &c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt, &c->partials,
                       &c->misfit, &c->check})
         release(*b);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -763,6 +939,30 @@ int fwi_ctx_set_profiling(fwi_ctx *c, int enable)
     return FWI_OK;
 }
 
+int fwi_ctx_set_tiling(fwi_ctx *c, int kernel, int cols_per_lane, int rows_per_wave)
+{
+    if (!c || kernel < -1 || kernel > 2) return FWI_EINVAL;
+    if (!((cols_per_lane == 0 && rows_per_wave == 0) ||
+          ((cols_per_lane == 1 || cols_per_lane == 2) && rows_per_wave >= 1 && rows_per_wave <= 4096)))
+        return FWI_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (kernel == -1 || kernel == k) {
+            c->force_cw[k] = cols_per_lane;
+            c->force_rows[k] = rows_per_wave;
+            c->tile[k].cw = c->tile[k].rows = 0;
+        }
+    return FWI_OK;
+}
+
+int fwi_ctx_set_autotune(fwi_ctx *c, int enable)
+{
+    if (!c) return FWI_EINVAL;
+    c->autotune = enable != 0;
+    for (int k = 0; k < 3; ++k)
+        if (!c->force_cw[k]) c->tile[k].cw = c->tile[k].rows = 0;
+    return FWI_OK;
+}
+
 int fwi_ctx_get_stats(const fwi_ctx *c, fwi_stats *out)
 {
     if (!c || !out) return FWI_EINVAL;
@@ -791,7 +991,7 @@ int fwi_forward(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float 
     if (rc) return rc;
     const Plan &p = c->plan;
     if (!d && p.data_size > 0) return set_err(c, FWI_EINVAL, "d is NULL");
-    if ((rc = check_model(c, v, "v"))) return rc;
+    if ((rc = check_model(c, v, "v")) || (rc = prepare(c, v))) return rc;
     if ((rc = forward_sweep_sampled(c, v))) return rc;
     TraceArgs t = trace_args(c);
     t.tm_in = static_cast<const float *>(c->samples.p);
@@ -809,7 +1009,7 @@ int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float
     const Plan &p = c->plan;
     if (!grad) return set_err(c, FWI_EINVAL, "g is NULL");
     if (!d_obs && p.data_size > 0) return set_err(c, FWI_EINVAL, "d_obs is NULL");
-    if ((rc = check_model(c, v, "v"))) return rc;
+    if ((rc = check_model(c, v, "v")) || (rc = prepare(c, v))) return rc;
     // forward with sampling and checkpoints, then the residual (in place
     // over the samples), then the backward sweep
     Sweep w;
@@ -851,7 +1051,8 @@ int born_demig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *
     if (rc) return rc;
     const Plan &p = c->plan;
     if (!dd && p.data_size > 0) return set_err(c, FWI_EINVAL, "dd is NULL");
-    if ((rc = check_model(c, v0, "v0")) || (rc = check_finite_perturbation(c, dv))) return rc;
+    if ((rc = check_model(c, v0, "v0")) || (rc = check_finite_perturbation(c, dv)) || (rc = prepare(c, v0)))
+        return rc;
     const int64_t ff = p.field_floats;
     if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) ||
         (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)))
@@ -859,12 +1060,12 @@ int born_demig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *
     float *F = static_cast<float *>(c->fields.p);
     float *samp = static_cast<float *>(c->samples.p);
     if ((rc = other(c, launch_fill(F, 4 * ff, 0.f, c->stream), "fill"))) return rc;
-    StepArgs a = base_args(c, v0);
+    StepArgs a = base_args(c, v0, K_BORN);
     a.dv = dv;
     float *U0 = F, *U1 = F + ff, *D0 = F + 2 * ff, *D1 = F + 3 * ff;
     for (int n = 0; n < p.nt_max; ++n) {
         a.n = n;
-        a.nwaves = p.active_waves(n);
+        a.nwaves = c->tile[K_BORN].prefix[p.active_slots(n)];
         a.cur = n % 2 == 0 ? U0 : U1;
         a.prev = n % 2 == 0 ? U1 : U0;
         a.cur2 = n % 2 == 0 ? D0 : D1;
@@ -894,7 +1095,7 @@ int born_mig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v0
     const Plan &p = c->plan;
     if (!img) return set_err(c, FWI_EINVAL, "img is NULL");
     if (!dd && p.data_size > 0) return set_err(c, FWI_EINVAL, "dd is NULL");
-    if ((rc = check_model(c, v0, "v0"))) return rc;
+    if ((rc = check_model(c, v0, "v0")) || (rc = prepare(c, v0))) return rc;
     if ((rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4))) return rc;
     TraceArgs t = trace_args(c);
     t.tr_in = dd;

@@ -8,12 +8,12 @@
 // (section 2.3 eq. 13), and the two-field variant is the jointly solved Born
 // system of section 2.2 eq. 9-11.
 //
-// Work decomposition: a wavefront owns a 64-column strip of one shot and a
-// run of rows. It streams down z keeping the nine rows of the current field
-// that the vertical stencil needs in registers; the horizontal neighbours of
-// the centre row go through a 72-float LDS row (64 + two 4-cell halos). The
-// kernel is bound by HBM/MALL bandwidth (about 1.7 flop per byte), so no
-// matrix cores are involved.
+// Work decomposition: a wavefront owns a strip of 64*CW columns of one shot
+// (CW = 1 or 2 columns per lane) and a run of rows. It streams down z keeping
+// the nine rows of the current field that the vertical stencil needs in
+// registers; the horizontal neighbours of the centre row go through an LDS
+// row (the strip plus two 4-cell halos). The kernel is bound by HBM/MALL
+// bandwidth (about 1.7 flop per byte), so no matrix cores are involved.
 #include "internal.h"
 
 namespace fwi {
@@ -48,10 +48,28 @@ __device__ __forceinline__ float sponge_a(float sh)
     return __builtin_amdgcn_rcpf(1.0f + sh);
 }
 
-template <int FL>
+template <int CW>
+__device__ __forceinline__ void ld(const float *p, float (&o)[CW])
+{
+    if constexpr (CW == 1) {
+        o[0] = *p;
+    } else {
+        const float2 t = *reinterpret_cast<const float2 *>(p);
+        o[0] = t.x;
+        o[1] = t.y;
+    }
+}
+
+// One time level of every active shot. Each lane owns CW adjacent columns of
+// a 64*CW-column strip and streams down the rows [z0, z1) of that strip; the
+// loads of row z+1 are issued before row z is computed so that two rows of
+// memory traffic are in flight per wave.
+template <int FL, int CW>
 __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs A)
 {
-    __shared__ float lds[kWavesPerBlock][kLanes + 2 * kHalo];
+    constexpr int SW = kLanes * CW;          // strip width
+    constexpr int RW = SW + 2 * kHalo;       // LDS row width
+    __shared__ float lds[kWavesPerBlock][RW];
     const int lane = threadIdx.x & (kLanes - 1);
     const int wl = threadIdx.x / kLanes;
     const int wid = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wl;
@@ -60,85 +78,142 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     const WaveDesc W = A.waves[wid];
     const ShotDesc S = A.shots[W.shot];
     const int P = S.P;
-    const int j = W.col0 + lane;
-    const bool valid = j < S.NX;
     const int nb = A.nb;
-    const int jm = S.x0 + clampi(j - nb, 0, S.wnx - 1);
-    const int ddx = max(max(nb - j, j - (S.NX - 1 - nb)), 0);
-    const float dx2 = float(ddx * ddx);
-    float ax = 1.0f, bx = 1.0f;
-    if (ddx > 0) {
-        const float sh = A.hs * dx2;
-        ax = sponge_a(sh);
-        bx = (1.0f - sh) * ax;
-    }
-    const float *cu = A.cur + S.f_off;
-    float *pv = A.prev + S.f_off;
-    const int64_t goff = S.g_off;
+    const int j0 = W.col0 + CW * lane;       // first column of this lane
+    // every load is unconditional: lanes past the shot's width read a zero
+    // column (P - CW >= NX + 2) instead
+    const int jl = min(j0, P - 2);
+    // offsets below are relative to the field block start (guard row), so
+    // they are non-negative 32-bit values
+    const float *cu = A.cur + (S.f_off - int64_t(kRowsAbove) * P);
+    float *pv = A.prev + (S.f_off - int64_t(kRowsAbove) * P);
+    const float *vmod = A.v;
+    float *gb = (FL & F_IMAGE) ? A.G + S.g_off : nullptr;
+    float *db = (FL & (F_IMAGE | F_EMIT)) ? A.dslot + S.g_off : nullptr;
 
-    float q0, q1, q2, q3, q4, q5, q6, q7, q8;
-    {
-        const int o = (W.z0 - kHalo) * P + j;
-        q0 = valid ? cu[o] : 0.0f;
-        q1 = valid ? cu[o + P] : 0.0f;
-        q2 = valid ? cu[o + 2 * P] : 0.0f;
-        q3 = valid ? cu[o + 3 * P] : 0.0f;
-        q4 = valid ? cu[o + 4 * P] : 0.0f;
-        q5 = valid ? cu[o + 5 * P] : 0.0f;
-        q6 = valid ? cu[o + 6 * P] : 0.0f;
-        q7 = valid ? cu[o + 7 * P] : 0.0f;
+    bool valid[CW];
+    int jm[CW];
+    float dx2[CW], ax[CW], bx[CW];
+#pragma unroll
+    for (int k = 0; k < CW; ++k) {
+        const int j = j0 + k;
+        valid[k] = j < S.NX;
+        jm[k] = S.x0 + clampi(j - nb, 0, S.wnx - 1);
+        const int ddx = max(max(nb - j, j - (S.NX - 1 - nb)), 0);
+        dx2[k] = float(ddx * ddx);
+        const float sh = A.hs * dx2[k];
+        ax[k] = sponge_a(sh);
+        bx[k] = (1.0f - sh) * ax[k];
     }
+    // halo: lane 0 reads the 4 columns left of the strip, lane 1 the 4
+    // columns right of it (a zero column block when past the shot's width)
+    const int hcol = lane == 0 ? W.col0 - kHalo : min(W.col0 + SW, P - kHalo);
+
+    float q[9][CW];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) ld<CW>(cu + (W.z0 - kHalo + r + kRowsAbove) * P + jl, q[r]);
+
+    // prefetched values of the row being computed
+    float nq[CW], npv[CW], nv[CW], nd[CW], ng[CW];
+    float4 nh = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto prefetch = [&](int z) {
+        const int o = (z + kRowsAbove) * P + jl;
+        ld<CW>(cu + o + kHalo * P, nq);
+        ld<CW>(pv + o, npv);
+        if (lane < 2) nh = *reinterpret_cast<const float4 *>(cu + (z + kRowsAbove) * P + hcol);
+        const int mrow = clampi(z - nb, 0, A.nz - 1) * A.nx;
+#pragma unroll
+        for (int k = 0; k < CW; ++k) nv[k] = vmod[mrow + jm[k]];
+        if (FL & F_IMAGE) {
+            ld<CW>(db + z * P + jl, nd);
+            ld<CW>(gb + z * P + jl, ng);
+        }
+    };
+    prefetch(W.z0);
+
     int rr = W.rr0;
     int rrow = -1;
     if (FL & (F_SAMPLE | F_INJECT)) rrow = rr < W.rr1 ? A.rrows[rr].row : -1;
-    const bool src_here = (FL & F_SRC) && S.src_j == j;
     const float wsrc = (FL & F_SRC) ? A.wav[S.wav_off + A.n] * A.ih2 : 0.0f;
+    const int src_k = S.src_j - j0;          // column of the source in this lane, if 0..CW-1
 
     for (int z = W.z0; z < W.z1; ++z) {
-        const int o = z * P + j;
-        q8 = valid ? cu[o + kHalo * P] : 0.0f;
-        row[lane + kHalo] = q4;
-        if (lane < 2 * kHalo) {
-            const int c = lane < kHalo ? W.col0 - kHalo + lane : W.col0 + kLanes - kHalo + lane;
-            row[lane < kHalo ? lane : lane + kLanes] = (c < P) ? cu[z * P + c] : 0.0f;
+        float cpv[CW], cv[CW], cd[CW], cg[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            q[8][k] = nq[k];
+            cpv[k] = npv[k];
+            cv[k] = nv[k];
+            if (FL & F_IMAGE) {
+                cd[k] = nd[k];
+                cg[k] = ng[k];
+            }
         }
+        const float4 ch = nh;
+        if (z + 1 < W.z1) prefetch(z + 1);
+
+        // centre row into LDS, then the horizontal neighbours back out
+        if constexpr (CW == 1) row[kHalo + lane] = q[4][0];
+        else *reinterpret_cast<float2 *>(&row[kHalo + CW * lane]) = make_float2(q[4][0], q[4][1]);
+        if (lane < 2) *reinterpret_cast<float4 *>(&row[lane == 0 ? 0 : kHalo + SW]) = ch;
         wave_sync();
-        float lap = A.w0 * q4 + A.w1 * ((q3 + q5) + (row[lane + 3] + row[lane + 5])) +
-                    A.w2 * ((q2 + q6) + (row[lane + 2] + row[lane + 6])) +
-                    A.w3 * ((q1 + q7) + (row[lane + 1] + row[lane + 7])) +
-                    A.w4 * ((q0 + q8) + (row[lane] + row[lane + 8]));
+        float xr[CW + 2 * kHalo];
+#pragma unroll
+        for (int m = 0; m < CW + 2 * kHalo; ++m) xr[m] = row[CW * lane + m];
         wave_sync();
-        if (FL & F_SRC)
-            if (src_here && z == S.src_i) lap += wsrc;
-        int qi = -1;
+
+        int qi[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) qi[k] = -1;
         if (FL & (F_SAMPLE | F_INJECT)) {
             if (z == rrow) {
-                qi = A.rmap[A.rrows[rr].map_off + lane];
+                const int mo = A.rrows[rr].map_off + CW * lane;
+#pragma unroll
+                for (int k = 0; k < CW; ++k) qi[k] = A.rmap[mo + k];
                 ++rr;
                 rrow = rr < W.rr1 ? A.rrows[rr].row : -1;
             }
-            if (FL & F_INJECT)
-                if (qi >= 0) lap += A.inj[qi];
         }
-        const float V = A.v[clampi(z - nb, 0, A.nz - 1) * A.nx + jm];
-        const float c = V * V * A.dt2;
-        float a = ax, b = bx;
         const int ddz = max(max(nb - z, z - (A.NZ - 1 - nb)), 0);
-        if (ddz > 0) {
-            const float sh = A.hs * (float(ddz * ddz) + dx2);
-            a = sponge_a(sh);
-            b = (1.0f - sh) * a;
+        const float dz2 = float(ddz * ddz);
+        float out[CW], Dv[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            float lap = A.w0 * q[4][k] +
+                        A.w1 * ((q[3][k] + q[5][k]) + (xr[k + 3] + xr[k + 5])) +
+                        A.w2 * ((q[2][k] + q[6][k]) + (xr[k + 2] + xr[k + 6])) +
+                        A.w3 * ((q[1][k] + q[7][k]) + (xr[k + 1] + xr[k + 7])) +
+                        A.w4 * ((q[0][k] + q[8][k]) + (xr[k] + xr[k + 8]));
+            if (FL & F_SRC)
+                if (src_k == k && z == S.src_i) lap += wsrc;
+            if (FL & F_INJECT)
+                if (qi[k] >= 0) lap += A.inj[qi[k]];
+            const float c = cv[k] * cv[k] * A.dt2;
+            float a = ax[k], b = bx[k];
+            if (ddz > 0) {
+                const float sh = A.hs * (dz2 + dx2[k]);
+                a = sponge_a(sh);
+                b = (1.0f - sh) * a;
+            }
+            Dv[k] = c * lap;
+            out[k] = a * (2.0f * q[4][k] + Dv[k]) - b * cpv[k];
         }
-        const float D = c * lap;
-        if (valid) {
-            const float out = a * (2.0f * q4 + D) - b * pv[o];
-            pv[o] = out;
-            if (FL & F_EMIT) A.dslot[goff + o] = D;
-            if (FL & F_IMAGE) A.G[goff + o] += out * A.dslot[goff + o];
-            if (FL & F_SAMPLE)
-                if (qi >= 0) A.samp[qi] = out;
+        const int o = (z + kRowsAbove) * P + j0;
+        const int og = z * P + j0;
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            if (valid[k]) {
+                pv[o + k] = out[k];
+                if (FL & F_EMIT) db[og + k] = Dv[k];
+                if (FL & F_IMAGE) gb[og + k] = cg[k] + out[k] * cd[k];
+                if (FL & F_SAMPLE)
+                    if (qi[k] >= 0) A.samp[qi[k]] = out[k];
+            }
         }
-        q0 = q1; q1 = q2; q2 = q3; q3 = q4; q4 = q5; q5 = q6; q6 = q7; q7 = q8;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int k = 0; k < CW; ++k) q[r][k] = q[r + 1][k];
     }
 }
 
@@ -146,9 +221,13 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
 // two equations are solved jointly so that u is never stored):
 //   du^{n+1} = a (2 du^n + V^2 dt^2 L8 du^n + 2 V dV dt^2 (L8 u^n + s^n)) - b du^{n-1}
 // where 2 V dV dt^2 = (2 dV / V) V^2 dt^2 is the linearised 1/V^2 term.
+// Same tiling and prefetching as k_step; receivers record du^{n+1}.
+template <int CW>
 __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const StepArgs A)
 {
-    __shared__ float lds[kWavesPerBlock][2][kLanes + 2 * kHalo];
+    constexpr int SW = kLanes * CW;
+    constexpr int RW = SW + 2 * kHalo;
+    __shared__ float lds[kWavesPerBlock][2][RW];
     const int lane = threadIdx.x & (kLanes - 1);
     const int wl = threadIdx.x / kLanes;
     const int wid = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wl;
@@ -158,90 +237,150 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
     const WaveDesc W = A.waves[wid];
     const ShotDesc S = A.shots[W.shot];
     const int P = S.P;
-    const int j = W.col0 + lane;
-    const bool valid = j < S.NX;
     const int nb = A.nb;
-    const int jm = S.x0 + clampi(j - nb, 0, S.wnx - 1);
-    const int ddx = max(max(nb - j, j - (S.NX - 1 - nb)), 0);
-    const float dx2 = float(ddx * ddx);
-    float ax = 1.0f, bx = 1.0f;
-    if (ddx > 0) {
-        const float sh = A.hs * dx2;
-        ax = sponge_a(sh);
-        bx = (1.0f - sh) * ax;
-    }
-    const float *cu = A.cur + S.f_off;
-    float *pv = A.prev + S.f_off;
-    const float *cd = A.cur2 + S.f_off;
-    float *pd = A.prev2 + S.f_off;
+    const int j0 = W.col0 + CW * lane;
+    const int jl = min(j0, P - 2);
+    const int64_t base = S.f_off - int64_t(kRowsAbove) * P;
+    const float *cu = A.cur + base;
+    float *pv = A.prev + base;
+    const float *cd = A.cur2 + base;
+    float *pd = A.prev2 + base;
 
-    float q[9], r[9];
-    {
-        const int o = (W.z0 - kHalo) * P + j;
+    bool valid[CW];
+    int jm[CW];
+    float dx2[CW], ax[CW], bx[CW];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            q[k] = valid ? cu[o + k * P] : 0.0f;
-            r[k] = valid ? cd[o + k * P] : 0.0f;
-        }
+    for (int k = 0; k < CW; ++k) {
+        const int j = j0 + k;
+        valid[k] = j < S.NX;
+        jm[k] = S.x0 + clampi(j - nb, 0, S.wnx - 1);
+        const int ddx = max(max(nb - j, j - (S.NX - 1 - nb)), 0);
+        dx2[k] = float(ddx * ddx);
+        const float sh = A.hs * dx2[k];
+        ax[k] = sponge_a(sh);
+        bx[k] = (1.0f - sh) * ax[k];
     }
+    const int hcol = lane == 0 ? W.col0 - kHalo : min(W.col0 + SW, P - kHalo);
+
+    float q[9][CW], r[9][CW];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        ld<CW>(cu + (W.z0 - kHalo + k + kRowsAbove) * P + jl, q[k]);
+        ld<CW>(cd + (W.z0 - kHalo + k + kRowsAbove) * P + jl, r[k]);
+    }
+    float nq[CW], nr[CW], npv[CW], npd[CW], nv[CW], ndv[CW];
+    float4 nh = make_float4(0.f, 0.f, 0.f, 0.f), nhd = nh;
+    auto prefetch = [&](int z) {
+        const int o = (z + kRowsAbove) * P + jl;
+        ld<CW>(cu + o + kHalo * P, nq);
+        ld<CW>(cd + o + kHalo * P, nr);
+        ld<CW>(pv + o, npv);
+        ld<CW>(pd + o, npd);
+        if (lane < 2) {
+            nh = *reinterpret_cast<const float4 *>(cu + (z + kRowsAbove) * P + hcol);
+            nhd = *reinterpret_cast<const float4 *>(cd + (z + kRowsAbove) * P + hcol);
+        }
+        const int mrow = clampi(z - nb, 0, A.nz - 1) * A.nx;
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            nv[k] = A.v[mrow + jm[k]];
+            ndv[k] = A.dv[mrow + jm[k]];
+        }
+    };
+    prefetch(W.z0);
+
     int rr = W.rr0;
     int rrow = rr < W.rr1 ? A.rrows[rr].row : -1;
-    const bool src_here = S.src_j == j;
     const float wsrc = A.wav[S.wav_off + A.n] * A.ih2;
+    const int src_k = S.src_j - j0;
 
     for (int z = W.z0; z < W.z1; ++z) {
-        const int o = z * P + j;
-        q[8] = valid ? cu[o + kHalo * P] : 0.0f;
-        r[8] = valid ? cd[o + kHalo * P] : 0.0f;
-        row[lane + kHalo] = q[4];
-        rod[lane + kHalo] = r[4];
-        if (lane < 2 * kHalo) {
-            const int c = lane < kHalo ? W.col0 - kHalo + lane : W.col0 + kLanes - kHalo + lane;
-            const int li = lane < kHalo ? lane : lane + kLanes;
-            row[li] = (c < P) ? cu[z * P + c] : 0.0f;
-            rod[li] = (c < P) ? cd[z * P + c] : 0.0f;
+        float cpv[CW], cpd[CW], cv[CW], cdv[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            q[8][k] = nq[k];
+            r[8][k] = nr[k];
+            cpv[k] = npv[k];
+            cpd[k] = npd[k];
+            cv[k] = nv[k];
+            cdv[k] = ndv[k];
+        }
+        const float4 ch = nh, chd = nhd;
+        if (z + 1 < W.z1) prefetch(z + 1);
+
+        if constexpr (CW == 1) {
+            row[kHalo + lane] = q[4][0];
+            rod[kHalo + lane] = r[4][0];
+        } else {
+            *reinterpret_cast<float2 *>(&row[kHalo + CW * lane]) = make_float2(q[4][0], q[4][1]);
+            *reinterpret_cast<float2 *>(&rod[kHalo + CW * lane]) = make_float2(r[4][0], r[4][1]);
+        }
+        if (lane < 2) {
+            *reinterpret_cast<float4 *>(&row[lane == 0 ? 0 : kHalo + SW]) = ch;
+            *reinterpret_cast<float4 *>(&rod[lane == 0 ? 0 : kHalo + SW]) = chd;
         }
         wave_sync();
-        float lap = A.w0 * q[4] + A.w1 * ((q[3] + q[5]) + (row[lane + 3] + row[lane + 5])) +
-                    A.w2 * ((q[2] + q[6]) + (row[lane + 2] + row[lane + 6])) +
-                    A.w3 * ((q[1] + q[7]) + (row[lane + 1] + row[lane + 7])) +
-                    A.w4 * ((q[0] + q[8]) + (row[lane] + row[lane + 8]));
-        const float lapd = A.w0 * r[4] + A.w1 * ((r[3] + r[5]) + (rod[lane + 3] + rod[lane + 5])) +
-                           A.w2 * ((r[2] + r[6]) + (rod[lane + 2] + rod[lane + 6])) +
-                           A.w3 * ((r[1] + r[7]) + (rod[lane + 1] + rod[lane + 7])) +
-                           A.w4 * ((r[0] + r[8]) + (rod[lane] + rod[lane + 8]));
+        float xr[CW + 2 * kHalo], xd[CW + 2 * kHalo];
+#pragma unroll
+        for (int m = 0; m < CW + 2 * kHalo; ++m) {
+            xr[m] = row[CW * lane + m];
+            xd[m] = rod[CW * lane + m];
+        }
         wave_sync();
-        if (src_here && z == S.src_i) lap += wsrc;
-        int qi = -1;
+
+        int qi[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) qi[k] = -1;
         if (z == rrow) {
-            qi = A.rmap[A.rrows[rr].map_off + lane];
+            const int mo = A.rrows[rr].map_off + CW * lane;
+#pragma unroll
+            for (int k = 0; k < CW; ++k) qi[k] = A.rmap[mo + k];
             ++rr;
             rrow = rr < W.rr1 ? A.rrows[rr].row : -1;
         }
-        const int mi = clampi(z - nb, 0, A.nz - 1) * A.nx + jm;
-        const float V = A.v[mi];
-        const float dV = A.dv[mi];
-        const float c = V * V * A.dt2;
-        const float cr = 2.0f * V * dV * A.dt2;
-        float a = ax, b = bx;
         const int ddz = max(max(nb - z, z - (A.NZ - 1 - nb)), 0);
-        if (ddz > 0) {
-            const float sh = A.hs * (float(ddz * ddz) + dx2);
-            a = sponge_a(sh);
-            b = (1.0f - sh) * a;
+        const float dz2 = float(ddz * ddz);
+        float ou[CW], od[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            float lap = A.w0 * q[4][k] +
+                        A.w1 * ((q[3][k] + q[5][k]) + (xr[k + 3] + xr[k + 5])) +
+                        A.w2 * ((q[2][k] + q[6][k]) + (xr[k + 2] + xr[k + 6])) +
+                        A.w3 * ((q[1][k] + q[7][k]) + (xr[k + 1] + xr[k + 7])) +
+                        A.w4 * ((q[0][k] + q[8][k]) + (xr[k] + xr[k + 8]));
+            const float lapd = A.w0 * r[4][k] +
+                               A.w1 * ((r[3][k] + r[5][k]) + (xd[k + 3] + xd[k + 5])) +
+                               A.w2 * ((r[2][k] + r[6][k]) + (xd[k + 2] + xd[k + 6])) +
+                               A.w3 * ((r[1][k] + r[7][k]) + (xd[k + 1] + xd[k + 7])) +
+                               A.w4 * ((r[0][k] + r[8][k]) + (xd[k] + xd[k + 8]));
+            if (src_k == k && z == S.src_i) lap += wsrc;
+            const float c = cv[k] * cv[k] * A.dt2;
+            const float cr = 2.0f * cv[k] * cdv[k] * A.dt2;
+            float a = ax[k], b = bx[k];
+            if (ddz > 0) {
+                const float sh = A.hs * (dz2 + dx2[k]);
+                a = sponge_a(sh);
+                b = (1.0f - sh) * a;
+            }
+            ou[k] = a * (2.0f * q[4][k] + c * lap) - b * cpv[k];
+            od[k] = a * (2.0f * r[4][k] + c * lapd + cr * lap) - b * cpd[k];
         }
-        if (valid) {
-            const float ou = a * (2.0f * q[4] + c * lap) - b * pv[o];
-            const float od = a * (2.0f * r[4] + c * lapd + cr * lap) - b * pd[o];
-            pv[o] = ou;
-            pd[o] = od;
-            if (qi >= 0) A.samp[qi] = od;
+        const int o = (z + kRowsAbove) * P + j0;
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            if (valid[k]) {
+                pv[o + k] = ou[k];
+                pd[o + k] = od[k];
+                if (qi[k] >= 0) A.samp[qi[k]] = od[k];
+            }
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            q[k] = q[k + 1];
-            r[k] = r[k + 1];
-        }
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int k = 0; k < CW; ++k) {
+                q[m][k] = q[m + 1][k];
+                r[m][k] = r[m + 1][k];
+            }
     }
 }
 
@@ -384,25 +523,25 @@ inline int blocks_for(int nwaves) { return (nwaves + kWavesPerBlock - 1) / kWave
 
 }  // namespace
 
-hipError_t launch_step(int flags, const StepArgs &a, hipStream_t s)
+template <int CW>
+hipError_t launch_step_cw(int flags, const StepArgs &a, hipStream_t s)
 {
-    if (a.nwaves <= 0) return hipSuccess;
     const dim3 grid(blocks_for(a.nwaves)), block(kLanes * kWavesPerBlock);
     switch (flags) {
     case F_SRC | F_SAMPLE:
-        hipLaunchKernelGGL(k_step<F_SRC | F_SAMPLE>, grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SRC | F_SAMPLE, CW>), grid, block, 0, s, a);
         break;
     case F_SRC:
-        hipLaunchKernelGGL(k_step<F_SRC>, grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SRC, CW>), grid, block, 0, s, a);
         break;
     case F_SRC | F_SAMPLE | F_EMIT:
-        hipLaunchKernelGGL(k_step<F_SRC | F_SAMPLE | F_EMIT>, grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SRC | F_SAMPLE | F_EMIT, CW>), grid, block, 0, s, a);
         break;
     case F_SRC | F_EMIT:
-        hipLaunchKernelGGL(k_step<F_SRC | F_EMIT>, grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SRC | F_EMIT, CW>), grid, block, 0, s, a);
         break;
     case F_INJECT | F_IMAGE:
-        hipLaunchKernelGGL(k_step<F_INJECT | F_IMAGE>, grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_INJECT | F_IMAGE, CW>), grid, block, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -410,10 +549,19 @@ hipError_t launch_step(int flags, const StepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_step(int flags, const StepArgs &a, hipStream_t s)
+{
+    if (a.nwaves <= 0) return hipSuccess;
+    return a.cw == 2 ? launch_step_cw<2>(flags, a, s) : launch_step_cw<1>(flags, a, s);
+}
+
 hipError_t launch_born_step(const StepArgs &a, hipStream_t s)
 {
     if (a.nwaves <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_born_step, dim3(blocks_for(a.nwaves)), dim3(kLanes * kWavesPerBlock), 0, s, a);
+    if (a.cw == 2)
+        hipLaunchKernelGGL(k_born_step<2>, dim3(blocks_for(a.nwaves)), dim3(kLanes * kWavesPerBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_born_step<1>, dim3(blocks_for(a.nwaves)), dim3(kLanes * kWavesPerBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -65,6 +65,7 @@ struct StepArgs {
     const float *dv;     // Born perturbation [nz][nx]
     const float *wav;    // wavelets
     int32_t nwaves, nz, nx, nb, NZ;
+    int32_t cw;                // columns per lane of the wave table (1 or 2)
     float w0, w1, w2, w3, w4;  // 2 c0 / h^2, c_k / h^2
     float dt2;                 // dt^2
     float hs;                  // smax dt / (2 nb^2): sigma dt/2 = hs (dz^2 + dx^2)

@@ -64,6 +64,14 @@ class FwiContext:
     def set_profiling(self, on: bool):
         _check(self.lib, self.ctx, self.lib.fwi_ctx_set_profiling(self.ctx, 1 if on else 0))
 
+    def set_tiling(self, kernel: int = -1, cols_per_lane: int = 0, rows_per_wave: int = 0):
+        """Force the step-kernel tiling (kernel 0 fwd, 1 adj, 2 Born, -1 all);
+        (0, 0) hands it back to the autotuner."""
+        _check(self.lib, self.ctx, self.lib.fwi_ctx_set_tiling(self.ctx, kernel, cols_per_lane, rows_per_wave))
+
+    def set_autotune(self, on: bool):
+        _check(self.lib, self.ctx, self.lib.fwi_ctx_set_autotune(self.ctx, 1 if on else 0))
+
     def stats(self) -> dict:
         s = _abi.fwi_stats()
         _check(self.lib, self.ctx, self.lib.fwi_ctx_get_stats(self.ctx, C.byref(s)))

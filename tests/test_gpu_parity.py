@@ -236,3 +236,48 @@ def test_empty_and_degenerate(ctx):
     for gg in (g0, grid):
         d = host(ctx.fwi_forward(gg, acq3, dev(v)))
         assert rel(d, oracle.forward(gg, acq3, v)) < TOL_DATA
+
+
+@pytest.mark.parametrize("cw,rows", [(1, 7), (2, 13), (1, 300), (2, 5)])
+def test_forced_tilings_match_oracle_and_each_other(ctx, ragged, cw, rows):
+    """Every tiling computes each cell with the same arithmetic, so results
+    are bitwise equal across tilings and match the oracle."""
+    wl = ragged
+    g, acq = wl.grid, wl.acq
+    print(f"[parity] tiling cw={cw} rows={rows}", flush=True)
+    v = dev(wl.v_true)
+    v0 = dev(wl.v0)
+    rng = np.random.default_rng(5)
+    y = dev(rng.standard_normal(acq.data_size(g)))
+    dv = dev(wl.v_true - wl.v0)
+
+    def run():
+        d = host(ctx.fwi_forward(g, acq, v))
+        gg = host(ctx.fwi_gradient(g, acq, v0, dev(d * 0.5))[0])
+        dd = host(ctx.born_demig(g, acq, v0, dv))
+        im = host(ctx.born_mig(g, acq, v0, y))
+        return d, gg, dd, im
+
+    ctx.set_tiling(-1, 1, 30)
+    ref = run()
+    ctx.set_tiling(-1, cw, rows)
+    got = run()
+    st = ctx.stats()
+    ctx.set_tiling(-1, 0, 0)
+    assert st["tile_cw"] == [cw] * 3 and st["tile_rows"] == [rows] * 3
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+    v64 = f32(wl.v_true).astype(np.float64)
+    assert rel(got[0], oracle.forward(g, acq, v64)) < TOL_DATA
+    assert rel(got[3], oracle.born_mig(g, acq, f32(wl.v0).astype(np.float64),
+                                       host(y))) < TOL_IMAGE
+
+
+def test_autotuner_picks_a_valid_tiling(ctx, two_layer):
+    wl, v_true, v0, d_obs = two_layer
+    ctx.set_tiling(-1, 0, 0)
+    ctx.set_autotune(True)
+    ctx.fwi_forward(wl.grid, wl.acq, dev(v0))
+    st = ctx.stats()
+    assert all(c in (1, 2) for c in st["tile_cw"])
+    assert all(r >= 1 for r in st["tile_rows"])
