@@ -21,6 +21,21 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc runs
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a plain 1 GiB copy;
+# see profiles/stencil_kernels_layered_600x200_hbm_counters.md). Valid only
+# for the kernel source it was measured on: reported as null otherwise.
+MEASURED_TRAFFIC = {
+    "stencil_adj": {"bytes": 265.5e6, "kernels_sha1": "6422529dde323a5a46cbd29c7b0d9246df9b28c5"},
+}
+
+
+def kernels_sha1() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_2403_17518_amd", "csrc", "fwi_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -30,10 +45,26 @@ def parse():
     ap.add_argument("--shots", type=int, default=64)
     ap.add_argument("--nt", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-shots", type=int, default=4)
-    ap.add_argument("--cpu-nt", type=int, default=400)
+    ap.add_argument("--cpu-shots", type=int, default=16)
+    ap.add_argument("--cpu-nt", type=int, default=1500)
     ap.add_argument("--mem-budget-gb", type=float, default=0.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain device copy of known size (HBM counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain 1 GiB device-to-device copy, three times: the reference for
+    scaling the FETCH_SIZE / WRITE_SIZE counters of the stencil kernels."""
+    import torch
+    n = 1 << 28
+    x = torch.ones(n, device="cuda", dtype=torch.float32)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": 4 * n, "copies": 3}), flush=True)
 
 
 def cpu_baseline(args):
@@ -61,6 +92,9 @@ def cpu_baseline(args):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -84,8 +118,11 @@ def main():
 
     acc = {}
 
+    st_last = {}
+
     def add_stats():
         s = ctx.stats()
+        st_last.update(s)
         for k in ("cell_updates", "ms_fwd", "ms_adj", "ms_born", "n_fwd", "n_adj", "n_born",
                   "bytes_fwd", "bytes_adj", "bytes_born"):
             acc[k] = acc.get(k, 0.0) + s[k]
@@ -130,6 +167,8 @@ def main():
     dom = max(kinds, key=lambda k: acc.get(kinds[k][0], 0.0))
     kms, kn, kb = (acc[x] for x in kinds[dom])
     achieved = (kb / kn) / ((kms / kn) * 1e-3) / 1e9
+    meas = MEASURED_TRAFFIC.get(dom)
+    traffic = meas["bytes"] if meas and meas["kernels_sha1"] == kernels_sha1() else None
     out = {
         "metric": "FD cell-updates/s & % HBM roofline; FWI iters+time to model error vs plain",
         "value": value,
@@ -153,10 +192,12 @@ def main():
             "executed_cell_updates_per_step": acc["cell_updates"] / args.steps,
             "useful_cell_updates_per_step": useful,
             "wall_s": wall,
+            "tiles_cols_rows": {k: [st_last["tile_cw"][i], st_last["tile_rows"][i]]
+                                for i, k in enumerate(("fwd", "adj", "born"))},
         },
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "avg_launch_us": kms / kn * 1e3, "launches": int(kn),
             "bytes_per_launch": kb / kn,
             "kernel_ms": {k: acc[v[0]] / args.steps for k, v in kinds.items()},

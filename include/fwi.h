@@ -107,7 +107,7 @@ typedef struct {
     int32_t n_segments;       /* adjoint segments (recompute passes + 1) */
     int64_t scratch_bytes;    /* device scratch held by the context */
     /* kernel timings, valid only when profiling is enabled (ms, summed
-       over launches) */
+       over runs of consecutive launches of one class) */
     double ms_fwd, ms_adj, ms_born, ms_other;
     int64_t n_fwd, n_adj, n_born;
     double bytes_fwd, bytes_adj, bytes_born; /* algorithmic bytes moved */
@@ -122,9 +122,15 @@ int fwi_ctx_create(int device, void *hip_stream, fwi_ctx **out);
 void fwi_ctx_destroy(fwi_ctx *ctx);
 int fwi_ctx_set_stream(fwi_ctx *ctx, void *hip_stream);
 /* Upper bound on device memory used for checkpoints and the stored
- * imaging-condition history (bytes); 0 = 40% of the device memory. */
+ * imaging-condition history (bytes); 0 = 70% of the device memory. The
+ * adjoint sweeps store D^n for every step when it fits (no recompute) and
+ * otherwise checkpoint; they never plan beyond the memory free at the call
+ * minus a 4 GiB margin. */
 int fwi_ctx_set_mem_budget(fwi_ctx *ctx, int64_t bytes);
-/* 1 = time every kernel launch with HIP events (adds a sync per call). */
+/* 1 = time the propagation kernels with HIP events recorded around every
+ * run of consecutive launches of one kernel class (forward, adjoint, Born),
+ * so the reported per-launch time includes the (small) gaps between
+ * back-to-back launches; adds a stream sync at the end of each call. */
 int fwi_ctx_set_profiling(fwi_ctx *ctx, int enable);
 /* Tiling of the step kernels. kernel: 0 forward, 1 adjoint, 2 Born, -1 all;
  * cols_per_lane 1 or 2 and rows_per_wave >= 1 force a tiling; (0, 0)

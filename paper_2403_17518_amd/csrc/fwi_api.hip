@@ -21,6 +21,8 @@ using namespace fwi;
 namespace {
 
 constexpr double kCflLimit = 0.55;     // 2D 8th-order leapfrog limit is 0.5546
+constexpr double kDefaultBudgetFrac = 0.7;  // of device memory, for D^n history + checkpoints
+constexpr int64_t kFreeMargin = int64_t(4) << 30;  // left free when sizing the history
 constexpr int kDefaultCw = 2;          // tiling used when autotuning is off
 constexpr int kDefaultRows = 16;
 
@@ -508,10 +510,7 @@ int fwd_step(fwi_ctx *c, StepArgs a, int flags, int n, float *F0, float *F1)
     a.nwaves = c->tile[K_FWD].prefix[p.active_slots(n)];
     a.cur = (n % 2 == 0) ? F0 : F1;
     a.prev = (n % 2 == 0) ? F1 : F0;
-    int rc = ev_begin(c, K_FWD);
-    if (rc) return rc;
     HIPCHK(c, launch_step(flags, a, c->stream));
-    if ((rc = ev_end(c))) return rc;
     const double upd = step_updates(p, n);
     c->stats.cell_updates += upd;
     c->stats.stencil_launches += 1;
@@ -528,10 +527,7 @@ int adj_step(fwi_ctx *c, StepArgs a, int n, float *A0, float *A1)
     // lambda^{n+1} lives in A[(n+1)%2], lambda^{n+2} (overwritten by lambda^n) in A[n%2]
     a.cur = ((n + 1) % 2 == 0) ? A0 : A1;
     a.prev = (n % 2 == 0) ? A0 : A1;
-    int rc = ev_begin(c, K_ADJ);
-    if (rc) return rc;
     HIPCHK(c, launch_step(F_INJECT | F_IMAGE, a, c->stream));
-    if ((rc = ev_end(c))) return rc;
     const double upd = step_updates(p, n);
     c->stats.cell_updates += upd;
     c->stats.stencil_launches += 1;
@@ -571,7 +567,14 @@ int choose_segments(fwi_ctx *c, int *k_out, int *nseg_out)
     int k;
     if (p.ckpt_every > 0) k = std::min(p.ckpt_every, nt);
     else {
-        const double budget = double(c->budget);
+        // never plan beyond what is free now (plus what this context already
+        // holds for the same purpose), keeping a margin for the caller
+        size_t fr = 0, tot = 0;
+        double budget = double(c->budget);
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+            const double avail = double(fr) + double(c->dhist.bytes) + double(c->ckpt.bytes) - double(kFreeMargin);
+            budget = std::min(budget, std::max(avail, 0.0));
+        }
         k = nt;
         if (mem(k) > budget) {
             k = int(std::max(1.0, std::min(double(nt), std::floor(budget / std::max(slot, 1.0)))));
@@ -620,6 +623,7 @@ int forward_for_adjoint(fwi_ctx *c, const float *v, bool sample, Sweep &w)
     if ((rc = other(c, launch_fill(w.F0, 2 * ff, 0.f, st), "fill"))) return rc;
     StepArgs a = base_args(c, v, K_FWD);
     const int last0 = (nseg - 1) * k;
+    if ((rc = ev_begin(c, K_FWD))) return rc;
     for (int n = 0; n < p.nt_max; ++n) {
         if (n % k == 0 && n / k < nseg - 1) {
             float *ckp = w.CK + size_t(n / k) * 2 * ff;
@@ -636,7 +640,7 @@ int forward_for_adjoint(fwi_ctx *c, const float *v, bool sample, Sweep &w)
         }
         if ((rc = fwd_step(c, a, fl, n, w.F0, w.F1))) return rc;
     }
-    return FWI_OK;
+    return ev_end(c);
 }
 
 // Backward sweep: for every segment, last to first, recompute D^n from its
@@ -661,16 +665,20 @@ int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
         if (sgi != nseg - 1) {
             HIPCHK(c, hipMemcpyAsync(w.F0, w.CK + size_t(sgi) * 2 * ff, size_t(2 * ff) * 4,
                                      hipMemcpyDeviceToDevice, st));
+            if ((rc = ev_begin(c, K_FWD))) return rc;
             for (int n = lo; n < hi; ++n) {
                 af.dslot = w.Dh + size_t(n - lo) * gf;
                 if ((rc = fwd_step(c, af, F_SRC | F_EMIT, n, w.F0, w.F1))) return rc;
             }
+            if ((rc = ev_end(c))) return rc;
         }
+        if ((rc = ev_begin(c, K_ADJ))) return rc;
         for (int n = hi - 1; n >= lo; --n) {
             a.dslot = w.Dh + size_t(n - lo) * gf;
             a.inj = inj + size_t(n) * p.Q;
             if ((rc = adj_step(c, a, n, w.A0, w.A1))) return rc;
         }
+        if ((rc = ev_end(c))) return rc;
     }
     FinalArgs fa{};
     fa.shots = static_cast<const ShotDesc *>(c->d_shots.p);
@@ -683,7 +691,9 @@ int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
     fa.NZ = p.NZ;
     fa.dt2 = float(double(p.dt) * p.dt);
     fa.img = img;
-    return other(c, launch_finalize(fa, st), "finalize");
+    int max_nx = 0;
+    for (const ShotDesc &d : p.shots) max_nx = std::max(max_nx, d.NX);
+    return other(c, launch_finalize(fa, max_nx, st), "finalize");
 }
 
 TraceArgs trace_args(fwi_ctx *c)
@@ -859,11 +869,12 @@ int forward_sweep_sampled(fwi_ctx *c, const float *v)
     float *samp = static_cast<float *>(c->samples.p);
     if ((rc = other(c, launch_fill(F0, 2 * ff, 0.f, c->stream), "fill"))) return rc;
     StepArgs a = base_args(c, v, K_FWD);
+    if ((rc = ev_begin(c, K_FWD))) return rc;
     for (int n = 0; n < p.nt_max; ++n) {
         a.samp = samp + size_t(n) * p.Q;
         if ((rc = fwd_step(c, a, F_SRC | F_SAMPLE, n, F0, F1))) return rc;
     }
-    return FWI_OK;
+    return ev_end(c);
 }
 
 }  // namespace
@@ -885,7 +896,7 @@ int fwi_ctx_create(int device, void *hip_stream, fwi_ctx **out)
     c->stream = static_cast<hipStream_t>(hip_stream);
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = size_t(64) << 30;
-    c->budget = int64_t(0.4 * double(tot));
+    c->budget = int64_t(kDefaultBudgetFrac * double(tot));
     if (hipHostMalloc(reinterpret_cast<void **>(&c->h_check), 4 * sizeof(float), hipHostMallocDefault) !=
             hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&c->h_misfit), sizeof(double), hipHostMallocDefault) !=
@@ -926,7 +937,7 @@ int fwi_ctx_set_mem_budget(fwi_ctx *c, int64_t bytes)
     if (bytes == 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = size_t(64) << 30;
-        bytes = int64_t(0.4 * double(tot));
+        bytes = int64_t(kDefaultBudgetFrac * double(tot));
     }
     c->budget = bytes;
     return FWI_OK;
@@ -1063,6 +1074,7 @@ int born_demig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *
     StepArgs a = base_args(c, v0, K_BORN);
     a.dv = dv;
     float *U0 = F, *U1 = F + ff, *D0 = F + 2 * ff, *D1 = F + 3 * ff;
+    if ((rc = ev_begin(c, K_BORN))) return rc;
     for (int n = 0; n < p.nt_max; ++n) {
         a.n = n;
         a.nwaves = c->tile[K_BORN].prefix[p.active_slots(n)];
@@ -1071,15 +1083,14 @@ int born_demig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *
         a.cur2 = n % 2 == 0 ? D0 : D1;
         a.prev2 = n % 2 == 0 ? D1 : D0;
         a.samp = samp + size_t(n) * p.Q;
-        if ((rc = ev_begin(c, K_BORN))) return rc;
         HIPCHK(c, launch_born_step(a, c->stream));
-        if ((rc = ev_end(c))) return rc;
         const double upd = step_updates(p, n);
         c->stats.cell_updates += 2 * upd;
         c->stats.stencil_launches += 1;
         c->stats.n_born += 1;
         c->stats.bytes_born += upd * kBytesBorn;
     }
+    if ((rc = ev_end(c))) return rc;
     TraceArgs t = trace_args(c);
     t.tm_in = samp;
     t.alpha = 1.f;

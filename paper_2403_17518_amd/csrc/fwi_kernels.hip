@@ -493,27 +493,66 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *p, int64_t n
     if (threadIdx.x == 0) *out = s[0];
 }
 
-// img = (2 / (v^3 dt^2)) sum_shots Pad^T G_s. Pad^T folds every sponge cell
-// onto the edge cell whose value it replicates; shots are summed in slot
-// order, so the result does not depend on scheduling.
+// Pad^T, first half: fold the top and bottom sponge rows of every shot's G
+// onto the first and last physical rows (one thread per shot column), then
+// the left and right sponge columns onto the first and last physical columns
+// (one thread per shot row). In place; a fixed summation order per cell.
+__global__ __launch_bounds__(256) void k_fold_rows(const FinalArgs A, int maxNX)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    const ShotDesc S = A.shots[s];
+    if (j >= S.NX || A.nb == 0) return;
+    float *G = A.G + S.g_off;
+    const int top = A.nb, bot = A.NZ - 1 - A.nb;
+    float t = 0.f, b = 0.f;
+    for (int r = 0; r <= A.nb; ++r) {
+        t += G[int64_t(r) * S.P + j];
+        b += G[int64_t(bot + r) * S.P + j];
+    }
+    if (top == bot) {  // one physical row: everything folds onto it
+        G[int64_t(top) * S.P + j] = t + b - G[int64_t(top) * S.P + j];
+    } else {
+        G[int64_t(top) * S.P + j] = t;
+        G[int64_t(bot) * S.P + j] = b;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fold_cols(const FinalArgs A)
+{
+    const int i = A.nb + blockIdx.x * blockDim.x + threadIdx.x;  // physical rows only
+    const int s = blockIdx.y;
+    if (i > A.NZ - 1 - A.nb || A.nb == 0) return;
+    const ShotDesc S = A.shots[s];
+    float *G = A.G + S.g_off + int64_t(i) * S.P;
+    const int lft = A.nb, rgt = S.NX - 1 - A.nb;
+    float l = 0.f, r = 0.f;
+    for (int c = 0; c <= A.nb; ++c) {
+        l += G[c];
+        r += G[rgt + c];
+    }
+    if (lft == rgt) {
+        G[lft] = l + r - G[lft];
+    } else {
+        G[lft] = l;
+        G[rgt] = r;
+    }
+}
+
+// img = (2 / (v^3 dt^2)) sum_shots Pad^T G_s, after the sponge folds: each
+// physical cell reads one value per shot whose window holds it; shots are
+// summed in slot order, so the result does not depend on scheduling.
 __global__ __launch_bounds__(256) void k_finalize(const FinalArgs A)
 {
     const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= int64_t(A.nz) * A.nx) return;
     const int i = int(p / A.nx), j = int(p % A.nx);
-    const int nb = A.nb;
-    const int r0 = i == 0 ? 0 : i + nb;
-    const int r1 = i == A.nz - 1 ? A.NZ - 1 : i + nb;
     float acc = 0.0f;
     for (int s = 0; s < A.nshots; ++s) {
         const ShotDesc S = A.shots[s];
         const int jl = j - S.x0;
         if (jl < 0 || jl >= S.wnx) continue;
-        const int c0 = jl == 0 ? 0 : jl + nb;
-        const int c1 = jl == S.wnx - 1 ? S.NX - 1 : jl + nb;
-        const float *G = A.G + S.g_off;
-        for (int r = r0; r <= r1; ++r)
-            for (int c = c0; c <= c1; ++c) acc += G[int64_t(r) * S.P + c];
+        acc += A.G[S.g_off + int64_t(i + A.nb) * S.P + jl + A.nb];
     }
     const float v = A.v[p];
     A.img[p] = acc * (2.0f / (v * v * v * A.dt2));
@@ -595,8 +634,17 @@ hipError_t launch_sum_partials(const double *part, int64_t n, double *out, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const FinalArgs &a, hipStream_t s)
+hipError_t launch_finalize(const FinalArgs &a, int max_nx, hipStream_t s)
 {
+    if (a.nshots > 0 && a.nb > 0) {
+        hipLaunchKernelGGL(k_fold_rows, dim3(unsigned((max_nx + 255) / 256), unsigned(a.nshots)), dim3(256), 0, s,
+                           a, max_nx);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fold_cols, dim3(unsigned((a.nz + 255) / 256), unsigned(a.nshots)), dim3(256), 0, s, a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const int64_t n = int64_t(a.nz) * a.nx;
     hipLaunchKernelGGL(k_finalize, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();

@@ -104,7 +104,7 @@ struct TraceArgs {
 struct FinalArgs {
     const ShotDesc *shots;
     int32_t nshots;
-    const float *G;
+    float *G;           // folded in place
     const float *v;
     int32_t nz, nx, nb, NZ;
     float dt2;
@@ -117,6 +117,6 @@ hipError_t launch_fill(float *p, int64_t n, float val, hipStream_t s);
 hipError_t launch_model_check(const float *v, int64_t n, float *out3, hipStream_t s);
 hipError_t launch_traces(const TraceArgs &a, hipStream_t s, int64_t *nblocks_out);
 hipError_t launch_sum_partials(const double *part, int64_t n, double *out, hipStream_t s);
-hipError_t launch_finalize(const FinalArgs &a, hipStream_t s);
+hipError_t launch_finalize(const FinalArgs &a, int max_nx, hipStream_t s);
 
 }  // namespace fwi
