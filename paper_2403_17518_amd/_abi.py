@@ -55,7 +55,12 @@ class fwi_stats(C.Structure):
         return out
 
 
-# exported symbols and their signatures (every one declared in include/fwi.h)
+class deblur_cfg(C.Structure):
+    _fields_ = [("depth", C.c_int32), ("base_ch", C.c_int32), ("leaky_slope", C.c_float),
+                ("in_h", C.c_int32), ("in_w", C.c_int32)]
+
+
+# exported symbols and their signatures (every one declared in include/*.h)
 _P = C.c_void_p
 SIGNATURES = {
     "fwi_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
@@ -73,6 +78,19 @@ SIGNATURES = {
                                C.POINTER(C.c_double), _P]),
     "born_demig": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P]),
     "born_mig": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P]),
+    "deblur_create": (C.c_int, [_P, C.POINTER(deblur_cfg), C.c_uint64, C.POINTER(_P)]),
+    "deblur_destroy": (None, [_P]),
+    "deblur_last_error": (C.c_char_p, [_P]),
+    "deblur_num_params": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "deblur_set_params": (C.c_int, [_P, _P, _P]),
+    "deblur_get_params": (C.c_int, [_P, _P, _P]),
+    "deblur_reset": (C.c_int, [_P, _P, C.c_uint64]),
+    "deblur_train": (C.c_int, [_P, _P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_float, _P]),
+    "deblur_apply": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
+    "deblur_forward_raw": (C.c_int, [_P, _P, _P, _P]),
+    "deblur_grad_raw": (C.c_int, [_P, _P, _P, _P, C.POINTER(C.c_double), _P]),
+    "deblur_save": (C.c_int, [_P, _P, C.c_char_p]),
+    "deblur_load": (C.c_int, [_P, _P, C.c_char_p]),
 }
 
 _lib = None

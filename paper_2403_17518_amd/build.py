@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libfwi.so")
-SOURCES = ["fwi_kernels.hip", "fwi_api.hip"]
+SOURCES = ["fwi_kernels.hip", "fwi_api.hip", "deblur_kernels.hip", "deblur_api.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

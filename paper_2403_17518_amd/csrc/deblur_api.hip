@@ -1,0 +1,852 @@
+// Deblurring network runtime and C ABI (include/deblur.h): parameter layout,
+// activation buffers, the forward and backward layer schedules, Adam with a
+// cosine learning-rate schedule, input scaling/padding, save/load.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/deblur.h"
+#include "deblur_internal.h"
+#include "internal.h"
+
+using namespace dbl;
+
+namespace {
+
+constexpr float kBeta1 = 0.9f, kBeta2 = 0.999f, kEps = 1e-8f;
+constexpr uint32_t kMagic = 0x44424c31;  // "DBL1"
+
+struct ConvL {
+    int cin, cout;
+    int64_t w, b;      // offsets into the flat parameter vector
+    int64_t aux;       // offset of the data-gradient weights (bf16)
+};
+
+enum Kind { KW3 = 0, KB = 1, KWT = 2, KW1 = 3 };
+struct Entry {
+    int kind, cin, cout;
+    int64_t off, n;
+};
+
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct deblur_net {
+    deblur_cfg cfg{};
+    int device = 0;
+    std::string err;
+    int D = 0;
+    std::vector<int> C, H, W, P;
+    ConvL inc[2];
+    std::vector<ConvL> down1, down2, upT, up1, up2;  // index by level
+    int64_t out_w = 0, out_b = 0;
+    std::vector<Entry> entries;  // parameter-vector order
+    int64_t nparam = 0, naux = 0;
+    // device memory
+    Buf params, grads, mom1, mom2, pbf, aux;
+    Buf xin, a, cat, eD, pool, c, d, y32, t32;       // forward activations
+    Buf da, dcat, deD, dpool, dc, dd, dy32;         // gradients
+    Buf wpart, bpart, lpart, loss_dev, hyper, scal;
+    std::vector<int64_t> a_off, cat_off, pool_off, c_off, d_off;  // per level offsets (elements)
+    int64_t wpart_max = 0, bpart_max = 0;
+    int nblk0 = 0;
+};
+
+namespace {
+
+int set_err(deblur_net *n, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (n) n->err = buf;
+    return code;
+}
+
+#define HCK(net, call)                                                                         \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return set_err(net, FWI_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+int alloc(deblur_net *n, Buf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return FWI_OK;
+    if (b.p) HCK(n, hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(n, FWI_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    b.bytes = bytes;
+    return FWI_OK;
+}
+
+void release(Buf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <class T>
+T *P_(const Buf &b, int64_t off = 0)
+{
+    return static_cast<T *>(b.p) + off;
+}
+
+// ---- layout -----------------------------------------------------------------
+
+ConvL add_conv(deblur_net *n, int cin, int cout)
+{
+    ConvL L{cin, cout, n->nparam, 0, n->naux};
+    n->entries.push_back({KW3, cin, cout, n->nparam, int64_t(cout) * cin * 9});
+    n->nparam += int64_t(cout) * cin * 9;
+    L.b = n->nparam;
+    n->entries.push_back({KB, cin, cout, n->nparam, cout});
+    n->nparam += cout;
+    n->naux += int64_t(cout) * cin * 9;
+    return L;
+}
+
+ConvL add_convt(deblur_net *n, int cin, int cout)
+{
+    ConvL L{cin, cout, n->nparam, 0, n->naux};
+    n->entries.push_back({KWT, cin, cout, n->nparam, int64_t(cin) * cout * 4});
+    n->nparam += int64_t(cin) * cout * 4;
+    L.b = n->nparam;
+    n->entries.push_back({KB, cin, cout, n->nparam, cout});
+    n->nparam += cout;
+    n->naux += int64_t(cin) * cout * 4;
+    return L;
+}
+
+void build_layout(deblur_net *n)
+{
+    const int D = n->D;
+    n->C.resize(D + 1);
+    n->H.resize(D + 1);
+    n->W.resize(D + 1);
+    n->P.resize(D + 1);
+    for (int l = 0; l <= D; ++l) {
+        n->C[l] = n->cfg.base_ch << l;
+        n->H[l] = n->cfg.in_h >> l;
+        n->W[l] = n->cfg.in_w >> l;
+        n->P[l] = n->H[l] * n->W[l];
+    }
+    n->inc[0] = add_conv(n, 1, n->C[0]);
+    n->inc[1] = add_conv(n, n->C[0], n->C[0]);
+    n->down1.assign(D + 1, ConvL{});
+    n->down2.assign(D + 1, ConvL{});
+    n->upT.assign(D, ConvL{});
+    n->up1.assign(D, ConvL{});
+    n->up2.assign(D, ConvL{});
+    for (int l = 1; l <= D; ++l) {
+        n->down1[l] = add_conv(n, n->C[l - 1], n->C[l]);
+        n->down2[l] = add_conv(n, n->C[l], n->C[l]);
+    }
+    for (int l = D - 1; l >= 0; --l) {
+        n->upT[l] = add_convt(n, n->C[l + 1], n->C[l]);
+        n->up1[l] = add_conv(n, 2 * n->C[l], n->C[l]);
+        n->up2[l] = add_conv(n, n->C[l], n->C[l]);
+    }
+    n->out_w = n->nparam;
+    n->entries.push_back({KW1, n->C[0], 1, n->nparam, n->C[0]});
+    n->nparam += n->C[0];
+    n->out_b = n->nparam;
+    n->entries.push_back({KB, n->C[0], 1, n->nparam, 1});
+    n->nparam += 1;
+}
+
+// pixels per split and split count of a weight-gradient reduction
+void wsplit(int M, int N, int P, int *nsplit, int *chunk)
+{
+    const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    int ns = std::max(1, std::min((512 + tiles - 1) / tiles, std::max(1, P / 256)));
+    int ch = (P + ns - 1) / ns;
+    ch = ((ch + 31) / 32) * 32;
+    ns = (P + ch - 1) / ch;
+    *nsplit = ns;
+    *chunk = ch;
+}
+
+int alloc_buffers(deblur_net *n)
+{
+    const int D = n->D;
+    int rc;
+    const size_t np = size_t(n->nparam);
+    if ((rc = alloc(n, n->params, np * 4)) || (rc = alloc(n, n->grads, np * 4)) ||
+        (rc = alloc(n, n->mom1, np * 4)) || (rc = alloc(n, n->mom2, np * 4)) ||
+        (rc = alloc(n, n->pbf, np * 2)) || (rc = alloc(n, n->aux, size_t(n->naux) * 2)))
+        return rc;
+    int64_t sa = 0, sc = 0, sp = 0, scc = 0, sd = 0;
+    n->a_off.assign(D + 1, 0);
+    n->cat_off.assign(D + 1, 0);
+    n->pool_off.assign(D + 1, 0);
+    n->c_off.assign(D + 1, 0);
+    n->d_off.assign(D + 1, 0);
+    for (int l = 0; l <= D; ++l) {
+        n->a_off[l] = sa;
+        sa += int64_t(n->P[l]) * n->C[l];
+        if (l < D) {
+            n->cat_off[l] = sc;
+            sc += int64_t(n->P[l]) * 2 * n->C[l];
+            n->c_off[l] = scc;
+            scc += int64_t(n->P[l]) * n->C[l];
+            n->d_off[l] = sd;
+            sd += int64_t(n->P[l]) * n->C[l];
+        }
+        if (l >= 1) {
+            n->pool_off[l] = sp;
+            sp += int64_t(n->P[l]) * n->C[l - 1];
+        }
+    }
+    const int64_t eD = int64_t(n->P[D]) * n->C[D];
+    const int64_t P0 = n->P[0];
+    if ((rc = alloc(n, n->xin, size_t(P0) * 2)) || (rc = alloc(n, n->a, size_t(sa) * 2)) ||
+        (rc = alloc(n, n->cat, size_t(sc) * 2)) || (rc = alloc(n, n->eD, size_t(eD) * 2)) ||
+        (rc = alloc(n, n->pool, size_t(sp) * 2)) || (rc = alloc(n, n->c, size_t(scc) * 2)) ||
+        (rc = alloc(n, n->d, size_t(sd) * 2)) || (rc = alloc(n, n->y32, size_t(P0) * 4)) ||
+        (rc = alloc(n, n->t32, size_t(P0) * 4)) || (rc = alloc(n, n->da, size_t(sa) * 2)) ||
+        (rc = alloc(n, n->dcat, size_t(sc) * 2)) || (rc = alloc(n, n->deD, size_t(eD) * 2)) ||
+        (rc = alloc(n, n->dpool, size_t(sp) * 2)) || (rc = alloc(n, n->dc, size_t(scc) * 2)) ||
+        (rc = alloc(n, n->dd, size_t(sd) * 2)) || (rc = alloc(n, n->dy32, size_t(P0) * 4)))
+        return rc;
+    // scratch of the weight- and bias-gradient reductions
+    int64_t wmax = 0, bmax = 0;
+    auto acc_w = [&](int M, int N, int P) {
+        int ns, ch;
+        wsplit(M, N, P, &ns, &ch);
+        wmax = std::max(wmax, int64_t(ns) * M * N);
+    };
+    auto acc_b = [&](int C, int P) {
+        const int ns = std::max(1, std::min(256, P / 1024));
+        bmax = std::max(bmax, int64_t(ns) * C);
+    };
+    for (int k = 0; k < 2; ++k) {
+        acc_w(n->inc[k].cout, 9 * n->inc[k].cin, n->P[0]);
+        acc_b(n->inc[k].cout, n->P[0]);
+    }
+    for (int l = 1; l <= D; ++l)
+        for (const ConvL *L : {&n->down1[l], &n->down2[l]}) {
+            acc_w(L->cout, 9 * L->cin, n->P[l]);
+            acc_b(L->cout, n->P[l]);
+        }
+    for (int l = 0; l < D; ++l) {
+        for (const ConvL *L : {&n->up1[l], &n->up2[l]}) {
+            acc_w(L->cout, 9 * L->cin, n->P[l]);
+            acc_b(L->cout, n->P[l]);
+        }
+        acc_w(n->upT[l].cin, 4 * n->upT[l].cout, n->P[l + 1]);
+        acc_b(n->upT[l].cout, n->P[l]);
+    }
+    wmax = std::max(wmax, int64_t((P0 + 255) / 256) * (n->C[0] + 1));  // output-conv partials
+    n->wpart_max = wmax;
+    n->bpart_max = bmax;
+    n->nblk0 = int((P0 + 255) / 256);
+    if ((rc = alloc(n, n->wpart, size_t(wmax) * 4)) || (rc = alloc(n, n->bpart, size_t(bmax) * 4)) ||
+        (rc = alloc(n, n->lpart, size_t(std::max<int64_t>(n->nblk0 * int64_t(n->C[0] + 1), n->nblk0)) * 8)) ||
+        (rc = alloc(n, n->scal, 64)))
+        return rc;
+    return FWI_OK;
+}
+
+// ---- initialisation and parameter exchange -------------------------------------
+
+uint64_t splitmix(uint64_t &s)
+{
+    uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+// default initialisation, in parameter-vector order and PyTorch layout:
+// weights and biases uniform in +-1/sqrt(fan_in) (fan_in = Cin*9 for 3x3,
+// Cout*4 for the transposed conv, C0 for the output conv)
+std::vector<float> init_params(const deblur_net *n, uint64_t seed)
+{
+    std::vector<float> v(size_t(n->nparam));
+    uint64_t s = seed;
+    for (const Entry &e : n->entries) {
+        double fan = 1;
+        switch (e.kind) {
+        case KW3: fan = e.cin * 9.0; break;
+        case KWT: fan = e.cout * 4.0; break;
+        case KW1: fan = e.cin; break;
+        default: break;
+        }
+        if (e.kind == KB) {
+            // fan of the weight just before it
+            const Entry &w = *(&e - 1);
+            fan = w.kind == KW3 ? w.cin * 9.0 : (w.kind == KWT ? w.cout * 4.0 : w.cin);
+        }
+        const double bound = 1.0 / std::sqrt(fan);
+        for (int64_t i = 0; i < e.n; ++i) {
+            const double u = double(splitmix(s) >> 11) * (1.0 / 9007199254740992.0);
+            v[size_t(e.off + i)] = float((2.0 * u - 1.0) * bound);
+        }
+    }
+    return v;
+}
+
+// PyTorch layout <-> internal layout (3x3: [co][tap][ci]; transposed conv:
+// [ab][co][ci]); biases and the 1x1 conv are unchanged
+void torch_to_internal(const deblur_net *n, const float *src, std::vector<float> &dst)
+{
+    dst.assign(size_t(n->nparam), 0.f);
+    for (const Entry &e : n->entries) {
+        const float *s = src + e.off;
+        float *d = dst.data() + e.off;
+        if (e.kind == KW3) {
+            for (int co = 0; co < e.cout; ++co)
+                for (int ci = 0; ci < e.cin; ++ci)
+                    for (int t = 0; t < 9; ++t)
+                        d[int64_t(co) * 9 * e.cin + int64_t(t) * e.cin + ci] = s[(int64_t(co) * e.cin + ci) * 9 + t];
+        } else if (e.kind == KWT) {
+            for (int ci = 0; ci < e.cin; ++ci)
+                for (int co = 0; co < e.cout; ++co)
+                    for (int ab = 0; ab < 4; ++ab)
+                        d[(int64_t(ab) * e.cout + co) * e.cin + ci] = s[(int64_t(ci) * e.cout + co) * 4 + ab];
+        } else {
+            std::memcpy(d, s, size_t(e.n) * 4);
+        }
+    }
+}
+
+void internal_to_torch(const deblur_net *n, const float *src, float *dst)
+{
+    for (const Entry &e : n->entries) {
+        const float *s = src + e.off;
+        float *d = dst + e.off;
+        if (e.kind == KW3) {
+            for (int co = 0; co < e.cout; ++co)
+                for (int ci = 0; ci < e.cin; ++ci)
+                    for (int t = 0; t < 9; ++t)
+                        d[(int64_t(co) * e.cin + ci) * 9 + t] = s[int64_t(co) * 9 * e.cin + int64_t(t) * e.cin + ci];
+        } else if (e.kind == KWT) {
+            for (int ci = 0; ci < e.cin; ++ci)
+                for (int co = 0; co < e.cout; ++co)
+                    for (int ab = 0; ab < 4; ++ab)
+                        d[(int64_t(ci) * e.cout + co) * 4 + ab] = s[(int64_t(ab) * e.cout + co) * e.cin + ci];
+        } else {
+            std::memcpy(d, s, size_t(e.n) * 4);
+        }
+    }
+}
+
+// bf16 copies: the forward weight matrices and the data-gradient matrices
+int refresh_weights(deblur_net *n, hipStream_t st)
+{
+    HCK(n, to_bf16(P_<float>(n->params), P_<bf16>(n->pbf), n->nparam, st));
+    auto flip = [&](const ConvL &L) {
+        return weight_flip(P_<float>(n->params, L.w), L.cout, L.cin, P_<bf16>(n->aux, L.aux), st);
+    };
+    for (int k = 0; k < 2; ++k) HCK(n, flip(n->inc[k]));
+    for (int l = 1; l <= n->D; ++l) {
+        HCK(n, flip(n->down1[l]));
+        HCK(n, flip(n->down2[l]));
+    }
+    for (int l = 0; l < n->D; ++l) {
+        HCK(n, flip(n->up1[l]));
+        HCK(n, flip(n->up2[l]));
+        const ConvL &T = n->upT[l];
+        HCK(n, convt_dgrad_weights(P_<float>(n->params, T.w), T.cin, T.cout, P_<bf16>(n->aux, T.aux), st));
+    }
+    return FWI_OK;
+}
+
+int upload_params(deblur_net *n, hipStream_t st, const std::vector<float> &internal)
+{
+    HCK(n, hipMemcpyAsync(n->params.p, internal.data(), internal.size() * 4, hipMemcpyHostToDevice, st));
+    HCK(n, hipStreamSynchronize(st));
+    return refresh_weights(n, st);
+}
+
+// ---- layer launches ---------------------------------------------------------------
+
+Gather conv_gather(const bf16 *src, int ld, int coff, int Cb, int H, int W)
+{
+    return Gather{src, ld, coff, Cb, H, W, H, W, 1, 3, -1, 9};
+}
+
+int conv_fwd(deblur_net *n, const ConvL &L, const bf16 *src, int ld, int coff, int lvl, bf16 *out, int out_ld,
+             int out_coff, hipStream_t st)
+{
+    GemmArgs a{};
+    a.M = L.cout;
+    a.N = n->P[lvl];
+    a.K = 9 * L.cin;
+    a.A = P_<bf16>(n->pbf, L.w);
+    a.lda = 9 * L.cin;
+    a.g = conv_gather(src, ld, coff, L.cin, n->H[lvl], n->W[lvl]);
+    a.out = out;
+    a.out_ld = out_ld;
+    a.out_coff = out_coff;
+    a.Cout = L.cout;
+    a.bias = P_<float>(n->params, L.b);
+    a.act = 1;
+    a.slope = n->cfg.leaky_slope;
+    HCK(n, gemm(a, st));
+    return FWI_OK;
+}
+
+// dsrc = data gradient of a 3x3 conv given dz (the gradient at its
+// pre-activation output)
+int conv_dgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff, int lvl, bf16 *dsrc, int ld,
+               int coff, hipStream_t st)
+{
+    GemmArgs a{};
+    a.M = L.cin;
+    a.N = n->P[lvl];
+    a.K = 9 * L.cout;
+    a.A = P_<bf16>(n->aux, L.aux);
+    a.lda = 9 * L.cout;
+    a.g = conv_gather(dz, ldz, zoff, L.cout, n->H[lvl], n->W[lvl]);
+    a.out = dsrc;
+    a.out_ld = ld;
+    a.out_coff = coff;
+    a.Cout = L.cin;
+    HCK(n, gemm(a, st));
+    return FWI_OK;
+}
+
+int conv_wgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff, const bf16 *src, int ld, int coff,
+               int lvl, hipStream_t st)
+{
+    WgradArgs w{};
+    w.M = L.cout;
+    w.N = 9 * L.cin;
+    w.A = dz;
+    w.lda = ldz;
+    w.acoff = zoff;
+    w.g = conv_gather(src, ld, coff, L.cin, n->H[lvl], n->W[lvl]);
+    wsplit(w.M, w.N, n->P[lvl], &w.nsplit, &w.chunk);
+    w.partial = P_<float>(n->wpart);
+    w.out = P_<float>(n->grads, L.w);
+    w.ldm = 9 * L.cin;
+    w.ldn = 1;
+    HCK(n, wgrad(w, st));
+    const int ns = std::max(1, std::min(256, n->P[lvl] / 1024));
+    HCK(n, bias_grad(dz, ldz, zoff, L.cout, n->P[lvl], P_<float>(n->grads, L.b), P_<float>(n->bpart), ns, st));
+    return FWI_OK;
+}
+
+// transposed conv of level l: src (level l+1, dense C_{l+1}) -> slice
+// [C_l, 2C_l) of cat_l
+int convt_fwd(deblur_net *n, int l, const bf16 *src, hipStream_t st)
+{
+    const ConvL &T = n->upT[l];
+    GemmArgs a{};
+    a.M = 4 * T.cout;
+    a.N = n->P[l + 1];
+    a.K = T.cin;
+    a.A = P_<bf16>(n->pbf, T.w);
+    a.lda = T.cin;
+    a.g = Gather{src, T.cin, 0, T.cin, n->H[l + 1], n->W[l + 1], n->H[l + 1], n->W[l + 1], 1, 1, 0, 1};
+    a.out = P_<bf16>(n->cat, n->cat_off[l]);
+    a.out_ld = 2 * n->C[l];
+    a.out_coff = n->C[l];
+    a.Cout = T.cout;
+    a.scatter = 1;
+    a.Ho = n->H[l];
+    a.Wo = n->W[l];
+    a.bias = P_<float>(n->params, T.b);
+    HCK(n, gemm(a, st));
+    return FWI_OK;
+}
+
+int convt_bwd(deblur_net *n, int l, const bf16 *src, bf16 *dsrc, hipStream_t st)
+{
+    const ConvL &T = n->upT[l];
+    const bf16 *du = P_<bf16>(n->dcat, n->cat_off[l]);
+    const Gather gu{du, 2 * n->C[l], n->C[l], T.cout, n->H[l], n->W[l], n->H[l + 1], n->W[l + 1], 2, 2, 0, 4};
+    WgradArgs w{};
+    w.M = T.cin;
+    w.N = 4 * T.cout;
+    w.A = src;
+    w.lda = T.cin;
+    w.acoff = 0;
+    w.g = gu;
+    wsplit(w.M, w.N, n->P[l + 1], &w.nsplit, &w.chunk);
+    w.partial = P_<float>(n->wpart);
+    w.out = P_<float>(n->grads, T.w);
+    w.ldm = 1;
+    w.ldn = T.cin;
+    HCK(n, wgrad(w, st));
+    const int ns = std::max(1, std::min(256, n->P[l] / 1024));
+    HCK(n, bias_grad(du, 2 * n->C[l], n->C[l], T.cout, n->P[l], P_<float>(n->grads, T.b), P_<float>(n->bpart), ns,
+                     st));
+    GemmArgs a{};
+    a.M = T.cin;
+    a.N = n->P[l + 1];
+    a.K = 4 * T.cout;
+    a.A = P_<bf16>(n->aux, T.aux);
+    a.lda = 4 * T.cout;
+    a.g = gu;
+    a.out = dsrc;
+    a.out_ld = T.cin;
+    a.Cout = T.cin;
+    HCK(n, gemm(a, st));
+    return FWI_OK;
+}
+
+// forward of the padded, normalised input in xin (bf16) to y32 (FP32)
+int forward(deblur_net *n, hipStream_t st)
+{
+    const int D = n->D;
+    int rc;
+    bf16 *cat = P_<bf16>(n->cat), *a = P_<bf16>(n->a), *pl = P_<bf16>(n->pool);
+    bf16 *c = P_<bf16>(n->c), *d = P_<bf16>(n->d), *eD = P_<bf16>(n->eD);
+    // input block
+    if ((rc = conv_fwd(n, n->inc[0], P_<bf16>(n->xin), 1, 0, 0, a + n->a_off[0], n->C[0], 0, st))) return rc;
+    if ((rc = conv_fwd(n, n->inc[1], a + n->a_off[0], n->C[0], 0, 0, cat + n->cat_off[0], 2 * n->C[0], 0, st)))
+        return rc;
+    // encoder
+    for (int l = 1; l <= D; ++l) {
+        HCK(n, pool_fwd(cat + n->cat_off[l - 1], 2 * n->C[l - 1], 0, n->C[l - 1], n->H[l - 1], n->W[l - 1],
+                        pl + n->pool_off[l], st));
+        if ((rc = conv_fwd(n, n->down1[l], pl + n->pool_off[l], n->C[l - 1], 0, l, a + n->a_off[l], n->C[l], 0, st)))
+            return rc;
+        bf16 *eo = l < D ? cat + n->cat_off[l] : eD;
+        const int eld = l < D ? 2 * n->C[l] : n->C[l];
+        if ((rc = conv_fwd(n, n->down2[l], a + n->a_off[l], n->C[l], 0, l, eo, eld, 0, st))) return rc;
+    }
+    // decoder
+    for (int l = D - 1; l >= 0; --l) {
+        const bf16 *src = l == D - 1 ? eD : d + n->d_off[l + 1];
+        if ((rc = convt_fwd(n, l, src, st))) return rc;
+        if ((rc = conv_fwd(n, n->up1[l], cat + n->cat_off[l], 2 * n->C[l], 0, l, c + n->c_off[l], n->C[l], 0, st)))
+            return rc;
+        if ((rc = conv_fwd(n, n->up2[l], c + n->c_off[l], n->C[l], 0, l, d + n->d_off[l], n->C[l], 0, st))) return rc;
+    }
+    HCK(n, outc_fwd(d + n->d_off[0], n->C[0], n->P[0], P_<float>(n->params, n->out_w),
+                    P_<float>(n->params, n->out_b), P_<float>(n->y32), st));
+    return FWI_OK;
+}
+
+// loss (into loss_slot, FP64 device, and its FP32 copy) and all parameter
+// gradients for target t32
+int backward(deblur_net *n, hipStream_t st, double *loss_slot)
+{
+    const int D = n->D;
+    const float slope = n->cfg.leaky_slope;
+    int rc;
+    bf16 *cat = P_<bf16>(n->cat), *a = P_<bf16>(n->a), *pl = P_<bf16>(n->pool);
+    bf16 *c = P_<bf16>(n->c), *d = P_<bf16>(n->d), *eD = P_<bf16>(n->eD);
+    bf16 *dcat = P_<bf16>(n->dcat), *da = P_<bf16>(n->da), *dpl = P_<bf16>(n->dpool);
+    bf16 *dc = P_<bf16>(n->dc), *dd = P_<bf16>(n->dd), *deD = P_<bf16>(n->deD);
+    const int P0 = n->P[0], C0 = n->C[0];
+    double *lpart = P_<double>(n->lpart);
+    HCK(n, mse(P_<float>(n->y32), P_<float>(n->t32), P0, lpart, n->nblk0, P_<float>(n->dy32), st));
+    HCK(n, sum_partials_d(lpart, n->nblk0, loss_slot, 1.0f / float(P0), nullptr, st));
+    float *wp = P_<float>(n->wpart);
+    HCK(n, outc_bwd(d + n->d_off[0], C0, P0, P_<float>(n->params, n->out_w), P_<float>(n->dy32), dd + n->d_off[0], wp,
+                    n->nblk0, st));
+    HCK(n, outc_wgrad_reduce(wp, C0, n->nblk0, P_<float>(n->grads, n->out_w), P_<float>(n->grads, n->out_b), st));
+    // decoder, level 0 up to D-1
+    for (int l = 0; l < D; ++l) {
+        const int Cl = n->C[l], Pl = n->P[l];
+        bf16 *ddl = dd + n->d_off[l], *dcl = dc + n->c_off[l];
+        HCK(n, act_bwd(ddl, Cl, 0, ddl, Cl, 0, d + n->d_off[l], Cl, 0, Cl, Pl, slope, st));
+        if ((rc = conv_wgrad(n, n->up2[l], ddl, Cl, 0, c + n->c_off[l], Cl, 0, l, st))) return rc;
+        if ((rc = conv_dgrad(n, n->up2[l], ddl, Cl, 0, l, dcl, Cl, 0, st))) return rc;
+        HCK(n, act_bwd(dcl, Cl, 0, dcl, Cl, 0, c + n->c_off[l], Cl, 0, Cl, Pl, slope, st));
+        if ((rc = conv_wgrad(n, n->up1[l], dcl, Cl, 0, cat + n->cat_off[l], 2 * Cl, 0, l, st))) return rc;
+        if ((rc = conv_dgrad(n, n->up1[l], dcl, Cl, 0, l, dcat + n->cat_off[l], 2 * Cl, 0, st))) return rc;
+        const bf16 *src = l == D - 1 ? eD : d + n->d_off[l + 1];
+        bf16 *dsrc = l == D - 1 ? deD : dd + n->d_off[l + 1];
+        if ((rc = convt_bwd(n, l, src, dsrc, st))) return rc;
+    }
+    // encoder, level D down to 1
+    for (int l = D; l >= 1; --l) {
+        const int Cl = n->C[l], Pl = n->P[l];
+        bf16 *de = l < D ? dcat + n->cat_off[l] : deD;
+        const bf16 *e = l < D ? cat + n->cat_off[l] : eD;
+        const int eld = l < D ? 2 * Cl : Cl;
+        HCK(n, act_bwd(de, eld, 0, de, eld, 0, e, eld, 0, Cl, Pl, slope, st));
+        bf16 *dal = da + n->a_off[l];
+        if ((rc = conv_wgrad(n, n->down2[l], de, eld, 0, a + n->a_off[l], Cl, 0, l, st))) return rc;
+        if ((rc = conv_dgrad(n, n->down2[l], de, eld, 0, l, dal, Cl, 0, st))) return rc;
+        HCK(n, act_bwd(dal, Cl, 0, dal, Cl, 0, a + n->a_off[l], Cl, 0, Cl, Pl, slope, st));
+        const int Cp = n->C[l - 1];
+        if ((rc = conv_wgrad(n, n->down1[l], dal, Cl, 0, pl + n->pool_off[l], Cp, 0, l, st))) return rc;
+        if ((rc = conv_dgrad(n, n->down1[l], dal, Cl, 0, l, dpl + n->pool_off[l], Cp, 0, st))) return rc;
+        HCK(n, pool_bwd(dpl + n->pool_off[l], Cp, n->H[l - 1], n->W[l - 1], dcat + n->cat_off[l - 1], 2 * Cp, 0, 1,
+                        st));
+    }
+    // input block
+    bf16 *de0 = dcat + n->cat_off[0];
+    HCK(n, act_bwd(de0, 2 * C0, 0, de0, 2 * C0, 0, cat + n->cat_off[0], 2 * C0, 0, C0, P0, slope, st));
+    if ((rc = conv_wgrad(n, n->inc[1], de0, 2 * C0, 0, a + n->a_off[0], C0, 0, 0, st))) return rc;
+    bf16 *da0 = da + n->a_off[0];
+    if ((rc = conv_dgrad(n, n->inc[1], de0, 2 * C0, 0, 0, da0, C0, 0, st))) return rc;
+    HCK(n, act_bwd(da0, C0, 0, da0, C0, 0, a + n->a_off[0], C0, 0, C0, P0, slope, st));
+    if ((rc = conv_wgrad(n, n->inc[0], da0, C0, 0, P_<bf16>(n->xin), 1, 0, 0, st))) return rc;
+    return FWI_OK;
+}
+
+int check_ctx(deblur_net *n, fwi_ctx *ctx, hipStream_t *st)
+{
+    if (!n || !ctx) return FWI_EINVAL;
+    n->err.clear();
+    if (fwi::ctx_device(ctx) != n->device)
+        return set_err(n, FWI_EINVAL, "context device %d differs from the network's %d", fwi::ctx_device(ctx),
+                       n->device);
+    HCK(n, hipSetDevice(n->device));
+    *st = fwi::ctx_stream(ctx);
+    return FWI_OK;
+}
+
+int check_image(deblur_net *n, int nz, int nx, int *py, int *px)
+{
+    if (nz < 1 || nx < 1 || nz > n->cfg.in_h || nx > n->cfg.in_w || (n->cfg.in_h - nz) % 2 ||
+        (n->cfg.in_w - nx) % 2)
+        return set_err(n, FWI_EINVAL, "image %dx%d does not fit the %dx%d network grid with even padding", nz, nx,
+                       n->cfg.in_h, n->cfg.in_w);
+    *py = (n->cfg.in_h - nz) / 2;
+    *px = (n->cfg.in_w - nx) / 2;
+    if ((*py > 0 && *py >= nz) || (*px > 0 && *px >= nx))
+        return set_err(n, FWI_EINVAL, "reflect padding wider than the image");
+    return FWI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int deblur_create(fwi_ctx *ctx, const deblur_cfg *cfg, uint64_t seed, deblur_net **out)
+{
+    if (!ctx || !cfg || !out) return FWI_EINVAL;
+    *out = nullptr;
+    if (cfg->depth < 1 || cfg->depth > 6 || cfg->base_ch < 8 || cfg->base_ch % 8 || cfg->base_ch > 1024 ||
+        cfg->in_h < 1 || cfg->in_w < 1 || cfg->in_h % (1 << cfg->depth) || cfg->in_w % (1 << cfg->depth) ||
+        !(cfg->leaky_slope >= 0.f && cfg->leaky_slope < 1.f))
+        return FWI_EINVAL;
+    deblur_net *n = new deblur_net();
+    n->cfg = *cfg;
+    n->D = cfg->depth;
+    n->device = fwi::ctx_device(ctx);
+    if (hipSetDevice(n->device) != hipSuccess) {
+        delete n;
+        return FWI_EHIP;
+    }
+    build_layout(n);
+    int rc = alloc_buffers(n);
+    if (rc == FWI_OK) {
+        std::vector<float> v = init_params(n, seed), internal;
+        torch_to_internal(n, v.data(), internal);
+        rc = upload_params(n, fwi::ctx_stream(ctx), internal);
+    }
+    if (rc != FWI_OK) {
+        deblur_destroy(n);
+        return rc;
+    }
+    *out = n;
+    return FWI_OK;
+}
+
+void deblur_destroy(deblur_net *n)
+{
+    if (!n) return;
+    (void)hipSetDevice(n->device);
+    (void)hipDeviceSynchronize();
+    for (Buf *b : {&n->params, &n->grads, &n->mom1, &n->mom2, &n->pbf, &n->aux, &n->xin, &n->a, &n->cat, &n->eD,
+                   &n->pool, &n->c, &n->d, &n->y32, &n->t32, &n->da, &n->dcat, &n->deD, &n->dpool, &n->dc, &n->dd,
+                   &n->dy32, &n->wpart, &n->bpart, &n->lpart, &n->loss_dev, &n->hyper, &n->scal})
+        release(*b);
+    delete n;
+}
+
+const char *deblur_last_error(const deblur_net *n)
+{
+    return n ? n->err.c_str() : "NULL network";
+}
+
+int deblur_num_params(const deblur_net *n, int64_t *np)
+{
+    if (!n || !np) return FWI_EINVAL;
+    *np = n->nparam;
+    return FWI_OK;
+}
+
+int deblur_set_params(fwi_ctx *ctx, deblur_net *n, const float *params)
+{
+    hipStream_t st;
+    int rc = check_ctx(n, ctx, &st);
+    if (rc) return rc;
+    if (!params) return set_err(n, FWI_EINVAL, "params is NULL");
+    std::vector<float> internal;
+    torch_to_internal(n, params, internal);
+    return upload_params(n, st, internal);
+}
+
+int deblur_get_params(fwi_ctx *ctx, const deblur_net *cn, float *params)
+{
+    deblur_net *n = const_cast<deblur_net *>(cn);
+    hipStream_t st;
+    int rc = check_ctx(n, ctx, &st);
+    if (rc) return rc;
+    if (!params) return set_err(n, FWI_EINVAL, "params is NULL");
+    std::vector<float> internal(size_t(n->nparam));
+    HCK(n, hipMemcpyAsync(internal.data(), n->params.p, internal.size() * 4, hipMemcpyDeviceToHost, st));
+    HCK(n, hipStreamSynchronize(st));
+    internal_to_torch(n, internal.data(), params);
+    return FWI_OK;
+}
+
+int deblur_reset(fwi_ctx *ctx, deblur_net *n, uint64_t seed)
+{
+    hipStream_t st;
+    int rc = check_ctx(n, ctx, &st);
+    if (rc) return rc;
+    std::vector<float> v = init_params(n, seed), internal;
+    torch_to_internal(n, v.data(), internal);
+    return upload_params(n, st, internal);
+}
+
+int deblur_forward_raw(fwi_ctx *ctx, deblur_net *n, const float *x, float *y)
+{
+    hipStream_t st;
+    int rc = check_ctx(n, ctx, &st);
+    if (rc) return rc;
+    if (!x || !y) return set_err(n, FWI_EINVAL, "NULL image");
+    const int64_t P0 = n->P[0];
+    HCK(n, to_bf16(x, P_<bf16>(n->xin), P0, st));
+    if ((rc = forward(n, st))) return rc;
+    HCK(n, hipMemcpyAsync(y, n->y32.p, size_t(P0) * 4, hipMemcpyDeviceToDevice, st));
+    return FWI_OK;
+}
+
+int deblur_grad_raw(fwi_ctx *ctx, deblur_net *n, const float *x, const float *t, double *loss, float *grads)
+{
+    hipStream_t st;
+    int rc = check_ctx(n, ctx, &st);
+    if (rc) return rc;
+    if (!x || !t) return set_err(n, FWI_EINVAL, "NULL image");
+    const int64_t P0 = n->P[0];
+    if ((rc = alloc(n, n->loss_dev, 8))) return rc;
+    HCK(n, to_bf16(x, P_<bf16>(n->xin), P0, st));
+    HCK(n, hipMemcpyAsync(n->t32.p, t, size_t(P0) * 4, hipMemcpyDeviceToDevice, st));
+    if ((rc = forward(n, st)) || (rc = backward(n, st, P_<double>(n->loss_dev)))) return rc;
+    double l = 0;
+    HCK(n, hipMemcpyAsync(&l, n->loss_dev.p, 8, hipMemcpyDeviceToHost, st));
+    std::vector<float> internal(size_t(n->nparam));
+    HCK(n, hipMemcpyAsync(internal.data(), n->grads.p, internal.size() * 4, hipMemcpyDeviceToHost, st));
+    HCK(n, hipStreamSynchronize(st));
+    if (loss) *loss = l;
+    if (grads) internal_to_torch(n, internal.data(), grads);
+    return FWI_OK;
+}
+
+int deblur_train(fwi_ctx *ctx, deblur_net *n, const float *x, const float *y, int32_t nz, int32_t nx, int32_t steps,
+                 float lr_max, float *loss_hist)
+{
+    hipStream_t st;
+    int rc = check_ctx(n, ctx, &st);
+    if (rc) return rc;
+    if (!x || !y) return set_err(n, FWI_EINVAL, "NULL image");
+    if (steps < 0 || !(lr_max >= 0.f)) return set_err(n, FWI_EINVAL, "bad steps or learning rate");
+    int py, px;
+    if ((rc = check_image(n, nz, nx, &py, &px))) return rc;
+    if (steps == 0) return FWI_OK;
+    const int H = n->cfg.in_h, W = n->cfg.in_w;
+    float *scal = P_<float>(n->scal);  // [0] max|x|, [1] max|y|
+    if ((rc = alloc(n, n->loss_dev, size_t(steps) * 8)) || (rc = alloc(n, n->hyper, size_t(steps) * 3 * 4)))
+        return rc;
+    HCK(n, absmax(x, int64_t(nz) * nx, scal, st));
+    HCK(n, absmax(y, int64_t(nz) * nx, scal + 1, st));
+    HCK(n, pad_norm(x, nz, nx, H, W, py, px, scal, P_<bf16>(n->xin), nullptr, st));
+    HCK(n, pad_norm(y, nz, nx, H, W, py, px, scal + 1, nullptr, P_<float>(n->t32), st));
+    // cosine-annealed learning rate and Adam bias corrections per step
+    std::vector<float> hyper(size_t(steps) * 3);
+    for (int t = 0; t < steps; ++t) {
+        hyper[3 * t] = float(lr_max * 0.5 * (1.0 + std::cos(M_PI * double(t) / double(steps))));
+        hyper[3 * t + 1] = float(1.0 - std::pow(double(kBeta1), t + 1));
+        hyper[3 * t + 2] = float(1.0 - std::pow(double(kBeta2), t + 1));
+    }
+    HCK(n, hipMemcpyAsync(n->hyper.p, hyper.data(), hyper.size() * 4, hipMemcpyHostToDevice, st));
+    HCK(n, fill_f(P_<float>(n->mom1), n->nparam, 0.f, st));
+    HCK(n, fill_f(P_<float>(n->mom2), n->nparam, 0.f, st));
+    for (int t = 0; t < steps; ++t) {
+        if ((rc = forward(n, st)) || (rc = backward(n, st, P_<double>(n->loss_dev, t)))) return rc;
+        HCK(n, adam(P_<float>(n->params), P_<float>(n->grads), P_<float>(n->mom1), P_<float>(n->mom2),
+                    P_<bf16>(n->pbf), n->nparam, P_<float>(n->hyper, 3 * t), kBeta1, kBeta2, kEps, st));
+        if ((rc = refresh_weights(n, st))) return rc;
+    }
+    std::vector<double> lh(static_cast<size_t>(steps));
+    HCK(n, hipMemcpyAsync(lh.data(), n->loss_dev.p, lh.size() * 8, hipMemcpyDeviceToHost, st));
+    HCK(n, hipStreamSynchronize(st));
+    if (loss_hist)
+        for (int t = 0; t < steps; ++t) loss_hist[t] = float(lh[size_t(t)]);
+    return FWI_OK;
+}
+
+int deblur_apply(fwi_ctx *ctx, deblur_net *n, const float *x, int32_t nz, int32_t nx, float *y)
+{
+    hipStream_t st;
+    int rc = check_ctx(n, ctx, &st);
+    if (rc) return rc;
+    if (!x || !y) return set_err(n, FWI_EINVAL, "NULL image");
+    int py, px;
+    if ((rc = check_image(n, nz, nx, &py, &px))) return rc;
+    const int H = n->cfg.in_h, W = n->cfg.in_w;
+    float *scal = P_<float>(n->scal);
+    HCK(n, absmax(x, int64_t(nz) * nx, scal, st));
+    HCK(n, pad_norm(x, nz, nx, H, W, py, px, scal, P_<bf16>(n->xin), nullptr, st));
+    if ((rc = forward(n, st))) return rc;
+    HCK(n, crop_scale(P_<float>(n->y32), H, W, py, px, nz, nx, scal, y, st));
+    return FWI_OK;
+}
+
+int deblur_save(fwi_ctx *ctx, const deblur_net *cn, const char *path)
+{
+    deblur_net *n = const_cast<deblur_net *>(cn);
+    if (!path) return set_err(n, FWI_EINVAL, "NULL path");
+    std::vector<float> v(size_t(n ? n->nparam : 0));
+    int rc = deblur_get_params(ctx, n, v.data());
+    if (rc) return rc;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return set_err(n, FWI_EINVAL, "cannot open %s", path);
+    const uint32_t magic = kMagic;
+    const int64_t np = n->nparam;
+    bool ok = std::fwrite(&magic, 4, 1, f) == 1 && std::fwrite(&n->cfg, sizeof(deblur_cfg), 1, f) == 1 &&
+              std::fwrite(&np, 8, 1, f) == 1 && std::fwrite(v.data(), 4, v.size(), f) == v.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? FWI_OK : set_err(n, FWI_EINVAL, "write to %s failed", path);
+}
+
+int deblur_load(fwi_ctx *ctx, deblur_net *n, const char *path)
+{
+    if (!n || !path) return FWI_EINVAL;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return set_err(n, FWI_EINVAL, "cannot open %s", path);
+    uint32_t magic = 0;
+    deblur_cfg cfg{};
+    int64_t np = 0;
+    bool ok = std::fread(&magic, 4, 1, f) == 1 && std::fread(&cfg, sizeof cfg, 1, f) == 1 &&
+              std::fread(&np, 8, 1, f) == 1;
+    ok = ok && magic == kMagic && np == n->nparam && std::memcmp(&cfg, &n->cfg, sizeof cfg) == 0;
+    std::vector<float> v(size_t(n->nparam));
+    ok = ok && std::fread(v.data(), 4, v.size(), f) == v.size();
+    std::fclose(f);
+    if (!ok) return set_err(n, FWI_EINVAL, "%s is not a checkpoint of this network", path);
+    return deblur_set_params(ctx, n, v.data());
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Internal declarations of the deblurring network (deblur_kernels.hip,
+// deblur_api.hip). Activations and gradients are NHWC bf16 (batch 1), with a
+// channel stride and offset so that concatenated tensors are slices of one
+// buffer; parameters are FP32 masters with a bf16 copy for the MFMA kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dbl {
+
+using bf16 = __bf16;
+
+// Source-pixel map of an implicit-GEMM operand: output pixel p = (i, j) of an
+// H x W grid and tap t read source pixel (i*stride + t/tapw + d0,
+// j*stride + t%tapw + d0) of an Hs x Ws grid, channels [coff, coff + Cb) of
+// a tensor with channel stride ld; outside the source grid the value is 0.
+//   3x3 conv (pad 1): stride 1, tapw 3, d0 -1, ntaps 9
+//   2x2 up-sampling taps (transposed-conv gradient): stride 2, tapw 2, d0 0
+//   identity: stride 1, tapw 1, d0 0, ntaps 1
+struct Gather {
+    const bf16 *src;
+    int32_t ld, coff, Cb;
+    int32_t Hs, Ws;
+    int32_t H, W;
+    int32_t stride, tapw, d0, ntaps;
+};
+
+// C[m][p] = sum_k A[m][k] * B[k][p] with A row-major [M][K] (K = ntaps*Cb,
+// k = tap*Cb + c) and B gathered from g. Epilogue: + bias[co], activation
+// (slope for x < 0; act = 0 means none), bf16 store to out[pix][coff + co].
+// scatter 0: pix = p, co = m. scatter 1 (2x2 stride-2 transposed conv):
+// m = ab*Cout + co, pix = (2i + ab/2, 2j + ab%2) of the Ho x Wo grid.
+struct GemmArgs {
+    int32_t M, N, K;
+    const bf16 *A;
+    int32_t lda;
+    Gather g;
+    bf16 *out;
+    int32_t out_ld, out_coff, Cout, scatter, Ho, Wo;
+    const float *bias;
+    int32_t act;
+    float slope;
+};
+
+// C[m][n] = sum_p A[p][acoff + m] * Bg(p, n), n = tap*Cb + c, reduced over the
+// pixels p of the gather grid in nsplit chunks: partial[z][m][n] (FP32), then
+// out[m*ldm + n*ldn] = sum_z partial[z][m][n].
+struct WgradArgs {
+    int32_t M, N;
+    const bf16 *A;
+    int32_t lda, acoff;
+    Gather g;
+    int32_t nsplit, chunk;  // pixels per split, multiple of 32
+    float *partial;
+    float *out;
+    int32_t ldm, ldn;
+};
+
+hipError_t gemm(const GemmArgs &a, hipStream_t s);
+hipError_t wgrad(const WgradArgs &a, hipStream_t s);
+// bias gradient: db[c] = sum_p dz[p][coff + c]; scratch holds nsplit * C floats
+hipError_t bias_grad(const bf16 *dz, int32_t ld, int32_t coff, int32_t C, int32_t P, float *db, float *scratch,
+                     int32_t nsplit, hipStream_t s);
+// dz = dy * (y > 0 ? 1 : slope), same layout for y and dy (slices allowed)
+hipError_t act_bwd(bf16 *dz, int32_t ldz, int32_t zoff, const bf16 *dy, int32_t ldy, int32_t yoff,
+                   const bf16 *y, int32_t ld, int32_t coff, int32_t C, int32_t P, float slope, hipStream_t s);
+// 3x3 stride-2 pad-1 average pooling (count_include_pad) and its adjoint
+hipError_t pool_fwd(const bf16 *in, int32_t ldi, int32_t coff, int32_t C, int32_t H, int32_t W, bf16 *out,
+                    hipStream_t s);
+hipError_t pool_bwd(const bf16 *dout, int32_t C, int32_t H, int32_t W, bf16 *din, int32_t ldi, int32_t coff,
+                    int32_t accumulate, hipStream_t s);
+// 1x1 output conv (C -> 1) to FP32, MSE loss partials and its gradient
+hipError_t outc_fwd(const bf16 *x, int32_t C, int32_t P, const float *w, const float *b, float *y,
+                    hipStream_t s);
+hipError_t mse(const float *y, const float *t, int32_t P, double *partials, int32_t nblk, float *dy,
+               hipStream_t s);
+hipError_t outc_bwd(const bf16 *x, int32_t C, int32_t P, const float *w, const float *dy, bf16 *dx,
+                    float *part_w, int32_t nblk, hipStream_t s);
+hipError_t outc_wgrad_reduce(const float *part_w, int32_t C, int32_t nblk, float *dw, float *db, hipStream_t s);
+hipError_t sum_partials_d(const double *p, int32_t n, double *out, float scale, float *out_f, hipStream_t s);
+// Adam on a flat FP32 parameter vector; also refreshes the bf16 copy.
+// hyper[0] = learning rate, [1] = 1 - beta1^t, [2] = 1 - beta2^t (device).
+hipError_t adam(float *p, const float *g, float *m, float *v, bf16 *pb, int64_t n, const float *hyper,
+                float beta1, float beta2, float eps, hipStream_t s);
+hipError_t to_bf16(const float *x, bf16 *y, int64_t n, hipStream_t s);
+// max |x| into out[0]
+hipError_t absmax(const float *x, int64_t n, float *out, hipStream_t s);
+// normalised, reflect-padded input: dst[(i,j)] = src[refl(i-py)][refl(j-px)] / max
+hipError_t pad_norm(const float *src, int32_t nz, int32_t nx, int32_t H, int32_t W, int32_t py, int32_t px,
+                    const float *maxabs, bf16 *dst_b, float *dst_f, hipStream_t s);
+// crop and rescale: out[i][j] = y[(i+py)*W + j+px] * max
+hipError_t crop_scale(const float *y, int32_t H, int32_t W, int32_t py, int32_t px, int32_t nz, int32_t nx,
+                      const float *maxabs, float *out, hipStream_t s);
+hipError_t fill_f(float *p, int64_t n, float v, hipStream_t s);
+hipError_t weight_flip(const float *w, int32_t Cout, int32_t Cin, bf16 *wt, hipStream_t s);
+hipError_t convt_dgrad_weights(const float *wt, int32_t Cin, int32_t Cout, bf16 *out, hipStream_t s);
+
+}  // namespace dbl

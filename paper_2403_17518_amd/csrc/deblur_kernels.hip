@@ -1,0 +1,718 @@
+// HIP kernels (gfx950) of the deblurring network that approximates the
+// inverse Hessian (paper section 2.3: a UNet-like network trained to map the
+// doubly migrated image to the FWI gradient; architecture in Appendix A,
+// Table 1).
+//
+// Convolutions are implicit GEMMs on the bf16 matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation): a workgroup of 4 waves owns a
+// (32*WM) x (32*WN) output tile, stages 32-deep K slices of the weight matrix
+// and of the gathered activations in LDS, and each wave accumulates one 32x32
+// block. The same kernel runs the forward 3x3 convolutions, their data
+// gradients (with flipped, transposed weights), the 2x2 stride-2 transposed
+// convolutions (scatter epilogue) and their data gradients (stride-2 gather).
+// Weight gradients reduce over pixels in a second kernel, split over pixel
+// chunks with a deterministic reduction of the partial sums.
+#include "deblur_internal.h"
+
+namespace dbl {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kBK = 32;
+constexpr int kLDK = kBK + 8;  // LDS row stride (bf16): 80 B, 16-B aligned
+
+__device__ __forceinline__ float bf2f(bf16 x) { return float(x); }
+__device__ __forceinline__ bf16 f2bf(float x) { return bf16(x); }
+
+// gathered source pixel index, or -1 outside the source grid
+__device__ __forceinline__ int64_t gather_pix(const Gather &g, int p, int tap)
+{
+    const int i = p / g.W, j = p - (p / g.W) * g.W;
+    const int si = i * g.stride + tap / g.tapw + g.d0;
+    const int sj = j * g.stride + tap % g.tapw + g.d0;
+    if (si < 0 || si >= g.Hs || sj < 0 || sj >= g.Ws) return -1;
+    return int64_t(si) * g.Ws + sj;
+}
+
+template <int WM, int WN, bool VEC>
+__global__ __launch_bounds__(256) void k_gemm(const GemmArgs a)
+{
+    constexpr int BM = 32 * WM, BN = 32 * WN;
+    __shared__ __attribute__((aligned(16))) bf16 As[BM * kLDK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[BN * kLDK];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w / WN, wn = w % WN;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int nk = (a.K + kBK - 1) / kBK;
+    const Gather &g = a.g;
+
+    constexpr int ACH = BM * kBK / 8, BCH = BN * kBK / 8;   // 16-byte chunks per tile
+    constexpr int AR = (ACH + 255) / 256, BR = (BCH + 255) / 256;
+    uint4 ra[AR], rb[BR];
+    // scalar staging for the generic path
+    constexpr int AE = (BM * kBK + 255) / 256, BE = (BN * kBK + 255) / 256;
+    bf16 sa[VEC ? 1 : AE], sb[VEC ? 1 : BE];
+
+    auto load_tiles = [&](int kt) {
+        const int kbase = kt * kBK;
+        if constexpr (VEC) {
+#pragma unroll
+            for (int r = 0; r < AR; ++r) {
+                const int c = tid + r * 256;
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (c < ACH) {
+                    const int row = c / 4, kc = (c % 4) * 8;
+                    if (m0 + row < a.M)
+                        v = *reinterpret_cast<const uint4 *>(a.A + int64_t(m0 + row) * a.lda + kbase + kc);
+                }
+                ra[r] = v;
+            }
+#pragma unroll
+            for (int r = 0; r < BR; ++r) {
+                const int c = tid + r * 256;
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (c < BCH) {
+                    const int nl = c / 4, kc = (c % 4) * 8;
+                    const int p = n0 + nl;
+                    const int k = kbase + kc;
+                    if (p < a.N) {
+                        const int tap = k / g.Cb, ch = k - tap * g.Cb;
+                        const int64_t sp = gather_pix(g, p, tap);
+                        if (sp >= 0) v = *reinterpret_cast<const uint4 *>(g.src + sp * g.ld + g.coff + ch);
+                    }
+                }
+                rb[r] = v;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < AE; ++r) {
+                const int e = tid + r * 256;
+                bf16 v = f2bf(0.f);
+                if (e < BM * kBK) {
+                    const int row = e / kBK, k = kbase + e % kBK;
+                    if (m0 + row < a.M && k < a.K) v = a.A[int64_t(m0 + row) * a.lda + k];
+                }
+                sa[r] = v;
+            }
+#pragma unroll
+            for (int r = 0; r < BE; ++r) {
+                const int e = tid + r * 256;
+                bf16 v = f2bf(0.f);
+                if (e < BN * kBK) {
+                    const int nl = e / kBK, k = kbase + e % kBK;
+                    const int p = n0 + nl;
+                    if (p < a.N && k < a.K) {
+                        const int tap = k / g.Cb, ch = k - tap * g.Cb;
+                        const int64_t sp = gather_pix(g, p, tap);
+                        if (sp >= 0) v = g.src[sp * g.ld + g.coff + ch];
+                    }
+                }
+                sb[r] = v;
+            }
+        }
+    };
+    auto store_tiles = [&]() {
+        if constexpr (VEC) {
+#pragma unroll
+            for (int r = 0; r < AR; ++r) {
+                const int c = tid + r * 256;
+                if (c < ACH) *reinterpret_cast<uint4 *>(&As[(c / 4) * kLDK + (c % 4) * 8]) = ra[r];
+            }
+#pragma unroll
+            for (int r = 0; r < BR; ++r) {
+                const int c = tid + r * 256;
+                if (c < BCH) *reinterpret_cast<uint4 *>(&Bs[(c / 4) * kLDK + (c % 4) * 8]) = rb[r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < AE; ++r) {
+                const int e = tid + r * 256;
+                if (e < BM * kBK) As[(e / kBK) * kLDK + e % kBK] = sa[r];
+            }
+#pragma unroll
+            for (int r = 0; r < BE; ++r) {
+                const int e = tid + r * 256;
+                if (e < BN * kBK) Bs[(e / kBK) * kLDK + e % kBK] = sb[r];
+            }
+        }
+    };
+
+    f32x16 acc = {};
+    load_tiles(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        __syncthreads();
+        store_tiles();
+        __syncthreads();
+        if (kt + 1 < nk) load_tiles(kt + 1);
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const bf16x8 av =
+                *reinterpret_cast<const bf16x8 *>(&As[(wm * 32 + lane % 32) * kLDK + kk * 16 + 8 * (lane / 32)]);
+            const bf16x8 bv =
+                *reinterpret_cast<const bf16x8 *>(&Bs[(wn * 32 + lane % 32) * kLDK + kk * 16 + 8 * (lane / 32)]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+    }
+    // epilogue: lane holds rows m = 8*(i/4) + 4*(lane/32) + i%4, column lane%32
+    const int n = n0 + wn * 32 + lane % 32;
+    if (n >= a.N) return;
+    const int pi = n / g.W, pj = n - (n / g.W) * g.W;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int m = m0 + wm * 32 + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+        if (m >= a.M) continue;
+        int co = m;
+        int64_t pix = n;
+        if (a.scatter) {
+            const int ab = m / a.Cout;
+            co = m - ab * a.Cout;
+            pix = int64_t(2 * pi + ab / 2) * a.Wo + 2 * pj + ab % 2;
+        }
+        float v = acc[i];
+        if (a.bias) v += a.bias[co];
+        if (a.act) v = v > 0.f ? v : a.slope * v;
+        a.out[pix * a.out_ld + a.out_coff + co] = f2bf(v);
+    }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_wgrad(const WgradArgs a)
+{
+    constexpr int BM = 64, BN = 64;
+    __shared__ __attribute__((aligned(16))) bf16 As[BM * kLDK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[BN * kLDK];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w / 2, wn = w % 2;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const Gather &g = a.g;
+    const int P = g.H * g.W;
+    const int p_lo = blockIdx.z * a.chunk;
+    const int p_hi = min(P, p_lo + a.chunk);
+    const int nk = p_hi > p_lo ? (p_hi - p_lo + kBK - 1) / kBK : 0;
+
+    // VEC: each thread moves one 8-wide chunk of A (8 m values of one pixel)
+    // and one of B (8 n values of one pixel); LDS tiles are [m][pixel] and
+    // [n][pixel] so the matrix-core operands read 8 consecutive pixels.
+    uint4 ra = make_uint4(0, 0, 0, 0), rb = make_uint4(0, 0, 0, 0);
+    bf16 sa[8], sb[8];
+    int pl = 0, mc = 0;
+    auto load_tiles = [&](int kt) {
+        const int pbase = p_lo + kt * kBK;
+        if constexpr (VEC) {
+            pl = tid / 8;
+            mc = (tid % 8) * 8;
+            const int p = pbase + pl;
+            ra = make_uint4(0, 0, 0, 0);
+            rb = make_uint4(0, 0, 0, 0);
+            if (p < p_hi) {
+                if (m0 + mc < a.M) ra = *reinterpret_cast<const uint4 *>(a.A + int64_t(p) * a.lda + a.acoff + m0 + mc);
+                const int nn = n0 + mc;
+                if (nn < a.N) {
+                    const int tap = nn / g.Cb, ch = nn - tap * g.Cb;
+                    const int64_t sp = gather_pix(g, p, tap);
+                    if (sp >= 0) rb = *reinterpret_cast<const uint4 *>(g.src + sp * g.ld + g.coff + ch);
+                }
+            }
+        } else {
+            pl = tid / 8;
+            mc = (tid % 8) * 8;
+            const int p = pbase + pl;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                bf16 va = f2bf(0.f), vb = f2bf(0.f);
+                if (p < p_hi) {
+                    if (m0 + mc + e < a.M) va = a.A[int64_t(p) * a.lda + a.acoff + m0 + mc + e];
+                    const int nn = n0 + mc + e;
+                    if (nn < a.N) {
+                        const int tap = nn / g.Cb, ch = nn - tap * g.Cb;
+                        const int64_t sp = gather_pix(g, p, tap);
+                        if (sp >= 0) vb = g.src[sp * g.ld + g.coff + ch];
+                    }
+                }
+                sa[e] = va;
+                sb[e] = vb;
+            }
+        }
+    };
+    auto store_tiles = [&]() {
+        if constexpr (VEC) {
+            const bf16 *pa = reinterpret_cast<const bf16 *>(&ra);
+            const bf16 *pb = reinterpret_cast<const bf16 *>(&rb);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                As[(mc + e) * kLDK + pl] = pa[e];
+                Bs[(mc + e) * kLDK + pl] = pb[e];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                As[(mc + e) * kLDK + pl] = sa[e];
+                Bs[(mc + e) * kLDK + pl] = sb[e];
+            }
+        }
+    };
+
+    f32x16 acc = {};
+    if (nk > 0) load_tiles(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        __syncthreads();
+        store_tiles();
+        __syncthreads();
+        if (kt + 1 < nk) load_tiles(kt + 1);
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const bf16x8 av =
+                *reinterpret_cast<const bf16x8 *>(&As[(wm * 32 + lane % 32) * kLDK + kk * 16 + 8 * (lane / 32)]);
+            const bf16x8 bv =
+                *reinterpret_cast<const bf16x8 *>(&Bs[(wn * 32 + lane % 32) * kLDK + kk * 16 + 8 * (lane / 32)]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+    }
+    const int n = n0 + wn * 32 + lane % 32;
+    if (n >= a.N) return;
+    float *part = a.partial + int64_t(blockIdx.z) * a.M * a.N;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int m = m0 + wm * 32 + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+        if (m < a.M) part[int64_t(m) * a.N + n] = acc[i];
+    }
+}
+
+__global__ void k_wgrad_reduce(const float *part, int32_t M, int32_t N, int32_t nsplit, float *out, int32_t ldm,
+                               int32_t ldn)
+{
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(M) * N) return;
+    float s = 0.f;
+    for (int z = 0; z < nsplit; ++z) s += part[int64_t(z) * M * N + e];
+    const int m = int(e / N), n = int(e % N);
+    out[int64_t(m) * ldm + int64_t(n) * ldn] = s;
+}
+
+// db[c] = sum_p dz[p][coff + c]: block (channel group of 64, pixel split),
+// then a second pass over the splits in fixed order.
+__global__ __launch_bounds__(256) void k_bias_part(const bf16 *dz, int32_t ld, int32_t coff, int32_t C, int32_t P,
+                                                   int32_t chunk, float *part)
+{
+    __shared__ float red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int r = threadIdx.x >> 6;
+    const int p0 = blockIdx.y * chunk, p1 = min(P, p0 + chunk);
+    float s = 0.f;
+    if (c < C)
+        for (int p = p0 + r; p < p1; p += 4) s += bf2f(dz[int64_t(p) * ld + coff + c]);
+    red[r][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (r == 0 && c < C)
+        part[int64_t(blockIdx.y) * C + c] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                                            red[3][threadIdx.x];
+}
+
+__global__ void k_sum_rows(const float *part, int32_t rows, int32_t C, float *out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    float s = 0.f;
+    for (int r = 0; r < rows; ++r) s += part[int64_t(r) * C + c];
+    out[c] = s;
+}
+
+__global__ void k_act_bwd(bf16 *dz, int32_t ldz, int32_t zoff, const bf16 *dy, int32_t ldy, int32_t yoff,
+                          const bf16 *y, int32_t ld, int32_t coff, int32_t C, int32_t P, float slope)
+{
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(P) * C) return;
+    const int64_t p = e / C;
+    const int c = int(e - p * C);
+    const float d = bf2f(dy[p * ldy + yoff + c]);
+    const float yy = bf2f(y[p * ld + coff + c]);
+    dz[p * ldz + zoff + c] = f2bf(yy > 0.f ? d : slope * d);
+}
+
+__global__ void k_pool_fwd(const bf16 *in, int32_t ldi, int32_t coff, int32_t C, int32_t H, int32_t W, bf16 *out)
+{
+    const int Ho = H / 2, Wo = W / 2;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(Ho) * Wo * C) return;
+    const int c = int(e % C);
+    const int64_t q = e / C;
+    const int i = int(q / Wo), j = int(q % Wo);
+    float s = 0.f;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int y = 2 * i + dy, x = 2 * j + dx;
+            if (y >= 0 && y < H && x >= 0 && x < W) s += bf2f(in[(int64_t(y) * W + x) * ldi + coff + c]);
+        }
+    out[q * C + c] = f2bf(s * (1.0f / 9.0f));
+}
+
+__global__ void k_pool_bwd(const bf16 *dout, int32_t C, int32_t H, int32_t W, bf16 *din, int32_t ldi, int32_t coff,
+                           int32_t accumulate)
+{
+    const int Ho = H / 2, Wo = W / 2;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(H) * W * C) return;
+    const int c = int(e % C);
+    const int64_t q = e / C;
+    const int y = int(q / W), x = int(q % W);
+    float s = 0.f;
+    for (int i = (y - 1 + 1) / 2; i <= (y + 1) / 2; ++i) {
+        if (i < 0 || i >= Ho || 2 * i - y > 1 || y - 2 * i > 1) continue;
+        for (int j = (x - 1 + 1) / 2; j <= (x + 1) / 2; ++j) {
+            if (j < 0 || j >= Wo || 2 * j - x > 1 || x - 2 * j > 1) continue;
+            s += bf2f(dout[(int64_t(i) * Wo + j) * C + c]);
+        }
+    }
+    s *= (1.0f / 9.0f);
+    bf16 *dst = din + q * ldi + coff + c;
+    if (accumulate) s += bf2f(*dst);
+    *dst = f2bf(s);
+}
+
+__global__ void k_outc_fwd(const bf16 *x, int32_t C, int32_t P, const float *w, const float *b, float *y)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    float s = b[0];
+    for (int c = 0; c < C; ++c) s += w[c] * bf2f(x[int64_t(p) * C + c]);
+    y[p] = s;
+}
+
+__global__ __launch_bounds__(256) void k_mse(const float *y, const float *t, int32_t P, double *partials, float *dy)
+{
+    __shared__ double red[256];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (p < P) {
+        const float d = y[p] - t[p];
+        s = double(d) * double(d);
+        dy[p] = 2.0f * d / float(P);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_outc_bwd(const bf16 *x, int32_t C, int32_t P, const float *w,
+                                                  const float *dy, bf16 *dx, float *part_w)
+{
+    // block of 256 pixels; part_w[block][c] for c < C, part_w[block][C] = sum dy
+    __shared__ float red[256];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const float d = p < P ? dy[p] : 0.f;
+    for (int c = 0; c <= C; ++c) {
+        float v = 0.f;
+        if (p < P) {
+            if (c < C) {
+                const float xv = bf2f(x[int64_t(p) * C + c]);
+                dx[int64_t(p) * C + c] = f2bf(w[c] * d);
+                v = d * xv;
+            } else {
+                v = d;
+            }
+        }
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int k = 128; k > 0; k >>= 1) {
+            if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part_w[int64_t(blockIdx.x) * (C + 1) + c] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_outc_reduce(const float *part, int32_t C, int32_t nblk, float *dw, float *db)
+{
+    const int c = threadIdx.x;
+    if (c > C) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += part[int64_t(b) * (C + 1) + c];
+    if (c < C) dw[c] = s;
+    else db[0] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sum_d(const double *p, int32_t n, double *out, float scale, float *out_f)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += p[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (out) *out = red[0] * scale;
+        if (out_f) *out_f = float(red[0] * scale);
+    }
+}
+
+__global__ void k_adam(float *p, const float *g, float *m, float *v, bf16 *pb, int64_t n, const float *hyper,
+                       float beta1, float beta2, float eps)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float lr = hyper[0], c1 = hyper[1], c2 = hyper[2];
+    const float gi = g[i];
+    const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+    const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float upd = (mi / c1) / (sqrtf(vi / c2) + eps);
+    const float pi = p[i] - lr * upd;
+    p[i] = pi;
+    pb[i] = f2bf(pi);
+}
+
+__global__ void k_to_bf16(const float *x, bf16 *y, int64_t n)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+__global__ __launch_bounds__(256) void k_absmax(const float *x, int64_t n, float *out)
+{
+    __shared__ float red[256];
+    float m = 0.f;
+    for (int64_t i = threadIdx.x; i < n; i += 256) m = fmaxf(m, fabsf(x[i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + k]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__device__ __forceinline__ int reflect(int k, int n)
+{
+    if (n == 1) return 0;
+    while (k < 0 || k >= n) {
+        if (k < 0) k = -k;
+        if (k >= n) k = 2 * (n - 1) - k;
+    }
+    return k;
+}
+
+__global__ void k_pad_norm(const float *src, int32_t nz, int32_t nx, int32_t H, int32_t W, int32_t py, int32_t px,
+                           const float *maxabs, bf16 *dst_b, float *dst_f)
+{
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(H) * W) return;
+    const int i = int(e / W), j = int(e % W);
+    const float mx = maxabs[0];
+    const float s = mx > 0.f ? 1.0f / mx : 0.f;
+    const float v = src[int64_t(reflect(i - py, nz)) * nx + reflect(j - px, nx)] * s;
+    if (dst_b) dst_b[e] = f2bf(v);
+    if (dst_f) dst_f[e] = v;
+}
+
+__global__ void k_crop_scale(const float *y, int32_t H, int32_t W, int32_t py, int32_t px, int32_t nz, int32_t nx,
+                             const float *maxabs, float *out)
+{
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(nz) * nx) return;
+    const int i = int(e / nx), j = int(e % nx);
+    (void)H;
+    out[e] = y[int64_t(i + py) * W + j + px] * maxabs[0];
+}
+
+__global__ void k_fill_f(float *p, int64_t n, float v)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// data-gradient weights of a 3x3 conv: wt[ci][t*Cout + co] = w[co][(8-t)*Cin + ci]
+__global__ void k_weight_flip(const float *w, int32_t Cout, int32_t Cin, bf16 *wt)
+{
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(Cout) * Cin * 9) return;
+    const int ci = int(e / (9 * Cout));
+    const int rem = int(e % (9 * Cout));
+    const int t = rem / Cout, co = rem % Cout;
+    wt[e] = f2bf(w[int64_t(co) * 9 * Cin + (8 - t) * Cin + ci]);
+}
+
+// data-gradient weights of a 2x2 stride-2 transposed conv:
+// out[ci][ab*Cout + co] = wt[(ab*Cout + co)][ci]
+__global__ void k_convt_dgrad_w(const float *wt, int32_t Cin, int32_t Cout, bf16 *out)
+{
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(4) * Cout * Cin) return;
+    const int ci = int(e / (4 * Cout));
+    const int r = int(e % (4 * Cout));
+    out[e] = f2bf(wt[int64_t(r) * Cin + ci]);
+}
+
+inline unsigned nblocks(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t gemm(const GemmArgs &a, hipStream_t s)
+{
+    if (a.M <= 0 || a.N <= 0) return hipSuccess;
+    const bool vec = a.K % kBK == 0 && a.g.Cb % 8 == 0 && a.lda % 8 == 0 && a.g.ld % 8 == 0 && a.g.coff % 8 == 0;
+    // thin outputs use 32-row tiles, wide ones 64x64
+    if (a.M <= 32) {
+        const dim3 grid(nblocks(a.N, 128), nblocks(a.M, 32));
+        if (vec) hipLaunchKernelGGL((k_gemm<1, 4, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_gemm<1, 4, false>), grid, dim3(256), 0, s, a);
+    } else {
+        const dim3 grid(nblocks(a.N, 64), nblocks(a.M, 64));
+        if (vec) hipLaunchKernelGGL((k_gemm<2, 2, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_gemm<2, 2, false>), grid, dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t wgrad(const WgradArgs &a, hipStream_t s)
+{
+    if (a.M <= 0 || a.N <= 0) return hipSuccess;
+    const bool vec = a.g.Cb % 8 == 0 && a.lda % 8 == 0 && a.acoff % 8 == 0 && a.g.ld % 8 == 0 &&
+                     a.g.coff % 8 == 0 && a.M % 8 == 0 && a.N % 8 == 0;
+    const dim3 grid(nblocks(a.N, 64), nblocks(a.M, 64), unsigned(a.nsplit));
+    if (vec) hipLaunchKernelGGL(k_wgrad<true>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_wgrad<false>, grid, dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(int64_t(a.M) * a.N)), dim3(256), 0, s, a.partial, a.M, a.N,
+                       a.nsplit, a.out, a.ldm, a.ldn);
+    return hipGetLastError();
+}
+
+hipError_t bias_grad(const bf16 *dz, int32_t ld, int32_t coff, int32_t C, int32_t P, float *db, float *scratch,
+                     int32_t nsplit, hipStream_t s);
+
+hipError_t act_bwd(bf16 *dz, int32_t ldz, int32_t zoff, const bf16 *dy, int32_t ldy, int32_t yoff, const bf16 *y,
+                   int32_t ld, int32_t coff, int32_t C, int32_t P, float slope, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_act_bwd, dim3(nblocks(int64_t(P) * C)), dim3(256), 0, s, dz, ldz, zoff, dy, ldy, yoff, y, ld,
+                       coff, C, P, slope);
+    return hipGetLastError();
+}
+
+hipError_t pool_fwd(const bf16 *in, int32_t ldi, int32_t coff, int32_t C, int32_t H, int32_t W, bf16 *out,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks(int64_t(H / 2) * (W / 2) * C)), dim3(256), 0, s, in, ldi, coff, C, H,
+                       W, out);
+    return hipGetLastError();
+}
+
+hipError_t pool_bwd(const bf16 *dout, int32_t C, int32_t H, int32_t W, bf16 *din, int32_t ldi, int32_t coff,
+                    int32_t accumulate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pool_bwd, dim3(nblocks(int64_t(H) * W * C)), dim3(256), 0, s, dout, C, H, W, din, ldi, coff,
+                       accumulate);
+    return hipGetLastError();
+}
+
+hipError_t outc_fwd(const bf16 *x, int32_t C, int32_t P, const float *w, const float *b, float *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_outc_fwd, dim3(nblocks(P)), dim3(256), 0, s, x, C, P, w, b, y);
+    return hipGetLastError();
+}
+
+hipError_t mse(const float *y, const float *t, int32_t P, double *partials, int32_t nblk, float *dy, hipStream_t s)
+{
+    (void)nblk;
+    hipLaunchKernelGGL(k_mse, dim3(nblocks(P)), dim3(256), 0, s, y, t, P, partials, dy);
+    return hipGetLastError();
+}
+
+hipError_t outc_bwd(const bf16 *x, int32_t C, int32_t P, const float *w, const float *dy, bf16 *dx, float *part_w,
+                    int32_t nblk, hipStream_t s)
+{
+    (void)nblk;
+    hipLaunchKernelGGL(k_outc_bwd, dim3(nblocks(P)), dim3(256), 0, s, x, C, P, w, dy, dx, part_w);
+    return hipGetLastError();
+}
+
+hipError_t outc_wgrad_reduce(const float *part_w, int32_t C, int32_t nblk, float *dw, float *db, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_outc_reduce, dim3(1), dim3(((C + 1 + 63) / 64) * 64), 0, s, part_w, C, nblk, dw, db);
+    return hipGetLastError();
+}
+
+hipError_t sum_partials_d(const double *p, int32_t n, double *out, float scale, float *out_f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_d, dim3(1), dim3(256), 0, s, p, n, out, scale, out_f);
+    return hipGetLastError();
+}
+
+hipError_t adam(float *p, const float *g, float *m, float *v, bf16 *pb, int64_t n, const float *hyper, float beta1,
+                float beta2, float eps, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(n)), dim3(256), 0, s, p, g, m, v, pb, n, hyper, beta1, beta2, eps);
+    return hipGetLastError();
+}
+
+hipError_t to_bf16(const float *x, bf16 *y, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblocks(n)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t absmax(const float *x, int64_t n, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, x, n, out);
+    return hipGetLastError();
+}
+
+hipError_t pad_norm(const float *src, int32_t nz, int32_t nx, int32_t H, int32_t W, int32_t py, int32_t px,
+                    const float *maxabs, bf16 *dst_b, float *dst_f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pad_norm, dim3(nblocks(int64_t(H) * W)), dim3(256), 0, s, src, nz, nx, H, W, py, px, maxabs,
+                       dst_b, dst_f);
+    return hipGetLastError();
+}
+
+hipError_t crop_scale(const float *y, int32_t H, int32_t W, int32_t py, int32_t px, int32_t nz, int32_t nx,
+                      const float *maxabs, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_crop_scale, dim3(nblocks(int64_t(nz) * nx)), dim3(256), 0, s, y, H, W, py, px, nz, nx,
+                       maxabs, out);
+    return hipGetLastError();
+}
+
+hipError_t fill_f(float *p, int64_t n, float v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f, dim3(nblocks(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t weight_flip(const float *w, int32_t Cout, int32_t Cin, bf16 *wt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_weight_flip, dim3(nblocks(int64_t(Cout) * Cin * 9)), dim3(256), 0, s, w, Cout, Cin, wt);
+    return hipGetLastError();
+}
+
+hipError_t convt_dgrad_weights(const float *wt, int32_t Cin, int32_t Cout, bf16 *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_convt_dgrad_w, dim3(nblocks(int64_t(4) * Cout * Cin)), dim3(256), 0, s, wt, Cin, Cout, out);
+    return hipGetLastError();
+}
+
+hipError_t bias_grad(const bf16 *dz, int32_t ld, int32_t coff, int32_t C, int32_t P, float *db, float *scratch,
+                     int32_t nsplit, hipStream_t s)
+{
+    const int chunk = (P + nsplit - 1) / nsplit;
+    hipLaunchKernelGGL(k_bias_part, dim3(unsigned((C + 63) / 64), unsigned(nsplit)), dim3(256), 0, s, dz, ld, coff, C,
+                       P, chunk, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_rows, dim3(nblocks(C)), dim3(256), 0, s, scratch, nsplit, C, db);
+    return hipGetLastError();
+}
+
+}  // namespace dbl

@@ -879,6 +879,11 @@ int forward_sweep_sampled(fwi_ctx *c, const float *v)
 
 }  // namespace
 
+namespace fwi {
+hipStream_t ctx_stream(const fwi_ctx *c) { return c->stream; }
+int ctx_device(const fwi_ctx *c) { return c->device; }
+}  // namespace fwi
+
 // ===========================================================================
 // public entry points
 

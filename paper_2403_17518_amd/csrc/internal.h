@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+struct fwi_ctx;
+
 namespace fwi {
 
 constexpr int kLanes = 64;          // wavefront width on CDNA
@@ -110,6 +112,10 @@ struct FinalArgs {
     float dt2;
     float *img;
 };
+
+// context accessors for the other parts of the library (deblur_api.hip)
+hipStream_t ctx_stream(const struct ::fwi_ctx *c);
+int ctx_device(const struct ::fwi_ctx *c);
 
 hipError_t launch_step(int flags, const StepArgs &a, hipStream_t s);
 hipError_t launch_born_step(const StepArgs &a, hipStream_t s);

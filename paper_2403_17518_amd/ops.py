@@ -80,11 +80,14 @@ class FwiContext:
     def trim(self):
         _check(self.lib, self.ctx, self.lib.fwi_ctx_trim(self.ctx))
 
+    def _prep_stream(self):
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(self.lib, self.ctx, self.lib.fwi_ctx_set_stream(self.ctx, C.c_void_p(stream)))
+
     def _prep(self, grid, acq):
         g = _abi.make_grid(grid)
         gv = _abi.GeomView(acq, grid)
-        stream = torch.cuda.current_stream(self.device).cuda_stream
-        _check(self.lib, self.ctx, self.lib.fwi_ctx_set_stream(self.ctx, C.c_void_p(stream)))
+        self._prep_stream()
         return g, gv
 
     def _data_size(self, grid, acq) -> int:

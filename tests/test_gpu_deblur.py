@@ -1,0 +1,168 @@
+"""GPU parity of the deblurring network (bf16 matrix cores, FP32 accumulation)
+against the FP64 network oracle, on weights and inputs drawn by the shared
+seeded generators.
+
+Tolerances: bf16 keeps 8 significant bits (unit roundoff 2^-9 ~ 2e-3); each
+conv rounds its inputs and output once, and errors from ~15 layers add in
+quadrature, so the network output is held to 3e-2 relative L2 and the
+parameter gradients (two more passes) to 6e-2 relative L2 per tensor group.
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import deblur_ref as R
+from synth import netparams
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2403_17518_amd import ops  # noqa: E402
+from paper_2403_17518_amd.deblur import DeblurConfig, DeblurNet  # noqa: E402
+
+TOL_FWD = 3e-2
+TOL_GRAD = 6e-2
+
+
+def rel(a, b):
+    a, b = np.ravel(np.asarray(a, np.float64)), np.ravel(np.asarray(b, np.float64))
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def smooth_field(H, W, seed):
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((H, W))
+    k = np.exp(-np.arange(-6, 7) ** 2 / 8.0)
+    z = np.apply_along_axis(lambda r: np.convolve(r, k, "same"), 0, z)
+    z = np.apply_along_axis(lambda r: np.convolve(r, k, "same"), 1, z)
+    return z / np.abs(z).max()
+
+
+@pytest.fixture(scope="module")
+def fctx():
+    c = ops.FwiContext(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("depth,base,H,W,slope", [(2, 16, 32, 64, 0.0), (3, 32, 64, 192, 0.2)])
+def test_forward_matches_oracle(fctx, depth, base, H, W, slope):
+    print(f"[deblur] forward depth={depth} base={base} {H}x{W}", flush=True)
+    cfg = DeblurConfig(depth, base, slope, H, W)
+    net = DeblurNet(fctx, cfg)
+    ps = netparams.draw(depth, base, seed=7)
+    flat = netparams.flatten(ps)
+    net.set_params(flat)
+    assert np.array_equal(net.get_params(), flat)
+    x = smooth_field(H, W, 1)
+    y = net.forward_raw(dev(x)).cpu().numpy()
+    ps32 = [torch.as_tensor(p.astype(np.float32).astype(np.float64)) for p in ps]
+    ref = R.forward(ps32, torch.as_tensor(x.astype(np.float32).astype(np.float64)), depth, slope).numpy()
+    e = rel(y, ref)
+    print("forward rel err", e)
+    assert e < TOL_FWD
+    net.close()
+
+
+def test_full_size_forward(fctx):
+    """The configuration trained in FWI: depth 3, widths 32-64-128-256, ReLU,
+    208 x 608."""
+    cfg = DeblurConfig()
+    net = DeblurNet(fctx, cfg)
+    ps = netparams.draw(3, 32, seed=9)
+    net.set_params(netparams.flatten(ps))
+    x = smooth_field(208, 608, 2)
+    y = net.forward_raw(dev(x)).cpu().numpy()
+    ps32 = [torch.as_tensor(p.astype(np.float32).astype(np.float64)) for p in ps]
+    ref = R.forward(ps32, torch.as_tensor(x.astype(np.float32).astype(np.float64)), 3, 0.0).numpy()
+    e = rel(y, ref)
+    print("full-size forward rel err", e)
+    assert e < TOL_FWD
+    net.close()
+
+
+@pytest.mark.parametrize("slope", [0.0, 0.2])
+def test_parameter_gradients_match_oracle(fctx, slope):
+    depth, base, H, W = 2, 16, 32, 64
+    cfg = DeblurConfig(depth, base, slope, H, W)
+    net = DeblurNet(fctx, cfg)
+    ps = netparams.draw(depth, base, seed=11)
+    net.set_params(netparams.flatten(ps))
+    x, t = smooth_field(H, W, 3), smooth_field(H, W, 4)
+    loss, g = net.grad_raw(dev(x), dev(t))
+    ps32 = [p.astype(np.float32).astype(np.float64) for p in ps]
+    lref, gref, _ = R.loss_and_grads(ps32, x.astype(np.float32), t.astype(np.float32), depth, slope)
+    assert abs(loss - lref) < TOL_FWD * lref
+    gg = netparams.unflatten(g, depth, base)
+    names = [n for n, _ in netparams.param_shapes(depth, base)]
+    worst = 0.0
+    for name, a, b in zip(names, gg, gref):
+        if np.linalg.norm(b) == 0:
+            continue
+        e = rel(a, b)
+        worst = max(worst, e)
+        assert e < TOL_GRAD, (name, e)
+    print("worst per-tensor gradient rel err", worst)
+    net.close()
+
+
+def test_training_follows_the_oracle_and_reduces_the_loss(fctx):
+    """Adam + cosine schedule on a known blur: the GPU loss curve tracks the
+    FP64 oracle's and falls by more than 10x."""
+    depth, base, H, W = 2, 16, 32, 64
+    cfg = DeblurConfig(depth, base, 0.0, H, W)
+    net = DeblurNet(fctx, cfg)
+    ps = netparams.draw(depth, base, seed=13)
+    net.set_params(netparams.flatten(ps))
+    y = smooth_field(H, W, 5)
+    k = np.exp(-np.arange(-4, 5) ** 2 / 4.0)
+    x = np.apply_along_axis(lambda r: np.convolve(r, k / k.sum(), "same"), 0, y)
+    x = np.apply_along_axis(lambda r: np.convolve(r, k / k.sum(), "same"), 1, x)
+    steps, lr = 60, 2e-3
+    hist = net.deblur_train(dev(x), dev(y), steps, lr)
+    # oracle on the same normalised pair (no padding: the image fills the grid)
+    xn = (x / np.abs(x).max()).astype(np.float32)
+    yn = (y / np.abs(y).max()).astype(np.float32)
+    _, lref = R.train([p.astype(np.float32).astype(np.float64) for p in ps], xn, yn, depth, steps, lr)
+    print("loss gpu", hist[0], hist[-1], "oracle", lref[0], lref[-1])
+    assert abs(hist[0] - lref[0]) < TOL_FWD * lref[0]
+    assert hist[-1] < hist[0] / 10.0
+    assert abs(np.log(hist[-1] / lref[-1])) < np.log(2.0)
+    net.close()
+
+
+def test_apply_scales_pads_and_crops(fctx):
+    depth, base = 2, 16
+    cfg = DeblurConfig(depth, base, 0.0, 40, 72)
+    net = DeblurNet(fctx, cfg)
+    g = smooth_field(36, 64, 6) * 3.7
+    out = net.deblur_apply(dev(g)).cpu().numpy()
+    xp, mx, py, px = R.normalise_pad(g.astype(np.float32), 40, 72)
+    raw = net.forward_raw(dev(xp)).cpu().numpy()
+    assert (py, px) == (2, 4)
+    assert rel(out, mx * raw[py:py + 36, px:px + 64]) < 1e-2
+    net.close()
+
+
+def test_save_load_reset(fctx):
+    cfg = DeblurConfig(2, 8, 0.0, 16, 32)
+    net = DeblurNet(fctx, cfg, seed=1)
+    p1 = net.get_params()
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "w.bin")
+        net.save(path)
+        net.reset(2)
+        p2 = net.get_params()
+        assert not np.array_equal(p1, p2)
+        net.load(path)
+        assert np.array_equal(net.get_params(), p1)
+    net.close()
