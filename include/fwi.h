@@ -156,6 +156,12 @@ int fwi_gradient(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
                  const float *v, const float *d_obs, float *g,
                  double *misfit, float *d_syn);
 
+/* misfit = 1/2 ||F(v) - d_obs||^2 (section 2.1 eq. 2) without the adjoint:
+ * one forward sweep and the residual reduction (line searches). misfit is a
+ * HOST pointer; the call waits for it. */
+int fwi_misfit(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
+               const float *v, const float *d_obs, double *misfit);
+
 /* dd = J dv: Born (single-scattering) data of the perturbation dv of the
  * background velocity v0. */
 int born_demig(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,

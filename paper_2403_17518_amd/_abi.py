@@ -76,6 +76,7 @@ SIGNATURES = {
     "fwi_forward": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P]),
     "fwi_gradient": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P,
                                C.POINTER(C.c_double), _P]),
+    "fwi_misfit": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, C.POINTER(C.c_double)]),
     "born_demig": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P]),
     "born_mig": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P]),
     "deblur_create": (C.c_int, [_P, C.POINTER(deblur_cfg), C.c_uint64, C.POINTER(_P)]),

@@ -1061,6 +1061,40 @@ int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float
     return finish_stats(c);
 }
 
+int fwi_misfit(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v, const float *d_obs,
+               double *misfit)
+{
+    int rc = begin_call(c, g, geo);
+    if (rc) return rc;
+    const Plan &p = c->plan;
+    if (!misfit) return set_err(c, FWI_EINVAL, "misfit is NULL");
+    if (!d_obs && p.data_size > 0) return set_err(c, FWI_EINVAL, "d_obs is NULL");
+    if ((rc = check_model(c, v, "v")) || (rc = prepare(c, v))) return rc;
+    if ((rc = forward_sweep_sampled(c, v))) return rc;
+    TraceArgs t = trace_args(c);
+    t.tm_in = static_cast<const float *>(c->samples.p);
+    t.alpha = 1.f;
+    t.tr_in = d_obs;
+    t.beta = -1.f;
+    const int64_t nblk = int64_t((p.Q + 63) / 64) * ((p.nt_max + 63) / 64);
+    if ((rc = ensure(c, c->partials, size_t(std::max<int64_t>(nblk, 1)) * sizeof(double))) ||
+        (rc = ensure(c, c->misfit, sizeof(double))))
+        return rc;
+    t.partials = static_cast<double *>(c->partials.p);
+    if ((rc = other(c, launch_traces(t, c->stream, nullptr), "residual"))) return rc;
+    if (nblk > 0) {
+        if ((rc = other(c, launch_sum_partials(t.partials, nblk, static_cast<double *>(c->misfit.p), c->stream),
+                        "misfit")))
+            return rc;
+    } else {
+        HIPCHK(c, hipMemsetAsync(c->misfit.p, 0, sizeof(double), c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->h_misfit, c->misfit.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *misfit = *c->h_misfit;
+    return finish_stats(c);
+}
+
 int born_demig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v0, const float *dv, float *dd)
 {
     int rc = begin_call(c, g, geo);

@@ -1,0 +1,296 @@
+"""Full-waveform-inversion driver: plain gradient descent versus the
+network-preconditioned update of the paper (section 2.3, Fig. 1).
+
+One iteration of the network method:
+  1. g_phi = fwi_gradient(v, d_obs)        (gradient of the misfit; the
+     paper's gradient is g = -g_phi, eq. 13 with d_o - d_s)
+  2. dm1 = born_mig(v, born_demig(v, g))    (doubly migrated image, eq. 15)
+  3. train the network dm1 -> g, warm-started from the previous iteration
+     (transfer learning), reset at every new frequency band
+  4. p = deblur_apply(g); if p is not a descent direction (<p, g_phi> >= 0)
+     the plain direction p = g is used instead (the gradient stays the
+     fallback and the judge)
+  5. line search along p and v <- clip(v + alpha p)
+The plain method skips steps 2-4 (p = g). Both use the same line search:
+a trial step with max|alpha p| = step_frac * v_max, a second at twice that,
+and the minimiser of the parabola through the three misfits.
+
+Multi-scale: the bands low-pass the data with a zero-phase 4th-order
+Butterworth filter (the same filter applied to the wavelet); for synthetic
+inputs the band's observed data are modelled with the filtered wavelet,
+which is the same thing for a linear, time-invariant forward map.
+
+Cost is counted two ways: wave-equation solves in the paper's convention
+(gradient 2, demigration 1, migration 1, each misfit 1) and the stencil
+passes the library actually ran.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+from scipy.signal import butter, sosfiltfilt
+
+from . import ops
+from .deblur import DeblurConfig, DeblurNet
+
+
+@dataclass
+class FwiOptions:
+    method: str = "plain"                 # "plain" or "net"
+    bands: tuple = (3.0, 8.0, 15.0)       # low-pass corner frequencies (Hz)
+    iters_per_band: int = 20
+    step_frac: float = 0.01               # trial step: max|dv| = step_frac * v_max
+    v_min: float = 1400.0
+    v_max: float | None = None            # default: grid.v_ref
+    train_steps_first: int = 500          # Adam steps in a band's first iteration
+    train_steps: int = 200                # ... and in the later ones (warm start)
+    lr: float = 1e-3
+    net: DeblurConfig = field(default_factory=DeblurConfig)
+    seed: int = 2403
+    mute_rows: int = 0                    # zero the update in the top rows (both methods)
+
+
+def lowpass(x: np.ndarray, dt: float, fmax: float, axis: int = -1) -> np.ndarray:
+    """Zero-phase 4th-order Butterworth low-pass (forward-backward)."""
+    sos = butter(4, fmax, btype="low", fs=1.0 / dt, output="sos")
+    return sosfiltfilt(sos, x, axis=axis)
+
+
+def band_acq(acq, grid, fmax):
+    w = np.asarray(acq.wavelet, dtype=np.float64)
+    wf = lowpass(w, grid.dt, fmax).astype(np.float32)
+    return replace_acq(acq, wf)
+
+
+def replace_acq(acq, wavelet):
+    from copy import copy
+    a = copy(acq)
+    a.wavelet = wavelet
+    return a
+
+
+def _sync():
+    torch.cuda.synchronize()
+
+
+class FwiRun:
+    def __init__(self, fctx: ops.FwiContext, grid, acq, v0: np.ndarray, opts: FwiOptions,
+                 v_true: np.ndarray | None = None, log=print):
+        self.fctx, self.grid, self.acq, self.opts, self.log = fctx, grid, acq, opts, log
+        self.dev = fctx.device
+        self.v = torch.from_numpy(np.ascontiguousarray(v0, dtype=np.float32)).to(self.dev)
+        self.v_true = None if v_true is None else torch.from_numpy(
+            np.ascontiguousarray(v_true, dtype=np.float32)).to(self.dev)
+        self.e0 = None if v_true is None else float(torch.linalg.norm(self.v - self.v_true))
+        self.v_max = opts.v_max if opts.v_max is not None else float(grid.v_ref)
+        self.solves = 0           # paper convention
+        self.passes = 0.0         # stencil passes actually run (one field, all shots)
+        self.t0 = None
+        self.history = []
+        self.net = None
+        if opts.method == "net":
+            self.net = DeblurNet(fctx, opts.net, seed=opts.seed)
+
+    def model_error(self) -> float | None:
+        if self.v_true is None:
+            return None
+        return float(torch.linalg.norm(self.v - self.v_true)) / self.e0
+
+    def _count(self, solves: int):
+        """Account one library call: paper-convention solves and the stencil
+        passes it ran (cell-updates / updates of one field pass)."""
+        self.solves += solves
+        st = self.fctx.stats()
+        self.passes += st["cell_updates"] / max(self._updates_per_pass, 1.0)
+
+    def _misfit(self, acq, v, d_obs):
+        phi = self.fctx.fwi_misfit(self.grid, acq, v, d_obs)
+        self._count(1)
+        return phi
+
+    def run(self, observe) -> list:
+        """observe(acq_band) -> d_obs (device tensor) for that band."""
+        o = self.opts
+        self._updates_per_pass = _updates_per_pass(self.grid, self.acq)
+        self.t0 = time.perf_counter()
+        for bi, fmax in enumerate(o.bands):
+            acq_b = band_acq(self.acq, self.grid, fmax)
+            d_obs = observe(acq_b)
+            if self.net is not None and bi > 0:
+                self.net.reset(o.seed + bi)      # a new band starts from scratch
+            for it in range(o.iters_per_band):
+                rec = self.iteration(acq_b, d_obs, bi, it, fmax)
+                self.history.append(rec)
+                self.log(json.dumps(rec))
+        return self.history
+
+    def iteration(self, acq, d_obs, band, it, fmax):
+        o = self.opts
+        t = {}
+        _sync()
+        ta = time.perf_counter()
+        g_phi, phi, _ = self.fctx.fwi_gradient(self.grid, acq, self.v, d_obs)
+        self._count(2)
+        _sync()
+        t["gradient"] = time.perf_counter() - ta
+        g = -g_phi                                   # the paper's gradient
+        if o.mute_rows:
+            g[:o.mute_rows] = 0
+        p = g
+        fallback = None
+        train_loss = None
+        if self.net is not None:
+            ta = time.perf_counter()
+            dd = self.fctx.born_demig(self.grid, acq, self.v, g.contiguous())
+            self._count(1)
+            dm1 = self.fctx.born_mig(self.grid, acq, self.v, dd)
+            self._count(1)
+            _sync()
+            t["pair"] = time.perf_counter() - ta
+            ta = time.perf_counter()
+            steps = o.train_steps_first if it == 0 else o.train_steps
+            hist = self.net.deblur_train(dm1, g.contiguous(), steps, o.lr)
+            train_loss = [float(hist[0]), float(hist[-1])]
+            q = self.net.deblur_apply(g.contiguous())
+            if o.mute_rows:
+                q[:o.mute_rows] = 0
+            _sync()
+            t["train_apply"] = time.perf_counter() - ta
+            fallback = not (float(torch.sum(q * g_phi)) < 0.0 and bool(torch.isfinite(q).all()))
+            if not fallback:
+                p = q
+        # line search along p (shared by both methods)
+        ta = time.perf_counter()
+        pmax = float(p.abs().max())
+        if not pmax > 0:
+            return self._record(band, it, fmax, phi, t, 0.0, fallback, train_loss)
+        a0 = o.step_frac * self.v_max / pmax
+        f1 = self._misfit(acq, self._clip(self.v + a0 * p), d_obs)
+        f2 = self._misfit(acq, self._clip(self.v + 2 * a0 * p), d_obs)
+        alpha = parabola_step(phi, f1, f2, a0)
+        self.v = self._clip(self.v + alpha * p)
+        _sync()
+        t["line_search"] = time.perf_counter() - ta
+        return self._record(band, it, fmax, phi, t, alpha * pmax, fallback, train_loss)
+
+    def _clip(self, v):
+        return torch.clamp(v, self.opts.v_min, self.v_max).contiguous()
+
+    def _record(self, band, it, fmax, phi, t, step, fallback, train_loss):
+        return {"method": self.opts.method, "band": band, "fmax": fmax, "iter": it, "misfit": phi,
+                "model_error": self.model_error(), "solves": self.solves,
+                "stencil_passes": round(self.passes, 3), "wall_s": time.perf_counter() - self.t0,
+                "phase_s": {k: round(v, 4) for k, v in t.items()}, "max_dv": step,
+                "fallback": fallback, "train_loss": train_loss}
+
+
+def _updates_per_pass(grid, acq) -> float:
+    tot = 0.0
+    for s in range(len(acq.src_z)):
+        wnx = grid.nx if acq.win_nx is None else int(acq.win_nx[s])
+        nt = grid.nt_max if acq.nt is None else int(acq.nt[s])
+        tot += (grid.nz + 2 * grid.nb) * (wnx + 2 * grid.nb) * nt
+    return tot
+
+
+def net_grid(nz: int, nx: int, depth: int) -> tuple[int, int]:
+    """Smallest network grid holding an nz x nx image with an even, non-zero
+    reflect padding on each axis and sides divisible by 2^depth."""
+    q = 1 << depth
+
+    def one(n):
+        m = ((n + 2 + q - 1) // q) * q
+        if (m - n) % 2:
+            raise ValueError("the network grid needs even image sides")
+        return m
+
+    return one(nz), one(nx)
+
+
+def parabola_step(phi0: float, f1: float, f2: float, a0: float) -> float:
+    """Step length from misfits at 0, a0 and 2 a0: the parabola's minimiser
+    (clamped to [0, 4 a0]) when it is convex, else the better trial point."""
+    curv = phi0 - 2 * f1 + f2
+    if curv > 0:
+        alpha = a0 * (3 * phi0 - 4 * f1 + f2) / (2 * curv)
+        return min(max(alpha, 0.0), 4 * a0)
+    if min(f1, f2) >= phi0:
+        return 0.0
+    return 2 * a0 if f2 < f1 else a0
+
+
+def time_to_error(plain: list, net: list) -> dict:
+    """Iterations, solves and wall time the network method needs to reach
+    the plain method's final model error."""
+    target = plain[-1]["model_error"]
+    out = {"target_model_error": target, "plain_iters": len(plain),
+           "plain_wall_s": plain[-1]["wall_s"], "plain_solves": plain[-1]["solves"],
+           "net_final_model_error": net[-1]["model_error"]}
+    for k, r in enumerate(net):
+        if r["model_error"] is not None and target is not None and r["model_error"] <= target:
+            out.update({"net_iters": k + 1, "net_wall_s": r["wall_s"], "net_solves": r["solves"]})
+            break
+    else:
+        out.update({"net_iters": None, "net_wall_s": None, "net_solves": None})
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="plain vs network-preconditioned FWI on a seeded workload")
+    ap.add_argument("--workload", default="salt_848x176")
+    ap.add_argument("--method", default="both", choices=["plain", "net", "both"])
+    ap.add_argument("--iters", type=int, default=20, help="iterations per band")
+    ap.add_argument("--bands", default="3,8,15")
+    ap.add_argument("--shots", type=int, default=0)
+    ap.add_argument("--train-first", type=int, default=500)
+    ap.add_argument("--train", type=int, default=200)
+    ap.add_argument("--out", default="")
+    args = ap.parse_args(argv)
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from synth import configs
+    wl = {"salt_848x176": lambda: configs.salt_848x176(args.shots or 100),
+          "salt_1700x350": lambda: configs.salt_1700x350(args.shots or 300),
+          "layered_600x200": lambda: configs.layered_600x200(args.shots or 64)}[args.workload]()
+    grid, acq = wl.grid, wl.acq
+    fctx = ops.FwiContext(0)
+    v_true_t = torch.from_numpy(wl.v_true.astype(np.float32)).cuda()
+
+    def observe(acq_b):
+        return fctx.fwi_forward(grid, acq_b, v_true_t)
+
+    H, W = net_grid(grid.nz, grid.nx, 3)
+    net_cfg = DeblurConfig(3, 32, 0.0, H, W)
+    bands = tuple(float(b) for b in args.bands.split(","))
+    out = {}
+    lines = []
+
+    def log(s):
+        print(s, flush=True)
+        lines.append(s)
+
+    for method in (["plain", "net"] if args.method == "both" else [args.method]):
+        opts = FwiOptions(method=method, bands=bands, iters_per_band=args.iters, net=net_cfg,
+                          train_steps_first=args.train_first, train_steps=args.train)
+        run = FwiRun(fctx, grid, acq, wl.v0, opts, v_true=wl.v_true, log=log)
+        out[method] = run.run(observe)
+        if run.net is not None:
+            run.net.close()
+    if "plain" in out and "net" in out:
+        summary = time_to_error(out["plain"], out["net"])
+        summary["workload"] = wl.name
+        log(json.dumps({"summary": summary}))
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    main()

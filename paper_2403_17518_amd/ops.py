@@ -134,6 +134,17 @@ class FwiContext:
             C.c_void_p(d_syn.data_ptr()) if d_syn is not None else None))
         return grad, (float(phi.value) if want_misfit else None), d_syn
 
+    def fwi_misfit(self, grid, acq, v, d_obs) -> float:
+        """phi = 1/2 ||F(v) - d_obs||^2 (forward sweep and residual only)."""
+        v = self._model(v, "v", grid)
+        d_obs = self._data(d_obs, "d_obs", self._data_size(grid, acq))
+        phi = C.c_double(0.0)
+        g, gv = self._prep(grid, acq)
+        _check(self.lib, self.ctx, self.lib.fwi_misfit(self.ctx, C.byref(g), C.byref(gv.geom),
+                                                       C.c_void_p(v.data_ptr()), C.c_void_p(d_obs.data_ptr()),
+                                                       C.byref(phi)))
+        return float(phi.value)
+
     def born_demig(self, grid, acq, v0, dv) -> torch.Tensor:
         """dd = J dv."""
         v0 = self._model(v0, "v0", grid)
@@ -182,6 +193,10 @@ def fwi_forward(grid, acq, v):
 
 def fwi_gradient(grid, acq, v, d_obs, want_dsyn: bool = False):
     return _ctx_of(v).fwi_gradient(grid, acq, v, d_obs, True, want_dsyn)
+
+
+def fwi_misfit(grid, acq, v, d_obs):
+    return _ctx_of(v).fwi_misfit(grid, acq, v, d_obs)
 
 
 def born_demig(grid, acq, v0, dv):

@@ -71,8 +71,8 @@ def layered_600x200(nshots: int = 64, nt: int = 4000) -> Workload:
 
 
 def salt_1700x350(nshots: int = 300, dt: float = 1e-3,
-                  seed: int = models.SEED) -> Workload:
-    nz, nx, margin = 350, 1700, 50
+                  seed: int = models.SEED, nz: int = 350, nx: int = 1700,
+                  h: float = 10.0, margin: int = 50, name: str = "salt_1700x350") -> Workload:
     rng = np.random.Generator(np.random.PCG64(seed + 5))
     v = models.layered_faulted(nz, nx, vmin=1500.0, vmax=4500.0, seed=seed)
     v_true = models.add_salt(v, zc=0.55 * nz, xc=0.5 * nx, r0=0.18 * nz)
@@ -81,7 +81,7 @@ def salt_1700x350(nshots: int = 300, dt: float = 1e-3,
     rec_lists, wx0, wnx, nts = [], [], [], []
     nt_max = 0
     for s in range(nshots):
-        nrec = int(rng.integers(200, 1701))
+        nrec = int(rng.integers(max(2, (200 * nx) // 1700), nx + 1))
         lo = int(src_x[s]) - nrec // 2
         hi = lo + nrec
         lo, hi = max(lo, 0), min(hi, nx)
@@ -94,12 +94,19 @@ def salt_1700x350(nshots: int = 300, dt: float = 1e-3,
         n = int(round(rng.uniform(3.0, 5.0) / dt))
         nts.append(n)
         nt_max = max(nt_max, n)
-    grid = Grid(nz=nz, nx=nx, nb=20, h=10.0, dt=dt, nt_max=nt_max,
+    grid = Grid(nz=nz, nx=nx, nb=20, h=h, dt=dt, nt_max=nt_max,
                 v_ref=4700.0)
     acq = _surface_acq(src_x, None, ricker(15.0, dt, nt_max),
                        win_x0=np.asarray(wx0), win_nx=np.asarray(wnx),
                        nt=np.asarray(nts), rec_lists=rec_lists)
-    return Workload("salt_1700x350", grid, acq, v_true, v0, 15.0)
+    return Workload(name, grid, acq, v_true, v0, 15.0)
+
+
+def salt_848x176(nshots: int = 100) -> Workload:
+    """The salt workload at half resolution (20 m cells, same 17 km x 3.5 km
+    extent, 2 ms steps): receivers per shot 100-848, record length 3-5 s."""
+    return salt_1700x350(nshots=nshots, dt=2e-3, nz=176, nx=848, h=20.0,
+                         margin=25, name="salt_848x176")
 
 
 def ragged_small(seed: int = models.SEED, nz: int = 37, nx: int = 150,
