@@ -12,8 +12,9 @@ One iteration of the network method:
      fallback and the judge)
   5. line search along p and v <- clip(v + alpha p)
 The plain method skips steps 2-4 (p = g). Both use the same line search:
-a trial step with max|alpha p| = step_frac * v_max, a second at twice that,
-and the minimiser of the parabola through the three misfits.
+a trial step with max|alpha p| = step_frac * v_max (shrunk by 4 until it
+lowers the misfit, at most 4 times), a second at twice that, and the
+minimiser of the parabola through the three misfits.
 
 Multi-scale: the bands low-pass the data with a zero-phase 4th-order
 Butterworth filter (the same filter applied to the wavelet); for synthetic
@@ -56,6 +57,7 @@ class FwiOptions:
     net: DeblurConfig = field(default_factory=DeblurConfig)
     seed: int = 2403
     mute_rows: int = 0                    # zero the update in the top rows (both methods)
+    max_backtrack: int = 4                # trial-step reductions by 4 in the line search
 
 
 def lowpass(x: np.ndarray, dt: float, fmax: float, axis: int = -1) -> np.ndarray:
@@ -91,6 +93,7 @@ class FwiRun:
             np.ascontiguousarray(v_true, dtype=np.float32)).to(self.dev)
         self.e0 = None if v_true is None else float(torch.linalg.norm(self.v - self.v_true))
         self.v_max = opts.v_max if opts.v_max is not None else float(grid.v_ref)
+        self.step_scale = 1.0     # trial step relative to step_frac * v_max
         self.solves = 0           # paper convention
         self.passes = 0.0         # stencil passes actually run (one field, all shots)
         self.t0 = None
@@ -126,6 +129,7 @@ class FwiRun:
             d_obs = observe(acq_b)
             if self.net is not None and bi > 0:
                 self.net.reset(o.seed + bi)      # a new band starts from scratch
+            self.step_scale = 1.0
             for it in range(o.iters_per_band):
                 rec = self.iteration(acq_b, d_obs, bi, it, fmax)
                 self.history.append(rec)
@@ -172,10 +176,24 @@ class FwiRun:
         pmax = float(p.abs().max())
         if not pmax > 0:
             return self._record(band, it, fmax, phi, t, 0.0, fallback, train_loss)
-        a0 = o.step_frac * self.v_max / pmax
+        # trial step, shrunk by 4 while it does not reduce the misfit
+        # (at most `max_backtrack` times), then a second point at twice it
+        a0 = self.step_scale * o.step_frac * self.v_max / pmax
         f1 = self._misfit(acq, self._clip(self.v + a0 * p), d_obs)
-        f2 = self._misfit(acq, self._clip(self.v + 2 * a0 * p), d_obs)
-        alpha = parabola_step(phi, f1, f2, a0)
+        nb = 0
+        while f1 >= phi and nb < o.max_backtrack:
+            a0 *= 0.25
+            nb += 1
+            f1 = self._misfit(acq, self._clip(self.v + a0 * p), d_obs)
+        if f1 < phi:
+            f2 = self._misfit(acq, self._clip(self.v + 2 * a0 * p), d_obs)
+            alpha = parabola_step(phi, f1, f2, a0)
+            if alpha == 0.0:
+                alpha = a0
+        else:
+            alpha = 0.0
+        # the next trial starts from the scale that worked
+        self.step_scale = min(1.0, self.step_scale * (0.25 ** nb) * (2.0 if nb == 0 else 1.0))
         self.v = self._clip(self.v + alpha * p)
         _sync()
         t["line_search"] = time.perf_counter() - ta
