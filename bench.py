@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--cpu-shots", type=int, default=16)
     ap.add_argument("--cpu-nt", type=int, default=1500)
     ap.add_argument("--mem-budget-gb", type=float, default=0.0)
+    ap.add_argument("--tiling", default="",
+                    help="force the forward/adjoint tiling 'cols,rows,levels[,prefetch]' (default: autotuned)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
     return ap.parse_args()
@@ -111,6 +113,10 @@ def main():
     ctx = ops.FwiContext(0)
     if args.mem_budget_gb > 0:
         ctx.set_mem_budget(int(args.mem_budget_gb * 2**30))
+    if args.tiling:
+        t = [int(x) for x in args.tiling.split(",")] + [0]
+        ctx.set_tiling(0, t[0], t[1], t[2], t[3])
+        ctx.set_tiling(1, t[0], t[1], t[2], t[3])
     v_true = torch.from_numpy(wl.v_true.astype(np.float32)).to(dev)
     v0 = torch.from_numpy(wl.v0.astype(np.float32)).to(dev)
     d_obs = ctx.fwi_forward(grid, acq, v_true)        # synthetic observed data
@@ -192,8 +198,9 @@ def main():
             "executed_cell_updates_per_step": acc["cell_updates"] / args.steps,
             "useful_cell_updates_per_step": useful,
             "wall_s": wall,
-            "tiles_cols_rows": {k: [st_last["tile_cw"][i], st_last["tile_rows"][i]]
-                                for i, k in enumerate(("fwd", "adj", "born"))},
+            "tiles_cols_rows_levels_prefetch": {k: [st_last["tile_cw"][i], st_last["tile_rows"][i],
+                                                    st_last["tile_levels"][i], st_last["tile_prefetch"][i]]
+                                                for i, k in enumerate(("fwd", "adj", "born"))},
         },
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,

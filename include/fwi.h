@@ -112,8 +112,10 @@ typedef struct {
     int64_t n_fwd, n_adj, n_born;
     double bytes_fwd, bytes_adj, bytes_born; /* algorithmic bytes moved */
     /* tiling used by the forward, adjoint and Born kernels: columns per
-       lane (strip width 64 * cols) and rows streamed per wave */
-    int32_t tile_cw[3], tile_rows[3];
+       lane (strip width 64 * cols), rows streamed per wave and time levels
+       advanced per launch */
+    int32_t tile_cw[3], tile_rows[3], tile_levels[3];
+    int32_t tile_prefetch[3]; /* rows prefetched ahead (one-level kernels) */
 } fwi_stats;
 
 /* Create a context on HIP device `device`, enqueueing on `hip_stream`
@@ -133,9 +135,13 @@ int fwi_ctx_set_mem_budget(fwi_ctx *ctx, int64_t bytes);
  * back-to-back launches; adds a stream sync at the end of each call. */
 int fwi_ctx_set_profiling(fwi_ctx *ctx, int enable);
 /* Tiling of the step kernels. kernel: 0 forward, 1 adjoint, 2 Born, -1 all;
- * cols_per_lane 1 or 2 and rows_per_wave >= 1 force a tiling; (0, 0)
- * returns the kernel to the autotuner. */
-int fwi_ctx_set_tiling(fwi_ctx *ctx, int kernel, int cols_per_lane, int rows_per_wave);
+ * cols_per_lane 1 or 2, rows_per_wave >= 1, levels_per_launch 1 or 2 (the
+ * Born kernel always advances one level) and prefetch_rows 1 or 2 (rows of
+ * loads issued ahead by one-level kernels; 0 = 2) force a tiling; all zero
+ * returns the kernel to the autotuner. Results do not depend on the tiling:
+ * every variant computes each cell with the same arithmetic. */
+int fwi_ctx_set_tiling(fwi_ctx *ctx, int kernel, int cols_per_lane, int rows_per_wave,
+                       int levels_per_launch, int prefetch_rows);
 /* 1 (default): pick each kernel's tiling by timing candidates once per
  * geometry; 0: use a fixed default tiling. */
 int fwi_ctx_set_autotune(fwi_ctx *ctx, int enable);

@@ -45,7 +45,8 @@ class fwi_stats(C.Structure):
                 ("n_fwd", C.c_int64), ("n_adj", C.c_int64), ("n_born", C.c_int64),
                 ("bytes_fwd", C.c_double), ("bytes_adj", C.c_double),
                 ("bytes_born", C.c_double),
-                ("tile_cw", C.c_int32 * 3), ("tile_rows", C.c_int32 * 3)]
+                ("tile_cw", C.c_int32 * 3), ("tile_rows", C.c_int32 * 3),
+                ("tile_levels", C.c_int32 * 3), ("tile_prefetch", C.c_int32 * 3)]
 
     def as_dict(self) -> dict:
         out = {}
@@ -69,7 +70,7 @@ SIGNATURES = {
     "fwi_ctx_set_mem_budget": (C.c_int, [_P, C.c_int64]),
     "fwi_ctx_set_profiling": (C.c_int, [_P, C.c_int]),
     "fwi_ctx_get_stats": (C.c_int, [_P, C.POINTER(fwi_stats)]),
-    "fwi_ctx_set_tiling": (C.c_int, [_P, C.c_int, C.c_int, C.c_int]),
+    "fwi_ctx_set_tiling": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "fwi_ctx_set_autotune": (C.c_int, [_P, C.c_int]),
     "fwi_ctx_trim": (C.c_int, [_P]),
     "fwi_last_error": (C.c_char_p, [_P]),

@@ -24,7 +24,9 @@ constexpr double kCflLimit = 0.55;     // 2D 8th-order leapfrog limit is 0.5546
 constexpr double kDefaultBudgetFrac = 0.7;  // of device memory, for D^n history + checkpoints
 constexpr int64_t kFreeMargin = int64_t(4) << 30;  // left free when sizing the history
 constexpr int kDefaultCw = 2;          // tiling used when autotuning is off
-constexpr int kDefaultRows = 16;
+constexpr int kDefaultRows = 32;
+constexpr int kDefaultTb = 1;
+constexpr int kDefaultPd = 2;
 
 // 8th-order central second-derivative weights (Fornberg 1988).
 constexpr double kC8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
@@ -71,7 +73,8 @@ struct Plan {
 
 // Wave table of one tiling: strips of 64*cw columns, runs of `rows` rows.
 struct Tiling {
-    int cw = 0, rows = 0;
+    int cw = 0, rows = 0, tb = 0;  // columns per lane, rows per wave, time levels per launch
+    int pd = 1;                    // one level per launch: rows prefetched ahead
     std::vector<WaveDesc> waves;
     std::vector<RecRow> rrows;
     std::vector<int32_t> rmap;
@@ -97,7 +100,7 @@ struct fwi_ctx {
     // one tiling per kernel class (forward, adjoint, Born), picked by the
     // autotuner or forced by fwi_ctx_set_tiling
     Tiling tile[3];
-    int force_cw[3] = {0, 0, 0}, force_rows[3] = {0, 0, 0};
+    int force_cw[3] = {0, 0, 0}, force_rows[3] = {0, 0, 0}, force_tb[3] = {0, 0, 0}, force_pd[3] = {0, 0, 0};
     bool autotune = true;
     // scratch
     DevBuf fields, samples, image, dhist, ckpt, partials, misfit, check;
@@ -279,7 +282,7 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
         const int s = p.order[k];
         ShotDesc &d = p.shots[k];
         d.NX = wnx[s] + 2 * p.nb;
-        d.P = ((d.NX + kHalo + 31) / 32) * 32;
+        d.P = ((d.NX + kZeroRows + 31) / 32) * 32;
         d.f_off = foff + int64_t(kRowsAbove) * d.P;
         d.g_off = goff;
         foff += int64_t(p.NZ + kRowsExtra) * d.P;
@@ -327,31 +330,39 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
     // context and make sure the copies finished before the plan can change
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->plan = std::move(p);
-    for (Tiling &t : c->tile) t.cw = t.rows = 0;  // stale for the new plan
+    for (Tiling &t : c->tile) t.cw = t.rows = t.tb = 0;  // stale for the new plan
     c->plan_valid = true;
     return FWI_OK;
 }
 
-void build_tiling(const Plan &p, int cw, int rows_target, Tiling &t)
+// Wave table of one tiling. One level per launch: a wave owns a strip of
+// 64*cw columns; two levels per launch: a strip of 64*cw - 8 columns whose
+// lanes also hold 4 columns on each side, and the receiver maps cover the
+// lanes' columns and 4 rows above and below the owned rows (the
+// intermediate level is computed there too).
+void build_tiling(const Plan &p, int cw, int rows_target, int tb, int pd, Tiling &t)
 {
     t.cw = cw;
     t.rows = rows_target;
+    t.tb = tb;
+    t.pd = pd;
     t.waves.clear();
     t.rrows.clear();
     t.rmap.clear();
     t.prefix.assign(p.S + 1, 0);
     const int SW = kLanes * cw;
+    const int reach = tb == 2 ? kHalo : 0;
+    const int SWo = SW - 2 * reach;
     const int nseg = std::max(1, (p.NZ + rows_target - 1) / rows_target);
     const int rows = (p.NZ + nseg - 1) / nseg;
     for (int k = 0; k < p.S; ++k) {
         const auto &cells = p.slot_cells[k];
-        const int nstrips = (p.shots[k].NX + SW - 1) / SW;
+        const int nstrips = (p.shots[k].NX + SWo - 1) / SWo;
         for (int st = 0; st < nstrips; ++st) {
-            const int col0 = st * SW;
-            std::vector<std::pair<std::pair<int, int>, int>> sc;
+            const int col0 = st * SWo, lane0 = col0 - reach;
+            std::vector<std::pair<std::pair<int, int>, int>> sc;  // sorted by row, then column
             for (const auto &cq : cells)
-                if (cq.first.second >= col0 && cq.first.second < col0 + SW) sc.push_back(cq);
-            size_t pos = 0;
+                if (cq.first.second >= lane0 && cq.first.second < lane0 + SW) sc.push_back(cq);
             for (int z0 = 0; z0 < p.NZ; z0 += rows) {
                 WaveDesc w{};
                 w.shot = k;
@@ -359,12 +370,15 @@ void build_tiling(const Plan &p, int cw, int rows_target, Tiling &t)
                 w.z0 = z0;
                 w.z1 = std::min(p.NZ, z0 + rows);
                 w.rr0 = int(t.rrows.size());
-                while (pos < sc.size() && sc[pos].first.first < w.z1) {
+                const int rlo = w.z0 - reach, rhi = w.z1 + reach;
+                size_t pos = 0;
+                while (pos < sc.size() && sc[pos].first.first < rlo) ++pos;
+                while (pos < sc.size() && sc[pos].first.first < rhi) {
                     const int rowi = sc[pos].first.first;
                     RecRow rrw{rowi, int32_t(t.rmap.size())};
                     t.rmap.resize(t.rmap.size() + SW, -1);
                     while (pos < sc.size() && sc[pos].first.first == rowi) {
-                        t.rmap[rrw.map_off + (sc[pos].first.second - col0)] = sc[pos].second;
+                        t.rmap[rrw.map_off + (sc[pos].first.second - lane0)] = sc[pos].second;
                         ++pos;
                     }
                     t.rrows.push_back(rrw);
@@ -422,6 +436,7 @@ StepArgs base_args(fwi_ctx *c, const float *v, int cls)
     a.rrows = static_cast<const RecRow *>(t.d_rrows.p);
     a.rmap = static_cast<const int32_t *>(t.d_rmap.p);
     a.cw = t.cw;
+    a.pd = t.pd;
     a.v = v;
     a.wav = static_cast<const float *>(c->d_wav.p);
     a.nz = p.nz;
@@ -503,36 +518,76 @@ double step_updates(const Plan &p, int n)
     return u;
 }
 
-int fwd_step(fwi_ctx *c, StepArgs a, int flags, int n, float *F0, float *F1)
+// The two newest time levels of a sweep and two spare buffers. A one-level
+// launch overwrites `prev` in place; a two-level launch writes the spares.
+struct Fields {
+    float *prev, *cur, *s0, *s1;
+};
+
+double bytes_per_update(int flags)
+{
+    if (flags & F_IMAGE) return kBytesAdj;
+    return kBytesFwd + ((flags & F_EMIT) ? kBytesEmit : 0.0);
+}
+
+// One launch of the forward or adjoint step kernel advancing `levels` (1 or
+// 2) time levels; a.n / a.n2 and the per-level pointers are set by the
+// caller. `active_n` selects the shots that take part (record length >
+// active_n).
+int step_launch(fwi_ctx *c, StepArgs a, int cls, int flags, int levels, int active_n, Fields &f)
 {
     const Plan &p = c->plan;
-    a.n = n;
-    a.nwaves = c->tile[K_FWD].prefix[p.active_slots(n)];
-    a.cur = (n % 2 == 0) ? F0 : F1;
-    a.prev = (n % 2 == 0) ? F1 : F0;
-    HIPCHK(c, launch_step(flags, a, c->stream));
-    const double upd = step_updates(p, n);
+    const Tiling &t = c->tile[cls];
+    a.nwaves = t.prefix[p.active_slots(active_n)];
+    a.cur = f.cur;
+    a.prev = f.prev;
+    if (levels == 2) {
+        a.out1 = f.s0;
+        a.out2 = f.s1;
+        HIPCHK(c, launch_step2(flags, a, c->stream));
+        f = Fields{f.s0, f.s1, f.prev, f.cur};
+    } else {
+        HIPCHK(c, launch_step(flags, a, c->stream));
+        std::swap(f.prev, f.cur);
+    }
+    const double upd = levels * step_updates(p, active_n);
     c->stats.cell_updates += upd;
     c->stats.stencil_launches += 1;
-    c->stats.n_fwd += 1;
-    c->stats.bytes_fwd += upd * (kBytesFwd + ((flags & F_EMIT) ? kBytesEmit : 0.0));
+    if (cls == K_ADJ) {
+        c->stats.n_adj += 1;
+        c->stats.bytes_adj += upd * bytes_per_update(flags);
+    } else {
+        c->stats.n_fwd += 1;
+        c->stats.bytes_fwd += upd * bytes_per_update(flags);
+    }
     return FWI_OK;
 }
 
-int adj_step(fwi_ctx *c, StepArgs a, int n, float *A0, float *A1)
+// Forward steps lo .. hi-1 (pairs when the tiling runs two levels). D^n goes
+// to slot n - dlo of `dh` (when emit), samples to samp + n*Q (when sample).
+int forward_range(fwi_ctx *c, StepArgs a, int lo, int hi, bool sample, float *samp, bool emit, float *dh, int dlo,
+                  Fields &f)
 {
     const Plan &p = c->plan;
-    a.n = n;
-    a.nwaves = c->tile[K_ADJ].prefix[p.active_slots(n)];
-    // lambda^{n+1} lives in A[(n+1)%2], lambda^{n+2} (overwritten by lambda^n) in A[n%2]
-    a.cur = ((n + 1) % 2 == 0) ? A0 : A1;
-    a.prev = (n % 2 == 0) ? A0 : A1;
-    HIPCHK(c, launch_step(F_INJECT | F_IMAGE, a, c->stream));
-    const double upd = step_updates(p, n);
-    c->stats.cell_updates += upd;
-    c->stats.stencil_launches += 1;
-    c->stats.n_adj += 1;
-    c->stats.bytes_adj += upd * kBytesAdj;
+    const int64_t gf = p.img_floats;
+    const int flags = F_SRC | (sample ? F_SAMPLE : 0) | (emit ? F_EMIT : 0);
+    const bool two = c->tile[K_FWD].tb == 2;
+    int rc;
+    for (int n = lo; n < hi;) {
+        const int levels = (two && n + 1 < hi) ? 2 : 1;
+        a.n = n;
+        a.n2 = n + 1;
+        if (sample) {
+            a.samp = samp + size_t(n) * p.Q;
+            a.samp2 = samp + size_t(n + 1) * p.Q;
+        }
+        if (emit) {
+            a.dslot = dh + size_t(n - dlo) * gf;
+            a.dslot2 = dh + size_t(n + 1 - dlo) * gf;
+        }
+        if ((rc = step_launch(c, a, K_FWD, flags, levels, n, f))) return rc;
+        n += levels;
+    }
     return FWI_OK;
 }
 
@@ -590,7 +645,7 @@ int choose_segments(fwi_ctx *c, int *k_out, int *nseg_out)
 
 struct Sweep {
     int k = 0, nseg = 0;
-    float *F0, *F1, *A0, *A1, *Dh, *CK, *G;
+    float *F[4], *A[4], *Dh, *CK, *G;
 };
 
 // Forward sweep for an adjoint: checkpoints of (u^{n-1}, u^n) at the start
@@ -605,40 +660,34 @@ int forward_for_adjoint(fwi_ctx *c, const float *v, bool sample, Sweep &w)
     c->stats.ckpt_every = nseg > 1 ? k : 0;
     c->stats.n_segments = nseg;
     const int64_t ff = p.field_floats, gf = p.img_floats;
-    if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
+    if ((rc = ensure(c, c->fields, size_t(8 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
         (rc = ensure(c, c->dhist, size_t(k) * gf * 4)) ||
         (rc = ensure(c, c->ckpt, size_t(std::max(0, nseg - 1)) * 2 * ff * 4)) ||
         (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)))
         return rc;
     float *F = static_cast<float *>(c->fields.p);
-    w.F0 = F;
-    w.F1 = F + ff;
-    w.A0 = F + 2 * ff;
-    w.A1 = F + 3 * ff;
+    for (int i = 0; i < 4; ++i) {
+        w.F[i] = F + i * ff;
+        w.A[i] = F + (4 + i) * ff;
+    }
     w.Dh = static_cast<float *>(c->dhist.p);
     w.CK = static_cast<float *>(c->ckpt.p);
     w.G = static_cast<float *>(c->image.p);
     float *samp = static_cast<float *>(c->samples.p);
     hipStream_t st = c->stream;
-    if ((rc = other(c, launch_fill(w.F0, 2 * ff, 0.f, st), "fill"))) return rc;
+    if ((rc = other(c, launch_fill(w.F[0], 4 * ff, 0.f, st), "fill"))) return rc;
     StepArgs a = base_args(c, v, K_FWD);
-    const int last0 = (nseg - 1) * k;
+    Fields f{w.F[0], w.F[1], w.F[2], w.F[3]};
     if ((rc = ev_begin(c, K_FWD))) return rc;
-    for (int n = 0; n < p.nt_max; ++n) {
-        if (n % k == 0 && n / k < nseg - 1) {
-            float *ckp = w.CK + size_t(n / k) * 2 * ff;
-            HIPCHK(c, hipMemcpyAsync(ckp, w.F0, size_t(2 * ff) * 4, hipMemcpyDeviceToDevice, st));
+    for (int sgi = 0; sgi < nseg; ++sgi) {
+        const int lo = sgi * k, hi = std::min(p.nt_max, lo + k);
+        const bool last = sgi == nseg - 1;
+        if (!last) {
+            float *ckp = w.CK + size_t(sgi) * 2 * ff;
+            HIPCHK(c, hipMemcpyAsync(ckp, f.prev, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipMemcpyAsync(ckp + ff, f.cur, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
         }
-        int fl = F_SRC;
-        if (sample) {
-            fl |= F_SAMPLE;
-            a.samp = samp + size_t(n) * p.Q;
-        }
-        if (n >= last0) {
-            fl |= F_EMIT;
-            a.dslot = w.Dh + size_t(n - last0) * gf;
-        }
-        if ((rc = fwd_step(c, a, fl, n, w.F0, w.F1))) return rc;
+        if ((rc = forward_range(c, a, lo, hi, sample, samp, last, w.Dh, lo, f))) return rc;
     }
     return ev_end(c);
 }
@@ -655,45 +704,56 @@ int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
     hipStream_t st = c->stream;
     float *inj = static_cast<float *>(c->samples.p);
     int rc;
-    if ((rc = other(c, launch_fill(w.A0, 2 * ff, 0.f, st), "fill"))) return rc;
+    if ((rc = other(c, launch_fill(w.A[0], 4 * ff, 0.f, st), "fill"))) return rc;
     if ((rc = other(c, launch_fill(w.G, gf, 0.f, st), "fill"))) return rc;
     StepArgs af = base_args(c, v, K_FWD);
     StepArgs a = base_args(c, v, K_ADJ);
     a.G = w.G;
+    const bool two = c->tile[K_ADJ].tb == 2;
+    // lambda^{n+2} (prev) and lambda^{n+1} (cur), both zero at the start
+    Fields fa{w.A[0], w.A[1], w.A[2], w.A[3]};
     for (int sgi = nseg - 1; sgi >= 0; --sgi) {
         const int lo = sgi * k, hi = std::min(p.nt_max, lo + k);
         if (sgi != nseg - 1) {
-            HIPCHK(c, hipMemcpyAsync(w.F0, w.CK + size_t(sgi) * 2 * ff, size_t(2 * ff) * 4,
-                                     hipMemcpyDeviceToDevice, st));
+            const float *ckp = w.CK + size_t(sgi) * 2 * ff;
+            HIPCHK(c, hipMemcpyAsync(w.F[0], ckp, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipMemcpyAsync(w.F[1], ckp + ff, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
+            Fields f{w.F[0], w.F[1], w.F[2], w.F[3]};
             if ((rc = ev_begin(c, K_FWD))) return rc;
-            for (int n = lo; n < hi; ++n) {
-                af.dslot = w.Dh + size_t(n - lo) * gf;
-                if ((rc = fwd_step(c, af, F_SRC | F_EMIT, n, w.F0, w.F1))) return rc;
-            }
+            if ((rc = forward_range(c, af, lo, hi, false, nullptr, true, w.Dh, lo, f))) return rc;
             if ((rc = ev_end(c))) return rc;
         }
         if ((rc = ev_begin(c, K_ADJ))) return rc;
-        for (int n = hi - 1; n >= lo; --n) {
+        for (int n = hi - 1; n >= lo;) {
+            const int levels = (two && n - 1 >= lo) ? 2 : 1;
+            a.n = n;
+            a.n2 = n - 1;
             a.dslot = w.Dh + size_t(n - lo) * gf;
             a.inj = inj + size_t(n) * p.Q;
-            if ((rc = adj_step(c, a, n, w.A0, w.A1))) return rc;
+            if (levels == 2) {
+                a.dslot2 = w.Dh + size_t(n - 1 - lo) * gf;
+                a.inj2 = inj + size_t(n - 1) * p.Q;
+            }
+            // a pair takes the shots alive at its second (earlier) level
+            if ((rc = step_launch(c, a, K_ADJ, F_INJECT | F_IMAGE, levels, n - levels + 1, fa))) return rc;
+            n -= levels;
         }
         if ((rc = ev_end(c))) return rc;
     }
-    FinalArgs fa{};
-    fa.shots = static_cast<const ShotDesc *>(c->d_shots.p);
-    fa.nshots = p.S;
-    fa.G = w.G;
-    fa.v = v;
-    fa.nz = p.nz;
-    fa.nx = p.nx;
-    fa.nb = p.nb;
-    fa.NZ = p.NZ;
-    fa.dt2 = float(double(p.dt) * p.dt);
-    fa.img = img;
+    FinalArgs fin{};
+    fin.shots = static_cast<const ShotDesc *>(c->d_shots.p);
+    fin.nshots = p.S;
+    fin.G = w.G;
+    fin.v = v;
+    fin.nz = p.nz;
+    fin.nx = p.nx;
+    fin.nb = p.nb;
+    fin.NZ = p.NZ;
+    fin.dt2 = float(double(p.dt) * p.dt);
+    fin.img = img;
     int max_nx = 0;
     for (const ShotDesc &d : p.shots) max_nx = std::max(max_nx, d.NX);
-    return other(c, launch_finalize(fa, max_nx, st), "finalize");
+    return other(c, launch_finalize(fin, max_nx, st), "finalize");
 }
 
 TraceArgs trace_args(fwi_ctx *c)
@@ -716,41 +776,51 @@ TraceArgs trace_args(fwi_ctx *c)
 // plan cache keeps the result) on zeroed scratch fields; timings do not
 // depend on the field values.
 
-const int kTuneCw[] = {1, 2};
-const int kTuneRows[] = {8, 12, 16, 24, 32, 48};
+struct Candidate {
+    int cw, rows, tb, pd;
+};
+// one level per launch: short row runs keep many waves in flight, a deeper
+// prefetch more bytes per wave; two levels per launch recompute 4 rows above
+// and below each run, so runs are longer
+const Candidate kTune[] = {
+    {1, 8, 1, 1},  {1, 16, 1, 1}, {1, 24, 1, 1}, {1, 32, 1, 1}, {1, 48, 1, 1}, {2, 8, 1, 1},  {2, 16, 1, 1},
+    {2, 24, 1, 1}, {2, 32, 1, 1}, {1, 8, 1, 2},  {1, 16, 1, 2}, {1, 24, 1, 2}, {1, 32, 1, 2}, {1, 48, 1, 2},
+    {2, 8, 1, 2},  {2, 16, 1, 2}, {2, 24, 1, 2}, {2, 32, 1, 2}, {1, 24, 2, 1}, {1, 48, 2, 1}, {2, 24, 2, 1},
+    {2, 48, 2, 1}};
 
+// time of one time level of kernel class `cls` with tiling t (ms per level)
 int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_out)
 {
     const Plan &p = c->plan;
-    const int64_t ff = p.field_floats;
+    const int64_t ff = p.field_floats, gf = p.img_floats;
     float *F = static_cast<float *>(c->fields.p);
-    StepArgs a{};
-    a.shots = static_cast<const ShotDesc *>(c->d_shots.p);
-    a.waves = static_cast<const WaveDesc *>(t.d_waves.p);
-    a.rrows = static_cast<const RecRow *>(t.d_rrows.p);
-    a.rmap = static_cast<const int32_t *>(t.d_rmap.p);
-    a.cw = t.cw;
     StepArgs b = base_args(c, v, cls);
-    b.shots = a.shots;
-    b.waves = a.waves;
-    b.rrows = a.rrows;
-    b.rmap = a.rmap;
-    b.cw = a.cw;
-    b.n = 0;
-    b.nwaves = t.prefix[p.active_slots(0)];
+    b.waves = static_cast<const WaveDesc *>(t.d_waves.p);
+    b.rrows = static_cast<const RecRow *>(t.d_rrows.p);
+    b.rmap = static_cast<const int32_t *>(t.d_rmap.p);
+    b.cw = t.cw;
+    b.pd = t.pd;
+    b.n = 1;
+    b.n2 = cls == K_ADJ ? 0 : 2;
+    b.nwaves = t.prefix[p.active_slots(std::min(b.n, b.n2))];
     b.cur = F;
     b.prev = F + ff;
+    b.out1 = F + 2 * ff;
+    b.out2 = F + 3 * ff;
     b.cur2 = F + 2 * ff;
     b.prev2 = F + 3 * ff;
     b.dv = v;
     b.dslot = static_cast<float *>(c->dhist.p);
+    b.dslot2 = b.dslot + gf;
     b.G = static_cast<float *>(c->image.p);
     b.samp = static_cast<float *>(c->samples.p);
+    b.samp2 = b.samp + p.Q;
     b.inj = b.samp;
+    b.inj2 = b.samp2;
+    const int flags = cls == K_ADJ ? (F_INJECT | F_IMAGE) : (F_SRC | F_SAMPLE);
     auto launch = [&]() -> hipError_t {
-        if (cls == K_FWD) return launch_step(F_SRC | F_SAMPLE, b, c->stream);
-        if (cls == K_ADJ) return launch_step(F_INJECT | F_IMAGE, b, c->stream);
-        return launch_born_step(b, c->stream);
+        if (cls == K_BORN) return launch_born_step(b, c->stream);
+        return t.tb == 2 ? launch_step2(flags, b, c->stream) : launch_step(flags, b, c->stream);
     };
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
@@ -765,7 +835,7 @@ int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_o
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return set_err(c, FWI_EHIP, "autotune launch: %s", hipGetErrorString(err));
-    *ms_out = ms;
+    *ms_out = ms / float(t.tb);
     return FWI_OK;
 }
 
@@ -775,11 +845,14 @@ int ensure_tilings(fwi_ctx *c, const float *v)
     bool need_tune = false;
     for (int k = 0; k < 3; ++k) {
         Tiling &t = c->tile[k];
-        const int want_cw = c->force_cw[k] ? c->force_cw[k] : (c->autotune ? 0 : kDefaultCw);
-        const int want_rows = c->force_rows[k] ? c->force_rows[k] : (c->autotune ? 0 : kDefaultRows);
-        if (want_cw && want_rows) {
-            if (t.cw == want_cw && t.rows == want_rows) continue;
-            build_tiling(p, want_cw, want_rows, t);
+        const bool forced = c->force_cw[k] != 0;
+        const int want_cw = forced ? c->force_cw[k] : (c->autotune ? 0 : kDefaultCw);
+        const int want_rows = forced ? c->force_rows[k] : (c->autotune ? 0 : kDefaultRows);
+        const int want_tb = k == K_BORN ? 1 : (forced ? c->force_tb[k] : (c->autotune ? 0 : kDefaultTb));
+        const int want_pd = forced ? c->force_pd[k] : kDefaultPd;
+        if (want_cw && want_rows && want_tb) {
+            if (t.cw == want_cw && t.rows == want_rows && t.tb == want_tb && t.pd == want_pd) continue;
+            build_tiling(p, want_cw, want_rows, want_tb, want_pd, t);
             int rc = upload_tiling(c, t);
             if (rc) return rc;
         } else if (t.cw == 0) {
@@ -787,47 +860,46 @@ int ensure_tilings(fwi_ctx *c, const float *v)
         }
     }
     if (!need_tune) return FWI_OK;
-    // scratch for the trial launches
+    // scratch for the trial launches (two levels: four fields, two D slots,
+    // two sample rows)
     const int64_t ff = p.field_floats, gf = p.img_floats;
+    const int64_t nq = 2 * std::max(p.Q, 1);
     int rc;
     if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
-        (rc = ensure(c, c->dhist, size_t(gf) * 4)) || (rc = ensure(c, c->samples, size_t(std::max(p.Q, 1)) * 4)))
+        (rc = ensure(c, c->dhist, size_t(2 * gf) * 4)) || (rc = ensure(c, c->samples, size_t(nq) * 4)))
         return rc;
     if ((rc = other(c, launch_fill(static_cast<float *>(c->fields.p), 4 * ff, 0.f, c->stream), "fill")) ||
         (rc = other(c, launch_fill(static_cast<float *>(c->image.p), gf, 0.f, c->stream), "fill")) ||
-        (rc = other(c, launch_fill(static_cast<float *>(c->dhist.p), gf, 0.f, c->stream), "fill")) ||
-        (rc = other(c, launch_fill(static_cast<float *>(c->samples.p), std::max(p.Q, 1), 0.f, c->stream), "fill")))
+        (rc = other(c, launch_fill(static_cast<float *>(c->dhist.p), 2 * gf, 0.f, c->stream), "fill")) ||
+        (rc = other(c, launch_fill(static_cast<float *>(c->samples.p), nq, 0.f, c->stream), "fill")))
         return rc;
     float best[3] = {1e30f, 1e30f, 1e30f};
-    int bcw[3] = {kDefaultCw, kDefaultCw, kDefaultCw}, brows[3] = {kDefaultRows, kDefaultRows, kDefaultRows};
+    Candidate bc[3] = {{kDefaultCw, kDefaultRows, kDefaultTb, kDefaultPd},
+                       {kDefaultCw, kDefaultRows, kDefaultTb, kDefaultPd},
+                       {kDefaultCw, kDefaultRows, 1, kDefaultPd}};
     Tiling trial;
-    for (int cw : kTuneCw)
-        for (int rows : kTuneRows) {
-            build_tiling(p, cw, rows, trial);
-            if ((rc = upload_tiling(c, trial))) return rc;
-            for (int k = 0; k < 3; ++k) {
-                if (c->tile[k].cw != 0) continue;
-                float ms = 0.f;
-                if ((rc = time_class(c, k, trial, v, &ms))) {
-                    release(trial.d_waves);
-                    release(trial.d_rrows);
-                    release(trial.d_rmap);
-                    return rc;
-                }
-                if (ms < best[k]) {
-                    best[k] = ms;
-                    bcw[k] = cw;
-                    brows[k] = rows;
-                }
+    for (const Candidate &cand : kTune) {
+        build_tiling(p, cand.cw, cand.rows, cand.tb, cand.pd, trial);
+        if ((rc = upload_tiling(c, trial))) break;
+        for (int k = 0; k < 3; ++k) {
+            if (c->tile[k].cw != 0 || (k == K_BORN && (cand.tb != 1 || cand.pd != 1))) continue;
+            float ms = 0.f;
+            if ((rc = time_class(c, k, trial, v, &ms))) break;
+            if (ms < best[k]) {
+                best[k] = ms;
+                bc[k] = cand;
             }
         }
+        if (rc) break;
+    }
     release(trial.d_waves);
     release(trial.d_rrows);
     release(trial.d_rmap);
+    if (rc) return rc;
     for (int k = 0; k < 3; ++k) {
         Tiling &t = c->tile[k];
         if (t.cw != 0) continue;
-        build_tiling(p, bcw[k], brows[k], t);
+        build_tiling(p, bc[k].cw, bc[k].rows, bc[k].tb, bc[k].pd, t);
         if ((rc = upload_tiling(c, t))) return rc;
     }
     return FWI_OK;
@@ -853,6 +925,8 @@ int prepare(fwi_ctx *c, const float *v)
     for (int k = 0; k < 3; ++k) {
         c->stats.tile_cw[k] = c->tile[k].cw;
         c->stats.tile_rows[k] = c->tile[k].rows;
+        c->stats.tile_levels[k] = c->tile[k].tb;
+        c->stats.tile_prefetch[k] = c->tile[k].pd;
     }
     return FWI_OK;
 }
@@ -862,18 +936,16 @@ int forward_sweep_sampled(fwi_ctx *c, const float *v)
     const Plan &p = c->plan;
     const int64_t ff = p.field_floats;
     int rc;
-    if ((rc = ensure(c, c->fields, size_t(2 * ff) * 4)) ||
+    if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) ||
         (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)))
         return rc;
-    float *F0 = static_cast<float *>(c->fields.p), *F1 = F0 + ff;
+    float *F = static_cast<float *>(c->fields.p);
     float *samp = static_cast<float *>(c->samples.p);
-    if ((rc = other(c, launch_fill(F0, 2 * ff, 0.f, c->stream), "fill"))) return rc;
+    if ((rc = other(c, launch_fill(F, 4 * ff, 0.f, c->stream), "fill"))) return rc;
     StepArgs a = base_args(c, v, K_FWD);
+    Fields f{F, F + ff, F + 2 * ff, F + 3 * ff};
     if ((rc = ev_begin(c, K_FWD))) return rc;
-    for (int n = 0; n < p.nt_max; ++n) {
-        a.samp = samp + size_t(n) * p.Q;
-        if ((rc = fwd_step(c, a, F_SRC | F_SAMPLE, n, F0, F1))) return rc;
-    }
+    if ((rc = forward_range(c, a, 0, p.nt_max, true, samp, false, nullptr, 0, f))) return rc;
     return ev_end(c);
 }
 
@@ -955,17 +1027,24 @@ int fwi_ctx_set_profiling(fwi_ctx *c, int enable)
     return FWI_OK;
 }
 
-int fwi_ctx_set_tiling(fwi_ctx *c, int kernel, int cols_per_lane, int rows_per_wave)
+int fwi_ctx_set_tiling(fwi_ctx *c, int kernel, int cols_per_lane, int rows_per_wave, int levels_per_launch,
+                       int prefetch_rows)
 {
     if (!c || kernel < -1 || kernel > 2) return FWI_EINVAL;
-    if (!((cols_per_lane == 0 && rows_per_wave == 0) ||
-          ((cols_per_lane == 1 || cols_per_lane == 2) && rows_per_wave >= 1 && rows_per_wave <= 4096)))
+    const bool reset = cols_per_lane == 0 && rows_per_wave == 0 && levels_per_launch == 0;
+    if (!reset && !((cols_per_lane == 1 || cols_per_lane == 2) && rows_per_wave >= 1 && rows_per_wave <= 4096 &&
+                    (levels_per_launch == 1 || levels_per_launch == 2) && prefetch_rows >= 0 &&
+                    prefetch_rows <= 2))
         return FWI_EINVAL;
+    if (kernel == 2 && levels_per_launch == 2) return FWI_EINVAL;  // Born runs one level per launch
     for (int k = 0; k < 3; ++k)
         if (kernel == -1 || kernel == k) {
             c->force_cw[k] = cols_per_lane;
             c->force_rows[k] = rows_per_wave;
-            c->tile[k].cw = c->tile[k].rows = 0;
+            c->force_tb[k] = k == 2 && !reset ? 1 : levels_per_launch;
+            // the Born kernel and the two-level kernel prefetch one row ahead
+            c->force_pd[k] = (k == 2 || levels_per_launch == 2) ? 1 : (prefetch_rows ? prefetch_rows : kDefaultPd);
+            c->tile[k].cw = c->tile[k].rows = c->tile[k].tb = 0;
         }
     return FWI_OK;
 }
@@ -975,7 +1054,7 @@ int fwi_ctx_set_autotune(fwi_ctx *c, int enable)
     if (!c) return FWI_EINVAL;
     c->autotune = enable != 0;
     for (int k = 0; k < 3; ++k)
-        if (!c->force_cw[k]) c->tile[k].cw = c->tile[k].rows = 0;
+        if (!c->force_cw[k]) c->tile[k].cw = c->tile[k].rows = c->tile[k].tb = 0;
     return FWI_OK;
 }
 

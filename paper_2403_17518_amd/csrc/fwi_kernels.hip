@@ -62,9 +62,9 @@ __device__ __forceinline__ void ld(const float *p, float (&o)[CW])
 
 // One time level of every active shot. Each lane owns CW adjacent columns of
 // a 64*CW-column strip and streams down the rows [z0, z1) of that strip; the
-// loads of row z+1 are issued before row z is computed so that two rows of
-// memory traffic are in flight per wave.
-template <int FL, int CW>
+// loads of rows z+1 .. z+PD are issued before row z is computed so that PD+1
+// rows of memory traffic are in flight per wave.
+template <int FL, int CW, int PD>
 __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs A)
 {
     constexpr int SW = kLanes * CW;          // strip width
@@ -113,23 +113,26 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
 #pragma unroll
     for (int r = 0; r < 8; ++r) ld<CW>(cu + (W.z0 - kHalo + r + kRowsAbove) * P + jl, q[r]);
 
-    // prefetched values of the row being computed
-    float nq[CW], npv[CW], nv[CW], nd[CW], ng[CW];
-    float4 nh = make_float4(0.f, 0.f, 0.f, 0.f);
-    auto prefetch = [&](int z) {
+    // prefetched loads of one row; PD rows are in flight ahead of the row
+    // being computed (a ring of PD statically indexed slots)
+    struct Pre {
+        float q[CW], pv[CW], v[CW], d[CW], g[CW];
+        float4 h;
+    };
+    auto prefetch = [&](int z, Pre &pre) {
         const int o = (z + kRowsAbove) * P + jl;
-        ld<CW>(cu + o + kHalo * P, nq);
-        ld<CW>(pv + o, npv);
-        if (lane < 2) nh = *reinterpret_cast<const float4 *>(cu + (z + kRowsAbove) * P + hcol);
+        ld<CW>(cu + o + kHalo * P, pre.q);
+        ld<CW>(pv + o, pre.pv);
+        pre.h = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lane < 2) pre.h = *reinterpret_cast<const float4 *>(cu + (z + kRowsAbove) * P + hcol);
         const int mrow = clampi(z - nb, 0, A.nz - 1) * A.nx;
 #pragma unroll
-        for (int k = 0; k < CW; ++k) nv[k] = vmod[mrow + jm[k]];
+        for (int k = 0; k < CW; ++k) pre.v[k] = vmod[mrow + jm[k]];
         if (FL & F_IMAGE) {
-            ld<CW>(db + z * P + jl, nd);
-            ld<CW>(gb + z * P + jl, ng);
+            ld<CW>(db + z * P + jl, pre.d);
+            ld<CW>(gb + z * P + jl, pre.g);
         }
     };
-    prefetch(W.z0);
 
     int rr = W.rr0;
     int rrow = -1;
@@ -137,25 +140,13 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     const float wsrc = (FL & F_SRC) ? A.wav[S.wav_off + A.n] * A.ih2 : 0.0f;
     const int src_k = S.src_j - j0;          // column of the source in this lane, if 0..CW-1
 
-    for (int z = W.z0; z < W.z1; ++z) {
-        float cpv[CW], cv[CW], cd[CW], cg[CW];
+    auto do_row = [&](int z, const Pre &c) {
 #pragma unroll
-        for (int k = 0; k < CW; ++k) {
-            q[8][k] = nq[k];
-            cpv[k] = npv[k];
-            cv[k] = nv[k];
-            if (FL & F_IMAGE) {
-                cd[k] = nd[k];
-                cg[k] = ng[k];
-            }
-        }
-        const float4 ch = nh;
-        if (z + 1 < W.z1) prefetch(z + 1);
-
+        for (int k = 0; k < CW; ++k) q[8][k] = c.q[k];
         // centre row into LDS, then the horizontal neighbours back out
         if constexpr (CW == 1) row[kHalo + lane] = q[4][0];
         else *reinterpret_cast<float2 *>(&row[kHalo + CW * lane]) = make_float2(q[4][0], q[4][1]);
-        if (lane < 2) *reinterpret_cast<float4 *>(&row[lane == 0 ? 0 : kHalo + SW]) = ch;
+        if (lane < 2) *reinterpret_cast<float4 *>(&row[lane == 0 ? 0 : kHalo + SW]) = c.h;
         wave_sync();
         float xr[CW + 2 * kHalo];
 #pragma unroll
@@ -188,15 +179,15 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
                 if (src_k == k && z == S.src_i) lap += wsrc;
             if (FL & F_INJECT)
                 if (qi[k] >= 0) lap += A.inj[qi[k]];
-            const float c = cv[k] * cv[k] * A.dt2;
+            const float cc = c.v[k] * c.v[k] * A.dt2;
             float a = ax[k], b = bx[k];
             if (ddz > 0) {
                 const float sh = A.hs * (dz2 + dx2[k]);
                 a = sponge_a(sh);
                 b = (1.0f - sh) * a;
             }
-            Dv[k] = c * lap;
-            out[k] = a * (2.0f * q[4][k] + Dv[k]) - b * cpv[k];
+            Dv[k] = cc * lap;
+            out[k] = a * (2.0f * q[4][k] + Dv[k]) - b * c.pv[k];
         }
         const int o = (z + kRowsAbove) * P + j0;
         const int og = z * P + j0;
@@ -205,7 +196,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
             if (valid[k]) {
                 pv[o + k] = out[k];
                 if (FL & F_EMIT) db[og + k] = Dv[k];
-                if (FL & F_IMAGE) gb[og + k] = cg[k] + out[k] * cd[k];
+                if (FL & F_IMAGE) gb[og + k] = __builtin_fmaf(out[k], c.d[k], c.g[k]);
                 if (FL & F_SAMPLE)
                     if (qi[k] >= 0) A.samp[qi[k]] = out[k];
             }
@@ -214,6 +205,287 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
         for (int r = 0; r < 8; ++r)
 #pragma unroll
             for (int k = 0; k < CW; ++k) q[r][k] = q[r + 1][k];
+    };
+
+    Pre pa, pb;
+    prefetch(W.z0, pa);
+    if (PD == 2 && W.z0 + 1 < W.z1) prefetch(W.z0 + 1, pb);
+    for (int z = W.z0; z < W.z1; z += PD) {
+        {
+            const Pre c = pa;
+            if (z + PD < W.z1) prefetch(z + PD, pa);
+            do_row(z, c);
+        }
+        if (PD == 2 && z + 1 < W.z1) {
+            const Pre c = pb;
+            if (z + 3 < W.z1) prefetch(z + 3, pb);
+            do_row(z + 1, c);
+        }
+    }
+}
+
+// Two time levels per launch (temporal blocking). With u^{n-1} (prev) and
+// u^n (cur) it produces u^{n+1} (out1) and u^{n+2} (out2); run backward in
+// time with the residual as source it produces lambda^n and lambda^{n-1}.
+// The lanes hold the owned columns plus 4 on each side; level 1 is computed
+// on all of them (and on 4 extra rows above and below the owned rows), so
+// level 2 can be computed on the owned cells without exchanging data with
+// other waves. Level 2 lags level 1 by 4 rows in the z stream. Level 1
+// outside the padded box is zero (the Dirichlet halo), as in the one-level
+// kernel. Per owned cell and two updates the kernel moves u^n, u^{n-1}, v
+// in and u^{n+1}, u^{n+2} out (plus D and G traffic for the adjoint), where
+// two one-level launches would move twice as much.
+template <int FL, int CW>
+__global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs A)
+{
+    constexpr int SW = kLanes * CW;           // lane columns
+    constexpr int RW = SW + 2 * kHalo;
+    __shared__ float lds[kWavesPerBlock][2][RW];
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int wl = threadIdx.x / kLanes;
+    const int wid = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wl;
+    if (wid >= A.nwaves) return;
+    float *row0 = lds[wl][0];                 // level n, row t (+ 4-column halos)
+    float *row1 = lds[wl][1];                 // level 1, row t-4
+    const WaveDesc W = A.waves[wid];
+    const ShotDesc S = A.shots[W.shot];
+    const int P = S.P, nb = A.nb, NZ = A.NZ;
+    const int cb = W.col0 - kHalo;            // column of lane 0
+    const int j0 = cb + CW * lane;
+    // loads are unconditional: negative columns read the previous row's zero
+    // tail, columns past the shot's width a zero column
+    const int jl = j0 < 0 ? j0 : min(j0, P - 2);
+    const int own_hi = min(W.col0 + SW - 2 * kHalo, S.NX);
+    const bool lvl1_ok = A.n < S.nt, lvl2_ok = A.n2 < S.nt;
+    const int64_t base = S.f_off - int64_t(kRowsAbove) * P;
+    const float *un = A.cur + base;
+    const float *um = A.prev + base;
+    float *o1 = A.out1 + base;
+    float *o2 = A.out2 + base;
+    float *gb = (FL & F_IMAGE) ? A.G + S.g_off : nullptr;
+    float *d1b = (FL & (F_IMAGE | F_EMIT)) ? A.dslot + S.g_off : nullptr;
+    float *d2b = (FL & (F_IMAGE | F_EMIT)) ? A.dslot2 + S.g_off : nullptr;
+
+    bool inbox[CW], own[CW];
+    int jm[CW];
+    float dx2[CW], ax[CW], bx[CW];
+#pragma unroll
+    for (int k = 0; k < CW; ++k) {
+        const int j = j0 + k;
+        inbox[k] = j >= 0 && j < S.NX;
+        own[k] = j >= W.col0 && j < own_hi;
+        jm[k] = S.x0 + clampi(j - nb, 0, S.wnx - 1);
+        const int ddx = max(max(nb - j, j - (S.NX - 1 - nb)), 0);
+        dx2[k] = float(ddx * ddx);
+        const float sh = A.hs * dx2[k];
+        ax[k] = sponge_a(sh);
+        bx[k] = (1.0f - sh) * ax[k];
+    }
+    const int hcol = lane == 0 ? cb - kHalo : min(cb + SW, P - kHalo);
+    if (lane < 2) *reinterpret_cast<float4 *>(&row1[lane == 0 ? 0 : kHalo + SW]) = make_float4(0.f, 0.f, 0.f, 0.f);
+
+    const int t0 = W.z0 - kHalo, t1 = W.z1 + kHalo;   // level-1 rows [t0, t1)
+    float qa[9][CW], qb[9][CW], cq[5][CW], gq[5][CW];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) ld<CW>(un + (t0 - kHalo + r + kRowsAbove) * P + jl, qa[r]);
+#pragma unroll
+    for (int r = 0; r < 9; ++r)
+#pragma unroll
+        for (int k = 0; k < CW; ++k) qb[r][k] = 0.f;
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            cq[r][k] = 0.f;
+            gq[r][k] = 0.f;
+        }
+
+    float nq[CW], npv[CW], nv[CW], nd1[CW], nd2[CW], ng[CW];
+    float4 nh = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto prefetch = [&](int t) {
+        const int o = (t + kRowsAbove) * P + jl;
+        ld<CW>(un + o + kHalo * P, nq);
+        ld<CW>(um + o, npv);
+        if (lane < 2) nh = *reinterpret_cast<const float4 *>(un + (t + kRowsAbove) * P + hcol);
+        const int mrow = clampi(t - nb, 0, A.nz - 1) * A.nx;
+#pragma unroll
+        for (int k = 0; k < CW; ++k) nv[k] = A.v[mrow + jm[k]];
+        if (FL & F_IMAGE) {
+            const int jc = min(max(jl, 0), P - CW);
+            if (t >= W.z0 && t < W.z1) {
+                ld<CW>(d1b + t * P + jc, nd1);
+                ld<CW>(gb + t * P + jc, ng);
+            }
+            const int r2 = t - kHalo;
+            if (r2 >= W.z0 && r2 < W.z1) ld<CW>(d2b + r2 * P + jc, nd2);
+        }
+    };
+    prefetch(t0);
+
+    int rr1 = W.rr0, rr2 = W.rr0;
+    int rrow1 = -1, rrow2 = -1;
+    if (FL & (F_SAMPLE | F_INJECT)) {
+        // skip receiver rows above the first level-1 row
+        while (rr1 < W.rr1 && A.rrows[rr1].row < t0) ++rr1;
+        rrow1 = rr1 < W.rr1 ? A.rrows[rr1].row : -1;
+        rr2 = rr1;
+        rrow2 = rrow1;
+    }
+    const float wsrc1 = (FL & F_SRC) ? A.wav[S.wav_off + A.n] * A.ih2 : 0.0f;
+    const float wsrc2 = (FL & F_SRC) && lvl2_ok ? A.wav[S.wav_off + A.n2] * A.ih2 : 0.0f;
+    const int src_k = S.src_j - j0;
+
+    for (int t = t0; t < t1; ++t) {
+        float cpv[CW], cv[CW], cd1[CW], cd2[CW], cg[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            qa[8][k] = nq[k];
+            cpv[k] = npv[k];
+            cv[k] = nv[k];
+            if (FL & F_IMAGE) {
+                cd1[k] = nd1[k];
+                cd2[k] = nd2[k];
+                cg[k] = ng[k];
+            }
+        }
+        const float4 ch = nh;
+        if (t + 1 < t1) prefetch(t + 1);
+
+        // ---- level 1 at row t ----------------------------------------------
+        if constexpr (CW == 1) row0[kHalo + lane] = qa[4][0];
+        else *reinterpret_cast<float2 *>(&row0[kHalo + CW * lane]) = make_float2(qa[4][0], qa[4][1]);
+        if (lane < 2) *reinterpret_cast<float4 *>(&row0[lane == 0 ? 0 : kHalo + SW]) = ch;
+        wave_sync();
+        float xr[CW + 2 * kHalo];
+#pragma unroll
+        for (int m = 0; m < CW + 2 * kHalo; ++m) xr[m] = row0[CW * lane + m];
+
+        int qi1[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) qi1[k] = -1;
+        if (FL & (F_SAMPLE | F_INJECT)) {
+            if (t == rrow1) {
+                const int mo = A.rrows[rr1].map_off + CW * lane;
+#pragma unroll
+                for (int k = 0; k < CW; ++k) qi1[k] = A.rmap[mo + k];
+                ++rr1;
+                rrow1 = rr1 < W.rr1 ? A.rrows[rr1].row : -1;
+            }
+        }
+        const bool row_in = t >= 0 && t < NZ;
+        const int ddz1 = max(max(nb - t, t - (NZ - 1 - nb)), 0);
+        const float dz1 = float(ddz1 * ddz1);
+        float v1[CW], D1[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            float lap = A.w0 * qa[4][k] +
+                        A.w1 * ((qa[3][k] + qa[5][k]) + (xr[k + 3] + xr[k + 5])) +
+                        A.w2 * ((qa[2][k] + qa[6][k]) + (xr[k + 2] + xr[k + 6])) +
+                        A.w3 * ((qa[1][k] + qa[7][k]) + (xr[k + 1] + xr[k + 7])) +
+                        A.w4 * ((qa[0][k] + qa[8][k]) + (xr[k] + xr[k + 8]));
+            if (FL & F_SRC)
+                if (src_k == k && t == S.src_i) lap += wsrc1;
+            if (FL & F_INJECT)
+                if (qi1[k] >= 0) lap += A.inj[qi1[k]];
+            const float c = cv[k] * cv[k] * A.dt2;
+            float a = ax[k], b = bx[k];
+            if (ddz1 > 0) {
+                const float sh = A.hs * (dz1 + dx2[k]);
+                a = sponge_a(sh);
+                b = (1.0f - sh) * a;
+            }
+            D1[k] = c * lap;
+            const float o = a * (2.0f * qa[4][k] + D1[k]) - b * cpv[k];
+            v1[k] = (row_in && inbox[k]) ? o : 0.0f;
+            qb[8][k] = v1[k];
+            cq[4][k] = c;
+        }
+        const bool own_row1 = t >= W.z0 && t < W.z1;
+        if (own_row1) {
+            const int o = (t + kRowsAbove) * P + j0;
+#pragma unroll
+            for (int k = 0; k < CW; ++k) {
+                if (own[k]) {
+                    o1[o + k] = v1[k];
+                    if (FL & F_EMIT) d1b[t * P + j0 + k] = D1[k];
+                    if (FL & F_SAMPLE)
+                        if (qi1[k] >= 0) A.samp[qi1[k]] = v1[k];
+                }
+                // G after level 1 (the same fused multiply-add as a one-level step)
+                if (FL & F_IMAGE) gq[4][k] = lvl1_ok ? __builtin_fmaf(v1[k], cd1[k], cg[k]) : cg[k];
+            }
+        }
+
+        // ---- level 2 at row t-4 -------------------------------------------
+        const int r2 = t - kHalo;
+        if constexpr (CW == 1) row1[kHalo + lane] = qb[4][0];
+        else *reinterpret_cast<float2 *>(&row1[kHalo + CW * lane]) = make_float2(qb[4][0], qb[4][1]);
+        wave_sync();
+        float yr[CW + 2 * kHalo];
+#pragma unroll
+        for (int m = 0; m < CW + 2 * kHalo; ++m) yr[m] = row1[CW * lane + m];
+        wave_sync();
+
+        int qi2[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) qi2[k] = -1;
+        if (FL & (F_SAMPLE | F_INJECT)) {
+            if (r2 == rrow2) {
+                const int mo = A.rrows[rr2].map_off + CW * lane;
+#pragma unroll
+                for (int k = 0; k < CW; ++k) qi2[k] = A.rmap[mo + k];
+                ++rr2;
+                rrow2 = rr2 < W.rr1 ? A.rrows[rr2].row : -1;
+            }
+        }
+        if (r2 >= W.z0) {   // r2 < z1 always holds
+            const int ddz2 = max(max(nb - r2, r2 - (NZ - 1 - nb)), 0);
+            const float dz2 = float(ddz2 * ddz2);
+            const int o = (r2 + kRowsAbove) * P + j0;
+#pragma unroll
+            for (int k = 0; k < CW; ++k) {
+                float lap = A.w0 * qb[4][k] +
+                            A.w1 * ((qb[3][k] + qb[5][k]) + (yr[k + 3] + yr[k + 5])) +
+                            A.w2 * ((qb[2][k] + qb[6][k]) + (yr[k + 2] + yr[k + 6])) +
+                            A.w3 * ((qb[1][k] + qb[7][k]) + (yr[k + 1] + yr[k + 7])) +
+                            A.w4 * ((qb[0][k] + qb[8][k]) + (yr[k] + yr[k + 8]));
+                if (FL & F_SRC)
+                    if (src_k == k && r2 == S.src_i) lap += wsrc2;
+                if (FL & F_INJECT)
+                    if (qi2[k] >= 0) lap += A.inj2[qi2[k]];
+                const float c = cq[0][k];
+                float a = ax[k], b = bx[k];
+                if (ddz2 > 0) {
+                    const float sh = A.hs * (dz2 + dx2[k]);
+                    a = sponge_a(sh);
+                    b = (1.0f - sh) * a;
+                }
+                const float D2 = c * lap;
+                const float v2 = a * (2.0f * qb[4][k] + D2) - b * qa[0][k];
+                if (own[k]) {
+                    o2[o + k] = v2;
+                    if (FL & F_EMIT)
+                        if (lvl2_ok) d2b[r2 * P + j0 + k] = D2;
+                    if (FL & F_SAMPLE)
+                        if (lvl2_ok && qi2[k] >= 0) A.samp2[qi2[k]] = v2;
+                    if (FL & F_IMAGE) gb[r2 * P + j0 + k] = __builtin_fmaf(v2, cd2[k], gq[0][k]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int k = 0; k < CW; ++k) {
+                qa[r][k] = qa[r + 1][k];
+                qb[r][k] = qb[r + 1][k];
+            }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int k = 0; k < CW; ++k) {
+                cq[r][k] = cq[r + 1][k];
+                gq[r][k] = gq[r + 1][k];
+            }
     }
 }
 
@@ -562,25 +834,25 @@ inline int blocks_for(int nwaves) { return (nwaves + kWavesPerBlock - 1) / kWave
 
 }  // namespace
 
-template <int CW>
+template <int CW, int PD>
 hipError_t launch_step_cw(int flags, const StepArgs &a, hipStream_t s)
 {
     const dim3 grid(blocks_for(a.nwaves)), block(kLanes * kWavesPerBlock);
     switch (flags) {
     case F_SRC | F_SAMPLE:
-        hipLaunchKernelGGL((k_step<F_SRC | F_SAMPLE, CW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SRC | F_SAMPLE, CW, PD>), grid, block, 0, s, a);
         break;
     case F_SRC:
-        hipLaunchKernelGGL((k_step<F_SRC, CW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SRC, CW, PD>), grid, block, 0, s, a);
         break;
     case F_SRC | F_SAMPLE | F_EMIT:
-        hipLaunchKernelGGL((k_step<F_SRC | F_SAMPLE | F_EMIT, CW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SRC | F_SAMPLE | F_EMIT, CW, PD>), grid, block, 0, s, a);
         break;
     case F_SRC | F_EMIT:
-        hipLaunchKernelGGL((k_step<F_SRC | F_EMIT, CW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SRC | F_EMIT, CW, PD>), grid, block, 0, s, a);
         break;
     case F_INJECT | F_IMAGE:
-        hipLaunchKernelGGL((k_step<F_INJECT | F_IMAGE, CW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_INJECT | F_IMAGE, CW, PD>), grid, block, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -591,7 +863,40 @@ hipError_t launch_step_cw(int flags, const StepArgs &a, hipStream_t s)
 hipError_t launch_step(int flags, const StepArgs &a, hipStream_t s)
 {
     if (a.nwaves <= 0) return hipSuccess;
-    return a.cw == 2 ? launch_step_cw<2>(flags, a, s) : launch_step_cw<1>(flags, a, s);
+    if (a.pd == 2) return a.cw == 2 ? launch_step_cw<2, 2>(flags, a, s) : launch_step_cw<1, 2>(flags, a, s);
+    return a.cw == 2 ? launch_step_cw<2, 1>(flags, a, s) : launch_step_cw<1, 1>(flags, a, s);
+}
+
+template <int CW>
+hipError_t launch_step2_cw(int flags, const StepArgs &a, hipStream_t s)
+{
+    const dim3 grid(blocks_for(a.nwaves)), block(kLanes * kWavesPerBlock);
+    switch (flags) {
+    case F_SRC | F_SAMPLE:
+        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE, CW>), grid, block, 0, s, a);
+        break;
+    case F_SRC:
+        hipLaunchKernelGGL((k_step2<F_SRC, CW>), grid, block, 0, s, a);
+        break;
+    case F_SRC | F_SAMPLE | F_EMIT:
+        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE | F_EMIT, CW>), grid, block, 0, s, a);
+        break;
+    case F_SRC | F_EMIT:
+        hipLaunchKernelGGL((k_step2<F_SRC | F_EMIT, CW>), grid, block, 0, s, a);
+        break;
+    case F_INJECT | F_IMAGE:
+        hipLaunchKernelGGL((k_step2<F_INJECT | F_IMAGE, CW>), grid, block, 0, s, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step2(int flags, const StepArgs &a, hipStream_t s)
+{
+    if (a.nwaves <= 0) return hipSuccess;
+    return a.cw == 2 ? launch_step2_cw<2>(flags, a, s) : launch_step2_cw<1>(flags, a, s);
 }
 
 hipError_t launch_born_step(const StepArgs &a, hipStream_t s)

@@ -13,13 +13,15 @@ namespace fwi {
 constexpr int kLanes = 64;          // wavefront width on CDNA
 constexpr int kHalo = 4;            // stencil radius (8th order)
 constexpr int kWavesPerBlock = 4;   // waves per workgroup of the step kernels
-// A wavefield of one shot is stored as (NZ + 2*kHalo + 2) rows of pitch P:
-// one guard row, kHalo zero rows, NZ padded rows, kHalo zero rows, one guard
-// row. Columns NX .. P-1 of every row stay zero (P >= NX + kHalo), so they
-// serve as the right halo of a row and, read through the flat index, as the
-// left halo of the next row.
-constexpr int kRowsAbove = kHalo + 1;
-constexpr int kRowsExtra = 2 * kHalo + 2;
+// A wavefield of one shot is stored as (NZ + 2*kZeroRows + 2) rows of pitch
+// P: one guard row, kZeroRows zero rows, NZ padded rows, kZeroRows zero rows,
+// one guard row. Columns NX .. P-1 of every row stay zero (P >= NX +
+// kZeroRows), so they serve as the right halo of a row and, read through the
+// flat index, as the left halo of the next row. Eight zero rows/columns cover
+// the reach of two stencil applications (two time levels per launch).
+constexpr int kZeroRows = 2 * kHalo;
+constexpr int kRowsAbove = kZeroRows + 1;
+constexpr int kRowsExtra = 2 * kZeroRows + 2;
 
 // Per-shot layout and acquisition (device table, indexed in "slot" order:
 // shots sorted by decreasing record length).
@@ -36,9 +38,13 @@ struct ShotDesc {
     int32_t wav_off; // float offset of the shot's wavelet
 };
 
-// One wavefront of a step kernel owns a strip of 64 columns and the rows
-// [z0, z1) of one shot. Rows holding receivers inside the strip are listed
-// in rrows[rr0 .. rr1).
+// One wavefront of a step kernel owns the columns [col0, col0 + width) and
+// the rows [z0, z1) of one shot. Its lanes hold the columns starting at
+// col0 (one level per launch, width = 64*cw) or col0 - 4 (two levels per
+// launch, width = 64*cw - 8: the outer 4 columns on each side are computed
+// at the intermediate level only). Rows holding receivers among the lanes'
+// columns are listed in rrows[rr0 .. rr1) (for two levels: rows z0-4 ..
+// z1+3).
 struct WaveDesc {
     int32_t shot, col0, z0, z1;
     int32_t rr0, rr1, pad0, pad1;
@@ -68,19 +74,26 @@ struct StepArgs {
     const float *wav;    // wavelets
     int32_t nwaves, nz, nx, nb, NZ;
     int32_t cw;                // columns per lane of the wave table (1 or 2)
+    int32_t pd;                // one-level kernel: rows prefetched ahead (1 or 2)
     float w0, w1, w2, w3, w4;  // 2 c0 / h^2, c_k / h^2
     float dt2;                 // dt^2
     float hs;                  // smax dt / (2 nb^2): sigma dt/2 = hs (dz^2 + dx^2)
     float ih2;                 // 1 / h^2
-    int32_t n;                 // time index
+    int32_t n;                 // time index (of the first level computed)
+    int32_t n2;                // time index of the second level (two-level kernels)
     const float *cur;          // field at the current level
-    float *prev;               // previous level in, next level out
+    float *prev;               // previous level in, next level out (one level);
+                               // previous level in (two levels)
+    float *out1, *out2;        // two-level kernels: the two new levels
     const float *cur2;         // second field (Born)
     float *prev2;
     float *dslot;              // D^n slot (F_EMIT writes, F_IMAGE reads)
     float *G;                  // imaging accumulator
     float *samp;               // receiver samples of step n: samp[q]
     const float *inj;          // adjoint sources of step n: inj[q]
+    float *samp2;              // ... of the second level
+    const float *inj2;
+    float *dslot2;
 };
 
 // Time-major <-> trace-major conversion, residual and misfit.
@@ -118,6 +131,7 @@ hipStream_t ctx_stream(const struct ::fwi_ctx *c);
 int ctx_device(const struct ::fwi_ctx *c);
 
 hipError_t launch_step(int flags, const StepArgs &a, hipStream_t s);
+hipError_t launch_step2(int flags, const StepArgs &a, hipStream_t s);
 hipError_t launch_born_step(const StepArgs &a, hipStream_t s);
 hipError_t launch_fill(float *p, int64_t n, float val, hipStream_t s);
 hipError_t launch_model_check(const float *v, int64_t n, float *out3, hipStream_t s);

@@ -64,10 +64,13 @@ class FwiContext:
     def set_profiling(self, on: bool):
         _check(self.lib, self.ctx, self.lib.fwi_ctx_set_profiling(self.ctx, 1 if on else 0))
 
-    def set_tiling(self, kernel: int = -1, cols_per_lane: int = 0, rows_per_wave: int = 0):
-        """Force the step-kernel tiling (kernel 0 fwd, 1 adj, 2 Born, -1 all);
-        (0, 0) hands it back to the autotuner."""
-        _check(self.lib, self.ctx, self.lib.fwi_ctx_set_tiling(self.ctx, kernel, cols_per_lane, rows_per_wave))
+    def set_tiling(self, kernel: int = -1, cols_per_lane: int = 0, rows_per_wave: int = 0,
+                   levels_per_launch: int = 0, prefetch_rows: int = 0):
+        """Force the step-kernel tiling (kernel 0 fwd, 1 adj, 2 Born, -1 all;
+        the Born kernel keeps one level per launch); (0, 0, 0) hands it back
+        to the autotuner."""
+        _check(self.lib, self.ctx, self.lib.fwi_ctx_set_tiling(self.ctx, kernel, cols_per_lane, rows_per_wave,
+                                                               levels_per_launch, prefetch_rows))
 
     def set_autotune(self, on: bool):
         _check(self.lib, self.ctx, self.lib.fwi_ctx_set_autotune(self.ctx, 1 if on else 0))

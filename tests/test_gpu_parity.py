@@ -238,13 +238,16 @@ def test_empty_and_degenerate(ctx):
         assert rel(d, oracle.forward(gg, acq3, v)) < TOL_DATA
 
 
-@pytest.mark.parametrize("cw,rows", [(1, 7), (2, 13), (1, 300), (2, 5)])
-def test_forced_tilings_match_oracle_and_each_other(ctx, ragged, cw, rows):
+@pytest.mark.parametrize("cw,rows,levels,pd", [(1, 7, 1, 1), (2, 13, 1, 1), (1, 300, 1, 1), (2, 5, 1, 1),
+                                                (1, 7, 1, 2), (2, 13, 1, 2), (1, 300, 1, 2), (2, 6, 1, 2),
+                                                (1, 7, 2, 1), (2, 13, 2, 1), (1, 300, 2, 1), (2, 5, 2, 1),
+                                                (2, 33, 2, 1)])
+def test_forced_tilings_match_oracle_and_each_other(ctx, ragged, cw, rows, levels, pd):
     """Every tiling computes each cell with the same arithmetic, so results
     are bitwise equal across tilings and match the oracle."""
     wl = ragged
     g, acq = wl.grid, wl.acq
-    print(f"[parity] tiling cw={cw} rows={rows}", flush=True)
+    print(f"[parity] tiling cw={cw} rows={rows} levels={levels} prefetch={pd}", flush=True)
     v = dev(wl.v_true)
     v0 = dev(wl.v0)
     rng = np.random.default_rng(5)
@@ -258,13 +261,15 @@ def test_forced_tilings_match_oracle_and_each_other(ctx, ragged, cw, rows):
         im = host(ctx.born_mig(g, acq, v0, y))
         return d, gg, dd, im
 
-    ctx.set_tiling(-1, 1, 30)
+    ctx.set_tiling(-1, 1, 30, 1, 1)
     ref = run()
-    ctx.set_tiling(-1, cw, rows)
+    ctx.set_tiling(-1, cw, rows, levels, pd)
     got = run()
     st = ctx.stats()
-    ctx.set_tiling(-1, 0, 0)
+    ctx.set_tiling(-1, 0, 0, 0)
     assert st["tile_cw"] == [cw] * 3 and st["tile_rows"] == [rows] * 3
+    assert st["tile_levels"] == [levels, levels, 1]
+    assert st["tile_prefetch"][:2] == [pd if levels == 1 else 1] * 2
     for a, b in zip(got, ref):
         assert np.array_equal(a, b)
     v64 = f32(wl.v_true).astype(np.float64)
@@ -275,9 +280,10 @@ def test_forced_tilings_match_oracle_and_each_other(ctx, ragged, cw, rows):
 
 def test_autotuner_picks_a_valid_tiling(ctx, two_layer):
     wl, v_true, v0, d_obs = two_layer
-    ctx.set_tiling(-1, 0, 0)
+    ctx.set_tiling(-1, 0, 0, 0)
     ctx.set_autotune(True)
     ctx.fwi_forward(wl.grid, wl.acq, dev(v0))
     st = ctx.stats()
     assert all(c in (1, 2) for c in st["tile_cw"])
     assert all(r >= 1 for r in st["tile_rows"])
+    assert st["tile_levels"][2] == 1 and all(t in (1, 2) for t in st["tile_levels"])
