@@ -233,6 +233,7 @@ int alloc_buffers(deblur_net *n)
         int ns, ch;
         wsplit(M, N, P, &ns, &ch);
         wmax = std::max(wmax, int64_t(ns) * M * N);
+        bmax = std::max(bmax, int64_t(ns) * M);
     };
     auto acc_b = [&](int C, int P) {
         const int ns = std::max(1, std::min(256, P / 1024));
@@ -441,9 +442,9 @@ int conv_wgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff,
     w.out = P_<float>(n->grads, L.w);
     w.ldm = 9 * L.cin;
     w.ldn = 1;
+    w.bias_partial = P_<float>(n->bpart);
+    w.bias_out = P_<float>(n->grads, L.b);
     HCK(n, wgrad(w, st));
-    const int ns = std::max(1, std::min(256, n->P[lvl] / 1024));
-    HCK(n, bias_grad(dz, ldz, zoff, L.cout, n->P[lvl], P_<float>(n->grads, L.b), P_<float>(n->bpart), ns, st));
     return FWI_OK;
 }
 

@@ -56,6 +56,10 @@ struct WgradArgs {
     float *partial;
     float *out;
     int32_t ldm, ldn;
+    // optional: bias gradient sum_p A[p][acoff + m], partials [nsplit][M]
+    // then bias_out[m]
+    float *bias_partial;
+    float *bias_out;
 };
 
 hipError_t gemm(const GemmArgs &a, hipStream_t s);

@@ -36,10 +36,12 @@ __device__ __forceinline__ int64_t gather_pix(const Gather &g, int p, int tap)
     return int64_t(si) * g.Ws + sj;
 }
 
-template <int WM, int WN, bool VEC>
+template <int WM, int WN, int TN, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm(const GemmArgs a)
 {
-    constexpr int BM = 32 * WM, BN = 32 * WN;
+    // each wave accumulates a 32 x (32*TN) block: TN matrix-core tiles share
+    // one A operand per K slice
+    constexpr int BM = 32 * WM, BN = 32 * WN * TN;
     __shared__ __attribute__((aligned(16))) bf16 As[BM * kLDK];
     __shared__ __attribute__((aligned(16))) bf16 Bs[BN * kLDK];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -139,7 +141,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs a)
         }
     };
 
-    f32x16 acc = {};
+    f32x16 acc[TN];
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) acc[tn] = f32x16{};
     load_tiles(0);
     for (int kt = 0; kt < nk; ++kt) {
         __syncthreads();
@@ -150,30 +154,36 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs a)
         for (int kk = 0; kk < 2; ++kk) {
             const bf16x8 av =
                 *reinterpret_cast<const bf16x8 *>(&As[(wm * 32 + lane % 32) * kLDK + kk * 16 + 8 * (lane / 32)]);
-            const bf16x8 bv =
-                *reinterpret_cast<const bf16x8 *>(&Bs[(wn * 32 + lane % 32) * kLDK + kk * 16 + 8 * (lane / 32)]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(
+                    &Bs[((wn * TN + tn) * 32 + lane % 32) * kLDK + kk * 16 + 8 * (lane / 32)]);
+                acc[tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[tn], 0, 0, 0);
+            }
         }
     }
     // epilogue: lane holds rows m = 8*(i/4) + 4*(lane/32) + i%4, column lane%32
-    const int n = n0 + wn * 32 + lane % 32;
-    if (n >= a.N) return;
-    const int pi = n / g.W, pj = n - (n / g.W) * g.W;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int m = m0 + wm * 32 + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
-        if (m >= a.M) continue;
-        int co = m;
-        int64_t pix = n;
-        if (a.scatter) {
-            const int ab = m / a.Cout;
-            co = m - ab * a.Cout;
-            pix = int64_t(2 * pi + ab / 2) * a.Wo + 2 * pj + ab % 2;
+    for (int tn = 0; tn < TN; ++tn) {
+        const int n = n0 + (wn * TN + tn) * 32 + lane % 32;
+        if (n >= a.N) continue;
+        const int pi = n / g.W, pj = n - (n / g.W) * g.W;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int m = m0 + wm * 32 + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+            if (m >= a.M) continue;
+            int co = m;
+            int64_t pix = n;
+            if (a.scatter) {
+                const int ab = m / a.Cout;
+                co = m - ab * a.Cout;
+                pix = int64_t(2 * pi + ab / 2) * a.Wo + 2 * pj + ab % 2;
+            }
+            float v = acc[tn][i];
+            if (a.bias) v += a.bias[co];
+            if (a.act) v = v > 0.f ? v : a.slope * v;
+            a.out[pix * a.out_ld + a.out_coff + co] = f2bf(v);
         }
-        float v = acc[i];
-        if (a.bias) v += a.bias[co];
-        if (a.act) v = v > 0.f ? v : a.slope * v;
-        a.out[pix * a.out_ld + a.out_coff + co] = f2bf(v);
     }
 }
 
@@ -254,11 +264,25 @@ __global__ __launch_bounds__(256) void k_wgrad(const WgradArgs a)
         }
     };
 
+    // the first column of blocks also sums A over its pixels: the bias
+    // gradient of the layer (A = dz), per split, reduced later in order
+    const bool do_bias = a.bias_partial != nullptr && blockIdx.x == 0;
+    float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     f32x16 acc = {};
     if (nk > 0) load_tiles(0);
     for (int kt = 0; kt < nk; ++kt) {
         __syncthreads();
         store_tiles();
+        if (do_bias) {
+            if constexpr (VEC) {
+                const bf16 *pa = reinterpret_cast<const bf16 *>(&ra);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bsum[e] += bf2f(pa[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bsum[e] += bf2f(sa[e]);
+            }
+        }
         __syncthreads();
         if (kt + 1 < nk) load_tiles(kt + 1);
 #pragma unroll
@@ -268,6 +292,19 @@ __global__ __launch_bounds__(256) void k_wgrad(const WgradArgs a)
             const bf16x8 bv =
                 *reinterpret_cast<const bf16x8 *>(&Bs[(wn * 32 + lane % 32) * kLDK + kk * 16 + 8 * (lane / 32)]);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+    }
+    if (do_bias) {
+        // threads tid, tid+8, ... hold the same 8 channels for 32 pixel rows
+        __shared__ float bred[32][65];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bred[tid / 8][(tid % 8) * 8 + e] = bsum[e];
+        __syncthreads();
+        if (tid < 64) {
+            float t = 0.f;
+            for (int r = 0; r < 32; ++r) t += bred[r][tid];
+            if (m0 + tid < a.M) a.bias_partial[int64_t(blockIdx.z) * a.M + m0 + tid] = t;
         }
     }
     const int n = n0 + wn * 32 + lane % 32;
@@ -280,43 +317,70 @@ __global__ __launch_bounds__(256) void k_wgrad(const WgradArgs a)
     }
 }
 
+// sum of `rows` partial rows with four independent accumulators (the loads
+// of a thread overlap; the combination order is fixed)
+__device__ __forceinline__ float sum_strided(const float *p, int rows, int64_t stride)
+{
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int z = 0;
+    for (; z + 4 <= rows; z += 4) {
+        s0 += p[int64_t(z) * stride];
+        s1 += p[int64_t(z + 1) * stride];
+        s2 += p[int64_t(z + 2) * stride];
+        s3 += p[int64_t(z + 3) * stride];
+    }
+    for (; z < rows; ++z) s0 += p[int64_t(z) * stride];
+    return (s0 + s1) + (s2 + s3);
+}
+
 __global__ void k_wgrad_reduce(const float *part, int32_t M, int32_t N, int32_t nsplit, float *out, int32_t ldm,
                                int32_t ldn)
 {
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= int64_t(M) * N) return;
-    float s = 0.f;
-    for (int z = 0; z < nsplit; ++z) s += part[int64_t(z) * M * N + e];
+    const float s = sum_strided(part + e, nsplit, int64_t(M) * N);
     const int m = int(e / N), n = int(e % N);
     out[int64_t(m) * ldm + int64_t(n) * ldn] = s;
 }
 
-// db[c] = sum_p dz[p][coff + c]: block (channel group of 64, pixel split),
-// then a second pass over the splits in fixed order.
+// db[c] = sum_p dz[p][coff + c] (C a multiple of 8, at most 2048): each
+// thread adds 16-byte chunks (8 channels) of one pixel per row of the block;
+// a block covers one pixel split; partial sums per split, reduced in order
+// by k_sum_rows.
 __global__ __launch_bounds__(256) void k_bias_part(const bf16 *dz, int32_t ld, int32_t coff, int32_t C, int32_t P,
                                                    int32_t chunk, float *part)
 {
-    __shared__ float red[4][64];
-    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int r = threadIdx.x >> 6;
-    const int p0 = blockIdx.y * chunk, p1 = min(P, p0 + chunk);
-    float s = 0.f;
-    if (c < C)
-        for (int p = p0 + r; p < p1; p += 4) s += bf2f(dz[int64_t(p) * ld + coff + c]);
-    red[r][threadIdx.x & 63] = s;
+    __shared__ float red[256][9];
+    const int cpp = C / 8;            // 8-channel chunks per pixel
+    const int rows = 256 / cpp;       // pixels handled per pass of the block
+    const int tid = threadIdx.x;
+    const int ch = tid % cpp, pr = tid / cpp;
+    const int p0 = blockIdx.x * chunk, p1 = min(P, p0 + chunk);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (pr < rows) {
+        for (int p = p0 + pr; p < p1; p += rows) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(dz + int64_t(p) * ld + coff + ch * 8);
+            const bf16 *b = reinterpret_cast<const bf16 *>(&v);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] += bf2f(b[e]);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[tid][e] = s[e];
     __syncthreads();
-    if (r == 0 && c < C)
-        part[int64_t(blockIdx.y) * C + c] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
-                                            red[3][threadIdx.x];
+    for (int c = tid; c < C; c += 256) {
+        const int cc = c / 8, e = c % 8;
+        float t = 0.f;
+        for (int r = 0; r < rows; ++r) t += red[r * cpp + cc][e];
+        part[int64_t(blockIdx.x) * C + c] = t;
+    }
 }
 
 __global__ void k_sum_rows(const float *part, int32_t rows, int32_t C, float *out)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C) return;
-    float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += part[int64_t(r) * C + c];
-    out[c] = s;
+    out[c] = sum_strided(part + c, rows, C);
 }
 
 __global__ void k_act_bwd(bf16 *dz, int32_t ldz, int32_t zoff, const bf16 *dy, int32_t ldy, int32_t yoff,
@@ -428,14 +492,24 @@ __global__ __launch_bounds__(256) void k_outc_bwd(const bf16 *x, int32_t C, int3
     }
 }
 
-__global__ void k_outc_reduce(const float *part, int32_t C, int32_t nblk, float *dw, float *db)
+// dw[c], db: block c reduces column c of the [nblk][C+1] partials with 256
+// threads (fixed order)
+__global__ __launch_bounds__(256) void k_outc_reduce(const float *part, int32_t C, int32_t nblk, float *dw, float *db)
 {
-    const int c = threadIdx.x;
-    if (c > C) return;
+    __shared__ float red[256];
+    const int c = blockIdx.x;
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[int64_t(b) * (C + 1) + c];
-    if (c < C) dw[c] = s;
-    else db[0] = s;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += part[int64_t(b) * (C + 1) + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (c < C) dw[c] = red[0];
+        else db[0] = red[0];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_sum_d(const double *p, int32_t n, double *out, float scale, float *out_f)
@@ -561,15 +635,21 @@ hipError_t gemm(const GemmArgs &a, hipStream_t s)
 {
     if (a.M <= 0 || a.N <= 0) return hipSuccess;
     const bool vec = a.K % kBK == 0 && a.g.Cb % 8 == 0 && a.lda % 8 == 0 && a.g.ld % 8 == 0 && a.g.coff % 8 == 0;
-    // thin outputs use 32-row tiles, wide ones 64x64
+    // thin outputs use 32 x 256 tiles, wide ones 64 x 128; small problems
+    // (the coarse levels) keep 64 x 64 tiles so that enough blocks run
+    const int64_t blocks_wide = int64_t(nblocks(a.N, 128)) * nblocks(a.M, 64);
     if (a.M <= 32) {
-        const dim3 grid(nblocks(a.N, 128), nblocks(a.M, 32));
-        if (vec) hipLaunchKernelGGL((k_gemm<1, 4, true>), grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_gemm<1, 4, false>), grid, dim3(256), 0, s, a);
+        const dim3 grid(nblocks(a.N, 256), nblocks(a.M, 32));
+        if (vec) hipLaunchKernelGGL((k_gemm<1, 4, 2, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_gemm<1, 4, 2, false>), grid, dim3(256), 0, s, a);
+    } else if (blocks_wide >= 512) {
+        const dim3 grid(nblocks(a.N, 128), nblocks(a.M, 64));
+        if (vec) hipLaunchKernelGGL((k_gemm<2, 2, 2, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_gemm<2, 2, 2, false>), grid, dim3(256), 0, s, a);
     } else {
         const dim3 grid(nblocks(a.N, 64), nblocks(a.M, 64));
-        if (vec) hipLaunchKernelGGL((k_gemm<2, 2, true>), grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_gemm<2, 2, false>), grid, dim3(256), 0, s, a);
+        if (vec) hipLaunchKernelGGL((k_gemm<2, 2, 1, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_gemm<2, 2, 1, false>), grid, dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -586,6 +666,9 @@ hipError_t wgrad(const WgradArgs &a, hipStream_t s)
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(int64_t(a.M) * a.N)), dim3(256), 0, s, a.partial, a.M, a.N,
                        a.nsplit, a.out, a.ldm, a.ldn);
+    e = hipGetLastError();
+    if (e != hipSuccess || !a.bias_partial) return e;
+    hipLaunchKernelGGL(k_sum_rows, dim3(nblocks(a.M)), dim3(256), 0, s, a.bias_partial, a.nsplit, a.M, a.bias_out);
     return hipGetLastError();
 }
 
@@ -639,7 +722,7 @@ hipError_t outc_bwd(const bf16 *x, int32_t C, int32_t P, const float *w, const f
 
 hipError_t outc_wgrad_reduce(const float *part_w, int32_t C, int32_t nblk, float *dw, float *db, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_outc_reduce, dim3(1), dim3(((C + 1 + 63) / 64) * 64), 0, s, part_w, C, nblk, dw, db);
+    hipLaunchKernelGGL(k_outc_reduce, dim3(unsigned(C + 1)), dim3(256), 0, s, part_w, C, nblk, dw, db);
     return hipGetLastError();
 }
 
@@ -706,9 +789,9 @@ hipError_t convt_dgrad_weights(const float *wt, int32_t Cin, int32_t Cout, bf16 
 hipError_t bias_grad(const bf16 *dz, int32_t ld, int32_t coff, int32_t C, int32_t P, float *db, float *scratch,
                      int32_t nsplit, hipStream_t s)
 {
+    if (C % 8 || C > 2048 || ld % 8 || coff % 8) return hipErrorInvalidValue;
     const int chunk = (P + nsplit - 1) / nsplit;
-    hipLaunchKernelGGL(k_bias_part, dim3(unsigned((C + 63) / 64), unsigned(nsplit)), dim3(256), 0, s, dz, ld, coff, C,
-                       P, chunk, scratch);
+    hipLaunchKernelGGL(k_bias_part, dim3(unsigned(nsplit)), dim3(256), 0, s, dz, ld, coff, C, P, chunk, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_rows, dim3(nblocks(C)), dim3(256), 0, s, scratch, nsplit, C, db);
