@@ -444,7 +444,6 @@ StepArgs base_args(fwi_ctx *c, const float *v, int cls)
     a.nb = p.nb;
     a.NZ = p.NZ;
     const double ih2 = 1.0 / (double(p.h) * p.h);
-    a.w0 = float(2.0 * kC8[0] * ih2);
     a.w1 = float(kC8[1] * ih2);
     a.w2 = float(kC8[2] * ih2);
     a.w3 = float(kC8[3] * ih2);

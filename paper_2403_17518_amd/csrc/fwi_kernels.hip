@@ -48,6 +48,32 @@ __device__ __forceinline__ float sponge_a(float sh)
     return __builtin_amdgcn_rcpf(1.0f + sh);
 }
 
+// 8th-order Laplacian at column k of a lane's strip: the column's rows
+// z-4..z+4 sit in q[0..8][k], the row's columns x-4..x+4 in xr[k..k+8].
+// Every neighbour enters as its difference to the centre value (the weights
+// sum to zero), so a smooth field loses no significant bits to the large
+// centre weight; the smallest weights are summed first.
+template <int CW>
+__device__ __forceinline__ float lap8(const float (&q)[9][CW], const float *xr, int k,
+                                      float w1, float w2, float w3, float w4)
+{
+    const float c = q[4][k];
+    float s = w4 * (((q[0][k] - c) + (q[8][k] - c)) + ((xr[k] - c) + (xr[k + 8] - c)));
+    s = __builtin_fmaf(w3, ((q[1][k] - c) + (q[7][k] - c)) + ((xr[k + 1] - c) + (xr[k + 7] - c)), s);
+    s = __builtin_fmaf(w2, ((q[2][k] - c) + (q[6][k] - c)) + ((xr[k + 2] - c) + (xr[k + 6] - c)), s);
+    s = __builtin_fmaf(w1, ((q[3][k] - c) + (q[5][k] - c)) + ((xr[k + 3] - c) + (xr[k + 5] - c)), s);
+    return s;
+}
+
+// Leapfrog update with the sponge, a (2u + D) - b u_prev where a = 1/(1+sh)
+// and b = (1-sh) a, written as a ((u - u_prev) + u + D + sh u_prev): the
+// change over one step is formed first, which keeps the low bits of a slowly
+// varying field (a = 1, sh = 0 away from the sponge).
+__device__ __forceinline__ float leapfrog(float u, float up, float D, float a, float sh)
+{
+    return a * (((u - up) + u) + __builtin_fmaf(sh, up, D));
+}
+
 template <int CW>
 __device__ __forceinline__ void ld(const float *p, float (&o)[CW])
 {
@@ -93,7 +119,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
 
     bool valid[CW];
     int jm[CW];
-    float dx2[CW], ax[CW], bx[CW];
+    float dx2[CW], ax[CW], shx[CW];
 #pragma unroll
     for (int k = 0; k < CW; ++k) {
         const int j = j0 + k;
@@ -103,7 +129,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
         dx2[k] = float(ddx * ddx);
         const float sh = A.hs * dx2[k];
         ax[k] = sponge_a(sh);
-        bx[k] = (1.0f - sh) * ax[k];
+        shx[k] = sh;
     }
     // halo: lane 0 reads the 4 columns left of the strip, lane 1 the 4
     // columns right of it (a zero column block when past the shot's width)
@@ -170,24 +196,19 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
         float out[CW], Dv[CW];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
-            float lap = A.w0 * q[4][k] +
-                        A.w1 * ((q[3][k] + q[5][k]) + (xr[k + 3] + xr[k + 5])) +
-                        A.w2 * ((q[2][k] + q[6][k]) + (xr[k + 2] + xr[k + 6])) +
-                        A.w3 * ((q[1][k] + q[7][k]) + (xr[k + 1] + xr[k + 7])) +
-                        A.w4 * ((q[0][k] + q[8][k]) + (xr[k] + xr[k + 8]));
+            float lap = lap8(q, xr, k, A.w1, A.w2, A.w3, A.w4);
             if (FL & F_SRC)
                 if (src_k == k && z == S.src_i) lap += wsrc;
             if (FL & F_INJECT)
                 if (qi[k] >= 0) lap += A.inj[qi[k]];
             const float cc = c.v[k] * c.v[k] * A.dt2;
-            float a = ax[k], b = bx[k];
+            float a = ax[k], sh = shx[k];
             if (ddz > 0) {
-                const float sh = A.hs * (dz2 + dx2[k]);
+                sh = A.hs * (dz2 + dx2[k]);
                 a = sponge_a(sh);
-                b = (1.0f - sh) * a;
             }
             Dv[k] = cc * lap;
-            out[k] = a * (2.0f * q[4][k] + Dv[k]) - b * c.pv[k];
+            out[k] = leapfrog(q[4][k], c.pv[k], Dv[k], a, sh);
         }
         const int o = (z + kRowsAbove) * P + j0;
         const int og = z * P + j0;
@@ -268,7 +289,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 
     bool inbox[CW], own[CW];
     int jm[CW];
-    float dx2[CW], ax[CW], bx[CW];
+    float dx2[CW], ax[CW], shx[CW];
 #pragma unroll
     for (int k = 0; k < CW; ++k) {
         const int j = j0 + k;
@@ -279,7 +300,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         dx2[k] = float(ddx * ddx);
         const float sh = A.hs * dx2[k];
         ax[k] = sponge_a(sh);
-        bx[k] = (1.0f - sh) * ax[k];
+        shx[k] = sh;
     }
     const int hcol = lane == 0 ? cb - kHalo : min(cb + SW, P - kHalo);
     if (lane < 2) *reinterpret_cast<float4 *>(&row1[lane == 0 ? 0 : kHalo + SW]) = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -378,24 +399,19 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         float v1[CW], D1[CW];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
-            float lap = A.w0 * qa[4][k] +
-                        A.w1 * ((qa[3][k] + qa[5][k]) + (xr[k + 3] + xr[k + 5])) +
-                        A.w2 * ((qa[2][k] + qa[6][k]) + (xr[k + 2] + xr[k + 6])) +
-                        A.w3 * ((qa[1][k] + qa[7][k]) + (xr[k + 1] + xr[k + 7])) +
-                        A.w4 * ((qa[0][k] + qa[8][k]) + (xr[k] + xr[k + 8]));
+            float lap = lap8(qa, xr, k, A.w1, A.w2, A.w3, A.w4);
             if (FL & F_SRC)
                 if (src_k == k && t == S.src_i) lap += wsrc1;
             if (FL & F_INJECT)
                 if (qi1[k] >= 0) lap += A.inj[qi1[k]];
             const float c = cv[k] * cv[k] * A.dt2;
-            float a = ax[k], b = bx[k];
+            float a = ax[k], sh = shx[k];
             if (ddz1 > 0) {
-                const float sh = A.hs * (dz1 + dx2[k]);
+                sh = A.hs * (dz1 + dx2[k]);
                 a = sponge_a(sh);
-                b = (1.0f - sh) * a;
             }
             D1[k] = c * lap;
-            const float o = a * (2.0f * qa[4][k] + D1[k]) - b * cpv[k];
+            const float o = leapfrog(qa[4][k], cpv[k], D1[k], a, sh);
             v1[k] = (row_in && inbox[k]) ? o : 0.0f;
             qb[8][k] = v1[k];
             cq[4][k] = c;
@@ -444,24 +460,19 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
             const int o = (r2 + kRowsAbove) * P + j0;
 #pragma unroll
             for (int k = 0; k < CW; ++k) {
-                float lap = A.w0 * qb[4][k] +
-                            A.w1 * ((qb[3][k] + qb[5][k]) + (yr[k + 3] + yr[k + 5])) +
-                            A.w2 * ((qb[2][k] + qb[6][k]) + (yr[k + 2] + yr[k + 6])) +
-                            A.w3 * ((qb[1][k] + qb[7][k]) + (yr[k + 1] + yr[k + 7])) +
-                            A.w4 * ((qb[0][k] + qb[8][k]) + (yr[k] + yr[k + 8]));
+                float lap = lap8(qb, yr, k, A.w1, A.w2, A.w3, A.w4);
                 if (FL & F_SRC)
                     if (src_k == k && r2 == S.src_i) lap += wsrc2;
                 if (FL & F_INJECT)
                     if (qi2[k] >= 0) lap += A.inj2[qi2[k]];
                 const float c = cq[0][k];
-                float a = ax[k], b = bx[k];
+                float a = ax[k], sh = shx[k];
                 if (ddz2 > 0) {
-                    const float sh = A.hs * (dz2 + dx2[k]);
+                    sh = A.hs * (dz2 + dx2[k]);
                     a = sponge_a(sh);
-                    b = (1.0f - sh) * a;
                 }
                 const float D2 = c * lap;
-                const float v2 = a * (2.0f * qb[4][k] + D2) - b * qa[0][k];
+                const float v2 = leapfrog(qb[4][k], qa[0][k], D2, a, sh);
                 if (own[k]) {
                     o2[o + k] = v2;
                     if (FL & F_EMIT)
@@ -520,7 +531,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
 
     bool valid[CW];
     int jm[CW];
-    float dx2[CW], ax[CW], bx[CW];
+    float dx2[CW], ax[CW], shx[CW];
 #pragma unroll
     for (int k = 0; k < CW; ++k) {
         const int j = j0 + k;
@@ -530,7 +541,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
         dx2[k] = float(ddx * ddx);
         const float sh = A.hs * dx2[k];
         ax[k] = sponge_a(sh);
-        bx[k] = (1.0f - sh) * ax[k];
+        shx[k] = sh;
     }
     const int hcol = lane == 0 ? W.col0 - kHalo : min(W.col0 + SW, P - kHalo);
 
@@ -615,27 +626,18 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
         float ou[CW], od[CW];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
-            float lap = A.w0 * q[4][k] +
-                        A.w1 * ((q[3][k] + q[5][k]) + (xr[k + 3] + xr[k + 5])) +
-                        A.w2 * ((q[2][k] + q[6][k]) + (xr[k + 2] + xr[k + 6])) +
-                        A.w3 * ((q[1][k] + q[7][k]) + (xr[k + 1] + xr[k + 7])) +
-                        A.w4 * ((q[0][k] + q[8][k]) + (xr[k] + xr[k + 8]));
-            const float lapd = A.w0 * r[4][k] +
-                               A.w1 * ((r[3][k] + r[5][k]) + (xd[k + 3] + xd[k + 5])) +
-                               A.w2 * ((r[2][k] + r[6][k]) + (xd[k + 2] + xd[k + 6])) +
-                               A.w3 * ((r[1][k] + r[7][k]) + (xd[k + 1] + xd[k + 7])) +
-                               A.w4 * ((r[0][k] + r[8][k]) + (xd[k] + xd[k + 8]));
+            float lap = lap8(q, xr, k, A.w1, A.w2, A.w3, A.w4);
+            const float lapd = lap8(r, xd, k, A.w1, A.w2, A.w3, A.w4);
             if (src_k == k && z == S.src_i) lap += wsrc;
             const float c = cv[k] * cv[k] * A.dt2;
             const float cr = 2.0f * cv[k] * cdv[k] * A.dt2;
-            float a = ax[k], b = bx[k];
+            float a = ax[k], sh = shx[k];
             if (ddz > 0) {
-                const float sh = A.hs * (dz2 + dx2[k]);
+                sh = A.hs * (dz2 + dx2[k]);
                 a = sponge_a(sh);
-                b = (1.0f - sh) * a;
             }
-            ou[k] = a * (2.0f * q[4][k] + c * lap) - b * cpv[k];
-            od[k] = a * (2.0f * r[4][k] + c * lapd + cr * lap) - b * cpd[k];
+            ou[k] = leapfrog(q[4][k], cpv[k], c * lap, a, sh);
+            od[k] = leapfrog(r[4][k], cpd[k], __builtin_fmaf(cr, lap, c * lapd), a, sh);
         }
         const int o = (z + kRowsAbove) * P + j0;
 #pragma unroll

@@ -75,7 +75,7 @@ struct StepArgs {
     int32_t nwaves, nz, nx, nb, NZ;
     int32_t cw;                // columns per lane of the wave table (1 or 2)
     int32_t pd;                // one-level kernel: rows prefetched ahead (1 or 2)
-    float w0, w1, w2, w3, w4;  // 2 c0 / h^2, c_k / h^2
+    float w1, w2, w3, w4;      // c_k / h^2 (the centre weight is -4 times their sum)
     float dt2;                 // dt^2
     float hs;                  // smax dt / (2 nb^2): sigma dt/2 = hs (dz^2 + dx^2)
     float ih2;                 // 1 / h^2
