@@ -358,12 +358,20 @@ void build_tiling(const Plan &p, int cw, int rows_target, int tb, int pd, Tiling
     for (int k = 0; k < p.S; ++k) {
         const auto &cells = p.slot_cells[k];
         const int nstrips = (p.shots[k].NX + SWo - 1) / SWo;
+        // receiver cells of each strip, sorted by row, then column
+        std::vector<std::vector<std::pair<std::pair<int, int>, int>>> strip_cells(nstrips);
         for (int st = 0; st < nstrips; ++st) {
-            const int col0 = st * SWo, lane0 = col0 - reach;
-            std::vector<std::pair<std::pair<int, int>, int>> sc;  // sorted by row, then column
+            const int lane0 = st * SWo - reach;
             for (const auto &cq : cells)
-                if (cq.first.second >= lane0 && cq.first.second < lane0 + SW) sc.push_back(cq);
-            for (int z0 = 0; z0 < p.NZ; z0 += rows) {
+                if (cq.first.second >= lane0 && cq.first.second < lane0 + SW) strip_cells[st].push_back(cq);
+        }
+        // adjacent strips of one row band get consecutive wave ids: the waves
+        // of a workgroup start together and read neighbouring stretches of
+        // each row at about the same time
+        for (int z0 = 0; z0 < p.NZ; z0 += rows) {
+            for (int st = 0; st < nstrips; ++st) {
+                const int col0 = st * SWo, lane0 = col0 - reach;
+                const auto &sc = strip_cells[st];
                 WaveDesc w{};
                 w.shot = k;
                 w.col0 = col0;
@@ -787,6 +795,9 @@ const Candidate kTune[] = {
     {2, 8, 1, 2},  {2, 16, 1, 2}, {2, 24, 1, 2}, {2, 32, 1, 2}, {1, 24, 2, 1}, {1, 48, 2, 1}, {2, 24, 2, 1},
     {2, 48, 2, 1}};
 
+constexpr int kTuneLaunches = 10;   // timed launches per candidate and pass
+constexpr int kTunePasses = 2;      // passes over the list; the best time counts
+
 // time of one time level of kernel class `cls` with tiling t (ms per level)
 int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_out)
 {
@@ -816,7 +827,9 @@ int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_o
     b.samp2 = b.samp + p.Q;
     b.inj = b.samp;
     b.inj2 = b.samp2;
-    const int flags = cls == K_ADJ ? (F_INJECT | F_IMAGE) : (F_SRC | F_SAMPLE);
+    // the forward class is timed as the forward of a gradient or migration
+    // (emitting D), its most frequent and heaviest form
+    const int flags = cls == K_ADJ ? (F_INJECT | F_IMAGE) : (F_SRC | F_SAMPLE | F_EMIT);
     auto launch = [&]() -> hipError_t {
         if (cls == K_BORN) return launch_born_step(b, c->stream);
         return t.tb == 2 ? launch_step2(flags, b, c->stream) : launch_step(flags, b, c->stream);
@@ -825,8 +838,9 @@ int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_o
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     hipError_t err = launch();
+    if (err == hipSuccess) err = launch();
     if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
-    for (int i = 0; i < 4 && err == hipSuccess; ++i) err = launch();
+    for (int i = 0; i < kTuneLaunches && err == hipSuccess; ++i) err = launch();
     if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -834,7 +848,7 @@ int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_o
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return set_err(c, FWI_EHIP, "autotune launch: %s", hipGetErrorString(err));
-    *ms_out = ms / float(t.tb);
+    *ms_out = ms / float(kTuneLaunches * t.tb);
     return FWI_OK;
 }
 
@@ -863,7 +877,7 @@ int ensure_tilings(fwi_ctx *c, const float *v)
     // two sample rows)
     const int64_t ff = p.field_floats, gf = p.img_floats;
     const int64_t nq = 2 * std::max(p.Q, 1);
-    int rc;
+    int rc = FWI_OK;
     if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
         (rc = ensure(c, c->dhist, size_t(2 * gf) * 4)) || (rc = ensure(c, c->samples, size_t(nq) * 4)))
         return rc;
@@ -877,19 +891,21 @@ int ensure_tilings(fwi_ctx *c, const float *v)
                        {kDefaultCw, kDefaultRows, kDefaultTb, kDefaultPd},
                        {kDefaultCw, kDefaultRows, 1, kDefaultPd}};
     Tiling trial;
-    for (const Candidate &cand : kTune) {
-        build_tiling(p, cand.cw, cand.rows, cand.tb, cand.pd, trial);
-        if ((rc = upload_tiling(c, trial))) break;
-        for (int k = 0; k < 3; ++k) {
-            if (c->tile[k].cw != 0 || (k == K_BORN && (cand.tb != 1 || cand.pd != 1))) continue;
-            float ms = 0.f;
-            if ((rc = time_class(c, k, trial, v, &ms))) break;
-            if (ms < best[k]) {
-                best[k] = ms;
-                bc[k] = cand;
+    for (int pass = 0; pass < kTunePasses && rc == 0; ++pass) {
+        for (const Candidate &cand : kTune) {
+            build_tiling(p, cand.cw, cand.rows, cand.tb, cand.pd, trial);
+            if ((rc = upload_tiling(c, trial))) break;
+            for (int k = 0; k < 3; ++k) {
+                if (c->tile[k].cw != 0 || (k == K_BORN && (cand.tb != 1 || cand.pd != 1))) continue;
+                float ms = 0.f;
+                if ((rc = time_class(c, k, trial, v, &ms))) break;
+                if (ms < best[k]) {
+                    best[k] = ms;
+                    bc[k] = cand;
+                }
             }
+            if (rc) break;
         }
-        if (rc) break;
     }
     release(trial.d_waves);
     release(trial.d_rrows);
