@@ -797,6 +797,10 @@ const Candidate kTune[] = {
 
 constexpr int kTuneLaunches = 10;   // timed launches per candidate and pass
 constexpr int kTunePasses = 2;      // passes over the list; the best time counts
+// D slots the trial launches cycle through, as a real sweep streams through
+// its history: together larger than the last-level cache, so D moves to and
+// from HBM as it does in a real sweep
+constexpr int kTuneSlots = 12;
 
 // time of one time level of kernel class `cls` with tiling t (ms per level)
 int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_out)
@@ -820,8 +824,9 @@ int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_o
     b.cur2 = F + 2 * ff;
     b.prev2 = F + 3 * ff;
     b.dv = v;
-    b.dslot = static_cast<float *>(c->dhist.p);
-    b.dslot2 = b.dslot + gf;
+    float *const dhist = static_cast<float *>(c->dhist.p);
+    b.dslot = dhist;
+    b.dslot2 = dhist + gf;
     b.G = static_cast<float *>(c->image.p);
     b.samp = static_cast<float *>(c->samples.p);
     b.samp2 = b.samp + p.Q;
@@ -830,7 +835,11 @@ int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_o
     // the forward class is timed as the forward of a gradient or migration
     // (emitting D), its most frequent and heaviest form
     const int flags = cls == K_ADJ ? (F_INJECT | F_IMAGE) : (F_SRC | F_SAMPLE | F_EMIT);
+    int slot = 0;
     auto launch = [&]() -> hipError_t {
+        b.dslot = dhist + int64_t(slot) * gf;
+        b.dslot2 = b.dslot + gf;
+        slot = (slot + 1) % kTuneSlots;
         if (cls == K_BORN) return launch_born_step(b, c->stream);
         return t.tb == 2 ? launch_step2(flags, b, c->stream) : launch_step(flags, b, c->stream);
     };
@@ -879,11 +888,13 @@ int ensure_tilings(fwi_ctx *c, const float *v)
     const int64_t nq = 2 * std::max(p.Q, 1);
     int rc = FWI_OK;
     if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
-        (rc = ensure(c, c->dhist, size_t(2 * gf) * 4)) || (rc = ensure(c, c->samples, size_t(nq) * 4)))
+        (rc = ensure(c, c->dhist, size_t((kTuneSlots + 1) * gf) * 4)) ||
+        (rc = ensure(c, c->samples, size_t(nq) * 4)))
         return rc;
     if ((rc = other(c, launch_fill(static_cast<float *>(c->fields.p), 4 * ff, 0.f, c->stream), "fill")) ||
         (rc = other(c, launch_fill(static_cast<float *>(c->image.p), gf, 0.f, c->stream), "fill")) ||
-        (rc = other(c, launch_fill(static_cast<float *>(c->dhist.p), 2 * gf, 0.f, c->stream), "fill")) ||
+        (rc = other(c, launch_fill(static_cast<float *>(c->dhist.p), (kTuneSlots + 1) * gf, 0.f, c->stream),
+                    "fill")) ||
         (rc = other(c, launch_fill(static_cast<float *>(c->samples.p), nq, 0.f, c->stream), "fill")))
         return rc;
     float best[3] = {1e30f, 1e30f, 1e30f};

@@ -86,6 +86,62 @@ __device__ __forceinline__ void ld(const float *p, float (&o)[CW])
     }
 }
 
+// Raw buffer view of a wave-uniform base address. A load or store names the
+// base by its descriptor (scalar registers), a per-row byte offset (scalar)
+// and a fixed per-lane byte offset (one vector register), so streaming a row
+// costs no vector address arithmetic. Range checking is left wide open:
+// every offset used is in bounds by construction. The loads and stores are
+// the raw-buffer intrinsics of the AMDGPU backend, bound by name.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ float raw_ld_f32(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.f32");
+__device__ f32x2 raw_ld_v2f32(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.v2f32");
+__device__ f32x4 raw_ld_v4f32(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.v4f32");
+__device__ void raw_st_f32(float v, i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.store.f32");
+
+using Rsrc = i32x4;
+constexpr int kRsrcWord3 = 0x00020000;   // 32-bit data format, no swizzle
+
+__device__ __forceinline__ Rsrc view(const float *base)
+{
+    const unsigned long long a = reinterpret_cast<unsigned long long>(base);
+    Rsrc r;
+    r.x = int(unsigned(a));
+    r.y = int(unsigned(a >> 32) & 0xffffu);   // stride 0
+    r.z = 0x7fffffff;                        // byte range
+    r.w = kRsrcWord3;
+    return r;
+}
+
+__device__ __forceinline__ float bld1(Rsrc r, unsigned lane_off, int row_off)
+{
+    return raw_ld_f32(r, int(lane_off), row_off, 0);
+}
+
+template <int CW>
+__device__ __forceinline__ void bld(Rsrc r, unsigned lane_off, int row_off, float (&o)[CW])
+{
+    if constexpr (CW == 1) {
+        o[0] = bld1(r, lane_off, row_off);
+    } else {
+        const f32x2 t = raw_ld_v2f32(r, int(lane_off), row_off, 0);
+        o[0] = t.x;
+        o[1] = t.y;
+    }
+}
+
+__device__ __forceinline__ float4 bld4(Rsrc r, unsigned lane_off, int row_off)
+{
+    const f32x4 t = raw_ld_v4f32(r, int(lane_off), row_off, 0);
+    return make_float4(t.x, t.y, t.z, t.w);
+}
+
+__device__ __forceinline__ void bst1(Rsrc r, unsigned lane_off, int row_off, float v)
+{
+    raw_st_f32(v, r, int(lane_off), row_off, 0);
+}
+
 // One time level of every active shot. Each lane owns CW adjacent columns of
 // a 64*CW-column strip and streams down the rows [z0, z1) of that strip; the
 // loads of rows z+1 .. z+PD are issued before row z is computed so that PD+1
@@ -97,7 +153,9 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     constexpr int RW = SW + 2 * kHalo;       // LDS row width
     __shared__ float lds[kWavesPerBlock][RW];
     const int lane = threadIdx.x & (kLanes - 1);
-    const int wl = threadIdx.x / kLanes;
+    // wave-uniform from here on: descriptors, bases and row offsets live in
+    // scalar registers
+    const int wl = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
     const int wid = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wl;
     if (wid >= A.nwaves) return;  // whole wave leaves; no block barrier used
     float *row = lds[wl];
@@ -108,23 +166,24 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     const int j0 = W.col0 + CW * lane;       // first column of this lane
     // every load is unconditional: lanes past the shot's width read a zero
     // column (P - CW >= NX + 2) instead
-    const int jl = min(j0, P - 2);
+    const unsigned jl = 4u * unsigned(min(j0, P - 2));   // byte offsets
+    const unsigned js = 4u * unsigned(j0);
     // offsets below are relative to the field block start (guard row), so
     // they are non-negative 32-bit values
     const float *cu = A.cur + (S.f_off - int64_t(kRowsAbove) * P);
     float *pv = A.prev + (S.f_off - int64_t(kRowsAbove) * P);
-    const float *vmod = A.v;
-    float *gb = (FL & F_IMAGE) ? A.G + S.g_off : nullptr;
-    float *db = (FL & (F_IMAGE | F_EMIT)) ? A.dslot + S.g_off : nullptr;
+    const Rsrc rcur = view(cu), rprev = view(pv), rv = view(A.v);
+    const Rsrc rg = view((FL & F_IMAGE) ? A.G + S.g_off : A.v);
+    const Rsrc rd = view((FL & (F_IMAGE | F_EMIT)) ? A.dslot + S.g_off : A.v);
 
     bool valid[CW];
-    int jm[CW];
+    unsigned jm[CW];
     float dx2[CW], ax[CW], shx[CW];
 #pragma unroll
     for (int k = 0; k < CW; ++k) {
         const int j = j0 + k;
         valid[k] = j < S.NX;
-        jm[k] = S.x0 + clampi(j - nb, 0, S.wnx - 1);
+        jm[k] = 4u * unsigned(S.x0 + clampi(j - nb, 0, S.wnx - 1));
         const int ddx = max(max(nb - j, j - (S.NX - 1 - nb)), 0);
         dx2[k] = float(ddx * ddx);
         const float sh = A.hs * dx2[k];
@@ -133,11 +192,13 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     }
     // halo: lane 0 reads the 4 columns left of the strip, lane 1 the 4
     // columns right of it (a zero column block when past the shot's width)
-    const int hcol = lane == 0 ? W.col0 - kHalo : min(W.col0 + SW, P - kHalo);
+    // (byte offset shifted up by the 4 halo columns so that it is never
+    // negative; the row offset of the load is lowered by as much)
+    const unsigned hcol = 4u * unsigned(lane == 0 ? W.col0 : min(W.col0 + SW, P - kHalo) + kHalo);
 
     float q[9][CW];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) ld<CW>(cu + (W.z0 - kHalo + r + kRowsAbove) * P + jl, q[r]);
+    for (int r = 0; r < 8; ++r) bld<CW>(rcur, jl, 4 * (W.z0 - kHalo + r + kRowsAbove) * P, q[r]);
 
     // prefetched loads of one row; PD rows are in flight ahead of the row
     // being computed (a ring of PD statically indexed slots)
@@ -146,17 +207,17 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
         float4 h;
     };
     auto prefetch = [&](int z, Pre &pre) {
-        const int o = (z + kRowsAbove) * P + jl;
-        ld<CW>(cu + o + kHalo * P, pre.q);
-        ld<CW>(pv + o, pre.pv);
-        pre.h = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (lane < 2) pre.h = *reinterpret_cast<const float4 *>(cu + (z + kRowsAbove) * P + hcol);
-        const int mrow = clampi(z - nb, 0, A.nz - 1) * A.nx;
+        const int ro = 4 * (z + kRowsAbove) * P;
+        bld<CW>(rcur, jl, ro + 4 * kHalo * P, pre.q);
+        bld<CW>(rprev, jl, ro, pre.pv);
+        // only lanes 0 and 1 read (and later use) the halo columns
+        if (lane < 2) pre.h = bld4(rcur, hcol, ro - 4 * kHalo);
+        const int vo = 4 * clampi(z - nb, 0, A.nz - 1) * A.nx;
 #pragma unroll
-        for (int k = 0; k < CW; ++k) pre.v[k] = vmod[mrow + jm[k]];
+        for (int k = 0; k < CW; ++k) pre.v[k] = bld1(rv, jm[k], vo);
         if (FL & F_IMAGE) {
-            ld<CW>(db + z * P + jl, pre.d);
-            ld<CW>(gb + z * P + jl, pre.g);
+            bld<CW>(rd, jl, 4 * z * P, pre.d);
+            bld<CW>(rg, jl, 4 * z * P, pre.g);
         }
     };
 
@@ -210,14 +271,13 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
             Dv[k] = cc * lap;
             out[k] = leapfrog(q[4][k], c.pv[k], Dv[k], a, sh);
         }
-        const int o = (z + kRowsAbove) * P + j0;
-        const int og = z * P + j0;
+        const int ro = 4 * (z + kRowsAbove) * P, go = 4 * z * P;
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             if (valid[k]) {
-                pv[o + k] = out[k];
-                if (FL & F_EMIT) db[og + k] = Dv[k];
-                if (FL & F_IMAGE) gb[og + k] = __builtin_fmaf(out[k], c.d[k], c.g[k]);
+                bst1(rprev, js + 4 * k, ro, out[k]);
+                if (FL & F_EMIT) bst1(rd, js + 4 * k, go, Dv[k]);
+                if (FL & F_IMAGE) bst1(rg, js + 4 * k, go, __builtin_fmaf(out[k], c.d[k], c.g[k]));
                 if (FL & F_SAMPLE)
                     if (qi[k] >= 0) A.samp[qi[k]] = out[k];
             }
@@ -228,19 +288,20 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
             for (int k = 0; k < CW; ++k) q[r][k] = q[r + 1][k];
     };
 
-    Pre pa, pb;
-    prefetch(W.z0, pa);
-    if (PD == 2 && W.z0 + 1 < W.z1) prefetch(W.z0 + 1, pb);
-    for (int z = W.z0; z < W.z1; z += PD) {
-        {
-            const Pre c = pa;
-            if (z + PD < W.z1) prefetch(z + PD, pa);
-            do_row(z, c);
-        }
-        if (PD == 2 && z + 1 < W.z1) {
-            const Pre c = pb;
-            if (z + 3 < W.z1) prefetch(z + 3, pb);
-            do_row(z + 1, c);
+    // a ring of PD+1 buffers, statically indexed: the loop is unrolled PD+1
+    // times so that no buffer is copied
+    Pre buf[PD + 1];
+#pragma unroll
+    for (int u = 0; u < PD; ++u)
+        if (W.z0 + u < W.z1) prefetch(W.z0 + u, buf[u]);
+    for (int z = W.z0; z < W.z1; z += PD + 1) {
+#pragma unroll
+        for (int u = 0; u <= PD; ++u) {
+            const int zz = z + u;
+            if (zz < W.z1) {
+                if (zz + PD < W.z1) prefetch(zz + PD, buf[(u + PD) % (PD + 1)]);
+                do_row(zz, buf[u]);
+            }
         }
     }
 }
