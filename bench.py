@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--mem-budget-gb", type=float, default=0.0)
     ap.add_argument("--tiling", default="",
                     help="force the forward/adjoint tiling 'cols,rows,levels[,prefetch]' (default: autotuned)")
+    ap.add_argument("--no-spill-probe", action="store_true",
+                    help="skip the full-width salt-grid measurement of the stencil kernels")
+    ap.add_argument("--spill-nt", type=int, default=60)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
     return ap.parse_args()
@@ -92,6 +95,54 @@ def cpu_baseline(args):
                       f"FP64, {dt:.1f} s"}
 
 
+def spill_probe(nt: int):
+    """The stencil kernels on the 1700 x 350 salt grid with full-width
+    windows (300 shots x 390 x 1740 padded cells, several GB per wavefield):
+    one FWI gradient and one Born demigration of ``nt`` steps, with the
+    per-class kernel times and algorithmic bytes. Its working set is far
+    beyond the 256 MB last-level cache, so the fractions measure HBM."""
+    import numpy as np
+    import torch
+    from paper_2403_17518_amd import ops
+    from synth import configs
+    from synth.problem import cell_updates
+
+    wl = configs.salt_full_width(nshots=300, nt=nt)
+    grid, acq = wl.grid, wl.acq
+    acq.wavelet = acq.wavelet.astype(np.float32)
+    ctx = ops.FwiContext(0)
+    try:
+        v0 = torch.from_numpy(wl.v0.astype(np.float32)).cuda()
+        d_obs = torch.zeros(acq.data_size(grid), device="cuda")
+        dv = torch.from_numpy((wl.v_true - wl.v0).astype(np.float32)).cuda()
+        ctx.fwi_gradient(grid, acq, v0, d_obs, want_misfit=False)   # plan, tuning, buffers
+        torch.cuda.synchronize()
+        ctx.set_profiling(True)
+        acc = {}
+        for call in (lambda: ctx.fwi_gradient(grid, acq, v0, d_obs, want_misfit=False),
+                     lambda: ctx.born_demig(grid, acq, v0, dv)):
+            call()
+            torch.cuda.synchronize()
+            s = ctx.stats()
+            for k in ("ms_fwd", "ms_adj", "ms_born", "bytes_fwd", "bytes_adj", "bytes_born",
+                      "n_fwd", "n_adj", "n_born"):
+                acc[k] = acc.get(k, 0.0) + s[k]
+        ctx.set_profiling(False)
+        out = {"workload": f"salt_full_width: 300 shots x 390 x 1760-pitch padded cells, {nt} steps, "
+                           f"gradient + Born demigration",
+               "cells_per_step": cell_updates(grid, acq) // nt}
+        for cls in ("fwd", "adj", "born"):
+            ms, b = acc["ms_" + cls], acc["bytes_" + cls]
+            if ms > 0:
+                gbs = b / (ms * 1e-3) / 1e9
+                out[cls] = {"avg_launch_us": ms / acc["n_" + cls] * 1e3, "achieved_GBs": gbs,
+                            "frac": gbs / HBM_PEAK_GBS}
+        return out
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -105,6 +156,8 @@ def main():
     from paper_2403_17518_amd import ops
     from synth import configs
     from synth.problem import cell_updates
+
+    spill = None if args.no_spill_probe else spill_probe(args.spill_nt)
 
     wl = configs.layered_600x200(nshots=args.shots, nt=args.nt)
     grid, acq = wl.grid, wl.acq
@@ -210,6 +263,8 @@ def main():
             "kernel_ms": {k: acc[v[0]] / args.steps for k, v in kinds.items()},
         },
     }
+    if spill is not None:
+        out["spill_probe"] = spill
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)

@@ -9,6 +9,8 @@
 * ``salt_1700x350()``   - 350x1700 grid, 10 m, layered + faulted + salt
   1500-4700 m/s, 300 shots of uneven aperture (200-1700 receivers) and record
   length (3-5 s), dt = 1 ms.
+* ``salt_full_width()`` - the salt grid with full-width windows and a short
+  record: a working set far larger than the last-level cache.
 * ``ragged_small()``    - a small ragged case (windows, record lengths,
   co-located receivers) for parity tests.
 
@@ -100,6 +102,19 @@ def salt_1700x350(nshots: int = 300, dt: float = 1e-3,
                        win_x0=np.asarray(wx0), win_nx=np.asarray(wnx),
                        nt=np.asarray(nts), rec_lists=rec_lists)
     return Workload(name, grid, acq, v_true, v0, 15.0)
+
+
+def salt_full_width(nshots: int = 300, nt: int = 100) -> Workload:
+    """The 1700 x 350 salt grid with every shot's window opened to the full
+    width (390 x 1740 padded cells per shot) and the record cut to ``nt``
+    steps: a working set of several GB per wavefield, far beyond the
+    last-level cache, for measuring the stencil kernels against HBM."""
+    wl = salt_1700x350(nshots=nshots)
+    acq, g = wl.acq, wl.grid
+    acq.win_x0 = acq.win_nx = acq.nt = None        # full width, nt steps each
+    acq.wavelet = ricker(15.0, g.dt, nt)
+    grid = Grid(nz=g.nz, nx=g.nx, nb=g.nb, h=g.h, dt=g.dt, nt_max=nt, v_ref=g.v_ref)
+    return Workload("salt_full_width", grid, acq, wl.v_true, wl.v0, 15.0)
 
 
 def salt_848x176(nshots: int = 100) -> Workload:
