@@ -116,6 +116,8 @@ typedef struct {
        advanced per launch */
     int32_t tile_cw[3], tile_rows[3], tile_levels[3];
     int32_t tile_prefetch[3]; /* rows prefetched ahead (one-level kernels) */
+    int64_t graph_launches;   /* time loops replayed from a captured HIP graph */
+    int64_t graph_captures;   /* time loops captured (first run of a loop) */
 } fwi_stats;
 
 /* Create a context on HIP device `device`, enqueueing on `hip_stream`
@@ -145,8 +147,16 @@ int fwi_ctx_set_tiling(fwi_ctx *ctx, int kernel, int cols_per_lane, int rows_per
 /* 1 (default): pick each kernel's tiling by timing candidates once per
  * geometry; 0: use a fixed default tiling. */
 int fwi_ctx_set_autotune(fwi_ctx *ctx, int enable);
+/* 1 (default): every time loop (a forward, adjoint or Born sweep over a
+ * range of steps) is captured once into a HIP graph and replayed on later
+ * calls with the same geometry, tiling and scratch buffers; the loops read
+ * only context-owned memory (the model and perturbation are copied in at
+ * the start of a call), so a graph stays valid across calls whatever
+ * buffers the caller passes. 0: launch every step directly. Results are
+ * identical either way. */
+int fwi_ctx_set_graphs(fwi_ctx *ctx, int enable);
 int fwi_ctx_get_stats(const fwi_ctx *ctx, fwi_stats *out);
-/* Release all scratch memory held by the context. */
+/* Release all scratch memory and captured graphs held by the context. */
 int fwi_ctx_trim(fwi_ctx *ctx);
 const char *fwi_last_error(const fwi_ctx *ctx);
 

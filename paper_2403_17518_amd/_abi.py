@@ -46,7 +46,8 @@ class fwi_stats(C.Structure):
                 ("bytes_fwd", C.c_double), ("bytes_adj", C.c_double),
                 ("bytes_born", C.c_double),
                 ("tile_cw", C.c_int32 * 3), ("tile_rows", C.c_int32 * 3),
-                ("tile_levels", C.c_int32 * 3), ("tile_prefetch", C.c_int32 * 3)]
+                ("tile_levels", C.c_int32 * 3), ("tile_prefetch", C.c_int32 * 3),
+                ("graph_launches", C.c_int64), ("graph_captures", C.c_int64)]
 
     def as_dict(self) -> dict:
         out = {}
@@ -72,6 +73,7 @@ SIGNATURES = {
     "fwi_ctx_get_stats": (C.c_int, [_P, C.POINTER(fwi_stats)]),
     "fwi_ctx_set_tiling": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "fwi_ctx_set_autotune": (C.c_int, [_P, C.c_int]),
+    "fwi_ctx_set_graphs": (C.c_int, [_P, C.c_int]),
     "fwi_ctx_trim": (C.c_int, [_P]),
     "fwi_last_error": (C.c_char_p, [_P]),
     "fwi_forward": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P]),

@@ -84,6 +84,27 @@ struct Tiling {
 
 enum KClass { K_FWD = 0, K_ADJ = 1, K_BORN = 2, K_OTHER = 3 };
 
+// The two newest time levels of a sweep and two spare buffers. A one-level
+// launch overwrites `prev` in place; a two-level launch writes the spares.
+struct Fields {
+    float *prev, *cur, *s0, *s1;
+};
+
+// A time loop captured into a HIP graph: the key serializes every input the
+// loop's launches depend on; `delta` holds the statistics one run adds and
+// `after` the field rotation it leaves.
+struct GraphEntry {
+    std::vector<char> key;
+    hipGraphExec_t exec = nullptr;
+    fwi_stats delta{};
+    Fields after{};
+    uint64_t used = 0;
+    size_t nodes = 0;
+};
+// captured loops kept per context: bounded by their total kernel nodes (a
+// few hundred bytes of host memory each)
+constexpr size_t kGraphNodeBudget = 400000;
+
 }  // namespace
 
 struct fwi_ctx {
@@ -104,6 +125,15 @@ struct fwi_ctx {
     bool autotune = true;
     // scratch
     DevBuf fields, samples, image, dhist, ckpt, partials, misfit, check;
+    // copies of the call's model and perturbation: the time loops read these,
+    // never the caller's buffers, so captured loops stay valid across calls
+    DevBuf model, dmodel;
+    // captured time loops (replayed on the caller's stream; captured on a
+    // private stream, since the legacy default stream cannot be captured)
+    bool graphs = true;
+    hipStream_t cap_stream = nullptr;
+    std::vector<GraphEntry> graph_cache;
+    uint64_t graph_tick = 0;
     float *h_check = nullptr;     // pinned [3]
     double *h_misfit = nullptr;   // pinned [1]
     // profiling events
@@ -157,6 +187,13 @@ void release(DevBuf &b)
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
+}
+
+void clear_graphs(fwi_ctx *c)
+{
+    for (GraphEntry &e : c->graph_cache)
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    c->graph_cache.clear();
 }
 
 template <class T>
@@ -228,6 +265,7 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
     }
     if (c->plan_valid && key == c->plan.key) return FWI_OK;
     c->plan_valid = false;
+    clear_graphs(c);
 
     Plan p;
     p.nz = g->nz;
@@ -410,7 +448,21 @@ int upload_tiling(fwi_ctx *c, Tiling &t)
     return FWI_OK;
 }
 
-int check_model(fwi_ctx *c, const float *v, const char *what)
+// copy of a caller's [nz][nx] array into a context buffer (enqueued)
+int copy_in(fwi_ctx *c, const float *src, DevBuf &dst, const float **out)
+{
+    const Plan &p = c->plan;
+    const size_t bytes = size_t(p.nz) * p.nx * sizeof(float);
+    int rc = ensure(c, dst, bytes);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(dst.p, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+    *out = static_cast<const float *>(dst.p);
+    return FWI_OK;
+}
+
+// Validates the model and copies it into the context; *out is the copy,
+// which every later step of the call reads.
+int check_model(fwi_ctx *c, const float *&v, const char *what)
 {
     const Plan &p = c->plan;
     if (!v) return set_err(c, FWI_EINVAL, "%s is NULL", what);
@@ -424,14 +476,14 @@ int check_model(fwi_ctx *c, const float *v, const char *what)
     const double cfl = double(c->h_check[1]) * p.dt / p.h;
     if (cfl > kCflLimit)
         return set_err(c, FWI_ECFL, "max(%s)*dt/h = %.4f exceeds %.2f", what, cfl, kCflLimit);
-    return FWI_OK;
+    return copy_in(c, v, c->model, &v);
 }
 
-int check_finite_perturbation(fwi_ctx *c, const float *dv)
+// The perturbation may take any sign; it is copied into the context.
+int check_perturbation(fwi_ctx *c, const float *&dv)
 {
-    // dv may be negative; only reject non-finite entries
     if (!dv) return set_err(c, FWI_EINVAL, "dv is NULL");
-    return FWI_OK;
+    return copy_in(c, dv, c->dmodel, &dv);
 }
 
 StepArgs base_args(fwi_ctx *c, const float *v, int cls)
@@ -525,16 +577,116 @@ double step_updates(const Plan &p, int n)
     return u;
 }
 
-// The two newest time levels of a sweep and two spare buffers. A one-level
-// launch overwrites `prev` in place; a two-level launch writes the spares.
-struct Fields {
-    float *prev, *cur, *s0, *s1;
-};
-
 double bytes_per_update(int flags)
 {
     if (flags & F_IMAGE) return kBytesAdj;
     return kBytesFwd + ((flags & F_EMIT) ? kBytesEmit : 0.0);
+}
+
+// ---- captured time loops -----------------------------------------------------
+
+// the counters a time loop adds to the statistics
+fwi_stats loop_delta(const fwi_stats &after, const fwi_stats &before)
+{
+    fwi_stats d{};
+    d.cell_updates = after.cell_updates - before.cell_updates;
+    d.stencil_launches = after.stencil_launches - before.stencil_launches;
+    d.n_fwd = after.n_fwd - before.n_fwd;
+    d.n_adj = after.n_adj - before.n_adj;
+    d.n_born = after.n_born - before.n_born;
+    d.bytes_fwd = after.bytes_fwd - before.bytes_fwd;
+    d.bytes_adj = after.bytes_adj - before.bytes_adj;
+    d.bytes_born = after.bytes_born - before.bytes_born;
+    return d;
+}
+
+void loop_add(fwi_stats &s, const fwi_stats &d)
+{
+    s.cell_updates += d.cell_updates;
+    s.stencil_launches += d.stencil_launches;
+    s.n_fwd += d.n_fwd;
+    s.n_adj += d.n_adj;
+    s.n_born += d.n_born;
+    s.bytes_fwd += d.bytes_fwd;
+    s.bytes_adj += d.bytes_adj;
+    s.bytes_born += d.bytes_born;
+}
+
+// Runs a time loop: `body(f)` enqueues its launches on c->stream and rotates
+// `f`. With graphs on, the first run with a given key is captured on the
+// private stream, instantiated and launched on the caller's stream; later
+// runs with the same key replay the graph. Keys hold every pointer and
+// scalar the launches take, and the cache is cleared whenever the plan or a
+// tiling is rebuilt, so a replay launches exactly what the body would.
+template <class Body>
+int run_loop(fwi_ctx *c, const std::vector<char> &key, Fields &f, Body &&body)
+{
+    if (!c->graphs) return body(f);
+    for (GraphEntry &e : c->graph_cache)
+        if (e.key == key) {
+            HIPCHK(c, hipGraphLaunch(e.exec, c->stream));
+            loop_add(c->stats, e.delta);
+            c->stats.graph_launches += 1;
+            f = e.after;
+            e.used = ++c->graph_tick;
+            return FWI_OK;
+        }
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const fwi_stats before = c->stats;
+    hipStream_t user = c->stream;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    c->stream = c->cap_stream;
+    int rc = body(f);
+    c->stream = user;
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+    if (rc || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc) return rc;
+        return set_err(c, FWI_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+    }
+    size_t nodes = 0;
+    if (hipGraphGetNodes(graph, nullptr, &nodes) == hipSuccess && nodes == 0) {
+        (void)hipGraphDestroy(graph);   // nothing to run (no active shots)
+        return FWI_OK;
+    }
+    GraphEntry e;
+    e.key = key;
+    e.nodes = nodes;
+    const hipError_t ei = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return set_err(c, FWI_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    const hipError_t el = hipGraphLaunch(e.exec, c->stream);
+    if (el != hipSuccess) {
+        (void)hipGraphExecDestroy(e.exec);
+        return set_err(c, FWI_EHIP, "hipGraphLaunch: %s", hipGetErrorString(el));
+    }
+    e.delta = loop_delta(c->stats, before);
+    e.after = f;
+    e.used = ++c->graph_tick;
+    c->stats.graph_captures += 1;
+    c->stats.graph_launches += 1;
+    c->graph_cache.push_back(std::move(e));
+    // least recently used entries go first; a destroyed graph's launches stay
+    // ordered before anything enqueued later
+    size_t total = 0;
+    for (const GraphEntry &g : c->graph_cache) total += g.nodes;
+    while (total > kGraphNodeBudget && c->graph_cache.size() > 1) {
+        size_t lru = 0;
+        for (size_t i = 1; i < c->graph_cache.size(); ++i)
+            if (c->graph_cache[i].used < c->graph_cache[lru].used) lru = i;
+        total -= c->graph_cache[lru].nodes;
+        (void)hipGraphExecDestroy(c->graph_cache[lru].exec);
+        c->graph_cache.erase(c->graph_cache.begin() + lru);
+    }
+    return FWI_OK;
+}
+
+template <class T>
+void key_put(std::vector<char> &k, const T &x)
+{
+    const char *b = reinterpret_cast<const char *>(&x);
+    k.insert(k.end(), b, b + sizeof(T));
 }
 
 // One launch of the forward or adjoint step kernel advancing `levels` (1 or
@@ -572,8 +724,8 @@ int step_launch(fwi_ctx *c, StepArgs a, int cls, int flags, int levels, int acti
 
 // Forward steps lo .. hi-1 (pairs when the tiling runs two levels). D^n goes
 // to slot n - dlo of `dh` (when emit), samples to samp + n*Q (when sample).
-int forward_range(fwi_ctx *c, StepArgs a, int lo, int hi, bool sample, float *samp, bool emit, float *dh, int dlo,
-                  Fields &f)
+int forward_range_direct(fwi_ctx *c, StepArgs a, int lo, int hi, bool sample, float *samp, bool emit, float *dh,
+                         int dlo, Fields &f)
 {
     const Plan &p = c->plan;
     const int64_t gf = p.img_floats;
@@ -596,6 +748,26 @@ int forward_range(fwi_ctx *c, StepArgs a, int lo, int hi, bool sample, float *sa
         n += levels;
     }
     return FWI_OK;
+}
+
+int forward_range(fwi_ctx *c, const StepArgs &a, int lo, int hi, bool sample, float *samp, bool emit, float *dh,
+                  int dlo, Fields &f)
+{
+    if (lo >= hi) return FWI_OK;
+    std::vector<char> key;
+    key_put(key, 'F');
+    key_put(key, a);
+    key_put(key, lo);
+    key_put(key, hi);
+    key_put(key, sample);
+    key_put(key, samp);
+    key_put(key, emit);
+    key_put(key, dh);
+    key_put(key, dlo);
+    key_put(key, f);
+    return run_loop(c, key, f, [&](Fields &ff) {
+        return forward_range_direct(c, a, lo, hi, sample, samp, emit, dh, dlo, ff);
+    });
 }
 
 int other(fwi_ctx *c, hipError_t e, const char *what)
@@ -731,20 +903,34 @@ int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
             if ((rc = ev_end(c))) return rc;
         }
         if ((rc = ev_begin(c, K_ADJ))) return rc;
-        for (int n = hi - 1; n >= lo;) {
-            const int levels = (two && n - 1 >= lo) ? 2 : 1;
-            a.n = n;
-            a.n2 = n - 1;
-            a.dslot = w.Dh + size_t(n - lo) * gf;
-            a.inj = inj + size_t(n) * p.Q;
-            if (levels == 2) {
-                a.dslot2 = w.Dh + size_t(n - 1 - lo) * gf;
-                a.inj2 = inj + size_t(n - 1) * p.Q;
+        std::vector<char> key;
+        key_put(key, 'A');
+        key_put(key, a);
+        key_put(key, lo);
+        key_put(key, hi);
+        key_put(key, w.Dh);
+        key_put(key, inj);
+        key_put(key, fa);
+        rc = run_loop(c, key, fa, [&](Fields &ff) {
+            StepArgs b = a;
+            for (int n = hi - 1; n >= lo;) {
+                const int levels = (two && n - 1 >= lo) ? 2 : 1;
+                b.n = n;
+                b.n2 = n - 1;
+                b.dslot = w.Dh + size_t(n - lo) * gf;
+                b.inj = inj + size_t(n) * p.Q;
+                if (levels == 2) {
+                    b.dslot2 = w.Dh + size_t(n - 1 - lo) * gf;
+                    b.inj2 = inj + size_t(n - 1) * p.Q;
+                }
+                // a pair takes the shots alive at its second (earlier) level
+                const int r = step_launch(c, b, K_ADJ, F_INJECT | F_IMAGE, levels, n - levels + 1, ff);
+                if (r) return r;
+                n -= levels;
             }
-            // a pair takes the shots alive at its second (earlier) level
-            if ((rc = step_launch(c, a, K_ADJ, F_INJECT | F_IMAGE, levels, n - levels + 1, fa))) return rc;
-            n -= levels;
-        }
+            return int(FWI_OK);
+        });
+        if (rc) return rc;
         if ((rc = ev_end(c))) return rc;
     }
     FinalArgs fin{};
@@ -874,6 +1060,7 @@ int ensure_tilings(fwi_ctx *c, const float *v)
         const int want_pd = forced ? c->force_pd[k] : kDefaultPd;
         if (want_cw && want_rows && want_tb) {
             if (t.cw == want_cw && t.rows == want_rows && t.tb == want_tb && t.pd == want_pd) continue;
+            clear_graphs(c);
             build_tiling(p, want_cw, want_rows, want_tb, want_pd, t);
             int rc = upload_tiling(c, t);
             if (rc) return rc;
@@ -882,6 +1069,7 @@ int ensure_tilings(fwi_ctx *c, const float *v)
         }
     }
     if (!need_tune) return FWI_OK;
+    clear_graphs(c);
     // scratch for the trial launches (two levels: four fields, two D slots,
     // two sample rows)
     const int64_t ff = p.field_floats, gf = p.img_floats;
@@ -1018,9 +1206,11 @@ void fwi_ctx_destroy(fwi_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (Tiling &t : c->tile)
         for (DevBuf *b : {&t.d_waves, &t.d_rrows, &t.d_rmap}) release(*b);
-    for (DevBuf *b : {&c->d_shots, &c->d_qnt, &c->d_qrptr, &c->d_qroff, &c->d_wav, &c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt, &c->partials,
-                      &c->misfit, &c->check})
+    for (DevBuf *b : {&c->d_shots, &c->d_qnt, &c->d_qrptr, &c->d_qroff, &c->d_wav, &c->fields, &c->samples,
+                      &c->image, &c->dhist, &c->ckpt, &c->partials, &c->misfit, &c->check, &c->model, &c->dmodel})
         release(*b);
+    clear_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->h_check) (void)hipHostFree(c->h_check);
     if (c->h_misfit) (void)hipHostFree(c->h_misfit);
@@ -1096,8 +1286,21 @@ int fwi_ctx_trim(fwi_ctx *c)
     if (!c) return FWI_EINVAL;
     (void)hipSetDevice(c->device);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return FWI_EHIP;
-    for (DevBuf *b : {&c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt, &c->partials})
+    clear_graphs(c);
+    for (DevBuf *b : {&c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt, &c->partials, &c->model, &c->dmodel})
         release(*b);
+    return FWI_OK;
+}
+
+int fwi_ctx_set_graphs(fwi_ctx *c, int enable)
+{
+    if (!c) return FWI_EINVAL;
+    (void)hipSetDevice(c->device);
+    if (!enable) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return FWI_EHIP;
+        clear_graphs(c);
+    }
+    c->graphs = enable != 0;
     return FWI_OK;
 }
 
@@ -1206,7 +1409,7 @@ int born_demig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *
     if (rc) return rc;
     const Plan &p = c->plan;
     if (!dd && p.data_size > 0) return set_err(c, FWI_EINVAL, "dd is NULL");
-    if ((rc = check_model(c, v0, "v0")) || (rc = check_finite_perturbation(c, dv)) || (rc = prepare(c, v0)))
+    if ((rc = check_model(c, v0, "v0")) || (rc = check_perturbation(c, dv)) || (rc = prepare(c, v0)))
         return rc;
     const int64_t ff = p.field_floats;
     if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) ||
@@ -1219,21 +1422,33 @@ int born_demig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *
     a.dv = dv;
     float *U0 = F, *U1 = F + ff, *D0 = F + 2 * ff, *D1 = F + 3 * ff;
     if ((rc = ev_begin(c, K_BORN))) return rc;
-    for (int n = 0; n < p.nt_max; ++n) {
-        a.n = n;
-        a.nwaves = c->tile[K_BORN].prefix[p.active_slots(n)];
-        a.cur = n % 2 == 0 ? U0 : U1;
-        a.prev = n % 2 == 0 ? U1 : U0;
-        a.cur2 = n % 2 == 0 ? D0 : D1;
-        a.prev2 = n % 2 == 0 ? D1 : D0;
-        a.samp = samp + size_t(n) * p.Q;
-        HIPCHK(c, launch_born_step(a, c->stream));
-        const double upd = step_updates(p, n);
-        c->stats.cell_updates += 2 * upd;
-        c->stats.stencil_launches += 1;
-        c->stats.n_born += 1;
-        c->stats.bytes_born += upd * kBytesBorn;
-    }
+    std::vector<char> key;
+    key_put(key, 'B');
+    key_put(key, a);
+    key_put(key, p.nt_max);
+    key_put(key, F);
+    key_put(key, samp);
+    Fields none{};
+    rc = run_loop(c, key, none, [&](Fields &) {
+        StepArgs b = a;
+        for (int n = 0; n < p.nt_max; ++n) {
+            b.n = n;
+            b.nwaves = c->tile[K_BORN].prefix[p.active_slots(n)];
+            b.cur = n % 2 == 0 ? U0 : U1;
+            b.prev = n % 2 == 0 ? U1 : U0;
+            b.cur2 = n % 2 == 0 ? D0 : D1;
+            b.prev2 = n % 2 == 0 ? D1 : D0;
+            b.samp = samp + size_t(n) * p.Q;
+            HIPCHK(c, launch_born_step(b, c->stream));
+            const double upd = step_updates(p, n);
+            c->stats.cell_updates += 2 * upd;
+            c->stats.stencil_launches += 1;
+            c->stats.n_born += 1;
+            c->stats.bytes_born += upd * kBytesBorn;
+        }
+        return int(FWI_OK);
+    });
+    if (rc) return rc;
     if ((rc = ev_end(c))) return rc;
     TraceArgs t = trace_args(c);
     t.tm_in = samp;

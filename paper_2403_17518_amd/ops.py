@@ -75,6 +75,10 @@ class FwiContext:
     def set_autotune(self, on: bool):
         _check(self.lib, self.ctx, self.lib.fwi_ctx_set_autotune(self.ctx, 1 if on else 0))
 
+    def set_graphs(self, on: bool):
+        """Capture time loops into HIP graphs and replay them (default on)."""
+        _check(self.lib, self.ctx, self.lib.fwi_ctx_set_graphs(self.ctx, 1 if on else 0))
+
     def stats(self) -> dict:
         s = _abi.fwi_stats()
         _check(self.lib, self.ctx, self.lib.fwi_ctx_get_stats(self.ctx, C.byref(s)))
