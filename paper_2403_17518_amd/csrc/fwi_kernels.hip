@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
     constexpr int RW = SW + 2 * kHalo;
     __shared__ float lds[kWavesPerBlock][2][RW];
     const int lane = threadIdx.x & (kLanes - 1);
-    const int wl = threadIdx.x / kLanes;
+    const int wl = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);   // wave-uniform
     const int wid = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wl;
     if (wid >= A.nwaves) return;
     float *row0 = lds[wl][0];                 // level n, row t (+ 4-column halos)
@@ -337,39 +337,43 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
     // loads are unconditional: negative columns read the previous row's zero
     // tail, columns past the shot's width a zero column
     const int jl = j0 < 0 ? j0 : min(j0, P - 2);
+    // byte offsets of the buffer accesses: columns shifted up by 4 (loads of
+    // negative columns, row offsets lowered by as much) so that they are
+    // never negative
+    const unsigned jl4 = 4u * unsigned(jl + kHalo);
+    const unsigned js4 = 4u * unsigned(max(j0, 0));    // stores: owned columns only
     const int own_hi = min(W.col0 + SW - 2 * kHalo, S.NX);
     const bool lvl1_ok = A.n < S.nt, lvl2_ok = A.n2 < S.nt;
     const int64_t base = S.f_off - int64_t(kRowsAbove) * P;
-    const float *un = A.cur + base;
-    const float *um = A.prev + base;
-    float *o1 = A.out1 + base;
-    float *o2 = A.out2 + base;
-    float *gb = (FL & F_IMAGE) ? A.G + S.g_off : nullptr;
-    float *d1b = (FL & (F_IMAGE | F_EMIT)) ? A.dslot + S.g_off : nullptr;
-    float *d2b = (FL & (F_IMAGE | F_EMIT)) ? A.dslot2 + S.g_off : nullptr;
+    const Rsrc run = view(A.cur + base), rum = view(A.prev + base), rv = view(A.v);
+    const Rsrc ro1 = view(A.out1 + base), ro2 = view(A.out2 + base);
+    const Rsrc rg = view((FL & F_IMAGE) ? A.G + S.g_off : A.v);
+    const Rsrc rd1 = view((FL & (F_IMAGE | F_EMIT)) ? A.dslot + S.g_off : A.v);
+    const Rsrc rd2 = view((FL & (F_IMAGE | F_EMIT)) ? A.dslot2 + S.g_off : A.v);
 
     bool inbox[CW], own[CW];
-    int jm[CW];
+    unsigned jm[CW];
     float dx2[CW], ax[CW], shx[CW];
 #pragma unroll
     for (int k = 0; k < CW; ++k) {
         const int j = j0 + k;
         inbox[k] = j >= 0 && j < S.NX;
         own[k] = j >= W.col0 && j < own_hi;
-        jm[k] = S.x0 + clampi(j - nb, 0, S.wnx - 1);
+        jm[k] = 4u * unsigned(S.x0 + clampi(j - nb, 0, S.wnx - 1));
         const int ddx = max(max(nb - j, j - (S.NX - 1 - nb)), 0);
         dx2[k] = float(ddx * ddx);
         const float sh = A.hs * dx2[k];
         ax[k] = sponge_a(sh);
         shx[k] = sh;
     }
-    const int hcol = lane == 0 ? cb - kHalo : min(cb + SW, P - kHalo);
+    // halo columns (byte offset shifted up by 8 columns: cb - 4 >= -8)
+    const unsigned hcol4 = 4u * unsigned((lane == 0 ? cb - kHalo : min(cb + SW, P - kHalo)) + 2 * kHalo);
     if (lane < 2) *reinterpret_cast<float4 *>(&row1[lane == 0 ? 0 : kHalo + SW]) = make_float4(0.f, 0.f, 0.f, 0.f);
 
     const int t0 = W.z0 - kHalo, t1 = W.z1 + kHalo;   // level-1 rows [t0, t1)
     float qa[9][CW], qb[9][CW], cq[5][CW], gq[5][CW];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) ld<CW>(un + (t0 - kHalo + r + kRowsAbove) * P + jl, qa[r]);
+    for (int r = 0; r < 8; ++r) bld<CW>(run, jl4, 4 * ((t0 - kHalo + r + kRowsAbove) * P - kHalo), qa[r]);
 #pragma unroll
     for (int r = 0; r < 9; ++r)
 #pragma unroll
@@ -384,22 +388,22 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 
     float nq[CW], npv[CW], nv[CW], nd1[CW], nd2[CW], ng[CW];
     float4 nh = make_float4(0.f, 0.f, 0.f, 0.f);
+    const unsigned jc4 = 4u * unsigned(min(max(jl, 0), P - CW));
     auto prefetch = [&](int t) {
-        const int o = (t + kRowsAbove) * P + jl;
-        ld<CW>(un + o + kHalo * P, nq);
-        ld<CW>(um + o, npv);
-        if (lane < 2) nh = *reinterpret_cast<const float4 *>(un + (t + kRowsAbove) * P + hcol);
-        const int mrow = clampi(t - nb, 0, A.nz - 1) * A.nx;
+        const int ro = 4 * ((t + kRowsAbove) * P - kHalo);
+        bld<CW>(run, jl4, ro + 4 * kHalo * P, nq);
+        bld<CW>(rum, jl4, ro, npv);
+        if (lane < 2) nh = bld4(run, hcol4, ro - 4 * kHalo);
+        const int vo = 4 * clampi(t - nb, 0, A.nz - 1) * A.nx;
 #pragma unroll
-        for (int k = 0; k < CW; ++k) nv[k] = A.v[mrow + jm[k]];
+        for (int k = 0; k < CW; ++k) nv[k] = bld1(rv, jm[k], vo);
         if (FL & F_IMAGE) {
-            const int jc = min(max(jl, 0), P - CW);
             if (t >= W.z0 && t < W.z1) {
-                ld<CW>(d1b + t * P + jc, nd1);
-                ld<CW>(gb + t * P + jc, ng);
+                bld<CW>(rd1, jc4, 4 * t * P, nd1);
+                bld<CW>(rg, jc4, 4 * t * P, ng);
             }
             const int r2 = t - kHalo;
-            if (r2 >= W.z0 && r2 < W.z1) ld<CW>(d2b + r2 * P + jc, nd2);
+            if (r2 >= W.z0 && r2 < W.z1) bld<CW>(rd2, jc4, 4 * r2 * P, nd2);
         }
     };
     prefetch(t0);
@@ -479,12 +483,12 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         }
         const bool own_row1 = t >= W.z0 && t < W.z1;
         if (own_row1) {
-            const int o = (t + kRowsAbove) * P + j0;
+            const int o = 4 * (t + kRowsAbove) * P;
 #pragma unroll
             for (int k = 0; k < CW; ++k) {
                 if (own[k]) {
-                    o1[o + k] = v1[k];
-                    if (FL & F_EMIT) d1b[t * P + j0 + k] = D1[k];
+                    bst1(ro1, js4 + 4 * k, o, v1[k]);
+                    if (FL & F_EMIT) bst1(rd1, js4 + 4 * k, 4 * t * P, D1[k]);
                     if (FL & F_SAMPLE)
                         if (qi1[k] >= 0) A.samp[qi1[k]] = v1[k];
                 }
@@ -518,7 +522,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         if (r2 >= W.z0) {   // r2 < z1 always holds
             const int ddz2 = max(max(nb - r2, r2 - (NZ - 1 - nb)), 0);
             const float dz2 = float(ddz2 * ddz2);
-            const int o = (r2 + kRowsAbove) * P + j0;
+            const int o = 4 * (r2 + kRowsAbove) * P;
 #pragma unroll
             for (int k = 0; k < CW; ++k) {
                 float lap = lap8(qb, yr, k, A.w1, A.w2, A.w3, A.w4);
@@ -535,12 +539,12 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                 const float D2 = c * lap;
                 const float v2 = leapfrog(qb[4][k], qa[0][k], D2, a, sh);
                 if (own[k]) {
-                    o2[o + k] = v2;
+                    bst1(ro2, js4 + 4 * k, o, v2);
                     if (FL & F_EMIT)
-                        if (lvl2_ok) d2b[r2 * P + j0 + k] = D2;
+                        if (lvl2_ok) bst1(rd2, js4 + 4 * k, 4 * r2 * P, D2);
                     if (FL & F_SAMPLE)
                         if (lvl2_ok && qi2[k] >= 0) A.samp2[qi2[k]] = v2;
-                    if (FL & F_IMAGE) gb[r2 * P + j0 + k] = __builtin_fmaf(v2, cd2[k], gq[0][k]);
+                    if (FL & F_IMAGE) bst1(rg, js4 + 4 * k, 4 * r2 * P, __builtin_fmaf(v2, cd2[k], gq[0][k]));
                 }
             }
         }
