@@ -58,6 +58,7 @@ class FwiOptions:
     seed: int = 2403
     mute_rows: int = 0                    # zero the update in the top rows (both methods)
     max_backtrack: int = 4                # trial-step reductions by 4 in the line search
+    target_error: float | None = None     # stop once the model error is at or below this
 
 
 def lowpass(x: np.ndarray, dt: float, fmax: float, axis: int = -1) -> np.ndarray:
@@ -134,6 +135,9 @@ class FwiRun:
                 rec = self.iteration(acq_b, d_obs, bi, it, fmax)
                 self.history.append(rec)
                 self.log(json.dumps(rec))
+                e = rec["model_error"]
+                if o.target_error is not None and e is not None and e <= o.target_error:
+                    return self.history
         return self.history
 
     def iteration(self, acq, d_obs, band, it, fmax):
@@ -271,6 +275,9 @@ def main(argv=None):
     ap.add_argument("--train-first", type=int, default=500)
     ap.add_argument("--train", type=int, default=200)
     ap.add_argument("--out", default="")
+    ap.add_argument("--plain-log", default="",
+                    help="log of an earlier plain run (JSON lines): the net run stops at its final "
+                         "model error and the time-to-error summary is computed against it")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from synth import configs
@@ -294,9 +301,15 @@ def main(argv=None):
         print(s, flush=True)
         lines.append(s)
 
+    if args.plain_log:
+        with open(args.plain_log) as f:
+            out["plain"] = [r for r in (json.loads(x) for x in f if x.startswith("{"))
+                            if r.get("method") == "plain"]
     for method in (["plain", "net"] if args.method == "both" else [args.method]):
+        target = out["plain"][-1]["model_error"] if method == "net" and "plain" in out else None
         opts = FwiOptions(method=method, bands=bands, iters_per_band=args.iters, net=net_cfg,
-                          train_steps_first=args.train_first, train_steps=args.train)
+                          train_steps_first=args.train_first, train_steps=args.train,
+                          target_error=target)
         run = FwiRun(fctx, grid, acq, wl.v0, opts, v_true=wl.v_true, log=log)
         out[method] = run.run(observe)
         if run.net is not None:
