@@ -16,6 +16,17 @@ a trial step with max|alpha p| = step_frac * v_max (shrunk by 4 until it
 lowers the misfit, at most 4 times), a second at twice that, and the
 minimiser of the parabola through the three misfits.
 
+The paper's comparators (section 3.1): "bb", steepest descent with the
+Barzilai-Borwein step alpha_short = (dx . dg) / (dg . dg) from the last two
+models and gradients, and "lbfgs", the two-loop L-BFGS direction (memory 5).
+Each takes its own step (alpha_short, resp. 1) as the trial of the shared
+backtracking and accepts it when it lowers the misfit; the first iteration
+of a band, which has no pair yet, uses the plain line search. "net" with
+net_iters set runs the hybrid schedule: the network direction for the first
+net_iters iterations of each band, the plain gradient afterwards.
+Model quality is reported as the relative model error and as the SSIM
+(structural similarity, Gaussian window) against the true model.
+
 Multi-scale: the bands low-pass the data with a zero-phase 4th-order
 Butterworth filter (the same filter applied to the wavelet); for synthetic
 inputs the band's observed data are modelled with the filtered wavelet,
@@ -59,6 +70,9 @@ class FwiOptions:
     mute_rows: int = 0                    # zero the update in the top rows (both methods)
     max_backtrack: int = 4                # trial-step reductions by 4 in the line search
     target_error: float | None = None     # stop once the model error is at or below this
+    net_iters: int | None = None          # hybrid: network direction only in the first k iterations
+    lbfgs_memory: int = 5
+    qn_max_frac: float = 0.05             # cap of a BB / L-BFGS trial step: max|dv| <= this * v_max
 
 
 def lowpass(x: np.ndarray, dt: float, fmax: float, axis: int = -1) -> np.ndarray:
@@ -102,6 +116,20 @@ class FwiRun:
         self.net = None
         if opts.method == "net":
             self.net = DeblurNet(fctx, opts.net, seed=opts.seed)
+        self.v_true_np = None if v_true is None else np.asarray(v_true, np.float64)
+        self._reset_pairs()
+
+    def _reset_pairs(self):
+        """Quasi-Newton memory (BB, L-BFGS): cleared at every band."""
+        self.prev_v = None
+        self.prev_g = None
+        self.pairs = []
+
+    def model_ssim(self) -> float | None:
+        if self.v_true_np is None:
+            return None
+        vt = self.v_true_np
+        return ssim(self.v.double().cpu().numpy(), vt, float(vt.max() - vt.min()))
 
     def model_error(self) -> float | None:
         if self.v_true is None:
@@ -131,6 +159,7 @@ class FwiRun:
             if self.net is not None and bi > 0:
                 self.net.reset(o.seed + bi)      # a new band starts from scratch
             self.step_scale = 1.0
+            self._reset_pairs()
             for it in range(o.iters_per_band):
                 rec = self.iteration(acq_b, d_obs, bi, it, fmax)
                 self.history.append(rec)
@@ -155,7 +184,11 @@ class FwiRun:
         p = g
         fallback = None
         train_loss = None
-        if self.net is not None:
+        a_qn = None              # quasi-Newton trial step along p
+        if o.method in ("bb", "lbfgs"):
+            p, a_qn = self._qn_direction(g_phi)
+        use_net = self.net is not None and (o.net_iters is None or it < o.net_iters)
+        if use_net:
             ta = time.perf_counter()
             dd = self.fctx.born_demig(self.grid, acq, self.v, g.contiguous())
             self._count(1)
@@ -175,11 +208,27 @@ class FwiRun:
             fallback = not (float(torch.sum(q * g_phi)) < 0.0 and bool(torch.isfinite(q).all()))
             if not fallback:
                 p = q
-        # line search along p (shared by both methods)
+        # line search along p (shared by all methods)
         ta = time.perf_counter()
         pmax = float(p.abs().max())
         if not pmax > 0:
             return self._record(band, it, fmax, phi, t, 0.0, fallback, train_loss)
+        self.prev_v, self.prev_g = self.v.clone(), g_phi.clone()
+        if a_qn is not None:
+            # the quasi-Newton step, capped and backtracked; accepted as soon
+            # as it lowers the misfit
+            a0 = min(a_qn, o.qn_max_frac * self.v_max / pmax)
+            f1 = self._misfit(acq, self._clip(self.v + a0 * p), d_obs)
+            nb = 0
+            while f1 >= phi and nb < o.max_backtrack:
+                a0 *= 0.25
+                nb += 1
+                f1 = self._misfit(acq, self._clip(self.v + a0 * p), d_obs)
+            alpha = a0 if f1 < phi else 0.0
+            self.v = self._clip(self.v + alpha * p)
+            _sync()
+            t["line_search"] = time.perf_counter() - ta
+            return self._record(band, it, fmax, phi, t, alpha * pmax, fallback, train_loss)
         # trial step, shrunk by 4 while it does not reduce the misfit
         # (at most `max_backtrack` times), then a second point at twice it
         a0 = self.step_scale * o.step_frac * self.v_max / pmax
@@ -203,12 +252,30 @@ class FwiRun:
         t["line_search"] = time.perf_counter() - ta
         return self._record(band, it, fmax, phi, t, alpha * pmax, fallback, train_loss)
 
+    def _qn_direction(self, g_phi):
+        """Search direction and trial step of the BB or L-BFGS iteration."""
+        o = self.opts
+        if self.prev_v is not None:
+            s_ = (self.v - self.prev_v).double()
+            y_ = (g_phi - self.prev_g).double()
+            sy = float(torch.sum(s_ * y_))
+            if sy > 1e-12 * float(torch.linalg.norm(s_)) * float(torch.linalg.norm(y_)):
+                self.pairs.append((s_, y_))
+                self.pairs = self.pairs[-(o.lbfgs_memory if o.method == "lbfgs" else 1):]
+        if not self.pairs:
+            return -g_phi, None            # no curvature pair yet: plain line search
+        if o.method == "bb":
+            a = bb_short(*self.pairs[-1])
+            return -g_phi, a
+        d = -lbfgs_two_loop(g_phi, self.pairs)
+        return d.float().contiguous(), 1.0
+
     def _clip(self, v):
         return torch.clamp(v, self.opts.v_min, self.v_max).contiguous()
 
     def _record(self, band, it, fmax, phi, t, step, fallback, train_loss):
         return {"method": self.opts.method, "band": band, "fmax": fmax, "iter": it, "misfit": phi,
-                "model_error": self.model_error(), "solves": self.solves,
+                "model_error": self.model_error(), "ssim": self.model_ssim(), "solves": self.solves,
                 "stencil_passes": round(self.passes, 3), "wall_s": time.perf_counter() - self.t0,
                 "phase_s": {k: round(v, 4) for k, v in t.items()}, "max_dv": step,
                 "fallback": fallback, "train_loss": train_loss}
@@ -249,6 +316,52 @@ def parabola_step(phi0: float, f1: float, f2: float, a0: float) -> float:
     return 2 * a0 if f2 < f1 else a0
 
 
+def bb_short(dx: torch.Tensor, dg: torch.Tensor) -> float | None:
+    """Barzilai-Borwein step alpha_short = (dx . dg) / (dg . dg) (the short
+    step of the two-point method, eq. 17); None when it is not positive."""
+    num = float(torch.sum(dx.double() * dg.double()))
+    den = float(torch.sum(dg.double() * dg.double()))
+    if not (den > 0.0) or not (num > 0.0):
+        return None
+    return num / den
+
+
+def lbfgs_two_loop(g: torch.Tensor, pairs: list) -> torch.Tensor:
+    """H g for the L-BFGS inverse-Hessian approximation built from the
+    (s, y) pairs, oldest first (Liu and Nocedal's two-loop recursion, with
+    H0 = (s.y)/(y.y) I from the newest pair)."""
+    q = g.double().clone()
+    alphas = []
+    for s_, y_ in reversed(pairs):
+        rho = 1.0 / float(torch.sum(y_ * s_))
+        a = rho * float(torch.sum(s_ * q))
+        alphas.append((a, rho))
+        q -= a * y_
+    s_, y_ = pairs[-1]
+    q *= float(torch.sum(s_ * y_)) / float(torch.sum(y_ * y_))
+    for (s_, y_), (a, rho) in zip(pairs, reversed(alphas)):
+        b = rho * float(torch.sum(y_ * q))
+        q += (a - b) * s_
+    return q
+
+
+def ssim(x: np.ndarray, y: np.ndarray, data_range: float, sigma: float = 1.5) -> float:
+    """Mean structural similarity of two images (Wang et al. 2004): local
+    means, variances and covariance under a Gaussian window (sigma 1.5,
+    truncated at 3.5 sigma), K1 = 0.01, K2 = 0.03."""
+    from scipy.ndimage import gaussian_filter
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    c1, c2 = (0.01 * data_range) ** 2, (0.03 * data_range) ** 2
+    f = lambda a: gaussian_filter(a, sigma, mode="reflect", truncate=3.5)
+    mx, my = f(x), f(y)
+    vx = f(x * x) - mx * mx
+    vy = f(y * y) - my * my
+    cxy = f(x * y) - mx * my
+    m = ((2 * mx * my + c1) * (2 * cxy + c2)) / ((mx * mx + my * my + c1) * (vx + vy + c2))
+    return float(m.mean())
+
+
 def time_to_error(plain: list, net: list) -> dict:
     """Iterations, solves and wall time the network method needs to reach
     the plain method's final model error."""
@@ -268,7 +381,10 @@ def time_to_error(plain: list, net: list) -> dict:
 def main(argv=None):
     ap = argparse.ArgumentParser(description="plain vs network-preconditioned FWI on a seeded workload")
     ap.add_argument("--workload", default="salt_848x176")
-    ap.add_argument("--method", default="both", choices=["plain", "net", "both"])
+    ap.add_argument("--method", default="both", choices=["plain", "net", "bb", "lbfgs", "both", "all"],
+                    help="both = plain then net; all = plain, bb, lbfgs, net")
+    ap.add_argument("--net-iters", type=int, default=0,
+                    help="hybrid schedule: network direction only in a band's first k iterations")
     ap.add_argument("--iters", type=int, default=20, help="iterations per band")
     ap.add_argument("--bands", default="3,8,15")
     ap.add_argument("--shots", type=int, default=0)
@@ -305,11 +421,14 @@ def main(argv=None):
         with open(args.plain_log) as f:
             out["plain"] = [r for r in (json.loads(x) for x in f if x.startswith("{"))
                             if r.get("method") == "plain"]
-    for method in (["plain", "net"] if args.method == "both" else [args.method]):
+    methods = {"both": ["plain", "net"], "all": ["plain", "bb", "lbfgs", "net"]}.get(args.method, [args.method])
+    for method in methods:
         target = out["plain"][-1]["model_error"] if method == "net" and "plain" in out else None
+        if args.method == "all":
+            target = None          # full curves for the comparison
         opts = FwiOptions(method=method, bands=bands, iters_per_band=args.iters, net=net_cfg,
                           train_steps_first=args.train_first, train_steps=args.train,
-                          target_error=target)
+                          target_error=target, net_iters=args.net_iters or None)
         run = FwiRun(fctx, grid, acq, wl.v0, opts, v_true=wl.v_true, log=log)
         out[method] = run.run(observe)
         if run.net is not None:

@@ -41,3 +41,64 @@ def test_time_to_error():
     net = [{"model_error": e, "wall_s": 2 * i, "solves": 8 * i} for i, e in enumerate([0.95, 0.79, 0.6])]
     s = D.time_to_error(plain, net)
     assert s["target_model_error"] == 0.8 and s["net_iters"] == 2 and s["net_wall_s"] == 2
+
+
+def test_bb_short_step_on_quadratics():
+    import torch
+    # 1-D quadratic f = a x^2 / 2: the two-point step is exactly 1/a
+    a = 3.7
+    dx = torch.tensor([0.4], dtype=torch.float64)
+    assert abs(D.bb_short(dx, a * dx) - 1 / a) < 1e-12
+    # diagonal quadratic: alpha_short lies between 1/max(a) and 1/min(a)
+    A = torch.tensor([1.0, 2.0, 5.0], dtype=torch.float64)
+    dx = torch.tensor([0.3, -0.2, 0.1], dtype=torch.float64)
+    al = D.bb_short(dx, A * dx)
+    assert 1 / 5.0 <= al <= 1.0
+    # negative curvature: no step
+    assert D.bb_short(dx, -dx) is None
+
+
+def test_lbfgs_two_loop_secant_and_quadratic():
+    import torch
+    rng = np.random.default_rng(0)
+    n = 6
+    M = rng.standard_normal((n, n))
+    A = torch.tensor(M @ M.T + n * np.eye(n))
+    # the newest pair satisfies the secant equation H y = s
+    s1 = torch.tensor(rng.standard_normal(n))
+    s2 = torch.tensor(rng.standard_normal(n))
+    pairs = [(s1, A @ s1), (s2, A @ s2)]
+    assert torch.allclose(D.lbfgs_two_loop(A @ s2, pairs), s2, atol=1e-10)
+    # one pair of a multiple of the identity gives its inverse exactly
+    c = 2.5
+    g = torch.tensor(rng.standard_normal(n))
+    assert torch.allclose(D.lbfgs_two_loop(g, [(s1, c * s1)]), g / c, atol=1e-12)
+    # BFGS on a quadratic with exact line searches: after n steps H = A^-1
+    x = torch.tensor(rng.standard_normal(n))
+    b = torch.tensor(rng.standard_normal(n))
+    pairs = []
+    gr = A @ x - b
+    for _ in range(n):
+        d = -(D.lbfgs_two_loop(gr, pairs) if pairs else gr)
+        t = -float(gr @ d) / float(d @ A @ d)      # exact minimiser along d
+        xn = x + t * d
+        gn = A @ xn - b
+        pairs.append((xn - x, gn - gr))
+        x, gr = xn, gn
+    assert torch.allclose(x, torch.linalg.solve(A, b), atol=1e-8)
+
+
+def test_ssim_properties():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((40, 60)).cumsum(0).cumsum(1)
+    r = float(x.max() - x.min())
+    assert abs(D.ssim(x, x, r) - 1.0) < 1e-12
+    assert abs(D.ssim(x, x + 0.0, r) - D.ssim(x, x, r)) < 1e-15
+    y = x + 0.05 * r * rng.standard_normal(x.shape)
+    assert abs(D.ssim(x, y, r) - D.ssim(y, x, r)) < 1e-12         # symmetric
+    z = x + 0.2 * r * rng.standard_normal(x.shape)
+    assert D.ssim(x, z, r) < D.ssim(x, y, r) < 1.0                 # more noise, lower
+    # constant images: the luminance term alone, in closed form
+    c1 = (0.01 * 10.0) ** 2
+    v = D.ssim(np.full((20, 20), 3.0), np.full((20, 20), 5.0), 10.0)
+    assert abs(v - (2 * 15 + c1) / (9 + 25 + c1)) < 1e-12
