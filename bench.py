@@ -20,6 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0      # dense bf16 matrix-core peak of MI355X
 
 # HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a plain 1 GiB copy;
@@ -40,8 +41,8 @@ def kernels_sha1() -> str:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--shots", type=int, default=64)
     ap.add_argument("--nt", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -50,6 +51,9 @@ def parse():
     ap.add_argument("--mem-budget-gb", type=float, default=0.0)
     ap.add_argument("--tiling", default="",
                     help="force the forward/adjoint tiling 'cols,rows,levels[,prefetch]' (default: autotuned)")
+    ap.add_argument("--no-deblur", action="store_true", help="skip the network timing")
+    ap.add_argument("--deblur-only", action="store_true",
+                    help="run only the network timing (for profiling its kernels)")
     ap.add_argument("--no-spill-probe", action="store_true",
                     help="skip the full-width salt-grid measurement of the stencil kernels")
     ap.add_argument("--spill-nt", type=int, default=60)
@@ -143,6 +147,59 @@ def spill_probe(nt: int):
         torch.cuda.empty_cache()
 
 
+def deblur_flops(H: int, W: int, depth: int = 3, base: int = 32) -> float:
+    """Flops (2 per multiply-add) of one forward pass of the deblurring UNet on
+    an H x W image: 3x3 convolutions at every level, 2x2 stride-2 transposed
+    convolutions, the 1x1 output convolution."""
+    C = [base << l for l in range(depth + 1)]
+    hw = lambda l: (H >> l) * (W >> l)
+    f = 2 * hw(0) * 9 * (C[0] * 1 + C[0] * C[0]) + 2 * hw(0) * C[0]
+    for l in range(1, depth + 1):
+        f += 2 * hw(l) * 9 * (C[l] * C[l - 1] + C[l] * C[l])
+    for l in range(depth):
+        f += 2 * hw(l) * (C[l + 1] * C[l] + 9 * (C[l] * 2 * C[l] + C[l] * C[l]))
+    return float(f)
+
+
+def deblur_timing(train_steps: int = 40, applies: int = 10) -> dict:
+    """Training (Adam steps) and inference of the deblurring network at the
+    208 x 608 size of the 600 x 200 workload; a training step is counted as
+    three forward passes (forward, data gradient, weight gradient)."""
+    import torch
+    from paper_2403_17518_amd import ops
+    from paper_2403_17518_amd.deblur import DeblurConfig, DeblurNet
+    ctx = ops.FwiContext(0)
+    net = DeblurNet(ctx, DeblurConfig())
+    try:
+        g = torch.Generator(device="cuda").manual_seed(2403)
+        x = torch.randn(200, 600, device="cuda", generator=g)
+        y = torch.randn(200, 600, device="cuda", generator=g)
+        net.deblur_train(x, y, 3, 1e-3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net.deblur_train(x, y, train_steps, 1e-3)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(applies):
+            net.deblur_apply(x)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fwd = deblur_flops(208, 608)
+        tr = (t1 - t0) / train_steps
+        ap = (t2 - t1) / applies
+        out = {"workload": "UNet depth 3, widths 32-64-128-256, ReLU, 208 x 608, bf16 MFMA, FP32 accumulation",
+               "train_ms_per_step": tr * 1e3, "train_TFLOPs": 3 * fwd / tr / 1e12,
+               "apply_ms": ap * 1e3, "apply_TFLOPs": fwd / ap / 1e12, "forward_GFLOP": fwd / 1e9,
+               "peak_TFLOPs": BF16_PEAK_TFLOPS}
+        out["train_frac"] = out["train_TFLOPs"] / BF16_PEAK_TFLOPS
+        print(f"train {train_steps} steps: {tr * 1e3:.2f} ms/step, {out['train_TFLOPs']:.1f} TFLOP/s; "
+              f"apply {ap * 1e3:.2f} ms, {out['apply_TFLOPs']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+        return out
+    finally:
+        net.close()
+        ctx.close()
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -151,6 +208,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.deblur_only:
+        print(json.dumps(deblur_timing(train_steps=100)), flush=True)
+        return
     import numpy as np
     import torch
     from paper_2403_17518_amd import ops
@@ -265,6 +325,8 @@ def main():
     }
     if spill is not None:
         out["spill_probe"] = spill
+    if not args.no_deblur:
+        out["deblur"] = deblur_timing()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)

@@ -371,7 +371,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
     if (lane < 2) *reinterpret_cast<float4 *>(&row1[lane == 0 ? 0 : kHalo + SW]) = make_float4(0.f, 0.f, 0.f, 0.f);
 
     const int t0 = W.z0 - kHalo, t1 = W.z1 + kHalo;   // level-1 rows [t0, t1)
-    float qa[9][CW], qb[9][CW], cq[5][CW], gq[5][CW];
+    float qa[9][CW], qb[9][CW], cq[5][CW];
 #pragma unroll
     for (int r = 0; r < 8; ++r) bld<CW>(run, jl4, 4 * ((t0 - kHalo + r + kRowsAbove) * P - kHalo), qa[r]);
 #pragma unroll
@@ -381,10 +381,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 #pragma unroll
     for (int r = 0; r < 5; ++r)
 #pragma unroll
-        for (int k = 0; k < CW; ++k) {
-            cq[r][k] = 0.f;
-            gq[r][k] = 0.f;
-        }
+        for (int k = 0; k < CW; ++k) cq[r][k] = 0.f;
 
     float nq[CW], npv[CW], nv[CW], nd1[CW], nd2[CW], ng[CW];
     float4 nh = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -398,12 +395,13 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 #pragma unroll
         for (int k = 0; k < CW; ++k) nv[k] = bld1(rv, jm[k], vo);
         if (FL & F_IMAGE) {
-            if (t >= W.z0 && t < W.z1) {
-                bld<CW>(rd1, jc4, 4 * t * P, nd1);
-                bld<CW>(rg, jc4, 4 * t * P, ng);
-            }
+            // the imaging terms of both levels are added at level 2 (row t-4)
             const int r2 = t - kHalo;
-            if (r2 >= W.z0 && r2 < W.z1) bld<CW>(rd2, jc4, 4 * r2 * P, nd2);
+            if (r2 >= W.z0 && r2 < W.z1) {
+                bld<CW>(rd1, jc4, 4 * r2 * P, nd1);
+                bld<CW>(rd2, jc4, 4 * r2 * P, nd2);
+                bld<CW>(rg, jc4, 4 * r2 * P, ng);
+            }
         }
     };
     prefetch(t0);
@@ -492,8 +490,6 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                     if (FL & F_SAMPLE)
                         if (qi1[k] >= 0) A.samp[qi1[k]] = v1[k];
                 }
-                // G after level 1 (the same fused multiply-add as a one-level step)
-                if (FL & F_IMAGE) gq[4][k] = lvl1_ok ? __builtin_fmaf(v1[k], cd1[k], cg[k]) : cg[k];
             }
         }
 
@@ -544,7 +540,12 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                         if (lvl2_ok) bst1(rd2, js4 + 4 * k, 4 * r2 * P, D2);
                     if (FL & F_SAMPLE)
                         if (lvl2_ok && qi2[k] >= 0) A.samp2[qi2[k]] = v2;
-                    if (FL & F_IMAGE) bst1(rg, js4 + 4 * k, 4 * r2 * P, __builtin_fmaf(v2, cd2[k], gq[0][k]));
+                    // G after both levels: the fused multiply-adds of two one-level
+                    // steps, in their order (qb[4] is the level-1 value of this row)
+                    if (FL & F_IMAGE) {
+                        const float g1 = lvl1_ok ? __builtin_fmaf(qb[4][k], cd1[k], cg[k]) : cg[k];
+                        bst1(rg, js4 + 4 * k, 4 * r2 * P, __builtin_fmaf(v2, cd2[k], g1));
+                    }
                 }
             }
         }
@@ -558,10 +559,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int k = 0; k < CW; ++k) {
-                cq[r][k] = cq[r + 1][k];
-                gq[r][k] = gq[r + 1][k];
-            }
+            for (int k = 0; k < CW; ++k) cq[r][k] = cq[r + 1][k];
     }
 }
 
@@ -577,7 +575,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
     constexpr int RW = SW + 2 * kHalo;
     __shared__ float lds[kWavesPerBlock][2][RW];
     const int lane = threadIdx.x & (kLanes - 1);
-    const int wl = threadIdx.x / kLanes;
+    const int wl = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);   // wave-uniform
     const int wid = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wl;
     if (wid >= A.nwaves) return;
     float *row = lds[wl][0];
@@ -587,52 +585,53 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
     const int P = S.P;
     const int nb = A.nb;
     const int j0 = W.col0 + CW * lane;
-    const int jl = min(j0, P - 2);
+    const unsigned jl = 4u * unsigned(min(j0, P - 2));   // byte offsets
+    const unsigned js = 4u * unsigned(j0);
     const int64_t base = S.f_off - int64_t(kRowsAbove) * P;
-    const float *cu = A.cur + base;
-    float *pv = A.prev + base;
-    const float *cd = A.cur2 + base;
-    float *pd = A.prev2 + base;
+    const Rsrc rcu = view(A.cur + base), rpv = view(A.prev + base);
+    const Rsrc rcd = view(A.cur2 + base), rpd = view(A.prev2 + base);
+    const Rsrc rv = view(A.v), rdv = view(A.dv);
 
     bool valid[CW];
-    int jm[CW];
+    unsigned jm[CW];
     float dx2[CW], ax[CW], shx[CW];
 #pragma unroll
     for (int k = 0; k < CW; ++k) {
         const int j = j0 + k;
         valid[k] = j < S.NX;
-        jm[k] = S.x0 + clampi(j - nb, 0, S.wnx - 1);
+        jm[k] = 4u * unsigned(S.x0 + clampi(j - nb, 0, S.wnx - 1));
         const int ddx = max(max(nb - j, j - (S.NX - 1 - nb)), 0);
         dx2[k] = float(ddx * ddx);
         const float sh = A.hs * dx2[k];
         ax[k] = sponge_a(sh);
         shx[k] = sh;
     }
-    const int hcol = lane == 0 ? W.col0 - kHalo : min(W.col0 + SW, P - kHalo);
+    // halo columns (byte offset shifted up by 4 columns, row offset lowered)
+    const unsigned hcol = 4u * unsigned(lane == 0 ? W.col0 : min(W.col0 + SW, P - kHalo) + kHalo);
 
     float q[9][CW], r[9][CW];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        ld<CW>(cu + (W.z0 - kHalo + k + kRowsAbove) * P + jl, q[k]);
-        ld<CW>(cd + (W.z0 - kHalo + k + kRowsAbove) * P + jl, r[k]);
+        bld<CW>(rcu, jl, 4 * (W.z0 - kHalo + k + kRowsAbove) * P, q[k]);
+        bld<CW>(rcd, jl, 4 * (W.z0 - kHalo + k + kRowsAbove) * P, r[k]);
     }
     float nq[CW], nr[CW], npv[CW], npd[CW], nv[CW], ndv[CW];
     float4 nh = make_float4(0.f, 0.f, 0.f, 0.f), nhd = nh;
     auto prefetch = [&](int z) {
-        const int o = (z + kRowsAbove) * P + jl;
-        ld<CW>(cu + o + kHalo * P, nq);
-        ld<CW>(cd + o + kHalo * P, nr);
-        ld<CW>(pv + o, npv);
-        ld<CW>(pd + o, npd);
+        const int ro = 4 * (z + kRowsAbove) * P;
+        bld<CW>(rcu, jl, ro + 4 * kHalo * P, nq);
+        bld<CW>(rcd, jl, ro + 4 * kHalo * P, nr);
+        bld<CW>(rpv, jl, ro, npv);
+        bld<CW>(rpd, jl, ro, npd);
         if (lane < 2) {
-            nh = *reinterpret_cast<const float4 *>(cu + (z + kRowsAbove) * P + hcol);
-            nhd = *reinterpret_cast<const float4 *>(cd + (z + kRowsAbove) * P + hcol);
+            nh = bld4(rcu, hcol, ro - 4 * kHalo);
+            nhd = bld4(rcd, hcol, ro - 4 * kHalo);
         }
-        const int mrow = clampi(z - nb, 0, A.nz - 1) * A.nx;
+        const int vo = 4 * clampi(z - nb, 0, A.nz - 1) * A.nx;
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
-            nv[k] = A.v[mrow + jm[k]];
-            ndv[k] = A.dv[mrow + jm[k]];
+            nv[k] = bld1(rv, jm[k], vo);
+            ndv[k] = bld1(rdv, jm[k], vo);
         }
     };
     prefetch(W.z0);
@@ -704,12 +703,12 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
             ou[k] = leapfrog(q[4][k], cpv[k], c * lap, a, sh);
             od[k] = leapfrog(r[4][k], cpd[k], __builtin_fmaf(cr, lap, c * lapd), a, sh);
         }
-        const int o = (z + kRowsAbove) * P + j0;
+        const int o = 4 * (z + kRowsAbove) * P;
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             if (valid[k]) {
-                pv[o + k] = ou[k];
-                pd[o + k] = od[k];
+                bst1(rpv, js + 4 * k, o, ou[k]);
+                bst1(rpd, js + 4 * k, o, od[k]);
                 if (qi[k] >= 0) A.samp[qi[k]] = od[k];
             }
         }
