@@ -27,7 +27,9 @@ BF16_PEAK_TFLOPS = 2500.0      # dense bf16 matrix-core peak of MI355X
 # see profiles/stencil_kernels_layered_600x200_hbm_counters.md). Valid only
 # for the kernel source it was measured on: reported as null otherwise.
 MEASURED_TRAFFIC = {
-    "stencil_adj": {"bytes": 265.5e6, "kernels_sha1": "6422529dde323a5a46cbd29c7b0d9246df9b28c5"},
+    # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 per launch of the autotuned adjoint
+    # kernel (k_step<INJECT|IMAGE, 1 column per lane, 2 rows prefetched>)
+    "stencil_adj": {"bytes": 276.4e6, "kernels_sha1": "bcac09e2073d7dfcd6b98fcb4754d5b558b9a65f"},
 }
 
 

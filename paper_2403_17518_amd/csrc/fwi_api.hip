@@ -583,6 +583,16 @@ double bytes_per_update(int flags)
     return kBytesFwd + ((flags & F_EMIT) ? kBytesEmit : 0.0);
 }
 
+// Algorithmic bytes per cell of a two-level launch (both levels): the
+// fields of levels n and n-1 and the model in, levels n+1 and n+2 out (20 B);
+// each level's D adds 4 B (written, or read by the adjoint), and the image
+// is read and written once for both levels.
+double bytes_two_levels(int flags)
+{
+    if (flags & F_IMAGE) return 20.0 + 2 * kBytesEmit + 8.0;
+    return 20.0 + ((flags & F_EMIT) ? 2 * kBytesEmit : 0.0);
+}
+
 // ---- captured time loops -----------------------------------------------------
 
 // the counters a time loop adds to the statistics
@@ -709,15 +719,17 @@ int step_launch(fwi_ctx *c, StepArgs a, int cls, int flags, int levels, int acti
         HIPCHK(c, launch_step(flags, a, c->stream));
         std::swap(f.prev, f.cur);
     }
-    const double upd = levels * step_updates(p, active_n);
+    const double cells = step_updates(p, active_n);
+    const double upd = levels * cells;
+    const double bytes = levels == 2 ? cells * bytes_two_levels(flags) : cells * bytes_per_update(flags);
     c->stats.cell_updates += upd;
     c->stats.stencil_launches += 1;
     if (cls == K_ADJ) {
         c->stats.n_adj += 1;
-        c->stats.bytes_adj += upd * bytes_per_update(flags);
+        c->stats.bytes_adj += bytes;
     } else {
         c->stats.n_fwd += 1;
-        c->stats.bytes_fwd += upd * bytes_per_update(flags);
+        c->stats.bytes_fwd += bytes;
     }
     return FWI_OK;
 }
