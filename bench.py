@@ -103,10 +103,12 @@ def cpu_baseline(args):
 
 def spill_probe(nt: int):
     """The stencil kernels on the 1700 x 350 salt grid with full-width
-    windows (300 shots x 390 x 1740 padded cells, several GB per wavefield):
-    one FWI gradient and one Born demigration of ``nt`` steps, with the
-    per-class kernel times and algorithmic bytes. Its working set is far
-    beyond the 256 MB last-level cache, so the fractions measure HBM."""
+    windows (300 shots x 390 x 1740 padded cells, 0.8 GB per wavefield): one
+    FWI gradient and one Born demigration of ``nt`` steps, first with the
+    autotuned tilings, then with one time level per launch forced. Its working
+    set is far beyond the 256 MB last-level cache, so the fractions measure
+    HBM. A two-level launch moves fewer algorithmic bytes per cell-update, so
+    its fraction is lower at a higher update rate; both are reported."""
     import numpy as np
     import torch
     from paper_2403_17518_amd import ops
@@ -116,33 +118,49 @@ def spill_probe(nt: int):
     wl = configs.salt_full_width(nshots=300, nt=nt)
     grid, acq = wl.grid, wl.acq
     acq.wavelet = acq.wavelet.astype(np.float32)
+    cells = cell_updates(grid, acq) // nt
     ctx = ops.FwiContext(0)
     try:
         v0 = torch.from_numpy(wl.v0.astype(np.float32)).cuda()
         d_obs = torch.zeros(acq.data_size(grid), device="cuda")
         dv = torch.from_numpy((wl.v_true - wl.v0).astype(np.float32)).cuda()
-        ctx.fwi_gradient(grid, acq, v0, d_obs, want_misfit=False)   # plan, tuning, buffers
-        torch.cuda.synchronize()
-        ctx.set_profiling(True)
-        acc = {}
-        for call in (lambda: ctx.fwi_gradient(grid, acq, v0, d_obs, want_misfit=False),
-                     lambda: ctx.born_demig(grid, acq, v0, dv)):
-            call()
+
+        def measure():
+            ctx.fwi_gradient(grid, acq, v0, d_obs, want_misfit=False)   # plan, tuning, buffers
+            ctx.born_demig(grid, acq, v0, dv)
             torch.cuda.synchronize()
-            s = ctx.stats()
-            for k in ("ms_fwd", "ms_adj", "ms_born", "bytes_fwd", "bytes_adj", "bytes_born",
-                      "n_fwd", "n_adj", "n_born"):
-                acc[k] = acc.get(k, 0.0) + s[k]
-        ctx.set_profiling(False)
-        out = {"workload": f"salt_full_width: 300 shots x 390 x 1760-pitch padded cells, {nt} steps, "
-                           f"gradient + Born demigration",
-               "cells_per_step": cell_updates(grid, acq) // nt}
-        for cls in ("fwd", "adj", "born"):
-            ms, b = acc["ms_" + cls], acc["bytes_" + cls]
-            if ms > 0:
+            ctx.set_profiling(True)
+            acc, tiles = {}, None
+            for call in (lambda: ctx.fwi_gradient(grid, acq, v0, d_obs, want_misfit=False),
+                         lambda: ctx.born_demig(grid, acq, v0, dv)):
+                call()
+                torch.cuda.synchronize()
+                st = ctx.stats()
+                tiles = tiles or st
+                for k in ("ms_fwd", "ms_adj", "ms_born", "bytes_fwd", "bytes_adj", "bytes_born",
+                          "n_fwd", "n_adj", "n_born"):
+                    acc[k] = acc.get(k, 0.0) + st[k]
+            ctx.set_profiling(False)
+            res = {}
+            for i, cls in enumerate(("fwd", "adj", "born")):
+                ms, b, n = acc["ms_" + cls], acc["bytes_" + cls], acc["n_" + cls]
+                if ms <= 0:
+                    continue
+                levels = tiles["tile_levels"][i] or 1
                 gbs = b / (ms * 1e-3) / 1e9
-                out[cls] = {"avg_launch_us": ms / acc["n_" + cls] * 1e3, "achieved_GBs": gbs,
-                            "frac": gbs / HBM_PEAK_GBS}
+                res[cls] = {"tiling_cols_rows_levels_prefetch": [tiles["tile_cw"][i], tiles["tile_rows"][i],
+                                                                 levels, tiles["tile_prefetch"][i]],
+                            "us_per_level": ms / (n * levels) * 1e3,
+                            "cell_updates_per_s": cells * (2 if cls == "born" else 1) / (ms / (n * levels) * 1e-3),
+                            "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+            return res
+
+        out = {"workload": f"salt_full_width: 300 shots x 390 x 1740 padded cells (pitch 1760), {nt} steps, "
+                           f"gradient + Born demigration", "cells_per_step": cells,
+               "autotuned": measure()}
+        ctx.set_tiling(0, 1, 32, 1, 1)
+        ctx.set_tiling(1, 1, 32, 1, 1)
+        out["one_level"] = measure()
         return out
     finally:
         ctx.close()
