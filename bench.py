@@ -181,7 +181,8 @@ def deblur_flops(H: int, W: int, depth: int = 3, base: int = 32) -> float:
     return float(f)
 
 
-def deblur_timing(train_steps: int = 40, applies: int = 10) -> dict:
+def deblur_timing(train_steps: int = 40, applies: int = 10, depth: int = 3, base: int = 32,
+                  slope: float = 0.0) -> dict:
     """Training (Adam steps) and inference of the deblurring network at the
     208 x 608 size of the 600 x 200 workload; a training step is counted as
     three forward passes (forward, data gradient, weight gradient)."""
@@ -189,7 +190,7 @@ def deblur_timing(train_steps: int = 40, applies: int = 10) -> dict:
     from paper_2403_17518_amd import ops
     from paper_2403_17518_amd.deblur import DeblurConfig, DeblurNet
     ctx = ops.FwiContext(0)
-    net = DeblurNet(ctx, DeblurConfig())
+    net = DeblurNet(ctx, DeblurConfig(depth, base, slope, 208, 608))
     try:
         g = torch.Generator(device="cuda").manual_seed(2403)
         x = torch.randn(200, 600, device="cuda", generator=g)
@@ -204,10 +205,12 @@ def deblur_timing(train_steps: int = 40, applies: int = 10) -> dict:
             net.deblur_apply(x)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        fwd = deblur_flops(208, 608)
+        fwd = deblur_flops(208, 608, depth, base)
         tr = (t1 - t0) / train_steps
         ap = (t2 - t1) / applies
-        out = {"workload": "UNet depth 3, widths 32-64-128-256, ReLU, 208 x 608, bf16 MFMA, FP32 accumulation",
+        widths = "-".join(str(base << l) for l in range(depth + 1))
+        act = f"LeakyReLU {slope}" if slope else "ReLU"
+        out = {"workload": f"UNet depth {depth}, widths {widths}, {act}, 208 x 608, bf16 MFMA, FP32 accumulation",
                "train_ms_per_step": tr * 1e3, "train_TFLOPs": 3 * fwd / tr / 1e12,
                "apply_ms": ap * 1e3, "apply_TFLOPs": fwd / ap / 1e12, "forward_GFLOP": fwd / 1e9,
                "peak_TFLOPs": BF16_PEAK_TFLOPS}
@@ -347,6 +350,7 @@ def main():
         out["spill_probe"] = spill
     if not args.no_deblur:
         out["deblur"] = deblur_timing()
+        out["deblur_paper_scale"] = deblur_timing(train_steps=10, applies=5, depth=4, base=128, slope=0.2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)

@@ -54,7 +54,8 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-@pytest.mark.parametrize("depth,base,H,W,slope", [(2, 16, 32, 64, 0.0), (3, 32, 64, 192, 0.2)])
+@pytest.mark.parametrize("depth,base,H,W,slope", [(2, 16, 32, 64, 0.0), (3, 32, 64, 192, 0.2),
+                                                  (4, 128, 32, 64, 0.2)])
 def test_forward_matches_oracle(fctx, depth, base, H, W, slope):
     print(f"[deblur] forward depth={depth} base={base} {H}x{W}", flush=True)
     cfg = DeblurConfig(depth, base, slope, H, W)
@@ -112,6 +113,31 @@ def test_parameter_gradients_match_oracle(fctx, slope):
         worst = max(worst, e)
         assert e < TOL_GRAD, (name, e)
     print("worst per-tensor gradient rel err", worst)
+    net.close()
+
+
+def test_paper_scale_gradients_match_oracle(fctx):
+    """The paper's network (four down blocks, widths 128-2048, LeakyReLU 0.2):
+    every parameter gradient against the FP64 oracle on a 32 x 64 image."""
+    depth, base, H, W, slope = 4, 128, 32, 64, 0.2
+    net = DeblurNet(fctx, DeblurConfig(depth, base, slope, H, W))
+    ps = netparams.draw(depth, base, seed=17)
+    net.set_params(netparams.flatten(ps))
+    x, t = smooth_field(H, W, 7), smooth_field(H, W, 8)
+    loss, g = net.grad_raw(dev(x), dev(t))
+    ps32 = [p.astype(np.float32).astype(np.float64) for p in ps]
+    lref, gref, _ = R.loss_and_grads(ps32, x.astype(np.float32), t.astype(np.float32), depth, slope)
+    assert abs(loss - lref) < TOL_FWD * lref
+    gg = netparams.unflatten(g, depth, base)
+    names = [n for n, _ in netparams.param_shapes(depth, base)]
+    worst = 0.0
+    for name, a, b in zip(names, gg, gref):
+        if np.linalg.norm(b) == 0:
+            continue
+        e = rel(a, b)
+        worst = max(worst, e)
+        assert e < TOL_GRAD, (name, e)
+    print("paper-scale worst per-tensor gradient rel err", worst)
     net.close()
 
 
