@@ -116,9 +116,18 @@ def test_parameter_gradients_match_oracle(fctx, slope):
     net.close()
 
 
+TOL_GRAD_PAPER = 0.12
+
+
 def test_paper_scale_gradients_match_oracle(fctx):
     """The paper's network (four down blocks, widths 128-2048, LeakyReLU 0.2):
-    every parameter gradient against the FP64 oracle on a 32 x 64 image."""
+    every parameter gradient against the FP64 oracle on a 32 x 64 image.
+
+    The deepest block works on 2 x 4 pixels, so its weight gradients are sums
+    of a handful of products of bf16-stored activations and bf16-stored
+    back-propagated gradients (after 23 layers): storing those tensors in bf16
+    with exact arithmetic otherwise (a CPU emulation on this case) already
+    puts down4.w1 7.5% from the FP64 gradient. The bound is 1.6x that."""
     depth, base, H, W, slope = 4, 128, 32, 64, 0.2
     net = DeblurNet(fctx, DeblurConfig(depth, base, slope, H, W))
     ps = netparams.draw(depth, base, seed=17)
@@ -136,7 +145,7 @@ def test_paper_scale_gradients_match_oracle(fctx):
             continue
         e = rel(a, b)
         worst = max(worst, e)
-        assert e < TOL_GRAD, (name, e)
+        assert e < TOL_GRAD_PAPER, (name, e)
     print("paper-scale worst per-tensor gradient rel err", worst)
     net.close()
 
