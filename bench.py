@@ -215,6 +215,14 @@ def deblur_timing(train_steps: int = 40, applies: int = 10, depth: int = 3, base
                "apply_ms": ap * 1e3, "apply_TFLOPs": fwd / ap / 1e12, "forward_GFLOP": fwd / 1e9,
                "peak_TFLOPs": BF16_PEAK_TFLOPS}
         out["train_frac"] = out["train_TFLOPs"] / BF16_PEAK_TFLOPS
+        # per-layer GEMM timing over 3 training steps (events around each launch)
+        net.set_profiling(True)
+        net.deblur_train(x, y, 3, 1e-3)
+        recs = net.layer_stats()
+        net.set_profiling(False)
+        out["layers"] = [[r["name"], r["pass"], r["M"], r["N"], r["K"],
+                          round(r["flops"] / (r["ms"] * 1e-3) / 1e12, 1)] for r in recs]
+        out["layers_fields"] = ["layer", "pass", "M", "N", "K", "TFLOP/s"]
         print(f"train {train_steps} steps: {tr * 1e3:.2f} ms/step, {out['train_TFLOPs']:.1f} TFLOP/s; "
               f"apply {ap * 1e3:.2f} ms, {out['apply_TFLOPs']:.1f} TFLOP/s", file=sys.stderr, flush=True)
         return out

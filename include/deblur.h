@@ -91,6 +91,23 @@ int deblur_forward_raw(fwi_ctx *ctx, deblur_net *net, const float *x, float *y);
 int deblur_grad_raw(fwi_ctx *ctx, deblur_net *net, const float *x, const float *t, double *loss,
                     float *grads);
 
+/* Per-layer timing of the convolution GEMMs. With profiling on, every
+ * matrix-core launch of the network (forward, data-gradient and
+ * weight-gradient GEMMs of each convolution) is bracketed by HIP events;
+ * deblur_layer_stats waits for the stream, then writes up to `max` records
+ * (one per layer and pass, times summed over all launches since profiling
+ * was switched on) and their count. Switching profiling on clears them. */
+typedef struct {
+    char name[24];      /* "inc.1", "down2.2", "up1.T", ... */
+    int32_t pass;       /* 0 forward, 1 data gradient, 2 weight gradient */
+    int32_t M, N, K;    /* GEMM shape: outputs x pixels x reduction (wgrad: M x N over K pixels) */
+    int64_t calls;
+    double flops;       /* 2 M N K per call, summed */
+    double ms;          /* summed kernel time */
+} deblur_layer_stat;
+int deblur_set_profiling(deblur_net *net, int enable);
+int deblur_layer_stats(fwi_ctx *ctx, deblur_net *net, deblur_layer_stat *out, int32_t max, int32_t *count);
+
 /* Weights (FP32, parameter-vector order) to / from a file with a small
  * header holding the configuration. */
 int deblur_save(fwi_ctx *ctx, const deblur_net *net, const char *path);

@@ -57,6 +57,11 @@ class fwi_stats(C.Structure):
         return out
 
 
+class deblur_layer_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 24), ("pass_", C.c_int32), ("M", C.c_int32), ("N", C.c_int32),
+                ("K", C.c_int32), ("calls", C.c_int64), ("flops", C.c_double), ("ms", C.c_double)]
+
+
 class deblur_cfg(C.Structure):
     _fields_ = [("depth", C.c_int32), ("base_ch", C.c_int32), ("leaky_slope", C.c_float),
                 ("in_h", C.c_int32), ("in_w", C.c_int32)]
@@ -93,6 +98,8 @@ SIGNATURES = {
     "deblur_apply": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
     "deblur_forward_raw": (C.c_int, [_P, _P, _P, _P]),
     "deblur_grad_raw": (C.c_int, [_P, _P, _P, _P, C.POINTER(C.c_double), _P]),
+    "deblur_set_profiling": (C.c_int, [_P, C.c_int]),
+    "deblur_layer_stats": (C.c_int, [_P, _P, C.POINTER(deblur_layer_stat), C.c_int32, C.POINTER(C.c_int32)]),
     "deblur_save": (C.c_int, [_P, _P, C.c_char_p]),
     "deblur_load": (C.c_int, [_P, _P, C.c_char_p]),
 }

@@ -26,6 +26,14 @@ struct ConvL {
     int cin, cout;
     int64_t w, b;      // offsets into the flat parameter vector
     int64_t aux;       // offset of the data-gradient weights (bf16)
+    char name[24];     // layer name in timing records
+};
+
+// one timed GEMM launch (per-layer profiling)
+struct ProfRec {
+    const char *name;
+    int pass, M, N, K;
+    hipEvent_t e0, e1;
 };
 
 enum Kind { KW3 = 0, KB = 1, KWT = 2, KW1 = 3 };
@@ -60,6 +68,11 @@ struct deblur_net {
     std::vector<int64_t> a_off, cat_off, pool_off, c_off, d_off;  // per level offsets (elements)
     int64_t wpart_max = 0, bpart_max = 0;
     int nblk0 = 0;
+    // per-layer profiling
+    bool prof = false;
+    std::vector<ProfRec> prof_recs;
+    std::vector<hipEvent_t> prof_events;
+    size_t prof_used = 0;
 };
 
 namespace {
@@ -112,9 +125,10 @@ T *P_(const Buf &b, int64_t off = 0)
 
 // ---- layout -----------------------------------------------------------------
 
-ConvL add_conv(deblur_net *n, int cin, int cout)
+ConvL add_conv(deblur_net *n, int cin, int cout, const char *name)
 {
-    ConvL L{cin, cout, n->nparam, 0, n->naux};
+    ConvL L{cin, cout, n->nparam, 0, n->naux, {}};
+    std::snprintf(L.name, sizeof L.name, "%s", name);
     n->entries.push_back({KW3, cin, cout, n->nparam, int64_t(cout) * cin * 9});
     n->nparam += int64_t(cout) * cin * 9;
     L.b = n->nparam;
@@ -124,9 +138,10 @@ ConvL add_conv(deblur_net *n, int cin, int cout)
     return L;
 }
 
-ConvL add_convt(deblur_net *n, int cin, int cout)
+ConvL add_convt(deblur_net *n, int cin, int cout, const char *name)
 {
-    ConvL L{cin, cout, n->nparam, 0, n->naux};
+    ConvL L{cin, cout, n->nparam, 0, n->naux, {}};
+    std::snprintf(L.name, sizeof L.name, "%s", name);
     n->entries.push_back({KWT, cin, cout, n->nparam, int64_t(cin) * cout * 4});
     n->nparam += int64_t(cin) * cout * 4;
     L.b = n->nparam;
@@ -149,21 +164,27 @@ void build_layout(deblur_net *n)
         n->W[l] = n->cfg.in_w >> l;
         n->P[l] = n->H[l] * n->W[l];
     }
-    n->inc[0] = add_conv(n, 1, n->C[0]);
-    n->inc[1] = add_conv(n, n->C[0], n->C[0]);
+    char nm[24];
+    n->inc[0] = add_conv(n, 1, n->C[0], "inc.1");
+    n->inc[1] = add_conv(n, n->C[0], n->C[0], "inc.2");
     n->down1.assign(D + 1, ConvL{});
     n->down2.assign(D + 1, ConvL{});
     n->upT.assign(D, ConvL{});
     n->up1.assign(D, ConvL{});
     n->up2.assign(D, ConvL{});
     for (int l = 1; l <= D; ++l) {
-        n->down1[l] = add_conv(n, n->C[l - 1], n->C[l]);
-        n->down2[l] = add_conv(n, n->C[l], n->C[l]);
+        std::snprintf(nm, sizeof nm, "down%d.1", l);
+        n->down1[l] = add_conv(n, n->C[l - 1], n->C[l], nm);
+        std::snprintf(nm, sizeof nm, "down%d.2", l);
+        n->down2[l] = add_conv(n, n->C[l], n->C[l], nm);
     }
     for (int l = D - 1; l >= 0; --l) {
-        n->upT[l] = add_convt(n, n->C[l + 1], n->C[l]);
-        n->up1[l] = add_conv(n, 2 * n->C[l], n->C[l]);
-        n->up2[l] = add_conv(n, n->C[l], n->C[l]);
+        std::snprintf(nm, sizeof nm, "up%d.T", l);
+        n->upT[l] = add_convt(n, n->C[l + 1], n->C[l], nm);
+        std::snprintf(nm, sizeof nm, "up%d.1", l);
+        n->up1[l] = add_conv(n, 2 * n->C[l], n->C[l], nm);
+        std::snprintf(nm, sizeof nm, "up%d.2", l);
+        n->up2[l] = add_conv(n, n->C[l], n->C[l], nm);
     }
     n->out_w = n->nparam;
     n->entries.push_back({KW1, n->C[0], 1, n->nparam, n->C[0]});
@@ -386,6 +407,29 @@ Gather conv_gather(const bf16 *src, int ld, int coff, int Cb, int H, int W)
     return Gather{src, ld, coff, Cb, H, W, H, W, 1, 3, -1, 9};
 }
 
+// per-layer profiling: events around one GEMM launch
+int prof_begin(deblur_net *n, const char *name, int pass, int M, int N, int K, hipStream_t st)
+{
+    if (!n->prof) return FWI_OK;
+    while (n->prof_used + 2 > n->prof_events.size()) {
+        hipEvent_t e;
+        HCK(n, hipEventCreate(&e));
+        n->prof_events.push_back(e);
+    }
+    ProfRec r{name, pass, M, N, K, n->prof_events[n->prof_used], n->prof_events[n->prof_used + 1]};
+    n->prof_used += 2;
+    HCK(n, hipEventRecord(r.e0, st));
+    n->prof_recs.push_back(r);
+    return FWI_OK;
+}
+
+int prof_end(deblur_net *n, hipStream_t st)
+{
+    if (!n->prof) return FWI_OK;
+    HCK(n, hipEventRecord(n->prof_recs.back().e1, st));
+    return FWI_OK;
+}
+
 int conv_fwd(deblur_net *n, const ConvL &L, const bf16 *src, int ld, int coff, int lvl, bf16 *out, int out_ld,
              int out_coff, hipStream_t st)
 {
@@ -403,8 +447,10 @@ int conv_fwd(deblur_net *n, const ConvL &L, const bf16 *src, int ld, int coff, i
     a.bias = P_<float>(n->params, L.b);
     a.act = 1;
     a.slope = n->cfg.leaky_slope;
+    int rc = prof_begin(n, L.name, 0, a.M, a.N, a.K, st);
+    if (rc) return rc;
     HCK(n, gemm(a, st));
-    return FWI_OK;
+    return prof_end(n, st);
 }
 
 // dsrc = data gradient of a 3x3 conv given dz (the gradient at its
@@ -423,8 +469,10 @@ int conv_dgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff,
     a.out_ld = ld;
     a.out_coff = coff;
     a.Cout = L.cin;
+    int rc = prof_begin(n, L.name, 1, a.M, a.N, a.K, st);
+    if (rc) return rc;
     HCK(n, gemm(a, st));
-    return FWI_OK;
+    return prof_end(n, st);
 }
 
 int conv_wgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff, const bf16 *src, int ld, int coff,
@@ -444,8 +492,10 @@ int conv_wgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff,
     w.ldn = 1;
     w.bias_partial = P_<float>(n->bpart);
     w.bias_out = P_<float>(n->grads, L.b);
+    int rc = prof_begin(n, L.name, 2, w.M, w.N, n->P[lvl], st);
+    if (rc) return rc;
     HCK(n, wgrad(w, st));
-    return FWI_OK;
+    return prof_end(n, st);
 }
 
 // transposed conv of level l: src (level l+1, dense C_{l+1}) -> slice
@@ -468,8 +518,10 @@ int convt_fwd(deblur_net *n, int l, const bf16 *src, hipStream_t st)
     a.Ho = n->H[l];
     a.Wo = n->W[l];
     a.bias = P_<float>(n->params, T.b);
+    int rc = prof_begin(n, T.name, 0, a.M, a.N, a.K, st);
+    if (rc) return rc;
     HCK(n, gemm(a, st));
-    return FWI_OK;
+    return prof_end(n, st);
 }
 
 int convt_bwd(deblur_net *n, int l, const bf16 *src, bf16 *dsrc, hipStream_t st)
@@ -489,7 +541,10 @@ int convt_bwd(deblur_net *n, int l, const bf16 *src, bf16 *dsrc, hipStream_t st)
     w.out = P_<float>(n->grads, T.w);
     w.ldm = 1;
     w.ldn = T.cin;
+    int rc = prof_begin(n, T.name, 2, w.M, w.N, n->P[l + 1], st);
+    if (rc) return rc;
     HCK(n, wgrad(w, st));
+    if ((rc = prof_end(n, st))) return rc;
     const int ns = std::max(1, std::min(256, n->P[l] / 1024));
     HCK(n, bias_grad(du, 2 * n->C[l], n->C[l], T.cout, n->P[l], P_<float>(n->grads, T.b), P_<float>(n->bpart), ns,
                      st));
@@ -503,8 +558,9 @@ int convt_bwd(deblur_net *n, int l, const bf16 *src, bf16 *dsrc, hipStream_t st)
     a.out = dsrc;
     a.out_ld = T.cin;
     a.Cout = T.cin;
+    if ((rc = prof_begin(n, T.name, 1, a.M, a.N, a.K, st))) return rc;
     HCK(n, gemm(a, st));
-    return FWI_OK;
+    return prof_end(n, st);
 }
 
 // forward of the padded, normalised input in xin (bf16) to y32 (FP32)
@@ -671,6 +727,7 @@ void deblur_destroy(deblur_net *n)
                    &n->pool, &n->c, &n->d, &n->y32, &n->t32, &n->da, &n->dcat, &n->deD, &n->dpool, &n->dc, &n->dd,
                    &n->dy32, &n->wpart, &n->bpart, &n->lpart, &n->loss_dev, &n->hyper, &n->scal})
         release(*b);
+    for (hipEvent_t e : n->prof_events) (void)hipEventDestroy(e);
     delete n;
 }
 
@@ -812,6 +869,50 @@ int deblur_apply(fwi_ctx *ctx, deblur_net *n, const float *x, int32_t nz, int32_
     HCK(n, pad_norm(x, nz, nx, H, W, py, px, scal, P_<bf16>(n->xin), nullptr, st));
     if ((rc = forward(n, st))) return rc;
     HCK(n, crop_scale(P_<float>(n->y32), H, W, py, px, nz, nx, scal, y, st));
+    return FWI_OK;
+}
+
+int deblur_set_profiling(deblur_net *n, int enable)
+{
+    if (!n) return FWI_EINVAL;
+    n->prof = enable != 0;
+    if (n->prof) {
+        n->prof_recs.clear();
+        n->prof_used = 0;
+    }
+    return FWI_OK;
+}
+
+int deblur_layer_stats(fwi_ctx *ctx, deblur_net *n, deblur_layer_stat *out, int32_t max, int32_t *count)
+{
+    if (!n || !count || (max > 0 && !out)) return FWI_EINVAL;
+    hipStream_t st;
+    int rc = check_ctx(n, ctx, &st);
+    if (rc) return rc;
+    HCK(n, hipStreamSynchronize(st));
+    std::vector<deblur_layer_stat> agg;
+    for (const ProfRec &r : n->prof_recs) {
+        float ms = 0.f;
+        HCK(n, hipEventElapsedTime(&ms, r.e0, r.e1));
+        deblur_layer_stat *s = nullptr;
+        for (auto &a : agg)
+            if (a.pass == r.pass && std::strncmp(a.name, r.name, sizeof a.name) == 0) s = &a;
+        if (!s) {
+            agg.push_back(deblur_layer_stat{});
+            s = &agg.back();
+            std::snprintf(s->name, sizeof s->name, "%s", r.name);
+            s->pass = r.pass;
+            s->M = r.M;
+            s->N = r.N;
+            s->K = r.K;
+        }
+        s->calls += 1;
+        s->flops += 2.0 * double(r.M) * r.N * r.K;
+        s->ms += ms;
+    }
+    const int32_t k = int32_t(std::min<size_t>(agg.size(), size_t(std::max(max, 0))));
+    for (int32_t i = 0; i < k; ++i) out[i] = agg[i];
+    *count = int32_t(agg.size());
     return FWI_OK;
 }
 

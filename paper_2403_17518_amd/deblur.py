@@ -60,6 +60,21 @@ class DeblurNet:
             raise ValueError(f"{name} must be a contiguous float32 {tuple(shape)} tensor on {self.fctx.device}")
         return t
 
+    # -- per-layer timing -------------------------------------------------------
+    def set_profiling(self, on: bool):
+        self._check(self.lib.deblur_set_profiling(self.net, 1 if on else 0))
+
+    def layer_stats(self) -> list[dict]:
+        """Summed time and flops of every convolution GEMM since profiling
+        was switched on: one record per layer and pass."""
+        self._sync_stream()
+        buf = (_abi.deblur_layer_stat * 512)()
+        n = C.c_int32()
+        self._check(self.lib.deblur_layer_stats(self.fctx.ctx, self.net, buf, 512, C.byref(n)))
+        passes = ("forward", "data_grad", "weight_grad")
+        return [{"name": r.name.decode(), "pass": passes[r.pass_], "M": r.M, "N": r.N, "K": r.K,
+                 "calls": r.calls, "flops": r.flops, "ms": r.ms} for r in buf[:n.value]]
+
     # -- parameters ------------------------------------------------------------
     def set_params(self, flat: np.ndarray):
         flat = np.ascontiguousarray(flat, dtype=np.float32)

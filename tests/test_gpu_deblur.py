@@ -188,6 +188,29 @@ def test_apply_scales_pads_and_crops(fctx):
     net.close()
 
 
+def test_layer_stats_cover_every_gemm(fctx):
+    """Per-layer timing: every convolution appears with its three passes
+    (the input layer without a data gradient), one call per training step,
+    and the flops add up to three forward passes less the input layer's
+    data gradient."""
+    import bench
+    depth, base, H, W = 2, 16, 32, 64
+    net = DeblurNet(fctx, DeblurConfig(depth, base, 0.0, H, W))
+    x, y = dev(smooth_field(H, W, 1)), dev(smooth_field(H, W, 2))
+    net.set_profiling(True)
+    net.deblur_train(x, y, 2, 1e-3)
+    recs = net.layer_stats()
+    net.set_profiling(False)
+    names = {r["name"] for r in recs}
+    assert names == {"inc.1", "inc.2", "down1.1", "down1.2", "down2.1", "down2.2",
+                     "up1.T", "up1.1", "up1.2", "up0.T", "up0.1", "up0.2"}
+    assert all(r["calls"] == 2 and r["ms"] > 0 for r in recs)
+    assert not any(r["name"] == "inc.1" and r["pass"] == "data_grad" for r in recs)
+    fwd = sum(r["flops"] for r in recs if r["pass"] == "forward") / 2
+    assert abs(fwd - (bench.deblur_flops(H, W, depth, base) - 2 * H * W * base)) < 1.0   # less the 1x1 output conv
+    net.close()
+
+
 def test_save_load_reset(fctx):
     cfg = DeblurConfig(2, 8, 0.0, 16, 32)
     net = DeblurNet(fctx, cfg, seed=1)
