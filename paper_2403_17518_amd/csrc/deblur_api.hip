@@ -449,7 +449,13 @@ int conv_fwd(deblur_net *n, const ConvL &L, const bf16 *src, int ld, int coff, i
     a.slope = n->cfg.leaky_slope;
     int rc = prof_begin(n, L.name, 0, a.M, a.N, a.K, st);
     if (rc) return rc;
-    HCK(n, gemm(a, st));
+    if (L.cin == 1 && ld == 1 && coff == 0 && L.cout % 8 == 0 && L.cout <= 1024 && out_ld % 8 == 0 &&
+        out_coff % 8 == 0) {
+        // the input layer: a direct convolution (K = 9 is too short for the matrix cores)
+        HCK(n, conv1_fwd(src, n->H[lvl], n->W[lvl], a.A, a.bias, L.cout, 1, a.slope, out, out_ld, out_coff, st));
+    } else {
+        HCK(n, gemm(a, st));
+    }
     return prof_end(n, st);
 }
 
@@ -494,7 +500,12 @@ int conv_wgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff,
     w.bias_out = P_<float>(n->grads, L.b);
     int rc = prof_begin(n, L.name, 2, w.M, w.N, n->P[lvl], st);
     if (rc) return rc;
-    HCK(n, wgrad(w, st));
+    if (L.cin == 1 && ld == 1 && coff == 0 && L.cout % 8 == 0 && L.cout <= 2048 && ldz % 8 == 0 && zoff % 8 == 0) {
+        HCK(n, conv1_wgrad(dz, ldz, zoff, src, n->H[lvl], n->W[lvl], L.cout, P_<float>(n->wpart), n->wpart_max,
+                           w.out, w.bias_out, st));
+    } else {
+        HCK(n, wgrad(w, st));
+    }
     return prof_end(n, st);
 }
 

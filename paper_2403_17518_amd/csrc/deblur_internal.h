@@ -63,6 +63,12 @@ struct WgradArgs {
 };
 
 hipError_t gemm(const GemmArgs &a, hipStream_t s);
+// the input layer (one input channel): direct 3x3 convolution and its
+// weight/bias gradients (part: scratch of part_floats floats)
+hipError_t conv1_fwd(const bf16 *x, int32_t H, int32_t W, const bf16 *w, const float *b, int32_t C, int32_t act,
+                     float slope, bf16 *out, int32_t ld, int32_t coff, hipStream_t s);
+hipError_t conv1_wgrad(const bf16 *dz, int32_t ld, int32_t zoff, const bf16 *x, int32_t H, int32_t W, int32_t C,
+                       float *part, int64_t part_floats, float *dw, float *db, hipStream_t s);
 hipError_t wgrad(const WgradArgs &a, hipStream_t s);
 // bias gradient: db[c] = sum_p dz[p][coff + c]; scratch holds nsplit * C floats
 hipError_t bias_grad(const bf16 *dz, int32_t ld, int32_t coff, int32_t C, int32_t P, float *db, float *scratch,

@@ -376,6 +376,107 @@ __global__ __launch_bounds__(256) void k_bias_part(const bf16 *dz, int32_t ld, i
     }
 }
 
+// 3x3 convolution of a one-channel image (the input layer), zero padding 1:
+// out[p][co] = act(b[co] + sum_t w[co][t] x[p + t]) with bf16 weights and
+// inputs and FP32 sums. One thread per pixel and 8 output channels (one
+// 16-byte store); the block's weights are staged in LDS as floats.
+__global__ __launch_bounds__(256) void k_conv1_fwd(const bf16 *x, int32_t H, int32_t W, const bf16 *w,
+                                                   const float *b, int32_t C, int32_t act, float slope, bf16 *out,
+                                                   int32_t ld, int32_t coff)
+{
+    extern __shared__ float wl[];   // [C][9]
+    for (int e = threadIdx.x; e < C * 9; e += blockDim.x) wl[e] = bf2f(w[e]);
+    __syncthreads();
+    const int cpp = C / 8;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(H) * W * cpp) return;
+    const int c8 = int(t % cpp);
+    const int p = int(t / cpp);
+    const int i = p / W, j = p - (p / W) * W;
+    float xv[9];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int si = i + tap / 3 - 1, sj = j + tap % 3 - 1;
+        xv[tap] = (si >= 0 && si < H && sj >= 0 && sj < W) ? bf2f(x[si * W + sj]) : 0.f;
+    }
+    bf16 o[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int co = c8 * 8 + e;
+        float acc = 0.f;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) acc = __builtin_fmaf(wl[co * 9 + tap], xv[tap], acc);
+        float v = acc + b[co];
+        if (act) v = v > 0.f ? v : slope * v;
+        o[e] = f2bf(v);
+    }
+    *reinterpret_cast<uint4 *>(out + int64_t(p) * ld + coff + c8 * 8) = *reinterpret_cast<const uint4 *>(o);
+}
+
+// Weight and bias gradients of the input layer: dW[co][t] = sum_p dz[p][co]
+// x[p + t] and db[co] = sum_p dz[p][co]. Block (s, c8) sums pixel split s for
+// channels 8 c8 .. 8 c8 + 7: per-thread sums over a strided pixel subset,
+// then a wave-shuffle and LDS reduction in a fixed order; partial[s][C][10]
+// (9 taps, then the bias).
+__global__ __launch_bounds__(256) void k_conv1_wgrad(const bf16 *dz, int32_t ld, int32_t zoff, const bf16 *x,
+                                                     int32_t H, int32_t W, int32_t C, int32_t chunk, float *part)
+{
+    __shared__ float red[4][80];
+    const int c8 = blockIdx.y, sp = blockIdx.x;
+    const int P = H * W;
+    const int p0 = sp * chunk, p1 = min(P, p0 + chunk);
+    float acc[8][10];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) acc[e][k] = 0.f;
+    for (int p = p0 + int(threadIdx.x); p < p1; p += blockDim.x) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(dz + int64_t(p) * ld + zoff + c8 * 8);
+        const bf16 *d = reinterpret_cast<const bf16 *>(&v);
+        const int i = p / W, j = p - (p / W) * W;
+        float xv[9];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int si = i + tap / 3 - 1, sj = j + tap % 3 - 1;
+            xv[tap] = (si >= 0 && si < H && sj >= 0 && sj < W) ? bf2f(x[si * W + sj]) : 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float de = bf2f(d[e]);
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) acc[e][tap] = __builtin_fmaf(de, xv[tap], acc[e][tap]);
+            acc[e][9] += de;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            float v = acc[e][k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) red[wv][e * 10 + k] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < 80) {
+        const float v = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+        part[(int64_t(sp) * C + c8 * 8) * 10 + threadIdx.x] = v;
+    }
+}
+
+// sums partial[s][C][10] over the splits in order and scatters into dW[C][9]
+// and db[C]
+__global__ void k_conv1_wgrad_finish(const float *part, int32_t nsplit, int32_t C, float *dw, float *db)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= C * 10) return;
+    const float v = sum_strided(part + e, nsplit, int64_t(C) * 10);
+    const int co = e / 10, k = e - (e / 10) * 10;
+    if (k < 9) dw[co * 9 + k] = v;
+    else db[co] = v;
+}
+
 __global__ void k_sum_rows(const float *part, int32_t rows, int32_t C, float *out)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -630,6 +731,32 @@ __global__ void k_convt_dgrad_w(const float *wt, int32_t Cin, int32_t Cout, bf16
 inline unsigned nblocks(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
 }  // namespace
+
+hipError_t conv1_fwd(const bf16 *x, int32_t H, int32_t W, const bf16 *w, const float *b, int32_t C, int32_t act,
+                     float slope, bf16 *out, int32_t ld, int32_t coff, hipStream_t s)
+{
+    if (C % 8 || C > 1024 || ld % 8 || coff % 8) return hipErrorInvalidValue;   // weights: <= 36 KB of LDS
+    const int64_t threads = int64_t(H) * W * (C / 8);
+    if (threads == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_conv1_fwd, dim3(unsigned((threads + 255) / 256)), dim3(256), size_t(C) * 9 * sizeof(float),
+                       s, x, H, W, w, b, C, act, slope, out, ld, coff);
+    return hipGetLastError();
+}
+
+hipError_t conv1_wgrad(const bf16 *dz, int32_t ld, int32_t zoff, const bf16 *x, int32_t H, int32_t W, int32_t C,
+                       float *part, int64_t part_floats, float *dw, float *db, hipStream_t s)
+{
+    if (C % 8 || C > 2048 || ld % 8 || zoff % 8) return hipErrorInvalidValue;
+    const int P = H * W;
+    if (P == 0) return hipSuccess;
+    int nsplit = std::max(1, std::min((P + 2047) / 2048, 512));
+    nsplit = int(std::min<int64_t>(nsplit, part_floats / (int64_t(C) * 10)));
+    if (nsplit < 1) return hipErrorInvalidValue;
+    const int chunk = (P + nsplit - 1) / nsplit;
+    hipLaunchKernelGGL(k_conv1_wgrad, dim3(nsplit, C / 8), dim3(256), 0, s, dz, ld, zoff, x, H, W, C, chunk, part);
+    hipLaunchKernelGGL(k_conv1_wgrad_finish, dim3(nblocks(C * 10)), dim3(256), 0, s, part, nsplit, C, dw, db);
+    return hipGetLastError();
+}
 
 hipError_t gemm(const GemmArgs &a, hipStream_t s)
 {
