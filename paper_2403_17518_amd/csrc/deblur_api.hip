@@ -195,12 +195,21 @@ void build_layout(deblur_net *n)
 }
 
 // pixels per split and split count of a weight-gradient reduction
-void wsplit(int M, int N, int P, int *nsplit, int *chunk)
+void wsplit(int M, int N, int P, int *nsplit, int *chunk, int *tile)
 {
-    const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
-    int ns = std::max(1, std::min((512 + tiles - 1) / tiles, std::max(1, P / 256)));
+    // output tile of the weight-gradient kernel: 128 x 128 when the layer is
+    // wide enough to give at least 512 workgroups that way, else 64 x 64;
+    // pixel splits fill the GPU up to 512 workgroups
+    auto splits = [&](int t) {
+        const int tiles = ((M + t - 1) / t) * ((N + t - 1) / t);
+        return std::pair<int, int>(tiles, std::max(1, std::min((512 + tiles - 1) / tiles, std::max(1, P / 256))));
+    };
+    const auto w128 = splits(128);
+    const int t = (M >= 128 && N >= 128 && w128.first * w128.second >= 512) ? 128 : 64;
+    int ns = splits(t).second;
+    *tile = t;
     int ch = (P + ns - 1) / ns;
-    ch = ((ch + 31) / 32) * 32;
+    ch = ((ch + 63) / 64) * 64;
     ns = (P + ch - 1) / ch;
     *nsplit = ns;
     *chunk = ch;
@@ -251,8 +260,8 @@ int alloc_buffers(deblur_net *n)
     // scratch of the weight- and bias-gradient reductions
     int64_t wmax = 0, bmax = 0;
     auto acc_w = [&](int M, int N, int P) {
-        int ns, ch;
-        wsplit(M, N, P, &ns, &ch);
+        int ns, ch, tile;
+        wsplit(M, N, P, &ns, &ch, &tile);
         wmax = std::max(wmax, int64_t(ns) * M * N);
         bmax = std::max(bmax, int64_t(ns) * M);
     };
@@ -491,7 +500,7 @@ int conv_wgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff,
     w.lda = ldz;
     w.acoff = zoff;
     w.g = conv_gather(src, ld, coff, L.cin, n->H[lvl], n->W[lvl]);
-    wsplit(w.M, w.N, n->P[lvl], &w.nsplit, &w.chunk);
+    wsplit(w.M, w.N, n->P[lvl], &w.nsplit, &w.chunk, &w.tile);
     w.partial = P_<float>(n->wpart);
     w.out = P_<float>(n->grads, L.w);
     w.ldm = 9 * L.cin;
@@ -547,7 +556,7 @@ int convt_bwd(deblur_net *n, int l, const bf16 *src, bf16 *dsrc, hipStream_t st)
     w.lda = T.cin;
     w.acoff = 0;
     w.g = gu;
-    wsplit(w.M, w.N, n->P[l + 1], &w.nsplit, &w.chunk);
+    wsplit(w.M, w.N, n->P[l + 1], &w.nsplit, &w.chunk, &w.tile);
     w.partial = P_<float>(n->wpart);
     w.out = P_<float>(n->grads, T.w);
     w.ldm = 1;

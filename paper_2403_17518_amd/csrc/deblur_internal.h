@@ -52,7 +52,8 @@ struct WgradArgs {
     const bf16 *A;
     int32_t lda, acoff;
     Gather g;
-    int32_t nsplit, chunk;  // pixels per split, multiple of 32
+    int32_t nsplit, chunk;  // pixels per split, multiple of 64
+    int32_t tile;           // output tile edge of the kernel (64 or 128)
     float *partial;
     float *out;
     int32_t ldm, ldn;

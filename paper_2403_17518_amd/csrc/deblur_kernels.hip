@@ -333,6 +333,142 @@ __device__ __forceinline__ float sum_strided(const float *p, int rows, int64_t s
     return (s0 + s1) + (s2 + s3);
 }
 
+// Weight gradient for wide layers: a 128 x 128 tile of C[m][n] = sum_p
+// A[p][m] B[p][n] per workgroup (4 waves of 64 x 64, four 32 x 32 matrix-core
+// tiles each), 64-pixel K slices. Each thread loads the same 8-channel chunk
+// of A and of the gathered B for 4 consecutive pixels (16-byte loads) and
+// writes them transposed into the [channel][pixel] LDS tiles with one 8-byte
+// store per channel, so the matrix-core operands read 8 consecutive pixels.
+// Requires M, N, Cb, lda, ld and the channel offsets to be multiples of 8
+// and the pixel split (chunk) a multiple of 64. Partial sums per split as in
+// k_wgrad; the first column of blocks also sums A (the bias gradient).
+__global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a)
+{
+    constexpr int BM = 128, BN = 128, BK = 64, LDK = BK + 8;   // LDS rows of 144 B
+    __shared__ __attribute__((aligned(16))) bf16 As[BM * LDK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[BN * LDK];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const Gather &g = a.g;
+    const int P = g.H * g.W;
+    const int p_lo = blockIdx.z * a.chunk;
+    const int p_hi = min(P, p_lo + a.chunk);
+    const int nk = p_hi > p_lo ? (p_hi - p_lo + BK - 1) / BK : 0;
+
+    const int cc = tid & 15, pg = tid >> 4;   // channel chunk, group of 4 pixels
+    const bool mval = m0 + cc * 8 < a.M;
+    const int nb = n0 + cc * 8;
+    const bool nval = nb < a.N;
+    const int tap = nval ? nb / g.Cb : 0;
+    const int ch = nb - tap * g.Cb;
+    const int ty = tap / g.tapw, tx = tap - (tap / g.tapw) * g.tapw;
+    uint4 ra[4], rb[4];
+    auto load = [&](int kt) {
+        const int p4 = p_lo + kt * BK + pg * 4;
+        int i = p4 / g.W, j = p4 - (p4 / g.W) * g.W;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = p4 + u;
+            ra[u] = make_uint4(0, 0, 0, 0);
+            rb[u] = make_uint4(0, 0, 0, 0);
+            if (p < p_hi) {
+                if (mval) ra[u] = *reinterpret_cast<const uint4 *>(a.A + int64_t(p) * a.lda + a.acoff + m0 + cc * 8);
+                if (nval) {
+                    const int si = i * g.stride + ty + g.d0, sj = j * g.stride + tx + g.d0;
+                    if (si >= 0 && si < g.Hs && sj >= 0 && sj < g.Ws)
+                        rb[u] = *reinterpret_cast<const uint4 *>(g.src + (int64_t(si) * g.Ws + sj) * g.ld + g.coff + ch);
+                }
+            }
+            if (++j == g.W) {
+                j = 0;
+                ++i;
+            }
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t a01 = (reinterpret_cast<const uint16_t *>(&ra[0])[e]) |
+                                 (uint32_t(reinterpret_cast<const uint16_t *>(&ra[1])[e]) << 16);
+            const uint32_t a23 = (reinterpret_cast<const uint16_t *>(&ra[2])[e]) |
+                                 (uint32_t(reinterpret_cast<const uint16_t *>(&ra[3])[e]) << 16);
+            const uint32_t b01 = (reinterpret_cast<const uint16_t *>(&rb[0])[e]) |
+                                 (uint32_t(reinterpret_cast<const uint16_t *>(&rb[1])[e]) << 16);
+            const uint32_t b23 = (reinterpret_cast<const uint16_t *>(&rb[2])[e]) |
+                                 (uint32_t(reinterpret_cast<const uint16_t *>(&rb[3])[e]) << 16);
+            *reinterpret_cast<uint2 *>(&As[(cc * 8 + e) * LDK + pg * 4]) = make_uint2(a01, a23);
+            *reinterpret_cast<uint2 *>(&Bs[(cc * 8 + e) * LDK + pg * 4]) = make_uint2(b01, b23);
+        }
+    };
+
+    const bool do_bias = a.bias_partial != nullptr && blockIdx.x == 0;
+    float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = f32x16{};
+    if (nk > 0) load(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        __syncthreads();
+        store();
+        if (do_bias) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bf16 *pa = reinterpret_cast<const bf16 *>(&ra[u]);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bsum[e] += bf2f(pa[e]);
+            }
+        }
+        __syncthreads();
+        if (kt + 1 < nk) load(kt + 1);
+#pragma unroll
+        for (int kk = 0; kk < BK / 16; ++kk) {
+            bf16x8 av[2], bv[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+                av[x] = *reinterpret_cast<const bf16x8 *>(
+                    &As[(wm * 64 + x * 32 + lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+                bv[y] = *reinterpret_cast<const bf16x8 *>(
+                    &Bs[(wn * 64 + y * 32 + lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x], bv[y], acc[x][y], 0, 0, 0);
+        }
+    }
+    if (do_bias) {
+        // threads with the same chunk cc hold the same 8 channels for 16 pixel groups
+        __shared__ float bred[16][BM + 1];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bred[pg][cc * 8 + e] = bsum[e];
+        __syncthreads();
+        if (tid < BM) {
+            float t = 0.f;
+            for (int r = 0; r < 16; ++r) t += bred[r][tid];
+            if (m0 + tid < a.M) a.bias_partial[int64_t(blockIdx.z) * a.M + m0 + tid] = t;
+        }
+    }
+    float *part = a.partial + int64_t(blockIdx.z) * a.M * a.N;
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+        const int n = n0 + wn * 64 + y * 32 + lane % 32;
+        if (n >= a.N) continue;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = m0 + wm * 64 + x * 32 + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+                if (m < a.M) part[int64_t(m) * a.N + n] = acc[x][y][i];
+            }
+    }
+}
+
 __global__ void k_wgrad_reduce(const float *part, int32_t M, int32_t N, int32_t nsplit, float *out, int32_t ldm,
                                int32_t ldn)
 {
@@ -786,9 +922,14 @@ hipError_t wgrad(const WgradArgs &a, hipStream_t s)
     if (a.M <= 0 || a.N <= 0) return hipSuccess;
     const bool vec = a.g.Cb % 8 == 0 && a.lda % 8 == 0 && a.acoff % 8 == 0 && a.g.ld % 8 == 0 &&
                      a.g.coff % 8 == 0 && a.M % 8 == 0 && a.N % 8 == 0;
-    const dim3 grid(nblocks(a.N, 64), nblocks(a.M, 64), unsigned(a.nsplit));
-    if (vec) hipLaunchKernelGGL(k_wgrad<true>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_wgrad<false>, grid, dim3(256), 0, s, a);
+    if (vec && a.tile == 128 && a.chunk % 64 == 0) {
+        const dim3 grid(nblocks(a.N, 128), nblocks(a.M, 128), unsigned(a.nsplit));
+        hipLaunchKernelGGL(k_wgrad2, grid, dim3(256), 0, s, a);
+    } else {
+        const dim3 grid(nblocks(a.N, 64), nblocks(a.M, 64), unsigned(a.nsplit));
+        if (vec) hipLaunchKernelGGL(k_wgrad<true>, grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(k_wgrad<false>, grid, dim3(256), 0, s, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(int64_t(a.M) * a.N)), dim3(256), 0, s, a.partial, a.M, a.N,
