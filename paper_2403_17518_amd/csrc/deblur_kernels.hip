@@ -187,6 +187,110 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs a)
     }
 }
 
+// Implicit GEMM for wide layers: a 128 x 128 output tile per workgroup (4
+// waves of 64 x 64, four 32 x 32 matrix-core tiles each), 64-deep K slices
+// staged through registers into LDS. Each thread loads 4 rows of A and 4
+// gathered rows of B at one 8-element K offset; the tap and channel of that
+// offset are computed once per slice and the pixel coordinates of the rows
+// once per kernel. Requires K, Cb, lda, ld and coff to be multiples of 8 and
+// K a multiple of 64. Same epilogue as k_gemm.
+__global__ __launch_bounds__(256) void k_gemm2(const GemmArgs a)
+{
+    constexpr int BM = 128, BN = 128, BK = 64, LDK = BK + 8;
+    __shared__ __attribute__((aligned(16))) bf16 As[BM * LDK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[BN * LDK];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const Gather &g = a.g;
+    const int nk = a.K / BK;
+    const int kc = (tid & 7) * 8;     // this thread's K offset within a slice
+    const int r0 = tid >> 3;          // rows r0, r0 + 32, r0 + 64, r0 + 96
+    int pi[4], pj[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int p = n0 + r0 + 32 * u;
+        pi[u] = p < a.N ? p / g.W : -1 << 20;   // rows past N never pass the bounds test
+        pj[u] = p < a.N ? p - (p / g.W) * g.W : 0;
+    }
+    uint4 ra[4], rb[4];
+    auto load = [&](int kt) {
+        const int k = kt * BK + kc;
+        const int tap = k / g.Cb, ch = k - (k / g.Cb) * g.Cb;
+        const int ty = tap / g.tapw, tx = tap - (tap / g.tapw) * g.tapw;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int m = m0 + r0 + 32 * u;
+            ra[u] = m < a.M ? *reinterpret_cast<const uint4 *>(a.A + int64_t(m) * a.lda + k) : make_uint4(0, 0, 0, 0);
+            const int si = pi[u] * g.stride + ty + g.d0, sj = pj[u] * g.stride + tx + g.d0;
+            rb[u] = (si >= 0 && si < g.Hs && sj >= 0 && sj < g.Ws)
+                        ? *reinterpret_cast<const uint4 *>(g.src + (int64_t(si) * g.Ws + sj) * g.ld + g.coff + ch)
+                        : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            *reinterpret_cast<uint4 *>(&As[(r0 + 32 * u) * LDK + kc]) = ra[u];
+            *reinterpret_cast<uint4 *>(&Bs[(r0 + 32 * u) * LDK + kc]) = rb[u];
+        }
+    };
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = f32x16{};
+    if (nk > 0) load(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (kt + 1 < nk) load(kt + 1);
+#pragma unroll
+        for (int kk = 0; kk < BK / 16; ++kk) {
+            bf16x8 av[2], bv[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+                av[x] = *reinterpret_cast<const bf16x8 *>(
+                    &As[(wm * 64 + x * 32 + lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+                bv[y] = *reinterpret_cast<const bf16x8 *>(
+                    &Bs[(wn * 64 + y * 32 + lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x], bv[y], acc[x][y], 0, 0, 0);
+        }
+    }
+    // epilogue: lane holds rows m = 8*(i/4) + 4*(lane/32) + i%4 of each tile, column lane%32
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+        const int n = n0 + wn * 64 + y * 32 + lane % 32;
+        if (n >= a.N) continue;
+        const int pi_ = n / g.W, pj_ = n - (n / g.W) * g.W;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = m0 + wm * 64 + x * 32 + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+                if (m >= a.M) continue;
+                int co = m;
+                int64_t pix = n;
+                if (a.scatter) {
+                    const int ab = m / a.Cout;
+                    co = m - ab * a.Cout;
+                    pix = int64_t(2 * pi_ + ab / 2) * a.Wo + 2 * pj_ + ab % 2;
+                }
+                float v = acc[x][y][i];
+                if (a.bias) v += a.bias[co];
+                if (a.act) v = v > 0.f ? v : a.slope * v;
+                a.out[pix * a.out_ld + a.out_coff + co] = f2bf(v);
+            }
+    }
+}
+
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_wgrad(const WgradArgs a)
 {
@@ -901,7 +1005,10 @@ hipError_t gemm(const GemmArgs &a, hipStream_t s)
     // thin outputs use 32 x 256 tiles, wide ones 64 x 128; small problems
     // (the coarse levels) keep 64 x 64 tiles so that enough blocks run
     const int64_t blocks_wide = int64_t(nblocks(a.N, 128)) * nblocks(a.M, 64);
-    if (a.M <= 32) {
+    const int64_t blocks_big = int64_t(nblocks(a.N, 128)) * nblocks(a.M, 128);
+    if (vec && a.K % 64 == 0 && a.M >= 128 && blocks_big >= 240) {
+        hipLaunchKernelGGL(k_gemm2, dim3(nblocks(a.N, 128), nblocks(a.M, 128)), dim3(256), 0, s, a);
+    } else if (a.M <= 32) {
         const dim3 grid(nblocks(a.N, 256), nblocks(a.M, 32));
         if (vec) hipLaunchKernelGGL((k_gemm<1, 4, 2, true>), grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_gemm<1, 4, 2, false>), grid, dim3(256), 0, s, a);
