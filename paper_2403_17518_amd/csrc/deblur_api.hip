@@ -64,7 +64,7 @@ struct deblur_net {
     Buf params, grads, mom1, mom2, pbf, aux;
     Buf xin, a, cat, eD, pool, c, d, y32, t32;       // forward activations
     Buf da, dcat, deD, dpool, dc, dd, dy32;         // gradients
-    Buf wpart, bpart, lpart, loss_dev, hyper, scal;
+    Buf wpart, bpart, lpart, loss_dev, hyper, scal, kpart;
     std::vector<int64_t> a_off, cat_off, pool_off, c_off, d_off;  // per level offsets (elements)
     int64_t wpart_max = 0, bpart_max = 0;
     int nblk0 = 0;
@@ -288,6 +288,7 @@ int alloc_buffers(deblur_net *n)
     }
     wmax = std::max(wmax, int64_t((P0 + 255) / 256) * (n->C[0] + 1));  // output-conv partials
     n->wpart_max = wmax;
+    if ((rc = alloc(n, n->kpart, size_t(kGemmSplitFloats) * 4))) return rc;
     n->bpart_max = bmax;
     n->nblk0 = int((P0 + 255) / 256);
     if ((rc = alloc(n, n->wpart, size_t(wmax) * 4)) || (rc = alloc(n, n->bpart, size_t(bmax) * 4)) ||
@@ -443,6 +444,8 @@ int conv_fwd(deblur_net *n, const ConvL &L, const bf16 *src, int ld, int coff, i
              int out_coff, hipStream_t st)
 {
     GemmArgs a{};
+    a.kpart = P_<float>(n->kpart);
+    a.kpart_cap = kGemmSplitFloats;
     a.M = L.cout;
     a.N = n->P[lvl];
     a.K = 9 * L.cin;
@@ -474,6 +477,8 @@ int conv_dgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff,
                int coff, hipStream_t st)
 {
     GemmArgs a{};
+    a.kpart = P_<float>(n->kpart);
+    a.kpart_cap = kGemmSplitFloats;
     a.M = L.cin;
     a.N = n->P[lvl];
     a.K = 9 * L.cout;
@@ -524,6 +529,8 @@ int convt_fwd(deblur_net *n, int l, const bf16 *src, hipStream_t st)
 {
     const ConvL &T = n->upT[l];
     GemmArgs a{};
+    a.kpart = P_<float>(n->kpart);
+    a.kpart_cap = kGemmSplitFloats;
     a.M = 4 * T.cout;
     a.N = n->P[l + 1];
     a.K = T.cin;
@@ -569,6 +576,8 @@ int convt_bwd(deblur_net *n, int l, const bf16 *src, bf16 *dsrc, hipStream_t st)
     HCK(n, bias_grad(du, 2 * n->C[l], n->C[l], T.cout, n->P[l], P_<float>(n->grads, T.b), P_<float>(n->bpart), ns,
                      st));
     GemmArgs a{};
+    a.kpart = P_<float>(n->kpart);
+    a.kpart_cap = kGemmSplitFloats;
     a.M = T.cin;
     a.N = n->P[l + 1];
     a.K = 4 * T.cout;
@@ -745,7 +754,7 @@ void deblur_destroy(deblur_net *n)
     (void)hipDeviceSynchronize();
     for (Buf *b : {&n->params, &n->grads, &n->mom1, &n->mom2, &n->pbf, &n->aux, &n->xin, &n->a, &n->cat, &n->eD,
                    &n->pool, &n->c, &n->d, &n->y32, &n->t32, &n->da, &n->dcat, &n->deD, &n->dpool, &n->dc, &n->dd,
-                   &n->dy32, &n->wpart, &n->bpart, &n->lpart, &n->loss_dev, &n->hyper, &n->scal})
+                   &n->dy32, &n->wpart, &n->bpart, &n->lpart, &n->loss_dev, &n->hyper, &n->scal, &n->kpart})
         release(*b);
     for (hipEvent_t e : n->prof_events) (void)hipEventDestroy(e);
     delete n;

@@ -42,7 +42,13 @@ struct GemmArgs {
     const float *bias;
     int32_t act;
     float slope;
+    // split-K scratch (FP32, kpart_cap floats; null: no split): layers with
+    // few output tiles split K over workgroups and a second pass sums the
+    // parts in order and applies the epilogue
+    float *kpart;
+    int64_t kpart_cap;
 };
+constexpr int64_t kGemmSplitFloats = 480 * 128 * 128;   // split-K scratch per network
 
 // C[m][n] = sum_p A[p][acoff + m] * Bg(p, n), n = tap*Cb + c, reduced over the
 // pixels p of the gather grid in nsplit chunks: partial[z][m][n] (FP32), then

@@ -203,7 +203,10 @@ __global__ __launch_bounds__(256) void k_gemm2(const GemmArgs a)
     const int wm = w >> 1, wn = w & 1;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const Gather &g = a.g;
-    const int nk = a.K / BK;
+    // split K: workgroup z takes slices [z*nkz, (z+1)*nkz)
+    const int nkz = (a.K / BK + gridDim.z - 1) / gridDim.z;
+    const int kt0 = blockIdx.z * nkz;
+    const int nk = max(0, min(a.K / BK, kt0 + nkz) - kt0);
     const int kc = (tid & 7) * 8;     // this thread's K offset within a slice
     const int r0 = tid >> 3;          // rows r0, r0 + 32, r0 + 64, r0 + 96
     int pi[4], pj[4];
@@ -215,7 +218,7 @@ __global__ __launch_bounds__(256) void k_gemm2(const GemmArgs a)
     }
     uint4 ra[4], rb[4];
     auto load = [&](int kt) {
-        const int k = kt * BK + kc;
+        const int k = (kt0 + kt) * BK + kc;
         const int tap = k / g.Cb, ch = k - (k / g.Cb) * g.Cb;
         const int ty = tap / g.tapw, tx = tap - (tap / g.tapw) * g.tapw;
 #pragma unroll
@@ -263,6 +266,23 @@ __global__ __launch_bounds__(256) void k_gemm2(const GemmArgs a)
                 for (int y = 0; y < 2; ++y)
                     acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x], bv[y], acc[x][y], 0, 0, 0);
         }
+    }
+    if (gridDim.z > 1) {
+        // split K: raw partial sums, [z][n][m]
+        float *part = a.kpart + int64_t(blockIdx.z) * a.N * a.M;
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            const int n = n0 + wn * 64 + y * 32 + lane % 32;
+            if (n >= a.N) continue;
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int m = m0 + wm * 64 + x * 32 + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+                    if (m < a.M) part[int64_t(n) * a.M + m] = acc[x][y][i];
+                }
+        }
+        return;
     }
     // epilogue: lane holds rows m = 8*(i/4) + 4*(lane/32) + i%4 of each tile, column lane%32
 #pragma unroll
@@ -436,6 +456,28 @@ __device__ __forceinline__ float sum_strided(const float *p, int rows, int64_t s
     for (; z < rows; ++z) s0 += p[int64_t(z) * stride];
     return (s0 + s1) + (s2 + s3);
 }
+
+// split-K second pass: sums the parts of output (m, n) in order, then bias,
+// activation and the bf16 store (or scatter) of the GEMM epilogue
+__global__ void k_gemm_finish(const GemmArgs a, int32_t ksplit)
+{
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(a.M) * a.N) return;
+    const int m = int(e % a.M), n = int(e / a.M);
+    float v = sum_strided(a.kpart + e, ksplit, int64_t(a.M) * a.N);
+    int co = m;
+    int64_t pix = n;
+    if (a.scatter) {
+        const int pi_ = n / a.g.W, pj_ = n - (n / a.g.W) * a.g.W;
+        const int ab = m / a.Cout;
+        co = m - ab * a.Cout;
+        pix = int64_t(2 * pi_ + ab / 2) * a.Wo + 2 * pj_ + ab % 2;
+    }
+    if (a.bias) v += a.bias[co];
+    if (a.act) v = v > 0.f ? v : a.slope * v;
+    a.out[pix * a.out_ld + a.out_coff + co] = f2bf(v);
+}
+
 
 // Weight gradient for wide layers: a 128 x 128 tile of C[m][n] = sum_p
 // A[p][m] B[p][n] per workgroup (4 waves of 64 x 64, four 32 x 32 matrix-core
@@ -1008,6 +1050,18 @@ hipError_t gemm(const GemmArgs &a, hipStream_t s)
     const int64_t blocks_big = int64_t(nblocks(a.N, 128)) * nblocks(a.M, 128);
     if (vec && a.K % 64 == 0 && a.M >= 128 && blocks_big >= 240) {
         hipLaunchKernelGGL(k_gemm2, dim3(nblocks(a.N, 128), nblocks(a.M, 128)), dim3(256), 0, s, a);
+    } else if (vec && a.K % 64 == 0 && a.M >= 128 && a.kpart && a.K >= 1024) {
+        // few output tiles and a long K: split K over up to ~480 workgroups
+        // (at least 4 slices each), then sum the parts in order
+        int ks = int(std::min<int64_t>(480 / blocks_big, a.K / 256));
+        ks = int(std::min<int64_t>(ks, a.kpart_cap / (int64_t(a.M) * a.N)));
+        ks = std::max(ks, 1);
+        hipLaunchKernelGGL(k_gemm2, dim3(nblocks(a.N, 128), nblocks(a.M, 128), unsigned(ks)), dim3(256), 0, s, a);
+        if (ks > 1) {
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_gemm_finish, dim3(nblocks(int64_t(a.M) * a.N)), dim3(256), 0, s, a, ks);
+        }
     } else if (a.M <= 32) {
         const dim3 grid(nblocks(a.N, 256), nblocks(a.M, 32));
         if (vec) hipLaunchKernelGGL((k_gemm<1, 4, 2, true>), grid, dim3(256), 0, s, a);
