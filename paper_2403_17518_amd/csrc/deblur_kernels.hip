@@ -588,8 +588,9 @@ __global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a)
         }
     }
     if (do_bias) {
-        // threads with the same chunk cc hold the same 8 channels for 16 pixel groups
-        __shared__ float bred[16][BM + 1];
+        // threads with the same chunk cc hold the same 8 channels for 16 pixel
+        // groups; the reduction reuses the A tile's LDS (free after the loop)
+        float(*bred)[BM + 1] = reinterpret_cast<float(*)[BM + 1]>(&As[0]);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < 8; ++e) bred[pg][cc * 8 + e] = bsum[e];
