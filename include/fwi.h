@@ -188,6 +188,15 @@ int born_demig(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
 int born_mig(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
              const float *v0, const float *dd, float *img);
 
+/* img = J^T J dv, the doubly migrated image of section 2.3 eq. 15 (the
+ * Gauss-Newton Hessian applied to dv), and optionally dd = J dv (NULL to
+ * skip). One joint Born sweep supplies both the data and the background
+ * wavefield of the migration, so the result equals
+ * born_mig(v0, born_demig(v0, dv)) bit for bit with one background sweep
+ * fewer. v0, dv, img: device [nz][nx]; dd: device packed traces. */
+int born_pair(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
+              const float *v0, const float *dv, float *dd, float *img);
+
 #ifdef __cplusplus
 }
 #endif

@@ -124,7 +124,7 @@ struct fwi_ctx {
     int force_cw[3] = {0, 0, 0}, force_rows[3] = {0, 0, 0}, force_tb[3] = {0, 0, 0}, force_pd[3] = {0, 0, 0};
     bool autotune = true;
     // scratch
-    DevBuf fields, samples, image, dhist, ckpt, partials, misfit, check;
+    DevBuf fields, samples, image, dhist, ckpt, partials, misfit, check, pairdata;
     // copies of the call's model and perturbation: the time loops read these,
     // never the caller's buffers, so captured loops stay valid across calls
     DevBuf model, dmodel;
@@ -1038,7 +1038,10 @@ int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_o
         b.dslot = dhist + int64_t(slot) * gf;
         b.dslot2 = b.dslot + gf;
         slot = (slot + 1) % kTuneSlots;
-        if (cls == K_BORN) return launch_born_step(b, c->stream);
+        if (cls == K_BORN) {
+            b.dslot = nullptr;   // the Born step of a demigration (no D output)
+            return launch_born_step(b, c->stream);
+        }
         return t.tb == 2 ? launch_step2(flags, b, c->stream) : launch_step(flags, b, c->stream);
     };
     hipEvent_t e0, e1;
@@ -1219,7 +1222,8 @@ void fwi_ctx_destroy(fwi_ctx *c)
     for (Tiling &t : c->tile)
         for (DevBuf *b : {&t.d_waves, &t.d_rrows, &t.d_rmap}) release(*b);
     for (DevBuf *b : {&c->d_shots, &c->d_qnt, &c->d_qrptr, &c->d_qroff, &c->d_wav, &c->fields, &c->samples,
-                      &c->image, &c->dhist, &c->ckpt, &c->partials, &c->misfit, &c->check, &c->model, &c->dmodel})
+                      &c->image, &c->dhist, &c->ckpt, &c->partials, &c->misfit, &c->check, &c->model, &c->dmodel,
+                      &c->pairdata})
         release(*b);
     clear_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -1299,7 +1303,8 @@ int fwi_ctx_trim(fwi_ctx *c)
     (void)hipSetDevice(c->device);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return FWI_EHIP;
     clear_graphs(c);
-    for (DevBuf *b : {&c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt, &c->partials, &c->model, &c->dmodel})
+    for (DevBuf *b : {&c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt, &c->partials, &c->model, &c->dmodel,
+                      &c->pairdata})
         release(*b);
     return FWI_OK;
 }
@@ -1415,6 +1420,50 @@ int fwi_misfit(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *
     return finish_stats(c);
 }
 
+// Joint Born steps lo .. hi-1 (background u in U0/U1, scattered du in
+// D0/D1, alternating by step parity); du samples to samp + n*Q; with dh the
+// background's D^n goes to slot n - dlo of dh.
+int born_range(fwi_ctx *c, const StepArgs &a, int lo, int hi, float *samp, float *dh, int dlo, float *U0, float *U1,
+               float *D0, float *D1)
+{
+    if (lo >= hi) return FWI_OK;
+    const Plan &p = c->plan;
+    const int64_t gf = p.img_floats;
+    std::vector<char> key;
+    key_put(key, 'B');
+    key_put(key, a);
+    key_put(key, lo);
+    key_put(key, hi);
+    key_put(key, samp);
+    key_put(key, dh);
+    key_put(key, dlo);
+    key_put(key, U0);
+    key_put(key, U1);
+    key_put(key, D0);
+    key_put(key, D1);
+    Fields none{};
+    return run_loop(c, key, none, [&](Fields &) {
+        StepArgs b = a;
+        for (int n = lo; n < hi; ++n) {
+            b.n = n;
+            b.nwaves = c->tile[K_BORN].prefix[p.active_slots(n)];
+            b.cur = n % 2 == 0 ? U0 : U1;
+            b.prev = n % 2 == 0 ? U1 : U0;
+            b.cur2 = n % 2 == 0 ? D0 : D1;
+            b.prev2 = n % 2 == 0 ? D1 : D0;
+            b.samp = samp + size_t(n) * p.Q;
+            b.dslot = dh ? dh + size_t(n - dlo) * gf : nullptr;
+            HIPCHK(c, launch_born_step(b, c->stream));
+            const double upd = step_updates(p, n);
+            c->stats.cell_updates += 2 * upd;
+            c->stats.stencil_launches += 1;
+            c->stats.n_born += 1;
+            c->stats.bytes_born += upd * (kBytesBorn + (dh ? kBytesEmit : 0.0));
+        }
+        return int(FWI_OK);
+    });
+}
+
 int born_demig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v0, const float *dv, float *dd)
 {
     int rc = begin_call(c, g, geo);
@@ -1434,39 +1483,81 @@ int born_demig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *
     a.dv = dv;
     float *U0 = F, *U1 = F + ff, *D0 = F + 2 * ff, *D1 = F + 3 * ff;
     if ((rc = ev_begin(c, K_BORN))) return rc;
-    std::vector<char> key;
-    key_put(key, 'B');
-    key_put(key, a);
-    key_put(key, p.nt_max);
-    key_put(key, F);
-    key_put(key, samp);
-    Fields none{};
-    rc = run_loop(c, key, none, [&](Fields &) {
-        StepArgs b = a;
-        for (int n = 0; n < p.nt_max; ++n) {
-            b.n = n;
-            b.nwaves = c->tile[K_BORN].prefix[p.active_slots(n)];
-            b.cur = n % 2 == 0 ? U0 : U1;
-            b.prev = n % 2 == 0 ? U1 : U0;
-            b.cur2 = n % 2 == 0 ? D0 : D1;
-            b.prev2 = n % 2 == 0 ? D1 : D0;
-            b.samp = samp + size_t(n) * p.Q;
-            HIPCHK(c, launch_born_step(b, c->stream));
-            const double upd = step_updates(p, n);
-            c->stats.cell_updates += 2 * upd;
-            c->stats.stencil_launches += 1;
-            c->stats.n_born += 1;
-            c->stats.bytes_born += upd * kBytesBorn;
-        }
-        return int(FWI_OK);
-    });
-    if (rc) return rc;
+    if ((rc = born_range(c, a, 0, p.nt_max, samp, nullptr, 0, U0, U1, D0, D1))) return rc;
     if ((rc = ev_end(c))) return rc;
     TraceArgs t = trace_args(c);
     t.tm_in = samp;
     t.alpha = 1.f;
     t.tr_out = dd;
     if ((rc = other(c, launch_traces(t, c->stream, nullptr), "traces"))) return rc;
+    return finish_stats(c);
+}
+
+// img = J^T J dv in one joint Born sweep: its background wavefield provides
+// the imaging history (D^n of the last segment directly, checkpoints of
+// (u^{n-1}, u^n) for the others), its scattered samples are the data J dv
+// whose adjoint is then run. Equal to born_mig(born_demig(dv)) bit for bit
+// without the migration's own background sweep.
+int born_pair(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v0, const float *dv, float *dd,
+              float *img)
+{
+    int rc = begin_call(c, g, geo);
+    if (rc) return rc;
+    const Plan &p = c->plan;
+    if (!img) return set_err(c, FWI_EINVAL, "img is NULL");
+    if ((rc = check_model(c, v0, "v0")) || (rc = check_perturbation(c, dv)) || (rc = prepare(c, v0))) return rc;
+    Sweep w;
+    if ((rc = choose_segments(c, &w.k, &w.nseg))) return rc;
+    const int k = w.k, nseg = w.nseg;
+    c->stats.ckpt_every = nseg > 1 ? k : 0;
+    c->stats.n_segments = nseg;
+    const int64_t ff = p.field_floats, gf = p.img_floats;
+    if ((rc = ensure(c, c->fields, size_t(8 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
+        (rc = ensure(c, c->dhist, size_t(k) * gf * 4)) ||
+        (rc = ensure(c, c->ckpt, size_t(std::max(0, nseg - 1)) * 2 * ff * 4)) ||
+        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)) ||
+        (!dd && (rc = ensure(c, c->pairdata, size_t(std::max<int64_t>(p.data_size, 1)) * 4))))
+        return rc;
+    float *F = static_cast<float *>(c->fields.p);
+    for (int i = 0; i < 4; ++i) {
+        w.F[i] = F + i * ff;
+        w.A[i] = F + (4 + i) * ff;
+    }
+    w.Dh = static_cast<float *>(c->dhist.p);
+    w.CK = static_cast<float *>(c->ckpt.p);
+    w.G = static_cast<float *>(c->image.p);
+    float *samp = static_cast<float *>(c->samples.p);
+    hipStream_t st = c->stream;
+    if ((rc = other(c, launch_fill(w.F[0], 4 * ff, 0.f, st), "fill"))) return rc;
+    StepArgs a = base_args(c, v0, K_BORN);
+    a.dv = dv;
+    float *U0 = w.F[0], *U1 = w.F[1], *D0 = w.F[2], *D1 = w.F[3];
+    if ((rc = ev_begin(c, K_BORN))) return rc;
+    for (int sgi = 0; sgi < nseg; ++sgi) {
+        const int lo = sgi * k, hi = std::min(p.nt_max, lo + k);
+        const bool last = sgi == nseg - 1;
+        if (!last) {
+            // (u^{lo-1}, u^lo): the fields the step at n = lo reads as prev, cur
+            float *ckp = w.CK + size_t(sgi) * 2 * ff;
+            HIPCHK(c, hipMemcpyAsync(ckp, lo % 2 == 0 ? U1 : U0, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipMemcpyAsync(ckp + ff, lo % 2 == 0 ? U0 : U1, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
+        }
+        if ((rc = born_range(c, a, lo, hi, samp, last ? w.Dh : nullptr, lo, U0, U1, D0, D1))) return rc;
+    }
+    if ((rc = ev_end(c))) return rc;
+    // samples -> packed data J dv -> adjoint sources (co-located receivers add)
+    float *data = dd ? dd : static_cast<float *>(c->pairdata.p);
+    TraceArgs t = trace_args(c);
+    t.tm_in = samp;
+    t.alpha = 1.f;
+    t.tr_out = data;
+    if ((rc = other(c, launch_traces(t, st, nullptr), "traces"))) return rc;
+    TraceArgs t2 = trace_args(c);
+    t2.tr_in = data;
+    t2.beta = 1.f;
+    t2.tm_out = samp;
+    if ((rc = other(c, launch_traces(t2, st, nullptr), "adjoint sources"))) return rc;
+    if ((rc = backward_sweep(c, v0, w, img))) return rc;
     return finish_stats(c);
 }
 

@@ -567,8 +567,11 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 // two equations are solved jointly so that u is never stored):
 //   du^{n+1} = a (2 du^n + V^2 dt^2 L8 du^n + 2 V dV dt^2 (L8 u^n + s^n)) - b du^{n-1}
 // where 2 V dV dt^2 = (2 dV / V) V^2 dt^2 is the linearised 1/V^2 term.
-// Same tiling and prefetching as k_step; receivers record du^{n+1}.
-template <int CW>
+// Same tiling and prefetching as k_step; receivers record du^{n+1}. With
+// EMIT the background's D^n = V^2 dt^2 (L8 u^n + s^n) is also written to the
+// D slot (the same value the forward step emits), so that a migration can
+// follow without a separate background sweep.
+template <int CW, bool EMIT>
 __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const StepArgs A)
 {
     constexpr int SW = kLanes * CW;
@@ -591,6 +594,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
     const Rsrc rcu = view(A.cur + base), rpv = view(A.prev + base);
     const Rsrc rcd = view(A.cur2 + base), rpd = view(A.prev2 + base);
     const Rsrc rv = view(A.v), rdv = view(A.dv);
+    const Rsrc rd = view(EMIT ? A.dslot + S.g_off : A.v);
 
     bool valid[CW];
     unsigned jm[CW];
@@ -687,7 +691,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
         }
         const int ddz = max(max(nb - z, z - (A.NZ - 1 - nb)), 0);
         const float dz2 = float(ddz * ddz);
-        float ou[CW], od[CW];
+        float ou[CW], od[CW], Dv[CW];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             float lap = lap8(q, xr, k, A.w1, A.w2, A.w3, A.w4);
@@ -700,7 +704,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
                 sh = A.hs * (dz2 + dx2[k]);
                 a = sponge_a(sh);
             }
-            ou[k] = leapfrog(q[4][k], cpv[k], c * lap, a, sh);
+            Dv[k] = c * lap;
+            ou[k] = leapfrog(q[4][k], cpv[k], Dv[k], a, sh);
             od[k] = leapfrog(r[4][k], cpd[k], __builtin_fmaf(cr, lap, c * lapd), a, sh);
         }
         const int o = 4 * (z + kRowsAbove) * P;
@@ -709,6 +714,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
             if (valid[k]) {
                 bst1(rpv, js + 4 * k, o, ou[k]);
                 bst1(rpd, js + 4 * k, o, od[k]);
+                if (EMIT) bst1(rd, js + 4 * k, 4 * z * P, Dv[k]);
                 if (qi[k] >= 0) A.samp[qi[k]] = od[k];
             }
         }
@@ -968,10 +974,14 @@ hipError_t launch_step2(int flags, const StepArgs &a, hipStream_t s)
 hipError_t launch_born_step(const StepArgs &a, hipStream_t s)
 {
     if (a.nwaves <= 0) return hipSuccess;
-    if (a.cw == 2)
-        hipLaunchKernelGGL(k_born_step<2>, dim3(blocks_for(a.nwaves)), dim3(kLanes * kWavesPerBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_born_step<1>, dim3(blocks_for(a.nwaves)), dim3(kLanes * kWavesPerBlock), 0, s, a);
+    const dim3 grid(blocks_for(a.nwaves)), block(kLanes * kWavesPerBlock);
+    if (a.dslot) {
+        if (a.cw == 2) hipLaunchKernelGGL((k_born_step<2, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_born_step<1, true>), grid, block, 0, s, a);
+    } else {
+        if (a.cw == 2) hipLaunchKernelGGL((k_born_step<2, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_born_step<1, false>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 

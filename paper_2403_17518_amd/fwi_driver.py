@@ -4,7 +4,8 @@ network-preconditioned update of the paper (section 2.3, Fig. 1).
 One iteration of the network method:
   1. g_phi = fwi_gradient(v, d_obs)        (gradient of the misfit; the
      paper's gradient is g = -g_phi, eq. 13 with d_o - d_s)
-  2. dm1 = born_mig(v, born_demig(v, g))    (doubly migrated image, eq. 15)
+  2. dm1 = born_pair(v, g) = born_mig(v, born_demig(v, g))   (doubly
+     migrated image, eq. 15; one joint Born sweep feeds the migration)
   3. train the network dm1 -> g, warm-started from the previous iteration
      (transfer learning), reset at every new frequency band
   4. p = deblur_apply(g); if p is not a descent direction (<p, g_phi> >= 0)
@@ -190,10 +191,9 @@ class FwiRun:
         use_net = self.net is not None and (o.net_iters is None or it < o.net_iters)
         if use_net:
             ta = time.perf_counter()
-            dd = self.fctx.born_demig(self.grid, acq, self.v, g.contiguous())
-            self._count(1)
-            dm1 = self.fctx.born_mig(self.grid, acq, self.v, dd)
-            self._count(1)
+            # the pair J^T J g (demigration + migration, 2 solves) in one joint sweep
+            dm1 = self.fctx.born_pair(self.grid, acq, self.v, g.contiguous())
+            self._count(2)
             _sync()
             t["pair"] = time.perf_counter() - ta
             ta = time.perf_counter()

@@ -175,9 +175,19 @@ class FwiContext:
                                                      C.c_void_p(img.data_ptr())))
         return img
 
-    def born_pair(self, grid, acq, v0, g_in) -> torch.Tensor:
-        """J^T J g_in, the doubly migrated image (paper section 2.3 eq. 15)."""
-        return self.born_mig(grid, acq, v0, self.born_demig(grid, acq, v0, g_in))
+    def born_pair(self, grid, acq, v0, g_in, want_dd: bool = False):
+        """J^T J g_in, the doubly migrated image (paper section 2.3 eq. 15),
+        from one joint Born sweep; with want_dd also J g_in: (img, dd)."""
+        v0 = self._model(v0, "v0", grid)
+        g_in = self._model(g_in, "g_in", grid)
+        img = torch.empty((grid.nz, grid.nx), device=self.device, dtype=torch.float32)
+        dd = torch.empty(self._data_size(grid, acq), device=self.device, dtype=torch.float32) if want_dd else None
+        g, gv = self._prep(grid, acq)
+        _check(self.lib, self.ctx, self.lib.born_pair(self.ctx, C.byref(g), C.byref(gv.geom),
+                                                      C.c_void_p(v0.data_ptr()), C.c_void_p(g_in.data_ptr()),
+                                                      C.c_void_p(dd.data_ptr()) if want_dd else None,
+                                                      C.c_void_p(img.data_ptr())))
+        return (img, dd) if want_dd else img
 
 
 _default: dict = {}
