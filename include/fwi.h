@@ -197,6 +197,19 @@ int born_mig(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
 int born_pair(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
               const float *v0, const float *dv, float *dd, float *img);
 
+/* The gradient and its doubly migrated image at the same model, as one FWI
+ * iteration of the network method needs them: grad = J^T (F(v) - d_obs) (as
+ * fwi_gradient, bit for bit), misfit (host, nullable), and
+ * img = J^T J (scale * grad). When the forward sweep's imaging history fits
+ * in memory whole (no checkpoints), the pair reuses it: only the scattered
+ * field is propagated, with the source (2 dV / V) D^n read from the stored
+ * background history, then the adjoint. Otherwise the pair runs as
+ * born_pair. The image equals born_pair(v, scale * grad) up to FP32
+ * rounding (the scattered source is formed from the stored D^n). */
+int fwi_gradient_pair(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
+                      const float *v, const float *d_obs, float *grad, double *misfit,
+                      float scale, float *img);
+
 #ifdef __cplusplus
 }
 #endif

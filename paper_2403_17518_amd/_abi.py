@@ -88,6 +88,8 @@ SIGNATURES = {
     "born_demig": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P]),
     "born_mig": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P]),
     "born_pair": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P, _P]),
+    "fwi_gradient_pair": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P,
+                                    C.POINTER(C.c_double), C.c_float, _P]),
     "deblur_create": (C.c_int, [_P, C.POINTER(deblur_cfg), C.c_uint64, C.POINTER(_P)]),
     "deblur_destroy": (None, [_P]),
     "deblur_last_error": (C.c_char_p, [_P]),

@@ -569,6 +569,8 @@ int ev_collect(fwi_ctx *c)
 // adjoint with imaging adds the D^n read and the G read-modify-write (28 B);
 // the Born step moves 32 B for its two field updates.
 constexpr double kBytesFwd = 16.0, kBytesEmit = 4.0, kBytesAdj = 28.0, kBytesBorn = 32.0;
+// scattered field from the stored history: du^n, du^{n-1}, v, dv, D^n in, du^{n+1} out
+constexpr double kBytesScat = 24.0;
 
 double step_updates(const Plan &p, int n)
 {
@@ -1178,6 +1180,192 @@ int forward_sweep_sampled(fwi_ctx *c, const float *v)
     return ev_end(c);
 }
 
+// Joint Born steps lo .. hi-1 (background u in U0/U1, scattered du in
+// D0/D1, alternating by step parity); du samples to samp + n*Q; with dh the
+// background's D^n goes to slot n - dlo of dh.
+int born_range(fwi_ctx *c, const StepArgs &a, int lo, int hi, float *samp, float *dh, int dlo, float *U0, float *U1,
+               float *D0, float *D1)
+{
+    if (lo >= hi) return FWI_OK;
+    const Plan &p = c->plan;
+    const int64_t gf = p.img_floats;
+    std::vector<char> key;
+    key_put(key, 'B');
+    key_put(key, a);
+    key_put(key, lo);
+    key_put(key, hi);
+    key_put(key, samp);
+    key_put(key, dh);
+    key_put(key, dlo);
+    key_put(key, U0);
+    key_put(key, U1);
+    key_put(key, D0);
+    key_put(key, D1);
+    Fields none{};
+    return run_loop(c, key, none, [&](Fields &) {
+        StepArgs b = a;
+        for (int n = lo; n < hi; ++n) {
+            b.n = n;
+            b.nwaves = c->tile[K_BORN].prefix[p.active_slots(n)];
+            b.cur = n % 2 == 0 ? U0 : U1;
+            b.prev = n % 2 == 0 ? U1 : U0;
+            b.cur2 = n % 2 == 0 ? D0 : D1;
+            b.prev2 = n % 2 == 0 ? D1 : D0;
+            b.samp = samp + size_t(n) * p.Q;
+            b.dslot = dh ? dh + size_t(n - dlo) * gf : nullptr;
+            HIPCHK(c, launch_born_step(b, c->stream));
+            const double upd = step_updates(p, n);
+            c->stats.cell_updates += 2 * upd;
+            c->stats.stencil_launches += 1;
+            c->stats.n_born += 1;
+            c->stats.bytes_born += upd * (kBytesBorn + (dh ? kBytesEmit : 0.0));
+        }
+        return int(FWI_OK);
+    });
+}
+
+// The FWI gradient after begin_call: leaves the sweep state (and, with one
+// segment, the whole D^n history) in the context.
+int gradient_core(fwi_ctx *c, const float *v, const float *d_obs, float *grad, double *misfit, float *d_syn,
+                  Sweep &w)
+{
+    int rc;
+    const Plan &p = c->plan;
+    if (!grad) return set_err(c, FWI_EINVAL, "g is NULL");
+    if (!d_obs && p.data_size > 0) return set_err(c, FWI_EINVAL, "d_obs is NULL");
+    if ((rc = check_model(c, v, "v")) || (rc = prepare(c, v))) return rc;
+    // forward with sampling and checkpoints, then the residual (in place
+    // over the samples), then the backward sweep
+    if ((rc = forward_for_adjoint(c, v, true, w))) return rc;
+    TraceArgs t = trace_args(c);
+    float *samp = static_cast<float *>(c->samples.p);
+    t.tm_in = samp;
+    t.alpha = 1.f;
+    t.tr_in = d_obs;
+    t.beta = -1.f;
+    t.tm_out = samp;
+    t.tr_out = d_syn;
+    const int64_t nblk = int64_t((p.Q + 63) / 64) * ((p.nt_max + 63) / 64);
+    if ((rc = ensure(c, c->partials, size_t(std::max<int64_t>(nblk, 1)) * sizeof(double))) ||
+        (rc = ensure(c, c->misfit, sizeof(double))))
+        return rc;
+    t.partials = static_cast<double *>(c->partials.p);
+    if ((rc = other(c, launch_traces(t, c->stream, nullptr), "residual"))) return rc;
+    if (nblk > 0) {
+        if ((rc = other(c, launch_sum_partials(t.partials, nblk, static_cast<double *>(c->misfit.p), c->stream),
+                        "misfit")))
+            return rc;
+    } else {
+        HIPCHK(c, hipMemsetAsync(c->misfit.p, 0, sizeof(double), c->stream));
+    }
+    if (misfit)
+        HIPCHK(c, hipMemcpyAsync(c->h_misfit, c->misfit.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if ((rc = backward_sweep(c, v, w, grad))) return rc;
+    if (misfit) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *misfit = *c->h_misfit;
+    }
+    return FWI_OK;
+}
+
+// The pair after the model and perturbation are in the context (v0, dv are
+// the context copies) and the tilings are prepared.
+int pair_core(fwi_ctx *c, const float *v0, const float *dv, float *dd, float *img)
+{
+    int rc;
+    const Plan &p = c->plan;
+    Sweep w;
+    if ((rc = choose_segments(c, &w.k, &w.nseg))) return rc;
+    const int k = w.k, nseg = w.nseg;
+    c->stats.ckpt_every = nseg > 1 ? k : 0;
+    c->stats.n_segments = nseg;
+    const int64_t ff = p.field_floats, gf = p.img_floats;
+    if ((rc = ensure(c, c->fields, size_t(8 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
+        (rc = ensure(c, c->dhist, size_t(k) * gf * 4)) ||
+        (rc = ensure(c, c->ckpt, size_t(std::max(0, nseg - 1)) * 2 * ff * 4)) ||
+        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)) ||
+        (!dd && (rc = ensure(c, c->pairdata, size_t(std::max<int64_t>(p.data_size, 1)) * 4))))
+        return rc;
+    float *F = static_cast<float *>(c->fields.p);
+    for (int i = 0; i < 4; ++i) {
+        w.F[i] = F + i * ff;
+        w.A[i] = F + (4 + i) * ff;
+    }
+    w.Dh = static_cast<float *>(c->dhist.p);
+    w.CK = static_cast<float *>(c->ckpt.p);
+    w.G = static_cast<float *>(c->image.p);
+    float *samp = static_cast<float *>(c->samples.p);
+    hipStream_t st = c->stream;
+    if ((rc = other(c, launch_fill(w.F[0], 4 * ff, 0.f, st), "fill"))) return rc;
+    StepArgs a = base_args(c, v0, K_BORN);
+    a.dv = dv;
+    float *U0 = w.F[0], *U1 = w.F[1], *D0 = w.F[2], *D1 = w.F[3];
+    if ((rc = ev_begin(c, K_BORN))) return rc;
+    for (int sgi = 0; sgi < nseg; ++sgi) {
+        const int lo = sgi * k, hi = std::min(p.nt_max, lo + k);
+        const bool last = sgi == nseg - 1;
+        if (!last) {
+            // (u^{lo-1}, u^lo): the fields the step at n = lo reads as prev, cur
+            float *ckp = w.CK + size_t(sgi) * 2 * ff;
+            HIPCHK(c, hipMemcpyAsync(ckp, lo % 2 == 0 ? U1 : U0, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipMemcpyAsync(ckp + ff, lo % 2 == 0 ? U0 : U1, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
+        }
+        if ((rc = born_range(c, a, lo, hi, samp, last ? w.Dh : nullptr, lo, U0, U1, D0, D1))) return rc;
+    }
+    if ((rc = ev_end(c))) return rc;
+    // samples -> packed data J dv -> adjoint sources (co-located receivers add)
+    float *data = dd ? dd : static_cast<float *>(c->pairdata.p);
+    TraceArgs t = trace_args(c);
+    t.tm_in = samp;
+    t.alpha = 1.f;
+    t.tr_out = data;
+    if ((rc = other(c, launch_traces(t, st, nullptr), "traces"))) return rc;
+    TraceArgs t2 = trace_args(c);
+    t2.tr_in = data;
+    t2.beta = 1.f;
+    t2.tm_out = samp;
+    if ((rc = other(c, launch_traces(t2, st, nullptr), "adjoint sources"))) return rc;
+    return backward_sweep(c, v0, w, img);
+}
+
+// Scattered-field steps lo .. hi-1 with the source (2 dV / V) D^n read from
+// slot n - dlo of dh (the stored background history); du^{n+1} samples to
+// samp + n*Q. One time level per launch on the Born tiling.
+int scat_range(fwi_ctx *c, const StepArgs &a, int lo, int hi, float *samp, float *dh, int dlo, Fields &f)
+{
+    if (lo >= hi) return FWI_OK;
+    const Plan &p = c->plan;
+    const int64_t gf = p.img_floats;
+    std::vector<char> key;
+    key_put(key, 'S');
+    key_put(key, a);
+    key_put(key, lo);
+    key_put(key, hi);
+    key_put(key, samp);
+    key_put(key, dh);
+    key_put(key, dlo);
+    key_put(key, f);
+    return run_loop(c, key, f, [&](Fields &ff) {
+        StepArgs b = a;
+        for (int n = lo; n < hi; ++n) {
+            b.n = n;
+            b.nwaves = c->tile[K_BORN].prefix[p.active_slots(n)];
+            b.cur = ff.cur;
+            b.prev = ff.prev;
+            b.samp = samp + size_t(n) * p.Q;
+            b.dslot = dh + size_t(n - dlo) * gf;
+            HIPCHK(c, launch_step(F_SAMPLE | F_SCAT, b, c->stream));
+            std::swap(ff.prev, ff.cur);
+            const double upd = step_updates(p, n);
+            c->stats.cell_updates += upd;
+            c->stats.stencil_launches += 1;
+            c->stats.n_born += 1;
+            c->stats.bytes_born += upd * kBytesScat;
+        }
+        return int(FWI_OK);
+    });
+}
+
 }  // namespace
 
 namespace fwi {
@@ -1347,42 +1535,55 @@ int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float
 {
     int rc = begin_call(c, g, geo);
     if (rc) return rc;
-    const Plan &p = c->plan;
-    if (!grad) return set_err(c, FWI_EINVAL, "g is NULL");
-    if (!d_obs && p.data_size > 0) return set_err(c, FWI_EINVAL, "d_obs is NULL");
-    if ((rc = check_model(c, v, "v")) || (rc = prepare(c, v))) return rc;
-    // forward with sampling and checkpoints, then the residual (in place
-    // over the samples), then the backward sweep
     Sweep w;
-    if ((rc = forward_for_adjoint(c, v, true, w))) return rc;
-    TraceArgs t = trace_args(c);
+    if ((rc = gradient_core(c, v, d_obs, grad, misfit, d_syn, w))) return rc;
+    return finish_stats(c);
+}
+
+int fwi_gradient_pair(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v, const float *d_obs,
+                      float *grad, double *misfit, float scale, float *img)
+{
+    int rc = begin_call(c, g, geo);
+    if (rc) return rc;
+    if (!img) return set_err(c, FWI_EINVAL, "img is NULL");
+    if (!(scale == scale) || std::isinf(scale)) return set_err(c, FWI_EINVAL, "scale must be finite");
+    Sweep w;
+    if ((rc = gradient_core(c, v, d_obs, grad, misfit, nullptr, w))) return rc;
+    const Plan &p = c->plan;
+    const float *mv = static_cast<const float *>(c->model.p);   // the call's model copy
+    // dv = scale * g, in the context
+    if ((rc = ensure(c, c->dmodel, size_t(p.nz) * p.nx * 4))) return rc;
+    float *dv = static_cast<float *>(c->dmodel.p);
+    if ((rc = other(c, launch_scale(grad, scale, dv, int64_t(p.nz) * p.nx, c->stream), "scale"))) return rc;
+    if (w.nseg > 1) {
+        // the history was checkpointed: the pair runs its own joint Born sweep
+        if ((rc = pair_core(c, mv, dv, nullptr, img))) return rc;
+        return finish_stats(c);
+    }
+    // the whole D^n history of the gradient's forward sweep is still stored:
+    // only the scattered field is propagated, with the source (2 dV / V) D^n
+    const int64_t ff = p.field_floats;
     float *samp = static_cast<float *>(c->samples.p);
+    if ((rc = ensure(c, c->pairdata, size_t(std::max<int64_t>(p.data_size, 1)) * 4))) return rc;
+    if ((rc = other(c, launch_fill(w.F[0], 2 * ff, 0.f, c->stream), "fill"))) return rc;
+    StepArgs a = base_args(c, mv, K_BORN);
+    a.dv = dv;
+    Fields f{w.F[0], w.F[1], w.F[2], w.F[3]};
+    if ((rc = ev_begin(c, K_BORN))) return rc;
+    if ((rc = scat_range(c, a, 0, p.nt_max, samp, w.Dh, 0, f))) return rc;
+    if ((rc = ev_end(c))) return rc;
+    float *data = static_cast<float *>(c->pairdata.p);
+    TraceArgs t = trace_args(c);
     t.tm_in = samp;
     t.alpha = 1.f;
-    t.tr_in = d_obs;
-    t.beta = -1.f;
-    t.tm_out = samp;
-    t.tr_out = d_syn;
-    const int64_t nblk = int64_t((p.Q + 63) / 64) * ((p.nt_max + 63) / 64);
-    if ((rc = ensure(c, c->partials, size_t(std::max<int64_t>(nblk, 1)) * sizeof(double))) ||
-        (rc = ensure(c, c->misfit, sizeof(double))))
-        return rc;
-    t.partials = static_cast<double *>(c->partials.p);
-    if ((rc = other(c, launch_traces(t, c->stream, nullptr), "residual"))) return rc;
-    if (nblk > 0) {
-        if ((rc = other(c, launch_sum_partials(t.partials, nblk, static_cast<double *>(c->misfit.p), c->stream),
-                        "misfit")))
-            return rc;
-    } else {
-        HIPCHK(c, hipMemsetAsync(c->misfit.p, 0, sizeof(double), c->stream));
-    }
-    if (misfit)
-        HIPCHK(c, hipMemcpyAsync(c->h_misfit, c->misfit.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    if ((rc = backward_sweep(c, v, w, grad))) return rc;
-    if (misfit) {
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        *misfit = *c->h_misfit;
-    }
+    t.tr_out = data;
+    if ((rc = other(c, launch_traces(t, c->stream, nullptr), "traces"))) return rc;
+    TraceArgs t2 = trace_args(c);
+    t2.tr_in = data;
+    t2.beta = 1.f;
+    t2.tm_out = samp;
+    if ((rc = other(c, launch_traces(t2, c->stream, nullptr), "adjoint sources"))) return rc;
+    if ((rc = backward_sweep(c, mv, w, img))) return rc;
     return finish_stats(c);
 }
 
@@ -1418,50 +1619,6 @@ int fwi_misfit(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *
     HIPCHK(c, hipStreamSynchronize(c->stream));
     *misfit = *c->h_misfit;
     return finish_stats(c);
-}
-
-// Joint Born steps lo .. hi-1 (background u in U0/U1, scattered du in
-// D0/D1, alternating by step parity); du samples to samp + n*Q; with dh the
-// background's D^n goes to slot n - dlo of dh.
-int born_range(fwi_ctx *c, const StepArgs &a, int lo, int hi, float *samp, float *dh, int dlo, float *U0, float *U1,
-               float *D0, float *D1)
-{
-    if (lo >= hi) return FWI_OK;
-    const Plan &p = c->plan;
-    const int64_t gf = p.img_floats;
-    std::vector<char> key;
-    key_put(key, 'B');
-    key_put(key, a);
-    key_put(key, lo);
-    key_put(key, hi);
-    key_put(key, samp);
-    key_put(key, dh);
-    key_put(key, dlo);
-    key_put(key, U0);
-    key_put(key, U1);
-    key_put(key, D0);
-    key_put(key, D1);
-    Fields none{};
-    return run_loop(c, key, none, [&](Fields &) {
-        StepArgs b = a;
-        for (int n = lo; n < hi; ++n) {
-            b.n = n;
-            b.nwaves = c->tile[K_BORN].prefix[p.active_slots(n)];
-            b.cur = n % 2 == 0 ? U0 : U1;
-            b.prev = n % 2 == 0 ? U1 : U0;
-            b.cur2 = n % 2 == 0 ? D0 : D1;
-            b.prev2 = n % 2 == 0 ? D1 : D0;
-            b.samp = samp + size_t(n) * p.Q;
-            b.dslot = dh ? dh + size_t(n - dlo) * gf : nullptr;
-            HIPCHK(c, launch_born_step(b, c->stream));
-            const double upd = step_updates(p, n);
-            c->stats.cell_updates += 2 * upd;
-            c->stats.stencil_launches += 1;
-            c->stats.n_born += 1;
-            c->stats.bytes_born += upd * (kBytesBorn + (dh ? kBytesEmit : 0.0));
-        }
-        return int(FWI_OK);
-    });
 }
 
 int born_demig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v0, const float *dv, float *dd)
@@ -1503,61 +1660,9 @@ int born_pair(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v
 {
     int rc = begin_call(c, g, geo);
     if (rc) return rc;
-    const Plan &p = c->plan;
     if (!img) return set_err(c, FWI_EINVAL, "img is NULL");
     if ((rc = check_model(c, v0, "v0")) || (rc = check_perturbation(c, dv)) || (rc = prepare(c, v0))) return rc;
-    Sweep w;
-    if ((rc = choose_segments(c, &w.k, &w.nseg))) return rc;
-    const int k = w.k, nseg = w.nseg;
-    c->stats.ckpt_every = nseg > 1 ? k : 0;
-    c->stats.n_segments = nseg;
-    const int64_t ff = p.field_floats, gf = p.img_floats;
-    if ((rc = ensure(c, c->fields, size_t(8 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
-        (rc = ensure(c, c->dhist, size_t(k) * gf * 4)) ||
-        (rc = ensure(c, c->ckpt, size_t(std::max(0, nseg - 1)) * 2 * ff * 4)) ||
-        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)) ||
-        (!dd && (rc = ensure(c, c->pairdata, size_t(std::max<int64_t>(p.data_size, 1)) * 4))))
-        return rc;
-    float *F = static_cast<float *>(c->fields.p);
-    for (int i = 0; i < 4; ++i) {
-        w.F[i] = F + i * ff;
-        w.A[i] = F + (4 + i) * ff;
-    }
-    w.Dh = static_cast<float *>(c->dhist.p);
-    w.CK = static_cast<float *>(c->ckpt.p);
-    w.G = static_cast<float *>(c->image.p);
-    float *samp = static_cast<float *>(c->samples.p);
-    hipStream_t st = c->stream;
-    if ((rc = other(c, launch_fill(w.F[0], 4 * ff, 0.f, st), "fill"))) return rc;
-    StepArgs a = base_args(c, v0, K_BORN);
-    a.dv = dv;
-    float *U0 = w.F[0], *U1 = w.F[1], *D0 = w.F[2], *D1 = w.F[3];
-    if ((rc = ev_begin(c, K_BORN))) return rc;
-    for (int sgi = 0; sgi < nseg; ++sgi) {
-        const int lo = sgi * k, hi = std::min(p.nt_max, lo + k);
-        const bool last = sgi == nseg - 1;
-        if (!last) {
-            // (u^{lo-1}, u^lo): the fields the step at n = lo reads as prev, cur
-            float *ckp = w.CK + size_t(sgi) * 2 * ff;
-            HIPCHK(c, hipMemcpyAsync(ckp, lo % 2 == 0 ? U1 : U0, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
-            HIPCHK(c, hipMemcpyAsync(ckp + ff, lo % 2 == 0 ? U0 : U1, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
-        }
-        if ((rc = born_range(c, a, lo, hi, samp, last ? w.Dh : nullptr, lo, U0, U1, D0, D1))) return rc;
-    }
-    if ((rc = ev_end(c))) return rc;
-    // samples -> packed data J dv -> adjoint sources (co-located receivers add)
-    float *data = dd ? dd : static_cast<float *>(c->pairdata.p);
-    TraceArgs t = trace_args(c);
-    t.tm_in = samp;
-    t.alpha = 1.f;
-    t.tr_out = data;
-    if ((rc = other(c, launch_traces(t, st, nullptr), "traces"))) return rc;
-    TraceArgs t2 = trace_args(c);
-    t2.tr_in = data;
-    t2.beta = 1.f;
-    t2.tm_out = samp;
-    if ((rc = other(c, launch_traces(t2, st, nullptr), "adjoint sources"))) return rc;
-    if ((rc = backward_sweep(c, v0, w, img))) return rc;
+    if ((rc = pair_core(c, v0, dv, dd, img))) return rc;
     return finish_stats(c);
 }
 

@@ -43,6 +43,11 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks)
     return x * per + min(x, rem) + k;
 }
 
+// Receiver-row cursor value once a wave's list of receiver rows is used up.
+// It must never equal a row index: the two-level kernel walks rows from 4
+// (level 1) and 8 (level 2) above the padded box, so -1 is a real row there.
+constexpr int kNoRow = -(1 << 30);
+
 __device__ __forceinline__ float sponge_a(float sh)
 {
     return __builtin_amdgcn_rcpf(1.0f + sh);
@@ -174,7 +179,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     float *pv = A.prev + (S.f_off - int64_t(kRowsAbove) * P);
     const Rsrc rcur = view(cu), rprev = view(pv), rv = view(A.v);
     const Rsrc rg = view((FL & F_IMAGE) ? A.G + S.g_off : A.v);
-    const Rsrc rd = view((FL & (F_IMAGE | F_EMIT)) ? A.dslot + S.g_off : A.v);
+    const Rsrc rd = view((FL & (F_IMAGE | F_EMIT | F_SCAT)) ? A.dslot + S.g_off : A.v);
+    const Rsrc rdv = view((FL & F_SCAT) ? A.dv : A.v);
 
     bool valid[CW];
     unsigned jm[CW];
@@ -203,7 +209,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     // prefetched loads of one row; PD rows are in flight ahead of the row
     // being computed (a ring of PD statically indexed slots)
     struct Pre {
-        float q[CW], pv[CW], v[CW], d[CW], g[CW];
+        float q[CW], pv[CW], v[CW], d[CW], g[CW], dv[CW];
         float4 h;
     };
     auto prefetch = [&](int z, Pre &pre) {
@@ -219,11 +225,16 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
             bld<CW>(rd, jl, 4 * z * P, pre.d);
             bld<CW>(rg, jl, 4 * z * P, pre.g);
         }
+        if (FL & F_SCAT) {
+            bld<CW>(rd, jl, 4 * z * P, pre.d);
+#pragma unroll
+            for (int k = 0; k < CW; ++k) pre.dv[k] = bld1(rdv, jm[k], vo);
+        }
     };
 
     int rr = W.rr0;
-    int rrow = -1;
-    if (FL & (F_SAMPLE | F_INJECT)) rrow = rr < W.rr1 ? A.rrows[rr].row : -1;
+    int rrow = kNoRow;
+    if (FL & (F_SAMPLE | F_INJECT)) rrow = rr < W.rr1 ? A.rrows[rr].row : kNoRow;
     const float wsrc = (FL & F_SRC) ? A.wav[S.wav_off + A.n] * A.ih2 : 0.0f;
     const int src_k = S.src_j - j0;          // column of the source in this lane, if 0..CW-1
 
@@ -249,7 +260,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
 #pragma unroll
                 for (int k = 0; k < CW; ++k) qi[k] = A.rmap[mo + k];
                 ++rr;
-                rrow = rr < W.rr1 ? A.rrows[rr].row : -1;
+                rrow = rr < W.rr1 ? A.rrows[rr].row : kNoRow;
             }
         }
         const int ddz = max(max(nb - z, z - (A.NZ - 1 - nb)), 0);
@@ -269,6 +280,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
                 a = sponge_a(sh);
             }
             Dv[k] = cc * lap;
+            // scattered field: the linearised velocity term (2 dV / V) D^n
+            if (FL & F_SCAT) Dv[k] = __builtin_fmaf(2.0f * c.dv[k] / c.v[k], c.d[k], Dv[k]);
             out[k] = leapfrog(q[4][k], c.pv[k], Dv[k], a, sh);
         }
         const int ro = 4 * (z + kRowsAbove) * P, go = 4 * z * P;
@@ -407,11 +420,11 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
     prefetch(t0);
 
     int rr1 = W.rr0, rr2 = W.rr0;
-    int rrow1 = -1, rrow2 = -1;
+    int rrow1 = kNoRow, rrow2 = kNoRow;
     if (FL & (F_SAMPLE | F_INJECT)) {
         // skip receiver rows above the first level-1 row
         while (rr1 < W.rr1 && A.rrows[rr1].row < t0) ++rr1;
-        rrow1 = rr1 < W.rr1 ? A.rrows[rr1].row : -1;
+        rrow1 = rr1 < W.rr1 ? A.rrows[rr1].row : kNoRow;
         rr2 = rr1;
         rrow2 = rrow1;
     }
@@ -453,7 +466,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 #pragma unroll
                 for (int k = 0; k < CW; ++k) qi1[k] = A.rmap[mo + k];
                 ++rr1;
-                rrow1 = rr1 < W.rr1 ? A.rrows[rr1].row : -1;
+                rrow1 = rr1 < W.rr1 ? A.rrows[rr1].row : kNoRow;
             }
         }
         const bool row_in = t >= 0 && t < NZ;
@@ -512,7 +525,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 #pragma unroll
                 for (int k = 0; k < CW; ++k) qi2[k] = A.rmap[mo + k];
                 ++rr2;
-                rrow2 = rr2 < W.rr1 ? A.rrows[rr2].row : -1;
+                rrow2 = rr2 < W.rr1 ? A.rrows[rr2].row : kNoRow;
             }
         }
         if (r2 >= W.z0) {   // r2 < z1 always holds
@@ -641,7 +654,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
     prefetch(W.z0);
 
     int rr = W.rr0;
-    int rrow = rr < W.rr1 ? A.rrows[rr].row : -1;
+    int rrow = rr < W.rr1 ? A.rrows[rr].row : kNoRow;
     const float wsrc = A.wav[S.wav_off + A.n] * A.ih2;
     const int src_k = S.src_j - j0;
 
@@ -687,7 +700,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
 #pragma unroll
             for (int k = 0; k < CW; ++k) qi[k] = A.rmap[mo + k];
             ++rr;
-            rrow = rr < W.rr1 ? A.rrows[rr].row : -1;
+            rrow = rr < W.rr1 ? A.rrows[rr].row : kNoRow;
         }
         const int ddz = max(max(nb - z, z - (A.NZ - 1 - nb)), 0);
         const float dz2 = float(ddz * ddz);
@@ -726,6 +739,12 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
                 r[m][k] = r[m + 1][k];
             }
     }
+}
+
+__global__ void k_scale(const float *x, float a, float *y, int64_t n)
+{
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = a * x[i];
 }
 
 __global__ void k_fill(float *p, int64_t n, float val)
@@ -926,6 +945,9 @@ hipError_t launch_step_cw(int flags, const StepArgs &a, hipStream_t s)
     case F_INJECT | F_IMAGE:
         hipLaunchKernelGGL((k_step<F_INJECT | F_IMAGE, CW, PD>), grid, block, 0, s, a);
         break;
+    case F_SAMPLE | F_SCAT:
+        hipLaunchKernelGGL((k_step<F_SAMPLE | F_SCAT, CW, PD>), grid, block, 0, s, a);
+        break;
     default:
         return hipErrorInvalidValue;
     }
@@ -982,6 +1004,15 @@ hipError_t launch_born_step(const StepArgs &a, hipStream_t s)
         if (a.cw == 2) hipLaunchKernelGGL((k_born_step<2, false>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_born_step<1, false>), grid, block, 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(const float *x, float a, float *y, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_scale, dim3(unsigned(blocks)), dim3(256), 0, s, x, a, y, n);
     return hipGetLastError();
 }
 

@@ -62,6 +62,7 @@ enum StepFlags : int {
     F_INJECT = 4,  // add the adjoint source at receiver cells
     F_EMIT = 8,    // store D^n = V^2 dt^2 (L8 u^n + s^n)
     F_IMAGE = 16,  // accumulate G += out * D^n
+    F_SCAT = 32,   // scattered field: source (2 dV / V) D^n from the stored background history
 };
 
 struct StepArgs {
@@ -134,6 +135,8 @@ hipError_t launch_step(int flags, const StepArgs &a, hipStream_t s);
 hipError_t launch_step2(int flags, const StepArgs &a, hipStream_t s);
 hipError_t launch_born_step(const StepArgs &a, hipStream_t s);
 hipError_t launch_fill(float *p, int64_t n, float val, hipStream_t s);
+// y = a x (n floats)
+hipError_t launch_scale(const float *x, float a, float *y, int64_t n, hipStream_t s);
 hipError_t launch_model_check(const float *v, int64_t n, float *out3, hipStream_t s);
 hipError_t launch_traces(const TraceArgs &a, hipStream_t s, int64_t *nblocks_out);
 hipError_t launch_sum_partials(const double *part, int64_t n, double *out, hipStream_t s);

@@ -175,8 +175,16 @@ class FwiRun:
         t = {}
         _sync()
         ta = time.perf_counter()
-        g_phi, phi, _ = self.fctx.fwi_gradient(self.grid, acq, self.v, d_obs)
-        self._count(2)
+        use_net = self.net is not None and (o.net_iters is None or it < o.net_iters)
+        dm1 = None
+        if use_net and not o.mute_rows:
+            # gradient and J^T J g in one call (the pair reuses the gradient's
+            # stored imaging history when it fits in memory)
+            g_phi, phi, dm1 = self.fctx.gradient_pair(self.grid, acq, self.v, d_obs, scale=-1.0)
+            self._count(4)
+        else:
+            g_phi, phi, _ = self.fctx.fwi_gradient(self.grid, acq, self.v, d_obs)
+            self._count(2)
         _sync()
         t["gradient"] = time.perf_counter() - ta
         g = -g_phi                                   # the paper's gradient
@@ -188,12 +196,12 @@ class FwiRun:
         a_qn = None              # quasi-Newton trial step along p
         if o.method in ("bb", "lbfgs"):
             p, a_qn = self._qn_direction(g_phi)
-        use_net = self.net is not None and (o.net_iters is None or it < o.net_iters)
         if use_net:
             ta = time.perf_counter()
-            # the pair J^T J g (demigration + migration, 2 solves) in one joint sweep
-            dm1 = self.fctx.born_pair(self.grid, acq, self.v, g.contiguous())
-            self._count(2)
+            if dm1 is None:
+                # the pair J^T J g (demigration + migration, 2 solves) in one joint sweep
+                dm1 = self.fctx.born_pair(self.grid, acq, self.v, g.contiguous())
+                self._count(2)
             _sync()
             t["pair"] = time.perf_counter() - ta
             ta = time.perf_counter()

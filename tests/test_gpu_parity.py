@@ -319,3 +319,40 @@ def test_born_pair_equals_demig_then_mig(ctx, case):
     e = rel(host(img), oracle.born_pair(grid, acq, v0, dv))
     print("born_pair rel err vs oracle", e)
     assert e < TOL_IMAGE
+
+
+@pytest.mark.parametrize("case", ["ragged", "two_layer", "two_layer_ckpt"])
+def test_gradient_pair(ctx, case):
+    """Gradient and doubly migrated image in one call: the gradient and
+    misfit are those of fwi_gradient bit for bit; the image matches
+    born_pair(v, -grad) (bitwise when the history is checkpointed and the
+    pair runs its own sweep, to FP32 rounding when the scattered field is
+    driven by the stored history) and the oracle's J^T J."""
+    from dataclasses import replace
+    if case == "ragged":
+        wl = wl32(configs.ragged_small())
+        grid = wl.grid
+    else:
+        wl = wl32(configs.two_layer(nt=400))
+        grid = replace(wl.grid, ckpt_every=37) if case == "two_layer_ckpt" else wl.grid
+    acq = wl.acq
+    print(f"[parity] gradient_pair {case}", flush=True)
+    v0 = f32(wl.v0).astype(np.float64)
+    d_obs = f32(oracle.forward(grid, acq, f32(wl.v_true).astype(np.float64))).astype(np.float64)
+    g_ref, phi_ref, _ = ctx.fwi_gradient(grid, acq, dev(v0), dev(d_obs))
+    grad, phi, img = ctx.gradient_pair(grid, acq, dev(v0), dev(d_obs), scale=-1.0)
+    st = ctx.stats()
+    assert torch.equal(grad, g_ref)
+    assert phi == phi_ref
+    pair = ctx.born_pair(grid, acq, dev(v0), -g_ref)
+    if case == "two_layer_ckpt":
+        assert st["n_segments"] > 1
+        assert torch.equal(img, pair)
+    else:
+        assert st["n_segments"] == 1
+        e = rel(host(img), host(pair))
+        print("fused pair vs born_pair", e)
+        assert e < 1e-5
+    e = rel(host(img), oracle.born_pair(grid, acq, v0, -host(grad)))
+    print("gradient_pair image rel err vs oracle", e)
+    assert e < TOL_IMAGE
