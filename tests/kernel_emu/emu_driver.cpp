@@ -1,0 +1,179 @@
+// Driver of the host kernel emulation: runs every public entry point of the
+// library through the C ABI on a geometry read from a text file, for a list
+// of tilings (or the autotuner), and the deblurring network for one
+// configuration. Any out-of-bounds kernel access aborts the process with an
+// AddressSanitizer report.
+//
+//   emu_driver fd  <geom> <spec>...      spec: "auto" or "cw,rows,levels,prefetch,ckpt_every"
+//   emu_driver net <depth> <base> <H> <W> <nz> <nx>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "deblur.h"
+#include "fwi.h"
+
+void emu_print_launches();
+
+static fwi_ctx *g_ctx = nullptr;
+static deblur_net *g_net = nullptr;
+
+#define CK(call)                                                                                 \
+    do {                                                                                         \
+        int rc_ = (call);                                                                        \
+        if (rc_) {                                                                               \
+            std::fprintf(stderr, "FAIL %s rc=%d: %s\n", #call, rc_, fwi_last_error(g_ctx));     \
+            std::exit(1);                                                                        \
+        }                                                                                        \
+    } while (0)
+#define DK(call)                                                                                 \
+    do {                                                                                         \
+        int rc_ = (call);                                                                        \
+        if (rc_) {                                                                               \
+            std::fprintf(stderr, "FAIL %s rc=%d: %s\n", #call, rc_, deblur_last_error(g_net));  \
+            std::exit(1);                                                                        \
+        }                                                                                        \
+    } while (0)
+
+template <class T>
+static T *dev(size_t n)
+{
+    return static_cast<T *>(std::calloc(n ? n : 1, sizeof(T)));
+}
+
+static int run_fd(int argc, char **argv)
+{
+    const char *path = argv[2];
+    FILE *f = std::fopen(path, "r");
+    if (!f) return 2;
+    fwi_grid g{};
+    int S = 0, has_win = 0, has_nt = 0, shared = 1;
+    if (std::fscanf(f, "%d %d %d %f %f %d %f %f %d %d %d %d", &g.nz, &g.nx, &g.nb, &g.h, &g.dt, &g.nt_max, &g.v_ref,
+                    &g.R, &S, &has_win, &has_nt, &shared) != 12)
+        return 2;
+    std::vector<int32_t> sz(S), sx(S), wx0(S), wnx(S), nt(S), rz, rx;
+    std::vector<int64_t> rptr(1, 0);
+    for (int s = 0; s < S; ++s) {
+        int nr = 0;
+        if (std::fscanf(f, "%d %d %d %d %d %d", &sz[s], &sx[s], &wx0[s], &wnx[s], &nt[s], &nr) != 6) return 2;
+        for (int i = 0; i < nr; ++i) {
+            int z, x;
+            if (std::fscanf(f, "%d %d", &z, &x) != 2) return 2;
+            rz.push_back(z);
+            rx.push_back(x);
+        }
+        rptr.push_back(rptr.back() + nr);
+    }
+    std::vector<float> wav(size_t(shared ? 1 : S) * g.nt_max);
+    for (auto &w : wav)
+        if (std::fscanf(f, "%f", &w) != 1) return 2;
+    const size_t nm = size_t(g.nz) * g.nx;
+    std::vector<float> hv0(nm), hvt(nm);
+    for (auto &v : hv0)
+        if (std::fscanf(f, "%f", &v) != 1) return 2;
+    for (auto &v : hvt)
+        if (std::fscanf(f, "%f", &v) != 1) return 2;
+    std::fclose(f);
+    fwi_geom geo{};
+    geo.nshots = S;
+    geo.src_z = sz.data();
+    geo.src_x = sx.data();
+    geo.win_x0 = has_win ? wx0.data() : nullptr;
+    geo.win_nx = has_win ? wnx.data() : nullptr;
+    geo.nt = has_nt ? nt.data() : nullptr;
+    geo.rec_ptr = rptr.data();
+    geo.rec_z = rz.data();
+    geo.rec_x = rx.data();
+    geo.wavelet = wav.data();
+    geo.wavelet_shared = shared;
+    int64_t ndata = 0;
+    for (int s = 0; s < S; ++s) ndata += (rptr[s + 1] - rptr[s]) * (has_nt ? nt[s] : g.nt_max);
+
+    for (int a = 3; a < argc; ++a) {
+        fwi_ctx *c = nullptr;
+        if (fwi_ctx_create(0, nullptr, &c)) return 3;
+        g_ctx = c;
+        CK(fwi_ctx_set_graphs(c, 0));
+        const std::string spec = argv[a];
+        int cw = 0, rows = 0, tb = 0, pd = 0, ck = 0;
+        if (spec != "auto") {
+            if (std::sscanf(spec.c_str(), "%d,%d,%d,%d,%d", &cw, &rows, &tb, &pd, &ck) != 5) return 2;
+            CK(fwi_ctx_set_tiling(c, -1, cw, rows, tb, pd));
+        }
+        g.ckpt_every = ck;
+        float *v0 = dev<float>(nm), *vt = dev<float>(nm), *grad = dev<float>(nm), *img = dev<float>(nm);
+        float *grad2 = dev<float>(nm), *img2 = dev<float>(nm);
+        float *dobs = dev<float>(size_t(ndata)), *dd = dev<float>(size_t(ndata)), *dsyn = dev<float>(size_t(ndata));
+        std::memcpy(v0, hv0.data(), nm * 4);
+        std::memcpy(vt, hvt.data(), nm * 4);
+        double phi = 0;
+        CK(fwi_forward(c, &g, &geo, vt, dobs));
+        CK(fwi_gradient_pair(c, &g, &geo, v0, dobs, grad, &phi, -1.f, img));
+        CK(fwi_gradient(c, &g, &geo, v0, dobs, grad2, &phi, dsyn));
+        CK(born_pair(c, &g, &geo, v0, grad, dd, img2));
+        CK(born_demig(c, &g, &geo, v0, grad, dd));
+        CK(born_mig(c, &g, &geo, v0, dd, img2));
+        CK(fwi_misfit(c, &g, &geo, v0, dobs, &phi));
+        fwi_stats st{};
+        fwi_ctx_get_stats(c, &st);
+        std::printf("ok %s tile_fwd=%d,%d,%d,%d segments=%d\n", spec.c_str(), st.tile_cw[0], st.tile_rows[0],
+                    st.tile_levels[0], st.tile_prefetch[0], st.n_segments);
+        std::fflush(stdout);
+        for (float *p : {v0, vt, grad, img, grad2, img2, dobs, dd, dsyn}) std::free(p);
+        fwi_ctx_destroy(c);
+        g_ctx = nullptr;
+    }
+    return 0;
+}
+
+static int run_net(int argc, char **argv)
+{
+    if (argc < 8) return 2;
+    deblur_cfg cfg{std::atoi(argv[2]), std::atoi(argv[3]), 0.2f, std::atoi(argv[4]), std::atoi(argv[5])};
+    const int nz = std::atoi(argv[6]), nx = std::atoi(argv[7]);
+    fwi_ctx *c = nullptr;
+    if (fwi_ctx_create(0, nullptr, &c)) return 3;
+    g_ctx = c;
+    if (deblur_create(c, &cfg, 7, &g_net)) return 4;
+    const size_t n = size_t(nz) * nx, P = size_t(cfg.in_h) * cfg.in_w;
+    float *x = dev<float>(n), *y = dev<float>(n), *q = dev<float>(n);
+    float *xr = dev<float>(P), *tr = dev<float>(P), *yr = dev<float>(P);
+    uint64_t s = 12345;
+    auto rnd = [&]() {
+        s = s * 6364136223846793005ULL + 1442695040888963407ULL;
+        return float(int64_t(s >> 33) % 2001 - 1000) * 1e-3f;
+    };
+    for (size_t i = 0; i < n; ++i) {
+        x[i] = rnd();
+        y[i] = rnd();
+    }
+    for (size_t i = 0; i < P; ++i) {
+        xr[i] = rnd();
+        tr[i] = rnd();
+    }
+    float hist[2];
+    DK(deblur_train(c, g_net, x, y, nz, nx, 1, 1e-3f, hist));
+    DK(deblur_apply(c, g_net, x, nz, nx, q));
+    DK(deblur_forward_raw(c, g_net, xr, yr));
+    int64_t np = 0;
+    DK(deblur_num_params(g_net, &np));
+    std::vector<float> grads(static_cast<size_t>(np));
+    double loss = 0;
+    DK(deblur_grad_raw(c, g_net, xr, tr, &loss, grads.data()));
+    std::printf("ok net depth=%d base=%d %dx%d\n", cfg.depth, cfg.base_ch, cfg.in_h, cfg.in_w);
+    deblur_destroy(g_net);
+    fwi_ctx_destroy(c);
+    for (float *p : {x, y, q, xr, tr, yr}) std::free(p);
+    return 0;
+}
+
+int main(int argc, char **argv)
+{
+    if (argc < 2) return 2;
+    const std::string what = argv[1];
+    const int rc = what == "fd" ? run_fd(argc, argv) : what == "net" ? run_net(argc, argv) : 2;
+    if (rc == 0) emu_print_launches();
+    return rc;
+}
