@@ -30,9 +30,14 @@ BF16_PEAK_TFLOPS = 2500.0      # dense bf16 matrix-core peak of MI355X
 # see profiles/stencil_kernels_layered_600x200_hbm_counters.md). Valid only
 # for the kernel source it was measured on: reported as null otherwise.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 per launch of the autotuned adjoint
-    # kernel (k_step<INJECT|IMAGE, 1 column per lane, 2 rows prefetched>)
-    "stencil_adj": {"bytes": 276.4e6, "kernels_sha1": "bcac09e2073d7dfcd6b98fcb4754d5b558b9a65f"},
+    # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 per launch, by the tiling the
+    # class runs with: "columns per lane, levels per launch, rows prefetched"
+    # (two-level launches advance two time levels)
+    "kernels_sha1": "422a8dee6d13898c8dd016839c36466a40e9c9bc",
+    "stencil_adj": {"1,1,1": 274.9e6, "1,1,2": 276.4e6, "1,2,1": 377.5e6, "2,1,1": 272.6e6, "2,1,2": 272.7e6,
+                    "2,2,1": 382.4e6},
+    "stencil_fwd": {"1,1,1": 185.1e6, "1,1,2": 185.0e6, "1,2,1": 288.4e6, "2,1,1": 188.2e6, "2,1,2": 186.7e6,
+                    "2,2,1": 293.4e6},
 }
 
 
@@ -314,8 +319,12 @@ def main():
     dom = max(kinds, key=lambda k: acc.get(kinds[k][0], 0.0))
     kms, kn, kb = (acc[x] for x in kinds[dom])
     achieved = (kb / kn) / ((kms / kn) * 1e-3) / 1e9
-    meas = MEASURED_TRAFFIC.get(dom)
-    traffic = meas["bytes"] if meas and meas["kernels_sha1"] == kernels_sha1() else None
+    st = st_last
+    cls = {"stencil_fwd": 0, "stencil_adj": 1, "stencil_born": 2}[dom]
+    tkey = f"{st['tile_cw'][cls]},{st['tile_levels'][cls]},{st['tile_prefetch'][cls]}"
+    traffic = None
+    if MEASURED_TRAFFIC["kernels_sha1"] == kernels_sha1():
+        traffic = MEASURED_TRAFFIC.get(dom, {}).get(tkey)
     out = {
         "metric": "FD cell-updates/s & % HBM roofline; FWI iters+time to model error vs plain",
         "value": value,

@@ -386,6 +386,25 @@ def time_to_error(plain: list, net: list) -> dict:
     return out
 
 
+def rtm_scores(fctx, grid, acq, wl, fmax, finals, observe) -> dict:
+    """Image score (normalised cross-correlation with the image migrated in
+    the true model) of the RTM image of each final model and of the initial
+    model, from the highest band's observed data with the direct arrival
+    muted; the top 10 rows (source/receiver footprint) are left out."""
+    from .rtm import direct_mute, image_score, rtm_image
+    acq_b = band_acq(acq, grid, fmax)
+    d_obs = observe(acq_b)
+    w = np.abs(np.asarray(acq_b.wavelet, np.float64))
+    t_peak = float(np.argmax(w)) * grid.dt
+    mask = torch.from_numpy(direct_mute(grid, acq_b, float(np.min(wl.v0[0])), t_peak + 1.0 / fmax,
+                                        0.5 / fmax)).to(d_obs.device)
+    dev = d_obs.device
+    ref = rtm_image(fctx, grid, acq_b, torch.from_numpy(wl.v_true.astype(np.float32)).to(dev), d_obs, mask)
+    models = {"initial": torch.from_numpy(wl.v0.astype(np.float32)).to(dev), **finals}
+    return {name: round(image_score(rtm_image(fctx, grid, acq_b, v, d_obs, mask), ref, top=10), 4)
+            for name, v in models.items()}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="plain vs network-preconditioned FWI on a seeded workload")
     ap.add_argument("--workload", default="salt_848x176")
@@ -399,6 +418,9 @@ def main(argv=None):
     ap.add_argument("--train-first", type=int, default=500)
     ap.add_argument("--train", type=int, default=200)
     ap.add_argument("--out", default="")
+    ap.add_argument("--rtm", action="store_true",
+                    help="after the runs, score the RTM image of each final model (and of the initial model) "
+                         "against the image migrated with the true model")
     ap.add_argument("--plain-log", default="",
                     help="log of an earlier plain run (JSON lines): the net run stops at its final "
                          "model error and the time-to-error summary is computed against it")
@@ -430,6 +452,7 @@ def main(argv=None):
             out["plain"] = [r for r in (json.loads(x) for x in f if x.startswith("{"))
                             if r.get("method") == "plain"]
     methods = {"both": ["plain", "net"], "all": ["plain", "bb", "lbfgs", "net"]}.get(args.method, [args.method])
+    finals = {}
     for method in methods:
         target = out["plain"][-1]["model_error"] if method == "net" and "plain" in out else None
         if args.method == "all":
@@ -439,12 +462,15 @@ def main(argv=None):
                           target_error=target, net_iters=args.net_iters or None)
         run = FwiRun(fctx, grid, acq, wl.v0, opts, v_true=wl.v_true, log=log)
         out[method] = run.run(observe)
+        finals[method] = run.v.clone()
         if run.net is not None:
             run.net.close()
     if "plain" in out and "net" in out:
         summary = time_to_error(out["plain"], out["net"])
         summary["workload"] = wl.name
         log(json.dumps({"summary": summary}))
+    if args.rtm:
+        log(json.dumps({"rtm": rtm_scores(fctx, grid, acq, wl, bands[-1], finals, observe)}))
     if args.out:
         with open(args.out, "w") as f:
             f.write("\n".join(lines) + "\n")
