@@ -320,7 +320,8 @@ def main():
     kms, kn, kb = (acc[x] for x in kinds[dom])
     achieved = (kb / kn) / ((kms / kn) * 1e-3) / 1e9
     st = st_last
-    cls = {"stencil_fwd": 0, "stencil_adj": 1, "stencil_born": 2}[dom]
+    # the step's Born-class time is the scattered-field pass (tiling class 3)
+    cls = {"stencil_fwd": 0, "stencil_adj": 1, "stencil_born": 3}[dom]
     tkey = f"{st['tile_cw'][cls]},{st['tile_levels'][cls]},{st['tile_prefetch'][cls]}"
     traffic = None
     if MEASURED_TRAFFIC["kernels_sha1"] == kernels_sha1():
@@ -350,7 +351,7 @@ def main():
             "wall_s": wall,
             "tiles_cols_rows_levels_prefetch": {k: [st_last["tile_cw"][i], st_last["tile_rows"][i],
                                                     st_last["tile_levels"][i], st_last["tile_prefetch"][i]]
-                                                for i, k in enumerate(("fwd", "adj", "born"))},
+                                                for i, k in enumerate(("fwd", "adj", "born", "scat"))},
         },
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -114,8 +114,9 @@ typedef struct {
     /* tiling used by the forward, adjoint and Born kernels: columns per
        lane (strip width 64 * cols), rows streamed per wave and time levels
        advanced per launch */
-    int32_t tile_cw[3], tile_rows[3], tile_levels[3];
-    int32_t tile_prefetch[3]; /* rows prefetched ahead (one-level kernels) */
+    /* tilings by class: forward, adjoint, joint Born, scattered field */
+    int32_t tile_cw[4], tile_rows[4], tile_levels[4];
+    int32_t tile_prefetch[4]; /* rows prefetched ahead (one-level kernels) */
     int64_t graph_launches;   /* time loops replayed from a captured HIP graph */
     int64_t graph_captures;   /* time loops captured (first run of a loop) */
 } fwi_stats;
@@ -136,9 +137,11 @@ int fwi_ctx_set_mem_budget(fwi_ctx *ctx, int64_t bytes);
  * so the reported per-launch time includes the (small) gaps between
  * back-to-back launches; adds a stream sync at the end of each call. */
 int fwi_ctx_set_profiling(fwi_ctx *ctx, int enable);
-/* Tiling of the step kernels. kernel: 0 forward, 1 adjoint, 2 Born, -1 all;
+/* Tiling of the step kernels. kernel: 0 forward, 1 adjoint, 2 joint Born,
+ * 3 scattered field driven by a stored history (fwi_gradient_pair), -1 all;
  * cols_per_lane 1 or 2, rows_per_wave >= 1, levels_per_launch 1 or 2 (the
- * Born kernel always advances one level) and prefetch_rows 1 or 2 (rows of
+ * Born and scattered-field kernels always advance one level; the joint Born
+ * kernel prefetches one row) and prefetch_rows 1 or 2 (rows of
  * loads issued ahead by one-level kernels; 0 = 2) force a tiling; all zero
  * returns the kernel to the autotuner. Results do not depend on the tiling:
  * every variant computes each cell with the same arithmetic. */

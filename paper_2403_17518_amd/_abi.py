@@ -45,8 +45,8 @@ class fwi_stats(C.Structure):
                 ("n_fwd", C.c_int64), ("n_adj", C.c_int64), ("n_born", C.c_int64),
                 ("bytes_fwd", C.c_double), ("bytes_adj", C.c_double),
                 ("bytes_born", C.c_double),
-                ("tile_cw", C.c_int32 * 3), ("tile_rows", C.c_int32 * 3),
-                ("tile_levels", C.c_int32 * 3), ("tile_prefetch", C.c_int32 * 3),
+                ("tile_cw", C.c_int32 * 4), ("tile_rows", C.c_int32 * 4),
+                ("tile_levels", C.c_int32 * 4), ("tile_prefetch", C.c_int32 * 4),
                 ("graph_launches", C.c_int64), ("graph_captures", C.c_int64)]
 
     def as_dict(self) -> dict:

@@ -82,7 +82,12 @@ struct Tiling {
     DevBuf d_waves, d_rrows, d_rmap;
 };
 
-enum KClass { K_FWD = 0, K_ADJ = 1, K_BORN = 2, K_OTHER = 3 };
+// tiling classes: forward, adjoint, joint Born, scattered field from a stored
+// history (kScatClass tilings: one level per launch)
+enum KClass { K_FWD = 0, K_ADJ = 1, K_BORN = 2, K_SCAT = 3, K_OTHER = 4 };
+constexpr int kClasses = 4;
+// classes whose kernels advance one time level per launch
+constexpr bool one_level(int k) { return k == K_BORN || k == K_SCAT; }
 
 // The two newest time levels of a sweep and two spare buffers. A one-level
 // launch overwrites `prev` in place; a two-level launch writes the spares.
@@ -120,8 +125,8 @@ struct fwi_ctx {
     DevBuf d_shots, d_qnt, d_qrptr, d_qroff, d_wav;
     // one tiling per kernel class (forward, adjoint, Born), picked by the
     // autotuner or forced by fwi_ctx_set_tiling
-    Tiling tile[3];
-    int force_cw[3] = {0, 0, 0}, force_rows[3] = {0, 0, 0}, force_tb[3] = {0, 0, 0}, force_pd[3] = {0, 0, 0};
+    Tiling tile[kClasses];
+    int force_cw[kClasses] = {}, force_rows[kClasses] = {}, force_tb[kClasses] = {}, force_pd[kClasses] = {};
     bool autotune = true;
     // scratch
     DevBuf fields, samples, image, dhist, ckpt, partials, misfit, check, pairdata;
@@ -1044,6 +1049,7 @@ int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_o
             b.dslot = nullptr;   // the Born step of a demigration (no D output)
             return launch_born_step(b, c->stream);
         }
+        if (cls == K_SCAT) return launch_step(F_SAMPLE | F_SCAT, b, c->stream);
         return t.tb == 2 ? launch_step2(flags, b, c->stream) : launch_step(flags, b, c->stream);
     };
     hipEvent_t e0, e1;
@@ -1068,12 +1074,12 @@ int ensure_tilings(fwi_ctx *c, const float *v)
 {
     const Plan &p = c->plan;
     bool need_tune = false;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kClasses; ++k) {
         Tiling &t = c->tile[k];
         const bool forced = c->force_cw[k] != 0;
         const int want_cw = forced ? c->force_cw[k] : (c->autotune ? 0 : kDefaultCw);
         const int want_rows = forced ? c->force_rows[k] : (c->autotune ? 0 : kDefaultRows);
-        const int want_tb = k == K_BORN ? 1 : (forced ? c->force_tb[k] : (c->autotune ? 0 : kDefaultTb));
+        const int want_tb = one_level(k) ? 1 : (forced ? c->force_tb[k] : (c->autotune ? 0 : kDefaultTb));
         const int want_pd = forced ? c->force_pd[k] : kDefaultPd;
         if (want_cw && want_rows && want_tb) {
             if (t.cw == want_cw && t.rows == want_rows && t.tb == want_tb && t.pd == want_pd) continue;
@@ -1102,17 +1108,20 @@ int ensure_tilings(fwi_ctx *c, const float *v)
                     "fill")) ||
         (rc = other(c, launch_fill(static_cast<float *>(c->samples.p), nq, 0.f, c->stream), "fill")))
         return rc;
-    float best[3] = {1e30f, 1e30f, 1e30f};
-    Candidate bc[3] = {{kDefaultCw, kDefaultRows, kDefaultTb, kDefaultPd},
-                       {kDefaultCw, kDefaultRows, kDefaultTb, kDefaultPd},
-                       {kDefaultCw, kDefaultRows, 1, kDefaultPd}};
+    float best[kClasses];
+    Candidate bc[kClasses];
+    for (int k = 0; k < kClasses; ++k) {
+        best[k] = 1e30f;
+        bc[k] = {kDefaultCw, kDefaultRows, one_level(k) ? 1 : kDefaultTb, kDefaultPd};
+    }
     Tiling trial;
     for (int pass = 0; pass < kTunePasses && rc == 0; ++pass) {
         for (const Candidate &cand : kTune) {
             build_tiling(p, cand.cw, cand.rows, cand.tb, cand.pd, trial);
             if ((rc = upload_tiling(c, trial))) break;
-            for (int k = 0; k < 3; ++k) {
-                if (c->tile[k].cw != 0 || (k == K_BORN && (cand.tb != 1 || cand.pd != 1))) continue;
+            for (int k = 0; k < kClasses; ++k) {
+                if (c->tile[k].cw != 0 || (one_level(k) && cand.tb != 1) || (k == K_BORN && cand.pd != 1))
+                    continue;
                 float ms = 0.f;
                 if ((rc = time_class(c, k, trial, v, &ms))) break;
                 if (ms < best[k]) {
@@ -1127,7 +1136,7 @@ int ensure_tilings(fwi_ctx *c, const float *v)
     release(trial.d_rrows);
     release(trial.d_rmap);
     if (rc) return rc;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kClasses; ++k) {
         Tiling &t = c->tile[k];
         if (t.cw != 0) continue;
         build_tiling(p, bc[k].cw, bc[k].rows, bc[k].tb, bc[k].pd, t);
@@ -1153,7 +1162,7 @@ int prepare(fwi_ctx *c, const float *v)
 {
     int rc = ensure_tilings(c, v);
     if (rc) return rc;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kClasses; ++k) {
         c->stats.tile_cw[k] = c->tile[k].cw;
         c->stats.tile_rows[k] = c->tile[k].rows;
         c->stats.tile_levels[k] = c->tile[k].tb;
@@ -1349,7 +1358,7 @@ int scat_range(fwi_ctx *c, const StepArgs &a, int lo, int hi, float *samp, float
         StepArgs b = a;
         for (int n = lo; n < hi; ++n) {
             b.n = n;
-            b.nwaves = c->tile[K_BORN].prefix[p.active_slots(n)];
+            b.nwaves = c->tile[K_SCAT].prefix[p.active_slots(n)];
             b.cur = ff.cur;
             b.prev = ff.prev;
             b.samp = samp + size_t(n) * p.Q;
@@ -1450,20 +1459,22 @@ int fwi_ctx_set_profiling(fwi_ctx *c, int enable)
 int fwi_ctx_set_tiling(fwi_ctx *c, int kernel, int cols_per_lane, int rows_per_wave, int levels_per_launch,
                        int prefetch_rows)
 {
-    if (!c || kernel < -1 || kernel > 2) return FWI_EINVAL;
+    if (!c || kernel < -1 || kernel >= kClasses) return FWI_EINVAL;
     const bool reset = cols_per_lane == 0 && rows_per_wave == 0 && levels_per_launch == 0;
     if (!reset && !((cols_per_lane == 1 || cols_per_lane == 2) && rows_per_wave >= 1 && rows_per_wave <= 4096 &&
                     (levels_per_launch == 1 || levels_per_launch == 2) && prefetch_rows >= 0 &&
                     prefetch_rows <= 2))
         return FWI_EINVAL;
-    if (kernel == 2 && levels_per_launch == 2) return FWI_EINVAL;  // Born runs one level per launch
-    for (int k = 0; k < 3; ++k)
+    // the Born and scattered-field kernels run one level per launch
+    if (kernel >= 0 && one_level(kernel) && levels_per_launch == 2) return FWI_EINVAL;
+    for (int k = 0; k < kClasses; ++k)
         if (kernel == -1 || kernel == k) {
             c->force_cw[k] = cols_per_lane;
             c->force_rows[k] = rows_per_wave;
-            c->force_tb[k] = k == 2 && !reset ? 1 : levels_per_launch;
+            c->force_tb[k] = one_level(k) && !reset ? 1 : levels_per_launch;
             // the Born kernel and the two-level kernel prefetch one row ahead
-            c->force_pd[k] = (k == 2 || levels_per_launch == 2) ? 1 : (prefetch_rows ? prefetch_rows : kDefaultPd);
+            c->force_pd[k] =
+                (k == K_BORN || levels_per_launch == 2) ? 1 : (prefetch_rows ? prefetch_rows : kDefaultPd);
             c->tile[k].cw = c->tile[k].rows = c->tile[k].tb = 0;
         }
     return FWI_OK;
@@ -1473,7 +1484,7 @@ int fwi_ctx_set_autotune(fwi_ctx *c, int enable)
 {
     if (!c) return FWI_EINVAL;
     c->autotune = enable != 0;
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < kClasses; ++k)
         if (!c->force_cw[k]) c->tile[k].cw = c->tile[k].rows = c->tile[k].tb = 0;
     return FWI_OK;
 }
@@ -1566,7 +1577,7 @@ int fwi_gradient_pair(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const 
     float *samp = static_cast<float *>(c->samples.p);
     if ((rc = ensure(c, c->pairdata, size_t(std::max<int64_t>(p.data_size, 1)) * 4))) return rc;
     if ((rc = other(c, launch_fill(w.F[0], 2 * ff, 0.f, c->stream), "fill"))) return rc;
-    StepArgs a = base_args(c, mv, K_BORN);
+    StepArgs a = base_args(c, mv, K_SCAT);
     a.dv = dv;
     Fields f{w.F[0], w.F[1], w.F[2], w.F[3]};
     if ((rc = ev_begin(c, K_BORN))) return rc;

@@ -45,7 +45,7 @@ import math
 import os
 import sys
 import time
-from dataclasses import dataclass, field
+from dataclasses import replace, dataclass, field
 
 import numpy as np
 import torch
@@ -418,6 +418,7 @@ def main(argv=None):
     ap.add_argument("--train-first", type=int, default=500)
     ap.add_argument("--train", type=int, default=200)
     ap.add_argument("--out", default="")
+    ap.add_argument("--seed", type=int, default=None, help="network initialisation seed (default: the options' seed)")
     ap.add_argument("--rtm", action="store_true",
                     help="after the runs, score the RTM image of each final model (and of the initial model) "
                          "against the image migrated with the true model")
@@ -460,6 +461,8 @@ def main(argv=None):
         opts = FwiOptions(method=method, bands=bands, iters_per_band=args.iters, net=net_cfg,
                           train_steps_first=args.train_first, train_steps=args.train,
                           target_error=target, net_iters=args.net_iters or None)
+        if args.seed is not None:
+            opts = replace(opts, seed=args.seed)
         run = FwiRun(fctx, grid, acq, wl.v0, opts, v_true=wl.v_true, log=log)
         out[method] = run.run(observe)
         finals[method] = run.v.clone()

@@ -259,7 +259,8 @@ def test_forced_tilings_match_oracle_and_each_other(ctx, ragged, cw, rows, level
         gg = host(ctx.fwi_gradient(g, acq, v0, dev(d * 0.5))[0])
         dd = host(ctx.born_demig(g, acq, v0, dv))
         im = host(ctx.born_mig(g, acq, v0, y))
-        return d, gg, dd, im
+        gp = host(ctx.gradient_pair(g, acq, v0, dev(d * 0.5), scale=-1.0)[2])   # scattered-field kernel
+        return d, gg, dd, im, gp
 
     ctx.set_tiling(-1, 1, 30, 1, 1)
     ref = run()
@@ -267,9 +268,10 @@ def test_forced_tilings_match_oracle_and_each_other(ctx, ragged, cw, rows, level
     got = run()
     st = ctx.stats()
     ctx.set_tiling(-1, 0, 0, 0)
-    assert st["tile_cw"] == [cw] * 3 and st["tile_rows"] == [rows] * 3
-    assert st["tile_levels"] == [levels, levels, 1]
+    assert st["tile_cw"] == [cw] * 4 and st["tile_rows"] == [rows] * 4
+    assert st["tile_levels"] == [levels, levels, 1, 1]
     assert st["tile_prefetch"][:2] == [pd if levels == 1 else 1] * 2
+    assert st["tile_prefetch"][3] == (pd if levels == 1 else 1)
     for a, b in zip(got, ref):
         assert np.array_equal(a, b)
     v64 = f32(wl.v_true).astype(np.float64)
@@ -286,7 +288,7 @@ def test_autotuner_picks_a_valid_tiling(ctx, two_layer):
     st = ctx.stats()
     assert all(c in (1, 2) for c in st["tile_cw"])
     assert all(r >= 1 for r in st["tile_rows"])
-    assert st["tile_levels"][2] == 1 and all(t in (1, 2) for t in st["tile_levels"])
+    assert st["tile_levels"][2] == st["tile_levels"][3] == 1 and all(t in (1, 2) for t in st["tile_levels"])
 
 
 @pytest.mark.parametrize("case", ["ragged", "two_layer_ckpt"])
