@@ -36,7 +36,9 @@ class _OgGeom(C.Structure):
                 ("nt", C.c_void_p), ("nt_max", C.c_int),
                 ("rec_ptr", C.c_void_p), ("rec_z", C.c_void_p),
                 ("rec_x", C.c_void_p), ("wavelet", C.c_void_p),
-                ("wavelet_shared", C.c_int)]
+                ("wavelet_shared", C.c_int),
+                ("src_fz", C.c_void_p), ("src_fx", C.c_void_p),
+                ("rec_fz", C.c_void_p), ("rec_fx", C.c_void_p)]
 
 
 def lib():
@@ -86,7 +88,9 @@ class _Call:
             ptr(acq.nt, np.int32), int(grid.nt_max),
             ptr(acq.rec_ptr, np.int64), ptr(acq.rec_z, np.int32),
             ptr(acq.rec_x, np.int32), wav.ctypes.data,
-            1 if acq.wavelet_shared else 0)
+            1 if acq.wavelet_shared else 0,
+            ptr(getattr(acq, "src_fz", None), np.float64), ptr(getattr(acq, "src_fx", None), np.float64),
+            ptr(getattr(acq, "rec_fz", None), np.float64), ptr(getattr(acq, "rec_fx", None), np.float64))
         if not acq.wavelet_shared and wav.shape[1] != grid.nt_max:
             raise ValueError("per-shot wavelets must be [nshots][nt_max]")
 

@@ -17,10 +17,14 @@
  *   sponge        sigma = smax (dz^2 + dx^2), dz = distance into the sponge
  *                 / nb, smax = 3 v_ref ln(1/R) / (2 nb h);
  *                 a = 1/(1 + sigma dt/2), b = (1 - sigma dt/2) a;
- *   source        s^n = w[n] / h^2 at the source cell;
+ *   source        s^n = w[n] / h^2 at the source cell; a source off the grid
+ *                 (fractional offsets fz, fx in [0, 1) toward +z, +x) is
+ *                 spread over the four surrounding cells with bilinear
+ *                 weights (1-fz)(1-fx), (1-fz) fx, fz (1-fx), fz fx;
  *   time step     u^{n+1} = a (2 u^n + V^2 dt^2 (L8 u^n + s^n)) - b u^{n-1},
  *                 u^{-1} = u^0 = 0  (eq. 1, leapfrog, damped in the sponge);
- *   receivers     d[r][n] = u^{n+1}[rz][rx];
+ *   receivers     d[r][n] = u^{n+1}[rz][rx]; off the grid, the bilinear
+ *                 combination of the four surrounding cells (same weights);
  *   misfit        phi = 1/2 sum (d - d_obs)^2   (eq. 2).
  *
  *   Born (eq. 9-11, solved jointly as the paper notes; velocity
@@ -33,7 +37,8 @@
  *                 lam^n = a (2 lam^{n+1} + V^2 dt^2 (L8 lam^{n+1} + R^T r^n))
  *                         - b lam^{n+2},  n = nt-1 .. 0, lam^{nt} = lam^{nt+1} = 0,
  *                 img = sum_shots Pad^T( (2/V) sum_n lam^n (L8 u^n + s^n) ),
- *                 where R^T adds r[r][n] at receiver cells and Pad^T sums
+ *                 where R^T adds r[r][n] at receiver cells (times the bilinear
+ *                 weights off the grid) and Pad^T sums
  *                 every sponge cell onto the edge cell it replicates.
  *
  * Every function below works on one shot at a time; shots are independent
@@ -63,6 +68,8 @@ typedef struct {
     const int *rec_z, *rec_x;
     const double *wavelet;      /* [nt_max] shared, or [nshots][nt_max] */
     int wavelet_shared;
+    const double *src_fz, *src_fx; /* NULL: sources on the grid */
+    const double *rec_fz, *rec_fx; /* NULL: receivers on the grid */
 } og_geom;
 
 /* 8th-order central second-derivative weights (Fornberg 1988). */
@@ -180,6 +187,56 @@ static int64_t cell_index(const og_grid *g, const shot_dom *D, int z, int x)
     return (int64_t)(z + g->nb) * D->NX + (x - D->x0 + g->nb);
 }
 
+/* A point (z + fz, x + fx) of shot s's physical grid: the cells it touches
+ * and their bilinear weights; cells whose weight is exactly zero are left
+ * out, so a point on the grid is its own cell with weight 1. */
+typedef struct {
+    int n;
+    int64_t cell[4];
+    double w[4];
+} point_w;
+
+static point_w point_weights(const og_grid *g, const shot_dom *D, int z, int x, double fz, double fx)
+{
+    point_w p;
+    p.n = 0;
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+            double w = (a ? fz : 1.0 - fz) * (b ? fx : 1.0 - fx);
+            if (w == 0.0) continue;
+            p.cell[p.n] = cell_index(g, D, z + a, x + b);
+            p.w[p.n] = w;
+            p.n++;
+        }
+    return p;
+}
+
+static point_w src_point(const og_grid *g, const og_geom *geo, const shot_dom *D, int s)
+{
+    return point_weights(g, D, geo->src_z[s], geo->src_x[s], geo->src_fz ? geo->src_fz[s] : 0.0,
+                         geo->src_fx ? geo->src_fx[s] : 0.0);
+}
+
+static point_w rec_point(const og_grid *g, const og_geom *geo, const shot_dom *D, int64_t r)
+{
+    return point_weights(g, D, geo->rec_z[r], geo->rec_x[r], geo->rec_fz ? geo->rec_fz[r] : 0.0,
+                         geo->rec_fx ? geo->rec_fx[r] : 0.0);
+}
+
+/* field[cells] += w * val */
+static void point_add(const point_w *p, double val, double *field)
+{
+    for (int k = 0; k < p->n; k++) field[p->cell[k]] += p->w[k] * val;
+}
+
+/* sum of w * field[cells] */
+static double point_sample(const point_w *p, const double *field)
+{
+    double acc = 0.0;
+    for (int k = 0; k < p->n; k++) acc += p->w[k] * field[p->cell[k]];
+    return acc;
+}
+
 /* ------------------------------------------------------------------ */
 /* one shot                                                            */
 
@@ -194,17 +251,19 @@ static int forward_shot(const og_grid *g, const og_geom *geo, int s, const shot_
     double *up = calloc(n, sizeof(double)), *lap = malloc(n * sizeof(double));
     if (!um || !u0 || !up || !lap) { free(um); free(u0); free(up); free(lap); return -1; }
     const double *w = shot_wavelet(geo, s);
-    int64_t src = cell_index(g, D, geo->src_z[s], geo->src_x[s]);
+    point_w src = src_point(g, geo, D, s);
     int64_t r0 = geo->rec_ptr[s], nrec = geo->rec_ptr[s + 1] - r0;
     double ih2 = 1.0 / (g->h * g->h);
     for (int t = 0; t < nt; t++) {
         if (hist) memcpy(hist + (int64_t)t * n, u0, n * sizeof(double));
         laplacian8(u0, D->NZ, D->NX, g->h, lap);
-        lap[src] += w[t] * ih2;
+        point_add(&src, w[t] * ih2, lap);
         for (int64_t k = 0; k < n; k++)
             up[k] = D->a[k] * (2.0 * u0[k] + D->c[k] * lap[k]) - D->b[k] * um[k];
-        for (int64_t r = 0; r < nrec; r++)
-            d_shot[r * nt + t] = up[cell_index(g, D, geo->rec_z[r0 + r], geo->rec_x[r0 + r])];
+        for (int64_t r = 0; r < nrec; r++) {
+            point_w rp = rec_point(g, geo, D, r0 + r);
+            d_shot[r * nt + t] = point_sample(&rp, up);
+        }
         double *tmp = um; um = u0; u0 = up; up = tmp;
     }
     if (hist) memcpy(hist + (int64_t)nt * n, u0, n * sizeof(double));
@@ -228,20 +287,22 @@ static int born_shot(const og_grid *g, const og_geom *geo, int s, const shot_dom
         pad_model(g, D->x0, D->wnx, dv, rho);            /* Pad(dv) */
         for (int64_t k = 0; k < n; k++) rho[k] = 2.0 * rho[k] / D->V[k];
         const double *w = shot_wavelet(geo, s);
-        int64_t src = cell_index(g, D, geo->src_z[s], geo->src_x[s]);
+        point_w src = src_point(g, geo, D, s);
         int64_t r0 = geo->rec_ptr[s], nrec = geo->rec_ptr[s + 1] - r0;
         double ih2 = 1.0 / (g->h * g->h);
         for (int t = 0; t < nt; t++) {
             laplacian8(u0, D->NZ, D->NX, g->h, lap);
-            lap[src] += w[t] * ih2;                       /* L8 u^n + s^n */
+            point_add(&src, w[t] * ih2, lap);             /* L8 u^n + s^n */
             laplacian8(d0, D->NZ, D->NX, g->h, dlap);
             for (int64_t k = 0; k < n; k++) {
                 dp[k] = D->a[k] * (2.0 * d0[k] + D->c[k] * (dlap[k] + rho[k] * lap[k]))
                         - D->b[k] * dm[k];
                 up[k] = D->a[k] * (2.0 * u0[k] + D->c[k] * lap[k]) - D->b[k] * um[k];
             }
-            for (int64_t r = 0; r < nrec; r++)
-                dd_shot[r * nt + t] = dp[cell_index(g, D, geo->rec_z[r0 + r], geo->rec_x[r0 + r])];
+            for (int64_t r = 0; r < nrec; r++) {
+                point_w rp = rec_point(g, geo, D, r0 + r);
+                dd_shot[r * nt + t] = point_sample(&rp, dp);
+            }
             double *tmp = um; um = u0; u0 = up; up = tmp;
             tmp = dm; dm = d0; d0 = dp; dp = tmp;
         }
@@ -267,18 +328,20 @@ static int adjoint_shot(const og_grid *g, const og_geom *geo, int s, const shot_
     if (ok) ok = forward_shot(g, geo, s, D, dummy, hist) == 0;
     if (ok) {
         const double *w = shot_wavelet(geo, s);
-        int64_t src = cell_index(g, D, geo->src_z[s], geo->src_x[s]);
+        point_w src = src_point(g, geo, D, s);
         int64_t r0 = geo->rec_ptr[s], nrec = geo->rec_ptr[s + 1] - r0;
         double ih2 = 1.0 / (g->h * g->h);
         for (int t = nt - 1; t >= 0; t--) {
             laplacian8(l1, D->NZ, D->NX, g->h, lap);    /* L8 lam^{n+1} */
-            for (int64_t r = 0; r < nrec; r++)            /* + R^T r^n */
-                lap[cell_index(g, D, geo->rec_z[r0 + r], geo->rec_x[r0 + r])] += res_shot[r * nt + t];
+            for (int64_t r = 0; r < nrec; r++) {          /* + R^T r^n */
+                point_w rp = rec_point(g, geo, D, r0 + r);
+                point_add(&rp, res_shot[r * nt + t], lap);
+            }
             for (int64_t k = 0; k < n; k++)
                 l0[k] = D->a[k] * (2.0 * l1[k] + D->c[k] * lap[k]) - D->b[k] * l2[k];
             if (lam_hist) memcpy(lam_hist + (int64_t)t * n, l0, n * sizeof(double));
             laplacian8(hist + (int64_t)t * n, D->NZ, D->NX, g->h, lu);
-            lu[src] += w[t] * ih2;                        /* L8 u^n + s^n */
+            point_add(&src, w[t] * ih2, lu);              /* L8 u^n + s^n */
             for (int64_t k = 0; k < n; k++) G[k] += l0[k] * lu[k];
             double *tmp = l2; l2 = l1; l1 = l0; l0 = tmp;
         }

@@ -45,6 +45,12 @@ class Acquisition:
     win_x0: np.ndarray | None = None  # int32 [nshots]; None = full width
     win_nx: np.ndarray | None = None  # int32 [nshots]
     nt: np.ndarray | None = None      # int32 [nshots]; None = nt_max for all
+    # off-grid positions: fractional offsets in [0, 1) toward +z / +x from
+    # (src_z, src_x) and (rec_z, rec_x), float32; None = on the grid
+    src_fz: np.ndarray | None = None
+    src_fx: np.ndarray | None = None
+    rec_fz: np.ndarray | None = None
+    rec_fx: np.ndarray | None = None
 
     def __post_init__(self):
         self.src_z = np.ascontiguousarray(self.src_z, dtype=np.int32)
@@ -56,6 +62,10 @@ class Acquisition:
             a = getattr(self, name)
             if a is not None:
                 setattr(self, name, np.ascontiguousarray(a, dtype=np.int32))
+        for name in ("src_fz", "src_fx", "rec_fz", "rec_fx"):
+            a = getattr(self, name)
+            if a is not None:
+                setattr(self, name, np.ascontiguousarray(a, dtype=np.float32))
 
     @property
     def nshots(self) -> int:
@@ -94,11 +104,14 @@ class Acquisition:
     def subset(self, shots) -> "Acquisition":
         shots = np.asarray(shots, dtype=np.int64)
         ptr = [0]
-        rz, rx = [], []
+        rz, rx, rfz, rfx = [], [], [], []
         for s in shots:
             a, b = self.rec_ptr[s], self.rec_ptr[s + 1]
             rz.append(self.rec_z[a:b])
             rx.append(self.rec_x[a:b])
+            if self.rec_fz is not None:
+                rfz.append(self.rec_fz[a:b])
+                rfx.append(self.rec_fx[a:b])
             ptr.append(ptr[-1] + (b - a))
         wav = self.wavelet if self.wavelet_shared else self.wavelet[shots]
         return Acquisition(
@@ -110,6 +123,10 @@ class Acquisition:
             win_x0=None if self.win_x0 is None else self.win_x0[shots],
             win_nx=None if self.win_nx is None else self.win_nx[shots],
             nt=None if self.nt is None else self.nt[shots],
+            src_fz=None if self.src_fz is None else self.src_fz[shots],
+            src_fx=None if self.src_fx is None else self.src_fx[shots],
+            rec_fz=None if self.rec_fz is None else (np.concatenate(rfz) if rfz else np.zeros(0, np.float32)),
+            rec_fx=None if self.rec_fx is None else (np.concatenate(rfx) if rfx else np.zeros(0, np.float32)),
         )
 
 
