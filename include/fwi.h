@@ -97,6 +97,16 @@ typedef struct {
     const float *wavelet;           /* host: [nt_max] if wavelet_shared,
                                        else [nshots][nt_max] */
     int32_t wavelet_shared;
+    /* Optional off-grid positions (host, NULL = on the grid): fractional
+     * offsets in [0, 1) toward +z and +x from (src_z, src_x) [nshots] and
+     * from (rec_z, rec_x) [rec_ptr[nshots]]. A source is spread over the
+     * four surrounding cells and a receiver combines them with bilinear
+     * weights (1-fz)(1-fx), (1-fz)fx, fz(1-fx), fz fx; a nonzero offset
+     * needs the next cell inside the model (z + 1 < nz) or the shot's
+     * window (x + 1 < win_x0 + win_nx). Both arrays of a pair are given or
+     * both are NULL. */
+    const float *src_fz, *src_fx;
+    const float *rec_fz, *rec_fx;
 } fwi_geom;
 
 typedef struct {

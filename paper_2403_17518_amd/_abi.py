@@ -33,7 +33,9 @@ class fwi_geom(C.Structure):
                 ("win_x0", C.c_void_p), ("win_nx", C.c_void_p),
                 ("nt", C.c_void_p), ("rec_ptr", C.c_void_p),
                 ("rec_z", C.c_void_p), ("rec_x", C.c_void_p),
-                ("wavelet", C.c_void_p), ("wavelet_shared", C.c_int32)]
+                ("wavelet", C.c_void_p), ("wavelet_shared", C.c_int32),
+                ("src_fz", C.c_void_p), ("src_fx", C.c_void_p),
+                ("rec_fz", C.c_void_p), ("rec_fx", C.c_void_p)]
 
 
 class fwi_stats(C.Structure):
@@ -175,4 +177,8 @@ class GeomView:
                              arr(getattr(acq, "win_nx", None), np.int32),
                              arr(getattr(acq, "nt", None), np.int32),
                              arr(acq.rec_ptr, np.int64), arr(acq.rec_z, np.int32),
-                             arr(acq.rec_x, np.int32), wav.ctypes.data, 1 if shared else 0)
+                             arr(acq.rec_x, np.int32), wav.ctypes.data, 1 if shared else 0,
+                             arr(getattr(acq, "src_fz", None), np.float32),
+                             arr(getattr(acq, "src_fx", None), np.float32),
+                             arr(getattr(acq, "rec_fz", None), np.float32),
+                             arr(getattr(acq, "rec_fx", None), np.float32))

@@ -51,6 +51,13 @@ struct Plan {
     int Q = 0;
     std::vector<int32_t> q_nt, q_rptr;
     std::vector<int64_t> q_roff;
+    std::vector<float> q_rw;             // weight of each q_roff entry (1 on the grid)
+    // receivers off the grid: each combines up to four cells (CSR per receiver)
+    bool offgrid = false;
+    int nrec = 0;
+    std::vector<int32_t> r_cptr, r_cq, r_nt;
+    std::vector<float> r_cw;
+    std::vector<int64_t> r_off;
     std::vector<float> wav;
     int64_t field_floats = 0;  // one wavefield buffer, all shots
     int64_t img_floats = 0;    // one image / D slot, all shots
@@ -123,6 +130,7 @@ struct fwi_ctx {
     bool plan_valid = false;
     // device copies of the plan tables
     DevBuf d_shots, d_qnt, d_qrptr, d_qroff, d_wav;
+    DevBuf d_qrw, d_rcptr, d_rcq, d_rnt, d_rcw, d_roff;   // off-grid receiver tables
     // one tiling per kernel class (forward, adjoint, Born), picked by the
     // autotuner or forced by fwi_ctx_set_tiling
     Tiling tile[kClasses];
@@ -130,6 +138,7 @@ struct fwi_ctx {
     bool autotune = true;
     // scratch
     DevBuf fields, samples, image, dhist, ckpt, partials, misfit, check, pairdata;
+    DevBuf resid;   // combined off-grid receiver traces / residuals [data]
     // copies of the call's model and perturbation: the time loops read these,
     // never the caller's buffers, so captured loops stay valid across calls
     DevBuf model, dmodel;
@@ -248,6 +257,9 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
     const int64_t nrec_tot = S > 0 ? geo->rec_ptr[S] : 0;
     if (nrec_tot > 0 && (!geo->rec_z || !geo->rec_x)) return set_err(c, FWI_EINVAL, "NULL receiver arrays");
     if (nrec_tot > (int64_t(1) << 30)) return set_err(c, FWI_EINVAL, "too many receivers");
+    if ((geo->src_fz == nullptr) != (geo->src_fx == nullptr) || (geo->rec_fz == nullptr) != (geo->rec_fx == nullptr))
+        return set_err(c, FWI_EINVAL, "off-grid offsets come in (fz, fx) pairs: both or neither");
+    auto bad_frac = [](float f) { return !(f >= 0.f && f < 1.f); };
 
     // plan cache key: every input the plan depends on
     std::vector<char> key;
@@ -263,6 +275,16 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
             put(key, geo->win_nx, S);
         }
         if (geo->nt) put(key, geo->nt, S);
+        const int fflags[2] = {geo->src_fz != nullptr, geo->rec_fz != nullptr};
+        put(key, fflags, 2);
+        if (geo->src_fz) {
+            put(key, geo->src_fz, S);
+            put(key, geo->src_fx, S);
+        }
+        if (geo->rec_fz) {
+            put(key, geo->rec_fz, nrec_tot);
+            put(key, geo->rec_fx, nrec_tot);
+        }
         put(key, geo->rec_ptr, S + 1);
         put(key, geo->rec_z, nrec_tot);
         put(key, geo->rec_x, nrec_tot);
@@ -297,13 +319,21 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
         if (nts[s] < 0 || nts[s] > g->nt_max)
             return set_err(c, FWI_EINVAL, "shot %d: nt=%d outside [0, nt_max=%d]", s, nts[s], g->nt_max);
         const int sz = geo->src_z[s], sx = geo->src_x[s];
+        const float sfz = geo->src_fz ? geo->src_fz[s] : 0.f, sfx = geo->src_fz ? geo->src_fx[s] : 0.f;
         if (sz < 0 || sz >= g->nz || sx < x0[s] || sx >= x0[s] + wnx[s])
             return set_err(c, FWI_EINVAL, "shot %d: source (%d, %d) outside its window", s, sz, sx);
+        if (bad_frac(sfz) || bad_frac(sfx) || (sfz > 0.f && sz + 1 >= g->nz) || (sfx > 0.f && sx + 1 >= x0[s] + wnx[s]))
+            return set_err(c, FWI_EINVAL, "shot %d: source offsets (%g, %g) outside [0, 1) or the window", s,
+                           double(sfz), double(sfx));
         for (int64_t r = geo->rec_ptr[s]; r < geo->rec_ptr[s + 1]; ++r) {
             const int rz = geo->rec_z[r], rx = geo->rec_x[r];
             if (rz < 0 || rz >= g->nz || rx < x0[s] || rx >= x0[s] + wnx[s])
                 return set_err(c, FWI_EINVAL, "shot %d: receiver %lld at (%d, %d) outside its window", s,
                                (long long)r, rz, rx);
+            const float fz = geo->rec_fz ? geo->rec_fz[r] : 0.f, fx = geo->rec_fz ? geo->rec_fx[r] : 0.f;
+            if (bad_frac(fz) || bad_frac(fx) || (fz > 0.f && rz + 1 >= g->nz) || (fx > 0.f && rx + 1 >= x0[s] + wnx[s]))
+                return set_err(c, FWI_EINVAL, "shot %d: receiver %lld offsets (%g, %g) outside [0, 1) or the window",
+                               s, (long long)r, double(fz), double(fx));
         }
         data_off[s + 1] = data_off[s] + (geo->rec_ptr[s + 1] - geo->rec_ptr[s]) * int64_t(nts[s]);
     }
@@ -343,19 +373,62 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
         }
         p.slot_nt[k] = nts[s];
         p.updates_per_field_pass += double(p.NZ) * d.NX * nts[s];
+        // bilinear weights: (1-fz)(1-fx), (1-fz)fx, fz(1-fx), fz fx
+        auto weights = [](double fz, double fx, float *w) {
+            w[0] = float((1.0 - fz) * (1.0 - fx));
+            w[1] = float((1.0 - fz) * fx);
+            w[2] = float(fz * (1.0 - fx));
+            w[3] = float(fz * fx);
+        };
+        {
+            float w[4];
+            weights(geo->src_fz ? geo->src_fz[s] : 0.0, geo->src_fz ? geo->src_fx[s] : 0.0, w);
+            d.sw00 = w[0];
+            d.sw01 = w[1];
+            d.sw10 = w[2];
+            d.sw11 = w[3];
+        }
 
-        // unique receiver cells of this shot, sorted by (row, col)
-        std::map<std::pair<int, int>, std::vector<int64_t>> cells;
+        // unique receiver cells of this shot, sorted by (row, col); a
+        // receiver off the grid touches the cells of its nonzero weights
+        std::map<std::pair<int, int>, std::vector<std::pair<int64_t, float>>> cells;
+        std::vector<std::vector<std::pair<std::pair<int, int>, float>>> rec_cells;
         for (int64_t r = geo->rec_ptr[s]; r < geo->rec_ptr[s + 1]; ++r) {
             const int i = geo->rec_z[r] + p.nb, jj = geo->rec_x[r] - x0[s] + p.nb;
-            cells[{i, jj}].push_back(data_off[s] + (r - geo->rec_ptr[s]) * int64_t(nts[s]));
+            const int64_t off = data_off[s] + (r - geo->rec_ptr[s]) * int64_t(nts[s]);
+            float w[4];
+            weights(geo->rec_fz ? geo->rec_fz[r] : 0.0, geo->rec_fz ? geo->rec_fx[r] : 0.0, w);
+            rec_cells.emplace_back();
+            for (int ab = 0; ab < 4; ++ab) {
+                if (w[ab] == 0.f) continue;
+                const std::pair<int, int> cell{i + ab / 2, jj + ab % 2};
+                cells[cell].push_back({off, w[ab]});
+                rec_cells.back().push_back({cell, w[ab]});
+                if (w[ab] != 1.f) p.offgrid = true;
+            }
+            p.r_off.push_back(off);
+            p.r_nt.push_back(nts[s]);
         }
+        std::map<std::pair<int, int>, int> qof;
         for (auto &kv : cells) {
             p.slot_cells[k].push_back({kv.first, p.Q});
+            qof[kv.first] = p.Q;
             p.q_nt.push_back(nts[s]);
-            for (int64_t off : kv.second) p.q_roff.push_back(off);
+            for (auto &ow : kv.second) {
+                p.q_roff.push_back(ow.first);
+                p.q_rw.push_back(ow.second);
+            }
             p.q_rptr.push_back(int32_t(p.q_roff.size()));
             ++p.Q;
+        }
+        for (auto &rc : rec_cells) {
+            if (p.r_cptr.empty()) p.r_cptr.push_back(0);
+            for (auto &cw : rc) {
+                p.r_cq.push_back(qof[cw.first]);
+                p.r_cw.push_back(cw.second);
+            }
+            p.r_cptr.push_back(int32_t(p.r_cq.size()));
+            ++p.nrec;
         }
     }
     p.field_floats = foff;
@@ -369,6 +442,13 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
     if ((rc = upload(c, c->d_shots, p.shots)) || (rc = upload(c, c->d_qnt, p.q_nt)) || (rc = upload(c, c->d_qrptr, p.q_rptr)) ||
         (rc = upload(c, c->d_qroff, p.q_roff)) || (rc = upload(c, c->d_wav, p.wav)))
         return rc;
+    if (p.offgrid) {
+        if ((rc = upload(c, c->d_qrw, p.q_rw)) || (rc = upload(c, c->d_rcptr, p.r_cptr)) ||
+            (rc = upload(c, c->d_rcq, p.r_cq)) || (rc = upload(c, c->d_rnt, p.r_nt)) ||
+            (rc = upload(c, c->d_rcw, p.r_cw)) || (rc = upload(c, c->d_roff, p.r_off)) ||
+            (rc = ensure(c, c->resid, size_t(std::max<int64_t>(p.data_size, 1)) * 4)))
+            return rc;
+    }
     // the host vectors are read by the copies above; keep them alive in the
     // context and make sure the copies finished before the plan can change
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -977,6 +1057,18 @@ TraceArgs trace_args(fwi_ctx *c)
     t.q_nt = static_cast<const int32_t *>(c->d_qnt.p);
     t.q_rptr = static_cast<const int32_t *>(c->d_qrptr.p);
     t.q_roff = static_cast<const int64_t *>(c->d_qroff.p);
+    t.ndata = p.data_size;
+    if (p.offgrid) {
+        t.offgrid = 1;
+        t.R = p.nrec;
+        t.r_cptr = static_cast<const int32_t *>(c->d_rcptr.p);
+        t.r_cq = static_cast<const int32_t *>(c->d_rcq.p);
+        t.r_nt = static_cast<const int32_t *>(c->d_rnt.p);
+        t.r_cw = static_cast<const float *>(c->d_rcw.p);
+        t.q_rw = static_cast<const float *>(c->d_qrw.p);
+        t.r_off = static_cast<const int64_t *>(c->d_roff.p);
+        t.resid = static_cast<float *>(c->resid.p);
+    }
     return t;
 }
 
@@ -1254,12 +1346,13 @@ int gradient_core(fwi_ctx *c, const float *v, const float *d_obs, float *grad, d
     t.beta = -1.f;
     t.tm_out = samp;
     t.tr_out = d_syn;
-    const int64_t nblk = int64_t((p.Q + 63) / 64) * ((p.nt_max + 63) / 64);
-    if ((rc = ensure(c, c->partials, size_t(std::max<int64_t>(nblk, 1)) * sizeof(double))) ||
+    const int64_t nmax = traces_partials_max(p.Q, p.nt_max);
+    if ((rc = ensure(c, c->partials, size_t(std::max<int64_t>(nmax, 1)) * sizeof(double))) ||
         (rc = ensure(c, c->misfit, sizeof(double))))
         return rc;
     t.partials = static_cast<double *>(c->partials.p);
-    if ((rc = other(c, launch_traces(t, c->stream, nullptr), "residual"))) return rc;
+    int64_t nblk = 0;
+    if ((rc = other(c, launch_traces(t, c->stream, &nblk), "residual"))) return rc;
     if (nblk > 0) {
         if ((rc = other(c, launch_sum_partials(t.partials, nblk, static_cast<double *>(c->misfit.p), c->stream),
                         "misfit")))
@@ -1418,6 +1511,8 @@ void fwi_ctx_destroy(fwi_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (Tiling &t : c->tile)
         for (DevBuf *b : {&t.d_waves, &t.d_rrows, &t.d_rmap}) release(*b);
+    for (DevBuf *b : {&c->d_qrw, &c->d_rcptr, &c->d_rcq, &c->d_rnt, &c->d_rcw, &c->d_roff, &c->resid})
+        release(*b);
     for (DevBuf *b : {&c->d_shots, &c->d_qnt, &c->d_qrptr, &c->d_qroff, &c->d_wav, &c->fields, &c->samples,
                       &c->image, &c->dhist, &c->ckpt, &c->partials, &c->misfit, &c->check, &c->model, &c->dmodel,
                       &c->pairdata})
@@ -1613,12 +1708,13 @@ int fwi_misfit(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *
     t.alpha = 1.f;
     t.tr_in = d_obs;
     t.beta = -1.f;
-    const int64_t nblk = int64_t((p.Q + 63) / 64) * ((p.nt_max + 63) / 64);
-    if ((rc = ensure(c, c->partials, size_t(std::max<int64_t>(nblk, 1)) * sizeof(double))) ||
+    const int64_t nmax = traces_partials_max(p.Q, p.nt_max);
+    if ((rc = ensure(c, c->partials, size_t(std::max<int64_t>(nmax, 1)) * sizeof(double))) ||
         (rc = ensure(c, c->misfit, sizeof(double))))
         return rc;
     t.partials = static_cast<double *>(c->partials.p);
-    if ((rc = other(c, launch_traces(t, c->stream, nullptr), "residual"))) return rc;
+    int64_t nblk = 0;
+    if ((rc = other(c, launch_traces(t, c->stream, &nblk), "residual"))) return rc;
     if (nblk > 0) {
         if ((rc = other(c, launch_sum_partials(t.partials, nblk, static_cast<double *>(c->misfit.p), c->stream),
                         "misfit")))

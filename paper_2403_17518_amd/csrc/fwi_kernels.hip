@@ -14,6 +14,8 @@
 // registers; the horizontal neighbours of the centre row go through an LDS
 // row (the strip plus two 4-cell halos). The kernel is bound by HBM/MALL
 // bandwidth (about 1.7 flop per byte), so no matrix cores are involved.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace fwi {
@@ -47,6 +49,17 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks)
 // It must never equal a row index: the two-level kernel walks rows from 4
 // (level 1) and 8 (level 2) above the padded box, so -1 is a real row there.
 constexpr int kNoRow = -(1 << 30);
+
+// The source term at (row, column) offset (a, b) from the source cell: a
+// source off the grid is spread over the four cells a, b in {0, 1} with
+// bilinear weights (on the grid the weights are 1, 0, 0, 0, and the term is
+// the plain add).
+__device__ __forceinline__ float add_source(float lap, float wsrc, int a, int b, const ShotDesc &S)
+{
+    if (unsigned(a) > 1u || unsigned(b) > 1u) return lap;
+    const float w = a == 0 ? (b == 0 ? S.sw00 : S.sw01) : (b == 0 ? S.sw10 : S.sw11);
+    return __builtin_fmaf(wsrc, w, lap);
+}
 
 __device__ __forceinline__ float sponge_a(float sh)
 {
@@ -269,8 +282,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             float lap = lap8(q, xr, k, A.w1, A.w2, A.w3, A.w4);
-            if (FL & F_SRC)
-                if (src_k == k && z == S.src_i) lap += wsrc;
+            if (FL & F_SRC) lap = add_source(lap, wsrc, z - S.src_i, k - src_k, S);
             if (FL & F_INJECT)
                 if (qi[k] >= 0) lap += A.inj[qi[k]];
             const float cc = c.v[k] * c.v[k] * A.dt2;
@@ -476,8 +488,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             float lap = lap8(qa, xr, k, A.w1, A.w2, A.w3, A.w4);
-            if (FL & F_SRC)
-                if (src_k == k && t == S.src_i) lap += wsrc1;
+            if (FL & F_SRC) lap = add_source(lap, wsrc1, t - S.src_i, k - src_k, S);
             if (FL & F_INJECT)
                 if (qi1[k] >= 0) lap += A.inj[qi1[k]];
             const float c = cv[k] * cv[k] * A.dt2;
@@ -535,8 +546,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 #pragma unroll
             for (int k = 0; k < CW; ++k) {
                 float lap = lap8(qb, yr, k, A.w1, A.w2, A.w3, A.w4);
-                if (FL & F_SRC)
-                    if (src_k == k && r2 == S.src_i) lap += wsrc2;
+                if (FL & F_SRC) lap = add_source(lap, wsrc2, r2 - S.src_i, k - src_k, S);
                 if (FL & F_INJECT)
                     if (qi2[k] >= 0) lap += A.inj2[qi2[k]];
                 const float c = cq[0][k];
@@ -709,7 +719,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
         for (int k = 0; k < CW; ++k) {
             float lap = lap8(q, xr, k, A.w1, A.w2, A.w3, A.w4);
             const float lapd = lap8(r, xd, k, A.w1, A.w2, A.w3, A.w4);
-            if (src_k == k && z == S.src_i) lap += wsrc;
+            lap = add_source(lap, wsrc, z - S.src_i, k - src_k, S);
             const float c = cv[k] * cv[k] * A.dt2;
             const float cr = 2.0f * cv[k] * cdv[k] * A.dt2;
             float a = ax[k], sh = shx[k];
@@ -839,6 +849,60 @@ __global__ __launch_bounds__(256) void k_traces(const TraceArgs A)
         if (threadIdx.x == 0)
             A.partials[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
     }
+}
+
+// Off-grid receivers, first pass (grid: receivers x time blocks): the trace
+// of receiver r is the weighted sum of its cells' time-major samples;
+// tr_out receives it and resid its residual alpha*trace + beta*tr_in.
+__global__ __launch_bounds__(256) void k_traces_rec(const TraceArgs A)
+{
+    const int r = blockIdx.x;
+    const int n = blockIdx.y * blockDim.x + threadIdx.x;
+    if (n >= A.r_nt[r]) return;
+    const int k1 = A.r_cptr[r + 1];
+    float s = 0.0f;
+    if (A.tm_in)
+        for (int k = A.r_cptr[r]; k < k1; ++k)
+            s = __builtin_fmaf(A.r_cw[k], A.tm_in[int64_t(n) * A.Q + A.r_cq[k]], s);
+    const int64_t off = A.r_off[r];
+    if (A.tr_out) A.tr_out[off + n] = s;
+    if (A.resid) {
+        float val = A.alpha * s;
+        if (A.tr_in) val += A.beta * A.tr_in[off + n];
+        A.resid[off + n] = val;
+    }
+}
+
+// Off-grid receivers, second pass (one thread per time-major sample n*Q+q):
+// the adjoint source of cell q is the weighted sum of the residuals of the
+// receivers that use it (zero past the cell's record length).
+__global__ __launch_bounds__(256) void k_traces_cell(const TraceArgs A)
+{
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(A.nt_max) * A.Q) return;
+    const int q = int(e % A.Q), n = int(e / A.Q);
+    float acc = 0.0f;
+    if (n < A.q_nt[q]) {
+        const int k1 = A.q_rptr[q + 1];
+        for (int k = A.q_rptr[q]; k < k1; ++k) acc = __builtin_fmaf(A.q_rw[k], A.resid[A.q_roff[k] + n], acc);
+    }
+    A.tm_out[e] = acc;
+}
+
+// partials[block] = 1/2 sum of x^2 over a block-strided share of x (fixed order)
+__global__ __launch_bounds__(256) void k_half_sumsq(const float *x, int64_t n, double *partials)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        acc += 0.5 * double(x[i]) * double(x[i]);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
 // Deterministic sum of the per-block partials (fixed order).
@@ -1031,13 +1095,45 @@ hipError_t launch_model_check(const float *v, int64_t n, float *out3, hipStream_
     return hipGetLastError();
 }
 
+constexpr int kSumsqBlocks = 1024;   // misfit partials of the off-grid path
+
+int64_t traces_partials_max(int32_t Q, int32_t nt_max)
+{
+    return std::max<int64_t>(int64_t((Q + 63) / 64) * ((nt_max + 63) / 64), kSumsqBlocks);
+}
+
 hipError_t launch_traces(const TraceArgs &a, hipStream_t s, int64_t *nblocks_out)
 {
-    const unsigned gx = unsigned((a.Q + 63) / 64), gy = unsigned((a.nt_max + 63) / 64);
-    if (nblocks_out) *nblocks_out = int64_t(gx) * gy;
-    if (gx == 0 || gy == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_traces, dim3(gx, gy), dim3(256), 0, s, a);
-    return hipGetLastError();
+    if (!a.offgrid) {
+        const unsigned gx = unsigned((a.Q + 63) / 64), gy = unsigned((a.nt_max + 63) / 64);
+        if (nblocks_out) *nblocks_out = int64_t(gx) * gy;
+        if (gx == 0 || gy == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_traces, dim3(gx, gy), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    // off the grid: receiver traces (and residuals), then the misfit and the
+    // cells' adjoint sources from the residuals
+    TraceArgs b = a;
+    if (!a.tm_out && !a.partials) b.resid = nullptr;
+    if (nblocks_out) *nblocks_out = 0;
+    if (a.R > 0 && a.nt_max > 0 && (b.resid || a.tr_out)) {
+        hipLaunchKernelGGL(k_traces_rec, dim3(unsigned(a.R), unsigned((a.nt_max + 255) / 256)), dim3(256), 0, s, b);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (a.partials) {
+        hipLaunchKernelGGL(k_half_sumsq, dim3(kSumsqBlocks), dim3(256), 0, s, static_cast<const float *>(a.resid),
+                           a.ndata, a.partials);
+        if (nblocks_out) *nblocks_out = kSumsqBlocks;
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (a.tm_out && int64_t(a.nt_max) * a.Q > 0) {
+        const int64_t n = int64_t(a.nt_max) * a.Q;
+        hipLaunchKernelGGL(k_traces_cell, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, b);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_sum_partials(const double *part, int64_t n, double *out, hipStream_t s)

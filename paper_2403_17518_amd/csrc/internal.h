@@ -36,6 +36,9 @@ struct ShotDesc {
     int32_t src_i;   // source row, padded coordinates
     int32_t src_j;   // source column, padded coordinates
     int32_t wav_off; // float offset of the shot's wavelet
+    // bilinear source weights of cells (src_i + a, src_j + b), index 2a + b
+    // (1, 0, 0, 0 for a source on the grid)
+    float sw00, sw01, sw10, sw11;
 };
 
 // One wavefront of a step kernel owns the columns [col0, col0 + width) and
@@ -108,6 +111,16 @@ struct TraceArgs {
     const int32_t *q_nt;     // [Q] record length of the cell's shot
     const int32_t *q_rptr;   // [Q+1] receivers of cell q: q_roff[q_rptr[q]..]
     const int64_t *q_roff;   // trace offsets (floats) in the packed data
+    // off-grid receivers (offgrid != 0): receiver r combines cells
+    // r_cq[r_cptr[r] ..] with weights r_cw[..]; q_rw[k] is the weight of
+    // the receiver entry q_roff[k]; resid [data] holds the combined traces
+    int32_t offgrid;
+    int32_t R;
+    const int32_t *r_cptr, *r_cq, *r_nt;
+    const float *r_cw, *q_rw;
+    const int64_t *r_off;
+    float *resid;
+    int64_t ndata;           // packed data samples
     const float *tm_in;
     float alpha;
     const float *tr_in;
@@ -138,7 +151,10 @@ hipError_t launch_fill(float *p, int64_t n, float val, hipStream_t s);
 // y = a x (n floats)
 hipError_t launch_scale(const float *x, float a, float *y, int64_t n, hipStream_t s);
 hipError_t launch_model_check(const float *v, int64_t n, float *out3, hipStream_t s);
+// Writes per-block misfit partials when a.partials is set; their count
+// goes to *nblocks_out (at most traces_partials_max(Q, nt_max)).
 hipError_t launch_traces(const TraceArgs &a, hipStream_t s, int64_t *nblocks_out);
+int64_t traces_partials_max(int32_t Q, int32_t nt_max);
 hipError_t launch_sum_partials(const double *part, int64_t n, double *out, hipStream_t s);
 hipError_t launch_finalize(const FinalArgs &a, int max_nx, hipStream_t s);
 

@@ -49,20 +49,26 @@ static int run_fd(int argc, char **argv)
     FILE *f = std::fopen(path, "r");
     if (!f) return 2;
     fwi_grid g{};
-    int S = 0, has_win = 0, has_nt = 0, shared = 1;
-    if (std::fscanf(f, "%d %d %d %f %f %d %f %f %d %d %d %d", &g.nz, &g.nx, &g.nb, &g.h, &g.dt, &g.nt_max, &g.v_ref,
-                    &g.R, &S, &has_win, &has_nt, &shared) != 12)
+    int S = 0, has_win = 0, has_nt = 0, shared = 1, has_frac = 0;
+    if (std::fscanf(f, "%d %d %d %f %f %d %f %f %d %d %d %d %d", &g.nz, &g.nx, &g.nb, &g.h, &g.dt, &g.nt_max,
+                    &g.v_ref, &g.R, &S, &has_win, &has_nt, &shared, &has_frac) != 13)
         return 2;
     std::vector<int32_t> sz(S), sx(S), wx0(S), wnx(S), nt(S), rz, rx;
+    std::vector<float> sfz(S), sfx(S), rfz, rfx;
     std::vector<int64_t> rptr(1, 0);
     for (int s = 0; s < S; ++s) {
         int nr = 0;
-        if (std::fscanf(f, "%d %d %d %d %d %d", &sz[s], &sx[s], &wx0[s], &wnx[s], &nt[s], &nr) != 6) return 2;
+        if (std::fscanf(f, "%d %d %d %d %d %d %f %f", &sz[s], &sx[s], &wx0[s], &wnx[s], &nt[s], &nr, &sfz[s],
+                        &sfx[s]) != 8)
+            return 2;
         for (int i = 0; i < nr; ++i) {
             int z, x;
-            if (std::fscanf(f, "%d %d", &z, &x) != 2) return 2;
+            float fz, fx;
+            if (std::fscanf(f, "%d %d %f %f", &z, &x, &fz, &fx) != 4) return 2;
             rz.push_back(z);
             rx.push_back(x);
+            rfz.push_back(fz);
+            rfx.push_back(fx);
         }
         rptr.push_back(rptr.back() + nr);
     }
@@ -88,6 +94,12 @@ static int run_fd(int argc, char **argv)
     geo.rec_x = rx.data();
     geo.wavelet = wav.data();
     geo.wavelet_shared = shared;
+    if (has_frac) {
+        geo.src_fz = sfz.data();
+        geo.src_fx = sfx.data();
+        geo.rec_fz = rfz.data();
+        geo.rec_fx = rfx.data();
+    }
     int64_t ndata = 0;
     for (int s = 0; s < S; ++s) ndata += (rptr[s + 1] - rptr[s]) * (has_nt ? nt[s] : g.nt_max);
 

@@ -49,12 +49,31 @@ def test_binding_signatures_cover_the_header():
     assert set(_abi.SIGNATURES) == _declared_functions()
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the ctypes mirrors equal what a C compiler
+    makes of include/fwi.h and include/deblur.h."""
+    import subprocess
     from paper_2403_17518_amd import _abi
-    # fwi_grid: 9 four-byte fields, no padding
-    assert ctypes.sizeof(_abi.fwi_grid) == 36
-    # fwi_geom: int32 + 9 pointers (padded) + int32
-    assert ctypes.sizeof(_abi.fwi_geom) == 8 + 9 * 8 + 8
+    structs = {"fwi_grid": _abi.fwi_grid, "fwi_geom": _abi.fwi_geom, "fwi_stats": _abi.fwi_stats,
+               "deblur_cfg": _abi.deblur_cfg, "deblur_layer_stat": _abi.deblur_layer_stat}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fwi.h"', '#include "deblur.h"',
+             "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            cname = "pass" if f[0] == "pass_" else f[0]   # a Python keyword in the mirror
+            lines.append(f'printf("{name}.{f[0]} %zu\\n", offsetof({name}, {cname}));')
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.split("\n") if l)
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f in cls._fields_:
+            assert int(got[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, (name, f[0])
 
 
 def test_product_path_does_not_import_the_oracle():

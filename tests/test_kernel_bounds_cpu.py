@@ -116,15 +116,20 @@ def _write_geom(path, grid, acq, v0, vt):
     S = int(acq.nshots)
     has_win, has_nt = acq.win_x0 is not None, acq.nt is not None
     wav = np.asarray(acq.wavelet)
+    frac = acq.src_fz is not None
     lines = [f"{grid.nz} {grid.nx} {grid.nb} {grid.h} {grid.dt} {grid.nt_max} {grid.v_ref} {grid.R} "
-             f"{S} {int(has_win)} {int(has_nt)} {int(wav.ndim == 1)}"]
+             f"{S} {int(has_win)} {int(has_nt)} {int(wav.ndim == 1)} {int(frac)}"]
     for s in range(S):
         r0, r1 = int(acq.rec_ptr[s]), int(acq.rec_ptr[s + 1])
         x0 = int(acq.win_x0[s]) if has_win else 0
         wn = int(acq.win_nx[s]) if has_win else grid.nx
         nt = int(acq.nt[s]) if has_nt else grid.nt_max
-        lines.append(f"{int(acq.src_z[s])} {int(acq.src_x[s])} {x0} {wn} {nt} {r1 - r0}")
-        lines.append(" ".join(f"{int(acq.rec_z[r])} {int(acq.rec_x[r])}" for r in range(r0, r1)))
+        sf = (float(acq.src_fz[s]), float(acq.src_fx[s])) if frac else (0.0, 0.0)
+        lines.append(f"{int(acq.src_z[s])} {int(acq.src_x[s])} {x0} {wn} {nt} {r1 - r0} {sf[0]!r} {sf[1]!r}")
+        lines.append(" ".join(
+            f"{int(acq.rec_z[r])} {int(acq.rec_x[r])} "
+            f"{float(acq.rec_fz[r]) if frac else 0.0!r} {float(acq.rec_fx[r]) if frac else 0.0!r}"
+            for r in range(r0, r1)))
     lines.append(" ".join(f"{float(w):.6e}" for w in wav[..., :grid.nt_max].ravel()))
     lines.append(" ".join(f"{float(v):.3f}" for v in np.asarray(v0, np.float32).ravel()))
     lines.append(" ".join(f"{float(v):.3f}" for v in np.asarray(vt, np.float32).ravel()))
@@ -159,6 +164,28 @@ def edge_geometry(nt_max: int = 8):
     return grid, acq, v0, vt
 
 
+def offgrid_geometry(nt_max: int = 8):
+    """The edge geometry with every source and most receivers between grid
+    points (bilinear spreading), including the last column of a window and
+    the last model row left on the grid where the next cell does not exist."""
+    grid, acq, v0, vt = edge_geometry(nt_max)
+    rng = np.random.default_rng(11)
+    nr = acq.rec_z.shape[0]
+    fz = rng.uniform(0.0, 1.0, nr).astype(np.float32)
+    fx = rng.uniform(0.0, 1.0, nr).astype(np.float32)
+    fz[::5] = 0.0
+    fx[::7] = 0.0
+    for s in range(acq.nshots):
+        a, b = acq.rec_ptr[s], acq.rec_ptr[s + 1]
+        last = acq.win_x0[s] + acq.win_nx[s] - 1
+        fx[a:b][acq.rec_x[a:b] == last] = 0.0
+    fz[acq.rec_z == grid.nz - 1] = 0.0
+    acq.rec_fz, acq.rec_fx = fz, fx
+    acq.src_fz = np.array([0.25, 0.5, 0.0], np.float32)
+    acq.src_fx = np.array([0.75, 0.0, 0.5], np.float32)
+    return grid, acq, v0, vt
+
+
 def _ragged(nt_max: int = 8):
     wl = configs.ragged_small()
     g = wl.grid
@@ -180,9 +207,9 @@ def test_edge_geometry_has_receiverless_last_waves():
     assert int(acq.win_nx[last]) == grid.nx
 
 
-@pytest.mark.parametrize("geom", ["edge", "ragged"])
+@pytest.mark.parametrize("geom", ["edge", "ragged", "offgrid"])
 def test_step_kernels_in_bounds_every_tiling(emu_driver, tmp_path, geom):
-    grid, acq, v0, vt = edge_geometry() if geom == "edge" else _ragged()
+    grid, acq, v0, vt = {"edge": edge_geometry, "ragged": _ragged, "offgrid": offgrid_geometry}[geom]()
     path = str(tmp_path / "geom.txt")
     _write_geom(path, grid, acq, v0, vt)
     out = _run_parallel(emu_driver, ["fd", path], TILINGS)
