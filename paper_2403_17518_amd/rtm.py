@@ -1,6 +1,6 @@
 """RTM images of the observed data in an inverted model (the paper's imaging
-check of its final velocity models, section 4, Volve: images from the
-initial model and from the models of each method are compared).
+check of its final velocity models, section 3.3, Volve field data: images
+from the initial model and from the models of each method are compared).
 
 The image is the migration J^T of the observed data (``born_mig``: the
 adjoint wavefield cross-correlated with the background's second time
