@@ -26,7 +26,8 @@ _lib = None
 class _OgGrid(C.Structure):
     _fields_ = [("nz", C.c_int), ("nx", C.c_int), ("nb", C.c_int),
                 ("h", C.c_double), ("dt", C.c_double),
-                ("v_ref", C.c_double), ("R", C.c_double)]
+                ("v_ref", C.c_double), ("R", C.c_double),
+                ("free_surface", C.c_int)]
 
 
 class _OgGeom(C.Structure):
@@ -69,7 +70,8 @@ class _Call:
     def __init__(self, grid, acq):
         self.keep = []
         self.g = _OgGrid(grid.nz, grid.nx, grid.nb, float(grid.h),
-                         float(grid.dt), float(grid.v_ref), float(grid.R))
+                         float(grid.dt), float(grid.v_ref), float(grid.R),
+                         1 if getattr(grid, "free_surface", False) else 0)
 
         def ptr(a, dt):
             if a is None:
@@ -168,7 +170,7 @@ def shot_fields(grid, acq, s, v, res_shot=None):
     v = _f64(v)
     nt = acq.nt_of(s, grid)
     _, wnx = acq.window(s, grid)
-    NZ, NX = grid.nz + 2 * grid.nb, wnx + 2 * grid.nb
+    NZ, NX = grid.NZ, wnx + 2 * grid.nb
     u = np.zeros((nt + 1, NZ, NX))
     lam = None
     rp = None
@@ -190,9 +192,9 @@ def pad(grid, v, x0=0, wnx=None):
     """Pad(v) of one window: edge replication into the sponge."""
     wnx = grid.nx if wnx is None else wnx
     g = _OgGrid(grid.nz, grid.nx, grid.nb, float(grid.h), float(grid.dt),
-                float(grid.v_ref), float(grid.R))
+                float(grid.v_ref), float(grid.R), 1 if getattr(grid, "free_surface", False) else 0)
     v = _f64(v)
-    P = np.zeros((grid.nz + 2 * grid.nb, wnx + 2 * grid.nb))
+    P = np.zeros((grid.NZ, wnx + 2 * grid.nb))
     lib().oracle_pad(C.byref(g), int(x0), int(wnx), v.ctypes.data_as(C.c_void_p),
                      P.ctypes.data_as(C.c_void_p))
     return P
@@ -202,7 +204,7 @@ def pad_adjoint(grid, P, x0=0, wnx=None):
     """Pad^T of one window: each padded cell adds onto its source cell."""
     wnx = grid.nx if wnx is None else wnx
     g = _OgGrid(grid.nz, grid.nx, grid.nb, float(grid.h), float(grid.dt),
-                float(grid.v_ref), float(grid.R))
+                float(grid.v_ref), float(grid.R), 1 if getattr(grid, "free_surface", False) else 0)
     P = _f64(P)
     img = np.zeros((grid.nz, grid.nx))
     lib().oracle_pad_adjoint(C.byref(g), int(x0), int(wnx), P.ctypes.data_as(C.c_void_p),

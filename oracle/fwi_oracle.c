@@ -11,6 +11,11 @@
  *
  *   padded grid   NZ = nz + 2 nb, NX = wnx + 2 nb per shot window, zero
  *                 values outside the padded box (Dirichlet halo);
+ *   free surface  (optional) the top of the model is a pressure-free
+ *                 surface instead of a sponge: no sponge rows above row 0
+ *                 (NZ = nz + nb), u = 0 on row 0 after every step, and the
+ *                 rows above it are the odd mirror u[-m] = -u[m] (image
+ *                 method);
  *   model         V = Pad(v): edge replication of the shot's window;
  *   Laplacian     L8 u = h^-2 (2 c0 u + sum_k c_k (u[i+-k][j] + u[i][j+-k])),
  *                 c = (-205/72, 8/5, -1/5, 8/315, -1/560);
@@ -56,6 +61,7 @@
 typedef struct {
     int nz, nx, nb;
     double h, dt, v_ref, R;
+    int free_surface;   /* 1: pressure-free top surface on physical row 0 */
 } og_grid;
 
 typedef struct {
@@ -81,6 +87,7 @@ static const double C8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0,
 
 typedef struct {
     int NZ, NX, x0, wnx;
+    int top;     /* padded rows above physical row 0 (0 with a free surface) */
     double *V;   /* padded velocity */
     double *c;   /* V^2 dt^2 */
     double *a, *b;
@@ -101,13 +108,15 @@ static const double *shot_wavelet(const og_geom *geo, int s)
     return geo->wavelet_shared ? geo->wavelet : geo->wavelet + (int64_t)s * geo->nt_max;
 }
 
+static int top_rows(const og_grid *g) { return g->free_surface ? 0 : g->nb; }
+
 /* Pad: edge replication of the window [x0, x0+wnx) of the nz x nx model. */
 static void pad_model(const og_grid *g, int x0, int wnx, const double *v, double *V)
 {
-    int NZ = g->nz + 2 * g->nb, NX = wnx + 2 * g->nb;
+    int NZ = g->nz + g->nb + top_rows(g), NX = wnx + 2 * g->nb;
     for (int i = 0; i < NZ; i++)
         for (int j = 0; j < NX; j++) {
-            int pi = clampi(i - g->nb, 0, g->nz - 1);
+            int pi = clampi(i - top_rows(g), 0, g->nz - 1);
             int pj = x0 + clampi(j - g->nb, 0, wnx - 1);
             V[(int64_t)i * NX + j] = v[(int64_t)pi * g->nx + pj];
         }
@@ -116,20 +125,21 @@ static void pad_model(const og_grid *g, int x0, int wnx, const double *v, double
 /* Pad^T: every padded cell adds onto the physical cell it was copied from. */
 static void pad_adjoint_add(const og_grid *g, int x0, int wnx, const double *P, double *img)
 {
-    int NZ = g->nz + 2 * g->nb, NX = wnx + 2 * g->nb;
+    int NZ = g->nz + g->nb + top_rows(g), NX = wnx + 2 * g->nb;
     for (int i = 0; i < NZ; i++)
         for (int j = 0; j < NX; j++) {
-            int pi = clampi(i - g->nb, 0, g->nz - 1);
+            int pi = clampi(i - top_rows(g), 0, g->nz - 1);
             int pj = x0 + clampi(j - g->nb, 0, wnx - 1);
             img[(int64_t)pi * g->nx + pj] += P[(int64_t)i * NX + j];
         }
 }
 
-static double sponge_depth(int i, int n, int nb)
+static double sponge_depth(int i, int n, int nb, int lo)
 {
-    /* distance (in cells, / nb) into the sponge along one axis */
+    /* distance (in cells, / nb) into the sponge along one axis; lo = width
+     * of the sponge at the low end (nb, or 0 under a free surface) */
     int d = 0;
-    if (i < nb) d = nb - i;
+    if (i < lo) d = lo - i;
     if (i > n - 1 - nb) d = i - (n - 1 - nb);
     return nb > 0 ? (double)d / (double)nb : 0.0;
 }
@@ -137,7 +147,8 @@ static double sponge_depth(int i, int n, int nb)
 static int dom_init(shot_dom *D, const og_grid *g, const og_geom *geo, int s, const double *v)
 {
     shot_window(g, geo, s, &D->x0, &D->wnx);
-    D->NZ = g->nz + 2 * g->nb;
+    D->top = top_rows(g);
+    D->NZ = g->nz + g->nb + D->top;
     D->NX = D->wnx + 2 * g->nb;
     int64_t n = (int64_t)D->NZ * D->NX;
     D->V = malloc(n * sizeof(double));
@@ -150,7 +161,7 @@ static int dom_init(shot_dom *D, const og_grid *g, const og_geom *geo, int s, co
     for (int i = 0; i < D->NZ; i++)
         for (int j = 0; j < D->NX; j++) {
             int64_t k = (int64_t)i * D->NX + j;
-            double dz = sponge_depth(i, D->NZ, g->nb), dx = sponge_depth(j, D->NX, g->nb);
+            double dz = sponge_depth(i, D->NZ, g->nb, D->top), dx = sponge_depth(j, D->NX, g->nb, g->nb);
             double sig = smax * (dz * dz + dx * dx);
             D->a[k] = 1.0 / (1.0 + 0.5 * sig * g->dt);
             D->b[k] = (1.0 - 0.5 * sig * g->dt) / (1.0 + 0.5 * sig * g->dt);
@@ -164,8 +175,9 @@ static void dom_free(shot_dom *D)
     free(D->V); free(D->c); free(D->a); free(D->b);
 }
 
-/* L8 u with zero values outside the NZ x NX box. */
-static void laplacian8(const double *u, int NZ, int NX, double h, double *out)
+/* L8 u with zero values outside the NZ x NX box; with mirror != 0 the rows
+ * above row 0 are the odd mirror u[-m] = -u[m] (free surface). */
+static void laplacian8(const double *u, int NZ, int NX, double h, double *out, int mirror)
 {
     double ih2 = 1.0 / (h * h);
     for (int i = 0; i < NZ; i++)
@@ -173,6 +185,7 @@ static void laplacian8(const double *u, int NZ, int NX, double h, double *out)
             double acc = 2.0 * C8[0] * u[(int64_t)i * NX + j];
             for (int k = 1; k <= 4; k++) {
                 if (i - k >= 0) acc += C8[k] * u[(int64_t)(i - k) * NX + j];
+                else if (mirror && k - i < NZ) acc -= C8[k] * u[(int64_t)(k - i) * NX + j];
                 if (i + k < NZ) acc += C8[k] * u[(int64_t)(i + k) * NX + j];
                 if (j - k >= 0) acc += C8[k] * u[(int64_t)i * NX + j - k];
                 if (j + k < NX) acc += C8[k] * u[(int64_t)i * NX + j + k];
@@ -184,7 +197,13 @@ static void laplacian8(const double *u, int NZ, int NX, double h, double *out)
 /* padded index of a physical cell (z, x) of shot s */
 static int64_t cell_index(const og_grid *g, const shot_dom *D, int z, int x)
 {
-    return (int64_t)(z + g->nb) * D->NX + (x - D->x0 + g->nb);
+    return (int64_t)(z + D->top) * D->NX + (x - D->x0 + g->nb);
+}
+
+/* the pressure-free surface: row 0 held at zero */
+static void pin_surface(const og_grid *g, const shot_dom *D, double *u)
+{
+    if (g->free_surface) memset(u, 0, (size_t)D->NX * sizeof(double));
 }
 
 /* A point (z + fz, x + fx) of shot s's physical grid: the cells it touches
@@ -256,10 +275,11 @@ static int forward_shot(const og_grid *g, const og_geom *geo, int s, const shot_
     double ih2 = 1.0 / (g->h * g->h);
     for (int t = 0; t < nt; t++) {
         if (hist) memcpy(hist + (int64_t)t * n, u0, n * sizeof(double));
-        laplacian8(u0, D->NZ, D->NX, g->h, lap);
+        laplacian8(u0, D->NZ, D->NX, g->h, lap, g->free_surface);
         point_add(&src, w[t] * ih2, lap);
         for (int64_t k = 0; k < n; k++)
             up[k] = D->a[k] * (2.0 * u0[k] + D->c[k] * lap[k]) - D->b[k] * um[k];
+        pin_surface(g, D, up);
         for (int64_t r = 0; r < nrec; r++) {
             point_w rp = rec_point(g, geo, D, r0 + r);
             d_shot[r * nt + t] = point_sample(&rp, up);
@@ -291,14 +311,16 @@ static int born_shot(const og_grid *g, const og_geom *geo, int s, const shot_dom
         int64_t r0 = geo->rec_ptr[s], nrec = geo->rec_ptr[s + 1] - r0;
         double ih2 = 1.0 / (g->h * g->h);
         for (int t = 0; t < nt; t++) {
-            laplacian8(u0, D->NZ, D->NX, g->h, lap);
+            laplacian8(u0, D->NZ, D->NX, g->h, lap, g->free_surface);
             point_add(&src, w[t] * ih2, lap);             /* L8 u^n + s^n */
-            laplacian8(d0, D->NZ, D->NX, g->h, dlap);
+            laplacian8(d0, D->NZ, D->NX, g->h, dlap, g->free_surface);
             for (int64_t k = 0; k < n; k++) {
                 dp[k] = D->a[k] * (2.0 * d0[k] + D->c[k] * (dlap[k] + rho[k] * lap[k]))
                         - D->b[k] * dm[k];
                 up[k] = D->a[k] * (2.0 * u0[k] + D->c[k] * lap[k]) - D->b[k] * um[k];
             }
+            pin_surface(g, D, up);
+            pin_surface(g, D, dp);
             for (int64_t r = 0; r < nrec; r++) {
                 point_w rp = rec_point(g, geo, D, r0 + r);
                 dd_shot[r * nt + t] = point_sample(&rp, dp);
@@ -332,15 +354,16 @@ static int adjoint_shot(const og_grid *g, const og_geom *geo, int s, const shot_
         int64_t r0 = geo->rec_ptr[s], nrec = geo->rec_ptr[s + 1] - r0;
         double ih2 = 1.0 / (g->h * g->h);
         for (int t = nt - 1; t >= 0; t--) {
-            laplacian8(l1, D->NZ, D->NX, g->h, lap);    /* L8 lam^{n+1} */
+            laplacian8(l1, D->NZ, D->NX, g->h, lap, g->free_surface);    /* L8 lam^{n+1} */
             for (int64_t r = 0; r < nrec; r++) {          /* + R^T r^n */
                 point_w rp = rec_point(g, geo, D, r0 + r);
                 point_add(&rp, res_shot[r * nt + t], lap);
             }
             for (int64_t k = 0; k < n; k++)
                 l0[k] = D->a[k] * (2.0 * l1[k] + D->c[k] * lap[k]) - D->b[k] * l2[k];
+            pin_surface(g, D, l0);
             if (lam_hist) memcpy(lam_hist + (int64_t)t * n, l0, n * sizeof(double));
-            laplacian8(hist + (int64_t)t * n, D->NZ, D->NX, g->h, lu);
+            laplacian8(hist + (int64_t)t * n, D->NZ, D->NX, g->h, lu, g->free_surface);
             point_add(&src, w[t] * ih2, lu);              /* L8 u^n + s^n */
             for (int64_t k = 0; k < n; k++) G[k] += l0[k] * lu[k];
             double *tmp = l2; l2 = l1; l1 = l0; l0 = tmp;

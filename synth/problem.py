@@ -28,10 +28,16 @@ class Grid:
     v_ref: float     # fixed sponge reference velocity (m/s)
     R: float = 1e-3  # nominal sponge reflection coefficient
     ckpt_every: int = 0  # checkpoint interval for the GPU path (0 = auto)
+    free_surface: bool = False  # pressure-free top surface on row 0 (no top sponge)
+
+    @property
+    def top(self) -> int:
+        """Padded rows above physical row 0."""
+        return 0 if self.free_surface else self.nb
 
     @property
     def NZ(self) -> int:
-        return self.nz + 2 * self.nb
+        return self.nz + self.nb + self.top
 
 
 @dataclass
