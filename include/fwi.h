@@ -73,7 +73,8 @@ typedef struct fwi_ctx fwi_ctx;
 
 typedef struct {
     int32_t nz, nx;     /* physical model rows (depth) and columns */
-    int32_t nb;         /* sponge width in cells on all four sides, >= 0 */
+    int32_t nb;         /* sponge width in cells on all four sides (three under
+                           a free surface), >= 0 */
     float h;            /* grid spacing (m); dz == dx */
     float dt;           /* time step (s) */
     int32_t nt_max;     /* longest record; length of a shared wavelet */
@@ -81,6 +82,10 @@ typedef struct {
     float R;            /* nominal sponge reflection coefficient, (0, 1) */
     int32_t ckpt_every; /* checkpoint interval (steps) for the adjoint
                            sweeps; 0 = chosen from the memory budget */
+    int32_t free_surface; /* 1: the top of the model (physical row 0) is a
+                             pressure-free surface - no sponge above it, u = 0
+                             on it, odd mirror above it (image method); the
+                             step kernels then run one level per launch */
 } fwi_grid;
 
 typedef struct {

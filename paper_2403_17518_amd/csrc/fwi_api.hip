@@ -39,6 +39,8 @@ struct DevBuf {
 struct Plan {
     // grid
     int nz = 0, nx = 0, nb = 0, NZ = 0, nt_max = 0, S = 0;
+    int top = 0;                  // padded rows above physical row 0
+    bool free_surface = false;    // pressure-free top surface (no top sponge)
     float h = 0, dt = 0, v_ref = 0, R = 0;
     int ckpt_every = 0;
     // shots in slot order (record length decreasing)
@@ -242,7 +244,9 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
         return set_err(c, FWI_ECFL, "v_ref*dt/h = %.4f exceeds %.2f", double(g->v_ref) * g->dt / g->h,
                        kCflLimit);
     if (g->ckpt_every < 0) return set_err(c, FWI_EINVAL, "ckpt_every must be >= 0");
-    const int64_t NZ64 = int64_t(g->nz) + 2 * int64_t(g->nb);
+    if (g->free_surface != 0 && g->free_surface != 1) return set_err(c, FWI_EINVAL, "free_surface must be 0 or 1");
+    const int top = g->free_surface ? 0 : g->nb;
+    const int64_t NZ64 = int64_t(g->nz) + int64_t(g->nb) + top;
     if (NZ64 > (1 << 20) || int64_t(g->nx) + 2 * g->nb > (1 << 20))
         return set_err(c, FWI_EINVAL, "grid too large");
     const int S = geo->nshots;
@@ -299,6 +303,8 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
     p.nx = g->nx;
     p.nb = g->nb;
     p.NZ = int(NZ64);
+    p.top = top;
+    p.free_surface = g->free_surface != 0;
     p.nt_max = g->nt_max;
     p.h = g->h;
     p.dt = g->dt;
@@ -363,7 +369,7 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
         d.x0 = x0[s];
         d.wnx = wnx[s];
         d.nt = nts[s];
-        d.src_i = geo->src_z[s] + p.nb;
+        d.src_i = geo->src_z[s] + p.top;
         d.src_j = geo->src_x[s] - x0[s] + p.nb;
         if (geo->wavelet_shared) d.wav_off = 0;
         else {
@@ -394,7 +400,7 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
         std::map<std::pair<int, int>, std::vector<std::pair<int64_t, float>>> cells;
         std::vector<std::vector<std::pair<std::pair<int, int>, float>>> rec_cells;
         for (int64_t r = geo->rec_ptr[s]; r < geo->rec_ptr[s + 1]; ++r) {
-            const int i = geo->rec_z[r] + p.nb, jj = geo->rec_x[r] - x0[s] + p.nb;
+            const int i = geo->rec_z[r] + p.top, jj = geo->rec_x[r] - x0[s] + p.nb;
             const int64_t off = data_off[s] + (r - geo->rec_ptr[s]) * int64_t(nts[s]);
             float w[4];
             weights(geo->rec_fz ? geo->rec_fz[r] : 0.0, geo->rec_fz ? geo->rec_fx[r] : 0.0, w);
@@ -587,6 +593,8 @@ StepArgs base_args(fwi_ctx *c, const float *v, int cls)
     a.nz = p.nz;
     a.nx = p.nx;
     a.nb = p.nb;
+    a.top = p.top;
+    a.fs = p.free_surface ? 1 : 0;
     a.NZ = p.NZ;
     const double ih2 = 1.0 / (double(p.h) * p.h);
     a.w1 = float(kC8[1] * ih2);
@@ -1040,6 +1048,7 @@ int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
     fin.nz = p.nz;
     fin.nx = p.nx;
     fin.nb = p.nb;
+    fin.top = p.top;
     fin.NZ = p.NZ;
     fin.dt2 = float(double(p.dt) * p.dt);
     fin.img = img;
@@ -1172,6 +1181,8 @@ int ensure_tilings(fwi_ctx *c, const float *v)
         const int want_cw = forced ? c->force_cw[k] : (c->autotune ? 0 : kDefaultCw);
         const int want_rows = forced ? c->force_rows[k] : (c->autotune ? 0 : kDefaultRows);
         const int want_tb = one_level(k) ? 1 : (forced ? c->force_tb[k] : (c->autotune ? 0 : kDefaultTb));
+        if (want_tb == 2 && p.free_surface)
+            return set_err(c, FWI_EINVAL, "two-level tilings do not support a free surface (force one level)");
         const int want_pd = forced ? c->force_pd[k] : kDefaultPd;
         if (want_cw && want_rows && want_tb) {
             if (t.cw == want_cw && t.rows == want_rows && t.tb == want_tb && t.pd == want_pd) continue;
@@ -1212,7 +1223,8 @@ int ensure_tilings(fwi_ctx *c, const float *v)
             build_tiling(p, cand.cw, cand.rows, cand.tb, cand.pd, trial);
             if ((rc = upload_tiling(c, trial))) break;
             for (int k = 0; k < kClasses; ++k) {
-                if (c->tile[k].cw != 0 || (one_level(k) && cand.tb != 1) || (k == K_BORN && cand.pd != 1))
+                if (c->tile[k].cw != 0 || ((one_level(k) || p.free_surface) && cand.tb != 1) ||
+                    (k == K_BORN && cand.pd != 1))
                     continue;
                 float ms = 0.f;
                 if ((rc = time_class(c, k, trial, v, &ms))) break;

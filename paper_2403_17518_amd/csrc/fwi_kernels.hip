@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
         bld<CW>(rprev, jl, ro, pre.pv);
         // only lanes 0 and 1 read (and later use) the halo columns
         if (lane < 2) pre.h = bld4(rcur, hcol, ro - 4 * kHalo);
-        const int vo = 4 * clampi(z - nb, 0, A.nz - 1) * A.nx;
+        const int vo = 4 * clampi(z - A.top, 0, A.nz - 1) * A.nx;
 #pragma unroll
         for (int k = 0; k < CW; ++k) pre.v[k] = bld1(rv, jm[k], vo);
         if (FL & F_IMAGE) {
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
                 rrow = rr < W.rr1 ? A.rrows[rr].row : kNoRow;
             }
         }
-        const int ddz = max(max(nb - z, z - (A.NZ - 1 - nb)), 0);
+        const int ddz = max(max(A.top - z, z - (A.NZ - 1 - nb)), 0);
         const float dz2 = float(ddz * ddz);
         float out[CW], Dv[CW];
 #pragma unroll
@@ -295,6 +295,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
             // scattered field: the linearised velocity term (2 dV / V) D^n
             if (FL & F_SCAT) Dv[k] = __builtin_fmaf(2.0f * c.dv[k] / c.v[k], c.d[k], Dv[k]);
             out[k] = leapfrog(q[4][k], c.pv[k], Dv[k], a, sh);
+            if (A.fs && z == 0) out[k] = 0.0f;   // the pressure-free surface
         }
         const int ro = 4 * (z + kRowsAbove) * P, go = 4 * z * P;
 #pragma unroll
@@ -305,6 +306,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
                 if (FL & F_IMAGE) bst1(rg, js + 4 * k, go, __builtin_fmaf(out[k], c.d[k], c.g[k]));
                 if (FL & F_SAMPLE)
                     if (qi[k] >= 0) A.samp[qi[k]] = out[k];
+                // odd mirror above the free surface: rows -1..-4 of the new level
+                if (A.fs && z >= 1 && z <= kHalo) bst1(rprev, js + 4 * k, 4 * (kRowsAbove - z) * P, -out[k]);
             }
         }
 #pragma unroll
@@ -416,7 +419,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         bld<CW>(run, jl4, ro + 4 * kHalo * P, nq);
         bld<CW>(rum, jl4, ro, npv);
         if (lane < 2) nh = bld4(run, hcol4, ro - 4 * kHalo);
-        const int vo = 4 * clampi(t - nb, 0, A.nz - 1) * A.nx;
+        const int vo = 4 * clampi(t - A.top, 0, A.nz - 1) * A.nx;
 #pragma unroll
         for (int k = 0; k < CW; ++k) nv[k] = bld1(rv, jm[k], vo);
         if (FL & F_IMAGE) {
@@ -482,7 +485,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
             }
         }
         const bool row_in = t >= 0 && t < NZ;
-        const int ddz1 = max(max(nb - t, t - (NZ - 1 - nb)), 0);
+        const int ddz1 = max(max(A.top - t, t - (NZ - 1 - nb)), 0);
         const float dz1 = float(ddz1 * ddz1);
         float v1[CW], D1[CW];
 #pragma unroll
@@ -540,7 +543,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
             }
         }
         if (r2 >= W.z0) {   // r2 < z1 always holds
-            const int ddz2 = max(max(nb - r2, r2 - (NZ - 1 - nb)), 0);
+            const int ddz2 = max(max(A.top - r2, r2 - (NZ - 1 - nb)), 0);
             const float dz2 = float(ddz2 * ddz2);
             const int o = 4 * (r2 + kRowsAbove) * P;
 #pragma unroll
@@ -654,7 +657,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
             nh = bld4(rcu, hcol, ro - 4 * kHalo);
             nhd = bld4(rcd, hcol, ro - 4 * kHalo);
         }
-        const int vo = 4 * clampi(z - nb, 0, A.nz - 1) * A.nx;
+        const int vo = 4 * clampi(z - A.top, 0, A.nz - 1) * A.nx;
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             nv[k] = bld1(rv, jm[k], vo);
@@ -712,7 +715,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
             ++rr;
             rrow = rr < W.rr1 ? A.rrows[rr].row : kNoRow;
         }
-        const int ddz = max(max(nb - z, z - (A.NZ - 1 - nb)), 0);
+        const int ddz = max(max(A.top - z, z - (A.NZ - 1 - nb)), 0);
         const float dz2 = float(ddz * ddz);
         float ou[CW], od[CW], Dv[CW];
 #pragma unroll
@@ -730,6 +733,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
             Dv[k] = c * lap;
             ou[k] = leapfrog(q[4][k], cpv[k], Dv[k], a, sh);
             od[k] = leapfrog(r[4][k], cpd[k], __builtin_fmaf(cr, lap, c * lapd), a, sh);
+            if (A.fs && z == 0) ou[k] = od[k] = 0.0f;   // the pressure-free surface
         }
         const int o = 4 * (z + kRowsAbove) * P;
 #pragma unroll
@@ -739,6 +743,10 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
                 bst1(rpd, js + 4 * k, o, od[k]);
                 if (EMIT) bst1(rd, js + 4 * k, 4 * z * P, Dv[k]);
                 if (qi[k] >= 0) A.samp[qi[k]] = od[k];
+                if (A.fs && z >= 1 && z <= kHalo) {   // odd mirror above the free surface
+                    bst1(rpv, js + 4 * k, 4 * (kRowsAbove - z) * P, -ou[k]);
+                    bst1(rpd, js + 4 * k, 4 * (kRowsAbove - z) * P, -od[k]);
+                }
             }
         }
 #pragma unroll
@@ -931,12 +939,10 @@ __global__ __launch_bounds__(256) void k_fold_rows(const FinalArgs A, int maxNX)
     const ShotDesc S = A.shots[s];
     if (j >= S.NX || A.nb == 0) return;
     float *G = A.G + S.g_off;
-    const int top = A.nb, bot = A.NZ - 1 - A.nb;
+    const int top = A.top, bot = A.NZ - 1 - A.nb;
     float t = 0.f, b = 0.f;
-    for (int r = 0; r <= A.nb; ++r) {
-        t += G[int64_t(r) * S.P + j];
-        b += G[int64_t(bot + r) * S.P + j];
-    }
+    for (int r = 0; r <= A.top; ++r) t += G[int64_t(r) * S.P + j];
+    for (int r = 0; r <= A.nb; ++r) b += G[int64_t(bot + r) * S.P + j];
     if (top == bot) {  // one physical row: everything folds onto it
         G[int64_t(top) * S.P + j] = t + b - G[int64_t(top) * S.P + j];
     } else {
@@ -947,7 +953,7 @@ __global__ __launch_bounds__(256) void k_fold_rows(const FinalArgs A, int maxNX)
 
 __global__ __launch_bounds__(256) void k_fold_cols(const FinalArgs A)
 {
-    const int i = A.nb + blockIdx.x * blockDim.x + threadIdx.x;  // physical rows only
+    const int i = A.top + blockIdx.x * blockDim.x + threadIdx.x;  // physical rows only
     const int s = blockIdx.y;
     if (i > A.NZ - 1 - A.nb || A.nb == 0) return;
     const ShotDesc S = A.shots[s];
@@ -979,7 +985,7 @@ __global__ __launch_bounds__(256) void k_finalize(const FinalArgs A)
         const ShotDesc S = A.shots[s];
         const int jl = j - S.x0;
         if (jl < 0 || jl >= S.wnx) continue;
-        acc += A.G[S.g_off + int64_t(i + A.nb) * S.P + jl + A.nb];
+        acc += A.G[S.g_off + int64_t(i + A.top) * S.P + jl + A.nb];
     }
     const float v = A.v[p];
     A.img[p] = acc * (2.0f / (v * v * v * A.dt2));

@@ -77,6 +77,8 @@ struct StepArgs {
     const float *dv;     // Born perturbation [nz][nx]
     const float *wav;    // wavelets
     int32_t nwaves, nz, nx, nb, NZ;
+    int32_t top;               // padded rows above physical row 0 (nb, or 0 under a free surface)
+    int32_t fs;                // free surface: row 0 held at zero, odd mirror above it
     int32_t cw;                // columns per lane of the wave table (1 or 2)
     int32_t pd;                // one-level kernel: rows prefetched ahead (1 or 2)
     float w1, w2, w3, w4;      // c_k / h^2 (the centre weight is -4 times their sum)
@@ -136,6 +138,7 @@ struct FinalArgs {
     float *G;           // folded in place
     const float *v;
     int32_t nz, nx, nb, NZ;
+    int32_t top;        // padded rows above physical row 0
     float dt2;
     float *img;
 };

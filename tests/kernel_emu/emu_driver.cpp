@@ -50,8 +50,8 @@ static int run_fd(int argc, char **argv)
     if (!f) return 2;
     fwi_grid g{};
     int S = 0, has_win = 0, has_nt = 0, shared = 1, has_frac = 0;
-    if (std::fscanf(f, "%d %d %d %f %f %d %f %f %d %d %d %d %d", &g.nz, &g.nx, &g.nb, &g.h, &g.dt, &g.nt_max,
-                    &g.v_ref, &g.R, &S, &has_win, &has_nt, &shared, &has_frac) != 13)
+    if (std::fscanf(f, "%d %d %d %f %f %d %f %f %d %d %d %d %d %d", &g.nz, &g.nx, &g.nb, &g.h, &g.dt, &g.nt_max,
+                    &g.v_ref, &g.R, &S, &has_win, &has_nt, &shared, &has_frac, &g.free_surface) != 14)
         return 2;
     std::vector<int32_t> sz(S), sx(S), wx0(S), wnx(S), nt(S), rz, rx;
     std::vector<float> sfz(S), sfx(S), rfz, rfx;

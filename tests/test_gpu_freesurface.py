@@ -1,0 +1,118 @@
+"""GPU parity of the pressure-free top surface (image method) against the
+FP64 oracle: forward data, misfit and gradient (with and without
+checkpointing), Born data, migration and the fused gradient + pair; the
+surface row records zero; one-level tilings agree bitwise; a two-level
+tiling is refused."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2403_17518_amd import ops, _abi  # noqa: E402
+
+TOL_DATA = 1e-4
+TOL_IMAGE = 1e-4
+TOL_GRAD = 1e-3
+
+
+def rel(a, b):
+    a, b = np.ravel(np.asarray(a, np.float64)), np.ravel(np.asarray(b, np.float64))
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ops.FwiContext(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ragged_fs():
+    wl = configs.ragged_small()
+    wl.grid = replace(wl.grid, free_surface=True)
+    wl.acq.wavelet = np.asarray(wl.acq.wavelet, np.float32)
+    return wl
+
+
+@pytest.mark.parametrize("ckpt", [0, 29])
+def test_free_surface_operators_match_oracle(ctx, ragged_fs, ckpt):
+    wl = ragged_fs
+    g, acq = replace(wl.grid, ckpt_every=ckpt), wl.acq
+    print(f"[free surface] ragged ckpt={ckpt}", flush=True)
+    vt = np.asarray(wl.v_true, np.float32).astype(np.float64)
+    v0 = np.asarray(wl.v0, np.float32).astype(np.float64)
+    d_obs = np.asarray(oracle.forward(g, acq, vt), np.float32).astype(np.float64)
+    d = host(ctx.fwi_forward(g, acq, dev(vt)))
+    assert rel(d, d_obs) < TOL_DATA
+    gr, phi, _ = ctx.fwi_gradient(g, acq, dev(v0), dev(d_obs))
+    g_ref, phi_ref, _ = oracle.gradient(g, acq, v0, d_obs)
+    e_g = rel(host(gr), g_ref)
+    print("gradient rel err", e_g)
+    assert e_g < TOL_GRAD
+    assert abs(phi - phi_ref) <= 1e-4 * abs(phi_ref)
+    if ckpt:
+        assert ctx.stats()["n_segments"] > 1
+    dv = np.asarray(wl.v_true - wl.v0, np.float32).astype(np.float64)
+    dd = host(ctx.born_demig(g, acq, dev(v0), dev(dv)))
+    assert rel(dd, oracle.born_demig(g, acq, v0, dv)) < TOL_DATA
+    y = np.random.default_rng(4).standard_normal(acq.data_size(g)).astype(np.float32).astype(np.float64)
+    im = host(ctx.born_mig(g, acq, dev(v0), dev(y)))
+    assert rel(im, oracle.born_mig(g, acq, v0, y)) < TOL_IMAGE
+    grad, phi2, img = ctx.gradient_pair(g, acq, dev(v0), dev(d_obs), scale=-1.0)
+    assert torch.equal(grad, gr) and phi2 == phi
+    e_p = rel(host(img), oracle.born_pair(g, acq, v0, -host(grad)))
+    print("pair rel err", e_p)
+    assert e_p < TOL_IMAGE
+
+
+def test_surface_receivers_record_zero(ctx, ragged_fs):
+    wl = ragged_fs
+    g, a = wl.grid, wl.acq
+    from synth import Acquisition
+    acq = Acquisition(src_z=a.src_z[:1], src_x=a.src_x[:1], rec_ptr=[0, 2], rec_z=[0, 3],
+                      rec_x=[a.src_x[0], a.src_x[0]], wavelet=a.wavelet, win_x0=a.win_x0[:1],
+                      win_nx=a.win_nx[:1], nt=a.nt[:1] if a.nt is not None else None)
+    d = host(ctx.fwi_forward(g, acq, dev(wl.v_true))).reshape(2, -1)
+    assert np.all(d[0] == 0.0) and np.abs(d[1]).max() > 0.0
+
+
+def test_free_surface_tilings_bitwise_equal_and_two_levels_refused(ctx, ragged_fs):
+    wl = ragged_fs
+    g, acq = wl.grid, wl.acq
+    v0, vt = dev(wl.v0), dev(wl.v_true)
+    outs = []
+    for t in [(1, 7, 1, 1), (2, 13, 1, 2), (1, 300, 1, 2), (2, 5, 1, 1)]:
+        print(f"[free surface] tiling {t}", flush=True)
+        ctx.set_tiling(-1, *t)
+        d = ctx.fwi_forward(g, acq, vt)
+        gr = ctx.fwi_gradient(g, acq, v0, d * 0.5)[0]
+        dd = ctx.born_demig(g, acq, v0, vt - v0)
+        gp = ctx.gradient_pair(g, acq, v0, d * 0.5, scale=-1.0)[2]
+        outs.append((d, gr, dd, gp))
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert torch.equal(a, b)
+    ctx.set_tiling(-1, 1, 24, 2, 1)
+    with pytest.raises(_abi.FwiError):
+        ctx.fwi_forward(g, acq, vt)
+    ctx.set_tiling(-1, 0, 0, 0)
+    ctx.fwi_forward(g, acq, vt)                   # the autotuner keeps to one level
+    assert ctx.stats()["tile_levels"] == [1, 1, 1, 1]
