@@ -50,15 +50,30 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks)
 // (level 1) and 8 (level 2) above the padded box, so -1 is a real row there.
 constexpr int kNoRow = -(1 << 30);
 
-// The source term at (row, column) offset (a, b) from the source cell: a
-// source off the grid is spread over the four cells a, b in {0, 1} with
-// bilinear weights (on the grid the weights are 1, 0, 0, 0, and the term is
-// the plain add).
-__device__ __forceinline__ float add_source(float lap, float wsrc, int a, int b, const ShotDesc &S)
+// Source weights of a lane's columns: a source off the grid is spread over
+// the cells (src_i + a, src_j + b), a, b in {0, 1}, with bilinear weights
+// (on the grid: 1 at the source cell, 0 elsewhere, and the fused add below
+// is the plain add). w0[k] / w1[k] hold the weights of column k on rows
+// src_i / src_i + 1 (zero off the source columns); src_k = src_j - j0.
+template <int CW>
+__device__ __forceinline__ void source_weights(const ShotDesc &S, int src_k, float (&w0)[CW], float (&w1)[CW])
 {
-    if (unsigned(a) > 1u || unsigned(b) > 1u) return lap;
-    const float w = a == 0 ? (b == 0 ? S.sw00 : S.sw01) : (b == 0 ? S.sw10 : S.sw11);
-    return __builtin_fmaf(wsrc, w, lap);
+#pragma unroll
+    for (int k = 0; k < CW; ++k) {
+        const int b = k - src_k;
+        w0[k] = b == 0 ? S.sw00 : (b == 1 ? S.sw01 : 0.0f);
+        w1[k] = b == 0 ? S.sw10 : (b == 1 ? S.sw11 : 0.0f);
+    }
+}
+
+// the source term on row r (wave-uniform) of column k
+template <int CW>
+__device__ __forceinline__ float add_source(float lap, float wsrc, int r, int src_i, const float (&w0)[CW],
+                                            const float (&w1)[CW], int k)
+{
+    if (r == src_i) return __builtin_fmaf(wsrc, w0[k], lap);
+    if (r == src_i + 1) return __builtin_fmaf(wsrc, w1[k], lap);
+    return lap;
 }
 
 __device__ __forceinline__ float sponge_a(float sh)
@@ -250,6 +265,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     if (FL & (F_SAMPLE | F_INJECT)) rrow = rr < W.rr1 ? A.rrows[rr].row : kNoRow;
     const float wsrc = (FL & F_SRC) ? A.wav[S.wav_off + A.n] * A.ih2 : 0.0f;
     const int src_k = S.src_j - j0;          // column of the source in this lane, if 0..CW-1
+    float sw0[CW], sw1[CW];
+    if (FL & F_SRC) source_weights<CW>(S, src_k, sw0, sw1);
 
     auto do_row = [&](int z, const Pre &c) {
 #pragma unroll
@@ -282,7 +299,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             float lap = lap8(q, xr, k, A.w1, A.w2, A.w3, A.w4);
-            if (FL & F_SRC) lap = add_source(lap, wsrc, z - S.src_i, k - src_k, S);
+            if (FL & F_SRC) lap = add_source<CW>(lap, wsrc, z, S.src_i, sw0, sw1, k);
             if (FL & F_INJECT)
                 if (qi[k] >= 0) lap += A.inj[qi[k]];
             const float cc = c.v[k] * c.v[k] * A.dt2;
@@ -446,6 +463,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
     const float wsrc1 = (FL & F_SRC) ? A.wav[S.wav_off + A.n] * A.ih2 : 0.0f;
     const float wsrc2 = (FL & F_SRC) && lvl2_ok ? A.wav[S.wav_off + A.n2] * A.ih2 : 0.0f;
     const int src_k = S.src_j - j0;
+    float sw0[CW], sw1[CW];
+    if (FL & F_SRC) source_weights<CW>(S, src_k, sw0, sw1);
 
     for (int t = t0; t < t1; ++t) {
         float cpv[CW], cv[CW], cd1[CW], cd2[CW], cg[CW];
@@ -491,7 +510,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             float lap = lap8(qa, xr, k, A.w1, A.w2, A.w3, A.w4);
-            if (FL & F_SRC) lap = add_source(lap, wsrc1, t - S.src_i, k - src_k, S);
+            if (FL & F_SRC) lap = add_source<CW>(lap, wsrc1, t, S.src_i, sw0, sw1, k);
             if (FL & F_INJECT)
                 if (qi1[k] >= 0) lap += A.inj[qi1[k]];
             const float c = cv[k] * cv[k] * A.dt2;
@@ -549,7 +568,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 #pragma unroll
             for (int k = 0; k < CW; ++k) {
                 float lap = lap8(qb, yr, k, A.w1, A.w2, A.w3, A.w4);
-                if (FL & F_SRC) lap = add_source(lap, wsrc2, r2 - S.src_i, k - src_k, S);
+                if (FL & F_SRC) lap = add_source<CW>(lap, wsrc2, r2, S.src_i, sw0, sw1, k);
                 if (FL & F_INJECT)
                     if (qi2[k] >= 0) lap += A.inj2[qi2[k]];
                 const float c = cq[0][k];
@@ -670,6 +689,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
     int rrow = rr < W.rr1 ? A.rrows[rr].row : kNoRow;
     const float wsrc = A.wav[S.wav_off + A.n] * A.ih2;
     const int src_k = S.src_j - j0;
+    float sw0[CW], sw1[CW];
+    source_weights<CW>(S, src_k, sw0, sw1);
 
     for (int z = W.z0; z < W.z1; ++z) {
         float cpv[CW], cpd[CW], cv[CW], cdv[CW];
@@ -722,7 +743,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
         for (int k = 0; k < CW; ++k) {
             float lap = lap8(q, xr, k, A.w1, A.w2, A.w3, A.w4);
             const float lapd = lap8(r, xd, k, A.w1, A.w2, A.w3, A.w4);
-            lap = add_source(lap, wsrc, z - S.src_i, k - src_k, S);
+            lap = add_source<CW>(lap, wsrc, z, S.src_i, sw0, sw1, k);
             const float c = cv[k] * cv[k] * A.dt2;
             const float cr = 2.0f * cv[k] * cdv[k] * A.dt2;
             float a = ax[k], sh = shx[k];
