@@ -27,7 +27,7 @@ class _OgGrid(C.Structure):
     _fields_ = [("nz", C.c_int), ("nx", C.c_int), ("nb", C.c_int),
                 ("h", C.c_double), ("dt", C.c_double),
                 ("v_ref", C.c_double), ("R", C.c_double),
-                ("free_surface", C.c_int)]
+                ("free_surface", C.c_int), ("relative", C.c_int)]
 
 
 class _OgGeom(C.Structure):
@@ -71,7 +71,8 @@ class _Call:
         self.keep = []
         self.g = _OgGrid(grid.nz, grid.nx, grid.nb, float(grid.h),
                          float(grid.dt), float(grid.v_ref), float(grid.R),
-                         1 if getattr(grid, "free_surface", False) else 0)
+                         1 if getattr(grid, "free_surface", False) else 0,
+                         1 if getattr(grid, "relative", False) else 0)
 
         def ptr(a, dt):
             if a is None:
@@ -114,7 +115,9 @@ def forward(grid, acq, v) -> np.ndarray:
 
 
 def born_demig(grid, acq, v, dv) -> np.ndarray:
-    """dd = J dv: Born modelling (section 2.2 eq. 11-12b)."""
+    """dd = J dv: Born modelling (section 2.2 eq. 11-12b); with
+    ``grid.relative`` the perturbation is dv / v and the operator J diag(v)
+    (eq. 12)."""
     c = _Call(grid, acq)
     v, dv = _f64(v), _f64(dv)
     dd = np.zeros(acq.data_size(grid))
@@ -126,7 +129,8 @@ def born_demig(grid, acq, v, dv) -> np.ndarray:
 
 
 def born_mig(grid, acq, v, dd) -> np.ndarray:
-    """img = J^T dd: adjoint Born / migration (section 2.3 eq. 13)."""
+    """img = J^T dd: adjoint Born / migration (section 2.3 eq. 13); with
+    ``grid.relative``, diag(v) J^T dd."""
     c = _Call(grid, acq)
     v, dd = _f64(v), _f64(dd)
     img = np.zeros((grid.nz, grid.nx))

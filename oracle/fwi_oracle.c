@@ -38,6 +38,12 @@
  *                 du^{n+1} = a (2 du^n + V^2 dt^2 (L8 du^n + rho (L8 u^n + s^n)))
  *                            - b du^{n-1},  dd[r][n] = du^{n+1}[rz][rx].
  *
+ *   Relative perturbation (eq. 12 writes the Born operator on dm / m_o):
+ *                 with the grid's `relative` flag set, the operator is
+ *                 J_rel = J diag(v): born_demig takes dm = dv / v and runs
+ *                 the above on dv = v dm; born_mig (and so the gradient)
+ *                 returns diag(v) J^T r, its exact transpose.
+ *
  *   Adjoint (eq. 13; exact transpose of the Born map):
  *                 lam^n = a (2 lam^{n+1} + V^2 dt^2 (L8 lam^{n+1} + R^T r^n))
  *                         - b lam^{n+2},  n = nt-1 .. 0, lam^{nt} = lam^{nt+1} = 0,
@@ -62,6 +68,7 @@ typedef struct {
     int nz, nx, nb;
     double h, dt, v_ref, R;
     int free_surface;   /* 1: pressure-free top surface on physical row 0 */
+    int relative;       /* 1: Born operator on dv / v (J diag(v)) */
 } og_grid;
 
 typedef struct {
@@ -410,9 +417,17 @@ int oracle_forward(const og_grid *g, const og_geom *geo, const double *v, double
     return err ? -1 : 0;
 }
 
-/* dd = J dv. */
+/* dd = J dv (relative: dd = J diag(v) dm, the perturbation given as dm = dv / v). */
 int oracle_born_demig(const og_grid *g, const og_geom *geo, const double *v, const double *dv, double *dd)
 {
+    double *abs_dv = NULL;
+    if (g->relative) {
+        int64_t npix = (int64_t)g->nz * g->nx;
+        abs_dv = malloc((size_t)npix * sizeof(double) + 1);
+        if (!abs_dv) return -1;
+        for (int64_t k = 0; k < npix; k++) abs_dv[k] = v[k] * dv[k];
+        dv = abs_dv;
+    }
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
     for (int s = 0; s < geo->nshots; s++) {
@@ -421,10 +436,11 @@ int oracle_born_demig(const og_grid *g, const og_geom *geo, const double *v, con
         err |= born_shot(g, geo, s, &D, dv, dd + shot_data_offset(geo, s)) ? 1 : 0;
         dom_free(&D);
     }
+    free(abs_dv);
     return err ? -1 : 0;
 }
 
-/* img = J^T r (shot images summed in shot order). */
+/* img = J^T r (shot images summed in shot order); relative: diag(v) J^T r. */
 int oracle_born_mig(const og_grid *g, const og_geom *geo, const double *v, const double *r, double *img)
 {
     int64_t npix = (int64_t)g->nz * g->nx;
@@ -441,6 +457,8 @@ int oracle_born_mig(const og_grid *g, const og_geom *geo, const double *v, const
     memset(img, 0, npix * sizeof(double));
     for (int s = 0; s < geo->nshots; s++)
         for (int64_t k = 0; k < npix; k++) img[k] += per[s * npix + k];
+    if (g->relative)
+        for (int64_t k = 0; k < npix; k++) img[k] *= v[k];
     free(per);
     return err ? -1 : 0;
 }

@@ -29,6 +29,7 @@ class Grid:
     R: float = 1e-3  # nominal sponge reflection coefficient
     ckpt_every: int = 0  # checkpoint interval for the GPU path (0 = auto)
     free_surface: bool = False  # pressure-free top surface on row 0 (no top sponge)
+    relative: bool = False  # Born perturbations and images per dv / v (J diag(v)) instead of per dv
 
     @property
     def top(self) -> int:
