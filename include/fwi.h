@@ -12,7 +12,8 @@
  *
  * where J = dF/dv is the exact Jacobian of the discrete forward map, so
  * born_mig(v, born_demig(v, g)) is the doubly migrated image J^T J g of
- * section 2.3 eq. 15.
+ * section 2.3 eq. 15. With fwi_grid.relative = 1 every J above is
+ * J diag(v), the operator on relative perturbations dv / v of eq. 12.
  *
  * Discretisation (the paper names the finite-difference method but not a
  * scheme; this is the library's definition): constant-density acoustic wave
@@ -86,6 +87,15 @@ typedef struct {
                              pressure-free surface - no sponge above it, u = 0
                              on it, odd mirror above it (image method); the
                              step kernels then run one level per launch */
+    int32_t relative;   /* perturbation parametrisation of the Born operator
+                           (section 2.2, eq. 12: L acts on dm / m_o).
+                           0: absolute velocity, J = dF/dv; born_demig takes
+                           dv in m/s, and born_mig, fwi_gradient and the
+                           pairs return images per m/s.
+                           1: relative perturbation dv / v, J_rel = J diag(v);
+                           born_demig takes the dimensionless dv / v, and the
+                           images are diag(v) J^T (fwi_gradient then returns
+                           the gradient with respect to ln v). */
 } fwi_grid;
 
 typedef struct {

@@ -10,9 +10,13 @@
   only scales the stored gradient.
 
 Both take a :class:`~paper_2403_17518_amd.ops.FwiContext` (or use the
-default context of the tensor's device).
+default context of the tensor's device). Gradients are with respect to v
+itself: a grid that asks for the relative-perturbation operator is run with
+the velocity parametrisation here.
 """
 from __future__ import annotations
+
+from dataclasses import replace
 
 import torch
 
@@ -21,6 +25,10 @@ from . import ops
 
 def _ctx(fctx, v):
     return fctx if fctx is not None else ops.default_context(v.device.index or 0)
+
+
+def _velocity(grid):
+    return replace(grid, relative=False) if getattr(grid, "relative", False) else grid
 
 
 class _ForwardModel(torch.autograd.Function):
@@ -62,10 +70,10 @@ class _Misfit(torch.autograd.Function):
 
 def forward_model(v: torch.Tensor, grid, acq, fctx: ops.FwiContext | None = None) -> torch.Tensor:
     """d = F(v), differentiable in v (backward = J^T via the adjoint sweep)."""
-    return _ForwardModel.apply(v, grid, acq, _ctx(fctx, v))
+    return _ForwardModel.apply(v, _velocity(grid), acq, _ctx(fctx, v))
 
 
 def misfit(v: torch.Tensor, d_obs: torch.Tensor, grid, acq,
            fctx: ops.FwiContext | None = None) -> torch.Tensor:
     """phi = 1/2 ||F(v) - d_obs||^2 as a float64 scalar, differentiable in v."""
-    return _Misfit.apply(v, d_obs, grid, acq, _ctx(fctx, v))
+    return _Misfit.apply(v, d_obs, _velocity(grid), acq, _ctx(fctx, v))

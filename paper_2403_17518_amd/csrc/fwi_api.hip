@@ -41,6 +41,7 @@ struct Plan {
     int nz = 0, nx = 0, nb = 0, NZ = 0, nt_max = 0, S = 0;
     int top = 0;                  // padded rows above physical row 0
     bool free_surface = false;    // pressure-free top surface (no top sponge)
+    bool relative = false;        // Born perturbations and images per dV / V
     float h = 0, dt = 0, v_ref = 0, R = 0;
     int ckpt_every = 0;
     // shots in slot order (record length decreasing)
@@ -245,6 +246,7 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
                        kCflLimit);
     if (g->ckpt_every < 0) return set_err(c, FWI_EINVAL, "ckpt_every must be >= 0");
     if (g->free_surface != 0 && g->free_surface != 1) return set_err(c, FWI_EINVAL, "free_surface must be 0 or 1");
+    if (g->relative != 0 && g->relative != 1) return set_err(c, FWI_EINVAL, "relative must be 0 or 1");
     const int top = g->free_surface ? 0 : g->nb;
     const int64_t NZ64 = int64_t(g->nz) + int64_t(g->nb) + top;
     if (NZ64 > (1 << 20) || int64_t(g->nx) + 2 * g->nb > (1 << 20))
@@ -305,6 +307,7 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
     p.NZ = int(NZ64);
     p.top = top;
     p.free_surface = g->free_surface != 0;
+    p.relative = g->relative != 0;
     p.nt_max = g->nt_max;
     p.h = g->h;
     p.dt = g->dt;
@@ -595,6 +598,7 @@ StepArgs base_args(fwi_ctx *c, const float *v, int cls)
     a.nb = p.nb;
     a.top = p.top;
     a.fs = p.free_surface ? 1 : 0;
+    a.rel = p.relative ? 1 : 0;
     a.NZ = p.NZ;
     const double ih2 = 1.0 / (double(p.h) * p.h);
     a.w1 = float(kC8[1] * ih2);
@@ -1049,6 +1053,7 @@ int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
     fin.nx = p.nx;
     fin.nb = p.nb;
     fin.top = p.top;
+    fin.rel = p.relative ? 1 : 0;
     fin.NZ = p.NZ;
     fin.dt2 = float(double(p.dt) * p.dt);
     fin.img = img;

@@ -309,8 +309,12 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
                 a = sponge_a(sh);
             }
             Dv[k] = cc * lap;
-            // scattered field: the linearised velocity term (2 dV / V) D^n
-            if (FL & F_SCAT) Dv[k] = __builtin_fmaf(2.0f * c.dv[k] / c.v[k], c.d[k], Dv[k]);
+            // scattered field: the linearised velocity term (2 dV / V) D^n;
+            // a relative perturbation dm = dV / V enters as 2 dm D^n
+            if (FL & F_SCAT) {
+                const float rho = A.rel ? 2.0f * c.dv[k] : 2.0f * c.dv[k] / c.v[k];
+                Dv[k] = __builtin_fmaf(rho, c.d[k], Dv[k]);
+            }
             out[k] = leapfrog(q[4][k], c.pv[k], Dv[k], a, sh);
             if (A.fs && z == 0) out[k] = 0.0f;   // the pressure-free surface
         }
@@ -745,7 +749,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
             const float lapd = lap8(r, xd, k, A.w1, A.w2, A.w3, A.w4);
             lap = add_source<CW>(lap, wsrc, z, S.src_i, sw0, sw1, k);
             const float c = cv[k] * cv[k] * A.dt2;
-            const float cr = 2.0f * cv[k] * cdv[k] * A.dt2;
+            // (2 dV / V) V^2 dt^2, or 2 dm V^2 dt^2 for a relative dm
+            const float cr = A.rel ? 2.0f * cdv[k] * c : 2.0f * cv[k] * cdv[k] * A.dt2;
             float a = ax[k], sh = shx[k];
             if (ddz > 0) {
                 sh = A.hs * (dz2 + dx2[k]);
@@ -1008,8 +1013,9 @@ __global__ __launch_bounds__(256) void k_finalize(const FinalArgs A)
         if (jl < 0 || jl >= S.wnx) continue;
         acc += A.G[S.g_off + int64_t(i + A.top) * S.P + jl + A.nb];
     }
+    // image of dV: (2 / (V^3 dt^2)) sum G; of the relative dV / V: V times that
     const float v = A.v[p];
-    A.img[p] = acc * (2.0f / (v * v * v * A.dt2));
+    A.img[p] = acc * (A.rel ? 2.0f / (v * v * A.dt2) : 2.0f / (v * v * v * A.dt2));
 }
 
 inline int blocks_for(int nwaves) { return (nwaves + kWavesPerBlock - 1) / kWavesPerBlock; }

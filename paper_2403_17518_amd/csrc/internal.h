@@ -66,6 +66,7 @@ enum StepFlags : int {
     F_EMIT = 8,    // store D^n = V^2 dt^2 (L8 u^n + s^n)
     F_IMAGE = 16,  // accumulate G += out * D^n
     F_SCAT = 32,   // scattered field: source (2 dV / V) D^n from the stored background history
+                   // (2 dm D^n for a relative perturbation dm)
 };
 
 struct StepArgs {
@@ -79,6 +80,7 @@ struct StepArgs {
     int32_t nwaves, nz, nx, nb, NZ;
     int32_t top;               // padded rows above physical row 0 (nb, or 0 under a free surface)
     int32_t fs;                // free surface: row 0 held at zero, odd mirror above it
+    int32_t rel;               // Born perturbation given as dV / V (1) or dV (0)
     int32_t cw;                // columns per lane of the wave table (1 or 2)
     int32_t pd;                // one-level kernel: rows prefetched ahead (1 or 2)
     float w1, w2, w3, w4;      // c_k / h^2 (the centre weight is -4 times their sum)
@@ -139,6 +141,7 @@ struct FinalArgs {
     const float *v;
     int32_t nz, nx, nb, NZ;
     int32_t top;        // padded rows above physical row 0
+    int32_t rel;        // 1: image of the relative perturbation (times v)
     float dt2;
     float *img;
 };
