@@ -132,6 +132,7 @@ __device__ float raw_ld_f32(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm
 __device__ f32x2 raw_ld_v2f32(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.v2f32");
 __device__ f32x4 raw_ld_v4f32(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.v4f32");
 __device__ void raw_st_f32(float v, i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.store.f32");
+__device__ void raw_st_v2f32(f32x2 v, i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.store.v2f32");
 
 using Rsrc = i32x4;
 constexpr int kRsrcWord3 = 0x00020000;   // 32-bit data format, no swizzle
@@ -173,6 +174,44 @@ __device__ __forceinline__ float4 bld4(Rsrc r, unsigned lane_off, int row_off)
 __device__ __forceinline__ void bst1(Rsrc r, unsigned lane_off, int row_off, float v)
 {
     raw_st_f32(v, r, int(lane_off), row_off, 0);
+}
+
+// The D^n history is written once per step and read once, much later, by
+// another sweep: its loads and stores carry the non-temporal cache policy
+// (bit 1 of the cache-policy operand) so that the stream does not displace
+// the fields and the image accumulator, which are re-read every step.
+constexpr int kStream = 2;
+
+template <int CW>
+__device__ __forceinline__ void bld_stream(Rsrc r, unsigned lane_off, int row_off, float (&o)[CW])
+{
+    if constexpr (CW == 1) {
+        o[0] = raw_ld_f32(r, int(lane_off), row_off, kStream);
+    } else {
+        const f32x2 t = raw_ld_v2f32(r, int(lane_off), row_off, kStream);
+        o[0] = t.x;
+        o[1] = t.y;
+    }
+}
+
+// A lane's CW values of one row of the history; ok[k] marks the columns it
+// owns (ok[1] implies ok[0]). Two columns go out as one 8-byte store: two
+// 4-byte non-temporal stores from every lane would leave each cache line
+// written in halves.
+template <int CW>
+__device__ __forceinline__ void bst_stream(Rsrc r, unsigned lane_off, int row_off, const float (&v)[CW],
+                                           const bool (&ok)[CW])
+{
+    if constexpr (CW == 2) {
+        if (ok[1]) {
+            f32x2 t;
+            t.x = v[0];
+            t.y = v[1];
+            raw_st_v2f32(t, r, int(lane_off), row_off, kStream);
+            return;
+        }
+    }
+    if (ok[0]) raw_st_f32(v[0], r, int(lane_off), row_off, kStream);
 }
 
 // One time level of every active shot. Each lane owns CW adjacent columns of
@@ -250,11 +289,11 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
 #pragma unroll
         for (int k = 0; k < CW; ++k) pre.v[k] = bld1(rv, jm[k], vo);
         if (FL & F_IMAGE) {
-            bld<CW>(rd, jl, 4 * z * P, pre.d);
+            bld_stream<CW>(rd, jl, 4 * z * P, pre.d);
             bld<CW>(rg, jl, 4 * z * P, pre.g);
         }
         if (FL & F_SCAT) {
-            bld<CW>(rd, jl, 4 * z * P, pre.d);
+            bld_stream<CW>(rd, jl, 4 * z * P, pre.d);
 #pragma unroll
             for (int k = 0; k < CW; ++k) pre.dv[k] = bld1(rdv, jm[k], vo);
         }
@@ -319,11 +358,11 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
             if (A.fs && z == 0) out[k] = 0.0f;   // the pressure-free surface
         }
         const int ro = 4 * (z + kRowsAbove) * P, go = 4 * z * P;
+        if (FL & F_EMIT) bst_stream<CW>(rd, js, go, Dv, valid);
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             if (valid[k]) {
                 bst1(rprev, js + 4 * k, ro, out[k]);
-                if (FL & F_EMIT) bst1(rd, js + 4 * k, go, Dv[k]);
                 if (FL & F_IMAGE) bst1(rg, js + 4 * k, go, __builtin_fmaf(out[k], c.d[k], c.g[k]));
                 if (FL & F_SAMPLE)
                     if (qi[k] >= 0) A.samp[qi[k]] = out[k];
@@ -447,8 +486,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
             // the imaging terms of both levels are added at level 2 (row t-4)
             const int r2 = t - kHalo;
             if (r2 >= W.z0 && r2 < W.z1) {
-                bld<CW>(rd1, jc4, 4 * r2 * P, nd1);
-                bld<CW>(rd2, jc4, 4 * r2 * P, nd2);
+                bld_stream<CW>(rd1, jc4, 4 * r2 * P, nd1);
+                bld_stream<CW>(rd2, jc4, 4 * r2 * P, nd2);
                 bld<CW>(rg, jc4, 4 * r2 * P, ng);
             }
         }
@@ -532,11 +571,11 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         const bool own_row1 = t >= W.z0 && t < W.z1;
         if (own_row1) {
             const int o = 4 * (t + kRowsAbove) * P;
+            if (FL & F_EMIT) bst_stream<CW>(rd1, js4, 4 * t * P, D1, own);
 #pragma unroll
             for (int k = 0; k < CW; ++k) {
                 if (own[k]) {
                     bst1(ro1, js4 + 4 * k, o, v1[k]);
-                    if (FL & F_EMIT) bst1(rd1, js4 + 4 * k, 4 * t * P, D1[k]);
                     if (FL & F_SAMPLE)
                         if (qi1[k] >= 0) A.samp[qi1[k]] = v1[k];
                 }
@@ -569,6 +608,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
             const int ddz2 = max(max(A.top - r2, r2 - (NZ - 1 - nb)), 0);
             const float dz2 = float(ddz2 * ddz2);
             const int o = 4 * (r2 + kRowsAbove) * P;
+            float D2[CW];
 #pragma unroll
             for (int k = 0; k < CW; ++k) {
                 float lap = lap8(qb, yr, k, A.w1, A.w2, A.w3, A.w4);
@@ -581,12 +621,10 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                     sh = A.hs * (dz2 + dx2[k]);
                     a = sponge_a(sh);
                 }
-                const float D2 = c * lap;
-                const float v2 = leapfrog(qb[4][k], qa[0][k], D2, a, sh);
+                D2[k] = c * lap;
+                const float v2 = leapfrog(qb[4][k], qa[0][k], D2[k], a, sh);
                 if (own[k]) {
                     bst1(ro2, js4 + 4 * k, o, v2);
-                    if (FL & F_EMIT)
-                        if (lvl2_ok) bst1(rd2, js4 + 4 * k, 4 * r2 * P, D2);
                     if (FL & F_SAMPLE)
                         if (lvl2_ok && qi2[k] >= 0) A.samp2[qi2[k]] = v2;
                     // G after both levels: the fused multiply-adds of two one-level
@@ -597,6 +635,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                     }
                 }
             }
+            if (FL & F_EMIT)
+                if (lvl2_ok) bst_stream<CW>(rd2, js4, 4 * r2 * P, D2, own);
         }
 #pragma unroll
         for (int r = 0; r < 8; ++r)
@@ -762,12 +802,12 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
             if (A.fs && z == 0) ou[k] = od[k] = 0.0f;   // the pressure-free surface
         }
         const int o = 4 * (z + kRowsAbove) * P;
+        if (EMIT) bst_stream<CW>(rd, js, 4 * z * P, Dv, valid);
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             if (valid[k]) {
                 bst1(rpv, js + 4 * k, o, ou[k]);
                 bst1(rpd, js + 4 * k, o, od[k]);
-                if (EMIT) bst1(rd, js + 4 * k, 4 * z * P, Dv[k]);
                 if (qi[k] >= 0) A.samp[qi[k]] = od[k];
                 if (A.fs && z >= 1 && z <= kHalo) {   // odd mirror above the free surface
                     bst1(rpv, js + 4 * k, 4 * (kRowsAbove - z) * P, -ou[k]);

@@ -263,6 +263,7 @@ float emu_raw_ld_f32(i32x4 r, int voff, int soff, int aux) __asm("emu_raw_ld_f32
 f32x2 emu_raw_ld_v2f32(i32x4 r, int voff, int soff, int aux) __asm("emu_raw_ld_v2f32");
 f32x4 emu_raw_ld_v4f32(i32x4 r, int voff, int soff, int aux) __asm("emu_raw_ld_v4f32");
 void emu_raw_st_f32(float v, i32x4 r, int voff, int soff, int aux) __asm("emu_raw_st_f32");
+void emu_raw_st_v2f32(f32x2 v, i32x4 r, int voff, int soff, int aux) __asm("emu_raw_st_v2f32");
 
 float emu_raw_ld_f32(i32x4 r, int voff, int soff, int aux)
 {
@@ -285,6 +286,10 @@ f32x4 emu_raw_ld_v4f32(i32x4 r, int voff, int soff, int aux)
 void emu_raw_st_f32(float v, i32x4 r, int voff, int soff, int aux)
 {
     std::memcpy(emu_buf_addr(r, voff, soff, 4), &v, 4);
+}
+void emu_raw_st_v2f32(f32x2 v, i32x4 r, int voff, int soff, int aux)
+{
+    std::memcpy(emu_buf_addr(r, voff, soff, 8), &v, 8);
 }
 
 // ---- host API -----------------------------------------------------------------
