@@ -144,6 +144,10 @@ typedef struct {
     int32_t tile_prefetch[4]; /* rows prefetched ahead (one-level kernels) */
     int64_t graph_launches;   /* time loops replayed from a captured HIP graph */
     int64_t graph_captures;   /* time loops captured (first run of a loop) */
+    int64_t recomputed_steps; /* forward time steps recomputed by the adjoint
+                                 sweeps from snapshots */
+    int32_t ckpt_slots;       /* snapshots of (u^{n-1}, u^n) the adjoint
+                                 sweeps held */
 } fwi_stats;
 
 /* Create a context on HIP device `device`, enqueueing on `hip_stream`
@@ -157,6 +161,27 @@ int fwi_ctx_set_stream(fwi_ctx *ctx, void *hip_stream);
  * otherwise checkpoint; they never plan beyond the memory free at the call
  * minus a 4 GiB margin. */
 int fwi_ctx_set_mem_budget(fwi_ctx *ctx, int64_t bytes);
+/* Checkpointing of the adjoint sweeps. When the history does not fit, the
+ * record is cut into segments of k steps (fwi_grid.ckpt_every, or chosen
+ * from the budget) whose D^n history is recomputed, last segment first, from
+ * snapshots of (u^{n-1}, u^n) placed by the binomial rule of Griewank's
+ * revolve (Griewank & Walther, ACM TOMS 26, 2000): with nseg - 2 snapshots
+ * every segment but the last is recomputed once; with fewer, segments are
+ * recomputed more often, the fewest times any placement allows. The budget
+ * decides the snapshot count (it takes the uniform schedule whenever that
+ * fits, else the segment length and snapshot count with the fewest
+ * recomputed steps). slots >= 0 caps the count at `slots` (tests, memory
+ * held back for other work); -1 (default) removes the cap. Results are the
+ * same bits whatever the schedule. */
+int fwi_ctx_set_ckpt_slots(fwi_ctx *ctx, int32_t slots);
+/* Host only, no device or context needed: replays the schedule the adjoint
+ * sweeps follow for nseg segments and `slots` snapshot slots, checking that
+ * every recomputation starts from a snapshot of the right segment, that the
+ * adjoint takes each segment's freshly recomputed history once, last
+ * segment first, and nothing else. *recomputed (nullable) receives the
+ * number of segments recomputed. Returns FWI_OK; FWI_EINVAL if nseg < 1 or
+ * slots < 0; FWI_ESTATE if a step is out of order (a library bug). */
+int fwi_checkpoint_schedule(int32_t nseg, int32_t slots, int64_t *recomputed);
 /* 1 = time the propagation kernels with HIP events recorded around every
  * run of consecutive launches of one kernel class (forward, adjoint, Born),
  * so the reported per-launch time includes the (small) gaps between

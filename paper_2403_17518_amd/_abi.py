@@ -50,7 +50,8 @@ class fwi_stats(C.Structure):
                 ("bytes_born", C.c_double),
                 ("tile_cw", C.c_int32 * 4), ("tile_rows", C.c_int32 * 4),
                 ("tile_levels", C.c_int32 * 4), ("tile_prefetch", C.c_int32 * 4),
-                ("graph_launches", C.c_int64), ("graph_captures", C.c_int64)]
+                ("graph_launches", C.c_int64), ("graph_captures", C.c_int64),
+                ("recomputed_steps", C.c_int64), ("ckpt_slots", C.c_int32)]
 
     def as_dict(self) -> dict:
         out = {}
@@ -77,6 +78,8 @@ SIGNATURES = {
     "fwi_ctx_destroy": (None, [_P]),
     "fwi_ctx_set_stream": (C.c_int, [_P, _P]),
     "fwi_ctx_set_mem_budget": (C.c_int, [_P, C.c_int64]),
+    "fwi_ctx_set_ckpt_slots": (C.c_int, [_P, C.c_int32]),
+    "fwi_checkpoint_schedule": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int64)]),
     "fwi_ctx_set_profiling": (C.c_int, [_P, C.c_int]),
     "fwi_ctx_get_stats": (C.c_int, [_P, C.POINTER(fwi_stats)]),
     "fwi_ctx_set_tiling": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),

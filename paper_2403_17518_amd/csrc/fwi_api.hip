@@ -90,6 +90,16 @@ struct Tiling {
     std::vector<int32_t> rmap;
     std::vector<int> prefix;  // waves of slots [0, k)
     DevBuf d_waves, d_rrows, d_rmap;
+    // two levels per launch: the one-level table over the same strip width,
+    // for the single step a range of odd length ends with (the two-level
+    // table's strips overlap by the 4-column halos and its receiver maps
+    // start 4 columns left of a strip, which the one-level kernel does not)
+    std::vector<WaveDesc> waves1;
+    std::vector<RecRow> rrows1;
+    std::vector<int32_t> rmap1;
+    std::vector<int> prefix1;
+    DevBuf d_waves1, d_rrows1, d_rmap1;
+    void release_all();
 };
 
 // tiling classes: forward, adjoint, joint Born, scattered field from a stored
@@ -127,6 +137,7 @@ struct fwi_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int64_t budget = 0;
+    int ckpt_slots = -1;          // forced snapshot slots of the adjoint sweeps (-1: from the budget)
     bool profiling = false;
     fwi_stats stats{};
     Plan plan;
@@ -205,6 +216,15 @@ void release(DevBuf &b)
     b.p = nullptr;
     b.bytes = 0;
 }
+
+}  // namespace
+
+void Tiling::release_all()
+{
+    for (DevBuf *b : {&d_waves, &d_rrows, &d_rmap, &d_waves1, &d_rrows1, &d_rmap1}) release(*b);
+}
+
+namespace {
 
 void clear_graphs(fwi_ctx *c)
 {
@@ -529,6 +549,18 @@ void build_tiling(const Plan &p, int cw, int rows_target, int tb, int pd, Tiling
         }
         t.prefix[k + 1] = int(t.waves.size());
     }
+    t.waves1.clear();
+    t.rrows1.clear();
+    t.rmap1.clear();
+    t.prefix1.clear();
+    if (tb == 2) {
+        Tiling one;
+        build_tiling(p, cw, rows_target, 1, 1, one);
+        t.waves1 = std::move(one.waves);
+        t.rrows1 = std::move(one.rrows);
+        t.rmap1 = std::move(one.rmap);
+        t.prefix1 = std::move(one.prefix);
+    }
 }
 
 int upload_tiling(fwi_ctx *c, Tiling &t)
@@ -536,6 +568,9 @@ int upload_tiling(fwi_ctx *c, Tiling &t)
     int rc;
     if ((rc = upload(c, t.d_waves, t.waves)) || (rc = upload(c, t.d_rrows, t.rrows)) ||
         (rc = upload(c, t.d_rmap, t.rmap)))
+        return rc;
+    if (t.tb == 2 && ((rc = upload(c, t.d_waves1, t.waves1)) || (rc = upload(c, t.d_rrows1, t.rrows1)) ||
+                      (rc = upload(c, t.d_rmap1, t.rmap1))))
         return rc;
     // pageable sources: make sure the copies have consumed them
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -809,6 +844,14 @@ int step_launch(fwi_ctx *c, StepArgs a, int cls, int flags, int levels, int acti
     a.nwaves = t.prefix[p.active_slots(active_n)];
     a.cur = f.cur;
     a.prev = f.prev;
+    if (levels == 1 && t.tb == 2) {
+        // the single step of a two-level tiling runs on its one-level table
+        a.waves = static_cast<const WaveDesc *>(t.d_waves1.p);
+        a.rrows = static_cast<const RecRow *>(t.d_rrows1.p);
+        a.rmap = static_cast<const int32_t *>(t.d_rmap1.p);
+        a.nwaves = t.prefix1[p.active_slots(active_n)];
+        a.pd = 1;
+    }
     if (levels == 2) {
         a.out1 = f.s0;
         a.out2 = f.s1;
@@ -899,19 +942,201 @@ int finish_stats(fwi_ctx *c)
     return ev_collect(c);
 }
 
-// Choose the checkpoint interval k: the last segment's D^n history is
-// stored during the forward sweep; every earlier segment is recomputed from
-// a checkpoint of (u^{n-1}, u^n). Memory = k slots + (segments-1) checkpoints.
-int choose_segments(fwi_ctx *c, int *k_out, int *nseg_out)
+// Checkpointing of the adjoint sweeps. The time axis is cut into segments
+// of k steps. Going backward, segment by segment from the last, the adjoint
+// needs that segment's D^n history, recomputed into a k-slot buffer from the
+// state (u^{lo-1}, u^lo) at the segment's start. Those states come from S
+// snapshot slots placed by the binomial rule of Griewank's revolve
+// (Griewank & Walther, ACM TOMS 26, 2000): with s snapshots (the zero state
+// at segment 0 counts as one) and at most r recomputations of any segment,
+// beta(s, r) = C(s + r, s) segments can be reversed; for l segments, with r
+// the least such that beta(s, r) >= l, placing the next snapshot after
+// max(beta(s, r - 2), l - beta(s - 1, r)) segments reverses them with the
+// fewest recomputed segments, r l - C(s + r, s + 1) in all. The forward
+// sweep that computes the data passes every segment once: it stores the
+// snapshots the first splits ask for and keeps the last segment's history,
+// so with S >= nseg - 2 every segment but the last is recomputed exactly
+// once (uniform checkpointing), and with fewer snapshots the sweep still
+// runs, recomputing more.
+
+// C(n, k), saturating at 2^62
+int64_t binom_sat(int n, int k)
+{
+    if (k < 0 || n < 0 || k > n) return 0;
+    k = std::min(k, n - k);
+    const __int128 cap = __int128(1) << 62;
+    __int128 r = 1;
+    for (int i = 1; i <= k; ++i) {
+        r = r * (n - k + i) / i;
+        if (r >= cap) return int64_t(cap);
+    }
+    return int64_t(r);
+}
+
+// segments left of the next snapshot when l >= 2 segments are reversed with
+// s >= 2 snapshots
+int revolve_left(int l, int s)
+{
+    int r = 0;
+    while (binom_sat(s + r, s) < l) ++r;
+    const int64_t a = r >= 2 ? binom_sat(s + r - 2, s) : 1;
+    const int64_t m = std::max<int64_t>(a, int64_t(l) - binom_sat(s + r - 1, s - 1));
+    return int(std::min<int64_t>(std::max<int64_t>(m, 1), l - 1));
+}
+
+// segments recomputed by the backward sweep over nseg segments with `slots`
+// snapshot slots (the closed form above, s = slots + 1)
+int64_t revolve_recompute(int nseg, int slots)
+{
+    const int s = slots + 1;
+    int r = 0;
+    while (binom_sat(s + r, s) < nseg) ++r;
+    return int64_t(r) * nseg - binom_sat(s + r, s + 1);
+}
+
+std::vector<int> revolve_free(int slots)
+{
+    std::vector<int> f;
+    for (int q = slots - 1; q >= 0; --q) f.push_back(q);   // slot 0 is used first
+    return f;
+}
+
+// snapshots the forward sweep stores: spine[sgi] = slot holding the state at
+// the start of segment sgi, -1 for none
+std::vector<int> revolve_spine(int nseg, int slots)
+{
+    std::vector<int> spine(size_t(std::max(nseg, 0)), -1), free = revolve_free(slots);
+    int lo = 0, s = 1 + slots;
+    while (nseg - lo > 1 && s >= 2) {
+        const int m = lo + revolve_left(nseg - lo, s);
+        spine[size_t(m)] = free.back();
+        free.pop_back();
+        lo = m;
+        --s;
+    }
+    return spine;
+}
+
+// Reverse segments [lo, hi), the state at segment lo being in snapshot
+// `root` (-1: the zero state), with the free slots `free` (taken from the
+// back). On the first-split path (hi == nseg) the forward sweep has stored
+// the snapshots and the last segment's history. Ops provides restore(slot,
+// seg), advance(seg0, seg1), store(slot, seg), emit(seg) (recompute the
+// segment storing its history) and adjoint(seg).
+template <class Ops>
+int revolve(Ops &op, int nseg, int lo, int hi, int root, std::vector<int> &free)
+{
+    int rc;
+    const bool spine = hi == nseg;
+    const int l = hi - lo;
+    if (l == 1) {
+        if (!spine && ((rc = op.restore(root, lo)) || (rc = op.emit(lo)))) return rc;
+        return op.adjoint(lo);
+    }
+    const int s = 1 + int(free.size());
+    if (s == 1) {
+        for (int j = hi - 1; j >= lo; --j) {
+            if (!(spine && j == nseg - 1))
+                if ((rc = op.restore(root, lo)) || (rc = op.advance(lo, j)) || (rc = op.emit(j))) return rc;
+            if ((rc = op.adjoint(j))) return rc;
+        }
+        return FWI_OK;
+    }
+    const int m = lo + revolve_left(l, s);
+    const int slot = free.back();
+    free.pop_back();
+    if (!spine)
+        if ((rc = op.restore(root, lo)) || (rc = op.advance(lo, m)) || (rc = op.store(slot, m))) return rc;
+    if ((rc = revolve(op, nseg, m, hi, slot, free))) return rc;
+    free.push_back(slot);
+    return revolve(op, nseg, lo, m, root, free);
+}
+
+// Replays a schedule on the host, checking every action against the state
+// it tracks; counts the recomputed segments.
+struct RevolveCheck {
+    int pos = -1;                 // segment whose start the current state is at (-1: none)
+    int hist = -1;                // segment whose history is in the buffer
+    int next_adj = 0;             // segment the adjoint must take next
+    std::vector<int> held;        // slot -> segment start it holds (-1: none)
+    int64_t forwards = 0;
+    int restore(int slot, int seg)
+    {
+        const int at = slot < 0 ? 0 : held[size_t(slot)];
+        if (at != seg) return FWI_ESTATE;
+        pos = seg;
+        return FWI_OK;
+    }
+    int advance(int a, int b)
+    {
+        if (pos != a || b < a) return FWI_ESTATE;
+        forwards += b - a;
+        pos = b;
+        return FWI_OK;
+    }
+    int store(int slot, int seg)
+    {
+        if (pos != seg) return FWI_ESTATE;
+        held[size_t(slot)] = seg;
+        return FWI_OK;
+    }
+    int emit(int seg)
+    {
+        if (pos != seg) return FWI_ESTATE;
+        forwards += 1;
+        hist = seg;
+        pos = seg + 1;
+        return FWI_OK;
+    }
+    int adjoint(int seg)
+    {
+        if (seg != next_adj || hist != seg) return FWI_ESTATE;
+        --next_adj;
+        return FWI_OK;
+    }
+};
+
+int revolve_check(int nseg, int slots, int64_t *forwards)
+{
+    if (nseg < 1 || slots < 0) return FWI_EINVAL;
+    RevolveCheck ck;
+    ck.held.assign(size_t(slots), -1);
+    const std::vector<int> spine = revolve_spine(nseg, slots);
+    for (int q = 0; q < nseg; ++q)
+        if (spine[size_t(q)] >= 0) ck.held[size_t(spine[size_t(q)])] = q;
+    ck.hist = nseg - 1;           // the forward sweep kept the last segment's history
+    ck.next_adj = nseg - 1;
+    std::vector<int> free = revolve_free(slots);
+    int rc = revolve(ck, nseg, 0, nseg, -1, free);
+    if (rc == FWI_OK && ck.next_adj != -1) rc = FWI_ESTATE;
+    if (forwards) *forwards = ck.forwards;
+    return rc;
+}
+
+struct Sweep {
+    int k = 0, nseg = 0, slots = 0;
+    std::vector<int> spine;       // snapshot slot stored at each segment start (-1: none)
+    float *F[4], *A[4], *Dh, *CK, *G;
+};
+
+// Choose the segment length k and the snapshot slots. Memory = k history
+// slots + S snapshots of (u^{n-1}, u^n). Uniform checkpointing (S = nseg - 2,
+// no segment recomputed twice) at the k that fits the budget; if none does,
+// the (k, S) within the budget with the fewest recomputed steps.
+int choose_segments(fwi_ctx *c, Sweep &w)
 {
     const Plan &p = c->plan;
     const int nt = p.nt_max;
     const double slot = double(p.img_floats) * 4.0;
     const double ck = 2.0 * double(p.field_floats) * 4.0;
-    auto mem = [&](int k) { return double(k) * slot + double((nt + k - 1) / k - 1) * ck; };
-    int k;
-    if (p.ckpt_every > 0) k = std::min(p.ckpt_every, nt);
-    else {
+    auto nseg_of = [&](int k) { return (nt + k - 1) / k; };
+    auto uniform = [&](int k) { return std::max(0, nseg_of(k) - 2); };
+    auto mem = [&](int k, int S) { return double(k) * slot + double(S) * ck; };
+    int k, S;
+    if (p.ckpt_every > 0) {
+        k = std::min(p.ckpt_every, std::max(nt, 1));
+        S = uniform(k);
+    } else {
         // never plan beyond what is free now (plus what this context already
         // holds for the same purpose), keeping a margin for the caller
         size_t fr = 0, tot = 0;
@@ -920,39 +1145,55 @@ int choose_segments(fwi_ctx *c, int *k_out, int *nseg_out)
             const double avail = double(fr) + double(c->dhist.bytes) + double(c->ckpt.bytes) - double(kFreeMargin);
             budget = std::min(budget, std::max(avail, 0.0));
         }
-        k = nt;
-        if (mem(k) > budget) {
+        k = std::max(nt, 1);
+        S = uniform(k);
+        if (mem(k, S) > budget) {
             k = int(std::max(1.0, std::min(double(nt), std::floor(budget / std::max(slot, 1.0)))));
-            while (k > 1 && mem(k) > budget) k = std::max(1, k - std::max(1, k / 32));
-            if (mem(k) > budget)
-                return set_err(c, FWI_ENOMEM, "memory budget %.3g B too small for the adjoint sweep", budget);
+            while (k > 1 && mem(k, uniform(k)) > budget) k = std::max(1, k - std::max(1, k / 32));
+            S = uniform(k);
+            if (mem(k, S) > budget) {
+                // binomial: the fewest recomputed steps over all k
+                double best = -1.0;
+                for (int kk = 1; kk <= nt; ++kk) {
+                    const double room = budget - double(kk) * slot;
+                    if (room < 0.0) break;
+                    const int SS = int(std::min<double>(uniform(kk), std::floor(room / std::max(ck, 1.0))));
+                    const double cost = double(kk) * double(revolve_recompute(nseg_of(kk), SS));
+                    if (best < 0.0 || cost < best) {
+                        best = cost;
+                        k = kk;
+                        S = SS;
+                    }
+                }
+                if (best < 0.0)
+                    return set_err(c, FWI_ENOMEM, "memory budget %.3g B too small for the adjoint sweep", budget);
+            }
         }
     }
-    *k_out = k;
-    *nseg_out = (nt + k - 1) / k;
+    if (c->ckpt_slots >= 0) S = std::min(S, c->ckpt_slots);
+    w.k = k;
+    w.nseg = nseg_of(k);
+    w.slots = S;
+    w.spine = revolve_spine(w.nseg, S);
+    c->stats.ckpt_every = w.nseg > 1 ? k : 0;
+    c->stats.n_segments = w.nseg;
+    c->stats.ckpt_slots = S;
     return FWI_OK;
 }
 
-struct Sweep {
-    int k = 0, nseg = 0;
-    float *F[4], *A[4], *Dh, *CK, *G;
-};
-
-// Forward sweep for an adjoint: checkpoints of (u^{n-1}, u^n) at the start
-// of every segment but the last, D^n stored for the last segment, receiver
+// Forward sweep for an adjoint: the snapshots of (u^{n-1}, u^n) the
+// checkpointing schedule asks for, D^n stored for the last segment, receiver
 // samples (time-major) if `sample`.
 int forward_for_adjoint(fwi_ctx *c, const float *v, bool sample, Sweep &w)
 {
     const Plan &p = c->plan;
     int rc;
-    if ((rc = choose_segments(c, &w.k, &w.nseg))) return rc;
+    if ((rc = choose_segments(c, w))) return rc;
     const int k = w.k, nseg = w.nseg;
-    c->stats.ckpt_every = nseg > 1 ? k : 0;
-    c->stats.n_segments = nseg;
     const int64_t ff = p.field_floats, gf = p.img_floats;
     if ((rc = ensure(c, c->fields, size_t(8 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
         (rc = ensure(c, c->dhist, size_t(k) * gf * 4)) ||
-        (rc = ensure(c, c->ckpt, size_t(std::max(0, nseg - 1)) * 2 * ff * 4)) ||
+        (rc = ensure(c, c->ckpt, size_t(w.slots) * 2 * ff * 4)) ||
         (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)))
         return rc;
     float *F = static_cast<float *>(c->fields.p);
@@ -972,8 +1213,8 @@ int forward_for_adjoint(fwi_ctx *c, const float *v, bool sample, Sweep &w)
     for (int sgi = 0; sgi < nseg; ++sgi) {
         const int lo = sgi * k, hi = std::min(p.nt_max, lo + k);
         const bool last = sgi == nseg - 1;
-        if (!last) {
-            float *ckp = w.CK + size_t(sgi) * 2 * ff;
+        if (w.spine[size_t(sgi)] >= 0) {
+            float *ckp = w.CK + size_t(w.spine[size_t(sgi)]) * 2 * ff;
             HIPCHK(c, hipMemcpyAsync(ckp, f.prev, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
             HIPCHK(c, hipMemcpyAsync(ckp + ff, f.cur, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
         }
@@ -982,37 +1223,66 @@ int forward_for_adjoint(fwi_ctx *c, const float *v, bool sample, Sweep &w)
     return ev_end(c);
 }
 
-// Backward sweep: for every segment, last to first, recompute D^n from its
-// checkpoint (the last segment's is already stored), then run the adjoint
-// steps with the fused imaging condition; finally fold and scale the image.
-// The adjoint sources (time-major [nt_max][Q]) are in the samples buffer.
-int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
-{
-    const Plan &p = c->plan;
-    const int64_t ff = p.field_floats, gf = p.img_floats;
-    const int k = w.k, nseg = w.nseg;
-    hipStream_t st = c->stream;
-    float *inj = static_cast<float *>(c->samples.p);
-    int rc;
-    if ((rc = other(c, launch_fill(w.A[0], 4 * ff, 0.f, st), "fill"))) return rc;
-    if ((rc = other(c, launch_fill(w.G, gf, 0.f, st), "fill"))) return rc;
-    StepArgs af = base_args(c, v, K_FWD);
-    StepArgs a = base_args(c, v, K_ADJ);
-    a.G = w.G;
-    const bool two = c->tile[K_ADJ].tb == 2;
-    // lambda^{n+2} (prev) and lambda^{n+1} (cur), both zero at the start
-    Fields fa{w.A[0], w.A[1], w.A[2], w.A[3]};
-    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
-        const int lo = sgi * k, hi = std::min(p.nt_max, lo + k);
-        if (sgi != nseg - 1) {
-            const float *ckp = w.CK + size_t(sgi) * 2 * ff;
+// The actions of the checkpointing schedule on the GPU: background
+// restores, advances and history recomputation on the forward tiling, the
+// adjoint with the fused imaging condition on the adjoint tiling.
+struct SweepOps {
+    fwi_ctx *c;
+    Sweep &w;
+    StepArgs af, a;
+    float *inj;
+    Fields f, fa;
+    int seg_lo(int q) const { return q * w.k; }
+    int seg_hi(int q) const { return std::min(c->plan.nt_max, (q + 1) * w.k); }
+    int restore(int slot, int)
+    {
+        const int64_t ff = c->plan.field_floats;
+        hipStream_t st = c->stream;
+        if (slot < 0) {
+            int rc = other(c, launch_fill(w.F[0], 2 * ff, 0.f, st), "fill");
+            if (rc) return rc;
+        } else {
+            const float *ckp = w.CK + size_t(slot) * 2 * ff;
             HIPCHK(c, hipMemcpyAsync(w.F[0], ckp, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
             HIPCHK(c, hipMemcpyAsync(w.F[1], ckp + ff, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
-            Fields f{w.F[0], w.F[1], w.F[2], w.F[3]};
-            if ((rc = ev_begin(c, K_FWD))) return rc;
-            if ((rc = forward_range(c, af, lo, hi, false, nullptr, true, w.Dh, lo, f))) return rc;
-            if ((rc = ev_end(c))) return rc;
         }
+        f = Fields{w.F[0], w.F[1], w.F[2], w.F[3]};
+        return FWI_OK;
+    }
+    int store(int slot, int)
+    {
+        const int64_t ff = c->plan.field_floats;
+        float *ckp = w.CK + size_t(slot) * 2 * ff;
+        HIPCHK(c, hipMemcpyAsync(ckp, f.prev, size_t(ff) * 4, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(ckp + ff, f.cur, size_t(ff) * 4, hipMemcpyDeviceToDevice, c->stream));
+        return FWI_OK;
+    }
+    // one segment per time loop, so that the captured loops repeat
+    int forward(int q, bool emit)
+    {
+        int rc;
+        const int lo = seg_lo(q), hi = seg_hi(q);
+        if ((rc = ev_begin(c, K_FWD))) return rc;
+        if ((rc = forward_range(c, af, lo, hi, false, nullptr, emit, w.Dh, lo, f))) return rc;
+        c->stats.recomputed_steps += hi - lo;
+        return ev_end(c);
+    }
+    int advance(int q0, int q1)
+    {
+        for (int q = q0; q < q1; ++q) {
+            const int rc = forward(q, false);
+            if (rc) return rc;
+        }
+        return FWI_OK;
+    }
+    int emit(int q) { return forward(q, true); }
+    int adjoint(int q)
+    {
+        int rc;
+        const Plan &p = c->plan;
+        const int64_t gf = p.img_floats;
+        const int lo = seg_lo(q), hi = seg_hi(q);
+        const bool two = c->tile[K_ADJ].tb == 2;
         if ((rc = ev_begin(c, K_ADJ))) return rc;
         std::vector<char> key;
         key_put(key, 'A');
@@ -1042,8 +1312,30 @@ int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
             return int(FWI_OK);
         });
         if (rc) return rc;
-        if ((rc = ev_end(c))) return rc;
+        return ev_end(c);
     }
+};
+
+// Backward sweep: the segments last to first, each one's D^n history
+// recomputed from a snapshot by the checkpointing schedule (the last one's
+// is already stored), the adjoint steps with the fused imaging condition
+// run over it; finally fold and scale the image. The adjoint sources
+// (time-major [nt_max][Q]) are in the samples buffer.
+int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
+{
+    const Plan &p = c->plan;
+    const int64_t ff = p.field_floats, gf = p.img_floats;
+    hipStream_t st = c->stream;
+    int rc;
+    if ((rc = other(c, launch_fill(w.A[0], 4 * ff, 0.f, st), "fill"))) return rc;
+    if ((rc = other(c, launch_fill(w.G, gf, 0.f, st), "fill"))) return rc;
+    SweepOps ops{c, w, base_args(c, v, K_FWD), base_args(c, v, K_ADJ), static_cast<float *>(c->samples.p),
+                 Fields{w.F[0], w.F[1], w.F[2], w.F[3]},
+                 // lambda^{n+2} (prev) and lambda^{n+1} (cur), both zero at the start
+                 Fields{w.A[0], w.A[1], w.A[2], w.A[3]}};
+    ops.a.G = w.G;
+    std::vector<int> free = revolve_free(w.slots);
+    if ((rc = revolve(ops, w.nseg, 0, w.nseg, -1, free))) return rc;
     FinalArgs fin{};
     fin.shots = static_cast<const ShotDesc *>(c->d_shots.p);
     fin.nshots = p.S;
@@ -1241,9 +1533,7 @@ int ensure_tilings(fwi_ctx *c, const float *v)
             if (rc) break;
         }
     }
-    release(trial.d_waves);
-    release(trial.d_rrows);
-    release(trial.d_rmap);
+    trial.release_all();
     if (rc) return rc;
     for (int k = 0; k < kClasses; ++k) {
         Tiling &t = c->tile[k];
@@ -1394,14 +1684,12 @@ int pair_core(fwi_ctx *c, const float *v0, const float *dv, float *dd, float *im
     int rc;
     const Plan &p = c->plan;
     Sweep w;
-    if ((rc = choose_segments(c, &w.k, &w.nseg))) return rc;
+    if ((rc = choose_segments(c, w))) return rc;
     const int k = w.k, nseg = w.nseg;
-    c->stats.ckpt_every = nseg > 1 ? k : 0;
-    c->stats.n_segments = nseg;
     const int64_t ff = p.field_floats, gf = p.img_floats;
     if ((rc = ensure(c, c->fields, size_t(8 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
         (rc = ensure(c, c->dhist, size_t(k) * gf * 4)) ||
-        (rc = ensure(c, c->ckpt, size_t(std::max(0, nseg - 1)) * 2 * ff * 4)) ||
+        (rc = ensure(c, c->ckpt, size_t(w.slots) * 2 * ff * 4)) ||
         (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)) ||
         (!dd && (rc = ensure(c, c->pairdata, size_t(std::max<int64_t>(p.data_size, 1)) * 4))))
         return rc;
@@ -1423,9 +1711,9 @@ int pair_core(fwi_ctx *c, const float *v0, const float *dv, float *dd, float *im
     for (int sgi = 0; sgi < nseg; ++sgi) {
         const int lo = sgi * k, hi = std::min(p.nt_max, lo + k);
         const bool last = sgi == nseg - 1;
-        if (!last) {
+        if (w.spine[size_t(sgi)] >= 0) {
             // (u^{lo-1}, u^lo): the fields the step at n = lo reads as prev, cur
-            float *ckp = w.CK + size_t(sgi) * 2 * ff;
+            float *ckp = w.CK + size_t(w.spine[size_t(sgi)]) * 2 * ff;
             HIPCHK(c, hipMemcpyAsync(ckp, lo % 2 == 0 ? U1 : U0, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
             HIPCHK(c, hipMemcpyAsync(ckp + ff, lo % 2 == 0 ? U0 : U1, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
         }
@@ -1526,8 +1814,7 @@ void fwi_ctx_destroy(fwi_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (Tiling &t : c->tile)
-        for (DevBuf *b : {&t.d_waves, &t.d_rrows, &t.d_rmap}) release(*b);
+    for (Tiling &t : c->tile) t.release_all();
     for (DevBuf *b : {&c->d_qrw, &c->d_rcptr, &c->d_rcq, &c->d_rnt, &c->d_rcw, &c->d_roff, &c->resid})
         release(*b);
     for (DevBuf *b : {&c->d_shots, &c->d_qnt, &c->d_qrptr, &c->d_qroff, &c->d_wav, &c->fields, &c->samples,
@@ -1547,6 +1834,19 @@ int fwi_ctx_set_stream(fwi_ctx *c, void *hip_stream)
     if (!c) return FWI_EINVAL;
     c->stream = static_cast<hipStream_t>(hip_stream);
     return FWI_OK;
+}
+
+int fwi_ctx_set_ckpt_slots(fwi_ctx *c, int32_t slots)
+{
+    if (!c) return FWI_EINVAL;
+    if (slots < -1) return set_err(c, FWI_EINVAL, "ckpt slots must be >= -1");
+    c->ckpt_slots = slots;
+    return FWI_OK;
+}
+
+int fwi_checkpoint_schedule(int32_t nseg, int32_t slots, int64_t *recomputed)
+{
+    return revolve_check(nseg, slots, recomputed);
 }
 
 int fwi_ctx_set_mem_budget(fwi_ctx *c, int64_t bytes)

@@ -61,6 +61,10 @@ class FwiContext:
     def set_mem_budget(self, nbytes: int):
         _check(self.lib, self.ctx, self.lib.fwi_ctx_set_mem_budget(self.ctx, int(nbytes)))
 
+    def set_ckpt_slots(self, slots: int = -1):
+        """Cap the snapshots the adjoint sweeps hold (-1: no cap)."""
+        _check(self.lib, self.ctx, self.lib.fwi_ctx_set_ckpt_slots(self.ctx, int(slots)))
+
     def set_profiling(self, on: bool):
         _check(self.lib, self.ctx, self.lib.fwi_ctx_set_profiling(self.ctx, 1 if on else 0))
 
@@ -238,3 +242,15 @@ def born_demig(grid, acq, v0, dv):
 
 def born_mig(grid, acq, v0, dd):
     return _ctx_of(v0).born_mig(grid, acq, v0, dd)
+
+
+def checkpoint_schedule(nseg: int, slots: int) -> int:
+    """Replay the adjoint sweeps' checkpointing schedule for `nseg` segments
+    and `slots` snapshot slots on the host (no device needed), checking
+    every action; returns the number of segments it recomputes."""
+    lib = _abi.load()
+    n = C.c_int64(0)
+    rc = lib.fwi_checkpoint_schedule(int(nseg), int(slots), C.byref(n))
+    if rc != _abi.FWI_OK:
+        raise _abi.FwiError(rc, f"checkpoint schedule nseg={nseg} slots={slots}")
+    return int(n.value)

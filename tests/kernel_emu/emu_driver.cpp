@@ -109,10 +109,12 @@ static int run_fd(int argc, char **argv)
         g_ctx = c;
         CK(fwi_ctx_set_graphs(c, 0));
         const std::string spec = argv[a];
-        int cw = 0, rows = 0, tb = 0, pd = 0, ck = 0;
+        int cw = 0, rows = 0, tb = 0, pd = 0, ck = 0, slots = -1;
         if (spec != "auto") {
-            if (std::sscanf(spec.c_str(), "%d,%d,%d,%d,%d", &cw, &rows, &tb, &pd, &ck) != 5) return 2;
+            const int nf = std::sscanf(spec.c_str(), "%d,%d,%d,%d,%d,%d", &cw, &rows, &tb, &pd, &ck, &slots);
+            if (nf != 5 && nf != 6) return 2;
             CK(fwi_ctx_set_tiling(c, -1, cw, rows, tb, pd));
+            CK(fwi_ctx_set_ckpt_slots(c, slots));
         }
         g.ckpt_every = ck;
         float *v0 = dev<float>(nm), *vt = dev<float>(nm), *grad = dev<float>(nm), *img = dev<float>(nm);
@@ -127,11 +129,23 @@ static int run_fd(int argc, char **argv)
         CK(born_pair(c, &g, &geo, v0, grad, dd, img2));
         CK(born_demig(c, &g, &geo, v0, grad, dd));
         CK(born_mig(c, &g, &geo, v0, dd, img2));
-        CK(fwi_misfit(c, &g, &geo, v0, dobs, &phi));
         fwi_stats st{};
         fwi_ctx_get_stats(c, &st);
-        std::printf("ok %s tile_fwd=%d,%d,%d,%d segments=%d\n", spec.c_str(), st.tile_cw[0], st.tile_rows[0],
-                    st.tile_levels[0], st.tile_prefetch[0], st.n_segments);
+        CK(fwi_misfit(c, &g, &geo, v0, dobs, &phi));
+        // FNV-1a over the bits of the gradients and the migrated image: the
+        // same for every checkpointing schedule
+        auto fnv = [&](const float *q) {
+            uint64_t h = 1469598103934665603ULL;
+            for (size_t i = 0; i < nm; ++i) {
+                uint32_t b;
+                std::memcpy(&b, q + i, 4);
+                for (int byte = 0; byte < 4; ++byte) h = (h ^ ((b >> (8 * byte)) & 0xffu)) * 1099511628211ULL;
+            }
+            return (unsigned long long)h;
+        };
+        std::printf("ok %s tile_fwd=%d,%d,%d,%d segments=%d slots=%d recomputed=%lld hash=%016llx,%016llx,%016llx\n",
+                    spec.c_str(), st.tile_cw[0], st.tile_rows[0], st.tile_levels[0], st.tile_prefetch[0],
+                    st.n_segments, st.ckpt_slots, (long long)st.recomputed_steps, fnv(grad), fnv(grad2), fnv(img2));
         std::fflush(stdout);
         for (float *p : {v0, vt, grad, img, grad2, img2, dobs, dd, dsyn}) std::free(p);
         fwi_ctx_destroy(c);

@@ -46,6 +46,8 @@ TILINGS = [
     "2,24,1,1,0", "2,32,1,1,0", "1,8,1,2,0", "1,16,1,2,0", "1,24,1,2,0", "1,32,1,2,0", "1,48,1,2,0",
     "2,8,1,2,0", "2,16,1,2,0", "2,24,1,2,0", "2,32,1,2,0", "1,24,2,1,0", "1,48,2,1,0", "2,24,2,1,0",
     "2,48,2,1,0", "1,24,1,1,3", "2,16,1,2,3", "1,24,2,1,3", "2,48,2,1,2", "auto",
+    # binomial checkpointing: a snapshot cap below the uniform schedule's
+    "1,24,1,1,1,1", "2,16,1,2,2,0", "1,24,2,1,1,2",
 ]
 
 pytestmark = pytest.mark.skipif(not os.path.exists(CLANG), reason="ROCm clang++ not found")
@@ -225,6 +227,28 @@ def test_step_kernels_in_bounds_every_tiling(emu_driver, tmp_path, geom):
     specs = [t for t in TILINGS if not grid.free_surface or t == "auto" or t.split(",")[2] == "1"]
     out = _run_parallel(emu_driver, ["fd", path], specs)
     assert out.count("ok ") == len(specs), out
+
+
+def test_checkpoint_schedules_give_the_same_bits(emu_driver, tmp_path):
+    """Gradients and migrated images are the same bits with the whole
+    history stored, uniform checkpoints, and binomial schedules down to no
+    snapshot at all (every segment recomputed from the zero state)."""
+    grid, acq, v0, vt = _ragged()
+    path = str(tmp_path / "geom.txt")
+    _write_geom(path, grid, acq, v0, vt)
+    groups = {"1,24,1,1": ["0", "3", "1", "1,0", "1,1", "1,3", "2,0"],
+              "1,24,2,1": ["0", "3", "1,0", "1,2"]}
+    specs = [f"{t},{c}" for t, cs in groups.items() for c in cs]
+    out = _run_parallel(emu_driver, ["fd", path], specs)
+    lines = [l for l in out.splitlines() if l.startswith("ok ")]
+    assert len(lines) == len(specs), out
+    info = {l.split()[1]: dict(kv.split("=") for kv in l.split()[2:]) for l in lines}
+    for t, cs in groups.items():
+        hashes = {info[f"{t},{c}"]["hash"] for c in cs}
+        assert len(hashes) == 1, (t, {c: info[f"{t},{c}"] for c in cs})
+    # the capped schedules really ran with fewer snapshots and recomputed more
+    assert int(info["1,24,1,1,1,0"]["slots"]) == 0
+    assert int(info["1,24,1,1,1,0"]["recomputed"]) > int(info["1,24,1,1,1"]["recomputed"])
 
 
 # (depth, base width, grid) -> kernels the configuration must reach
