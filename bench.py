@@ -300,7 +300,7 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the propagation path runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.deblur_only:
         print(json.dumps(deblur_timing(train_steps=100)), flush=True)

@@ -10,7 +10,7 @@ One iteration of the network method:
      (transfer learning), reset at every new frequency band
   4. p = deblur_apply(g); if p is not a descent direction (<p, g_phi> >= 0)
      the plain direction p = g is used instead (the gradient stays the
-     fallback and the judge)
+     fallback and the reference for the descent test)
   5. line search along p and v <- clip(v + alpha p)
 The plain method skips steps 2-4 (p = g). Both use the same line search:
 a trial step with max|alpha p| = step_frac * v_max (shrunk by 4 until it
