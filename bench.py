@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--no-spill-probe", action="store_true",
                     help="skip the full-width salt-grid measurement of the stencil kernels")
     ap.add_argument("--spill-nt", type=int, default=60)
+    ap.add_argument("--spill-only", action="store_true",
+                    help="run only the full-width salt-grid measurement (for profiling its kernels)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the off-grid / free-surface / relative-perturbation step timings")
     ap.add_argument("--variant-steps", type=int, default=2)
@@ -304,6 +306,9 @@ def main():
         sys.exit(2)
     if args.deblur_only:
         print(json.dumps(deblur_timing(train_steps=100)), flush=True)
+        return
+    if args.spill_only:
+        print(json.dumps(spill_probe(args.spill_nt)), flush=True)
         return
     import numpy as np
     import torch
