@@ -66,6 +66,7 @@ class FwiOptions:
     train_steps_first: int = 500          # Adam steps in a band's first iteration
     train_steps: int = 200                # ... and in the later ones (warm start)
     lr: float = 1e-3
+    diverge_factor: float = 100.0         # training whose loss ends above this x its start is discarded
     net: DeblurConfig = field(default_factory=DeblurConfig)
     seed: int = 2403
     mute_rows: int = 0                    # zero the update in the top rows (both methods)
@@ -193,6 +194,7 @@ class FwiRun:
         p = g
         fallback = None
         train_loss = None
+        net_dir = False          # p is the network's direction
         a_qn = None              # quasi-Newton trial step along p
         if o.method in ("bb", "lbfgs"):
             p, a_qn = self._qn_direction(g_phi)
@@ -208,20 +210,44 @@ class FwiRun:
             steps = o.train_steps_first if it == 0 else o.train_steps
             hist = self.net.deblur_train(dm1, g.contiguous(), steps, o.lr)
             train_loss = [float(hist[0]), float(hist[-1])]
-            q = self.net.deblur_apply(g.contiguous())
-            if o.mute_rows:
-                q[:o.mute_rows] = 0
+            if not (np.isfinite(train_loss[1]) and train_loss[1] <= o.diverge_factor * train_loss[0]):
+                # training diverged: redraw the weights and take the plain
+                # direction this iteration
+                self.net.reset(o.seed + 7919 * (band + 1) + it)
+                fallback = "diverged"
+            else:
+                q = self.net.deblur_apply(g.contiguous())
+                if o.mute_rows:
+                    q[:o.mute_rows] = 0
+                fallback = not (float(torch.sum(q * g_phi)) < 0.0 and bool(torch.isfinite(q).all()))
+                if not fallback:
+                    p = q
+                    net_dir = True
             _sync()
             t["train_apply"] = time.perf_counter() - ta
-            fallback = not (float(torch.sum(q * g_phi)) < 0.0 and bool(torch.isfinite(q).all()))
-            if not fallback:
-                p = q
         # line search along p (shared by all methods)
         ta = time.perf_counter()
         pmax = float(p.abs().max())
         if not pmax > 0:
             return self._record(band, it, fmax, phi, t, 0.0, fallback, train_loss)
         self.prev_v, self.prev_g = self.v.clone(), g_phi.clone()
+        scale0 = self.step_scale
+        alpha = self._search(acq, d_obs, phi, p, pmax, a_qn)
+        if alpha == 0.0 and net_dir:
+            # no decrease along the network's direction: the plain gradient
+            # takes this iteration, from the step scale that held before
+            self.step_scale = scale0
+            p, pmax = g, float(g.abs().max())
+            fallback = "no decrease"
+            alpha = self._search(acq, d_obs, phi, p, pmax, None)
+        self.v = self._clip(self.v + alpha * p)
+        _sync()
+        t["line_search"] = time.perf_counter() - ta
+        return self._record(band, it, fmax, phi, t, alpha * pmax, fallback, train_loss)
+
+    def _search(self, acq, d_obs, phi, p, pmax, a_qn):
+        """Step length along p that lowers the misfit (0 if none is found)."""
+        o = self.opts
         if a_qn is not None:
             # the quasi-Newton step, capped and backtracked; accepted as soon
             # as it lowers the misfit
@@ -232,11 +258,7 @@ class FwiRun:
                 a0 *= 0.25
                 nb += 1
                 f1 = self._misfit(acq, self._clip(self.v + a0 * p), d_obs)
-            alpha = a0 if f1 < phi else 0.0
-            self.v = self._clip(self.v + alpha * p)
-            _sync()
-            t["line_search"] = time.perf_counter() - ta
-            return self._record(band, it, fmax, phi, t, alpha * pmax, fallback, train_loss)
+            return a0 if f1 < phi else 0.0
         # trial step, shrunk by 4 while it does not reduce the misfit
         # (at most `max_backtrack` times), then a second point at twice it
         a0 = self.step_scale * o.step_frac * self.v_max / pmax
@@ -255,10 +277,7 @@ class FwiRun:
             alpha = 0.0
         # the next trial starts from the scale that worked
         self.step_scale = min(1.0, self.step_scale * (0.25 ** nb) * (2.0 if nb == 0 else 1.0))
-        self.v = self._clip(self.v + alpha * p)
-        _sync()
-        t["line_search"] = time.perf_counter() - ta
-        return self._record(band, it, fmax, phi, t, alpha * pmax, fallback, train_loss)
+        return alpha
 
     def _qn_direction(self, g_phi):
         """Search direction and trial step of the BB or L-BFGS iteration."""
@@ -415,6 +434,12 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=20, help="iterations per band")
     ap.add_argument("--bands", default="3,8,15")
     ap.add_argument("--shots", type=int, default=0)
+    ap.add_argument("--net", default="small", choices=["small", "paper"],
+                    help="small: depth 3, widths 32-256, ReLU; paper: the paper's network (Appendix A, "
+                         "Table 1): depth 4, widths 128-2048, LeakyReLU 0.2")
+    ap.add_argument("--lr", type=float, default=None,
+                    help="peak learning rate of the network's Adam steps (default 1e-3 for the small "
+                         "network, 1e-4 for the paper's)")
     ap.add_argument("--train-first", type=int, default=500)
     ap.add_argument("--train", type=int, default=200)
     ap.add_argument("--out", default="")
@@ -438,8 +463,9 @@ def main(argv=None):
     def observe(acq_b):
         return fctx.fwi_forward(grid, acq_b, v_true_t)
 
-    H, W = net_grid(grid.nz, grid.nx, 3)
-    net_cfg = DeblurConfig(3, 32, 0.0, H, W)
+    depth, base, slope = (3, 32, 0.0) if args.net == "small" else (4, 128, 0.2)
+    H, W = net_grid(grid.nz, grid.nx, depth)
+    net_cfg = DeblurConfig(depth, base, slope, H, W)
     bands = tuple(float(b) for b in args.bands.split(","))
     out = {}
     lines = []
@@ -458,8 +484,9 @@ def main(argv=None):
         target = out["plain"][-1]["model_error"] if method == "net" and "plain" in out else None
         if args.method == "all":
             target = None          # full curves for the comparison
+        lr = args.lr if args.lr is not None else (1e-3 if args.net == "small" else 1e-4)
         opts = FwiOptions(method=method, bands=bands, iters_per_band=args.iters, net=net_cfg,
-                          train_steps_first=args.train_first, train_steps=args.train,
+                          train_steps_first=args.train_first, train_steps=args.train, lr=lr,
                           target_error=target, net_iters=args.net_iters or None)
         if args.seed is not None:
             opts = replace(opts, seed=args.seed)

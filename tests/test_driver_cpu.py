@@ -102,3 +102,94 @@ def test_ssim_properties():
     c1 = (0.01 * 10.0) ** 2
     v = D.ssim(np.full((20, 20), 3.0), np.full((20, 20), 5.0), 10.0)
     assert abs(v - (2 * 15 + c1) / (9 + 25 + c1)) < 1e-12
+
+
+class _QuadCtx:
+    """Stand-in for the propagation context: misfit 1/2 ||v - v*||^2."""
+    device = "cpu"
+
+    def __init__(self, v_star):
+        self.v_star = v_star
+
+    def _phi(self, v):
+        return 0.5 * float(((v - self.v_star).double() ** 2).sum())
+
+    def gradient_pair(self, grid, acq, v, d_obs, scale=-1.0):
+        g = (v - self.v_star).float()
+        return g, self._phi(v), scale * g
+
+    def fwi_gradient(self, grid, acq, v, d_obs):
+        return (v - self.v_star).float(), self._phi(v), None
+
+    def fwi_misfit(self, grid, acq, v, d_obs):
+        return self._phi(v)
+
+    def stats(self):
+        return {"cell_updates": 0.0}
+
+
+class _Net:
+    """Stand-in for the network: a fixed loss history and a direction maker."""
+
+    def __init__(self, loss, direction):
+        self.loss, self.direction, self.resets = loss, direction, []
+
+    def deblur_train(self, x, y, steps, lr):
+        return np.asarray(self.loss, np.float32)
+
+    def deblur_apply(self, g):
+        return self.direction(g)
+
+    def reset(self, seed):
+        self.resets.append(seed)
+
+
+def _run(net, monkeypatch):
+    import torch
+    monkeypatch.setattr(D, "_sync", lambda: None)
+    rng = np.random.default_rng(0)
+    v_star = torch.from_numpy((2000.0 + 100.0 * rng.standard_normal((6, 7))).astype(np.float32))
+    v0 = (v_star + 50.0 * torch.from_numpy(rng.standard_normal((6, 7)).astype(np.float32))).numpy()
+    grid = type("G", (), {"v_ref": 3000.0})()
+    run = D.FwiRun(_QuadCtx(v_star), grid, None, v0, D.FwiOptions(method="plain"), v_true=v_star.numpy())
+    run._updates_per_pass = 1.0
+    run.t0 = 0.0
+    run.opts = D.FwiOptions(method="net")
+    run.net = net
+    return run
+
+
+def test_network_direction_without_decrease_falls_back_to_the_gradient(monkeypatch):
+    """A direction that passes the descent test (a 1e-4 share of the paper's
+    gradient g = -grad phi, which the network receives) but is otherwise
+    orthogonal to it and large: no trial step lowers the misfit, so the
+    iteration takes the plain gradient instead."""
+    import torch
+
+    def bad(g):
+        g = g.double()
+        w = torch.ones_like(g) - (torch.ones_like(g) * g).sum() / (g * g).sum() * g
+        return (1e3 * w / torch.linalg.norm(w) + 1e-4 * g).float()
+    run = _run(_Net([1.0, 0.5], bad), monkeypatch)
+    e_before = run.model_error()
+    rec = run.iteration(None, None, 0, 0, 3.0)
+    assert rec["fallback"] == "no decrease"
+    assert rec["max_dv"] > 0 and run.model_error() < e_before
+    assert run.net.resets == []
+
+
+def test_diverged_training_is_discarded(monkeypatch):
+    import torch
+    run = _run(_Net([1.0, 1e9], lambda g: g), monkeypatch)
+    e_before = run.model_error()
+    rec = run.iteration(None, None, 1, 0, 8.0)
+    assert rec["fallback"] == "diverged" and len(run.net.resets) == 1
+    assert run.model_error() < e_before
+
+
+def test_good_network_direction_is_taken(monkeypatch):
+    run = _run(_Net([1.0, 0.1], lambda g: 2.0 * g), monkeypatch)
+    e_before = run.model_error()
+    rec = run.iteration(None, None, 0, 0, 3.0)
+    assert rec["fallback"] is False and rec["max_dv"] > 0
+    assert run.model_error() < e_before
