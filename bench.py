@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--spill-nt", type=int, default=60)
     ap.add_argument("--spill-only", action="store_true",
                     help="run only the full-width salt-grid measurement (for profiling its kernels)")
+    ap.add_argument("--no-fwi", action="store_true",
+                    help="skip the plain vs network-preconditioned FWI time-to-error run")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the off-grid / free-surface / relative-perturbation step timings")
     ap.add_argument("--variant-steps", type=int, default=2)
@@ -230,6 +232,42 @@ def variants(ctx, wl, v_true, v0, steps: int, base_ms: float):
                                                              st["tile_levels"][i], st["tile_prefetch"][i]]
                                                          for i, k in enumerate(("fwd", "adj", "born", "scat"))}}
     return out
+
+
+def fwi_time_to_error() -> dict:
+    """Plain gradient against network-preconditioned FWI on the 848 x 176
+    salt workload (100 shots of uneven aperture and record length, bands 3 /
+    8 / 15 Hz, 20 iterations each, the driver's default options): the
+    iterations, solves and wall time (gradient, pair, training, line search)
+    the network method needs to reach the plain method's final model error."""
+    import numpy as np
+    import torch
+    from paper_2403_17518_amd import fwi_driver as D
+    from paper_2403_17518_amd import ops
+    from paper_2403_17518_amd.deblur import DeblurConfig
+    from synth import configs
+    wl = configs.salt_848x176(100)
+    grid, acq = wl.grid, wl.acq
+    fctx = ops.FwiContext(0)
+    try:
+        v_true = torch.from_numpy(wl.v_true.astype(np.float32)).cuda()
+        H, W = D.net_grid(grid.nz, grid.nx, 3)
+        res = {}
+        for method in ("plain", "net"):
+            target = res["plain"][-1]["model_error"] if method == "net" else None
+            opts = D.FwiOptions(method=method, net=DeblurConfig(3, 32, 0.0, H, W), target_error=target)
+            run = D.FwiRun(fctx, grid, acq, wl.v0, opts, v_true=wl.v_true, log=lambda line: None)
+            res[method] = run.run(lambda a: fctx.fwi_forward(grid, a, v_true))
+            if run.net is not None:
+                run.net.close()
+        out = {"workload": "salt_848x176: 100 shots, 176 x 848 cells of 20 m, records 3-5 s at 2 ms, "
+                           "bands 3/8/15 Hz x 20 iterations, network widths 32-256"}
+        out.update(D.time_to_error(res["plain"], res["net"]))
+        out["plain_final_ssim"] = res["plain"][-1]["ssim"]
+        return out
+    finally:
+        fctx.close()
+        torch.cuda.empty_cache()
 
 
 def deblur_flops(H: int, W: int, depth: int = 3, base: int = 32) -> float:
@@ -431,6 +469,8 @@ def main():
     if not args.no_deblur:
         out["deblur"] = deblur_timing()
         out["deblur_paper_scale"] = deblur_timing(train_steps=10, applies=5, depth=4, base=128, slope=0.2)
+    if not args.no_fwi:
+        out["fwi_time_to_error"] = fwi_time_to_error()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)
