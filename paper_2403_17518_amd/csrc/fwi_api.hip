@@ -1022,34 +1022,53 @@ std::vector<int> revolve_spine(int nseg, int slots)
 // back). On the first-split path (hi == nseg) the forward sweep has stored
 // the snapshots and the last segment's history. Ops provides restore(slot,
 // seg), advance(seg0, seg1), store(slot, seg), emit(seg) (recompute the
-// segment storing its history) and adjoint(seg).
+// segment storing its history) and adjoint(seg). A split reverses the part
+// right of the new snapshot, frees the snapshot, then reverses the part
+// left of it; the pending work is kept on an explicit stack (with ample
+// snapshots the splits nest once per segment).
 template <class Ops>
-int revolve(Ops &op, int nseg, int lo, int hi, int root, std::vector<int> &free)
+int revolve(Ops &op, int nseg, int lo0, int hi0, int root0, std::vector<int> &free)
 {
+    struct Task {
+        int lo, hi, root;
+        bool release;   // only return `root` to the free slots
+    };
+    std::vector<Task> todo{{lo0, hi0, root0, false}};
     int rc;
-    const bool spine = hi == nseg;
-    const int l = hi - lo;
-    if (l == 1) {
-        if (!spine && ((rc = op.restore(root, lo)) || (rc = op.emit(lo)))) return rc;
-        return op.adjoint(lo);
-    }
-    const int s = 1 + int(free.size());
-    if (s == 1) {
-        for (int j = hi - 1; j >= lo; --j) {
-            if (!(spine && j == nseg - 1))
-                if ((rc = op.restore(root, lo)) || (rc = op.advance(lo, j)) || (rc = op.emit(j))) return rc;
-            if ((rc = op.adjoint(j))) return rc;
+    while (!todo.empty()) {
+        const Task t = todo.back();
+        todo.pop_back();
+        if (t.release) {
+            free.push_back(t.root);
+            continue;
         }
-        return FWI_OK;
+        const int lo = t.lo, hi = t.hi, root = t.root;
+        const bool spine = hi == nseg;
+        const int l = hi - lo;
+        if (l == 1) {
+            if (!spine && ((rc = op.restore(root, lo)) || (rc = op.emit(lo)))) return rc;
+            if ((rc = op.adjoint(lo))) return rc;
+            continue;
+        }
+        const int s = 1 + int(free.size());
+        if (s == 1) {
+            for (int j = hi - 1; j >= lo; --j) {
+                if (!(spine && j == nseg - 1))
+                    if ((rc = op.restore(root, lo)) || (rc = op.advance(lo, j)) || (rc = op.emit(j))) return rc;
+                if ((rc = op.adjoint(j))) return rc;
+            }
+            continue;
+        }
+        const int m = lo + revolve_left(l, s);
+        const int slot = free.back();
+        free.pop_back();
+        if (!spine)
+            if ((rc = op.restore(root, lo)) || (rc = op.advance(lo, m)) || (rc = op.store(slot, m))) return rc;
+        todo.push_back({lo, m, root, false});
+        todo.push_back({0, 0, slot, true});
+        todo.push_back({m, hi, slot, false});
     }
-    const int m = lo + revolve_left(l, s);
-    const int slot = free.back();
-    free.pop_back();
-    if (!spine)
-        if ((rc = op.restore(root, lo)) || (rc = op.advance(lo, m)) || (rc = op.store(slot, m))) return rc;
-    if ((rc = revolve(op, nseg, m, hi, slot, free))) return rc;
-    free.push_back(slot);
-    return revolve(op, nseg, lo, m, root, free);
+    return FWI_OK;
 }
 
 // Replays a schedule on the host, checking every action against the state

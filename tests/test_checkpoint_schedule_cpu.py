@@ -69,3 +69,10 @@ def test_bad_arguments_rejected():
     for nseg, slots in ((0, 3), (-1, 0), (5, -1)):
         with pytest.raises(_abi.FwiError):
             ops.checkpoint_schedule(nseg, slots)
+
+
+def test_long_records_do_not_exhaust_the_host_stack():
+    """With ample snapshots the splits nest once per segment; the schedule
+    keeps its pending work on the heap, so 200000 segments run."""
+    assert ops.checkpoint_schedule(200000, 200000) == 199999
+    assert ops.checkpoint_schedule(200000, 2) == griewank(200000, 3)
