@@ -26,7 +26,12 @@
  *     b = (1 - sigma dt/2) a,
  * zero field values outside the padded box, V = the shot window of v
  * edge-replicated into the sponge, a point source s^n = w[n]/h^2 at the
- * source cell and point receivers d[r][n] = u^{n+1}[rz][rx].
+ * source cell and point receivers d[r][n] = u^{n+1}[rz][rx]. Options:
+ * sources and receivers between cells (fwi_geom offsets, bilinear
+ * weights), a pressure-free top surface instead of the top sponge
+ * (fwi_grid.free_surface), the Born operator on relative perturbations
+ * (fwi_grid.relative), and the checkpointing of the adjoint sweeps
+ * (fwi_grid.ckpt_every, fwi_ctx_set_mem_budget, fwi_ctx_set_ckpt_slots).
  *
  * Memory and ownership
  *   - Every float pointer argument of an operator is a DEVICE pointer that
