@@ -479,6 +479,111 @@ __global__ void k_gemm_finish(const GemmArgs a, int32_t ksplit)
 }
 
 
+// Weight gradient for thin layers (M <= 32 output channels): a 32 x 128
+// tile of C[m][n] = sum_p A[p][m] B[p][n] per workgroup, each wave one
+// 32 x 32 matrix-core tile of its own 32 columns, 64-pixel K slices. Each
+// thread loads one 8-channel chunk of A and four of the gathered B for one
+// pixel (16-byte loads) and writes them transposed into the [channel][pixel]
+// LDS tiles. Requires the 16-byte alignments of the vectorised k_wgrad and
+// a pixel split (chunk) that is a multiple of 64. Partial sums per split as
+// in k_wgrad; the first column of blocks also sums A (the bias gradient).
+__global__ __launch_bounds__(256) void k_wgrad_m32(const WgradArgs a)
+{
+    constexpr int BM = 32, BN = 128, BK = 64, LDK = BK + 8;
+    __shared__ __attribute__((aligned(16))) bf16 As[BM * LDK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[BN * LDK];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int n0 = blockIdx.x * BN;
+    const Gather &g = a.g;
+    const int P = g.H * g.W;
+    const int p_lo = blockIdx.z * a.chunk;
+    const int p_hi = min(P, p_lo + a.chunk);
+    const int nk = p_hi > p_lo ? (p_hi - p_lo + BK - 1) / BK : 0;
+    const int pl = tid >> 2;           // pixel of the slice
+    const int cq = (tid & 3) * 8;      // 8-channel chunk (A) / first chunk (B)
+    const bool mval = cq < a.M;
+    int ntap[4], nch[4];
+    bool nval[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int nn = n0 + cq + 32 * j;
+        nval[j] = nn < a.N;
+        ntap[j] = nval[j] ? nn / g.Cb : 0;
+        nch[j] = nn - ntap[j] * g.Cb;
+    }
+    uint4 ra, rb[4];
+    auto load = [&](int kt) {
+        const int p = p_lo + kt * BK + pl;
+        ra = make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rb[j] = make_uint4(0, 0, 0, 0);
+        if (p < p_hi) {
+            if (mval) ra = *reinterpret_cast<const uint4 *>(a.A + int64_t(p) * a.lda + a.acoff + cq);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (nval[j]) {
+                    const int64_t sp = gather_pix(g, p, ntap[j]);
+                    if (sp >= 0) rb[j] = *reinterpret_cast<const uint4 *>(g.src + sp * g.ld + g.coff + nch[j]);
+                }
+        }
+    };
+    auto store = [&]() {
+        const bf16 *pa = reinterpret_cast<const bf16 *>(&ra);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[(cq + e) * LDK + pl] = pa[e];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bf16 *pb = reinterpret_cast<const bf16 *>(&rb[j]);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) Bs[(cq + 32 * j + e) * LDK + pl] = pb[e];
+        }
+    };
+
+    const bool do_bias = a.bias_partial != nullptr && blockIdx.x == 0;
+    float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    f32x16 acc = {};
+    if (nk > 0) load(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        __syncthreads();
+        store();
+        if (do_bias) {
+            const bf16 *pa = reinterpret_cast<const bf16 *>(&ra);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bsum[e] += bf2f(pa[e]);
+        }
+        __syncthreads();
+        if (kt + 1 < nk) load(kt + 1);
+#pragma unroll
+        for (int kk = 0; kk < BK / 16; ++kk) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&As[(lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
+            const bf16x8 bv =
+                *reinterpret_cast<const bf16x8 *>(&Bs[(w * 32 + lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+    }
+    if (do_bias) {
+        // threads with the same chunk hold the same 8 channels for 64 pixels
+        float(*bred)[BM + 1] = reinterpret_cast<float(*)[BM + 1]>(&Bs[0]);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bred[pl][cq + e] = bsum[e];
+        __syncthreads();
+        if (tid < BM) {
+            float t = 0.f;
+            for (int r = 0; r < BK; ++r) t += bred[r][tid];
+            if (tid < a.M) a.bias_partial[int64_t(blockIdx.z) * a.M + tid] = t;
+        }
+    }
+    const int n = n0 + w * 32 + lane % 32;
+    if (n >= a.N) return;
+    float *part = a.partial + int64_t(blockIdx.z) * a.M * a.N;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int m = 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+        if (m < a.M) part[int64_t(m) * a.N + n] = acc[i];
+    }
+}
+
 // Weight gradient for wide layers: a 128 x 128 tile of C[m][n] = sum_p
 // A[p][m] B[p][n] per workgroup (4 waves of 64 x 64, four 32 x 32 matrix-core
 // tiles each), 64-pixel K slices. Each thread loads the same 8-channel chunk
@@ -1087,6 +1192,9 @@ hipError_t wgrad(const WgradArgs &a, hipStream_t s)
     if (vec && a.tile == 128 && a.chunk % 64 == 0) {
         const dim3 grid(nblocks(a.N, 128), nblocks(a.M, 128), unsigned(a.nsplit));
         hipLaunchKernelGGL(k_wgrad2, grid, dim3(256), 0, s, a);
+    } else if (vec && a.M <= 32 && a.chunk % 64 == 0) {
+        const dim3 grid(nblocks(a.N, 128), 1, unsigned(a.nsplit));
+        hipLaunchKernelGGL(k_wgrad_m32, grid, dim3(256), 0, s, a);
     } else {
         const dim3 grid(nblocks(a.N, 64), nblocks(a.M, 64), unsigned(a.nsplit));
         if (vec) hipLaunchKernelGGL(k_wgrad<true>, grid, dim3(256), 0, s, a);

@@ -253,7 +253,7 @@ def test_checkpoint_schedules_give_the_same_bits(emu_driver, tmp_path):
 
 # (depth, base width, grid) -> kernels the configuration must reach
 NET_CASES = {
-    (3, 32, 40, 56): ("k_gemm<", "k_wgrad<", "k_pool_fwd", "k_conv1_fwd"),   # odd coarse levels (5 x 7)
+    (3, 32, 40, 56): ("k_gemm<", "k_wgrad<", "k_wgrad_m32", "k_pool_fwd", "k_conv1_fwd"),   # odd coarse levels (5 x 7)
     (1, 128, 64, 240): ("k_gemm2", "k_gemm_finish", "k_wgrad2", "k_conv1_wgrad"),  # wide level 0
     (2, 256, 16, 16): ("k_gemm_finish", "k_bias_part"),  # deep, narrow: split K with the scatter epilogue
 }
