@@ -34,10 +34,8 @@ MEASURED_TRAFFIC = {
     # class runs with: "columns per lane, levels per launch, rows prefetched"
     # (two-level launches advance two time levels)
     "kernels_sha1": "3d2f9c7780956c991ca3b2fbb85e2cd0ca658701",
-    "stencil_adj": {"1,1,1": 268.6e6, "1,1,2": 267.9e6, "1,2,1": 404.3e6, "2,1,1": 268.3e6, "2,1,2": 268.5e6,
-                    "2,2,1": 377.0e6},
-    "stencil_fwd": {"1,1,1": 178.4e6, "1,1,2": 176.5e6, "1,2,1": 287.9e6, "2,1,1": 183.5e6, "2,1,2": 181.3e6,
-                    "2,2,1": 291.4e6},
+    "stencil_adj": {"1,1,1": 268.5e6, "1,1,2": 267.8e6, "1,2,1": 387.1e6, "2,1,1": 268.2e6, "2,1,2": 268.5e6, "2,2,1": 389.1e6},
+    "stencil_fwd": {"1,1,1": 178.3e6, "1,1,2": 176.3e6, "1,2,1": 288.2e6, "2,1,1": 183.4e6, "2,1,2": 181.3e6, "2,2,1": 291.3e6},
 }
 
 
