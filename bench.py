@@ -334,12 +334,12 @@ def deblur_timing(train_steps: int = 40, applies: int = 10, depth: int = 3, base
 
 def main():
     args = parse()
-    if args.calibrate_copy:
-        calibrate_copy()
-        return
     if args.gpus != 1:
         print(json.dumps({"error": "the propagation path runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.deblur_only:
         print(json.dumps(deblur_timing(train_steps=100)), flush=True)
         return

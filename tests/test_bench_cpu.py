@@ -30,3 +30,19 @@ def test_paper_scale_network_size():
     n = sum(int(__import__("numpy").prod(s)) for _, s in netparams.param_shapes(4, 128))
     assert 123e6 < n < 125e6
     assert abs(bench.deblur_flops(208, 608, 4, 128) / 1e9 - 742.1) < 0.5
+
+
+@pytest.mark.parametrize("n", ["2", "8", "0"])
+def test_more_than_one_gpu_refused(n):
+    """The propagation path runs on one GPU: any other count exits with a
+    message (before touching a device)."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", n],
+                       capture_output=True, text=True, timeout=300, cwd=root)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
