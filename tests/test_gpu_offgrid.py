@@ -110,6 +110,41 @@ def test_offgrid_operators_match_oracle(ctx, ragged_off):
     assert e_p < TOL_IMAGE
 
 
+def test_offgrid_checkpointed_sweeps_give_the_full_history_bits(ctx, ragged_off):
+    """Off-grid adjoint sources injected in recomputed segments: uniform and
+    binomial snapshot schedules give the full-history bits for the gradient
+    and the migration; the fused call's pair (its own joint sweep once
+    checkpointed) equals the separate pair and the oracle's."""
+    from dataclasses import replace
+    wl = ragged_off
+    g0, acq = wl.grid, wl.acq
+    v0, vt = dev(wl.v0), dev(wl.v_true)
+    d_obs = ctx.fwi_forward(g0, acq, vt)
+    y = dev(np.random.default_rng(4).standard_normal(acq.data_size(g0)))
+    gr0, phi0, _ = ctx.fwi_gradient(g0, acq, v0, d_obs)
+    im0 = ctx.born_mig(g0, acq, v0, y)
+    g = replace(g0, ckpt_every=29)
+    try:
+        for slots in (-1, 1):
+            print(f"[offgrid] checkpointed sweeps, slots={slots}", flush=True)
+            ctx.set_ckpt_slots(slots)
+            gr, phi, _ = ctx.fwi_gradient(g, acq, v0, d_obs)
+            st = ctx.stats()
+            assert st["n_segments"] > 3
+            assert st["ckpt_slots"] == (st["n_segments"] - 2 if slots < 0 else slots)
+            assert torch.equal(gr, gr0) and phi == phi0
+            assert torch.equal(ctx.born_mig(g, acq, v0, y), im0)
+            grad, phi2, img = ctx.gradient_pair(g, acq, v0, d_obs, scale=-1.0)
+            assert torch.equal(grad, gr0) and phi2 == phi0
+            assert torch.equal(img, ctx.born_pair(g, acq, v0, -grad))
+        e_p = rel(host(img), oracle.born_pair(g0, acq, np.asarray(wl.v0, np.float32).astype(np.float64),
+                                              -host(grad)))
+        print("checkpointed pair rel err", e_p)
+        assert e_p < TOL_IMAGE
+    finally:
+        ctx.set_ckpt_slots(-1)
+
+
 def test_zero_offsets_are_the_on_grid_path(ctx):
     wl = configs.ragged_small()
     g, a = wl.grid, wl.acq
