@@ -77,6 +77,12 @@ class FwiOptions:
     qn_max_frac: float = 0.05             # cap of a BB / L-BFGS trial step: max|dv| <= this * v_max
 
 
+# (depth, widths of the first level, LeakyReLU slope): a small network, and
+# the paper's (four pooling levels, 128 to 2048 channels, slope 0.2; its
+# network subsection and appendix table)
+NETWORKS = {"small": (3, 32, 0.0), "paper": (4, 128, 0.2)}
+
+
 def lowpass(x: np.ndarray, dt: float, fmax: float, axis: int = -1) -> np.ndarray:
     """Zero-phase 4th-order Butterworth low-pass (forward-backward)."""
     sos = butter(4, fmax, btype="low", fs=1.0 / dt, output="sos")
@@ -463,7 +469,7 @@ def main(argv=None):
     def observe(acq_b):
         return fctx.fwi_forward(grid, acq_b, v_true_t)
 
-    depth, base, slope = (3, 32, 0.0) if args.net == "small" else (4, 128, 0.2)
+    depth, base, slope = NETWORKS[args.net]
     H, W = net_grid(grid.nz, grid.nx, depth)
     net_cfg = DeblurConfig(depth, base, slope, H, W)
     bands = tuple(float(b) for b in args.bands.split(","))
