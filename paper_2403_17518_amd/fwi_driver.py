@@ -461,7 +461,8 @@ def main(argv=None):
     from synth import configs
     wl = {"salt_848x176": lambda: configs.salt_848x176(args.shots or 100),
           "salt_1700x350": lambda: configs.salt_1700x350(args.shots or 300),
-          "layered_600x200": lambda: configs.layered_600x200(args.shots or 64)}[args.workload]()
+          "layered_600x200": lambda: configs.layered_600x200(args.shots or 64),
+          "marmousi_601x221": lambda: configs.marmousi_601x221()}[args.workload]()
     grid, acq = wl.grid, wl.acq
     fctx = ops.FwiContext(0)
     v_true_t = torch.from_numpy(wl.v_true.astype(np.float32)).cuda()

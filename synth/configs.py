@@ -72,6 +72,22 @@ def layered_600x200(nshots: int = 64, nt: int = 4000) -> Workload:
     return Workload("layered_600x200", grid, acq, v_true, v0, 15.0)
 
 
+def marmousi_601x221(nt: int = 3000, dt: float = 1.4e-3) -> Workload:
+    """The acquisition of the paper's Marmousi example: 601 x 221 grid
+    points at 15 m, 30 sources and 300 receivers equally spaced along the
+    top row (zero depth), a 5 Hz Ricker wavelet. The Marmousi model itself is
+    not available: a seeded layered and faulted model over Marmousi's
+    velocity range (1500-5500 m/s) stands in for it, smoothed for the
+    starting model. dt keeps v_max dt / h at 0.51; 3000 steps record 4.2 s."""
+    grid = Grid(nz=221, nx=601, nb=20, h=15.0, dt=dt, nt_max=nt, v_ref=5500.0)
+    v_true = models.layered_faulted(221, 601, vmin=1500.0, vmax=5500.0)
+    v0 = models.smooth(v_true, 10.0)
+    src_x = np.round((np.arange(30) + 0.5) * 601 / 30).astype(np.int32)
+    rec_x = np.round((np.arange(300) + 0.5) * 601 / 300).astype(np.int32)
+    acq = _surface_acq(src_x, rec_x, ricker(5.0, dt, nt), z=0)
+    return Workload("marmousi_601x221", grid, acq, v_true, v0, 5.0)
+
+
 def salt_1700x350(nshots: int = 300, dt: float = 1e-3,
                   seed: int = models.SEED, nz: int = 350, nx: int = 1700,
                   h: float = 10.0, margin: int = 50, name: str = "salt_1700x350") -> Workload:
