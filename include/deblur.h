@@ -32,8 +32,10 @@
  *   output       W[1][C0][1][1], b[1]
  *
  * Images (x, y of deblur_train / deblur_apply) are device FP32 [nz][nx]
- * with nz <= in_h, nx <= in_w and in_h - nz, in_w - nx even: they are
- * scaled by 1 / max|.|, reflect-padded to in_h x in_w, and the network
+ * with nz <= in_h, nx <= in_w: they are scaled by 1 / max|.| and
+ * reflect-padded to in_h x in_w, floor((in_h - nz) / 2) rows above and the
+ * rest below (columns alike: floor((in_w - nx) / 2) on the left), each
+ * padding narrower than the image; the network
  * output is cropped back and multiplied by max|x| (apply). Training uses
  * the MSE loss on the padded grid, Adam (beta 0.9, 0.999, eps 1e-8) with a
  * cosine-annealed learning rate from lr_max to 0 over the call's steps; Adam

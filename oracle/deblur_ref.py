@@ -97,9 +97,10 @@ def train(params_np, x_np, t_np, depth: int, steps: int, lr_max: float, slope: f
 
 
 def normalise_pad(img, H: int, W: int):
-    """img / max|img|, reflect-padded (centred) to H x W."""
+    """img / max|img|, reflect-padded to H x W: floor((H - nz) / 2) rows
+    above, the rest below; columns alike."""
     img = np.asarray(img, dtype=np.float64)
     mx = np.max(np.abs(img))
     nz, nx = img.shape
     py, px = (H - nz) // 2, (W - nx) // 2
-    return np.pad(img / mx if mx > 0 else img * 0, ((py, py), (px, px)), mode="reflect"), mx, py, px
+    return np.pad(img / mx if mx > 0 else img * 0, ((py, H - nz - py), (px, W - nx - px)), mode="reflect"), mx, py, px

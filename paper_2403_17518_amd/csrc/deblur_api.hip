@@ -701,13 +701,14 @@ int check_ctx(deblur_net *n, fwi_ctx *ctx, hipStream_t *st)
 
 int check_image(deblur_net *n, int nz, int nx, int *py, int *px)
 {
-    if (nz < 1 || nx < 1 || nz > n->cfg.in_h || nx > n->cfg.in_w || (n->cfg.in_h - nz) % 2 ||
-        (n->cfg.in_w - nx) % 2)
-        return set_err(n, FWI_EINVAL, "image %dx%d does not fit the %dx%d network grid with even padding", nz, nx,
-                       n->cfg.in_h, n->cfg.in_w);
+    if (nz < 1 || nx < 1 || nz > n->cfg.in_h || nx > n->cfg.in_w)
+        return set_err(n, FWI_EINVAL, "image %dx%d does not fit the %dx%d network grid", nz, nx, n->cfg.in_h,
+                       n->cfg.in_w);
+    // padding above / left rounded down; an odd remainder goes below / right
     *py = (n->cfg.in_h - nz) / 2;
     *px = (n->cfg.in_w - nx) / 2;
-    if ((*py > 0 && *py >= nz) || (*px > 0 && *px >= nx))
+    const int pb = n->cfg.in_h - nz - *py, pr = n->cfg.in_w - nx - *px;
+    if ((pb > 0 && pb >= nz) || (pr > 0 && pr >= nx))
         return set_err(n, FWI_EINVAL, "reflect padding wider than the image");
     return FWI_OK;
 }

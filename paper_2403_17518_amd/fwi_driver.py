@@ -324,15 +324,12 @@ def _updates_per_pass(grid, acq) -> float:
 
 
 def net_grid(nz: int, nx: int, depth: int) -> tuple[int, int]:
-    """Smallest network grid holding an nz x nx image with an even, non-zero
-    reflect padding on each axis and sides divisible by 2^depth."""
+    """Smallest network grid holding an nz x nx image with at least one cell
+    of reflect padding on each side and sides divisible by 2^depth."""
     q = 1 << depth
 
     def one(n):
-        m = ((n + 2 + q - 1) // q) * q
-        if (m - n) % 2:
-            raise ValueError("the network grid needs even image sides")
-        return m
+        return ((n + 2 + q - 1) // q) * q
 
     return one(nz), one(nx)
 

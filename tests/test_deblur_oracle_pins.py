@@ -136,3 +136,14 @@ def test_normalise_pad_reflects():
     out, mx, py, px = R.normalise_pad(img, 5, 8)
     assert mx == 6 and (py, px) == (1, 2)
     assert out[1, 2] == img[0, 0] / 6 and out[0, 2] == img[1, 0] / 6 and out[1, 0] == img[0, 2] / 6
+
+
+def test_odd_padding_puts_the_extra_cell_below_and_right():
+    img = np.arange(12.0).reshape(3, 4) + 1
+    out, mx, py, px = R.normalise_pad(img, 6, 7)
+    assert out.shape == (6, 7) and (py, px) == (1, 1) and mx == 12
+    assert np.array_equal(out[1:4, 1:5], img / 12)
+    # mirror images about the first and last row / column, edge not repeated
+    assert np.array_equal(out[0, 1:5], img[1] / 12)
+    assert np.array_equal(out[4, 1:5], img[1] / 12) and np.array_equal(out[5, 1:5], img[0] / 12)
+    assert np.array_equal(out[1:4, 5], img[:, 2] / 12) and np.array_equal(out[1:4, 6], img[:, 1] / 12)

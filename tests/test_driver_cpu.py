@@ -32,8 +32,9 @@ def test_parabola_step_finds_the_minimum_of_a_quadratic():
 def test_net_grid_padding():
     assert D.net_grid(200, 600, 3) == (208, 608)
     assert D.net_grid(176, 848, 3) == (184, 856)
-    with pytest.raises(ValueError):
-        D.net_grid(175, 848, 3)
+    # odd sides: the odd padding cell goes below / right
+    assert D.net_grid(175, 848, 3) == (184, 856)
+    assert D.net_grid(221, 601, 3) == (224, 608) and D.net_grid(221, 601, 4) == (224, 608)
 
 
 def test_time_to_error():

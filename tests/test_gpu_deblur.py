@@ -185,6 +185,13 @@ def test_apply_scales_pads_and_crops(fctx):
     raw = net.forward_raw(dev(xp)).cpu().numpy()
     assert (py, px) == (2, 4)
     assert rel(out, mx * raw[py:py + 36, px:px + 64]) < 1e-2
+    # odd padding (3 rows, 5 columns): the extra cell below and right
+    g = smooth_field(37, 67, 6) * 2.1
+    out = net.deblur_apply(dev(g)).cpu().numpy()
+    xp, mx, py, px = R.normalise_pad(g.astype(np.float32), 40, 72)
+    raw = net.forward_raw(dev(xp)).cpu().numpy()
+    assert (py, px) == (1, 2) and out.shape == (37, 67)
+    assert rel(out, mx * raw[py:py + 37, px:px + 67]) < 1e-2
     net.close()
 
 
