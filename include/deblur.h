@@ -81,6 +81,21 @@ int deblur_reset(fwi_ctx *ctx, deblur_net *net, uint64_t seed);
  * every step (before that step's update). Waits for completion. */
 int deblur_train(fwi_ctx *ctx, deblur_net *net, const float *x_blurred, const float *y_target, int32_t nz,
                  int32_t nx, int32_t steps, float lr_max, float *loss_hist);
+/* Steps first .. first+count-1 of a training run of `total` steps on the
+ * pair (x_blurred -> y_target), as deblur_train runs them: the cosine
+ * schedule spans the run's `total` steps and the Adam moments carry from
+ * one call to the next, so a run split over several calls (to watch the
+ * loss, stop early or inspect the weights between steps) gives the same
+ * weights as one deblur_train(total) call. first = 0 starts a run (moments
+ * zeroed); first > 0 must continue the run the previous call on this
+ * network left at step `first`, with the same total and lr_max, else
+ * FWI_ESTATE (deblur_set_params, deblur_reset and deblur_load end a run;
+ * deblur_grad_raw, deblur_forward_raw, deblur_apply and deblur_get_params
+ * leave it). loss_hist (host, nullable) receives `count` losses. Waits for
+ * completion. deblur_train(steps) is deblur_train_range(0, steps, steps). */
+int deblur_train_range(fwi_ctx *ctx, deblur_net *net, const float *x_blurred, const float *y_target,
+                       int32_t nz, int32_t nx, int32_t first, int32_t count, int32_t total, float lr_max,
+                       float *loss_hist);
 /* y = max|x| * N(pad(x / max|x|)) cropped to [nz][nx]; device FP32. */
 int deblur_apply(fwi_ctx *ctx, deblur_net *net, const float *x, int32_t nz, int32_t nx, float *y);
 

@@ -256,17 +256,20 @@ int born_pair(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
               const float *v0, const float *dv, float *dd, float *img);
 
 /* The gradient and its doubly migrated image at the same model, as one FWI
- * iteration of the network method needs them: grad = J^T (F(v) - d_obs) (as
- * fwi_gradient, bit for bit), misfit (host, nullable), and
- * img = J^T J (scale * grad). When the forward sweep's imaging history fits
- * in memory whole (no checkpoints), the pair reuses it: only the scattered
- * field is propagated, with the source (2 dV / V) D^n read from the stored
- * background history, then the adjoint. Otherwise the pair runs as
- * born_pair. The image equals born_pair(v, scale * grad) up to FP32
- * rounding (the scattered source is formed from the stored D^n). */
+ * iteration of the network method needs them (section 2.3 eq. 13 and 15):
+ * grad = J^T (F(v) - d_obs) (as fwi_gradient, bit for bit), misfit (host,
+ * nullable), img = J^T J (scale * grad) and, if dd is not NULL, the
+ * demigrated data dd = J (scale * grad) (device, packed traces). When the
+ * forward sweep's imaging history fits in memory whole (no checkpoints),
+ * the pair reuses it: only the scattered field is propagated, with the
+ * source (2 dV / V) D^n read from the stored background history, then the
+ * adjoint. Otherwise the pair runs as born_pair (and dd, img equal
+ * born_pair(v, scale * grad) bit for bit). In the stored-history case dd
+ * and img equal born_pair's up to FP32 rounding (the scattered source is
+ * formed from the stored D^n). */
 int fwi_gradient_pair(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
                       const float *v, const float *d_obs, float *grad, double *misfit,
-                      float scale, float *img);
+                      float scale, float *img, float *dd);
 
 #ifdef __cplusplus
 }

@@ -95,7 +95,7 @@ SIGNATURES = {
     "born_mig": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P]),
     "born_pair": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P, _P]),
     "fwi_gradient_pair": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P,
-                                    C.POINTER(C.c_double), C.c_float, _P]),
+                                    C.POINTER(C.c_double), C.c_float, _P, _P]),
     "deblur_create": (C.c_int, [_P, C.POINTER(deblur_cfg), C.c_uint64, C.POINTER(_P)]),
     "deblur_destroy": (None, [_P]),
     "deblur_last_error": (C.c_char_p, [_P]),
@@ -104,6 +104,8 @@ SIGNATURES = {
     "deblur_get_params": (C.c_int, [_P, _P, _P]),
     "deblur_reset": (C.c_int, [_P, _P, C.c_uint64]),
     "deblur_train": (C.c_int, [_P, _P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_float, _P]),
+    "deblur_train_range": (C.c_int, [_P, _P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_float, _P]),
     "deblur_apply": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
     "deblur_forward_raw": (C.c_int, [_P, _P, _P, _P]),
     "deblur_grad_raw": (C.c_int, [_P, _P, _P, _P, C.POINTER(C.c_double), _P]),

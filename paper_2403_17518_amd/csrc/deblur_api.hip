@@ -68,6 +68,10 @@ struct deblur_net {
     std::vector<int64_t> a_off, cat_off, pool_off, c_off, d_off;  // per level offsets (elements)
     int64_t wpart_max = 0, bpart_max = 0;
     int nblk0 = 0;
+    // training run in progress (deblur_train_range): the next step of a
+    // schedule of run_total steps at run_lr; run_next < 0 = none
+    int32_t run_next = -1, run_total = 0;
+    float run_lr = 0.f;
     // per-layer profiling
     bool prof = false;
     std::vector<ProfRec> prof_recs;
@@ -775,6 +779,7 @@ int deblur_num_params(const deblur_net *n, int64_t *np)
 
 int deblur_set_params(fwi_ctx *ctx, deblur_net *n, const float *params)
 {
+    if (n) n->run_next = -1;   // new weights end a training run
     hipStream_t st;
     int rc = check_ctx(n, ctx, &st);
     if (rc) return rc;
@@ -800,6 +805,7 @@ int deblur_get_params(fwi_ctx *ctx, const deblur_net *cn, float *params)
 
 int deblur_reset(fwi_ctx *ctx, deblur_net *n, uint64_t seed)
 {
+    if (n) n->run_next = -1;   // new weights end a training run
     hipStream_t st;
     int rc = check_ctx(n, ctx, &st);
     if (rc) return rc;
@@ -842,47 +848,67 @@ int deblur_grad_raw(fwi_ctx *ctx, deblur_net *n, const float *x, const float *t,
     return FWI_OK;
 }
 
-int deblur_train(fwi_ctx *ctx, deblur_net *n, const float *x, const float *y, int32_t nz, int32_t nx, int32_t steps,
-                 float lr_max, float *loss_hist)
+int deblur_train_range(fwi_ctx *ctx, deblur_net *n, const float *x, const float *y, int32_t nz, int32_t nx,
+                       int32_t first, int32_t count, int32_t total, float lr_max, float *loss_hist)
 {
     hipStream_t st;
     int rc = check_ctx(n, ctx, &st);
     if (rc) return rc;
     if (!x || !y) return set_err(n, FWI_EINVAL, "NULL image");
-    if (steps < 0 || !(lr_max >= 0.f)) return set_err(n, FWI_EINVAL, "bad steps or learning rate");
+    if (first < 0 || count < 0 || total < 0 || int64_t(first) + count > total || !(lr_max >= 0.f))
+        return set_err(n, FWI_EINVAL, "bad step range %d + %d of %d or learning rate", first, count, total);
+    if (first > 0 && (n->run_next != first || n->run_total != total || n->run_lr != lr_max))
+        return set_err(n, FWI_ESTATE, "step %d does not continue the network's training run", first);
     int py, px;
     if ((rc = check_image(n, nz, nx, &py, &px))) return rc;
-    if (steps == 0) return FWI_OK;
+    if (count == 0) return FWI_OK;
+    n->run_next = -1;   // until this call has completed
     const int H = n->cfg.in_h, W = n->cfg.in_w;
     float *scal = P_<float>(n->scal);  // [0] max|x|, [1] max|y|
-    if ((rc = alloc(n, n->loss_dev, size_t(steps) * 8)) || (rc = alloc(n, n->hyper, size_t(steps) * 3 * 4)))
+    if ((rc = alloc(n, n->loss_dev, size_t(count) * 8)) || (rc = alloc(n, n->hyper, size_t(count) * 3 * 4)))
         return rc;
     HCK(n, absmax(x, int64_t(nz) * nx, scal, st));
     HCK(n, absmax(y, int64_t(nz) * nx, scal + 1, st));
     HCK(n, pad_norm(x, nz, nx, H, W, py, px, scal, P_<bf16>(n->xin), nullptr, st));
     HCK(n, pad_norm(y, nz, nx, H, W, py, px, scal + 1, nullptr, P_<float>(n->t32), st));
-    // cosine-annealed learning rate and Adam bias corrections per step
-    std::vector<float> hyper(size_t(steps) * 3);
-    for (int t = 0; t < steps; ++t) {
-        hyper[3 * t] = float(lr_max * 0.5 * (1.0 + std::cos(M_PI * double(t) / double(steps))));
-        hyper[3 * t + 1] = float(1.0 - std::pow(double(kBeta1), t + 1));
-        hyper[3 * t + 2] = float(1.0 - std::pow(double(kBeta2), t + 1));
+    // cosine-annealed learning rate (over the run's total steps) and the Adam
+    // bias corrections of each step
+    std::vector<float> hyper(size_t(count) * 3);
+    for (int i = 0; i < count; ++i) {
+        const int t = first + i;
+        hyper[3 * i] = float(lr_max * 0.5 * (1.0 + std::cos(M_PI * double(t) / double(total))));
+        hyper[3 * i + 1] = float(1.0 - std::pow(double(kBeta1), t + 1));
+        hyper[3 * i + 2] = float(1.0 - std::pow(double(kBeta2), t + 1));
     }
     HCK(n, hipMemcpyAsync(n->hyper.p, hyper.data(), hyper.size() * 4, hipMemcpyHostToDevice, st));
-    HCK(n, fill_f(P_<float>(n->mom1), n->nparam, 0.f, st));
-    HCK(n, fill_f(P_<float>(n->mom2), n->nparam, 0.f, st));
-    for (int t = 0; t < steps; ++t) {
-        if ((rc = forward(n, st)) || (rc = backward(n, st, P_<double>(n->loss_dev, t)))) return rc;
+    if (first == 0) {
+        HCK(n, fill_f(P_<float>(n->mom1), n->nparam, 0.f, st));
+        HCK(n, fill_f(P_<float>(n->mom2), n->nparam, 0.f, st));
+    }
+    for (int i = 0; i < count; ++i) {
+        if ((rc = forward(n, st)) || (rc = backward(n, st, P_<double>(n->loss_dev, i)))) return rc;
         HCK(n, adam(P_<float>(n->params), P_<float>(n->grads), P_<float>(n->mom1), P_<float>(n->mom2),
-                    P_<bf16>(n->pbf), n->nparam, P_<float>(n->hyper, 3 * t), kBeta1, kBeta2, kEps, st));
+                    P_<bf16>(n->pbf), n->nparam, P_<float>(n->hyper, 3 * i), kBeta1, kBeta2, kEps, st));
         if ((rc = refresh_weights(n, st))) return rc;
     }
-    std::vector<double> lh(static_cast<size_t>(steps));
+    std::vector<double> lh(static_cast<size_t>(count));
     HCK(n, hipMemcpyAsync(lh.data(), n->loss_dev.p, lh.size() * 8, hipMemcpyDeviceToHost, st));
     HCK(n, hipStreamSynchronize(st));
     if (loss_hist)
-        for (int t = 0; t < steps; ++t) loss_hist[t] = float(lh[size_t(t)]);
+        for (int i = 0; i < count; ++i) loss_hist[i] = float(lh[size_t(i)]);
+    if (first + count < total) {
+        n->run_next = first + count;
+        n->run_total = total;
+        n->run_lr = lr_max;
+    }
     return FWI_OK;
+}
+
+int deblur_train(fwi_ctx *ctx, deblur_net *n, const float *x, const float *y, int32_t nz, int32_t nx, int32_t steps,
+                 float lr_max, float *loss_hist)
+{
+    if (steps < 0) return n ? set_err(n, FWI_EINVAL, "bad steps or learning rate") : FWI_EINVAL;
+    return deblur_train_range(ctx, n, x, y, nz, nx, 0, steps, steps, lr_max, loss_hist);
 }
 
 int deblur_apply(fwi_ctx *ctx, deblur_net *n, const float *x, int32_t nz, int32_t nx, float *y)

@@ -1983,7 +1983,7 @@ int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float
 }
 
 int fwi_gradient_pair(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v, const float *d_obs,
-                      float *grad, double *misfit, float scale, float *img)
+                      float *grad, double *misfit, float scale, float *img, float *dd)
 {
     int rc = begin_call(c, g, geo);
     if (rc) return rc;
@@ -1999,14 +1999,14 @@ int fwi_gradient_pair(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const 
     if ((rc = other(c, launch_scale(grad, scale, dv, int64_t(p.nz) * p.nx, c->stream), "scale"))) return rc;
     if (w.nseg > 1) {
         // the history was checkpointed: the pair runs its own joint Born sweep
-        if ((rc = pair_core(c, mv, dv, nullptr, img))) return rc;
+        if ((rc = pair_core(c, mv, dv, dd, img))) return rc;
         return finish_stats(c);
     }
     // the whole D^n history of the gradient's forward sweep is still stored:
     // only the scattered field is propagated, with the source (2 dV / V) D^n
     const int64_t ff = p.field_floats;
     float *samp = static_cast<float *>(c->samples.p);
-    if ((rc = ensure(c, c->pairdata, size_t(std::max<int64_t>(p.data_size, 1)) * 4))) return rc;
+    if (!dd && (rc = ensure(c, c->pairdata, size_t(std::max<int64_t>(p.data_size, 1)) * 4))) return rc;
     if ((rc = other(c, launch_fill(w.F[0], 2 * ff, 0.f, c->stream), "fill"))) return rc;
     StepArgs a = base_args(c, mv, K_SCAT);
     a.dv = dv;
@@ -2014,7 +2014,7 @@ int fwi_gradient_pair(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const 
     if ((rc = ev_begin(c, K_BORN))) return rc;
     if ((rc = scat_range(c, a, 0, p.nt_max, samp, w.Dh, 0, f))) return rc;
     if ((rc = ev_end(c))) return rc;
-    float *data = static_cast<float *>(c->pairdata.p);
+    float *data = dd ? dd : static_cast<float *>(c->pairdata.p);
     TraceArgs t = trace_args(c);
     t.tm_in = samp;
     t.alpha = 1.f;

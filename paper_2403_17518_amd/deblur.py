@@ -131,6 +131,21 @@ class DeblurNet:
                                           int(steps), float(lr_max), hist.ctypes.data))
         return hist[:steps]
 
+    def train_range(self, x: torch.Tensor, y: torch.Tensor, first: int, count: int, total: int,
+                    lr_max: float = 1e-3) -> np.ndarray:
+        """Steps first .. first+count-1 of a training run of `total` steps
+        (first = 0 starts the run; a later call continues it); returns the
+        loss history of these steps."""
+        x = self._img(x, x.shape, "x")
+        y = self._img(y, x.shape, "y")
+        hist = np.zeros(max(count, 1), dtype=np.float32)
+        self._sync_stream()
+        self._check(self.lib.deblur_train_range(self.fctx.ctx, self.net, C.c_void_p(x.data_ptr()),
+                                                C.c_void_p(y.data_ptr()), int(x.shape[0]), int(x.shape[1]),
+                                                int(first), int(count), int(total), float(lr_max),
+                                                hist.ctypes.data))
+        return hist[:count]
+
     def deblur_apply(self, x: torch.Tensor) -> torch.Tensor:
         x = self._img(x, x.shape, "x")
         y = torch.empty_like(x)

@@ -194,20 +194,24 @@ class FwiContext:
         return (img, dd) if want_dd else img
 
 
-    def gradient_pair(self, grid, acq, v, d_obs, scale: float = -1.0):
+    def gradient_pair(self, grid, acq, v, d_obs, scale: float = -1.0, want_dd: bool = False):
         """(grad, misfit, img): the FWI gradient and J^T J (scale * grad) at
         the same model in one call (the pair reuses the gradient's stored
-        imaging history when it fits in memory)."""
+        imaging history when it fits in memory); with want_dd also the
+        demigrated data J (scale * grad): (grad, misfit, img, dd)."""
         v = self._model(v, "v", grid)
-        d_obs = self._data(d_obs, "d_obs", self._data_size(grid, acq))
+        nd = self._data_size(grid, acq)
+        d_obs = self._data(d_obs, "d_obs", nd)
         grad = torch.empty((grid.nz, grid.nx), device=self.device, dtype=torch.float32)
         img = torch.empty((grid.nz, grid.nx), device=self.device, dtype=torch.float32)
+        dd = torch.empty(nd, device=self.device, dtype=torch.float32) if want_dd else None
         phi = C.c_double()
         g, gv = self._prep(grid, acq)
         _check(self.lib, self.ctx, self.lib.fwi_gradient_pair(
             self.ctx, C.byref(g), C.byref(gv.geom), C.c_void_p(v.data_ptr()), C.c_void_p(d_obs.data_ptr()),
-            C.c_void_p(grad.data_ptr()), C.byref(phi), C.c_float(scale), C.c_void_p(img.data_ptr())))
-        return grad, float(phi.value), img
+            C.c_void_p(grad.data_ptr()), C.byref(phi), C.c_float(scale), C.c_void_p(img.data_ptr()),
+            C.c_void_p(dd.data_ptr()) if want_dd else None))
+        return (grad, float(phi.value), img, dd) if want_dd else (grad, float(phi.value), img)
 
 
 _default: dict = {}

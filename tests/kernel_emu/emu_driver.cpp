@@ -124,7 +124,7 @@ static int run_fd(int argc, char **argv)
         std::memcpy(vt, hvt.data(), nm * 4);
         double phi = 0;
         CK(fwi_forward(c, &g, &geo, vt, dobs));
-        CK(fwi_gradient_pair(c, &g, &geo, v0, dobs, grad, &phi, -1.f, img));
+        CK(fwi_gradient_pair(c, &g, &geo, v0, dobs, grad, &phi, -1.f, img, nullptr));
         CK(fwi_gradient(c, &g, &geo, v0, dobs, grad2, &phi, dsyn));
         CK(born_pair(c, &g, &geo, v0, grad, dd, img2));
         CK(born_demig(c, &g, &geo, v0, grad, dd));

@@ -2,10 +2,18 @@
 against the FP64 network oracle, on weights and inputs drawn by the shared
 seeded generators.
 
-Tolerances: bf16 keeps 8 significant bits (unit roundoff 2^-9 ~ 2e-3); each
-conv rounds its inputs and output once, and errors from ~15 layers add in
-quadrature, so the network output is held to 3e-2 relative L2 and the
-parameter gradients (two more passes) to 6e-2 relative L2 per tensor group.
+Tolerances are derived, not fixed: the library stores activations, weights
+and back-propagated gradients in bf16 (unit roundoff 2^-8) and accumulates in
+FP32, so the error it can show against the FP64 oracle is the error bf16
+storage causes. tests/bf16_storage.py computes that error for each case (the
+oracle's network with values rounded to bf16 where the library stores them)
+and every bound below is BF16_FACTOR (2) times it: per output for the
+forward pass, per tensor for the parameter gradients, and for the loss the
+first-order effect of the output error, 2 |dy| / |y - t| + (|dy| / |y - t|)^2.
+
+The optimiser is checked element by element: the weights after each Adam
+step of a training run equal the oracle's Adam update (FP64) of the weights
+before it, fed the gradient the GPU used, to FP32 rounding.
 """
 import os
 import tempfile
@@ -13,6 +21,7 @@ import tempfile
 import numpy as np
 import pytest
 
+import bf16_storage as B
 from oracle import deblur_ref as R
 from synth import netparams
 
@@ -22,11 +31,14 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_2403_17518_amd import ops  # noqa: E402
+from paper_2403_17518_amd import _abi, ops  # noqa: E402
 from paper_2403_17518_amd.deblur import DeblurConfig, DeblurNet  # noqa: E402
 
-TOL_FWD = 3e-2
-TOL_GRAD = 6e-2
+
+def loss_bound(fwd_bound, y_exact, t):
+    """Relative loss error that an output error of fwd_bound |y| allows."""
+    r = fwd_bound * np.linalg.norm(y_exact) / np.linalg.norm(np.asarray(y_exact) - np.asarray(t, np.float64))
+    return 2.0 * r + r * r
 
 
 def rel(a, b):
@@ -68,9 +80,10 @@ def test_forward_matches_oracle(fctx, depth, base, H, W, slope):
     y = net.forward_raw(dev(x)).cpu().numpy()
     ps32 = [torch.as_tensor(p.astype(np.float32).astype(np.float64)) for p in ps]
     ref = R.forward(ps32, torch.as_tensor(x.astype(np.float32).astype(np.float64)), depth, slope).numpy()
+    bound, _ = B.forward_bound([p.numpy() for p in ps32], x.astype(np.float32), depth, slope)
     e = rel(y, ref)
-    print("forward rel err", e)
-    assert e < TOL_FWD
+    print(f"forward rel err {e:.3e}, derived bound {bound:.3e}")
+    assert e < bound
     net.close()
 
 
@@ -85,68 +98,119 @@ def test_full_size_forward(fctx):
     y = net.forward_raw(dev(x)).cpu().numpy()
     ps32 = [torch.as_tensor(p.astype(np.float32).astype(np.float64)) for p in ps]
     ref = R.forward(ps32, torch.as_tensor(x.astype(np.float32).astype(np.float64)), 3, 0.0).numpy()
+    bound, _ = B.forward_bound([p.numpy() for p in ps32], x.astype(np.float32), 3, 0.0)
     e = rel(y, ref)
-    print("full-size forward rel err", e)
-    assert e < TOL_FWD
+    print(f"full-size forward rel err {e:.3e}, derived bound {bound:.3e}")
+    assert e < bound
     net.close()
+
+
+def _check_gradients(net, depth, base, slope, ps, x, t, tag):
+    loss, g = net.grad_raw(dev(x), dev(t))
+    ps32 = [p.astype(np.float32).astype(np.float64) for p in ps]
+    x32, t32 = x.astype(np.float32), t.astype(np.float32)
+    lref, gref, yref = R.loss_and_grads(ps32, x32, t32, depth, slope)
+    fb, _ = B.forward_bound(ps32, x32, depth, slope)
+    lb = loss_bound(fb, yref, t32)
+    print(f"[{tag}] loss rel err {abs(loss - lref) / lref:.3e}, derived bound {lb:.3e}")
+    assert abs(loss - lref) <= lb * lref
+    bounds = B.gradient_bounds(ps32, x32, t32, depth, slope, gref)
+    gg = netparams.unflatten(g, depth, base)
+    names = [n for n, _ in netparams.param_shapes(depth, base)]
+    worst = (0.0, "", 0.0)
+    for name, a, b, bd in zip(names, gg, gref, bounds):
+        if np.linalg.norm(b) == 0:
+            continue
+        e = rel(a, b)
+        if e / bd > worst[0]:
+            worst = (e / bd, name, e)
+        assert e < bd, (name, e, bd)
+    print(f"[{tag}] largest gradient error / derived bound: {worst[0]:.2f} ({worst[1]}, {worst[2]:.3e})")
 
 
 @pytest.mark.parametrize("slope", [0.0, 0.2])
 def test_parameter_gradients_match_oracle(fctx, slope):
     depth, base, H, W = 2, 16, 32, 64
-    cfg = DeblurConfig(depth, base, slope, H, W)
-    net = DeblurNet(fctx, cfg)
+    net = DeblurNet(fctx, DeblurConfig(depth, base, slope, H, W))
     ps = netparams.draw(depth, base, seed=11)
     net.set_params(netparams.flatten(ps))
-    x, t = smooth_field(H, W, 3), smooth_field(H, W, 4)
-    loss, g = net.grad_raw(dev(x), dev(t))
-    ps32 = [p.astype(np.float32).astype(np.float64) for p in ps]
-    lref, gref, _ = R.loss_and_grads(ps32, x.astype(np.float32), t.astype(np.float32), depth, slope)
-    assert abs(loss - lref) < TOL_FWD * lref
-    gg = netparams.unflatten(g, depth, base)
-    names = [n for n, _ in netparams.param_shapes(depth, base)]
-    worst = 0.0
-    for name, a, b in zip(names, gg, gref):
-        if np.linalg.norm(b) == 0:
-            continue
-        e = rel(a, b)
-        worst = max(worst, e)
-        assert e < TOL_GRAD, (name, e)
-    print("worst per-tensor gradient rel err", worst)
+    _check_gradients(net, depth, base, slope, ps, smooth_field(H, W, 3), smooth_field(H, W, 4), f"slope {slope}")
     net.close()
-
-
-TOL_GRAD_PAPER = 0.12
 
 
 def test_paper_scale_gradients_match_oracle(fctx):
     """The paper's network (four down blocks, widths 128-2048, LeakyReLU 0.2):
-    every parameter gradient against the FP64 oracle on a 32 x 64 image.
-
-    The deepest block works on 2 x 4 pixels, so its weight gradients are sums
-    of a handful of products of bf16-stored activations and bf16-stored
-    back-propagated gradients (after 23 layers): storing those tensors in bf16
-    with exact arithmetic otherwise (a CPU emulation on this case) already
-    puts down4.w1 7.5% from the FP64 gradient. The bound is 1.6x that."""
+    every parameter gradient against the FP64 oracle on a 32 x 64 image. The
+    deepest block works on 2 x 4 pixels, so its weight gradients are sums of
+    a handful of products of bf16-stored activations and gradients after 23
+    layers: its derived bound is the loosest (about 0.14)."""
     depth, base, H, W, slope = 4, 128, 32, 64, 0.2
     net = DeblurNet(fctx, DeblurConfig(depth, base, slope, H, W))
     ps = netparams.draw(depth, base, seed=17)
     net.set_params(netparams.flatten(ps))
-    x, t = smooth_field(H, W, 7), smooth_field(H, W, 8)
-    loss, g = net.grad_raw(dev(x), dev(t))
-    ps32 = [p.astype(np.float32).astype(np.float64) for p in ps]
-    lref, gref, _ = R.loss_and_grads(ps32, x.astype(np.float32), t.astype(np.float32), depth, slope)
-    assert abs(loss - lref) < TOL_FWD * lref
-    gg = netparams.unflatten(g, depth, base)
-    names = [n for n, _ in netparams.param_shapes(depth, base)]
-    worst = 0.0
-    for name, a, b in zip(names, gg, gref):
-        if np.linalg.norm(b) == 0:
-            continue
-        e = rel(a, b)
-        worst = max(worst, e)
-        assert e < TOL_GRAD_PAPER, (name, e)
-    print("paper-scale worst per-tensor gradient rel err", worst)
+    _check_gradients(net, depth, base, slope, ps, smooth_field(H, W, 7), smooth_field(H, W, 8), "paper scale")
+    net.close()
+
+
+def test_adam_steps_match_the_oracle_elementwise(fctx):
+    """Adam with bias correction and the cosine-annealed rate (paper section
+    2.4): a 3-step run split over three deblur_train_range calls. Before each
+    step the gradient at the network's current weights is read with
+    deblur_grad_raw (the image fills the grid and is already scaled to
+    max |x| = 1, so it is the gradient the training step computes); after it,
+    every weight must equal the oracle's FP64 Adam update of the weights
+    before it with that gradient and the oracle's moments, within one FP32
+    unit in the last place of the weight plus 1e-5 of the step's learning
+    rate (the FP32 arithmetic of the update). The split run must give the
+    weights of one deblur_train(3) call bit for bit."""
+    depth, base, H, W, slope = 2, 16, 32, 64, 0.2
+    net = DeblurNet(fctx, DeblurConfig(depth, base, slope, H, W))
+    p0 = netparams.flatten(netparams.draw(depth, base, seed=19))
+    x, y = dev(smooth_field(H, W, 3)), dev(smooth_field(H, W, 4))
+    assert float(x.abs().max()) == 1.0 and float(y.abs().max()) == 1.0
+    total, lr_max = 3, 1e-3
+    net.set_params(p0)
+    net.deblur_train(x, y, total, lr_max)
+    p_once = net.get_params()
+    net.set_params(p0)
+    p = p0.copy()
+    m = np.zeros(p.size)
+    v = np.zeros(p.size)
+    for t in range(total):
+        _, g = net.grad_raw(x, y)
+        net.train_range(x, y, t, 1, total, lr_max)
+        p_new = net.get_params()
+        lr = R.cosine_lr(lr_max, t, total)
+        ref, m, v = R.adam_step(p.astype(np.float64), g.astype(np.float64), m, v, t + 1, lr)
+        err = np.abs(p_new.astype(np.float64) - ref)
+        tol = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64) + 1e-5 * lr
+        k = int(np.argmax(err / tol))
+        print(f"[adam] step {t}: lr {lr:.3e}, worst |err| / tol = {err[k] / tol[k]:.3f} "
+              f"(update {abs(ref[k] - p[k]):.3e})")
+        assert np.all(err <= tol)
+        # the step moved every weight with a non-zero gradient by about lr
+        moved = np.abs(ref - p) > 0.5 * lr
+        assert moved.mean() > 0.5
+        p = p_new
+    assert np.array_equal(p, p_once)
+    net.close()
+
+
+def test_train_range_refuses_a_broken_run(fctx):
+    depth, base, H, W = 2, 8, 16, 32
+    net = DeblurNet(fctx, DeblurConfig(depth, base, 0.0, H, W))
+    x, y = dev(smooth_field(H, W, 1)), dev(smooth_field(H, W, 2))
+    net.train_range(x, y, 0, 2, 5, 1e-3)
+    for first, total, lr in ((3, 5, 1e-3), (2, 6, 1e-3), (2, 5, 2e-3)):
+        with pytest.raises(_abi.FwiError) as ei:
+            net.train_range(x, y, first, 1, total, lr)
+        assert ei.value.code == _abi.FWI_ESTATE
+    with pytest.raises(_abi.FwiError):
+        net.train_range(x, y, 4, 2, 5, 1e-3)        # past the end of the run
+    net.train_range(x, y, 2, 3, 5, 1e-3)            # the run continues where it stopped
+    net.set_params(net.get_params())                 # new weights end the run
+    with pytest.raises(_abi.FwiError):
+        net.train_range(x, y, 0 + 1, 1, 5, 1e-3)
     net.close()
 
 
@@ -167,9 +231,12 @@ def test_training_follows_the_oracle_and_reduces_the_loss(fctx):
     # oracle on the same normalised pair (no padding: the image fills the grid)
     xn = (x / np.abs(x).max()).astype(np.float32)
     yn = (y / np.abs(y).max()).astype(np.float32)
-    _, lref = R.train([p.astype(np.float32).astype(np.float64) for p in ps], xn, yn, depth, steps, lr)
-    print("loss gpu", hist[0], hist[-1], "oracle", lref[0], lref[-1])
-    assert abs(hist[0] - lref[0]) < TOL_FWD * lref[0]
+    ps32 = [p.astype(np.float32).astype(np.float64) for p in ps]
+    _, lref = R.train(ps32, xn, yn, depth, steps, lr)
+    fb, y0 = B.forward_bound(ps32, xn, depth, 0.0)
+    lb = loss_bound(fb, y0, yn)
+    print("loss gpu", hist[0], hist[-1], "oracle", lref[0], lref[-1], "first-loss bound", lb)
+    assert abs(hist[0] - lref[0]) <= lb * lref[0]
     assert hist[-1] < hist[0] / 10.0
     assert abs(np.log(hist[-1] / lref[-1])) < np.log(2.0)
     net.close()
@@ -184,14 +251,14 @@ def test_apply_scales_pads_and_crops(fctx):
     xp, mx, py, px = R.normalise_pad(g.astype(np.float32), 40, 72)
     raw = net.forward_raw(dev(xp)).cpu().numpy()
     assert (py, px) == (2, 4)
-    assert rel(out, mx * raw[py:py + 36, px:px + 64]) < 1e-2
+    assert rel(out, mx * raw[py:py + 36, px:px + 64]) < 1e-3
     # odd padding (3 rows, 5 columns): the extra cell below and right
     g = smooth_field(37, 67, 6) * 2.1
     out = net.deblur_apply(dev(g)).cpu().numpy()
     xp, mx, py, px = R.normalise_pad(g.astype(np.float32), 40, 72)
     raw = net.forward_raw(dev(xp)).cpu().numpy()
     assert (py, px) == (1, 2) and out.shape == (37, 67)
-    assert rel(out, mx * raw[py:py + 37, px:px + 67]) < 1e-2
+    assert rel(out, mx * raw[py:py + 37, px:px + 67]) < 1e-3
     net.close()
 
 

@@ -33,6 +33,7 @@ TOL_DATA = 1e-4
 TOL_IMAGE = 1e-4
 TOL_GRAD = 1e-3
 SAMPLED = [3, 40]
+_PAIR = {}   # stored-history pair results, for the checkpointed test
 
 
 def rel(a, b):
@@ -84,8 +85,9 @@ def test_forward_sampled_shots(full):
     assert e < TOL_DATA
 
 
-def test_gradient_sampled_shots(full):
-    wl, sub, v_true, v0, d_ref, c = full
+def _obs_sampled(c, wl, sub, v0, d_ref):
+    """Observed data: the oracle's traces on the sampled shots, the GPU's own
+    synthetic data on every other shot (whose residual is then exactly 0)."""
     g, acq = wl.grid, wl.acq
     zeros = torch.zeros(acq.data_size(g), device="cuda")
     _, _, d_syn = c.fwi_gradient(g, acq, dev(v0), zeros, want_misfit=False, want_dsyn=True)
@@ -95,6 +97,13 @@ def test_gradient_sampled_shots(full):
     d_obs_sub = f32(d_ref)
     for i, s in enumerate(SAMPLED):
         d_obs[int(off[s]):int(off[s + 1])] = dev(d_obs_sub[sub_off[i]:sub_off[i + 1]])
+    return d_obs, d_obs_sub
+
+
+def test_gradient_sampled_shots(full):
+    wl, sub, v_true, v0, d_ref, c = full
+    g, acq = wl.grid, wl.acq
+    d_obs, d_obs_sub = _obs_sampled(c, wl, sub, v0, d_ref)
     grad, phi, _ = c.fwi_gradient(g, acq, dev(v0), d_obs)
     print(f"[fullsize] oracle gradient of shots {SAMPLED}", flush=True)
     g_ref, phi_ref, _ = oracle.gradient(g, sub, v0, d_obs_sub.astype(np.float64))
@@ -130,3 +139,77 @@ def test_born_mig_sampled_shots(full):
     e = rel(img, img_ref)
     print("full-size Born migration rel err", e)
     assert e < TOL_IMAGE
+
+
+def _pair_checks(wl, sub, v0, c, grad, img, dd, dd_ref, tag):
+    """The pair's outputs at full size: the demigrated data J(-grad) of the
+    sampled shots against the oracle; the image through the identity
+    <-grad, J^T J (-grad)> = |J(-grad)|^2 over all 64 shots (eq. 14-15: the
+    image is the migration of exactly the data returned); and the image
+    against the library's own migration of those data, which the oracle
+    checks at this size in test_born_mig_sampled_shots."""
+    g, acq = wl.grid, wl.acq
+    e = _sampled_rel(wl, sub, host(dd), dd_ref)
+    print(f"[{tag}] demigrated data, worst sampled-shot rel err {e:.3e}", flush=True)
+    assert e < TOL_DATA
+    x = -host(grad)
+    lhs, rhs = float(np.dot(x.ravel(), host(img).ravel())), float(np.dot(host(dd), host(dd)))
+    print(f"[{tag}] <-g, JtJ(-g)> = {lhs:.6e}, |J(-g)|^2 = {rhs:.6e}, rel {abs(lhs - rhs) / rhs:.3e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-4 * rhs
+    mig = c.born_mig(g, acq, dev(v0), dd)
+    em = rel(host(img), host(mig))
+    print(f"[{tag}] image vs born_mig of its data rel {em:.3e}", flush=True)
+    assert em < 1e-5
+
+
+def test_gradient_pair_stored_history(full):
+    """The call the benchmark times, in the benchmark's configuration: one
+    forward sweep stores the whole D^n history (164 GB), the adjoint images
+    the gradient, the scattered field is driven by the stored history and a
+    second adjoint images it (section 2.3 eq. 13 and 15)."""
+    wl, sub, v_true, v0, d_ref, c = full
+    g, acq = wl.grid, wl.acq
+    d_obs, _ = _obs_sampled(c, wl, sub, v0, d_ref)
+    g0, phi0, _ = c.fwi_gradient(g, acq, dev(v0), d_obs)
+    print("[fullsize] gradient_pair, stored history", flush=True)
+    grad, phi, img, dd = c.gradient_pair(g, acq, dev(v0), d_obs, scale=-1.0, want_dd=True)
+    st = c.stats()
+    assert st["n_segments"] == 1 and st["recomputed_steps"] == 0
+    assert torch.equal(grad, g0) and phi == phi0
+    print(f"[fullsize] oracle Born demigration of -grad, shots {SAMPLED}", flush=True)
+    dd_ref = oracle.born_demig(g, sub, v0, -host(grad))
+    _pair_checks(wl, sub, v0, c, grad, img, dd, dd_ref, "pair, stored history")
+    _PAIR["stored"] = (host(grad), host(img), dd_ref)
+
+
+def test_gradient_pair_checkpointed(full):
+    """The same call under a 24 GiB memory budget: the history no longer
+    fits, so the record is cut into segments recomputed from snapshots and
+    the pair runs its own joint Born sweep; the gradient keeps its bits, the
+    pair equals born_pair(v, -grad) bit for bit and matches the oracle."""
+    wl, sub, v_true, v0, d_ref, _ = full
+    g, acq = wl.grid, wl.acq
+    c2 = ops.FwiContext(0)
+    try:
+        c2.set_mem_budget(24 << 30)
+        d_obs, _ = _obs_sampled(c2, wl, sub, v0, d_ref)
+        print("[fullsize] gradient_pair, checkpointed", flush=True)
+        grad, phi, img, dd = c2.gradient_pair(g, acq, dev(v0), d_obs, scale=-1.0, want_dd=True)
+        st = c2.stats()
+        print(f"[fullsize] segments {st['n_segments']} of {st['ckpt_every']} steps, "
+              f"{st['ckpt_slots']} snapshots, {st['recomputed_steps']} recomputed steps", flush=True)
+        assert st["n_segments"] > 1 and st["recomputed_steps"] > 0
+        img_bp, dd_bp = c2.born_pair(g, acq, dev(v0), -grad, want_dd=True)
+        assert torch.equal(img, img_bp) and torch.equal(dd, dd_bp)
+        stored = _PAIR.get("stored")
+        if stored is not None:
+            assert np.array_equal(host(grad), stored[0])
+            ei = rel(host(img), stored[1])
+            print(f"[fullsize] checkpointed vs stored-history image rel {ei:.3e}", flush=True)
+            assert ei < 1e-5
+            dd_ref = stored[2]
+        else:
+            dd_ref = oracle.born_demig(g, sub, v0, -host(grad))
+        _pair_checks(wl, sub, v0, c2, grad, img, dd, dd_ref, "pair, checkpointed")
+    finally:
+        c2.close()
