@@ -222,6 +222,23 @@ const char *fwi_last_error(const fwi_ctx *ctx);
 int fwi_forward(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
                 const float *v, float *d);
 
+/* d = F(v) as fwi_forward computes it (the same kernels: the same bits),
+ * for callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc): the call allocates nothing. Its scratch
+ * (the plan tables, the two wavefield levels, the receiver samples and the
+ * model copy) comes from a static device array of 64 MiB that each device
+ * the library runs on holds until the process ends; a problem that needs
+ * more returns FWI_ENOMEM (with the size in fwi_last_error) before any
+ * propagation runs. The context's own buffers, plan, tilings and captured
+ * loops are neither used nor changed; the tiling is the forced one
+ * (fwi_ctx_set_tiling) or the fixed default, never autotuned, and no loop is
+ * captured. Every allocation-free call on a device shares that device's
+ * array and leaves its contents behind: such calls that overlap on one
+ * device (other streams, other contexts, other host threads) race. Waits
+ * for the model check, as every operator does. */
+int fwi_forward_noalloc(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
+                        const float *v, float *d);
+
 /* g = J^T (F(v) - d_obs), the gradient of phi = 1/2 ||F(v) - d_obs||^2
  * with respect to v (the negative of the paper's g = L^T (d_o - d_s)).
  * misfit: HOST pointer, may be NULL (then the call does not wait);

@@ -88,6 +88,7 @@ SIGNATURES = {
     "fwi_ctx_trim": (C.c_int, [_P]),
     "fwi_last_error": (C.c_char_p, [_P]),
     "fwi_forward": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P]),
+    "fwi_forward_noalloc": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P]),
     "fwi_gradient": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P,
                                C.POINTER(C.c_double), _P]),
     "fwi_misfit": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, C.POINTER(C.c_double)]),

@@ -4,11 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -23,6 +25,9 @@ namespace {
 constexpr double kCflLimit = 0.55;     // 2D 8th-order leapfrog limit is 0.5546
 constexpr double kDefaultBudgetFrac = 0.7;  // of device memory, for D^n history + checkpoints
 constexpr int64_t kFreeMargin = int64_t(4) << 30;  // left free when sizing the history
+// Static device scratch of the allocation-free entry points (per device, held
+// until the process ends).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
 constexpr int kDefaultCw = 2;          // tiling used when autotuning is off
 constexpr int kDefaultRows = 32;
 constexpr int kDefaultTb = 1;
@@ -132,6 +137,11 @@ constexpr size_t kGraphNodeBudget = 400000;
 
 }  // namespace
 
+// The scratch of the allocation-free entry points. In host code this name is
+// a stand-in, not a device address: the address of each device's copy is
+// looked up once per device (scratch_address) and only that is used.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 struct fwi_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -164,6 +174,13 @@ struct fwi_ctx {
     uint64_t graph_tick = 0;
     float *h_check = nullptr;     // pinned [3]
     double *h_misfit = nullptr;   // pinned [1]
+    // the allocation-free entry points' scratch: this device's copy of the
+    // static `scratch` array (device address), and, while such a call runs,
+    // the bytes carved from it so far (arena != nullptr: ensure() carves
+    // instead of allocating)
+    unsigned char *scratch_dev = nullptr;
+    unsigned char *arena = nullptr;
+    size_t arena_used = 0;
     // profiling events
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
@@ -194,6 +211,20 @@ int ensure(fwi_ctx *c, DevBuf &b, size_t bytes)
 {
     if (bytes == 0) bytes = 256;
     if (b.bytes >= bytes) return FWI_OK;
+    if (c->arena) {
+        // an allocation-free call: carve the buffer from the static scratch
+        // (a buffer that grows is carved again; nothing is freed)
+        const size_t off = (c->arena_used + 255) & ~size_t(255);
+        if (off > kNoAllocScratchBytes || bytes > kNoAllocScratchBytes - off)
+            return set_err(c, FWI_ENOMEM,
+                           "the allocation-free entry points have %zu bytes of scratch; this call needs more "
+                           "(at least %zu)",
+                           kNoAllocScratchBytes, off + bytes);
+        b.p = c->arena + off;
+        b.bytes = bytes;
+        c->arena_used = off + bytes;
+        return FWI_OK;
+    }
     if (b.p) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         HIPCHK(c, hipFree(b.p));
@@ -215,6 +246,26 @@ void release(DevBuf &b)
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
+}
+
+// Device address of this device's copy of `scratch` (the device must be
+// current), looked up once per device.
+int scratch_address(int device, unsigned char **out)
+{
+    static std::mutex mu;
+    static std::map<int, unsigned char *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return FWI_EHIP;
+        }
+        it = addr.emplace(device, static_cast<unsigned char *>(p)).first;
+    }
+    *out = it->second;
+    return FWI_OK;
 }
 
 }  // namespace
@@ -1792,6 +1843,74 @@ int scat_range(fwi_ctx *c, const StepArgs &a, int lo, int hi, float *samp, float
     });
 }
 
+// An allocation-free call runs on a set-aside copy of the context: every
+// device buffer, the plan, the tilings and the captured loops of the
+// context are moved out for the call and moved back afterwards (the call's
+// own buffers, carved from the static scratch, are then dropped), so the
+// context is left as it was. Inside, ensure() carves instead of allocating,
+// and graph capture, profiling events and the autotuner (which create HIP
+// objects) are off: the tiling is the forced one or the fixed default, and
+// every tiling gives the same bits.
+class ArenaScope {
+   public:
+    explicit ArenaScope(fwi_ctx *c) : c_(c)
+    {
+        for (size_t i = 0; i < kBufs; ++i) {
+            saved_[i] = *bufs()[i];
+            *bufs()[i] = DevBuf{};
+        }
+        plan_ = std::move(c->plan);
+        c->plan = Plan{};
+        plan_valid_ = c->plan_valid;
+        c->plan_valid = false;
+        for (int k = 0; k < kClasses; ++k) {
+            tile_[k] = std::move(c->tile[k]);
+            c->tile[k] = Tiling{};
+        }
+        graphs_cache_ = std::move(c->graph_cache);
+        c->graph_cache.clear();
+        graphs_ = c->graphs;
+        profiling_ = c->profiling;
+        autotune_ = c->autotune;
+        c->graphs = c->profiling = c->autotune = false;
+        c->arena = c->scratch_dev;
+        c->arena_used = 0;
+    }
+    ~ArenaScope()
+    {
+        fwi_ctx *c = c_;
+        c->arena = nullptr;
+        c->arena_used = 0;
+        for (size_t i = 0; i < kBufs; ++i) *bufs()[i] = saved_[i];
+        c->plan = std::move(plan_);
+        c->plan_valid = plan_valid_;
+        for (int k = 0; k < kClasses; ++k) c->tile[k] = std::move(tile_[k]);
+        c->graph_cache = std::move(graphs_cache_);
+        c->graphs = graphs_;
+        c->profiling = profiling_;
+        c->autotune = autotune_;
+    }
+    ArenaScope(const ArenaScope &) = delete;
+    ArenaScope &operator=(const ArenaScope &) = delete;
+
+   private:
+    static constexpr size_t kBufs = 23;
+    std::array<DevBuf *, kBufs> bufs()
+    {
+        fwi_ctx *c = c_;
+        return {&c->d_shots, &c->d_qnt, &c->d_qrptr, &c->d_qroff, &c->d_wav, &c->d_qrw, &c->d_rcptr, &c->d_rcq,
+                &c->d_rnt, &c->d_rcw, &c->d_roff, &c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt,
+                &c->partials, &c->misfit, &c->check, &c->pairdata, &c->resid, &c->model, &c->dmodel};
+    }
+    fwi_ctx *c_;
+    DevBuf saved_[kBufs];
+    Plan plan_;
+    bool plan_valid_ = false;
+    Tiling tile_[kClasses];
+    std::vector<GraphEntry> graphs_cache_;
+    bool graphs_ = true, profiling_ = false, autotune_ = true;
+};
+
 }  // namespace
 
 namespace fwi {
@@ -1821,8 +1940,12 @@ int fwi_ctx_create(int device, void *hip_stream, fwi_ctx **out)
             hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&c->h_misfit), sizeof(double), hipHostMallocDefault) !=
             hipSuccess) {
-        delete c;
+        fwi_ctx_destroy(c);
         return FWI_ENOMEM;
+    }
+    if (scratch_address(device, &c->scratch_dev) != FWI_OK) {
+        fwi_ctx_destroy(c);
+        return FWI_EHIP;
     }
     *out = c;
     return FWI_OK;
@@ -1970,6 +2093,15 @@ int fwi_forward(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float 
     t.tr_out = d;
     if ((rc = other(c, launch_traces(t, c->stream, nullptr), "traces"))) return rc;
     return finish_stats(c);
+}
+
+int fwi_forward_noalloc(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v, float *d)
+{
+    if (!c) return FWI_EINVAL;
+    if (!c->scratch_dev) return set_err(c, FWI_ESTATE, "no scratch address on device %d", c->device);
+    if (c->arena) return set_err(c, FWI_ESTATE, "allocation-free call inside another");
+    ArenaScope scope(c);
+    return fwi_forward(c, g, geo, v, d);
 }
 
 int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v, const float *d_obs,

@@ -129,6 +129,16 @@ class FwiContext:
                                                         C.c_void_p(v.data_ptr()), C.c_void_p(d.data_ptr())))
         return d
 
+    def fwi_forward_noalloc(self, grid, acq, v: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """d = F(v) into the caller's `out` without any device allocation in
+        the library (its scratch is a static 64 MiB device array)."""
+        v = self._model(v, "v", grid)
+        d = self._data(out, "out", self._data_size(grid, acq))
+        g, gv = self._prep(grid, acq)
+        _check(self.lib, self.ctx, self.lib.fwi_forward_noalloc(self.ctx, C.byref(g), C.byref(gv.geom),
+                                                                C.c_void_p(v.data_ptr()), C.c_void_p(d.data_ptr())))
+        return d
+
     def fwi_gradient(self, grid, acq, v, d_obs, want_misfit: bool = True, want_dsyn: bool = False):
         """(g, misfit, d_syn): g = J^T (F(v) - d_obs); misfit = 1/2 ||F(v) - d_obs||^2."""
         v = self._model(v, "v", grid)

@@ -124,7 +124,13 @@ static int run_fd(int argc, char **argv)
         std::memcpy(vt, hvt.data(), nm * 4);
         double phi = 0;
         CK(fwi_forward(c, &g, &geo, vt, dobs));
-        CK(fwi_gradient_pair(c, &g, &geo, v0, dobs, grad, &phi, -1.f, img, nullptr));
+        // the allocation-free forward: the same bits from the static scratch
+        CK(fwi_forward_noalloc(c, &g, &geo, vt, dd));
+        if (ndata > 0 && std::memcmp(dd, dobs, size_t(ndata) * 4) != 0) {
+            std::fprintf(stderr, "FAIL fwi_forward_noalloc differs from fwi_forward (%s)\n", spec.c_str());
+            std::exit(1);
+        }
+        CK(fwi_gradient_pair(c, &g, &geo, v0, dobs, grad, &phi, -1.f, img, dd));
         CK(fwi_gradient(c, &g, &geo, v0, dobs, grad2, &phi, dsyn));
         CK(born_pair(c, &g, &geo, v0, grad, dd, img2));
         CK(born_demig(c, &g, &geo, v0, grad, dd));

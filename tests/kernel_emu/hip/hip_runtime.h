@@ -18,6 +18,7 @@
 
 #define __global__
 #define __device__
+#define __align__(n) __attribute__((aligned(n)))
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
@@ -146,6 +147,13 @@ hipError_t hipSetDevice(int d);
 hipError_t hipDeviceSynchronize();
 hipError_t hipMemGetInfo(size_t *fr, size_t *tot);
 hipError_t hipMalloc(void **p, size_t n);
+// a __device__ variable is host memory here: its address is the symbol
+#define HIP_SYMBOL(x) (&(x))
+inline hipError_t hipGetSymbolAddress(void **p, const void *sym)
+{
+    *p = const_cast<void *>(sym);
+    return hipSuccess;
+}
 hipError_t hipFree(void *p);
 hipError_t hipHostMalloc(void **p, size_t n, unsigned flags);
 hipError_t hipHostFree(void *p);
