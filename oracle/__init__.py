@@ -2,7 +2,8 @@
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may
 import this package. It is an independent, plain implementation of the
-paper's operators (section 2.1 eq. 1-2: forward modelling and misfit;
+paper's operators (section 2.1 eq. 1-2: forward modelling and misfit, with a damping sponge
+or a perfectly matched layer around the model;
 section 2.2 eq. 5-12b: Born modelling; section 2.3 eq. 13-15: adjoint /
 FWI gradient and the demigration-remigration pair) written in C
 (``fwi_oracle.c``) and shares no code with the HIP library.
@@ -27,7 +28,7 @@ class _OgGrid(C.Structure):
     _fields_ = [("nz", C.c_int), ("nx", C.c_int), ("nb", C.c_int),
                 ("h", C.c_double), ("dt", C.c_double),
                 ("v_ref", C.c_double), ("R", C.c_double),
-                ("free_surface", C.c_int), ("relative", C.c_int)]
+                ("free_surface", C.c_int), ("relative", C.c_int), ("pml", C.c_int)]
 
 
 class _OgGeom(C.Structure):
@@ -72,7 +73,8 @@ class _Call:
         self.g = _OgGrid(grid.nz, grid.nx, grid.nb, float(grid.h),
                          float(grid.dt), float(grid.v_ref), float(grid.R),
                          1 if getattr(grid, "free_surface", False) else 0,
-                         1 if getattr(grid, "relative", False) else 0)
+                         1 if getattr(grid, "relative", False) else 0,
+                         1 if getattr(grid, "pml", False) else 0)
 
         def ptr(a, dt):
             if a is None:

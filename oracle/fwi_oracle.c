@@ -44,6 +44,31 @@
  *                 the above on dv = v dm; born_mig (and so the gradient)
  *                 returns diag(v) J^T r, its exact transpose.
  *
+ *   PML (optional, the grid's `pml` flag; the paper names no boundary): a
+ *   perfectly matched layer in the nb padded cells instead of the sponge.
+ *   Stretching each axis by s_x = 1 + d_x / s (s the Laplace variable,
+ *   d_x = smax dx^2 the sponge's profile) and multiplying the stretched
+ *   equation by s_x s_z gives a symmetric operator,
+ *     (1/V^2)(u_tt + (d_x + d_z) u_t + d_x d_z u)
+ *       - d/dx(du/dx + psi_x) - d/dz(du/dz + psi_z) = f,
+ *     psi_x = (s_z / s_x - 1) du/dx:  psi_x,t + d_x psi_x = (d_z - d_x) du/dx,
+ *   (psi_z alike with x and z exchanged), with f in the physical cells
+ *   where d_x = d_z = 0. Discretised as the sponge scheme plus
+ *     psi_x lives on the x edges (i, j+1/2), j = 0 .. NX-2, with d_x taken at
+ *     the edge and d_z at row i; Dx u = (u[i][j+1] - u[i][j]) / h;
+ *     psi_x^n = b_x psi_x^{n-1} + a_x Dx u^n, b_x = exp(-d_x dt),
+ *     a_x = (d_z - d_x)(1 - b_x) / d_x (= d_z dt where d_x = 0), a
+ *     recursive convolution; psi_z on the z edges (i+1/2, j) alike;
+ *     u^{n+1} = a ((2 - d_x d_z dt^2) u^n
+ *               + V^2 dt^2 (L8 u^n + s^n - Dx^T psi_x^n - Dz^T psi_z^n))
+ *               - b u^{n-1},  (a, b the sponge's coefficients),
+ *   where -Dx^T psi = (psi[j+1/2] - psi[j-1/2]) / h. For every time shift the
+ *   operator is diag(mass) - L8 + Dx^T diag(m_x) Dx + Dz^T diag(m_z) Dz with
+ *   diagonal m_x, m_z, hence symmetric: reciprocity holds exactly, and the
+ *   adjoint is the same recursion (psi included) run backward in time. The
+ *   imaging history becomes V^2 dt^2 (L8 u^n + s^n - D^T psi^n), and the
+ *   Born source uses the same term.
+ *
  *   Adjoint (eq. 13; exact transpose of the Born map):
  *                 lam^n = a (2 lam^{n+1} + V^2 dt^2 (L8 lam^{n+1} + R^T r^n))
  *                         - b lam^{n+2},  n = nt-1 .. 0, lam^{nt} = lam^{nt+1} = 0,
@@ -69,6 +94,7 @@ typedef struct {
     double h, dt, v_ref, R;
     int free_surface;   /* 1: pressure-free top surface on physical row 0 */
     int relative;       /* 1: Born operator on dv / v (J diag(v)) */
+    int pml;            /* 1: perfectly matched layer instead of the sponge */
 } og_grid;
 
 typedef struct {
@@ -98,6 +124,10 @@ typedef struct {
     double *V;   /* padded velocity */
     double *c;   /* V^2 dt^2 */
     double *a, *b;
+    /* PML only (NULL otherwise): d_x d_z dt^2 per cell; recursion
+     * coefficients of the x edges (index j: edge j+1/2) and z edges (index
+     * i: edge i+1/2) */
+    double *fdt2, *bx, *ax, *bz, *az;
 } shot_dom;
 
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -151,6 +181,23 @@ static double sponge_depth(int i, int n, int nb, int lo)
     return nb > 0 ? (double)d / (double)nb : 0.0;
 }
 
+/* the same depth at a half-integer position x (an edge between cells) */
+static double layer_depth(double x, int n, int nb, int lo)
+{
+    double d = 0.0;
+    if (x < lo) d = lo - x;
+    if (x > n - 1 - nb) d = x - (n - 1 - nb);
+    return nb > 0 ? d / (double)nb : 0.0;
+}
+
+/* recursion coefficients of an edge: damping d along the edge's own axis,
+ * e along the other; psi^n = b psi^{n-1} + a D u^n */
+static void edge_coef(double d, double e, double dt, double *b, double *a)
+{
+    *b = exp(-d * dt);
+    *a = (e - d) * (d > 0.0 ? (1.0 - *b) / d : dt);
+}
+
 static int dom_init(shot_dom *D, const og_grid *g, const og_geom *geo, int s, const double *v)
 {
     shot_window(g, geo, s, &D->x0, &D->wnx);
@@ -162,6 +209,7 @@ static int dom_init(shot_dom *D, const og_grid *g, const og_geom *geo, int s, co
     D->c = malloc(n * sizeof(double));
     D->a = malloc(n * sizeof(double));
     D->b = malloc(n * sizeof(double));
+    D->fdt2 = D->bx = D->ax = D->bz = D->az = NULL;
     if (!D->V || !D->c || !D->a || !D->b) return -1;
     pad_model(g, D->x0, D->wnx, v, D->V);
     double smax = g->nb > 0 ? 3.0 * g->v_ref * log(1.0 / g->R) / (2.0 * g->nb * g->h) : 0.0;
@@ -174,12 +222,67 @@ static int dom_init(shot_dom *D, const og_grid *g, const og_geom *geo, int s, co
             D->b[k] = (1.0 - 0.5 * sig * g->dt) / (1.0 + 0.5 * sig * g->dt);
             D->c[k] = D->V[k] * D->V[k] * g->dt * g->dt;
         }
+    if (g->pml && g->nb > 0) {
+        D->fdt2 = malloc(n * sizeof(double));
+        D->bx = malloc(n * sizeof(double));
+        D->ax = malloc(n * sizeof(double));
+        D->bz = malloc(n * sizeof(double));
+        D->az = malloc(n * sizeof(double));
+        if (!D->fdt2 || !D->bx || !D->ax || !D->bz || !D->az) return -1;
+        for (int i = 0; i < D->NZ; i++)
+            for (int j = 0; j < D->NX; j++) {
+                int64_t k = (int64_t)i * D->NX + j;
+                double dz = smax * pow(sponge_depth(i, D->NZ, g->nb, D->top), 2);
+                double dx = smax * pow(sponge_depth(j, D->NX, g->nb, g->nb), 2);
+                D->fdt2[k] = dx * dz * g->dt * g->dt;
+                /* x edge (i, j+1/2): d_x at the edge, d_z of row i */
+                double dxe = smax * pow(layer_depth(j + 0.5, D->NX, g->nb, g->nb), 2);
+                edge_coef(dxe, dz, g->dt, &D->bx[k], &D->ax[k]);
+                if (j == D->NX - 1) D->ax[k] = 0.0;     /* no edge right of the box */
+                /* z edge (i+1/2, j): d_z at the edge, d_x of column j */
+                double dze = smax * pow(layer_depth(i + 0.5, D->NZ, g->nb, D->top), 2);
+                edge_coef(dze, dx, g->dt, &D->bz[k], &D->az[k]);
+                if (i == D->NZ - 1) D->az[k] = 0.0;     /* no edge below the box */
+            }
+    }
     return 0;
 }
 
 static void dom_free(shot_dom *D)
 {
     free(D->V); free(D->c); free(D->a); free(D->b);
+    free(D->fdt2); free(D->bx); free(D->ax); free(D->bz); free(D->az);
+}
+
+/* PML: advance the edge fields psi_x, psi_z of a wavefield from u (level n)
+ * and add -Dx^T psi_x - Dz^T psi_z to lap. No-op without a PML. */
+static void pml_terms(const shot_dom *D, double h, const double *u, double *psx, double *psz, double *lap)
+{
+    if (!D->fdt2) return;
+    int NZ = D->NZ, NX = D->NX;
+    for (int i = 0; i < NZ; i++)
+        for (int j = 0; j < NX; j++) {
+            int64_t k = (int64_t)i * NX + j;
+            double dux = j + 1 < NX ? (u[k + 1] - u[k]) / h : 0.0;
+            double duz = i + 1 < NZ ? (u[k + NX] - u[k]) / h : 0.0;
+            psx[k] = D->bx[k] * psx[k] + D->ax[k] * dux;
+            psz[k] = D->bz[k] * psz[k] + D->az[k] * duz;
+        }
+    for (int i = 0; i < NZ; i++)
+        for (int j = 0; j < NX; j++) {
+            int64_t k = (int64_t)i * NX + j;
+            double div = psx[k] + psz[k];
+            if (j > 0) div -= psx[k - 1];
+            if (i > 0) div -= psz[k - NX];
+            lap[k] += div / h;
+        }
+}
+
+/* the leapfrog update of one cell: a ((2 - d_x d_z dt^2) u + c lap) - b u_prev */
+static double leap(const shot_dom *D, int64_t k, double u, double lap, double um)
+{
+    double two = D->fdt2 ? 2.0 - D->fdt2[k] : 2.0;
+    return D->a[k] * (two * u + D->c[k] * lap) - D->b[k] * um;
 }
 
 /* L8 u with zero values outside the NZ x NX box; with mirror != 0 the rows
@@ -267,15 +370,21 @@ static double point_sample(const point_w *p, const double *field)
 /* one shot                                                            */
 
 /* Forward modelling of shot s. d_shot is [nrec][nt]. If hist != NULL it
- * receives u^n for n = 0 .. nt ([nt+1][NZ][NX]). */
+ * receives u^n for n = 0 .. nt ([nt+1][NZ][NX]); if lap_hist != NULL it
+ * receives L8 u^n + s^n (- D^T psi^n with a PML) for n = 0 .. nt-1
+ * ([nt][NZ][NX]), the term the imaging condition multiplies. */
 static int forward_shot(const og_grid *g, const og_geom *geo, int s, const shot_dom *D,
-                        double *d_shot, double *hist)
+                        double *d_shot, double *hist, double *lap_hist)
 {
     int nt = shot_nt(geo, s);
     int64_t n = (int64_t)D->NZ * D->NX;
     double *um = calloc(n, sizeof(double)), *u0 = calloc(n, sizeof(double));
     double *up = calloc(n, sizeof(double)), *lap = malloc(n * sizeof(double));
-    if (!um || !u0 || !up || !lap) { free(um); free(u0); free(up); free(lap); return -1; }
+    double *psx = calloc(n, sizeof(double)), *psz = calloc(n, sizeof(double));
+    if (!um || !u0 || !up || !lap || !psx || !psz) {
+        free(um); free(u0); free(up); free(lap); free(psx); free(psz);
+        return -1;
+    }
     const double *w = shot_wavelet(geo, s);
     point_w src = src_point(g, geo, D, s);
     int64_t r0 = geo->rec_ptr[s], nrec = geo->rec_ptr[s + 1] - r0;
@@ -284,8 +393,9 @@ static int forward_shot(const og_grid *g, const og_geom *geo, int s, const shot_
         if (hist) memcpy(hist + (int64_t)t * n, u0, n * sizeof(double));
         laplacian8(u0, D->NZ, D->NX, g->h, lap, g->free_surface);
         point_add(&src, w[t] * ih2, lap);
-        for (int64_t k = 0; k < n; k++)
-            up[k] = D->a[k] * (2.0 * u0[k] + D->c[k] * lap[k]) - D->b[k] * um[k];
+        pml_terms(D, g->h, u0, psx, psz, lap);
+        if (lap_hist) memcpy(lap_hist + (int64_t)t * n, lap, n * sizeof(double));
+        for (int64_t k = 0; k < n; k++) up[k] = leap(D, k, u0[k], lap[k], um[k]);
         pin_surface(g, D, up);
         for (int64_t r = 0; r < nrec; r++) {
             point_w rp = rec_point(g, geo, D, r0 + r);
@@ -294,7 +404,7 @@ static int forward_shot(const og_grid *g, const og_geom *geo, int s, const shot_
         double *tmp = um; um = u0; u0 = up; up = tmp;
     }
     if (hist) memcpy(hist + (int64_t)nt * n, u0, n * sizeof(double));
-    free(um); free(u0); free(up); free(lap);
+    free(um); free(u0); free(up); free(lap); free(psx); free(psz);
     return 0;
 }
 
@@ -309,7 +419,9 @@ static int born_shot(const og_grid *g, const og_geom *geo, int s, const shot_dom
     double *dm = calloc(n, sizeof(double)), *d0 = calloc(n, sizeof(double));
     double *dp = calloc(n, sizeof(double)), *dlap = malloc(n * sizeof(double));
     double *rho = malloc(n * sizeof(double));
-    int ok = um && u0 && up && lap && dm && d0 && dp && dlap && rho;
+    double *psx = calloc(n, sizeof(double)), *psz = calloc(n, sizeof(double));
+    double *qsx = calloc(n, sizeof(double)), *qsz = calloc(n, sizeof(double));
+    int ok = um && u0 && up && lap && dm && d0 && dp && dlap && rho && psx && psz && qsx && qsz;
     if (ok) {
         pad_model(g, D->x0, D->wnx, dv, rho);            /* Pad(dv) */
         for (int64_t k = 0; k < n; k++) rho[k] = 2.0 * rho[k] / D->V[k];
@@ -320,11 +432,12 @@ static int born_shot(const og_grid *g, const og_geom *geo, int s, const shot_dom
         for (int t = 0; t < nt; t++) {
             laplacian8(u0, D->NZ, D->NX, g->h, lap, g->free_surface);
             point_add(&src, w[t] * ih2, lap);             /* L8 u^n + s^n */
+            pml_terms(D, g->h, u0, psx, psz, lap);        /* - D^T psi^n */
             laplacian8(d0, D->NZ, D->NX, g->h, dlap, g->free_surface);
+            pml_terms(D, g->h, d0, qsx, qsz, dlap);
             for (int64_t k = 0; k < n; k++) {
-                dp[k] = D->a[k] * (2.0 * d0[k] + D->c[k] * (dlap[k] + rho[k] * lap[k]))
-                        - D->b[k] * dm[k];
-                up[k] = D->a[k] * (2.0 * u0[k] + D->c[k] * lap[k]) - D->b[k] * um[k];
+                dp[k] = leap(D, k, d0[k], dlap[k] + rho[k] * lap[k], dm[k]);
+                up[k] = leap(D, k, u0[k], lap[k], um[k]);
             }
             pin_surface(g, D, up);
             pin_surface(g, D, dp);
@@ -337,48 +450,46 @@ static int born_shot(const og_grid *g, const og_geom *geo, int s, const shot_dom
         }
     }
     free(um); free(u0); free(up); free(lap); free(dm); free(d0); free(dp); free(dlap); free(rho);
+    free(psx); free(psz); free(qsx); free(qsz);
     return ok ? 0 : -1;
 }
 
-/* Adjoint of shot s: adds Pad^T((2/V) sum_n lam^n (L8 u^n + s^n)) to img.
- * res_shot is [nrec][nt]. If lam_hist != NULL it receives lam^n for
- * n = 0..nt-1 ([nt][NZ][NX]). */
+/* Adjoint of shot s: adds Pad^T((2/V) sum_n lam^n (L8 u^n + s^n)) to img
+ * (with a PML, L8 u^n + s^n - D^T psi^n). res_shot is [nrec][nt]. If
+ * lam_hist != NULL it receives lam^n for n = 0..nt-1 ([nt][NZ][NX]). */
 static int adjoint_shot(const og_grid *g, const og_geom *geo, int s, const shot_dom *D,
                         const double *res_shot, double *img, double *lam_hist)
 {
     int nt = shot_nt(geo, s);
     int64_t n = (int64_t)D->NZ * D->NX;
-    double *hist = malloc((size_t)(nt + 1) * n * sizeof(double));
+    double *lhist = malloc((size_t)(nt + 1) * n * sizeof(double));
     double *dummy = malloc(((geo->rec_ptr[s + 1] - geo->rec_ptr[s]) * (int64_t)nt + 1) * sizeof(double));
     double *l1 = calloc(n, sizeof(double)), *l2 = calloc(n, sizeof(double));
     double *l0 = calloc(n, sizeof(double)), *lap = malloc(n * sizeof(double));
-    double *lu = malloc(n * sizeof(double)), *G = calloc(n, sizeof(double));
-    int ok = hist && dummy && l1 && l2 && l0 && lap && lu && G;
-    if (ok) ok = forward_shot(g, geo, s, D, dummy, hist) == 0;
+    double *G = calloc(n, sizeof(double));
+    double *psx = calloc(n, sizeof(double)), *psz = calloc(n, sizeof(double));
+    int ok = lhist && dummy && l1 && l2 && l0 && lap && G && psx && psz;
+    if (ok) ok = forward_shot(g, geo, s, D, dummy, NULL, lhist) == 0;
     if (ok) {
-        const double *w = shot_wavelet(geo, s);
-        point_w src = src_point(g, geo, D, s);
         int64_t r0 = geo->rec_ptr[s], nrec = geo->rec_ptr[s + 1] - r0;
-        double ih2 = 1.0 / (g->h * g->h);
         for (int t = nt - 1; t >= 0; t--) {
             laplacian8(l1, D->NZ, D->NX, g->h, lap, g->free_surface);    /* L8 lam^{n+1} */
+            pml_terms(D, g->h, l1, psx, psz, lap);        /* - D^T psi~^{n+1} */
             for (int64_t r = 0; r < nrec; r++) {          /* + R^T r^n */
                 point_w rp = rec_point(g, geo, D, r0 + r);
                 point_add(&rp, res_shot[r * nt + t], lap);
             }
-            for (int64_t k = 0; k < n; k++)
-                l0[k] = D->a[k] * (2.0 * l1[k] + D->c[k] * lap[k]) - D->b[k] * l2[k];
+            for (int64_t k = 0; k < n; k++) l0[k] = leap(D, k, l1[k], lap[k], l2[k]);
             pin_surface(g, D, l0);
             if (lam_hist) memcpy(lam_hist + (int64_t)t * n, l0, n * sizeof(double));
-            laplacian8(hist + (int64_t)t * n, D->NZ, D->NX, g->h, lu, g->free_surface);
-            point_add(&src, w[t] * ih2, lu);              /* L8 u^n + s^n */
+            const double *lu = lhist + (int64_t)t * n;     /* L8 u^n + s^n (- D^T psi^n) */
             for (int64_t k = 0; k < n; k++) G[k] += l0[k] * lu[k];
             double *tmp = l2; l2 = l1; l1 = l0; l0 = tmp;
         }
         for (int64_t k = 0; k < n; k++) G[k] *= 2.0 / D->V[k];
         pad_adjoint_add(g, D->x0, D->wnx, G, img);
     }
-    free(hist); free(dummy); free(l1); free(l2); free(l0); free(lap); free(lu); free(G);
+    free(lhist); free(dummy); free(l1); free(l2); free(l0); free(lap); free(G); free(psx); free(psz);
     return ok ? 0 : -1;
 }
 
@@ -411,7 +522,7 @@ int oracle_forward(const og_grid *g, const og_geom *geo, const double *v, double
     for (int s = 0; s < geo->nshots; s++) {
         shot_dom D;
         if (dom_init(&D, g, geo, s, v)) { err |= 1; dom_free(&D); continue; }
-        err |= forward_shot(g, geo, s, &D, d + shot_data_offset(geo, s), NULL) ? 1 : 0;
+        err |= forward_shot(g, geo, s, &D, d + shot_data_offset(geo, s), NULL, NULL) ? 1 : 0;
         dom_free(&D);
     }
     return err ? -1 : 0;
@@ -501,7 +612,7 @@ int oracle_shot_fields(const og_grid *g, const og_geom *geo, int s, const double
     double *d = malloc((nrec * nt + 1) * sizeof(double));
     double *img = calloc((int64_t)g->nz * g->nx, sizeof(double));
     int err = (!d || !img) ? -1 : 0;
-    if (!err) err = forward_shot(g, geo, s, &D, d, u_hist);
+    if (!err) err = forward_shot(g, geo, s, &D, d, u_hist, NULL);
     if (!err && lam_hist) err = adjoint_shot(g, geo, s, &D, res_shot, img, lam_hist);
     if (a_out) memcpy(a_out, D.a, n * sizeof(double));
     if (b_out) memcpy(b_out, D.b, n * sizeof(double));

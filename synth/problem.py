@@ -30,6 +30,7 @@ class Grid:
     ckpt_every: int = 0  # checkpoint interval for the GPU path (0 = auto)
     free_surface: bool = False  # pressure-free top surface on row 0 (no top sponge)
     relative: bool = False  # Born perturbations and images per dv / v (J diag(v)) instead of per dv
+    pml: bool = False  # perfectly matched layer in the nb padded cells instead of the sponge
 
     @property
     def top(self) -> int:
