@@ -239,7 +239,8 @@ def variants(ctx, wl, v_true, v0, steps: int, base_ms: float):
     """The timed step (fused gradient + Born pair) of the same workload with
     each operator variant: sources and receivers off the grid (bilinear
     spreading and sampling, seeded fractions), a pressure-free top surface,
-    and the relative-perturbation Born operator. Per variant: observed data
+    the relative-perturbation Born operator, and a perfectly matched layer
+    instead of the sponge. Per variant: observed data
     in that setting, one untimed step (plan, autotuning, graph capture),
     then `steps` steps timed with events."""
     import copy
@@ -265,7 +266,7 @@ def variants(ctx, wl, v_true, v0, steps: int, base_ms: float):
     fz[off.rec_z >= g0.nz - 1] = 0.0
     off.rec_fz, off.rec_fx, off.src_fz, off.src_fx = fz, fx, sfz, sfx
     cases = {"off_grid": (g0, off), "free_surface": (replace(g0, free_surface=True), a0),
-             "relative": (replace(g0, relative=True), a0)}
+             "relative": (replace(g0, relative=True), a0), "pml": (replace(g0, pml=True), a0)}
     stream = torch.cuda.current_stream()
     out = {}
     for name, (g, a) in cases.items():

@@ -29,7 +29,8 @@
  * source cell and point receivers d[r][n] = u^{n+1}[rz][rx]. Options:
  * sources and receivers between cells (fwi_geom offsets, bilinear
  * weights), a pressure-free top surface instead of the top sponge
- * (fwi_grid.free_surface), the Born operator on relative perturbations
+ * (fwi_grid.free_surface), a perfectly matched layer instead of the
+ * sponge (fwi_grid.pml), the Born operator on relative perturbations
  * (fwi_grid.relative), and the checkpointing of the adjoint sweeps
  * (fwi_grid.ckpt_every, fwi_ctx_set_mem_budget, fwi_ctx_set_ckpt_slots).
  *
@@ -101,6 +102,17 @@ typedef struct {
                            born_demig takes the dimensionless dv / v, and the
                            images are diag(v) J^T (fwi_gradient then returns
                            the gradient with respect to ln v). */
+    int32_t pml;        /* 1: the nb padded cells are a perfectly matched
+                           layer instead of the sponge (the same damping
+                           profile, in the stretched-coordinate equation
+                           multiplied by s_x s_z, which keeps the operator
+                           symmetric: the adjoint is the same recursion run
+                           backward). Two edge fields per propagated field
+                           ride along (memory: four more field-sized buffers
+                           per field, snapshots twice as large); the step
+                           kernels run one level per launch (a two-level
+                           tiling forced with fwi_ctx_set_tiling makes the
+                           call fail with FWI_EINVAL). */
 } fwi_grid;
 
 typedef struct {

@@ -25,7 +25,7 @@ class fwi_grid(C.Structure):
     _fields_ = [("nz", C.c_int32), ("nx", C.c_int32), ("nb", C.c_int32),
                 ("h", C.c_float), ("dt", C.c_float), ("nt_max", C.c_int32),
                 ("v_ref", C.c_float), ("R", C.c_float), ("ckpt_every", C.c_int32),
-                ("free_surface", C.c_int32), ("relative", C.c_int32)]
+                ("free_surface", C.c_int32), ("relative", C.c_int32), ("pml", C.c_int32)]
 
 
 class fwi_geom(C.Structure):
@@ -157,7 +157,8 @@ def make_grid(grid) -> fwi_grid:
                     float(grid.dt), int(grid.nt_max), float(grid.v_ref),
                     float(getattr(grid, "R", 1e-3)), int(getattr(grid, "ckpt_every", 0)),
                     1 if getattr(grid, "free_surface", False) else 0,
-                    1 if getattr(grid, "relative", False) else 0)
+                    1 if getattr(grid, "relative", False) else 0,
+                    1 if getattr(grid, "pml", False) else 0)
 
 
 class GeomView:

@@ -46,6 +46,7 @@ struct Plan {
     int nz = 0, nx = 0, nb = 0, NZ = 0, nt_max = 0, S = 0;
     int top = 0;                  // padded rows above physical row 0
     bool free_surface = false;    // pressure-free top surface (no top sponge)
+    bool pml = false;             // perfectly matched layer in the padding (nb > 0)
     bool relative = false;        // Born perturbations and images per dV / V
     float h = 0, dt = 0, v_ref = 0, R = 0;
     int ckpt_every = 0;
@@ -118,6 +119,9 @@ constexpr bool one_level(int k) { return k == K_BORN || k == K_SCAT; }
 // launch overwrites `prev` in place; a two-level launch writes the spares.
 struct Fields {
     float *prev, *cur, *s0, *s1;
+    // perfectly matched layer: the field's edge fields (x, z) at the previous
+    // level and the buffers their next level goes to
+    float *px = nullptr, *pz = nullptr, *qx = nullptr, *qz = nullptr;
 };
 
 // A time loop captured into a HIP graph: the key serializes every input the
@@ -163,6 +167,10 @@ struct fwi_ctx {
     // scratch
     DevBuf fields, samples, image, dhist, ckpt, partials, misfit, check, pairdata;
     DevBuf resid;   // combined off-grid receiver traces / residuals [data]
+    // perfectly matched layer: edge fields of the background / forward field,
+    // of the scattered field and of the adjoint field, four field-sized
+    // buffers each (x and z at two levels)
+    DevBuf psi;
     // copies of the call's model and perturbation: the time loops read these,
     // never the caller's buffers, so captured loops stay valid across calls
     DevBuf model, dmodel;
@@ -318,6 +326,7 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
     if (g->ckpt_every < 0) return set_err(c, FWI_EINVAL, "ckpt_every must be >= 0");
     if (g->free_surface != 0 && g->free_surface != 1) return set_err(c, FWI_EINVAL, "free_surface must be 0 or 1");
     if (g->relative != 0 && g->relative != 1) return set_err(c, FWI_EINVAL, "relative must be 0 or 1");
+    if (g->pml != 0 && g->pml != 1) return set_err(c, FWI_EINVAL, "pml must be 0 or 1");
     const int top = g->free_surface ? 0 : g->nb;
     const int64_t NZ64 = int64_t(g->nz) + int64_t(g->nb) + top;
     if (NZ64 > (1 << 20) || int64_t(g->nx) + 2 * g->nb > (1 << 20))
@@ -378,6 +387,7 @@ int build_plan(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo)
     p.NZ = int(NZ64);
     p.top = top;
     p.free_surface = g->free_surface != 0;
+    p.pml = g->pml != 0 && g->nb > 0;
     p.relative = g->relative != 0;
     p.nt_max = g->nt_max;
     p.h = g->h;
@@ -696,7 +706,11 @@ StepArgs base_args(fwi_ctx *c, const float *v, int cls)
     if (p.nb > 0) {
         const double smax = 3.0 * p.v_ref * std::log(1.0 / p.R) / (2.0 * p.nb * p.h);
         a.hs = float(smax * p.dt / (2.0 * double(p.nb) * p.nb));
+        a.hd0 = float(smax / (4.0 * double(p.nb) * p.nb));
     }
+    a.pml = p.pml ? 1 : 0;
+    a.dt = p.dt;
+    a.ih = float(1.0 / double(p.h));
     return a;
 }
 
@@ -895,6 +909,10 @@ int step_launch(fwi_ctx *c, StepArgs a, int cls, int flags, int levels, int acti
     a.nwaves = t.prefix[p.active_slots(active_n)];
     a.cur = f.cur;
     a.prev = f.prev;
+    a.psx_in = f.px;
+    a.psz_in = f.pz;
+    a.psx_out = f.qx;
+    a.psz_out = f.qz;
     if (levels == 1 && t.tb == 2) {
         // the single step of a two-level tiling runs on its one-level table
         a.waves = static_cast<const WaveDesc *>(t.d_waves1.p);
@@ -907,10 +925,12 @@ int step_launch(fwi_ctx *c, StepArgs a, int cls, int flags, int levels, int acti
         a.out1 = f.s0;
         a.out2 = f.s1;
         HIPCHK(c, launch_step2(flags, a, c->stream));
-        f = Fields{f.s0, f.s1, f.prev, f.cur};
+        f = Fields{f.s0, f.s1, f.prev, f.cur, f.px, f.pz, f.qx, f.qz};
     } else {
         HIPCHK(c, launch_step(flags, a, c->stream));
         std::swap(f.prev, f.cur);
+        std::swap(f.px, f.qx);
+        std::swap(f.pz, f.qz);
     }
     const double cells = step_updates(p, active_n);
     const double upd = levels * cells;
@@ -980,6 +1000,49 @@ int other(fwi_ctx *c, hipError_t e, const char *what)
     if (e != hipSuccess) return set_err(c, FWI_EHIP, "%s: %s", what, hipGetErrorString(e));
     return FWI_OK;
 }
+
+// ---- perfectly matched layer: edge-field buffers ------------------------------
+// Block PSI_FWD holds the forward (or background) field's edge fields, PSI_SCAT
+// the scattered field's, PSI_ADJ the adjoint field's: x and z at the previous
+// level, then x and z at the next. Outside the layer's rows and strips they
+// stay zero (the kernels never write there), so a block is zeroed once per
+// sweep.
+enum PsiBlock { PSI_FWD = 0, PSI_SCAT = 1, PSI_ADJ = 2 };
+constexpr int kPsiBlocks = 3;
+
+int ensure_psi(fwi_ctx *c)
+{
+    const Plan &p = c->plan;
+    if (!p.pml) return FWI_OK;
+    return ensure(c, c->psi, size_t(4 * kPsiBlocks) * size_t(p.field_floats) * 4);
+}
+
+float *psi_block(fwi_ctx *c, int b)
+{
+    if (!c->plan.pml) return nullptr;
+    return static_cast<float *>(c->psi.p) + size_t(4 * b) * size_t(c->plan.field_floats);
+}
+
+int zero_psi(fwi_ctx *c, int b)
+{
+    if (!c->plan.pml) return FWI_OK;
+    return other(c, launch_fill(psi_block(c, b), 4 * c->plan.field_floats, 0.f, c->stream), "fill");
+}
+
+Fields with_psi(Fields f, float *P, int64_t ff)
+{
+    if (P) {
+        f.px = P;
+        f.pz = P + ff;
+        f.qx = P + 2 * ff;
+        f.qz = P + 3 * ff;
+    }
+    return f;
+}
+
+// fields per snapshot of a forward state: (u^{n-1}, u^n) and, with the
+// layer, the edge fields of level n-1
+int snap_fields(const Plan &p) { return p.pml ? 4 : 2; }
 
 void reset_stats(fwi_ctx *c)
 {
@@ -1198,7 +1261,7 @@ int choose_segments(fwi_ctx *c, Sweep &w)
     const Plan &p = c->plan;
     const int nt = p.nt_max;
     const double slot = double(p.img_floats) * 4.0;
-    const double ck = 2.0 * double(p.field_floats) * 4.0;
+    const double ck = double(snap_fields(p)) * double(p.field_floats) * 4.0;
     auto nseg_of = [&](int k) { return (nt + k - 1) / k; };
     auto uniform = [&](int k) { return std::max(0, nseg_of(k) - 2); };
     auto mem = [&](int k, int S) { return double(k) * slot + double(S) * ck; };
@@ -1261,10 +1324,11 @@ int forward_for_adjoint(fwi_ctx *c, const float *v, bool sample, Sweep &w)
     if ((rc = choose_segments(c, w))) return rc;
     const int k = w.k, nseg = w.nseg;
     const int64_t ff = p.field_floats, gf = p.img_floats;
+    const int sf = snap_fields(p);
     if ((rc = ensure(c, c->fields, size_t(8 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
         (rc = ensure(c, c->dhist, size_t(k) * gf * 4)) ||
-        (rc = ensure(c, c->ckpt, size_t(w.slots) * 2 * ff * 4)) ||
-        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)))
+        (rc = ensure(c, c->ckpt, size_t(w.slots) * sf * ff * 4)) ||
+        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)) || (rc = ensure_psi(c)))
         return rc;
     float *F = static_cast<float *>(c->fields.p);
     for (int i = 0; i < 4; ++i) {
@@ -1276,17 +1340,21 @@ int forward_for_adjoint(fwi_ctx *c, const float *v, bool sample, Sweep &w)
     w.G = static_cast<float *>(c->image.p);
     float *samp = static_cast<float *>(c->samples.p);
     hipStream_t st = c->stream;
-    if ((rc = other(c, launch_fill(w.F[0], 4 * ff, 0.f, st), "fill"))) return rc;
+    if ((rc = other(c, launch_fill(w.F[0], 4 * ff, 0.f, st), "fill")) || (rc = zero_psi(c, PSI_FWD))) return rc;
     StepArgs a = base_args(c, v, K_FWD);
-    Fields f{w.F[0], w.F[1], w.F[2], w.F[3]};
+    Fields f = with_psi(Fields{w.F[0], w.F[1], w.F[2], w.F[3]}, psi_block(c, PSI_FWD), ff);
     if ((rc = ev_begin(c, K_FWD))) return rc;
     for (int sgi = 0; sgi < nseg; ++sgi) {
         const int lo = sgi * k, hi = std::min(p.nt_max, lo + k);
         const bool last = sgi == nseg - 1;
         if (w.spine[size_t(sgi)] >= 0) {
-            float *ckp = w.CK + size_t(w.spine[size_t(sgi)]) * 2 * ff;
+            float *ckp = w.CK + size_t(w.spine[size_t(sgi)]) * sf * ff;
             HIPCHK(c, hipMemcpyAsync(ckp, f.prev, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
             HIPCHK(c, hipMemcpyAsync(ckp + ff, f.cur, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
+            if (p.pml) {
+                HIPCHK(c, hipMemcpyAsync(ckp + 2 * ff, f.px, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
+                HIPCHK(c, hipMemcpyAsync(ckp + 3 * ff, f.pz, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
+            }
         }
         if ((rc = forward_range(c, a, lo, hi, sample, samp, last, w.Dh, lo, f))) return rc;
     }
@@ -1306,25 +1374,34 @@ struct SweepOps {
     int seg_hi(int q) const { return std::min(c->plan.nt_max, (q + 1) * w.k); }
     int restore(int slot, int)
     {
-        const int64_t ff = c->plan.field_floats;
+        const Plan &p = c->plan;
+        const int64_t ff = p.field_floats;
         hipStream_t st = c->stream;
+        float *P = psi_block(c, PSI_FWD);
         if (slot < 0) {
             int rc = other(c, launch_fill(w.F[0], 2 * ff, 0.f, st), "fill");
+            if (!rc && P) rc = other(c, launch_fill(P, 2 * ff, 0.f, st), "fill");
             if (rc) return rc;
         } else {
-            const float *ckp = w.CK + size_t(slot) * 2 * ff;
+            const float *ckp = w.CK + size_t(slot) * snap_fields(p) * ff;
             HIPCHK(c, hipMemcpyAsync(w.F[0], ckp, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
             HIPCHK(c, hipMemcpyAsync(w.F[1], ckp + ff, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
+            if (P) HIPCHK(c, hipMemcpyAsync(P, ckp + 2 * ff, size_t(2 * ff) * 4, hipMemcpyDeviceToDevice, st));
         }
-        f = Fields{w.F[0], w.F[1], w.F[2], w.F[3]};
+        f = with_psi(Fields{w.F[0], w.F[1], w.F[2], w.F[3]}, P, ff);
         return FWI_OK;
     }
     int store(int slot, int)
     {
-        const int64_t ff = c->plan.field_floats;
-        float *ckp = w.CK + size_t(slot) * 2 * ff;
+        const Plan &p = c->plan;
+        const int64_t ff = p.field_floats;
+        float *ckp = w.CK + size_t(slot) * snap_fields(p) * ff;
         HIPCHK(c, hipMemcpyAsync(ckp, f.prev, size_t(ff) * 4, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(ckp + ff, f.cur, size_t(ff) * 4, hipMemcpyDeviceToDevice, c->stream));
+        if (p.pml) {
+            HIPCHK(c, hipMemcpyAsync(ckp + 2 * ff, f.px, size_t(ff) * 4, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(ckp + 3 * ff, f.pz, size_t(ff) * 4, hipMemcpyDeviceToDevice, c->stream));
+        }
         return FWI_OK;
     }
     // one segment per time loop, so that the captured loops repeat
@@ -1399,10 +1476,11 @@ int backward_sweep(fwi_ctx *c, const float *v, Sweep &w, float *img)
     int rc;
     if ((rc = other(c, launch_fill(w.A[0], 4 * ff, 0.f, st), "fill"))) return rc;
     if ((rc = other(c, launch_fill(w.G, gf, 0.f, st), "fill"))) return rc;
+    if ((rc = ensure_psi(c)) || (rc = zero_psi(c, PSI_ADJ))) return rc;
     SweepOps ops{c, w, base_args(c, v, K_FWD), base_args(c, v, K_ADJ), static_cast<float *>(c->samples.p),
-                 Fields{w.F[0], w.F[1], w.F[2], w.F[3]},
+                 with_psi(Fields{w.F[0], w.F[1], w.F[2], w.F[3]}, psi_block(c, PSI_FWD), ff),
                  // lambda^{n+2} (prev) and lambda^{n+1} (cur), both zero at the start
-                 Fields{w.A[0], w.A[1], w.A[2], w.A[3]}};
+                 with_psi(Fields{w.A[0], w.A[1], w.A[2], w.A[3]}, psi_block(c, PSI_ADJ), ff)};
     ops.a.G = w.G;
     std::vector<int> free = revolve_free(w.slots);
     if ((rc = revolve(ops, w.nseg, 0, w.nseg, -1, free))) return rc;
@@ -1505,6 +1583,17 @@ int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_o
     b.samp2 = b.samp + p.Q;
     b.inj = b.samp;
     b.inj2 = b.samp2;
+    if (float *P = psi_block(c, PSI_FWD)) {   // zeroed trial edge fields
+        float *Q = psi_block(c, PSI_SCAT);
+        b.psx_in = P;
+        b.psz_in = P + ff;
+        b.psx_out = P + 2 * ff;
+        b.psz_out = P + 3 * ff;
+        b.psx2_in = Q;
+        b.psz2_in = Q + ff;
+        b.psx2_out = Q + 2 * ff;
+        b.psz2_out = Q + 3 * ff;
+    }
     // the forward class is timed as the forward of a gradient or migration
     // (emitting D), its most frequent and heaviest form
     const int flags = cls == K_ADJ ? (F_INJECT | F_IMAGE) : (F_SRC | F_SAMPLE | F_EMIT);
@@ -1550,6 +1639,8 @@ int ensure_tilings(fwi_ctx *c, const float *v)
         const int want_tb = one_level(k) ? 1 : (forced ? c->force_tb[k] : (c->autotune ? 0 : kDefaultTb));
         if (want_tb == 2 && p.free_surface)
             return set_err(c, FWI_EINVAL, "two-level tilings do not support a free surface (force one level)");
+        if (want_tb == 2 && p.pml)
+            return set_err(c, FWI_EINVAL, "two-level tilings do not support the PML (force one level)");
         const int want_pd = forced ? c->force_pd[k] : kDefaultPd;
         if (want_cw && want_rows && want_tb) {
             if (t.cw == want_cw && t.rows == want_rows && t.tb == want_tb && t.pd == want_pd) continue;
@@ -1570,7 +1661,8 @@ int ensure_tilings(fwi_ctx *c, const float *v)
     int rc = FWI_OK;
     if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
         (rc = ensure(c, c->dhist, size_t((kTuneSlots + 1) * gf) * 4)) ||
-        (rc = ensure(c, c->samples, size_t(nq) * 4)))
+        (rc = ensure(c, c->samples, size_t(nq) * 4)) || (rc = ensure_psi(c)) || (rc = zero_psi(c, PSI_FWD)) ||
+        (rc = zero_psi(c, PSI_SCAT)))
         return rc;
     if ((rc = other(c, launch_fill(static_cast<float *>(c->fields.p), 4 * ff, 0.f, c->stream), "fill")) ||
         (rc = other(c, launch_fill(static_cast<float *>(c->image.p), gf, 0.f, c->stream), "fill")) ||
@@ -1590,7 +1682,7 @@ int ensure_tilings(fwi_ctx *c, const float *v)
             build_tiling(p, cand.cw, cand.rows, cand.tb, cand.pd, trial);
             if ((rc = upload_tiling(c, trial))) break;
             for (int k = 0; k < kClasses; ++k) {
-                if (c->tile[k].cw != 0 || ((one_level(k) || p.free_surface) && cand.tb != 1) ||
+                if (c->tile[k].cw != 0 || ((one_level(k) || p.free_surface || p.pml) && cand.tb != 1) ||
                     (k == K_BORN && cand.pd != 1))
                     continue;
                 float ms = 0.f;
@@ -1646,13 +1738,13 @@ int forward_sweep_sampled(fwi_ctx *c, const float *v)
     const int64_t ff = p.field_floats;
     int rc;
     if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) ||
-        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)))
+        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)) || (rc = ensure_psi(c)))
         return rc;
     float *F = static_cast<float *>(c->fields.p);
     float *samp = static_cast<float *>(c->samples.p);
-    if ((rc = other(c, launch_fill(F, 4 * ff, 0.f, c->stream), "fill"))) return rc;
+    if ((rc = other(c, launch_fill(F, 4 * ff, 0.f, c->stream), "fill")) || (rc = zero_psi(c, PSI_FWD))) return rc;
     StepArgs a = base_args(c, v, K_FWD);
-    Fields f{F, F + ff, F + 2 * ff, F + 3 * ff};
+    Fields f = with_psi(Fields{F, F + ff, F + 2 * ff, F + 3 * ff}, psi_block(c, PSI_FWD), ff);
     if ((rc = ev_begin(c, K_FWD))) return rc;
     if ((rc = forward_range(c, a, 0, p.nt_max, true, samp, false, nullptr, 0, f))) return rc;
     return ev_end(c);
@@ -1679,7 +1771,11 @@ int born_range(fwi_ctx *c, const StepArgs &a, int lo, int hi, float *samp, float
     key_put(key, U1);
     key_put(key, D0);
     key_put(key, D1);
+    key_put(key, c->psi.p);
     Fields none{};
+    // the layer's edge fields alternate by step parity as the fields do
+    float *PU = psi_block(c, PSI_FWD), *PD = psi_block(c, PSI_SCAT);
+    const int64_t ff = p.field_floats;
     return run_loop(c, key, none, [&](Fields &) {
         StepArgs b = a;
         for (int n = lo; n < hi; ++n) {
@@ -1689,6 +1785,17 @@ int born_range(fwi_ctx *c, const StepArgs &a, int lo, int hi, float *samp, float
             b.prev = n % 2 == 0 ? U1 : U0;
             b.cur2 = n % 2 == 0 ? D0 : D1;
             b.prev2 = n % 2 == 0 ? D1 : D0;
+            if (PU) {
+                const int64_t i = n % 2 == 0 ? 0 : 2 * ff, o = n % 2 == 0 ? 2 * ff : 0;
+                b.psx_in = PU + i;
+                b.psz_in = PU + i + ff;
+                b.psx_out = PU + o;
+                b.psz_out = PU + o + ff;
+                b.psx2_in = PD + i;
+                b.psz2_in = PD + i + ff;
+                b.psx2_out = PD + o;
+                b.psz2_out = PD + o + ff;
+            }
             b.samp = samp + size_t(n) * p.Q;
             b.dslot = dh ? dh + size_t(n - dlo) * gf : nullptr;
             HIPCHK(c, launch_born_step(b, c->stream));
@@ -1757,10 +1864,11 @@ int pair_core(fwi_ctx *c, const float *v0, const float *dv, float *dd, float *im
     if ((rc = choose_segments(c, w))) return rc;
     const int k = w.k, nseg = w.nseg;
     const int64_t ff = p.field_floats, gf = p.img_floats;
+    const int sf = snap_fields(p);
     if ((rc = ensure(c, c->fields, size_t(8 * ff) * 4)) || (rc = ensure(c, c->image, size_t(gf) * 4)) ||
         (rc = ensure(c, c->dhist, size_t(k) * gf * 4)) ||
-        (rc = ensure(c, c->ckpt, size_t(w.slots) * 2 * ff * 4)) ||
-        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)) ||
+        (rc = ensure(c, c->ckpt, size_t(w.slots) * sf * ff * 4)) ||
+        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)) || (rc = ensure_psi(c)) ||
         (!dd && (rc = ensure(c, c->pairdata, size_t(std::max<int64_t>(p.data_size, 1)) * 4))))
         return rc;
     float *F = static_cast<float *>(c->fields.p);
@@ -1773,19 +1881,26 @@ int pair_core(fwi_ctx *c, const float *v0, const float *dv, float *dd, float *im
     w.G = static_cast<float *>(c->image.p);
     float *samp = static_cast<float *>(c->samples.p);
     hipStream_t st = c->stream;
-    if ((rc = other(c, launch_fill(w.F[0], 4 * ff, 0.f, st), "fill"))) return rc;
+    if ((rc = other(c, launch_fill(w.F[0], 4 * ff, 0.f, st), "fill")) || (rc = zero_psi(c, PSI_FWD)) ||
+        (rc = zero_psi(c, PSI_SCAT)))
+        return rc;
     StepArgs a = base_args(c, v0, K_BORN);
     a.dv = dv;
     float *U0 = w.F[0], *U1 = w.F[1], *D0 = w.F[2], *D1 = w.F[3];
+    float *PU = psi_block(c, PSI_FWD);
     if ((rc = ev_begin(c, K_BORN))) return rc;
     for (int sgi = 0; sgi < nseg; ++sgi) {
         const int lo = sgi * k, hi = std::min(p.nt_max, lo + k);
         const bool last = sgi == nseg - 1;
         if (w.spine[size_t(sgi)] >= 0) {
-            // (u^{lo-1}, u^lo): the fields the step at n = lo reads as prev, cur
-            float *ckp = w.CK + size_t(w.spine[size_t(sgi)]) * 2 * ff;
+            // (u^{lo-1}, u^lo): the fields the step at n = lo reads as prev,
+            // cur (and the edge fields it reads)
+            float *ckp = w.CK + size_t(w.spine[size_t(sgi)]) * sf * ff;
             HIPCHK(c, hipMemcpyAsync(ckp, lo % 2 == 0 ? U1 : U0, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
             HIPCHK(c, hipMemcpyAsync(ckp + ff, lo % 2 == 0 ? U0 : U1, size_t(ff) * 4, hipMemcpyDeviceToDevice, st));
+            if (PU)
+                HIPCHK(c, hipMemcpyAsync(ckp + 2 * ff, PU + (lo % 2 == 0 ? 0 : 2 * ff), size_t(2 * ff) * 4,
+                                         hipMemcpyDeviceToDevice, st));
         }
         if ((rc = born_range(c, a, lo, hi, samp, last ? w.Dh : nullptr, lo, U0, U1, D0, D1))) return rc;
     }
@@ -1829,10 +1944,16 @@ int scat_range(fwi_ctx *c, const StepArgs &a, int lo, int hi, float *samp, float
             b.nwaves = c->tile[K_SCAT].prefix[p.active_slots(n)];
             b.cur = ff.cur;
             b.prev = ff.prev;
+            b.psx_in = ff.px;
+            b.psz_in = ff.pz;
+            b.psx_out = ff.qx;
+            b.psz_out = ff.qz;
             b.samp = samp + size_t(n) * p.Q;
             b.dslot = dh + size_t(n - dlo) * gf;
             HIPCHK(c, launch_step(F_SAMPLE | F_SCAT, b, c->stream));
             std::swap(ff.prev, ff.cur);
+            std::swap(ff.px, ff.qx);
+            std::swap(ff.pz, ff.qz);
             const double upd = step_updates(p, n);
             c->stats.cell_updates += upd;
             c->stats.stencil_launches += 1;
@@ -1894,13 +2015,13 @@ class ArenaScope {
     ArenaScope &operator=(const ArenaScope &) = delete;
 
    private:
-    static constexpr size_t kBufs = 23;
+    static constexpr size_t kBufs = 24;
     std::array<DevBuf *, kBufs> bufs()
     {
         fwi_ctx *c = c_;
         return {&c->d_shots, &c->d_qnt, &c->d_qrptr, &c->d_qroff, &c->d_wav, &c->d_qrw, &c->d_rcptr, &c->d_rcq,
                 &c->d_rnt, &c->d_rcw, &c->d_roff, &c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt,
-                &c->partials, &c->misfit, &c->check, &c->pairdata, &c->resid, &c->model, &c->dmodel};
+                &c->partials, &c->misfit, &c->check, &c->pairdata, &c->resid, &c->model, &c->dmodel, &c->psi};
     }
     fwi_ctx *c_;
     DevBuf saved_[kBufs];
@@ -1957,7 +2078,7 @@ void fwi_ctx_destroy(fwi_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (Tiling &t : c->tile) t.release_all();
-    for (DevBuf *b : {&c->d_qrw, &c->d_rcptr, &c->d_rcq, &c->d_rnt, &c->d_rcw, &c->d_roff, &c->resid})
+    for (DevBuf *b : {&c->d_qrw, &c->d_rcptr, &c->d_rcq, &c->d_rnt, &c->d_rcw, &c->d_roff, &c->resid, &c->psi})
         release(*b);
     for (DevBuf *b : {&c->d_shots, &c->d_qnt, &c->d_qrptr, &c->d_qroff, &c->d_wav, &c->fields, &c->samples,
                       &c->image, &c->dhist, &c->ckpt, &c->partials, &c->misfit, &c->check, &c->model, &c->dmodel,
@@ -2057,7 +2178,7 @@ int fwi_ctx_trim(fwi_ctx *c)
     if (hipStreamSynchronize(c->stream) != hipSuccess) return FWI_EHIP;
     clear_graphs(c);
     for (DevBuf *b : {&c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt, &c->partials, &c->model, &c->dmodel,
-                      &c->pairdata})
+                      &c->pairdata, &c->psi})
         release(*b);
     return FWI_OK;
 }
@@ -2139,10 +2260,11 @@ int fwi_gradient_pair(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const 
     const int64_t ff = p.field_floats;
     float *samp = static_cast<float *>(c->samples.p);
     if (!dd && (rc = ensure(c, c->pairdata, size_t(std::max<int64_t>(p.data_size, 1)) * 4))) return rc;
-    if ((rc = other(c, launch_fill(w.F[0], 2 * ff, 0.f, c->stream), "fill"))) return rc;
+    if ((rc = other(c, launch_fill(w.F[0], 2 * ff, 0.f, c->stream), "fill")) || (rc = zero_psi(c, PSI_SCAT)))
+        return rc;
     StepArgs a = base_args(c, mv, K_SCAT);
     a.dv = dv;
-    Fields f{w.F[0], w.F[1], w.F[2], w.F[3]};
+    Fields f = with_psi(Fields{w.F[0], w.F[1], w.F[2], w.F[3]}, psi_block(c, PSI_SCAT), ff);
     if ((rc = ev_begin(c, K_BORN))) return rc;
     if ((rc = scat_range(c, a, 0, p.nt_max, samp, w.Dh, 0, f))) return rc;
     if ((rc = ev_end(c))) return rc;
@@ -2206,11 +2328,13 @@ int born_demig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *
         return rc;
     const int64_t ff = p.field_floats;
     if ((rc = ensure(c, c->fields, size_t(4 * ff) * 4)) ||
-        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)))
+        (rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)) || (rc = ensure_psi(c)))
         return rc;
     float *F = static_cast<float *>(c->fields.p);
     float *samp = static_cast<float *>(c->samples.p);
-    if ((rc = other(c, launch_fill(F, 4 * ff, 0.f, c->stream), "fill"))) return rc;
+    if ((rc = other(c, launch_fill(F, 4 * ff, 0.f, c->stream), "fill")) || (rc = zero_psi(c, PSI_FWD)) ||
+        (rc = zero_psi(c, PSI_SCAT)))
+        return rc;
     StepArgs a = base_args(c, v0, K_BORN);
     a.dv = dv;
     float *U0 = F, *U1 = F + ff, *D0 = F + 2 * ff, *D1 = F + 3 * ff;

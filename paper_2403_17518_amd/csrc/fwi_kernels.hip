@@ -214,11 +214,144 @@ __device__ __forceinline__ void bst_stream(Rsrc r, unsigned lane_off, int row_of
     if (ok[0]) raw_st_f32(v[0], r, int(lane_off), row_off, kStream);
 }
 
+// ---- perfectly matched layer ---------------------------------------------
+// The layer adds to the Laplacian the divergence of two edge fields: psi_x on
+// the x edges (i, j+1/2), stored at column j, and psi_z on the z edges
+// (i+1/2, j), stored at row i, each advanced from its previous level by the
+// recursive convolution psi^n = b psi^{n-1} + (e - d) g (u^n across the edge)
+// / h, where d is the damping along the edge's own axis (at the edge), e the
+// damping along the other axis (at the edge's row or column), b = exp(-d dt),
+// g = (1 - b) / d (dt where d = 0); and -d_x d_z dt^2 u^n to the update. A
+// wave computes the edges it owns (the right and lower edge of each cell)
+// and recomputes, from the previous level, the edge left of its strip and the
+// edge above its first row, which neighbouring waves own: every edge value is
+// formed from the same operands in the same order whichever wave forms it.
+
+// Squared depth into the layer, in half cells, of the position m half cells
+// along an axis of n cells with a layer of lo cells at the low end and nb at
+// the high end; the damping there is smax (depth / nb)^2 = hd0 * m2 with
+// hd0 = smax / (4 nb^2). Dampings are formed from these integers, and the
+// difference of two dampings as hd0 * (m2 - m2'), exactly: a difference of
+// two rounded products would leave the compiler free to fuse one of them
+// into the subtraction, which rounds differently where both are non-zero
+// (the corners), and differently in different kernels.
+__device__ __forceinline__ int pml_m2(int m, int n, int lo, int nb)
+{
+    const int d = max(max(2 * lo - m, m - 2 * (n - 1 - nb)), 0);
+    return d * d;
+}
+
+__device__ __forceinline__ void pml_rec(float d, float dt, float &b, float &g)
+{
+    b = expf(-d * dt);
+    g = d > 0.f ? -expm1f(-d * dt) / d : dt;
+}
+
+// new value of an edge from its previous value; ed = e - d, du = u(after) -
+// u(before) across the edge
+__device__ __forceinline__ float pml_edge(float old, float b, float g, float ed, float du, float ih)
+{
+    return __builtin_fmaf(b, old, (ed * g) * (du * ih));
+}
+
+// Per-lane layer coefficients of a strip's columns: damping of the column
+// (cell) and of its right edge with that edge's recursion, and the recursion
+// of the edge left of the lane's first column.
+template <int CW>
+struct PmlCols {
+    int mxc[CW], mxe[CW], mxl;  // squared half-cell depths: column, right edge, left edge
+    float dxc[CW], bxe[CW], gxe[CW];
+    bool xok[CW];               // the right edge lies inside the box
+    float bxl, gxl;
+    bool lok;                   // the left edge lies inside the box
+    __device__ __forceinline__ void init(const StepArgs &A, int j0, int NX)
+    {
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            const int j = j0 + k;
+            mxc[k] = pml_m2(2 * j, NX, A.nb, A.nb);
+            mxe[k] = pml_m2(2 * j + 1, NX, A.nb, A.nb);
+            dxc[k] = A.hd0 * float(mxc[k]);
+            pml_rec(A.hd0 * float(mxe[k]), A.dt, bxe[k], gxe[k]);
+            xok[k] = j + 1 < NX;
+        }
+        mxl = pml_m2(2 * j0 - 1, NX, A.nb, A.nb);
+        pml_rec(A.hd0 * float(mxl), A.dt, bxl, gxl);
+        lok = j0 >= 1;
+    }
+};
+
+// Per-row layer coefficients: depth and damping of row z (cell), depth of
+// the edge below it and that edge's recursion.
+struct PmlRow {
+    int mzc, mze;
+    float dzc, bze, gze;
+    bool zok;                   // the edge below lies inside the box
+    __device__ __forceinline__ void init(const StepArgs &A, int z)
+    {
+        mzc = pml_m2(2 * z, A.NZ, A.top, A.nb);
+        mze = pml_m2(2 * z + 1, A.NZ, A.top, A.nb);
+        dzc = A.hd0 * float(mzc);
+        pml_rec(A.hd0 * float(mze), A.dt, bze, gze);
+        zok = z >= 0 && z + 1 < A.NZ;
+    }
+};
+
+// Rows whose cells read a non-zero edge field in a strip without layer
+// columns: the layer rows and the first row below / last row above them.
+__device__ __forceinline__ bool pml_row(const StepArgs &A, int z)
+{
+    return z <= A.top || z >= A.NZ - 1 - A.nb;
+}
+
+// Strips whose columns reach the layer or the column next to it.
+template <int CW>
+__device__ __forceinline__ bool pml_strip(const StepArgs &A, int col0, int NX)
+{
+    return col0 <= A.nb || col0 + kLanes * CW - 1 >= NX - 1 - A.nb;
+}
+
+// One row of the layer terms of a field: new edge values from the previous
+// ones (own right and lower edges; for lane 0 the edge left of the strip;
+// the edge above comes from `up`, the previous row's lower edges), and
+// div[k], the edge differences that divided by h give the divergence (the
+// caller adds div * (1/h) to the Laplacian as one fused multiply-add, so that
+// every kernel rounds it alike); up[] becomes this row's lower edges.
+template <int CW>
+__device__ __forceinline__ void pml_row_terms(const StepArgs &A, const PmlCols<CW> &C, const PmlRow &R, int lane,
+                                              const float (&q)[9][CW], const float *xr, const float (&px)[CW],
+                                              const float (&pz)[CW], float pxl, float (&nx)[CW], float (&nz)[CW],
+                                              float (&up)[CW], float (&div)[CW])
+{
+    const float ih = A.ih;
+#pragma unroll
+    for (int k = 0; k < CW; ++k) {
+        const float c = q[4][k];
+        // x edge: e = d_z of the row, d = d_x of the edge; z edge: e = d_x of
+        // the column, d = d_z of the edge
+        nx[k] = C.xok[k] ? pml_edge(px[k], C.bxe[k], C.gxe[k], A.hd0 * float(R.mzc - C.mxe[k]), xr[k + 5] - c, ih)
+                         : 0.f;
+        nz[k] = R.zok ? pml_edge(pz[k], R.bze, R.gze, A.hd0 * float(C.mxc[k] - R.mze), q[5][k] - c, ih) : 0.f;
+    }
+    // the edge left of each column: the previous column's right edge, for
+    // the lane's first column from the lane to the left, for lane 0 formed
+    // here from the previous level
+    float left = __shfl_up(nx[CW - 1], 1, kLanes);
+    if (lane == 0)
+        left = C.lok ? pml_edge(pxl, C.bxl, C.gxl, A.hd0 * float(R.mzc - C.mxl), q[4][0] - xr[3], ih) : 0.f;
+#pragma unroll
+    for (int k = 0; k < CW; ++k) {
+        const float l = k == 0 ? left : nx[k - 1];
+        div[k] = (nx[k] - l) + (nz[k] - up[k]);
+        up[k] = nz[k];
+    }
+}
+
 // One time level of every active shot. Each lane owns CW adjacent columns of
 // a 64*CW-column strip and streams down the rows [z0, z1) of that strip; the
 // loads of rows z+1 .. z+PD are issued before row z is computed so that PD+1
 // rows of memory traffic are in flight per wave.
-template <int FL, int CW, int PD>
+template <int FL, int CW, int PD, bool PML>
 __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs A)
 {
     constexpr int SW = kLanes * CW;          // strip width
@@ -269,6 +402,26 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     // negative; the row offset of the load is lowered by as much)
     const unsigned hcol = 4u * unsigned(lane == 0 ? W.col0 : min(W.col0 + SW, P - kHalo) + kHalo);
 
+    // perfectly matched layer: edge fields in the field layout
+    PmlCols<CW> pc;
+    bool pstrip = false;
+    Rsrc rpxi = rv, rpzi = rv, rpxo = rv, rpzo = rv;
+    float pup[CW], pup_old[CW];
+    const unsigned jleft = 4u * unsigned(max(W.col0 - 1, 0));
+    if constexpr (PML) {
+        pc.init(A, j0, S.NX);
+        pstrip = pml_strip<CW>(A, W.col0, S.NX);
+        const int64_t fb = S.f_off - int64_t(kRowsAbove) * P;
+        rpxi = view(A.psx_in + fb);
+        rpzi = view(A.psz_in + fb);
+        rpxo = view(A.psx_out + fb);
+        rpzo = view(A.psz_out + fb);
+#pragma unroll
+        for (int k = 0; k < CW; ++k) pup[k] = pup_old[k] = 0.f;
+        // the edges above the first row, owned by the wave above
+        if ((pstrip || pml_row(A, W.z0)) && W.z0 >= 1) bld<CW>(rpzi, jl, 4 * (W.z0 - 1 + kRowsAbove) * P, pup_old);
+    }
+
     float q[9][CW];
 #pragma unroll
     for (int r = 0; r < 8; ++r) bld<CW>(rcur, jl, 4 * (W.z0 - kHalo + r + kRowsAbove) * P, q[r]);
@@ -277,6 +430,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     // being computed (a ring of PD statically indexed slots)
     struct Pre {
         float q[CW], pv[CW], v[CW], d[CW], g[CW], dv[CW];
+        float px[CW], pz[CW], pxl;
         float4 h;
     };
     auto prefetch = [&](int z, Pre &pre) {
@@ -296,6 +450,13 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
             bld_stream<CW>(rd, jl, 4 * z * P, pre.d);
 #pragma unroll
             for (int k = 0; k < CW; ++k) pre.dv[k] = bld1(rdv, jm[k], vo);
+        }
+        if constexpr (PML) {
+            if (pstrip || pml_row(A, z)) {
+                bld<CW>(rpxi, jl, ro, pre.px);
+                bld<CW>(rpzi, jl, ro, pre.pz);
+                pre.pxl = lane == 0 ? bld1(rpxi, jleft, ro) : 0.f;
+            }
         }
     };
 
@@ -334,10 +495,37 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
         }
         const int ddz = max(max(A.top - z, z - (A.NZ - 1 - nb)), 0);
         const float dz2 = float(ddz * ddz);
+        // layer terms of this row: edge divergence and d_x d_z dt^2
+        float pdiv[CW], pnx[CW], pnz[CW], fdt2[CW];
+        bool prow = false;
+        if constexpr (PML) {
+            prow = pstrip || pml_row(A, z);
+            if (prow) {
+                PmlRow pr;
+                pr.init(A, z);
+                if (z == W.z0 && z >= 1) {
+                    // the edges above the first row, from their previous level
+                    PmlRow pu;
+                    pu.init(A, z - 1);
+#pragma unroll
+                    for (int k = 0; k < CW; ++k)
+                        pup[k] = pml_edge(pup_old[k], pu.bze, pu.gze, A.hd0 * float(pc.mxc[k] - pu.mze),
+                                          q[4][k] - q[3][k], A.ih);
+                }
+                pml_row_terms<CW>(A, pc, pr, lane, q, xr, c.px, c.pz, c.pxl, pnx, pnz, pup, pdiv);
+#pragma unroll
+                for (int k = 0; k < CW; ++k) fdt2[k] = (pc.dxc[k] * pr.dzc) * A.dt2;
+            } else {
+#pragma unroll
+                for (int k = 0; k < CW; ++k) pup[k] = 0.f;
+            }
+        }
         float out[CW], Dv[CW];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             float lap = lap8(q, xr, k, A.w1, A.w2, A.w3, A.w4);
+            if constexpr (PML)
+                if (prow) lap = __builtin_fmaf(pdiv[k], A.ih, lap);
             if (FL & F_SRC) lap = add_source<CW>(lap, wsrc, z, S.src_i, sw0, sw1, k);
             if (FL & F_INJECT)
                 if (qi[k] >= 0) lap += A.inj[qi[k]];
@@ -354,11 +542,24 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
                 const float rho = A.rel ? 2.0f * c.dv[k] : 2.0f * c.dv[k] / c.v[k];
                 Dv[k] = __builtin_fmaf(rho, c.d[k], Dv[k]);
             }
-            out[k] = leapfrog(q[4][k], c.pv[k], Dv[k], a, sh);
+            float Du = Dv[k];
+            if constexpr (PML)
+                if (prow) Du = __builtin_fmaf(-fdt2[k], q[4][k], Du);
+            out[k] = leapfrog(q[4][k], c.pv[k], Du, a, sh);
             if (A.fs && z == 0) out[k] = 0.0f;   // the pressure-free surface
         }
         const int ro = 4 * (z + kRowsAbove) * P, go = 4 * z * P;
         if (FL & F_EMIT) bst_stream<CW>(rd, js, go, Dv, valid);
+        if constexpr (PML) {
+            if (prow) {
+#pragma unroll
+                for (int k = 0; k < CW; ++k)
+                    if (valid[k]) {
+                        bst1(rpxo, js + 4 * k, ro, pnx[k]);
+                        bst1(rpzo, js + 4 * k, ro, pnz[k]);
+                    }
+            }
+        }
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             if (valid[k]) {
@@ -660,7 +861,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 // EMIT the background's D^n = V^2 dt^2 (L8 u^n + s^n) is also written to the
 // D slot (the same value the forward step emits), so that a migration can
 // follow without a separate background sweep.
-template <int CW, bool EMIT>
+template <int CW, bool EMIT, bool PML>
 __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const StepArgs A)
 {
     constexpr int SW = kLanes * CW;
@@ -702,6 +903,31 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
     // halo columns (byte offset shifted up by 4 columns, row offset lowered)
     const unsigned hcol = 4u * unsigned(lane == 0 ? W.col0 : min(W.col0 + SW, P - kHalo) + kHalo);
 
+    // perfectly matched layer: edge fields of u (psx, psz) and du (psx2, psz2)
+    PmlCols<CW> pc;
+    bool pstrip = false;
+    Rsrc rpxi = rv, rpzi = rv, rpxo = rv, rpzo = rv, rqxi = rv, rqzi = rv, rqxo = rv, rqzo = rv;
+    float pup[CW], pup_old[CW], qup[CW], qup_old[CW];
+    const unsigned jleft = 4u * unsigned(max(W.col0 - 1, 0));
+    if constexpr (PML) {
+        pc.init(A, j0, S.NX);
+        pstrip = pml_strip<CW>(A, W.col0, S.NX);
+        rpxi = view(A.psx_in + base);
+        rpzi = view(A.psz_in + base);
+        rpxo = view(A.psx_out + base);
+        rpzo = view(A.psz_out + base);
+        rqxi = view(A.psx2_in + base);
+        rqzi = view(A.psz2_in + base);
+        rqxo = view(A.psx2_out + base);
+        rqzo = view(A.psz2_out + base);
+#pragma unroll
+        for (int k = 0; k < CW; ++k) pup[k] = pup_old[k] = qup[k] = qup_old[k] = 0.f;
+        if ((pstrip || pml_row(A, W.z0)) && W.z0 >= 1) {
+            bld<CW>(rpzi, jl, 4 * (W.z0 - 1 + kRowsAbove) * P, pup_old);
+            bld<CW>(rqzi, jl, 4 * (W.z0 - 1 + kRowsAbove) * P, qup_old);
+        }
+    }
+
     float q[9][CW], r[9][CW];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -709,6 +935,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
         bld<CW>(rcd, jl, 4 * (W.z0 - kHalo + k + kRowsAbove) * P, r[k]);
     }
     float nq[CW], nr[CW], npv[CW], npd[CW], nv[CW], ndv[CW];
+    float npx[CW], npz[CW], nqx[CW], nqz[CW], npxl = 0.f, nqxl = 0.f;
     float4 nh = make_float4(0.f, 0.f, 0.f, 0.f), nhd = nh;
     auto prefetch = [&](int z) {
         const int ro = 4 * (z + kRowsAbove) * P;
@@ -726,6 +953,16 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
             nv[k] = bld1(rv, jm[k], vo);
             ndv[k] = bld1(rdv, jm[k], vo);
         }
+        if constexpr (PML) {
+            if (pstrip || pml_row(A, z)) {
+                bld<CW>(rpxi, jl, ro, npx);
+                bld<CW>(rpzi, jl, ro, npz);
+                bld<CW>(rqxi, jl, ro, nqx);
+                bld<CW>(rqzi, jl, ro, nqz);
+                npxl = lane == 0 ? bld1(rpxi, jleft, ro) : 0.f;
+                nqxl = lane == 0 ? bld1(rqxi, jleft, ro) : 0.f;
+            }
+        }
     };
     prefetch(W.z0);
 
@@ -738,6 +975,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
 
     for (int z = W.z0; z < W.z1; ++z) {
         float cpv[CW], cpd[CW], cv[CW], cdv[CW];
+        float cpx[CW], cpz[CW], cqx[CW], cqz[CW];
+        const float cpxl = npxl, cqxl = nqxl;
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             q[8][k] = nq[k];
@@ -746,6 +985,10 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
             cpd[k] = npd[k];
             cv[k] = nv[k];
             cdv[k] = ndv[k];
+            cpx[k] = npx[k];
+            cpz[k] = npz[k];
+            cqx[k] = nqx[k];
+            cqz[k] = nqz[k];
         }
         const float4 ch = nh, chd = nhd;
         if (z + 1 < W.z1) prefetch(z + 1);
@@ -782,11 +1025,44 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
         }
         const int ddz = max(max(A.top - z, z - (A.NZ - 1 - nb)), 0);
         const float dz2 = float(ddz * ddz);
+        // layer terms of this row for both fields
+        float pdiv[CW], pnx[CW], pnz[CW], qdiv[CW], qnx[CW], qnz[CW], fdt2[CW];
+        bool prow = false;
+        if constexpr (PML) {
+            prow = pstrip || pml_row(A, z);
+            if (prow) {
+                PmlRow pr;
+                pr.init(A, z);
+                if (z == W.z0 && z >= 1) {
+                    PmlRow pu;
+                    pu.init(A, z - 1);
+#pragma unroll
+                    for (int k = 0; k < CW; ++k) {
+                        const float ed = A.hd0 * float(pc.mxc[k] - pu.mze);
+                        pup[k] = pml_edge(pup_old[k], pu.bze, pu.gze, ed, q[4][k] - q[3][k], A.ih);
+                        qup[k] = pml_edge(qup_old[k], pu.bze, pu.gze, ed, r[4][k] - r[3][k], A.ih);
+                    }
+                }
+                pml_row_terms<CW>(A, pc, pr, lane, q, xr, cpx, cpz, cpxl, pnx, pnz, pup, pdiv);
+                pml_row_terms<CW>(A, pc, pr, lane, r, xd, cqx, cqz, cqxl, qnx, qnz, qup, qdiv);
+#pragma unroll
+                for (int k = 0; k < CW; ++k) fdt2[k] = (pc.dxc[k] * pr.dzc) * A.dt2;
+            } else {
+#pragma unroll
+                for (int k = 0; k < CW; ++k) pup[k] = qup[k] = 0.f;
+            }
+        }
         float ou[CW], od[CW], Dv[CW];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             float lap = lap8(q, xr, k, A.w1, A.w2, A.w3, A.w4);
-            const float lapd = lap8(r, xd, k, A.w1, A.w2, A.w3, A.w4);
+            float lapd = lap8(r, xd, k, A.w1, A.w2, A.w3, A.w4);
+            if constexpr (PML) {
+                if (prow) {
+                    lap = __builtin_fmaf(pdiv[k], A.ih, lap);
+                    lapd = __builtin_fmaf(qdiv[k], A.ih, lapd);
+                }
+            }
             lap = add_source<CW>(lap, wsrc, z, S.src_i, sw0, sw1, k);
             const float c = cv[k] * cv[k] * A.dt2;
             // (2 dV / V) V^2 dt^2, or 2 dm V^2 dt^2 for a relative dm
@@ -797,12 +1073,31 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
                 a = sponge_a(sh);
             }
             Dv[k] = c * lap;
-            ou[k] = leapfrog(q[4][k], cpv[k], Dv[k], a, sh);
-            od[k] = leapfrog(r[4][k], cpd[k], __builtin_fmaf(cr, lap, c * lapd), a, sh);
+            float Du = Dv[k], Dd = __builtin_fmaf(cr, lap, c * lapd);
+            if constexpr (PML) {
+                if (prow) {
+                    Du = __builtin_fmaf(-fdt2[k], q[4][k], Du);
+                    Dd = __builtin_fmaf(-fdt2[k], r[4][k], Dd);
+                }
+            }
+            ou[k] = leapfrog(q[4][k], cpv[k], Du, a, sh);
+            od[k] = leapfrog(r[4][k], cpd[k], Dd, a, sh);
             if (A.fs && z == 0) ou[k] = od[k] = 0.0f;   // the pressure-free surface
         }
         const int o = 4 * (z + kRowsAbove) * P;
         if (EMIT) bst_stream<CW>(rd, js, 4 * z * P, Dv, valid);
+        if constexpr (PML) {
+            if (prow) {
+#pragma unroll
+                for (int k = 0; k < CW; ++k)
+                    if (valid[k]) {
+                        bst1(rpxo, js + 4 * k, o, pnx[k]);
+                        bst1(rpzo, js + 4 * k, o, pnz[k]);
+                        bst1(rqxo, js + 4 * k, o, qnx[k]);
+                        bst1(rqzo, js + 4 * k, o, qnz[k]);
+                    }
+            }
+        }
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             if (valid[k]) {
@@ -1062,28 +1357,28 @@ inline int blocks_for(int nwaves) { return (nwaves + kWavesPerBlock - 1) / kWave
 
 }  // namespace
 
-template <int CW, int PD>
+template <int CW, int PD, bool PML>
 hipError_t launch_step_cw(int flags, const StepArgs &a, hipStream_t s)
 {
     const dim3 grid(blocks_for(a.nwaves)), block(kLanes * kWavesPerBlock);
     switch (flags) {
     case F_SRC | F_SAMPLE:
-        hipLaunchKernelGGL((k_step<F_SRC | F_SAMPLE, CW, PD>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SRC | F_SAMPLE, CW, PD, PML>), grid, block, 0, s, a);
         break;
     case F_SRC:
-        hipLaunchKernelGGL((k_step<F_SRC, CW, PD>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SRC, CW, PD, PML>), grid, block, 0, s, a);
         break;
     case F_SRC | F_SAMPLE | F_EMIT:
-        hipLaunchKernelGGL((k_step<F_SRC | F_SAMPLE | F_EMIT, CW, PD>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SRC | F_SAMPLE | F_EMIT, CW, PD, PML>), grid, block, 0, s, a);
         break;
     case F_SRC | F_EMIT:
-        hipLaunchKernelGGL((k_step<F_SRC | F_EMIT, CW, PD>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SRC | F_EMIT, CW, PD, PML>), grid, block, 0, s, a);
         break;
     case F_INJECT | F_IMAGE:
-        hipLaunchKernelGGL((k_step<F_INJECT | F_IMAGE, CW, PD>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_INJECT | F_IMAGE, CW, PD, PML>), grid, block, 0, s, a);
         break;
     case F_SAMPLE | F_SCAT:
-        hipLaunchKernelGGL((k_step<F_SAMPLE | F_SCAT, CW, PD>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step<F_SAMPLE | F_SCAT, CW, PD, PML>), grid, block, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1091,11 +1386,18 @@ hipError_t launch_step_cw(int flags, const StepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <bool PML>
+hipError_t launch_step_pml(int flags, const StepArgs &a, hipStream_t s)
+{
+    if (a.pd == 2)
+        return a.cw == 2 ? launch_step_cw<2, 2, PML>(flags, a, s) : launch_step_cw<1, 2, PML>(flags, a, s);
+    return a.cw == 2 ? launch_step_cw<2, 1, PML>(flags, a, s) : launch_step_cw<1, 1, PML>(flags, a, s);
+}
+
 hipError_t launch_step(int flags, const StepArgs &a, hipStream_t s)
 {
     if (a.nwaves <= 0) return hipSuccess;
-    if (a.pd == 2) return a.cw == 2 ? launch_step_cw<2, 2>(flags, a, s) : launch_step_cw<1, 2>(flags, a, s);
-    return a.cw == 2 ? launch_step_cw<2, 1>(flags, a, s) : launch_step_cw<1, 1>(flags, a, s);
+    return a.pml ? launch_step_pml<true>(flags, a, s) : launch_step_pml<false>(flags, a, s);
 }
 
 template <int CW>
@@ -1130,18 +1432,24 @@ hipError_t launch_step2(int flags, const StepArgs &a, hipStream_t s)
     return a.cw == 2 ? launch_step2_cw<2>(flags, a, s) : launch_step2_cw<1>(flags, a, s);
 }
 
+template <bool PML>
+hipError_t launch_born_step_pml(const StepArgs &a, hipStream_t s)
+{
+    const dim3 grid(blocks_for(a.nwaves)), block(kLanes * kWavesPerBlock);
+    if (a.dslot) {
+        if (a.cw == 2) hipLaunchKernelGGL((k_born_step<2, true, PML>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_born_step<1, true, PML>), grid, block, 0, s, a);
+    } else {
+        if (a.cw == 2) hipLaunchKernelGGL((k_born_step<2, false, PML>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_born_step<1, false, PML>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_born_step(const StepArgs &a, hipStream_t s)
 {
     if (a.nwaves <= 0) return hipSuccess;
-    const dim3 grid(blocks_for(a.nwaves)), block(kLanes * kWavesPerBlock);
-    if (a.dslot) {
-        if (a.cw == 2) hipLaunchKernelGGL((k_born_step<2, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_born_step<1, true>), grid, block, 0, s, a);
-    } else {
-        if (a.cw == 2) hipLaunchKernelGGL((k_born_step<2, false>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_born_step<1, false>), grid, block, 0, s, a);
-    }
-    return hipGetLastError();
+    return a.pml ? launch_born_step_pml<true>(a, s) : launch_born_step_pml<false>(a, s);
 }
 
 hipError_t launch_scale(const float *x, float a, float *y, int64_t n, hipStream_t s)

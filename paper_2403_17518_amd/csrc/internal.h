@@ -102,6 +102,19 @@ struct StepArgs {
     float *samp2;              // ... of the second level
     const float *inj2;
     float *dslot2;
+    // perfectly matched layer (pml != 0): edge fields of the field (psx: x
+    // edges (i, j+1/2) at column j; psz: z edges (i+1/2, j) at row i) in the
+    // field layout, read at level n-1 and written at level n, and those of
+    // the second (Born) field; damping d = hd0 m^2 at a position of m half
+    // cells into the layer
+    int32_t pml;
+    float hd0;                 // smax / (4 nb^2)
+    float dt;
+    float ih;                  // 1 / h
+    const float *psx_in, *psz_in;
+    float *psx_out, *psz_out;
+    const float *psx2_in, *psz2_in;
+    float *psx2_out, *psz2_out;
 };
 
 // Time-major <-> trace-major conversion, residual and misfit.

@@ -50,8 +50,8 @@ static int run_fd(int argc, char **argv)
     if (!f) return 2;
     fwi_grid g{};
     int S = 0, has_win = 0, has_nt = 0, shared = 1, has_frac = 0;
-    if (std::fscanf(f, "%d %d %d %f %f %d %f %f %d %d %d %d %d %d", &g.nz, &g.nx, &g.nb, &g.h, &g.dt, &g.nt_max,
-                    &g.v_ref, &g.R, &S, &has_win, &has_nt, &shared, &has_frac, &g.free_surface) != 14)
+    if (std::fscanf(f, "%d %d %d %f %f %d %f %f %d %d %d %d %d %d %d", &g.nz, &g.nx, &g.nb, &g.h, &g.dt, &g.nt_max,
+                    &g.v_ref, &g.R, &S, &has_win, &has_nt, &shared, &has_frac, &g.free_surface, &g.pml) != 15)
         return 2;
     std::vector<int32_t> sz(S), sx(S), wx0(S), wnx(S), nt(S), rz, rx;
     std::vector<float> sfz(S), sfx(S), rfz, rfx;
@@ -115,10 +115,20 @@ static int run_fd(int argc, char **argv)
             if (nf != 5 && nf != 6) return 2;
             CK(fwi_ctx_set_tiling(c, -1, cw, rows, tb, pd));
             CK(fwi_ctx_set_ckpt_slots(c, slots));
+            // optional tilings of single kernel classes: EMU_TILING_<class>="cw,rows,levels,prefetch"
+            for (int k = 0; k < 4; ++k) {
+                char name[32];
+                std::snprintf(name, sizeof name, "EMU_TILING_%d", k);
+                if (const char *e = std::getenv(name)) {
+                    int t[4] = {0, 0, 0, 0};
+                    if (std::sscanf(e, "%d,%d,%d,%d", &t[0], &t[1], &t[2], &t[3]) == 4)
+                        CK(fwi_ctx_set_tiling(c, k, t[0], t[1], t[2], t[3]));
+                }
+            }
         }
         g.ckpt_every = ck;
         float *v0 = dev<float>(nm), *vt = dev<float>(nm), *grad = dev<float>(nm), *img = dev<float>(nm);
-        float *grad2 = dev<float>(nm), *img2 = dev<float>(nm);
+        float *grad2 = dev<float>(nm), *img2 = dev<float>(nm), *img3 = dev<float>(nm);
         float *dobs = dev<float>(size_t(ndata)), *dd = dev<float>(size_t(ndata)), *dsyn = dev<float>(size_t(ndata));
         std::memcpy(v0, hv0.data(), nm * 4);
         std::memcpy(vt, hvt.data(), nm * 4);
@@ -132,7 +142,7 @@ static int run_fd(int argc, char **argv)
         }
         CK(fwi_gradient_pair(c, &g, &geo, v0, dobs, grad, &phi, -1.f, img, dd));
         CK(fwi_gradient(c, &g, &geo, v0, dobs, grad2, &phi, dsyn));
-        CK(born_pair(c, &g, &geo, v0, grad, dd, img2));
+        CK(born_pair(c, &g, &geo, v0, grad, dd, img3));
         CK(born_demig(c, &g, &geo, v0, grad, dd));
         CK(born_mig(c, &g, &geo, v0, dd, img2));
         fwi_stats st{};
@@ -149,11 +159,13 @@ static int run_fd(int argc, char **argv)
             }
             return (unsigned long long)h;
         };
-        std::printf("ok %s tile_fwd=%d,%d,%d,%d segments=%d slots=%d recomputed=%lld hash=%016llx,%016llx,%016llx\n",
+        std::printf("ok %s tile_fwd=%d,%d,%d,%d segments=%d slots=%d recomputed=%lld "
+                    "hash=%016llx,%016llx,%016llx,%016llx\n",
                     spec.c_str(), st.tile_cw[0], st.tile_rows[0], st.tile_levels[0], st.tile_prefetch[0],
-                    st.n_segments, st.ckpt_slots, (long long)st.recomputed_steps, fnv(grad), fnv(grad2), fnv(img2));
+                    st.n_segments, st.ckpt_slots, (long long)st.recomputed_steps, fnv(grad), fnv(grad2), fnv(img2),
+                    fnv(img3));
         std::fflush(stdout);
-        for (float *p : {v0, vt, grad, img, grad2, img2, dobs, dd, dsyn}) std::free(p);
+        for (float *p : {v0, vt, grad, img, grad2, img2, img3, dobs, dd, dsyn}) std::free(p);
         fwi_ctx_destroy(c);
         g_ctx = nullptr;
     }

@@ -76,6 +76,13 @@ inline T __shfl_xor(T v, int mask, int width = 64)
     return emu_shfl(v, int(threadIdx.x & 63) ^ mask);
 }
 template <class T>
+inline T __shfl_up(T v, unsigned d, int width = 64)
+{
+    const int lane = int(threadIdx.x & 63);
+    const int s = lane - int(d);
+    return emu_shfl(v, s >= 0 ? s : lane);
+}
+template <class T>
 inline T __shfl_down(T v, unsigned d, int width = 64)
 {
     const int lane = int(threadIdx.x & 63);

@@ -120,7 +120,8 @@ def _write_geom(path, grid, acq, v0, vt):
     wav = np.asarray(acq.wavelet)
     frac = acq.src_fz is not None
     lines = [f"{grid.nz} {grid.nx} {grid.nb} {grid.h} {grid.dt} {grid.nt_max} {grid.v_ref} {grid.R} "
-             f"{S} {int(has_win)} {int(has_nt)} {int(wav.ndim == 1)} {int(frac)} {int(grid.free_surface)}"]
+             f"{S} {int(has_win)} {int(has_nt)} {int(wav.ndim == 1)} {int(frac)} {int(grid.free_surface)} "
+             f"{int(grid.pml)}"]
     for s in range(S):
         r0, r1 = int(acq.rec_ptr[s]), int(acq.rec_ptr[s + 1])
         x0 = int(acq.win_x0[s]) if has_win else 0
@@ -196,6 +197,20 @@ def free_surface_geometry(nt_max: int = 8):
     return replace(grid, free_surface=True), acq, v0, vt
 
 
+def pml_geometry(nt_max: int = 8):
+    """The off-grid edge geometry with a perfectly matched layer."""
+    from dataclasses import replace
+    grid, acq, v0, vt = offgrid_geometry(nt_max)
+    return replace(grid, pml=True), acq, v0, vt
+
+
+def pml_free_surface_geometry(nt_max: int = 8):
+    """The layer on three sides under a pressure-free top surface."""
+    from dataclasses import replace
+    grid, acq, v0, vt = offgrid_geometry(nt_max)
+    return replace(grid, pml=True, free_surface=True), acq, v0, vt
+
+
 def _ragged(nt_max: int = 8):
     wl = configs.ragged_small()
     g = wl.grid
@@ -217,27 +232,38 @@ def test_edge_geometry_has_receiverless_last_waves():
     assert int(acq.win_nx[last]) == grid.nx
 
 
-@pytest.mark.parametrize("geom", ["edge", "ragged", "offgrid", "free_surface"])
+@pytest.mark.parametrize("geom", ["edge", "ragged", "offgrid", "free_surface", "pml", "pml_free_surface"])
 def test_step_kernels_in_bounds_every_tiling(emu_driver, tmp_path, geom):
     grid, acq, v0, vt = {"edge": edge_geometry, "ragged": _ragged, "offgrid": offgrid_geometry,
-                         "free_surface": free_surface_geometry}[geom]()
+                         "free_surface": free_surface_geometry, "pml": pml_geometry,
+                         "pml_free_surface": pml_free_surface_geometry}[geom]()
     path = str(tmp_path / "geom.txt")
     _write_geom(path, grid, acq, v0, vt)
-    # a free surface runs one level per launch
-    specs = [t for t in TILINGS if not grid.free_surface or t == "auto" or t.split(",")[2] == "1"]
+    # a free surface or a layer runs one level per launch
+    one = grid.free_surface or grid.pml
+    specs = [t for t in TILINGS if not one or t == "auto" or t.split(",")[2] == "1"]
     out = _run_parallel(emu_driver, ["fd", path], specs)
     assert out.count("ok ") == len(specs), out
+    # every tiling computes each cell with the same arithmetic: one set of bits
+    hashes = {l.split("hash=")[1] for l in out.splitlines() if l.startswith("ok ")}
+    assert len(hashes) == 1, out
 
 
-def test_checkpoint_schedules_give_the_same_bits(emu_driver, tmp_path):
+@pytest.mark.parametrize("pml", [False, True])
+def test_checkpoint_schedules_give_the_same_bits(emu_driver, tmp_path, pml):
     """Gradients and migrated images are the same bits with the whole
     history stored, uniform checkpoints, and binomial schedules down to no
-    snapshot at all (every segment recomputed from the zero state)."""
+    snapshot at all (every segment recomputed from the zero state); with the
+    layer the snapshots carry its edge fields."""
+    from dataclasses import replace
     grid, acq, v0, vt = _ragged()
+    grid = replace(grid, pml=pml)
     path = str(tmp_path / "geom.txt")
     _write_geom(path, grid, acq, v0, vt)
     groups = {"1,24,1,1": ["0", "3", "1", "1,0", "1,1", "1,3", "2,0"],
               "1,24,2,1": ["0", "3", "1,0", "1,2"]}
+    if pml:
+        del groups["1,24,2,1"]
     specs = [f"{t},{c}" for t, cs in groups.items() for c in cs]
     out = _run_parallel(emu_driver, ["fd", path], specs)
     lines = [l for l in out.splitlines() if l.startswith("ok ")]
