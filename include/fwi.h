@@ -275,6 +275,19 @@ int born_demig(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
 int born_mig(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom,
              const float *v0, const float *dd, float *img);
 
+/* RTM image of observed data in the model v, the image product with which
+ * the paper compares inverted models (section 3.3): img = Lap5(J^T (M
+ * d_obs)), where M mutes the direct arrival and Lap5 y = 4 y - (its four
+ * neighbours), zero outside [nz][nx], suppresses the low-wavenumber
+ * backscatter of the cross-correlation image. The mute weights sample n
+ * (time n dt) of the trace of receiver r by 0 up to t0 = |x_r - x_s| h /
+ * mute_v + mute_pad (positions with their off-grid offsets), then by a
+ * half-cosine ramp over mute_taper seconds, then by 1; mute_v = 0 skips it.
+ * v, img: device [nz][nx]; d_obs: device packed traces. FWI_EINVAL for a
+ * negative or non-finite mute velocity or taper. */
+int fwi_rtm(fwi_ctx *ctx, const fwi_grid *grid, const fwi_geom *geom, const float *v, const float *d_obs,
+            float mute_v, float mute_pad, float mute_taper, float *img);
+
 /* img = J^T J dv, the doubly migrated image of section 2.3 eq. 15 (the
  * Gauss-Newton Hessian applied to dv), and optionally dd = J dv (NULL to
  * skip). One joint Born sweep supplies both the data and the background

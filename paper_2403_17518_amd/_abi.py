@@ -94,6 +94,8 @@ SIGNATURES = {
     "fwi_misfit": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, C.POINTER(C.c_double)]),
     "born_demig": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P]),
     "born_mig": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P]),
+    "fwi_rtm": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, C.c_float, C.c_float, C.c_float,
+                          _P]),
     "born_pair": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P, _P]),
     "fwi_gradient_pair": (C.c_int, [_P, C.POINTER(fwi_grid), C.POINTER(fwi_geom), _P, _P, _P,
                                     C.POINTER(C.c_double), C.c_float, _P, _P]),

@@ -171,6 +171,12 @@ struct fwi_ctx {
     // of the scattered field and of the adjoint field, four field-sized
     // buffers each (x and z at two levels)
     DevBuf psi;
+    // RTM image product: muted data, the migrated image before the filter,
+    // and the per-trace mute table (host copies kept until the next call)
+    DevBuf rtm_data, rtm_img, d_mute_off, d_mute_nt, d_mute_t0;
+    std::vector<int64_t> h_mute_off;
+    std::vector<int32_t> h_mute_nt;
+    std::vector<float> h_mute_t0;
     // copies of the call's model and perturbation: the time loops read these,
     // never the caller's buffers, so captured loops stay valid across calls
     DevBuf model, dmodel;
@@ -2082,7 +2088,7 @@ void fwi_ctx_destroy(fwi_ctx *c)
         release(*b);
     for (DevBuf *b : {&c->d_shots, &c->d_qnt, &c->d_qrptr, &c->d_qroff, &c->d_wav, &c->fields, &c->samples,
                       &c->image, &c->dhist, &c->ckpt, &c->partials, &c->misfit, &c->check, &c->model, &c->dmodel,
-                      &c->pairdata})
+                      &c->pairdata, &c->rtm_data, &c->rtm_img, &c->d_mute_off, &c->d_mute_nt, &c->d_mute_t0})
         release(*b);
     clear_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -2178,7 +2184,7 @@ int fwi_ctx_trim(fwi_ctx *c)
     if (hipStreamSynchronize(c->stream) != hipSuccess) return FWI_EHIP;
     clear_graphs(c);
     for (DevBuf *b : {&c->fields, &c->samples, &c->image, &c->dhist, &c->ckpt, &c->partials, &c->model, &c->dmodel,
-                      &c->pairdata, &c->psi})
+                      &c->pairdata, &c->psi, &c->rtm_data, &c->rtm_img})
         release(*b);
     return FWI_OK;
 }
@@ -2382,6 +2388,68 @@ int born_mig(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v0
     Sweep w;
     if ((rc = forward_for_adjoint(c, v0, false, w))) return rc;
     if ((rc = backward_sweep(c, v0, w, img))) return rc;
+    return finish_stats(c);
+}
+
+int fwi_rtm(fwi_ctx *c, const fwi_grid *g, const fwi_geom *geo, const float *v, const float *d_obs, float mute_v,
+            float mute_pad, float mute_taper, float *img)
+{
+    int rc = begin_call(c, g, geo);
+    if (rc) return rc;
+    const Plan &p = c->plan;
+    if (!img) return set_err(c, FWI_EINVAL, "img is NULL");
+    if (!d_obs && p.data_size > 0) return set_err(c, FWI_EINVAL, "d_obs is NULL");
+    if (!std::isfinite(mute_v) || !std::isfinite(mute_pad) || !std::isfinite(mute_taper) || mute_v < 0.f ||
+        mute_taper < 0.f)
+        return set_err(c, FWI_EINVAL, "mute: velocity and taper must be finite and >= 0 (velocity 0 = no mute)");
+    if ((rc = check_model(c, v, "v")) || (rc = prepare(c, v))) return rc;
+    const float *src = d_obs;
+    if (mute_v > 0.f && p.data_size > 0) {
+        // per-trace table: offset in the packed data, length, mute time
+        HIPCHK(c, hipStreamSynchronize(c->stream));   // the previous table may still be in flight
+        c->h_mute_off.clear();
+        c->h_mute_nt.clear();
+        c->h_mute_t0.clear();
+        int64_t off = 0;
+        for (int s = 0; s < geo->nshots; ++s) {
+            const int32_t nt = geo->nt ? geo->nt[s] : g->nt_max;
+            const double sz = geo->src_z[s] + (geo->src_fz ? geo->src_fz[s] : 0.f);
+            const double sx = geo->src_x[s] + (geo->src_fx ? geo->src_fx[s] : 0.f);
+            for (int64_t r = geo->rec_ptr[s]; r < geo->rec_ptr[s + 1]; ++r) {
+                const double rz = geo->rec_z[r] + (geo->rec_fz ? geo->rec_fz[r] : 0.f);
+                const double rx = geo->rec_x[r] + (geo->rec_fx ? geo->rec_fx[r] : 0.f);
+                c->h_mute_off.push_back(off);
+                c->h_mute_nt.push_back(nt);
+                c->h_mute_t0.push_back(float(std::hypot(rz - sz, rx - sx) * g->h / mute_v + mute_pad));
+                off += nt;
+            }
+        }
+        if ((rc = upload(c, c->d_mute_off, c->h_mute_off)) || (rc = upload(c, c->d_mute_nt, c->h_mute_nt)) ||
+            (rc = upload(c, c->d_mute_t0, c->h_mute_t0)) ||
+            (rc = ensure(c, c->rtm_data, size_t(p.data_size) * 4)))
+            return rc;
+        if ((rc = other(c,
+                        launch_mute(static_cast<const int64_t *>(c->d_mute_off.p),
+                                    static_cast<const int32_t *>(c->d_mute_nt.p),
+                                    static_cast<const float *>(c->d_mute_t0.p), int32_t(c->h_mute_t0.size()),
+                                    g->dt, mute_taper, d_obs, static_cast<float *>(c->rtm_data.p), c->stream),
+                        "mute")))
+            return rc;
+        src = static_cast<const float *>(c->rtm_data.p);
+    }
+    if ((rc = ensure(c, c->samples, size_t(p.nt_max) * p.Q * 4)) ||
+        (rc = ensure(c, c->rtm_img, size_t(g->nz) * g->nx * 4)))
+        return rc;
+    TraceArgs t = trace_args(c);
+    t.tr_in = src;
+    t.beta = 1.f;
+    t.tm_out = static_cast<float *>(c->samples.p);
+    if ((rc = other(c, launch_traces(t, c->stream, nullptr), "adjoint sources"))) return rc;
+    Sweep w;
+    if ((rc = forward_for_adjoint(c, v, false, w))) return rc;
+    float *mig = static_cast<float *>(c->rtm_img.p);
+    if ((rc = backward_sweep(c, v, w, mig))) return rc;
+    if ((rc = other(c, launch_laplace5(mig, g->nz, g->nx, img, c->stream), "laplacian"))) return rc;
     return finish_stats(c);
 }
 

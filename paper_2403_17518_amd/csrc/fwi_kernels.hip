@@ -1132,6 +1132,37 @@ __global__ void k_fill(float *p, int64_t n, float val)
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = val;
 }
 
+// Direct-arrival mute of packed traces (the RTM image product, section 3.3):
+// sample n (time n dt) of trace r is weighted by 0 up to t0[r], by a
+// half-cosine ramp over the taper, then by 1. One block per trace at a time.
+__global__ __launch_bounds__(256) void k_mute(const int64_t *off, const int32_t *nt, const float *t0, int32_t ntr,
+                                              float dt, float itaper, const float *din, float *dout)
+{
+    for (int r = blockIdx.x; r < ntr; r += gridDim.x) {
+        const int64_t o = off[r];
+        const int32_t n_r = nt[r];
+        const float t0r = t0[r];
+        for (int n = threadIdx.x; n < n_r; n += blockDim.x) {
+            const float u = fminf(fmaxf((float(n) * dt - t0r) * itaper, 0.f), 1.f);
+            dout[o + n] = din[o + n] * (0.5f - 0.5f * cospif(u));
+        }
+    }
+}
+
+// y = -(d2/dz2 + d2/dx2) x in grid units: the 5-point Laplacian with zero
+// outside the image, [nz][nx] row-major.
+__global__ __launch_bounds__(256) void k_laplace5(const float *x, int32_t nz, int32_t nx, float *y)
+{
+    const int64_t n = int64_t(nz) * nx;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int z = int(i / nx), xj = int(i - int64_t(z) * nx);
+        const float up = z > 0 ? x[i - nx] : 0.f, dn = z + 1 < nz ? x[i + nx] : 0.f;
+        const float lf = xj > 0 ? x[i - 1] : 0.f, rt = xj + 1 < nx ? x[i + 1] : 0.f;
+        y[i] = 4.f * x[i] - ((up + dn) + (lf + rt));
+    }
+}
+
 // min, max and count of non-finite or non-positive entries of v.
 __global__ __launch_bounds__(256) void k_model_check(const float *v, int64_t n, float *out3)
 {
@@ -1467,6 +1498,26 @@ hipError_t launch_fill(float *p, int64_t n, float val, hipStream_t s)
     int64_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_fill, dim3(unsigned(blocks)), dim3(256), 0, s, p, n, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_mute(const int64_t *off, const int32_t *nt, const float *t0, int32_t ntr, float dt, float taper,
+                       const float *din, float *dout, hipStream_t s)
+{
+    if (ntr <= 0) return hipSuccess;
+    const int blocks = ntr < 8192 ? ntr : 8192;
+    hipLaunchKernelGGL(k_mute, dim3(unsigned(blocks)), dim3(256), 0, s, off, nt, t0, ntr, dt,
+                       1.f / fmaxf(taper, 1e-12f), din, dout);
+    return hipGetLastError();
+}
+
+hipError_t launch_laplace5(const float *x, int32_t nz, int32_t nx, float *y, hipStream_t s)
+{
+    const int64_t n = int64_t(nz) * nx;
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_laplace5, dim3(unsigned(blocks)), dim3(256), 0, s, x, nz, nx, y);
     return hipGetLastError();
 }
 

@@ -170,6 +170,12 @@ hipError_t launch_fill(float *p, int64_t n, float val, hipStream_t s);
 // y = a x (n floats)
 hipError_t launch_scale(const float *x, float a, float *y, int64_t n, hipStream_t s);
 hipError_t launch_model_check(const float *v, int64_t n, float *out3, hipStream_t s);
+// dout[off[r] + n] = din[off[r] + n] * mute weight of sample n of trace r
+// (ntr traces, nt[r] samples, ramp from t0[r] over `taper` seconds)
+hipError_t launch_mute(const int64_t *off, const int32_t *nt, const float *t0, int32_t ntr, float dt, float taper,
+                       const float *din, float *dout, hipStream_t s);
+// y = 4 x - (its four neighbours), zero outside [nz][nx]
+hipError_t launch_laplace5(const float *x, int32_t nz, int32_t nx, float *y, hipStream_t s);
 // Writes per-block misfit partials when a.partials is set; their count
 // goes to *nblocks_out (at most traces_partials_max(Q, nt_max)).
 hipError_t launch_traces(const TraceArgs &a, hipStream_t s, int64_t *nblocks_out);

@@ -413,17 +413,16 @@ def rtm_scores(fctx, grid, acq, wl, fmax, finals, observe) -> dict:
     the true model) of the RTM image of each final model and of the initial
     model, from the highest band's observed data with the direct arrival
     muted; the top 10 rows (source/receiver footprint) are left out."""
-    from .rtm import direct_mute, image_score, rtm_image
+    from .rtm import image_score, rtm_image
     acq_b = band_acq(acq, grid, fmax)
     d_obs = observe(acq_b)
     w = np.abs(np.asarray(acq_b.wavelet, np.float64))
     t_peak = float(np.argmax(w)) * grid.dt
-    mask = torch.from_numpy(direct_mute(grid, acq_b, float(np.min(wl.v0[0])), t_peak + 1.0 / fmax,
-                                        0.5 / fmax)).to(d_obs.device)
+    mute = (float(np.min(wl.v0[0])), t_peak + 1.0 / fmax, 0.5 / fmax)
     dev = d_obs.device
-    ref = rtm_image(fctx, grid, acq_b, torch.from_numpy(wl.v_true.astype(np.float32)).to(dev), d_obs, mask)
+    ref = rtm_image(fctx, grid, acq_b, torch.from_numpy(wl.v_true.astype(np.float32)).to(dev), d_obs, *mute)
     models = {"initial": torch.from_numpy(wl.v0.astype(np.float32)).to(dev), **finals}
-    return {name: round(image_score(rtm_image(fctx, grid, acq_b, v, d_obs, mask), ref, top=10), 4)
+    return {name: round(image_score(rtm_image(fctx, grid, acq_b, v, d_obs, *mute), ref, top=10), 4)
             for name, v in models.items()}
 
 

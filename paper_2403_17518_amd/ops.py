@@ -189,6 +189,21 @@ class FwiContext:
                                                      C.c_void_p(img.data_ptr())))
         return img
 
+    def rtm(self, grid, acq, v, d_obs, mute_v: float = 0.0, mute_pad: float = 0.0,
+            mute_taper: float = 0.0) -> torch.Tensor:
+        """RTM image: the 5-point Laplacian (4 x - neighbours) of J^T of the
+        observed data with the direct arrival muted (mute_v > 0: zero before
+        offset / mute_v + mute_pad, half-cosine ramp over mute_taper s)."""
+        v = self._model(v, "v", grid)
+        d_obs = self._data(d_obs, "d_obs", self._data_size(grid, acq))
+        img = torch.empty((grid.nz, grid.nx), device=self.device, dtype=torch.float32)
+        g, gv = self._prep(grid, acq)
+        _check(self.lib, self.ctx, self.lib.fwi_rtm(self.ctx, C.byref(g), C.byref(gv.geom),
+                                                    C.c_void_p(v.data_ptr()), C.c_void_p(d_obs.data_ptr()),
+                                                    float(mute_v), float(mute_pad), float(mute_taper),
+                                                    C.c_void_p(img.data_ptr())))
+        return img
+
     def born_pair(self, grid, acq, v0, g_in, want_dd: bool = False):
         """J^T J g_in, the doubly migrated image (paper section 2.3 eq. 15),
         from one joint Born sweep; with want_dd also J g_in: (img, dd)."""

@@ -145,6 +145,7 @@ static int run_fd(int argc, char **argv)
         CK(born_pair(c, &g, &geo, v0, grad, dd, img3));
         CK(born_demig(c, &g, &geo, v0, grad, dd));
         CK(born_mig(c, &g, &geo, v0, dd, img2));
+        CK(fwi_rtm(c, &g, &geo, v0, dobs, 1500.f, 0.01f, 0.02f, img));
         fwi_stats st{};
         fwi_ctx_get_stats(c, &st);
         CK(fwi_misfit(c, &g, &geo, v0, dobs, &phi));

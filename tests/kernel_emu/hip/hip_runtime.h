@@ -50,6 +50,7 @@ void *emu_dyn_shared();
 #define __builtin_amdgcn_fence(a, b) ((void)0)
 #define __builtin_amdgcn_readfirstlane(x) (x)
 #define __builtin_amdgcn_rcpf(x) (1.0f / (x))
+inline float cospif(float x) { return float(std::cos(3.14159265358979323846 * double(x))); }
 template <class A, class B, class C>
 inline C emu_mfma(const A &a, const B &b, const C &c)
 {
