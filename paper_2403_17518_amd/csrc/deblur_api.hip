@@ -65,8 +65,22 @@ struct deblur_net {
     Buf xin, a, cat, eD, pool, c, d, y32, t32;       // forward activations
     Buf da, dcat, deD, dpool, dc, dd, dy32;         // gradients
     Buf wpart, bpart, lpart, loss_dev, hyper, scal, kpart;
+    // the weight tensors whose data-gradient matrices Adam refreshes
+    // (device AuxSeg table, sorted by parameter offset), and the host copy
+    Buf segs;
+    std::vector<AuxSeg> h_segs;
+    int64_t aux_tiles = 0;   // transpose tiles over all weight tensors
+    Buf amax;   // per-block maxima of absmax
     std::vector<int64_t> a_off, cat_off, pool_off, c_off, d_off;  // per level offsets (elements)
     int64_t wpart_max = 0, bpart_max = 0;
+    // each weight gradient of a backward pass takes its own stretch of wpart
+    // and bpart (cursors reset per pass), so that the second passes of all of
+    // them run as one launch at the end of the pass: their arguments (fin),
+    // the blocks of 64 outputs before each (fin_begin), and the device copies
+    int64_t wp_cursor = 0, bp_cursor = 0;
+    std::vector<WgradArgs> fin, fin_dev_copy;
+    std::vector<int64_t> fin_begin, fin_beg_copy;
+    Buf fin_tab, fin_beg;
     int nblk0 = 0;
     // training run in progress (deblur_train_range): the next step of a
     // schedule of run_total steps at run_lr; run_next < 0 = none
@@ -198,23 +212,22 @@ void build_layout(deblur_net *n)
     n->nparam += 1;
 }
 
-// pixels per split and split count of a weight-gradient reduction
-void wsplit(int M, int N, int P, int *nsplit, int *chunk, int *tile)
+// output tile, pixels per split and split count of a weight-gradient
+// reduction: the tile's height follows M (32, 64 or 128 rows), its width is
+// 128 unless N is narrower; pixel splits (at least 256 pixels each) fill the
+// GPU up to 512 workgroups
+void wsplit(int M, int N, int P, int *nsplit, int *chunk, int *bm, int *bn)
 {
-    // output tile of the weight-gradient kernel: 128 x 128 when the layer is
-    // wide enough to give at least 512 workgroups that way, else 64 x 64;
-    // pixel splits fill the GPU up to 512 workgroups
-    auto splits = [&](int t) {
-        const int tiles = ((M + t - 1) / t) * ((N + t - 1) / t);
-        return std::pair<int, int>(tiles, std::max(1, std::min((512 + tiles - 1) / tiles, std::max(1, P / 256))));
-    };
-    const auto w128 = splits(128);
-    const int t = (M >= 128 && N >= 128 && w128.first * w128.second >= 512) ? 128 : 64;
-    int ns = splits(t).second;
-    *tile = t;
+    int tm = M <= 32 ? 32 : (M <= 64 ? 64 : 128);
+    int tn = 128;
+    if (N <= 64 || (tm == 64 && N < 128)) tm = 64, tn = 64;
+    const int tiles = ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
+    int ns = std::max(1, std::min((512 + tiles - 1) / tiles, std::max(1, P / 256)));
     int ch = (P + ns - 1) / ns;
     ch = ((ch + 63) / 64) * 64;
     ns = (P + ch - 1) / ch;
+    *bm = tm;
+    *bn = tn;
     *nsplit = ns;
     *chunk = ch;
 }
@@ -261,43 +274,31 @@ int alloc_buffers(deblur_net *n)
         (rc = alloc(n, n->dpool, size_t(sp) * 2)) || (rc = alloc(n, n->dc, size_t(scc) * 2)) ||
         (rc = alloc(n, n->dd, size_t(sd) * 2)) || (rc = alloc(n, n->dy32, size_t(P0) * 4)))
         return rc;
-    // scratch of the weight- and bias-gradient reductions
+    // scratch of the weight- and bias-gradient reductions: one stretch per
+    // layer of a backward pass (the sum over the layers)
     int64_t wmax = 0, bmax = 0;
     auto acc_w = [&](int M, int N, int P) {
-        int ns, ch, tile;
-        wsplit(M, N, P, &ns, &ch, &tile);
-        wmax = std::max(wmax, int64_t(ns) * M * N);
-        bmax = std::max(bmax, int64_t(ns) * M);
+        int ns, ch, bm, bn;
+        wsplit(M, N, P, &ns, &ch, &bm, &bn);
+        wmax += int64_t(ns) * M * N;
+        bmax += int64_t(ns) * std::max(M, N);   // bias partials from A ([ns][M]) or B ([ns][N])
     };
-    auto acc_b = [&](int C, int P) {
-        const int ns = std::max(1, std::min(256, P / 1024));
-        bmax = std::max(bmax, int64_t(ns) * C);
-    };
-    for (int k = 0; k < 2; ++k) {
-        acc_w(n->inc[k].cout, 9 * n->inc[k].cin, n->P[0]);
-        acc_b(n->inc[k].cout, n->P[0]);
-    }
+    acc_w(n->inc[1].cout, 9 * n->inc[1].cin, n->P[0]);
     for (int l = 1; l <= D; ++l)
-        for (const ConvL *L : {&n->down1[l], &n->down2[l]}) {
-            acc_w(L->cout, 9 * L->cin, n->P[l]);
-            acc_b(L->cout, n->P[l]);
-        }
+        for (const ConvL *L : {&n->down1[l], &n->down2[l]}) acc_w(L->cout, 9 * L->cin, n->P[l]);
     for (int l = 0; l < D; ++l) {
-        for (const ConvL *L : {&n->up1[l], &n->up2[l]}) {
-            acc_w(L->cout, 9 * L->cin, n->P[l]);
-            acc_b(L->cout, n->P[l]);
-        }
+        for (const ConvL *L : {&n->up1[l], &n->up2[l]}) acc_w(L->cout, 9 * L->cin, n->P[l]);
         acc_w(n->upT[l].cin, 4 * n->upT[l].cout, n->P[l + 1]);
-        acc_b(n->upT[l].cout, n->P[l]);
     }
-    wmax = std::max(wmax, int64_t((P0 + 255) / 256) * (n->C[0] + 1));  // output-conv partials
+    wmax += int64_t((P0 + 255) / 256) * (n->C[0] + 1);   // output-conv partials
+    wmax += int64_t(512) * n->C[0] * 10;                  // input-layer partials
     n->wpart_max = wmax;
     if ((rc = alloc(n, n->kpart, size_t(kGemmSplitFloats) * 4))) return rc;
     n->bpart_max = bmax;
     n->nblk0 = int((P0 + 255) / 256);
     if ((rc = alloc(n, n->wpart, size_t(wmax) * 4)) || (rc = alloc(n, n->bpart, size_t(bmax) * 4)) ||
         (rc = alloc(n, n->lpart, size_t(std::max<int64_t>(n->nblk0 * int64_t(n->C[0] + 1), n->nblk0)) * 8)) ||
-        (rc = alloc(n, n->scal, 64)))
+        (rc = alloc(n, n->scal, 64)) || (rc = alloc(n, n->amax, size_t(kAbsmaxBlocks) * 4)))
         return rc;
     return FWI_OK;
 }
@@ -390,20 +391,8 @@ void internal_to_torch(const deblur_net *n, const float *src, float *dst)
 int refresh_weights(deblur_net *n, hipStream_t st)
 {
     HCK(n, to_bf16(P_<float>(n->params), P_<bf16>(n->pbf), n->nparam, st));
-    auto flip = [&](const ConvL &L) {
-        return weight_flip(P_<float>(n->params, L.w), L.cout, L.cin, P_<bf16>(n->aux, L.aux), st);
-    };
-    for (int k = 0; k < 2; ++k) HCK(n, flip(n->inc[k]));
-    for (int l = 1; l <= n->D; ++l) {
-        HCK(n, flip(n->down1[l]));
-        HCK(n, flip(n->down2[l]));
-    }
-    for (int l = 0; l < n->D; ++l) {
-        HCK(n, flip(n->up1[l]));
-        HCK(n, flip(n->up2[l]));
-        const ConvL &T = n->upT[l];
-        HCK(n, convt_dgrad_weights(P_<float>(n->params, T.w), T.cin, T.cout, P_<bf16>(n->aux, T.aux), st));
-    }
+    HCK(n, aux_from_pb(static_cast<const AuxSeg *>(n->segs.p), int32_t(n->h_segs.size()), n->aux_tiles,
+                       P_<bf16>(n->pbf), P_<bf16>(n->aux), st));
     return FWI_OK;
 }
 
@@ -478,7 +467,7 @@ int conv_fwd(deblur_net *n, const ConvL &L, const bf16 *src, int ld, int coff, i
 // dsrc = data gradient of a 3x3 conv given dz (the gradient at its
 // pre-activation output)
 int conv_dgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff, int lvl, bf16 *dsrc, int ld,
-               int coff, hipStream_t st)
+               int coff, const bf16 *act_y, hipStream_t st)
 {
     GemmArgs a{};
     a.kpart = P_<float>(n->kpart);
@@ -493,10 +482,69 @@ int conv_dgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff,
     a.out_ld = ld;
     a.out_coff = coff;
     a.Cout = L.cin;
+    // act_y (the activated input of this layer, same layout as dsrc): the
+    // result is the gradient at the pre-activation of the layer below
+    a.act_y = act_y;
+    a.act_ld = ld;
+    a.act_coff = coff;
+    a.slope = n->cfg.leaky_slope;
     int rc = prof_begin(n, L.name, 1, a.M, a.N, a.K, st);
     if (rc) return rc;
     HCK(n, gemm(a, st));
     return prof_end(n, st);
+}
+
+// the next stretch of the weight- / bias-gradient scratch (nullptr past the end)
+float *take_w(deblur_net *n, int64_t floats)
+{
+    if (n->wp_cursor + floats > n->wpart_max) return nullptr;
+    float *p = P_<float>(n->wpart, n->wp_cursor);
+    n->wp_cursor += floats;
+    return p;
+}
+
+float *take_b(deblur_net *n, int64_t floats)
+{
+    if (n->bp_cursor + floats > n->bpart_max) return nullptr;
+    float *p = P_<float>(n->bpart, n->bp_cursor);
+    n->bp_cursor += floats;
+    return p;
+}
+
+void defer_finish(deblur_net *n, const WgradArgs &w)
+{
+    const int64_t cnt = wgrad_finish_count(w);
+    if (cnt == 0) return;
+    if (n->fin_begin.empty()) n->fin_begin.push_back(0);
+    n->fin.push_back(w);
+    n->fin_begin.push_back(n->fin_begin.back() + (cnt + 63) / 64);
+}
+
+// the deferred second passes of this backward pass, in one launch; the
+// table is uploaded when it differs from the one on the device (the layer
+// schedule is fixed, so in practice once)
+int finish_weight_grads(deblur_net *n, hipStream_t st)
+{
+    if (n->fin.empty()) return FWI_OK;
+    const size_t nf = n->fin.size();
+    const bool same = n->fin_dev_copy.size() == nf &&
+                      std::memcmp(n->fin_dev_copy.data(), n->fin.data(), nf * sizeof(WgradArgs)) == 0;
+    if (!same) {
+        int rc;
+        if ((rc = alloc(n, n->fin_tab, nf * sizeof(WgradArgs))) ||
+            (rc = alloc(n, n->fin_beg, (nf + 1) * sizeof(int64_t))))
+            return rc;
+        HCK(n, hipStreamSynchronize(st));   // the previous copies' host buffers are reused
+        n->fin_dev_copy = n->fin;
+        n->fin_beg_copy = n->fin_begin;
+        HCK(n, hipMemcpyAsync(n->fin_tab.p, n->fin_dev_copy.data(), nf * sizeof(WgradArgs), hipMemcpyHostToDevice,
+                              st));
+        HCK(n, hipMemcpyAsync(n->fin_beg.p, n->fin_beg_copy.data(), (nf + 1) * sizeof(int64_t),
+                              hipMemcpyHostToDevice, st));
+    }
+    HCK(n, wgrad_finish_all(static_cast<const WgradArgs *>(n->fin_tab.p), static_cast<const int64_t *>(n->fin_beg.p),
+                            int32_t(nf), n->fin_begin.back(), st));
+    return FWI_OK;
 }
 
 int conv_wgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff, const bf16 *src, int ld, int coff,
@@ -509,20 +557,24 @@ int conv_wgrad(deblur_net *n, const ConvL &L, const bf16 *dz, int ldz, int zoff,
     w.lda = ldz;
     w.acoff = zoff;
     w.g = conv_gather(src, ld, coff, L.cin, n->H[lvl], n->W[lvl]);
-    wsplit(w.M, w.N, n->P[lvl], &w.nsplit, &w.chunk, &w.tile);
-    w.partial = P_<float>(n->wpart);
+    wsplit(w.M, w.N, n->P[lvl], &w.nsplit, &w.chunk, &w.bm, &w.bn);
     w.out = P_<float>(n->grads, L.w);
     w.ldm = 9 * L.cin;
     w.ldn = 1;
-    w.bias_partial = P_<float>(n->bpart);
     w.bias_out = P_<float>(n->grads, L.b);
     int rc = prof_begin(n, L.name, 2, w.M, w.N, n->P[lvl], st);
     if (rc) return rc;
     if (L.cin == 1 && ld == 1 && coff == 0 && L.cout % 8 == 0 && L.cout <= 2048 && ldz % 8 == 0 && zoff % 8 == 0) {
-        HCK(n, conv1_wgrad(dz, ldz, zoff, src, n->H[lvl], n->W[lvl], L.cout, P_<float>(n->wpart), n->wpart_max,
-                           w.out, w.bias_out, st));
+        const int64_t cap = int64_t(512) * L.cout * 10;
+        float *part = take_w(n, cap);
+        if (!part) return set_err(n, FWI_EINVAL, "weight-gradient scratch exhausted");
+        HCK(n, conv1_wgrad(dz, ldz, zoff, src, n->H[lvl], n->W[lvl], L.cout, part, cap, w.out, w.bias_out, st));
     } else {
-        HCK(n, wgrad(w, st));
+        w.partial = take_w(n, int64_t(w.nsplit) * w.M * w.N);
+        w.bias_partial = take_b(n, int64_t(w.nsplit) * std::max(w.M, w.N));
+        if (!w.partial || !w.bias_partial) return set_err(n, FWI_EINVAL, "weight-gradient scratch exhausted");
+        HCK(n, wgrad(w, st, true));
+        defer_finish(n, w);
     }
     return prof_end(n, st);
 }
@@ -567,18 +619,21 @@ int convt_bwd(deblur_net *n, int l, const bf16 *src, bf16 *dsrc, hipStream_t st)
     w.lda = T.cin;
     w.acoff = 0;
     w.g = gu;
-    wsplit(w.M, w.N, n->P[l + 1], &w.nsplit, &w.chunk, &w.tile);
-    w.partial = P_<float>(n->wpart);
+    wsplit(w.M, w.N, n->P[l + 1], &w.nsplit, &w.chunk, &w.bm, &w.bn);
+    w.partial = take_w(n, int64_t(w.nsplit) * w.M * w.N);
     w.out = P_<float>(n->grads, T.w);
     w.ldm = 1;
     w.ldn = T.cin;
+    // the bias gradient is the sum of the gathered output gradient
+    w.bias_partial = take_b(n, int64_t(w.nsplit) * std::max(w.M, w.N));
+    w.bias_out = P_<float>(n->grads, T.b);
+    w.bias_from_b = 1;
+    if (!w.partial || !w.bias_partial) return set_err(n, FWI_EINVAL, "weight-gradient scratch exhausted");
     int rc = prof_begin(n, T.name, 2, w.M, w.N, n->P[l + 1], st);
     if (rc) return rc;
-    HCK(n, wgrad(w, st));
+    HCK(n, wgrad(w, st, true));
+    defer_finish(n, w);
     if ((rc = prof_end(n, st))) return rc;
-    const int ns = std::max(1, std::min(256, n->P[l] / 1024));
-    HCK(n, bias_grad(du, 2 * n->C[l], n->C[l], T.cout, n->P[l], P_<float>(n->grads, T.b), P_<float>(n->bpart), ns,
-                     st));
     GemmArgs a{};
     a.kpart = P_<float>(n->kpart);
     a.kpart_cap = kGemmSplitFloats;
@@ -591,6 +646,11 @@ int convt_bwd(deblur_net *n, int l, const bf16 *src, bf16 *dsrc, hipStream_t st)
     a.out = dsrc;
     a.out_ld = T.cin;
     a.Cout = T.cin;
+    // src is the activated output of the layer below (dense, T.cin channels)
+    a.act_y = src;
+    a.act_ld = T.cin;
+    a.act_coff = 0;
+    a.slope = n->cfg.leaky_slope;
     if ((rc = prof_begin(n, T.name, 1, a.M, a.N, a.K, st))) return rc;
     HCK(n, gemm(a, st));
     return prof_end(n, st);
@@ -645,50 +705,51 @@ int backward(deblur_net *n, hipStream_t st, double *loss_slot)
     double *lpart = P_<double>(n->lpart);
     HCK(n, mse(P_<float>(n->y32), P_<float>(n->t32), P0, lpart, n->nblk0, P_<float>(n->dy32), st));
     HCK(n, sum_partials_d(lpart, n->nblk0, loss_slot, 1.0f / float(P0), nullptr, st));
-    float *wp = P_<float>(n->wpart);
+    n->wp_cursor = n->bp_cursor = 0;
+    n->fin.clear();
+    n->fin_begin.clear();
+    float *wp = take_w(n, int64_t(n->nblk0) * (C0 + 1));
+    if (!wp) return set_err(n, FWI_EINVAL, "weight-gradient scratch exhausted");
+    // Every activation derivative is folded into the kernel that produces the
+    // gradient it scales: the output convolution's backward (dd_0), the data
+    // gradients whose input was activated (act_y), and the pooling adjoint
+    // that completes a skip connection's gradient (after its accumulation).
     HCK(n, outc_bwd(d + n->d_off[0], C0, P0, P_<float>(n->params, n->out_w), P_<float>(n->dy32), dd + n->d_off[0], wp,
-                    n->nblk0, st));
+                    n->nblk0, slope, st));
     HCK(n, outc_wgrad_reduce(wp, C0, n->nblk0, P_<float>(n->grads, n->out_w), P_<float>(n->grads, n->out_b), st));
     // decoder, level 0 up to D-1
     for (int l = 0; l < D; ++l) {
-        const int Cl = n->C[l], Pl = n->P[l];
+        const int Cl = n->C[l];
         bf16 *ddl = dd + n->d_off[l], *dcl = dc + n->c_off[l];
-        HCK(n, act_bwd(ddl, Cl, 0, ddl, Cl, 0, d + n->d_off[l], Cl, 0, Cl, Pl, slope, st));
         if ((rc = conv_wgrad(n, n->up2[l], ddl, Cl, 0, c + n->c_off[l], Cl, 0, l, st))) return rc;
-        if ((rc = conv_dgrad(n, n->up2[l], ddl, Cl, 0, l, dcl, Cl, 0, st))) return rc;
-        HCK(n, act_bwd(dcl, Cl, 0, dcl, Cl, 0, c + n->c_off[l], Cl, 0, Cl, Pl, slope, st));
+        if ((rc = conv_dgrad(n, n->up2[l], ddl, Cl, 0, l, dcl, Cl, 0, c + n->c_off[l], st))) return rc;
         if ((rc = conv_wgrad(n, n->up1[l], dcl, Cl, 0, cat + n->cat_off[l], 2 * Cl, 0, l, st))) return rc;
-        if ((rc = conv_dgrad(n, n->up1[l], dcl, Cl, 0, l, dcat + n->cat_off[l], 2 * Cl, 0, st))) return rc;
+        if ((rc = conv_dgrad(n, n->up1[l], dcl, Cl, 0, l, dcat + n->cat_off[l], 2 * Cl, 0, nullptr, st))) return rc;
         const bf16 *src = l == D - 1 ? eD : d + n->d_off[l + 1];
         bf16 *dsrc = l == D - 1 ? deD : dd + n->d_off[l + 1];
         if ((rc = convt_bwd(n, l, src, dsrc, st))) return rc;
     }
     // encoder, level D down to 1
     for (int l = D; l >= 1; --l) {
-        const int Cl = n->C[l], Pl = n->P[l];
+        const int Cl = n->C[l];
         bf16 *de = l < D ? dcat + n->cat_off[l] : deD;
-        const bf16 *e = l < D ? cat + n->cat_off[l] : eD;
         const int eld = l < D ? 2 * Cl : Cl;
-        HCK(n, act_bwd(de, eld, 0, de, eld, 0, e, eld, 0, Cl, Pl, slope, st));
         bf16 *dal = da + n->a_off[l];
         if ((rc = conv_wgrad(n, n->down2[l], de, eld, 0, a + n->a_off[l], Cl, 0, l, st))) return rc;
-        if ((rc = conv_dgrad(n, n->down2[l], de, eld, 0, l, dal, Cl, 0, st))) return rc;
-        HCK(n, act_bwd(dal, Cl, 0, dal, Cl, 0, a + n->a_off[l], Cl, 0, Cl, Pl, slope, st));
+        if ((rc = conv_dgrad(n, n->down2[l], de, eld, 0, l, dal, Cl, 0, a + n->a_off[l], st))) return rc;
         const int Cp = n->C[l - 1];
         if ((rc = conv_wgrad(n, n->down1[l], dal, Cl, 0, pl + n->pool_off[l], Cp, 0, l, st))) return rc;
-        if ((rc = conv_dgrad(n, n->down1[l], dal, Cl, 0, l, dpl + n->pool_off[l], Cp, 0, st))) return rc;
+        if ((rc = conv_dgrad(n, n->down1[l], dal, Cl, 0, l, dpl + n->pool_off[l], Cp, 0, nullptr, st))) return rc;
         HCK(n, pool_bwd(dpl + n->pool_off[l], Cp, n->H[l - 1], n->W[l - 1], dcat + n->cat_off[l - 1], 2 * Cp, 0, 1,
-                        st));
+                        cat + n->cat_off[l - 1], slope, st));
     }
     // input block
     bf16 *de0 = dcat + n->cat_off[0];
-    HCK(n, act_bwd(de0, 2 * C0, 0, de0, 2 * C0, 0, cat + n->cat_off[0], 2 * C0, 0, C0, P0, slope, st));
     if ((rc = conv_wgrad(n, n->inc[1], de0, 2 * C0, 0, a + n->a_off[0], C0, 0, 0, st))) return rc;
     bf16 *da0 = da + n->a_off[0];
-    if ((rc = conv_dgrad(n, n->inc[1], de0, 2 * C0, 0, 0, da0, C0, 0, st))) return rc;
-    HCK(n, act_bwd(da0, C0, 0, da0, C0, 0, a + n->a_off[0], C0, 0, C0, P0, slope, st));
+    if ((rc = conv_dgrad(n, n->inc[1], de0, 2 * C0, 0, 0, da0, C0, 0, a + n->a_off[0], st))) return rc;
     if ((rc = conv_wgrad(n, n->inc[0], da0, C0, 0, P_<bf16>(n->xin), 1, 0, 0, st))) return rc;
-    return FWI_OK;
+    return finish_weight_grads(n, st);
 }
 
 int check_ctx(deblur_net *n, fwi_ctx *ctx, hipStream_t *st)
@@ -740,6 +801,22 @@ int deblur_create(fwi_ctx *ctx, const deblur_cfg *cfg, uint64_t seed, deblur_net
     build_layout(n);
     int rc = alloc_buffers(n);
     if (rc == FWI_OK) {
+        // weight tensors in parameter order with their data-gradient matrices
+        // (laid out in the same order)
+        int64_t aux = 0;
+        for (const Entry &e : n->entries) {
+            if (e.kind != KW3 && e.kind != KWT) continue;
+            const int R = e.kind == KW3 ? e.cout : 4 * e.cout, C = e.kind == KW3 ? 9 * e.cin : e.cin;
+            n->h_segs.push_back(AuxSeg{e.off, e.n, aux, n->aux_tiles, e.kind == KW3 ? 0 : 1, e.cin, e.cout, 0});
+            aux += e.n;
+            n->aux_tiles += int64_t((R + 31) / 32) * ((C + 63) / 64);
+        }
+        rc = alloc(n, n->segs, n->h_segs.size() * sizeof(AuxSeg));
+        if (rc == FWI_OK && hipMemcpyAsync(n->segs.p, n->h_segs.data(), n->h_segs.size() * sizeof(AuxSeg),
+                                           hipMemcpyHostToDevice, fwi::ctx_stream(ctx)) != hipSuccess)
+            rc = set_err(n, FWI_EHIP, "upload of the weight table failed");
+    }
+    if (rc == FWI_OK) {
         std::vector<float> v = init_params(n, seed), internal;
         torch_to_internal(n, v.data(), internal);
         rc = upload_params(n, fwi::ctx_stream(ctx), internal);
@@ -759,7 +836,8 @@ void deblur_destroy(deblur_net *n)
     (void)hipDeviceSynchronize();
     for (Buf *b : {&n->params, &n->grads, &n->mom1, &n->mom2, &n->pbf, &n->aux, &n->xin, &n->a, &n->cat, &n->eD,
                    &n->pool, &n->c, &n->d, &n->y32, &n->t32, &n->da, &n->dcat, &n->deD, &n->dpool, &n->dc, &n->dd,
-                   &n->dy32, &n->wpart, &n->bpart, &n->lpart, &n->loss_dev, &n->hyper, &n->scal, &n->kpart})
+                   &n->dy32, &n->wpart, &n->bpart, &n->lpart, &n->loss_dev, &n->hyper, &n->scal, &n->kpart,
+                   &n->segs, &n->fin_tab, &n->fin_beg, &n->amax})
         release(*b);
     for (hipEvent_t e : n->prof_events) (void)hipEventDestroy(e);
     delete n;
@@ -867,8 +945,8 @@ int deblur_train_range(fwi_ctx *ctx, deblur_net *n, const float *x, const float 
     float *scal = P_<float>(n->scal);  // [0] max|x|, [1] max|y|
     if ((rc = alloc(n, n->loss_dev, size_t(count) * 8)) || (rc = alloc(n, n->hyper, size_t(count) * 3 * 4)))
         return rc;
-    HCK(n, absmax(x, int64_t(nz) * nx, scal, st));
-    HCK(n, absmax(y, int64_t(nz) * nx, scal + 1, st));
+    HCK(n, absmax(x, int64_t(nz) * nx, scal, P_<float>(n->amax), st));
+    HCK(n, absmax(y, int64_t(nz) * nx, scal + 1, P_<float>(n->amax), st));
     HCK(n, pad_norm(x, nz, nx, H, W, py, px, scal, P_<bf16>(n->xin), nullptr, st));
     HCK(n, pad_norm(y, nz, nx, H, W, py, px, scal + 1, nullptr, P_<float>(n->t32), st));
     // cosine-annealed learning rate (over the run's total steps) and the Adam
@@ -887,9 +965,11 @@ int deblur_train_range(fwi_ctx *ctx, deblur_net *n, const float *x, const float 
     }
     for (int i = 0; i < count; ++i) {
         if ((rc = forward(n, st)) || (rc = backward(n, st, P_<double>(n->loss_dev, i)))) return rc;
+        // the update writes the bf16 weights; the data-gradient matrices follow
         HCK(n, adam(P_<float>(n->params), P_<float>(n->grads), P_<float>(n->mom1), P_<float>(n->mom2),
                     P_<bf16>(n->pbf), n->nparam, P_<float>(n->hyper, 3 * i), kBeta1, kBeta2, kEps, st));
-        if ((rc = refresh_weights(n, st))) return rc;
+        HCK(n, aux_from_pb(static_cast<const AuxSeg *>(n->segs.p), int32_t(n->h_segs.size()), n->aux_tiles,
+                           P_<bf16>(n->pbf), P_<bf16>(n->aux), st));
     }
     std::vector<double> lh(static_cast<size_t>(count));
     HCK(n, hipMemcpyAsync(lh.data(), n->loss_dev.p, lh.size() * 8, hipMemcpyDeviceToHost, st));
@@ -921,7 +1001,7 @@ int deblur_apply(fwi_ctx *ctx, deblur_net *n, const float *x, int32_t nz, int32_
     if ((rc = check_image(n, nz, nx, &py, &px))) return rc;
     const int H = n->cfg.in_h, W = n->cfg.in_w;
     float *scal = P_<float>(n->scal);
-    HCK(n, absmax(x, int64_t(nz) * nx, scal, st));
+    HCK(n, absmax(x, int64_t(nz) * nx, scal, P_<float>(n->amax), st));
     HCK(n, pad_norm(x, nz, nx, H, W, py, px, scal, P_<bf16>(n->xin), nullptr, st));
     if ((rc = forward(n, st))) return rc;
     HCK(n, crop_scale(P_<float>(n->y32), H, W, py, px, nz, nx, scal, y, st));

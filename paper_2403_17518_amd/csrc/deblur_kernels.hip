@@ -182,6 +182,202 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs a)
             float v = acc[tn][i];
             if (a.bias) v += a.bias[co];
             if (a.act) v = v > 0.f ? v : a.slope * v;
+            if (a.act_y && !(bf2f(a.act_y[pix * a.act_ld + a.act_coff + co]) > 0.f)) v *= a.slope;
+            a.out[pix * a.out_ld + a.out_coff + co] = f2bf(v);
+        }
+    }
+}
+
+// Epilogue of one 32 x 32 accumulator tile of the implicit GEMMs with
+// vectorised outputs (out_vec): the lane holds channels m = mt + 8 j +
+// 4 (lane / 32) + q (j, q < 4) of output column n, so the four consecutive
+// channels of each j leave as one 8-byte store (and the activation
+// derivative, if any, arrives as one 8-byte load).
+__device__ __forceinline__ void gemm_store_tile(const GemmArgs &a, const f32x16 &acc, int mt, int n, int lane)
+{
+    if (n >= a.N) return;
+    const int pi = n / a.g.W, pj = n - (n / a.g.W) * a.g.W;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int mb = mt + 8 * j + 4 * (lane / 32);
+        if (mb >= a.M) continue;
+        int co = mb;
+        int64_t pix = n;
+        if (a.scatter) {
+            const int ab = mb / a.Cout;
+            co = mb - ab * a.Cout;
+            pix = int64_t(2 * pi + ab / 2) * a.Wo + 2 * pj + ab % 2;
+        }
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = acc[4 * j + q];
+            if (a.bias) v[q] += a.bias[co + q];
+            if (a.act) v[q] = v[q] > 0.f ? v[q] : a.slope * v[q];
+        }
+        if (a.act_y) {
+            const uint2 yw = *reinterpret_cast<const uint2 *>(a.act_y + pix * a.act_ld + a.act_coff + co);
+            const bf16 *y = reinterpret_cast<const bf16 *>(&yw);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (!(bf2f(y[q]) > 0.f)) v[q] *= a.slope;
+        }
+        bf16 o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = f2bf(v[q]);
+        *reinterpret_cast<uint2 *>(a.out + pix * a.out_ld + a.out_coff + co) = *reinterpret_cast<const uint2 *>(o);
+    }
+}
+
+// Implicit GEMM with 16-byte operand loads: a (32*WM) x (32*WN*TN) output
+// tile per workgroup, 32-deep K slices double-buffered in LDS (one barrier
+// per slice). The output pixels whose gathered rows a thread loads are the
+// same in every slice, so their coordinates are computed once, and the tap
+// and channel of each row's K offset advance with the slice instead of being
+// divided out at every load; the loads of the next DEPTH slices are in
+// flight while a slice is computed (a ring of register stages). Requires K,
+// Cb, lda, ld and coff to be multiples of 8 and K a multiple of 32. Same
+// epilogue as k_gemm.
+template <int WM, int WN, int TN, int DEPTH>
+__global__ __launch_bounds__(256) void k_gemm_v(const GemmArgs a)
+{
+    constexpr int BM = 32 * WM, BN = 32 * WN * TN;
+    __shared__ __attribute__((aligned(16))) bf16 As[2][BM * kLDK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN * kLDK];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w / WN, wn = w % WN;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int nk = a.K / kBK;
+    const Gather &g = a.g;
+    constexpr int ACH = BM * kBK / 8, BCH = BN * kBK / 8;   // 16-byte chunks per tile
+    constexpr int AR = (ACH + 255) / 256, BR = (BCH + 255) / 256;
+    // the thread's B rows: pixel coordinates, and the running tap (ty, tx)
+    // and channel of the row's 8-wide K offset
+    int bpi[BR], bpj[BR], bch[BR], bty[BR], btx[BR];
+    bool bok[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+        const int c = tid + r * 256, p = n0 + (c >> 2), kc = (c & 3) * 8;
+        bok[r] = c < BCH && p < a.N;
+        bpi[r] = bok[r] ? p / g.W : 0;
+        bpj[r] = bok[r] ? p - bpi[r] * g.W : 0;
+        const int tap = kc / g.Cb;
+        bch[r] = kc - tap * g.Cb;
+        bty[r] = tap / g.tapw;
+        btx[r] = tap - bty[r] * g.tapw;
+    }
+    uint4 ra[DEPTH][AR], rb[DEPTH][BR];
+    auto load = [&](int kt, int sl) {
+        const int kbase = kt * kBK;
+#pragma unroll
+        for (int r = 0; r < AR; ++r) {
+            const int c = tid + r * 256;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (c < ACH && m0 + (c >> 2) < a.M)
+                v = *reinterpret_cast<const uint4 *>(a.A + int64_t(m0 + (c >> 2)) * a.lda + kbase + (c & 3) * 8);
+            ra[sl][r] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (bok[r]) {
+                const int si = bpi[r] * g.stride + bty[r] + g.d0, sj = bpj[r] * g.stride + btx[r] + g.d0;
+                if (si >= 0 && si < g.Hs && sj >= 0 && sj < g.Ws)
+                    v = *reinterpret_cast<const uint4 *>(g.src + (int64_t(si) * g.Ws + sj) * g.ld + g.coff + bch[r]);
+            }
+            rb[sl][r] = v;
+        }
+    };
+    auto advance = [&]() {   // the K offsets move on by one slice
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            bch[r] += kBK;
+            while (bch[r] >= g.Cb) {
+                bch[r] -= g.Cb;
+                if (++btx[r] == g.tapw) {
+                    btx[r] = 0;
+                    ++bty[r];
+                }
+            }
+        }
+    };
+    auto store = [&](int sl, int buf) {
+#pragma unroll
+        for (int r = 0; r < AR; ++r) {
+            const int c = tid + r * 256;
+            if (c < ACH) *reinterpret_cast<uint4 *>(&As[buf][(c >> 2) * kLDK + (c & 3) * 8]) = ra[sl][r];
+        }
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            const int c = tid + r * 256;
+            if (c < BCH) *reinterpret_cast<uint4 *>(&Bs[buf][(c >> 2) * kLDK + (c & 3) * 8]) = rb[sl][r];
+        }
+    };
+
+    f32x16 acc[TN];
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) acc[tn] = f32x16{};
+    // ring of register stages as in k_wgrad_t (the tap state advances in
+    // load order)
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d)
+        if (d < nk) {
+            load(d, d);
+            advance();
+        }
+    if (nk > 0) store(0, 0);
+    __syncthreads();
+    for (int kt0 = 0; kt0 < nk; kt0 += DEPTH) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) {
+            const int kt = kt0 + d;
+            if (kt < nk) {
+                const int buf = kt & 1;
+                if (kt + DEPTH < nk) {
+                    load(kt + DEPTH, d);
+                    advance();
+                }
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) {
+                    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(
+                        &As[buf][(wm * 32 + lane % 32) * kLDK + kk * 16 + 8 * (lane / 32)]);
+#pragma unroll
+                    for (int tn = 0; tn < TN; ++tn) {
+                        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(
+                            &Bs[buf][((wn * TN + tn) * 32 + lane % 32) * kLDK + kk * 16 + 8 * (lane / 32)]);
+                        acc[tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[tn], 0, 0, 0);
+                    }
+                }
+                if (kt + 1 < nk) store((d + 1) % DEPTH, buf ^ 1);
+                __syncthreads();
+            }
+        }
+    }
+    // epilogue: lane holds rows m = 8*(i/4) + 4*(lane/32) + i%4, column lane%32
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) {
+        const int n = n0 + (wn * TN + tn) * 32 + lane % 32;
+        if (a.out_vec) {
+            gemm_store_tile(a, acc[tn], m0 + wm * 32, n, lane);
+            continue;
+        }
+        if (n >= a.N) continue;
+        const int pi = n / g.W, pj = n - (n / g.W) * g.W;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int m = m0 + wm * 32 + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+            if (m >= a.M) continue;
+            int co = m;
+            int64_t pix = n;
+            if (a.scatter) {
+                const int ab = m / a.Cout;
+                co = m - ab * a.Cout;
+                pix = int64_t(2 * pi + ab / 2) * a.Wo + 2 * pj + ab % 2;
+            }
+            float v = acc[tn][i];
+            if (a.bias) v += a.bias[co];
+            if (a.act) v = v > 0.f ? v : a.slope * v;
+            if (a.act_y && !(bf2f(a.act_y[pix * a.act_ld + a.act_coff + co]) > 0.f)) v *= a.slope;
             a.out[pix * a.out_ld + a.out_coff + co] = f2bf(v);
         }
     }
@@ -277,14 +473,31 @@ __global__ __launch_bounds__(256) void k_gemm2(const GemmArgs a)
 #pragma unroll
             for (int x = 0; x < 2; ++x)
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int m = m0 + wm * 64 + x * 32 + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
-                    if (m < a.M) part[int64_t(n) * a.M + m] = acc[x][y][i];
+                for (int j = 0; j < 4; ++j) {
+                    const int mb = m0 + wm * 64 + x * 32 + 8 * j + 4 * (lane / 32);
+                    if (mb >= a.M) continue;
+                    if (a.out_vec) {
+                        *reinterpret_cast<float4 *>(part + int64_t(n) * a.M + mb) =
+                            make_float4(acc[x][y][4 * j], acc[x][y][4 * j + 1], acc[x][y][4 * j + 2],
+                                        acc[x][y][4 * j + 3]);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (mb + q < a.M) part[int64_t(n) * a.M + mb + q] = acc[x][y][4 * j + q];
+                    }
                 }
         }
         return;
     }
     // epilogue: lane holds rows m = 8*(i/4) + 4*(lane/32) + i%4 of each tile, column lane%32
+    if (a.out_vec) {
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+                gemm_store_tile(a, acc[x][y], m0 + wm * 64 + x * 32, n0 + wn * 64 + y * 32 + lane % 32, lane);
+        return;
+    }
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
         const int n = n0 + wn * 64 + y * 32 + lane % 32;
@@ -306,6 +519,7 @@ __global__ __launch_bounds__(256) void k_gemm2(const GemmArgs a)
                 float v = acc[x][y][i];
                 if (a.bias) v += a.bias[co];
                 if (a.act) v = v > 0.f ? v : a.slope * v;
+                if (a.act_y && !(bf2f(a.act_y[pix * a.act_ld + a.act_coff + co]) > 0.f)) v *= a.slope;
                 a.out[pix * a.out_ld + a.out_coff + co] = f2bf(v);
             }
     }
@@ -475,160 +689,89 @@ __global__ void k_gemm_finish(const GemmArgs a, int32_t ksplit)
     }
     if (a.bias) v += a.bias[co];
     if (a.act) v = v > 0.f ? v : a.slope * v;
+    if (a.act_y && !(bf2f(a.act_y[pix * a.act_ld + a.act_coff + co]) > 0.f)) v *= a.slope;
     a.out[pix * a.out_ld + a.out_coff + co] = f2bf(v);
 }
 
 
-// Weight gradient for thin layers (M <= 32 output channels): a 32 x 128
-// tile of C[m][n] = sum_p A[p][m] B[p][n] per workgroup, each wave one
-// 32 x 32 matrix-core tile of its own 32 columns, 64-pixel K slices. Each
-// thread loads one 8-channel chunk of A and four of the gathered B for one
-// pixel (16-byte loads) and writes them transposed into the [channel][pixel]
-// LDS tiles. Requires the 16-byte alignments of the vectorised k_wgrad and
-// a pixel split (chunk) that is a multiple of 64. Partial sums per split as
-// in k_wgrad; the first column of blocks also sums A (the bias gradient).
-__global__ __launch_bounds__(256) void k_wgrad_m32(const WgradArgs a)
+// Weight gradient C[m][n] = sum_p A[p][acoff + m] Bg(p, n) over the pixels
+// [p_lo, p_hi) of split z (blockIdx.z): a BM x BN tile per workgroup,
+// 64-pixel K slices double-buffered in LDS (one barrier per slice). Both
+// operands are pixel-major in memory and channel-major in the matrix-core
+// layout, so they are transposed on the way into LDS: a task of 8 channels x
+// 4 pixels is four 16-byte loads and eight 8-byte LDS stores, and the 16
+// lanes that share a channel chunk take consecutive pixel groups, so each
+// store of a wave fills whole LDS rows. Requires M, N, Cb, lda, ld and the
+// channel offsets to be multiples of 8 and the split (chunk) a multiple of
+// 64. The loads of the next DEPTH slices are in flight while a slice is
+// computed (a ring of DEPTH register stages). With one split the sums go
+// straight to out, else to partial[z][m][n] for k_wgrad_finish. Bias gradients, per split: the first column of blocks
+// sums A over its pixels (bias_from_b = 0: A is the output gradient of a
+// convolution), or the first row of blocks sums B (bias_from_b = 1: the
+// transposed convolution, whose output gradient is the gathered B).
+template <int BM, int BN, int DEPTH>
+__global__ __launch_bounds__(256) void k_wgrad_t(const WgradArgs a)
 {
-    constexpr int BM = 32, BN = 128, BK = 64, LDK = BK + 8;
-    __shared__ __attribute__((aligned(16))) bf16 As[BM * LDK];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[BN * LDK];
+    constexpr int BK = 64, LDK = BK + 8;   // LDS rows of 144 B
+    constexpr int TA = (BM / 8) * 16, TB = (BN / 8) * 16;
+    constexpr int NR = (TA + TB + 255) / 256;
+    constexpr int WTM = BM / 32, WTN = BN / 32;
+    constexpr int WGM = WTM >= 2 ? 2 : 1, WGN = 4 / WGM;
+    constexpr int XM = WTM / WGM, YN = WTN / WGN;
+    static_assert(TA % 64 == 0 && WTN % WGN == 0 && XM >= 1 && YN >= 1, "tile shape");
+    __shared__ __attribute__((aligned(16))) bf16 As[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN * LDK];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int n0 = blockIdx.x * BN;
-    const Gather &g = a.g;
-    const int P = g.H * g.W;
-    const int p_lo = blockIdx.z * a.chunk;
-    const int p_hi = min(P, p_lo + a.chunk);
-    const int nk = p_hi > p_lo ? (p_hi - p_lo + BK - 1) / BK : 0;
-    const int pl = tid >> 2;           // pixel of the slice
-    const int cq = (tid & 3) * 8;      // 8-channel chunk (A) / first chunk (B)
-    const bool mval = cq < a.M;
-    int ntap[4], nch[4];
-    bool nval[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int nn = n0 + cq + 32 * j;
-        nval[j] = nn < a.N;
-        ntap[j] = nval[j] ? nn / g.Cb : 0;
-        nch[j] = nn - ntap[j] * g.Cb;
-    }
-    uint4 ra, rb[4];
-    auto load = [&](int kt) {
-        const int p = p_lo + kt * BK + pl;
-        ra = make_uint4(0, 0, 0, 0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) rb[j] = make_uint4(0, 0, 0, 0);
-        if (p < p_hi) {
-            if (mval) ra = *reinterpret_cast<const uint4 *>(a.A + int64_t(p) * a.lda + a.acoff + cq);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (nval[j]) {
-                    const int64_t sp = gather_pix(g, p, ntap[j]);
-                    if (sp >= 0) rb[j] = *reinterpret_cast<const uint4 *>(g.src + sp * g.ld + g.coff + nch[j]);
-                }
-        }
-    };
-    auto store = [&]() {
-        const bf16 *pa = reinterpret_cast<const bf16 *>(&ra);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) As[(cq + e) * LDK + pl] = pa[e];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bf16 *pb = reinterpret_cast<const bf16 *>(&rb[j]);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) Bs[(cq + 32 * j + e) * LDK + pl] = pb[e];
-        }
-    };
-
-    const bool do_bias = a.bias_partial != nullptr && blockIdx.x == 0;
-    float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    f32x16 acc = {};
-    if (nk > 0) load(0);
-    for (int kt = 0; kt < nk; ++kt) {
-        __syncthreads();
-        store();
-        if (do_bias) {
-            const bf16 *pa = reinterpret_cast<const bf16 *>(&ra);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) bsum[e] += bf2f(pa[e]);
-        }
-        __syncthreads();
-        if (kt + 1 < nk) load(kt + 1);
-#pragma unroll
-        for (int kk = 0; kk < BK / 16; ++kk) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&As[(lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
-            const bf16x8 bv =
-                *reinterpret_cast<const bf16x8 *>(&Bs[(w * 32 + lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
-        }
-    }
-    if (do_bias) {
-        // threads with the same chunk hold the same 8 channels for 64 pixels
-        float(*bred)[BM + 1] = reinterpret_cast<float(*)[BM + 1]>(&Bs[0]);
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 8; ++e) bred[pl][cq + e] = bsum[e];
-        __syncthreads();
-        if (tid < BM) {
-            float t = 0.f;
-            for (int r = 0; r < BK; ++r) t += bred[r][tid];
-            if (tid < a.M) a.bias_partial[int64_t(blockIdx.z) * a.M + tid] = t;
-        }
-    }
-    const int n = n0 + w * 32 + lane % 32;
-    if (n >= a.N) return;
-    float *part = a.partial + int64_t(blockIdx.z) * a.M * a.N;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int m = 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
-        if (m < a.M) part[int64_t(m) * a.N + n] = acc[i];
-    }
-}
-
-// Weight gradient for wide layers: a 128 x 128 tile of C[m][n] = sum_p
-// A[p][m] B[p][n] per workgroup (4 waves of 64 x 64, four 32 x 32 matrix-core
-// tiles each), 64-pixel K slices. Each thread loads the same 8-channel chunk
-// of A and of the gathered B for 4 consecutive pixels (16-byte loads) and
-// writes them transposed into the [channel][pixel] LDS tiles with one 8-byte
-// store per channel, so the matrix-core operands read 8 consecutive pixels.
-// Requires M, N, Cb, lda, ld and the channel offsets to be multiples of 8
-// and the pixel split (chunk) a multiple of 64. Partial sums per split as in
-// k_wgrad; the first column of blocks also sums A (the bias gradient).
-__global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a)
-{
-    constexpr int BM = 128, BN = 128, BK = 64, LDK = BK + 8;   // LDS rows of 144 B
-    __shared__ __attribute__((aligned(16))) bf16 As[BM * LDK];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[BN * LDK];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
+    const int wm = w / WGN, wn = w % WGN;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const Gather &g = a.g;
     const int P = g.H * g.W;
     const int p_lo = blockIdx.z * a.chunk;
     const int p_hi = min(P, p_lo + a.chunk);
     const int nk = p_hi > p_lo ? (p_hi - p_lo + BK - 1) / BK : 0;
+    const int pg = tid & 15;   // group of 4 pixels within the slice
 
-    const int cc = tid & 15, pg = tid >> 4;   // channel chunk, group of 4 pixels
-    const bool mval = m0 + cc * 8 < a.M;
-    const int nb = n0 + cc * 8;
-    const bool nval = nb < a.N;
-    const int tap = nval ? nb / g.Cb : 0;
-    const int ch = nb - tap * g.Cb;
-    const int ty = tap / g.tapw, tx = tap - (tap / g.tapw) * g.tapw;
-    uint4 ra[4], rb[4];
-    auto load = [&](int kt) {
+    // the task of each round: operand, 8-channel chunk, source offsets
+    bool act[NR], isA[NR], val[NR];
+    int cc[NR], ty[NR], tx[NR], ch[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int t = tid + 256 * r;
+        act[r] = t < TA + TB;
+        isA[r] = t < TA;
+        cc[r] = isA[r] ? t >> 4 : (t - TA) >> 4;
+        ty[r] = tx[r] = ch[r] = 0;
+        if (isA[r]) {
+            val[r] = act[r] && m0 + cc[r] * 8 < a.M;
+        } else {
+            const int nb = n0 + cc[r] * 8;
+            val[r] = act[r] && nb < a.N;
+            const int tap = val[r] ? nb / g.Cb : 0;
+            ch[r] = nb - tap * g.Cb;
+            ty[r] = tap / g.tapw;
+            tx[r] = tap - ty[r] * g.tapw;
+        }
+    }
+    uint4 rg[DEPTH][NR][4];
+    auto load = [&](int kt, int sl) {
         const int p4 = p_lo + kt * BK + pg * 4;
         int i = p4 / g.W, j = p4 - (p4 / g.W) * g.W;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int p = p4 + u;
-            ra[u] = make_uint4(0, 0, 0, 0);
-            rb[u] = make_uint4(0, 0, 0, 0);
-            if (p < p_hi) {
-                if (mval) ra[u] = *reinterpret_cast<const uint4 *>(a.A + int64_t(p) * a.lda + a.acoff + m0 + cc * 8);
-                if (nval) {
-                    const int si = i * g.stride + ty + g.d0, sj = j * g.stride + tx + g.d0;
-                    if (si >= 0 && si < g.Hs && sj >= 0 && sj < g.Ws)
-                        rb[u] = *reinterpret_cast<const uint4 *>(g.src + (int64_t(si) * g.Ws + sj) * g.ld + g.coff + ch);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                rg[sl][r][u] = make_uint4(0, 0, 0, 0);
+                if (val[r] && p < p_hi) {
+                    if (isA[r]) {
+                        rg[sl][r][u] =
+                            *reinterpret_cast<const uint4 *>(a.A + int64_t(p) * a.lda + a.acoff + m0 + cc[r] * 8);
+                    } else {
+                        const int si = i * g.stride + ty[r] + g.d0, sj = j * g.stride + tx[r] + g.d0;
+                        if (si >= 0 && si < g.Hs && sj >= 0 && sj < g.Ws)
+                            rg[sl][r][u] = *reinterpret_cast<const uint4 *>(g.src + (int64_t(si) * g.Ws + sj) * g.ld +
+                                                                            g.coff + ch[r]);
+                    }
                 }
             }
             if (++j == g.W) {
@@ -637,88 +780,208 @@ __global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a)
             }
         }
     };
-    auto store = [&]() {
+    auto store = [&](int sl, int buf) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const uint32_t a01 = (reinterpret_cast<const uint16_t *>(&ra[0])[e]) |
-                                 (uint32_t(reinterpret_cast<const uint16_t *>(&ra[1])[e]) << 16);
-            const uint32_t a23 = (reinterpret_cast<const uint16_t *>(&ra[2])[e]) |
-                                 (uint32_t(reinterpret_cast<const uint16_t *>(&ra[3])[e]) << 16);
-            const uint32_t b01 = (reinterpret_cast<const uint16_t *>(&rb[0])[e]) |
-                                 (uint32_t(reinterpret_cast<const uint16_t *>(&rb[1])[e]) << 16);
-            const uint32_t b23 = (reinterpret_cast<const uint16_t *>(&rb[2])[e]) |
-                                 (uint32_t(reinterpret_cast<const uint16_t *>(&rb[3])[e]) << 16);
-            *reinterpret_cast<uint2 *>(&As[(cc * 8 + e) * LDK + pg * 4]) = make_uint2(a01, a23);
-            *reinterpret_cast<uint2 *>(&Bs[(cc * 8 + e) * LDK + pg * 4]) = make_uint2(b01, b23);
+        for (int r = 0; r < NR; ++r) {
+            if (!act[r]) continue;
+            bf16 *base = isA[r] ? &As[buf][cc[r] * 8 * LDK] : &Bs[buf][cc[r] * 8 * LDK];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t lo = reinterpret_cast<const uint16_t *>(&rg[sl][r][0])[e] |
+                                    (uint32_t(reinterpret_cast<const uint16_t *>(&rg[sl][r][1])[e]) << 16);
+                const uint32_t hi = reinterpret_cast<const uint16_t *>(&rg[sl][r][2])[e] |
+                                    (uint32_t(reinterpret_cast<const uint16_t *>(&rg[sl][r][3])[e]) << 16);
+                *reinterpret_cast<uint2 *>(base + e * LDK + pg * 4) = make_uint2(lo, hi);
+            }
         }
     };
 
-    const bool do_bias = a.bias_partial != nullptr && blockIdx.x == 0;
-    float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    f32x16 acc[2][2];
+    const bool bias_a = a.bias_partial != nullptr && !a.bias_from_b && blockIdx.x == 0;
+    const bool bias_b = a.bias_partial != nullptr && a.bias_from_b && blockIdx.y == 0;
+    float bs[NR][8];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = f32x16{};
-    if (nk > 0) load(0);
-    for (int kt = 0; kt < nk; ++kt) {
-        __syncthreads();
-        store();
-        if (do_bias) {
+        for (int e = 0; e < 8; ++e) bs[r][e] = 0.f;
+    auto bias_add = [&](int sl) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (!(isA[r] ? bias_a : bias_b)) continue;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const bf16 *pa = reinterpret_cast<const bf16 *>(&ra[u]);
+                const bf16 *v = reinterpret_cast<const bf16 *>(&rg[sl][r][u]);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) bsum[e] += bf2f(pa[e]);
+                for (int e = 0; e < 8; ++e) bs[r][e] += bf2f(v[e]);
             }
         }
-        __syncthreads();
-        if (kt + 1 < nk) load(kt + 1);
+    };
+
+    f32x16 acc[XM][YN];
 #pragma unroll
-        for (int kk = 0; kk < BK / 16; ++kk) {
-            bf16x8 av[2], bv[2];
+    for (int x = 0; x < XM; ++x)
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
-                av[x] = *reinterpret_cast<const bf16x8 *>(
-                    &As[(wm * 64 + x * 32 + lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
+        for (int y = 0; y < YN; ++y) acc[x][y] = f32x16{};
+    // ring: register stage s holds slice kt with kt % DEPTH == s; slice kt
+    // goes to LDS buffer kt & 1 at the end of the previous slice, which frees
+    // its stage for slice kt + DEPTH
 #pragma unroll
-            for (int y = 0; y < 2; ++y)
-                bv[y] = *reinterpret_cast<const bf16x8 *>(
-                    &Bs[(wn * 64 + y * 32 + lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
+    for (int d = 0; d < DEPTH; ++d)
+        if (d < nk) load(d, d);
+    if (nk > 0) {
+        store(0, 0);
+        bias_add(0);
+    }
+    __syncthreads();
+    for (int kt0 = 0; kt0 < nk; kt0 += DEPTH) {
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+        for (int d = 0; d < DEPTH; ++d) {
+            const int kt = kt0 + d;
+            if (kt < nk) {
+                const int buf = kt & 1;
+                if (kt + DEPTH < nk) load(kt + DEPTH, d);
 #pragma unroll
-                for (int y = 0; y < 2; ++y)
-                    acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x], bv[y], acc[x][y], 0, 0, 0);
+                for (int kk = 0; kk < BK / 16; ++kk) {
+                    bf16x8 av[XM], bv[YN];
+#pragma unroll
+                    for (int x = 0; x < XM; ++x)
+                        av[x] = *reinterpret_cast<const bf16x8 *>(
+                            &As[buf][((wm * XM + x) * 32 + lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
+#pragma unroll
+                    for (int y = 0; y < YN; ++y)
+                        bv[y] = *reinterpret_cast<const bf16x8 *>(
+                            &Bs[buf][((wn * YN + y) * 32 + lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
+#pragma unroll
+                    for (int x = 0; x < XM; ++x)
+#pragma unroll
+                        for (int y = 0; y < YN; ++y)
+                            acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x], bv[y], acc[x][y], 0, 0, 0);
+                }
+                if (kt + 1 < nk) {
+                    store((d + 1) % DEPTH, buf ^ 1);
+                    bias_add((d + 1) % DEPTH);
+                }
+                __syncthreads();
+            }
         }
     }
-    if (do_bias) {
-        // threads with the same chunk cc hold the same 8 channels for 16 pixel
-        // groups; the reduction reuses the A tile's LDS (free after the loop)
-        float(*bred)[BM + 1] = reinterpret_cast<float(*)[BM + 1]>(&As[0]);
-        __syncthreads();
+    if (bias_a || bias_b) {
+        // the 16 lanes of a channel chunk hold sums over their pixel groups:
+        // combine them in a fixed order, then one lane writes the 8 channels
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bred[pg][cc * 8 + e] = bsum[e];
-        __syncthreads();
-        if (tid < BM) {
-            float t = 0.f;
-            for (int r = 0; r < 16; ++r) t += bred[r][tid];
-            if (m0 + tid < a.M) a.bias_partial[int64_t(blockIdx.z) * a.M + m0 + tid] = t;
+        for (int r = 0; r < NR; ++r) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                float v = bs[r][e];
+#pragma unroll
+                for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                bs[r][e] = v;
+            }
+            const bool on = isA[r] ? bias_a : bias_b;
+            if (!on || !val[r] || pg != 0) continue;
+            const int base = isA[r] ? m0 + cc[r] * 8 : n0 + cc[r] * 8;
+            const int len = isA[r] ? a.M : a.N;
+            if (isA[r] && a.nsplit == 1) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) a.bias_out[base + e] = bs[r][e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) a.bias_partial[int64_t(blockIdx.z) * len + base + e] = bs[r][e];
+            }
         }
     }
+    const bool direct = a.nsplit == 1;
     float *part = a.partial + int64_t(blockIdx.z) * a.M * a.N;
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
-        const int n = n0 + wn * 64 + y * 32 + lane % 32;
+    for (int y = 0; y < YN; ++y) {
+        const int n = n0 + (wn * YN + y) * 32 + lane % 32;
         if (n >= a.N) continue;
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < XM; ++x)
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int m = m0 + wm * 64 + x * 32 + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
-                if (m < a.M) part[int64_t(m) * a.N + n] = acc[x][y][i];
+                const int m = m0 + (wm * XM + x) * 32 + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+                if (m >= a.M) continue;
+                if (direct) a.out[int64_t(m) * a.ldm + int64_t(n) * a.ldn] = acc[x][y][i];
+                else part[int64_t(m) * a.N + n] = acc[x][y][i];
             }
     }
+}
+
+// Second pass of a split weight gradient: sums the splits of each output in
+// order into out[m*ldm + n*ldn]; the threads past M*N sum the bias partials
+// ([nsplit][M] from A, or [nsplit][N] from B, where the taps n = tap*Cb + c
+// of one channel c are added as well).
+__global__ void k_wgrad_finish(const WgradArgs a)
+{
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t MN = int64_t(a.M) * a.N;
+    if (e < MN) {
+        if (a.nsplit == 1) return;   // written by the first pass
+        const float s = sum_strided(a.partial + e, a.nsplit, MN);
+        const int m = int(e / a.N), n = int(e % a.N);
+        a.out[int64_t(m) * a.ldm + int64_t(n) * a.ldn] = s;
+        return;
+    }
+    if (!a.bias_partial) return;
+    const int c = int(e - MN);
+    if (!a.bias_from_b) {
+        if (c < a.M && a.nsplit > 1) a.bias_out[c] = sum_strided(a.bias_partial + c, a.nsplit, a.M);
+    } else if (c < a.g.Cb) {
+        float t = 0.f;
+        for (int tap = 0; tap * a.g.Cb < a.N; ++tap)
+            t += sum_strided(a.bias_partial + tap * a.g.Cb + c, a.nsplit, a.N);
+        a.bias_out[c] = t;
+    }
+}
+
+// All deferred second passes of one backward pass in one launch. Entry l of
+// tab owns the blocks [bbeg[l], bbeg[l+1]) (its split weight sums, then its
+// bias sums, 64 outputs per block), so the entry is the same for the whole
+// block. Wave g of a block sums the splits z = g, g + 4, ... of each of the
+// block's 64 outputs; the four sums are added in LDS in a fixed order.
+__global__ __launch_bounds__(256) void k_wgrad_finish_all(const WgradArgs *tab, const int64_t *bbeg, int32_t n)
+{
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int64_t blk = blockIdx.x;
+    int lo = 0, hi = n;   // the entry holding the block: bbeg[lo] <= blk < bbeg[lo + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bbeg[mid] <= blk) lo = mid;
+        else hi = mid;
+    }
+    const WgradArgs a = tab[lo];
+    const int64_t k = (blk - bbeg[lo]) * 64 + lane;
+    const int64_t MN = int64_t(a.M) * a.N;
+    const int64_t nw = a.nsplit > 1 ? MN : 0;
+    const int64_t nb = a.bias_partial ? (a.bias_from_b ? a.g.Cb : (a.nsplit > 1 ? a.M : 0)) : 0;
+    float t = 0.f;
+    if (k < nw) {
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        int z = grp;
+        for (; z + 12 < a.nsplit; z += 16) {
+            s0 += a.partial[int64_t(z) * MN + k];
+            s1 += a.partial[int64_t(z + 4) * MN + k];
+            s2 += a.partial[int64_t(z + 8) * MN + k];
+            s3 += a.partial[int64_t(z + 12) * MN + k];
+        }
+        for (; z < a.nsplit; z += 4) s0 += a.partial[int64_t(z) * MN + k];
+        t = (s0 + s1) + (s2 + s3);
+    } else if (k < nw + nb) {
+        const int c = int(k - nw);
+        const int len = a.bias_from_b ? a.N : a.M;
+        const int ntap = a.bias_from_b ? a.N / a.g.Cb : 1;
+        for (int tap = 0; tap < ntap; ++tap) {
+            const float *bp = a.bias_partial + tap * (a.bias_from_b ? a.g.Cb : 0) + c;
+            for (int z = grp; z < a.nsplit; z += 4) t += bp[int64_t(z) * len];
+        }
+    }
+    red[grp][lane] = t;
+    __syncthreads();
+    if (grp != 0 || k >= nw + nb) return;
+    const float s = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    if (k < nw) a.out[(k / a.N) * a.ldm + (k % a.N) * a.ldn] = s;
+    else a.bias_out[k - nw] = s;
 }
 
 __global__ void k_wgrad_reduce(const float *part, int32_t M, int32_t N, int32_t nsplit, float *out, int32_t ldm,
@@ -902,7 +1165,7 @@ __global__ void k_pool_fwd(const bf16 *in, int32_t ldi, int32_t coff, int32_t C,
 }
 
 __global__ void k_pool_bwd(const bf16 *dout, int32_t C, int32_t H, int32_t W, bf16 *din, int32_t ldi, int32_t coff,
-                           int32_t accumulate)
+                           int32_t accumulate, const bf16 *act_y, float slope)
 {
     const int Ho = H / 2, Wo = W / 2;
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -921,7 +1184,147 @@ __global__ void k_pool_bwd(const bf16 *dout, int32_t C, int32_t H, int32_t W, bf
     s *= (1.0f / 9.0f);
     bf16 *dst = din + q * ldi + coff + c;
     if (accumulate) s += bf2f(*dst);
+    if (act_y && !(bf2f(act_y[q * ldi + coff + c]) > 0.f)) s *= slope;
     *dst = f2bf(s);
+}
+
+// Vectorised pooling (C, ldi and coff multiples of 8): one thread per pixel
+// and 8 channels, 16-byte loads and stores; same sums in the same order as
+// the scalar kernels.
+__global__ void k_pool_fwd8(const bf16 *in, int32_t ldi, int32_t coff, int32_t C, int32_t H, int32_t W, bf16 *out)
+{
+    const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(Ho) * Wo * C8) return;
+    const int c8 = int(e % C8);
+    const int64_t q = e / C8;
+    const int i = int(q / Wo), j = int(q % Wo);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int y = 2 * i + dy, x = 2 * j + dx;
+            if (y < 0 || y >= H || x < 0 || x >= W) continue;
+            const uint4 v = *reinterpret_cast<const uint4 *>(in + (int64_t(y) * W + x) * ldi + coff + c8 * 8);
+            const bf16 *b = reinterpret_cast<const bf16 *>(&v);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s[k] += bf2f(b[k]);
+        }
+    bf16 o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = f2bf(s[k] * (1.0f / 9.0f));
+    *reinterpret_cast<uint4 *>(out + q * C + c8 * 8) = *reinterpret_cast<const uint4 *>(o);
+}
+
+__global__ void k_pool_bwd8(const bf16 *dout, int32_t C, int32_t H, int32_t W, bf16 *din, int32_t ldi, int32_t coff,
+                            int32_t accumulate, const bf16 *act_y, float slope)
+{
+    const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(H) * W * C8) return;
+    const int c8 = int(e % C8);
+    const int64_t q = e / C8;
+    const int y = int(q / W), x = int(q % W);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int i = (y - 1 + 1) / 2; i <= (y + 1) / 2; ++i) {
+        if (i < 0 || i >= Ho || 2 * i - y > 1 || y - 2 * i > 1) continue;
+        for (int j = (x - 1 + 1) / 2; j <= (x + 1) / 2; ++j) {
+            if (j < 0 || j >= Wo || 2 * j - x > 1 || x - 2 * j > 1) continue;
+            const uint4 v = *reinterpret_cast<const uint4 *>(dout + (int64_t(i) * Wo + j) * C + c8 * 8);
+            const bf16 *b = reinterpret_cast<const bf16 *>(&v);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s[k] += bf2f(b[k]);
+        }
+    }
+    bf16 *dst = din + q * ldi + coff + c8 * 8;
+    float prev[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (accumulate) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(dst);
+        const bf16 *b = reinterpret_cast<const bf16 *>(&v);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) prev[k] = bf2f(b[k]);
+    }
+    float yy[8] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
+    if (act_y) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(act_y + q * ldi + coff + c8 * 8);
+        const bf16 *b = reinterpret_cast<const bf16 *>(&v);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) yy[k] = bf2f(b[k]);
+    }
+    bf16 o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        float v = s[k] * (1.0f / 9.0f);
+        if (accumulate) v += prev[k];
+        if (act_y && !(yy[k] > 0.f)) v *= slope;
+        o[k] = f2bf(v);
+    }
+    *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(o);
+}
+
+// Backward of the 1x1 output convolution for C a multiple of 8 with C/8 <=
+// 256: a block of 256 pixels; thread t takes the 8-channel chunk t % (C/8)
+// of every (256 / (C/8))-th pixel, writes dx = w dy (times the activation
+// derivative at x) with 16-byte stores and sums dy x per channel; the sums
+// of the block are combined in LDS in a fixed order into part_w[block][C]
+// and the sum of dy into part_w[block][C].
+__global__ __launch_bounds__(256) void k_outc_bwd8(const bf16 *x, int32_t C, int32_t P, const float *w,
+                                                   const float *dy, bf16 *dx, float *part_w, float slope)
+{
+    __shared__ float red[2048 + 256];
+    const int C8 = C / 8, rows = 256 / C8;
+    const int tid = threadIdx.x, cc = tid % C8, ps = tid / C8;
+    const int p0 = blockIdx.x * 256;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, sd = 0.f;
+    float wc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) wc[k] = w[cc * 8 + k];
+    if (ps < rows) {
+        for (int p = p0 + ps; p < min(P, p0 + 256); p += rows) {
+            const float d = dy[p];
+            const uint4 v = *reinterpret_cast<const uint4 *>(x + int64_t(p) * C + cc * 8);
+            const bf16 *xb = reinterpret_cast<const bf16 *>(&v);
+            bf16 o[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float xv = bf2f(xb[k]);
+                const float gx = wc[k] * d;
+                o[k] = f2bf(xv > 0.f ? gx : slope * gx);
+                s[k] += d * xv;
+            }
+            sd += d;
+            *reinterpret_cast<uint4 *>(dx + int64_t(p) * C + cc * 8) = *reinterpret_cast<const uint4 *>(o);
+        }
+        // rows x C channel sums, then rows sums of dy
+#pragma unroll
+        for (int k = 0; k < 8; ++k) red[ps * C + cc * 8 + k] = s[k];
+        if (cc == 0) red[2048 + ps] = sd;
+    }
+    __syncthreads();
+    for (int c = tid; c <= C; c += 256) {
+        float t = 0.f;
+        if (c < C)
+            for (int r = 0; r < rows; ++r) t += red[r * C + c];
+        else
+            for (int r = 0; r < rows; ++r) t += red[2048 + r];
+        part_w[int64_t(blockIdx.x) * (C + 1) + c] = t;
+    }
+}
+
+// max |x| in two passes: per-block maxima, then the maximum of those (the
+// result does not depend on the order)
+__global__ __launch_bounds__(256) void k_absmax_part(const float *x, int64_t n, float *part)
+{
+    __shared__ float red[256];
+    float m = 0.f;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) m = fmaxf(m, fabsf(x[i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + k]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 __global__ void k_outc_fwd(const bf16 *x, int32_t C, int32_t P, const float *w, const float *b, float *y)
@@ -953,7 +1356,7 @@ __global__ __launch_bounds__(256) void k_mse(const float *y, const float *t, int
 }
 
 __global__ __launch_bounds__(256) void k_outc_bwd(const bf16 *x, int32_t C, int32_t P, const float *w,
-                                                  const float *dy, bf16 *dx, float *part_w)
+                                                  const float *dy, bf16 *dx, float *part_w, float slope)
 {
     // block of 256 pixels; part_w[block][c] for c < C, part_w[block][C] = sum dy
     __shared__ float red[256];
@@ -964,7 +1367,8 @@ __global__ __launch_bounds__(256) void k_outc_bwd(const bf16 *x, int32_t C, int3
         if (p < P) {
             if (c < C) {
                 const float xv = bf2f(x[int64_t(p) * C + c]);
-                dx[int64_t(p) * C + c] = f2bf(w[c] * d);
+                const float gx = w[c] * d;
+                dx[int64_t(p) * C + c] = f2bf(xv > 0.f ? gx : slope * gx);
                 v = d * xv;
             } else {
                 v = d;
@@ -1035,6 +1439,51 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, bf16 *pb, i
     pb[i] = f2bf(pi);
 }
 
+// The bf16 data-gradient matrices from the bf16 weights, a transpose through
+// LDS in 32 x 64 tiles (coalesced on both sides). Weight tensor s is an R x
+// C matrix at pb + off: a 3x3 convolution [co][tap*Cin + ci] (R = Cout, C =
+// 9 Cin) going to aux[ci][(8 - tap)*Cout + co]; a 2x2 transposed convolution
+// [ab*Cout + co][ci] (R = 4 Cout, C = Cin) going to aux[ci][ab*Cout + co].
+// Block t is tile t - tile0[s] of tensor s (row-major over the tiles).
+__global__ __launch_bounds__(256) void k_aux_from_pb(const AuxSeg *segs, int32_t nseg, const bf16 *pb, bf16 *aux)
+{
+    __shared__ bf16 tl[32][65];
+    const int64_t t = blockIdx.x;
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (segs[mid].tile0 <= t) lo = mid;
+        else hi = mid;
+    }
+    const AuxSeg sg = segs[lo];
+    const int R = sg.kind == 0 ? sg.cout : 4 * sg.cout;
+    const int C = sg.kind == 0 ? 9 * sg.cin : sg.cin;
+    const int tc = (C + 63) / 64;
+    const int64_t local = t - sg.tile0;
+    const int r0 = int(local / tc) * 32, c0 = int(local % tc) * 64;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int e = tid + 256 * i, r = e >> 6, c = e & 63;
+        if (r0 + r < R && c0 + c < C) tl[r][c] = pb[sg.off + int64_t(r0 + r) * C + c0 + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int e = tid + 256 * i, c = e >> 5, r = e & 31;
+        if (r0 + r >= R || c0 + c >= C) continue;
+        const int cc = c0 + c;
+        int64_t dst;
+        if (sg.kind == 0) {
+            const int tap = cc / sg.cin, ci = cc - tap * sg.cin;
+            dst = int64_t(ci) * 9 * sg.cout + int64_t(8 - tap) * sg.cout + r0 + r;
+        } else {
+            dst = int64_t(cc) * R + r0 + r;
+        }
+        aux[sg.aux_off + dst] = tl[r][c];
+    }
+}
+
 __global__ void k_to_bf16(const float *x, bf16 *y, int64_t n)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1094,28 +1543,6 @@ __global__ void k_fill_f(float *p, int64_t n, float v)
     if (i < n) p[i] = v;
 }
 
-// data-gradient weights of a 3x3 conv: wt[ci][t*Cout + co] = w[co][(8-t)*Cin + ci]
-__global__ void k_weight_flip(const float *w, int32_t Cout, int32_t Cin, bf16 *wt)
-{
-    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= int64_t(Cout) * Cin * 9) return;
-    const int ci = int(e / (9 * Cout));
-    const int rem = int(e % (9 * Cout));
-    const int t = rem / Cout, co = rem % Cout;
-    wt[e] = f2bf(w[int64_t(co) * 9 * Cin + (8 - t) * Cin + ci]);
-}
-
-// data-gradient weights of a 2x2 stride-2 transposed conv:
-// out[ci][ab*Cout + co] = wt[(ab*Cout + co)][ci]
-__global__ void k_convt_dgrad_w(const float *wt, int32_t Cin, int32_t Cout, bf16 *out)
-{
-    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= int64_t(4) * Cout * Cin) return;
-    const int ci = int(e / (4 * Cout));
-    const int r = int(e % (4 * Cout));
-    out[e] = f2bf(wt[int64_t(r) * Cin + ci]);
-}
-
 inline unsigned nblocks(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
 }  // namespace
@@ -1146,9 +1573,14 @@ hipError_t conv1_wgrad(const bf16 *dz, int32_t ld, int32_t zoff, const bf16 *x, 
     return hipGetLastError();
 }
 
-hipError_t gemm(const GemmArgs &a, hipStream_t s)
+hipError_t gemm(const GemmArgs &a_in, hipStream_t s)
 {
-    if (a.M <= 0 || a.N <= 0) return hipSuccess;
+    if (a_in.M <= 0 || a_in.N <= 0) return hipSuccess;
+    GemmArgs a = a_in;
+    // 8-byte epilogue stores of 4 consecutive channels (and 16-byte split-K
+    // partials) when every channel offset and stride allows them
+    a.out_vec = a.M % 4 == 0 && a.out_ld % 4 == 0 && a.out_coff % 4 == 0 && (!a.scatter || a.Cout % 4 == 0) &&
+                (!a.act_y || (a.act_ld % 4 == 0 && a.act_coff % 4 == 0));
     const bool vec = a.K % kBK == 0 && a.g.Cb % 8 == 0 && a.lda % 8 == 0 && a.g.ld % 8 == 0 && a.g.coff % 8 == 0;
     // thin outputs use 32 x 256 tiles, wide ones 64 x 128; small problems
     // (the coarse levels) keep 64 x 64 tiles so that enough blocks run
@@ -1170,45 +1602,76 @@ hipError_t gemm(const GemmArgs &a, hipStream_t s)
         }
     } else if (a.M <= 32) {
         const dim3 grid(nblocks(a.N, 256), nblocks(a.M, 32));
-        if (vec) hipLaunchKernelGGL((k_gemm<1, 4, 2, true>), grid, dim3(256), 0, s, a);
+        if (vec) hipLaunchKernelGGL((k_gemm_v<1, 4, 2, 4>), grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_gemm<1, 4, 2, false>), grid, dim3(256), 0, s, a);
     } else if (blocks_wide >= 512) {
         const dim3 grid(nblocks(a.N, 128), nblocks(a.M, 64));
-        if (vec) hipLaunchKernelGGL((k_gemm<2, 2, 2, true>), grid, dim3(256), 0, s, a);
+        if (vec) hipLaunchKernelGGL((k_gemm_v<2, 2, 2, 4>), grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_gemm<2, 2, 2, false>), grid, dim3(256), 0, s, a);
     } else {
         const dim3 grid(nblocks(a.N, 64), nblocks(a.M, 64));
-        if (vec) hipLaunchKernelGGL((k_gemm<2, 2, 1, true>), grid, dim3(256), 0, s, a);
+        if (vec) hipLaunchKernelGGL((k_gemm_v<2, 2, 1, 4>), grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_gemm<2, 2, 1, false>), grid, dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }
 
-hipError_t wgrad(const WgradArgs &a, hipStream_t s)
+bool wgrad_vec(const WgradArgs &a)
 {
-    if (a.M <= 0 || a.N <= 0) return hipSuccess;
-    const bool vec = a.g.Cb % 8 == 0 && a.lda % 8 == 0 && a.acoff % 8 == 0 && a.g.ld % 8 == 0 &&
-                     a.g.coff % 8 == 0 && a.M % 8 == 0 && a.N % 8 == 0;
-    if (vec && a.tile == 128 && a.chunk % 64 == 0) {
-        const dim3 grid(nblocks(a.N, 128), nblocks(a.M, 128), unsigned(a.nsplit));
-        hipLaunchKernelGGL(k_wgrad2, grid, dim3(256), 0, s, a);
-    } else if (vec && a.M <= 32 && a.chunk % 64 == 0) {
-        const dim3 grid(nblocks(a.N, 128), 1, unsigned(a.nsplit));
-        hipLaunchKernelGGL(k_wgrad_m32, grid, dim3(256), 0, s, a);
-    } else {
-        const dim3 grid(nblocks(a.N, 64), nblocks(a.M, 64), unsigned(a.nsplit));
-        if (vec) hipLaunchKernelGGL(k_wgrad<true>, grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL(k_wgrad<false>, grid, dim3(256), 0, s, a);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(int64_t(a.M) * a.N)), dim3(256), 0, s, a.partial, a.M, a.N,
-                       a.nsplit, a.out, a.ldm, a.ldn);
-    e = hipGetLastError();
-    if (e != hipSuccess || !a.bias_partial) return e;
-    hipLaunchKernelGGL(k_sum_rows, dim3(nblocks(a.M)), dim3(256), 0, s, a.bias_partial, a.nsplit, a.M, a.bias_out);
+    return a.g.Cb % 8 == 0 && a.lda % 8 == 0 && a.acoff % 8 == 0 && a.g.ld % 8 == 0 && a.g.coff % 8 == 0 &&
+           a.M % 8 == 0 && a.N % 8 == 0 && a.chunk % 64 == 0;
+}
+
+int64_t wgrad_finish_count(const WgradArgs &a)
+{
+    if (a.M <= 0 || a.N <= 0 || !wgrad_vec(a)) return 0;
+    const int64_t nw = a.nsplit > 1 ? int64_t(a.M) * a.N : 0;
+    const int64_t nb = !a.bias_partial ? 0 : (a.bias_from_b ? a.g.Cb : (a.nsplit > 1 ? a.M : 0));
+    return nw + nb;
+}
+
+hipError_t wgrad_finish_all(const WgradArgs *tab, const int64_t *bbeg, int32_t n, int64_t nblk, hipStream_t s)
+{
+    if (n <= 0 || nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_wgrad_finish_all, dim3(unsigned(nblk)), dim3(256), 0, s, tab, bbeg, n);
     return hipGetLastError();
 }
+
+hipError_t wgrad(const WgradArgs &a, hipStream_t s, bool defer_finish)
+{
+    if (a.M <= 0 || a.N <= 0) return hipSuccess;
+    if (a.nsplit < 1) return hipErrorInvalidValue;
+    const bool vec = wgrad_vec(a);
+    if (!vec) {
+        // generic path (unaligned channels): partials, then the ordered sums
+        if (a.bias_from_b) return hipErrorInvalidValue;
+        const dim3 grid(nblocks(a.N, 64), nblocks(a.M, 64), unsigned(a.nsplit));
+        hipLaunchKernelGGL(k_wgrad<false>, grid, dim3(256), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(int64_t(a.M) * a.N)), dim3(256), 0, s, a.partial, a.M, a.N,
+                           a.nsplit, a.out, a.ldm, a.ldn);
+        e = hipGetLastError();
+        if (e != hipSuccess || !a.bias_partial) return e;
+        hipLaunchKernelGGL(k_sum_rows, dim3(nblocks(a.M)), dim3(256), 0, s, a.bias_partial, a.nsplit, a.M,
+                           a.bias_out);
+        return hipGetLastError();
+    }
+    const dim3 grid(nblocks(a.N, a.bn), nblocks(a.M, a.bm), unsigned(a.nsplit));
+    if (a.bm == 128 && a.bn == 128) hipLaunchKernelGGL((k_wgrad_t<128, 128, 3>), grid, dim3(256), 0, s, a);
+    else if (a.bm == 64 && a.bn == 128) hipLaunchKernelGGL((k_wgrad_t<64, 128, 3>), grid, dim3(256), 0, s, a);
+    else if (a.bm == 32 && a.bn == 128) hipLaunchKernelGGL((k_wgrad_t<32, 128, 3>), grid, dim3(256), 0, s, a);
+    else if (a.bm == 64 && a.bn == 64) hipLaunchKernelGGL((k_wgrad_t<64, 64, 3>), grid, dim3(256), 0, s, a);
+    else return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // one split and a bias from A: the first pass wrote everything
+    if ((a.nsplit == 1 && !a.bias_from_b) || defer_finish) return hipSuccess;
+    const int64_t nbias = a.bias_partial ? (a.bias_from_b ? a.g.Cb : a.M) : 0;
+    hipLaunchKernelGGL(k_wgrad_finish, dim3(nblocks(int64_t(a.M) * a.N + nbias)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 
 hipError_t bias_grad(const bf16 *dz, int32_t ld, int32_t coff, int32_t C, int32_t P, float *db, float *scratch,
                      int32_t nsplit, hipStream_t s);
@@ -1224,16 +1687,26 @@ hipError_t act_bwd(bf16 *dz, int32_t ldz, int32_t zoff, const bf16 *dy, int32_t 
 hipError_t pool_fwd(const bf16 *in, int32_t ldi, int32_t coff, int32_t C, int32_t H, int32_t W, bf16 *out,
                     hipStream_t s)
 {
+    if (C % 8 == 0 && ldi % 8 == 0 && coff % 8 == 0) {
+        hipLaunchKernelGGL(k_pool_fwd8, dim3(nblocks(int64_t(H / 2) * (W / 2) * (C / 8))), dim3(256), 0, s, in, ldi,
+                           coff, C, H, W, out);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks(int64_t(H / 2) * (W / 2) * C)), dim3(256), 0, s, in, ldi, coff, C, H,
                        W, out);
     return hipGetLastError();
 }
 
 hipError_t pool_bwd(const bf16 *dout, int32_t C, int32_t H, int32_t W, bf16 *din, int32_t ldi, int32_t coff,
-                    int32_t accumulate, hipStream_t s)
+                    int32_t accumulate, const bf16 *act_y, float slope, hipStream_t s)
 {
+    if (C % 8 == 0 && ldi % 8 == 0 && coff % 8 == 0) {
+        hipLaunchKernelGGL(k_pool_bwd8, dim3(nblocks(int64_t(H) * W * (C / 8))), dim3(256), 0, s, dout, C, H, W, din,
+                           ldi, coff, accumulate, act_y, slope);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_pool_bwd, dim3(nblocks(int64_t(H) * W * C)), dim3(256), 0, s, dout, C, H, W, din, ldi, coff,
-                       accumulate);
+                       accumulate, act_y, slope);
     return hipGetLastError();
 }
 
@@ -1251,10 +1724,14 @@ hipError_t mse(const float *y, const float *t, int32_t P, double *partials, int3
 }
 
 hipError_t outc_bwd(const bf16 *x, int32_t C, int32_t P, const float *w, const float *dy, bf16 *dx, float *part_w,
-                    int32_t nblk, hipStream_t s)
+                    int32_t nblk, float slope, hipStream_t s)
 {
     (void)nblk;
-    hipLaunchKernelGGL(k_outc_bwd, dim3(nblocks(P)), dim3(256), 0, s, x, C, P, w, dy, dx, part_w);
+    if (C % 8 == 0 && C <= 2048) {
+        hipLaunchKernelGGL(k_outc_bwd8, dim3(nblocks(P)), dim3(256), 0, s, x, C, P, w, dy, dx, part_w, slope);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_outc_bwd, dim3(nblocks(P)), dim3(256), 0, s, x, C, P, w, dy, dx, part_w, slope);
     return hipGetLastError();
 }
 
@@ -1277,15 +1754,25 @@ hipError_t adam(float *p, const float *g, float *m, float *v, bf16 *pb, int64_t 
     return hipGetLastError();
 }
 
+hipError_t aux_from_pb(const AuxSeg *segs, int32_t nseg, int64_t ntiles, const bf16 *pb, bf16 *aux, hipStream_t s)
+{
+    if (nseg <= 0 || ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_aux_from_pb, dim3(unsigned(ntiles)), dim3(256), 0, s, segs, nseg, pb, aux);
+    return hipGetLastError();
+}
+
 hipError_t to_bf16(const float *x, bf16 *y, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_to_bf16, dim3(nblocks(n)), dim3(256), 0, s, x, y, n);
     return hipGetLastError();
 }
 
-hipError_t absmax(const float *x, int64_t n, float *out, hipStream_t s)
+hipError_t absmax(const float *x, int64_t n, float *out, float *part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, x, n, out);
+    hipLaunchKernelGGL(k_absmax_part, dim3(kAbsmaxBlocks), dim3(256), 0, s, x, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, part, int64_t(kAbsmaxBlocks), out);
     return hipGetLastError();
 }
 
@@ -1309,18 +1796,6 @@ hipError_t fill_f(float *p, int64_t n, float v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_f, dim3(nblocks(n)), dim3(256), 0, s, p, n, v);
-    return hipGetLastError();
-}
-
-hipError_t weight_flip(const float *w, int32_t Cout, int32_t Cin, bf16 *wt, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_weight_flip, dim3(nblocks(int64_t(Cout) * Cin * 9)), dim3(256), 0, s, w, Cout, Cin, wt);
-    return hipGetLastError();
-}
-
-hipError_t convt_dgrad_weights(const float *wt, int32_t Cin, int32_t Cout, bf16 *out, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_convt_dgrad_w, dim3(nblocks(int64_t(4) * Cout * Cin)), dim3(256), 0, s, wt, Cin, Cout, out);
     return hipGetLastError();
 }
 

@@ -279,9 +279,15 @@ def test_checkpoint_schedules_give_the_same_bits(emu_driver, tmp_path, pml):
 
 # (depth, base width, grid) -> kernels the configuration must reach
 NET_CASES = {
-    (3, 32, 40, 56): ("k_gemm<", "k_wgrad<", "k_wgrad_m32", "k_pool_fwd", "k_conv1_fwd"),   # odd coarse levels (5 x 7)
-    (1, 128, 64, 240): ("k_gemm2", "k_gemm_finish", "k_wgrad2", "k_conv1_wgrad"),  # wide level 0
-    (2, 256, 16, 16): ("k_gemm_finish", "k_bias_part"),  # deep, narrow: split K with the scatter epilogue
+    # odd coarse levels (5 x 7); weight-gradient tiles of 32, 64 and 128 rows
+    (3, 32, 40, 56): ("k_gemm_v<", "k_wgrad_t<32, 128,", "k_wgrad_t<64, 128,", "k_wgrad_t<128, 128,", "k_pool_fwd",
+                      "k_conv1_fwd", "k_wgrad_finish"),
+    (1, 128, 64, 240): ("k_gemm2", "k_gemm_finish", "k_wgrad_t<128, 128,", "k_conv1_wgrad"),  # wide level 0
+    # deep, narrow: split K with the scatter epilogue; bias of the transposed
+    # convolutions from the gathered gradient
+    (2, 256, 16, 16): ("k_gemm_finish", "k_wgrad_finish"),
+    # narrow transposed convolution (N = 4 x 8): 64 x 64 weight-gradient tiles
+    (1, 8, 32, 48): ("k_wgrad_t<64, 64,",),
 }
 
 
