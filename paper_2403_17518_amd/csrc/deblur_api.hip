@@ -76,7 +76,7 @@ struct deblur_net {
     // each weight gradient of a backward pass takes its own stretch of wpart
     // and bpart (cursors reset per pass), so that the second passes of all of
     // them run as one launch at the end of the pass: their arguments (fin),
-    // the blocks of 64 outputs before each (fin_begin), and the device copies
+    // the finish blocks before each (fin_begin), and the device copies
     int64_t wp_cursor = 0, bp_cursor = 0;
     std::vector<WgradArgs> fin, fin_dev_copy;
     std::vector<int64_t> fin_begin, fin_beg_copy;
@@ -511,13 +511,15 @@ float *take_b(deblur_net *n, int64_t floats)
     return p;
 }
 
-void defer_finish(deblur_net *n, const WgradArgs &w)
+void defer_finish(deblur_net *n, WgradArgs w)
 {
     const int64_t cnt = wgrad_finish_count(w);
     if (cnt == 0) return;
+    w.fin_groups = wgrad_finish_groups(w);
+    const int64_t per = kFinishOutputs / w.fin_groups;
     if (n->fin_begin.empty()) n->fin_begin.push_back(0);
     n->fin.push_back(w);
-    n->fin_begin.push_back(n->fin_begin.back() + (cnt + 63) / 64);
+    n->fin_begin.push_back(n->fin_begin.back() + (cnt + per - 1) / per);
 }
 
 // the deferred second passes of this backward pass, in one launch; the
@@ -806,10 +808,14 @@ int deblur_create(fwi_ctx *ctx, const deblur_cfg *cfg, uint64_t seed, deblur_net
         int64_t aux = 0;
         for (const Entry &e : n->entries) {
             if (e.kind != KW3 && e.kind != KWT) continue;
+            if (e.kind == KW3 && e.cin == 1) {   // the input layer: no data gradient is formed
+                aux += e.n;
+                continue;
+            }
             const int R = e.kind == KW3 ? e.cout : 4 * e.cout, C = e.kind == KW3 ? 9 * e.cin : e.cin;
             n->h_segs.push_back(AuxSeg{e.off, e.n, aux, n->aux_tiles, e.kind == KW3 ? 0 : 1, e.cin, e.cout, 0});
             aux += e.n;
-            n->aux_tiles += int64_t((R + 31) / 32) * ((C + 63) / 64);
+            n->aux_tiles += int64_t((R + 63) / 64) * ((C + 63) / 64);
         }
         rc = alloc(n, n->segs, n->h_segs.size() * sizeof(AuxSeg));
         if (rc == FWI_OK && hipMemcpyAsync(n->segs.p, n->h_segs.data(), n->h_segs.size() * sizeof(AuxSeg),

@@ -77,6 +77,7 @@ struct WgradArgs {
     float *bias_partial;
     float *bias_out;
     int32_t bias_from_b;
+    int32_t fin_groups;     // deferred second pass: split groups per output (wgrad_finish_groups)
 };
 
 hipError_t gemm(const GemmArgs &a, hipStream_t s);
@@ -91,8 +92,12 @@ hipError_t conv1_wgrad(const bf16 *dz, int32_t ld, int32_t zoff, const bf16 *x, 
 // path always finishes itself (count 0)
 hipError_t wgrad(const WgradArgs &a, hipStream_t s, bool defer_finish = false);
 int64_t wgrad_finish_count(const WgradArgs &a);
+// split groups of a deferred second pass (1, 2, 4 or 8); its finish blocks
+// cover kFinishOutputs / groups outputs each
+int wgrad_finish_groups(const WgradArgs &a);
 // the deferred second passes of n weight gradients (device table tab; entry
-// l owns blocks bbeg[l] .. bbeg[l+1]-1 of 64 outputs, nblk = bbeg[n])
+// l owns blocks bbeg[l] .. bbeg[l+1]-1, nblk = bbeg[n])
+constexpr int kFinishOutputs = 1024;
 hipError_t wgrad_finish_all(const WgradArgs *tab, const int64_t *bbeg, int32_t n, int64_t nblk, hipStream_t s);
 // bias gradient: db[c] = sum_p dz[p][coff + c]; scratch holds nsplit * C floats
 hipError_t bias_grad(const bf16 *dz, int32_t ld, int32_t coff, int32_t C, int32_t P, float *db, float *scratch,
@@ -125,7 +130,7 @@ hipError_t adam(float *p, const float *g, float *m, float *v, bf16 *pb, int64_t 
 // A weight tensor and its bf16 data-gradient matrix at aux_off: kind 0, a
 // 3x3 convolution [co][tap][ci] -> [ci][(8 - tap)*Cout + co]; kind 1, a 2x2
 // transposed convolution [ab][co][ci] -> [ci][ab*Cout + co]. tile0: the
-// first of the tensor's 32 x 64 transpose tiles.
+// first of the tensor's 64 x 64 transpose tiles.
 struct AuxSeg {
     int64_t off, n, aux_off, tile0;
     int32_t kind, cin, cout, pad;

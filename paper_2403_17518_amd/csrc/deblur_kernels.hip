@@ -699,9 +699,11 @@ __global__ void k_gemm_finish(const GemmArgs a, int32_t ksplit)
 // 64-pixel K slices double-buffered in LDS (one barrier per slice). Both
 // operands are pixel-major in memory and channel-major in the matrix-core
 // layout, so they are transposed on the way into LDS: a task of 8 channels x
-// 4 pixels is four 16-byte loads and eight 8-byte LDS stores, and the 16
-// lanes that share a channel chunk take consecutive pixel groups, so each
-// store of a wave fills whole LDS rows. Requires M, N, Cb, lda, ld and the
+// 4 pixels is four 16-byte loads and eight 8-byte LDS stores. A wave's 64
+// tasks are 4 adjacent channel chunks x 16 pixel groups (chunk fastest), so
+// a load instruction reads 64 contiguous bytes of each of 16 pixels; the
+// 16-byte chunk of an LDS row is XOR-swizzled by bit 4 of the row, which
+// keeps the four rows a store instruction writes on distinct banks. Requires M, N, Cb, lda, ld and the
 // channel offsets to be multiples of 8 and the split (chunk) a multiple of
 // 64. The loads of the next DEPTH slices are in flight while a slice is
 // computed (a ring of DEPTH register stages). With one split the sums go
@@ -729,7 +731,7 @@ __global__ __launch_bounds__(256) void k_wgrad_t(const WgradArgs a)
     const int p_lo = blockIdx.z * a.chunk;
     const int p_hi = min(P, p_lo + a.chunk);
     const int nk = p_hi > p_lo ? (p_hi - p_lo + BK - 1) / BK : 0;
-    const int pg = tid & 15;   // group of 4 pixels within the slice
+    const int pg = (tid >> 2) & 15;   // group of 4 pixels within the slice
 
     // the task of each round: operand, 8-channel chunk, source offsets
     bool act[NR], isA[NR], val[NR];
@@ -739,7 +741,10 @@ __global__ __launch_bounds__(256) void k_wgrad_t(const WgradArgs a)
         const int t = tid + 256 * r;
         act[r] = t < TA + TB;
         isA[r] = t < TA;
-        cc[r] = isA[r] ? t >> 4 : (t - TA) >> 4;
+        {
+            const int u = isA[r] ? t : t - TA;   // 4 chunks x 16 pixel groups per wave
+            cc[r] = (u & 3) | ((u >> 6) << 2);
+        }
         ty[r] = tx[r] = ch[r] = 0;
         if (isA[r]) {
             val[r] = act[r] && m0 + cc[r] * 8 < a.M;
@@ -785,13 +790,15 @@ __global__ __launch_bounds__(256) void k_wgrad_t(const WgradArgs a)
         for (int r = 0; r < NR; ++r) {
             if (!act[r]) continue;
             bf16 *base = isA[r] ? &As[buf][cc[r] * 8 * LDK] : &Bs[buf][cc[r] * 8 * LDK];
+            // 16-byte chunk pg/2 of the row, swizzled by bit 4 of the row
+            const int col = (((pg >> 1) ^ (((cc[r] >> 1) & 1) << 2)) << 3) + (pg & 1) * 4;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const uint32_t lo = reinterpret_cast<const uint16_t *>(&rg[sl][r][0])[e] |
                                     (uint32_t(reinterpret_cast<const uint16_t *>(&rg[sl][r][1])[e]) << 16);
                 const uint32_t hi = reinterpret_cast<const uint16_t *>(&rg[sl][r][2])[e] |
                                     (uint32_t(reinterpret_cast<const uint16_t *>(&rg[sl][r][3])[e]) << 16);
-                *reinterpret_cast<uint2 *>(base + e * LDK + pg * 4) = make_uint2(lo, hi);
+                *reinterpret_cast<uint2 *>(base + e * LDK + col) = make_uint2(lo, hi);
             }
         }
     };
@@ -842,14 +849,19 @@ __global__ __launch_bounds__(256) void k_wgrad_t(const WgradArgs a)
 #pragma unroll
                 for (int kk = 0; kk < BK / 16; ++kk) {
                     bf16x8 av[XM], bv[YN];
+                    const int jj = kk * 2 + lane / 32;   // 16-byte chunk of the row
 #pragma unroll
-                    for (int x = 0; x < XM; ++x)
+                    for (int x = 0; x < XM; ++x) {
+                        const int row = (wm * XM + x) * 32 + lane % 32;
                         av[x] = *reinterpret_cast<const bf16x8 *>(
-                            &As[buf][((wm * XM + x) * 32 + lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
+                            &As[buf][row * LDK + ((jj ^ (((row >> 4) & 1) << 2)) << 3)]);
+                    }
 #pragma unroll
-                    for (int y = 0; y < YN; ++y)
+                    for (int y = 0; y < YN; ++y) {
+                        const int row = (wn * YN + y) * 32 + lane % 32;
                         bv[y] = *reinterpret_cast<const bf16x8 *>(
-                            &Bs[buf][((wn * YN + y) * 32 + lane % 32) * LDK + kk * 16 + 8 * (lane / 32)]);
+                            &Bs[buf][row * LDK + ((jj ^ (((row >> 4) & 1) << 2)) << 3)]);
+                    }
 #pragma unroll
                     for (int x = 0; x < XM; ++x)
 #pragma unroll
@@ -873,7 +885,7 @@ __global__ __launch_bounds__(256) void k_wgrad_t(const WgradArgs a)
             for (int e = 0; e < 8; ++e) {
                 float v = bs[r][e];
 #pragma unroll
-                for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                for (int off = 32; off >= 4; off >>= 1) v += __shfl_xor(v, off);
                 bs[r][e] = v;
             }
             const bool on = isA[r] ? bias_a : bias_b;
@@ -936,13 +948,15 @@ __global__ void k_wgrad_finish(const WgradArgs a)
 
 // All deferred second passes of one backward pass in one launch. Entry l of
 // tab owns the blocks [bbeg[l], bbeg[l+1]) (its split weight sums, then its
-// bias sums, 64 outputs per block), so the entry is the same for the whole
-// block. Wave g of a block sums the splits z = g, g + 4, ... of each of the
-// block's 64 outputs; the four sums are added in LDS in a fixed order.
+// bias sums), so the entry is the same for the whole block and is looked up
+// once. The entry's fin_groups G (1, 2, 4 or 8) splits a block's threads into
+// G groups over the splits: thread (g, j) sums the splits z = g, g + G, ...
+// of outputs j, j + 256/G, j + 512/G and j + 768/G of the block's 1024/G
+// (eight loads in flight), and the G sums of an output are added in LDS in
+// a fixed order.
 __global__ __launch_bounds__(256) void k_wgrad_finish_all(const WgradArgs *tab, const int64_t *bbeg, int32_t n)
 {
-    __shared__ float red[4][64];
-    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    __shared__ float red[256];
     const int64_t blk = blockIdx.x;
     int lo = 0, hi = n;   // the entry holding the block: bbeg[lo] <= blk < bbeg[lo + 1]
     while (hi - lo > 1) {
@@ -951,37 +965,43 @@ __global__ __launch_bounds__(256) void k_wgrad_finish_all(const WgradArgs *tab, 
         else hi = mid;
     }
     const WgradArgs a = tab[lo];
-    const int64_t k = (blk - bbeg[lo]) * 64 + lane;
+    const int G = a.fin_groups, W = 256 / G;
+    const int g = threadIdx.x / W, j = threadIdx.x - g * W;
     const int64_t MN = int64_t(a.M) * a.N;
     const int64_t nw = a.nsplit > 1 ? MN : 0;
     const int64_t nb = a.bias_partial ? (a.bias_from_b ? a.g.Cb : (a.nsplit > 1 ? a.M : 0)) : 0;
-    float t = 0.f;
-    if (k < nw) {
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-        int z = grp;
-        for (; z + 12 < a.nsplit; z += 16) {
-            s0 += a.partial[int64_t(z) * MN + k];
-            s1 += a.partial[int64_t(z + 4) * MN + k];
-            s2 += a.partial[int64_t(z + 8) * MN + k];
-            s3 += a.partial[int64_t(z + 12) * MN + k];
+    const int64_t k0 = (blk - bbeg[lo]) * (kFinishOutputs / G) + j;
+    for (int q = 0; q < 4; ++q) {
+        const int64_t k = k0 + int64_t(W) * q;
+        float t = 0.f;
+        if (k < nw) {
+            float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            const float *p = a.partial + k;
+            int z = g;
+            for (; z + 7 * G < a.nsplit; z += 8 * G)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s[u] += p[int64_t(z + u * G) * MN];
+            for (; z < a.nsplit; z += G) s[0] += p[int64_t(z) * MN];
+            t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+        } else if (k < nw + nb) {
+            const int c = int(k - nw);
+            const int len = a.bias_from_b ? a.N : a.M;
+            const int ntap = a.bias_from_b ? a.N / a.g.Cb : 1;
+            for (int tap = 0; tap < ntap; ++tap) {
+                const float *bp = a.bias_partial + tap * (a.bias_from_b ? a.g.Cb : 0) + c;
+                for (int z = g; z < a.nsplit; z += G) t += bp[int64_t(z) * len];
+            }
         }
-        for (; z < a.nsplit; z += 4) s0 += a.partial[int64_t(z) * MN + k];
-        t = (s0 + s1) + (s2 + s3);
-    } else if (k < nw + nb) {
-        const int c = int(k - nw);
-        const int len = a.bias_from_b ? a.N : a.M;
-        const int ntap = a.bias_from_b ? a.N / a.g.Cb : 1;
-        for (int tap = 0; tap < ntap; ++tap) {
-            const float *bp = a.bias_partial + tap * (a.bias_from_b ? a.g.Cb : 0) + c;
-            for (int z = grp; z < a.nsplit; z += 4) t += bp[int64_t(z) * len];
+        red[threadIdx.x] = t;
+        __syncthreads();
+        if (g == 0 && k < nw + nb) {
+            float v = red[j];
+            for (int h = 1; h < G; ++h) v += red[h * W + j];
+            if (k < nw) a.out[(k / a.N) * a.ldm + (k % a.N) * a.ldn] = v;
+            else a.bias_out[k - nw] = v;
         }
+        __syncthreads();
     }
-    red[grp][lane] = t;
-    __syncthreads();
-    if (grp != 0 || k >= nw + nb) return;
-    const float s = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-    if (k < nw) a.out[(k / a.N) * a.ldm + (k % a.N) * a.ldn] = s;
-    else a.bias_out[k - nw] = s;
 }
 
 __global__ void k_wgrad_reduce(const float *part, int32_t M, int32_t N, int32_t nsplit, float *out, int32_t ldm,
@@ -1440,14 +1460,15 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, bf16 *pb, i
 }
 
 // The bf16 data-gradient matrices from the bf16 weights, a transpose through
-// LDS in 32 x 64 tiles (coalesced on both sides). Weight tensor s is an R x
-// C matrix at pb + off: a 3x3 convolution [co][tap*Cin + ci] (R = Cout, C =
-// 9 Cin) going to aux[ci][(8 - tap)*Cout + co]; a 2x2 transposed convolution
-// [ab*Cout + co][ci] (R = 4 Cout, C = Cin) going to aux[ci][ab*Cout + co].
+// LDS in 64 x 64 tiles with 16-byte loads and stores (coalesced on both
+// sides). Weight tensor s is an R x C matrix at pb + off: a 3x3 convolution
+// [co][tap*Cin + ci] (R = Cout, C = 9 Cin) going to aux[ci][(8 - tap)*Cout +
+// co]; a 2x2 transposed convolution [ab*Cout + co][ci] (R = 4 Cout, C = Cin)
+// going to aux[ci][ab*Cout + co]. R, C, off and aux_off are multiples of 8.
 // Block t is tile t - tile0[s] of tensor s (row-major over the tiles).
 __global__ __launch_bounds__(256) void k_aux_from_pb(const AuxSeg *segs, int32_t nseg, const bf16 *pb, bf16 *aux)
 {
-    __shared__ bf16 tl[32][65];
+    __shared__ uint16_t tl[64][66];
     const int64_t t = blockIdx.x;
     int lo = 0, hi = nseg;
     while (hi - lo > 1) {
@@ -1460,27 +1481,37 @@ __global__ __launch_bounds__(256) void k_aux_from_pb(const AuxSeg *segs, int32_t
     const int C = sg.kind == 0 ? 9 * sg.cin : sg.cin;
     const int tc = (C + 63) / 64;
     const int64_t local = t - sg.tile0;
-    const int r0 = int(local / tc) * 32, c0 = int(local % tc) * 64;
+    const int r0 = int(local / tc) * 64, c0 = int(local % tc) * 64;
     const int tid = threadIdx.x;
+    // load: 64 rows x 8 chunks of 8 columns
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int e = tid + 256 * i, r = e >> 6, c = e & 63;
-        if (r0 + r < R && c0 + c < C) tl[r][c] = pb[sg.off + int64_t(r0 + r) * C + c0 + c];
+    for (int i = 0; i < 2; ++i) {
+        const int e = tid + 256 * i, r = e >> 3, ch = (e & 7) * 8;
+        if (r0 + r < R && c0 + ch < C) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(pb + sg.off + int64_t(r0 + r) * C + c0 + ch);
+            const uint16_t *h = reinterpret_cast<const uint16_t *>(&v);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) tl[r][ch + k] = h[k];
+        }
     }
     __syncthreads();
+    // store: 64 columns x 8 chunks of 8 rows
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int e = tid + 256 * i, c = e >> 5, r = e & 31;
-        if (r0 + r >= R || c0 + c >= C) continue;
+    for (int i = 0; i < 2; ++i) {
+        const int e = tid + 256 * i, c = e >> 3, rh = (e & 7) * 8;
+        if (r0 + rh >= R || c0 + c >= C) continue;
         const int cc = c0 + c;
         int64_t dst;
         if (sg.kind == 0) {
             const int tap = cc / sg.cin, ci = cc - tap * sg.cin;
-            dst = int64_t(ci) * 9 * sg.cout + int64_t(8 - tap) * sg.cout + r0 + r;
+            dst = int64_t(ci) * 9 * sg.cout + int64_t(8 - tap) * sg.cout + r0 + rh;
         } else {
-            dst = int64_t(cc) * R + r0 + r;
+            dst = int64_t(cc) * R + r0 + rh;
         }
-        aux[sg.aux_off + dst] = tl[r][c];
+        uint16_t h[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) h[k] = tl[rh + k][c];
+        *reinterpret_cast<uint4 *>(aux + sg.aux_off + dst) = *reinterpret_cast<const uint4 *>(h);
     }
 }
 
@@ -1620,6 +1651,11 @@ bool wgrad_vec(const WgradArgs &a)
 {
     return a.g.Cb % 8 == 0 && a.lda % 8 == 0 && a.acoff % 8 == 0 && a.g.ld % 8 == 0 && a.g.coff % 8 == 0 &&
            a.M % 8 == 0 && a.N % 8 == 0 && a.chunk % 64 == 0;
+}
+
+int wgrad_finish_groups(const WgradArgs &a)
+{
+    return a.nsplit >= 64 ? 8 : a.nsplit >= 32 ? 4 : a.nsplit >= 16 ? 2 : 1;
 }
 
 int64_t wgrad_finish_count(const WgradArgs &a)
