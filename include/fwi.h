@@ -158,7 +158,7 @@ typedef struct {
        advanced per launch */
     /* tilings by class: forward, adjoint, joint Born, scattered field */
     int32_t tile_cw[4], tile_rows[4], tile_levels[4];
-    int32_t tile_prefetch[4]; /* rows prefetched ahead (one-level kernels) */
+    int32_t tile_prefetch[4]; /* rows of loads issued ahead */
     int64_t graph_launches;   /* time loops replayed from a captured HIP graph */
     int64_t graph_captures;   /* time loops captured (first run of a loop) */
     int64_t recomputed_steps; /* forward time steps recomputed by the adjoint
@@ -208,8 +208,8 @@ int fwi_ctx_set_profiling(fwi_ctx *ctx, int enable);
  * 3 scattered field driven by a stored history (fwi_gradient_pair), -1 all;
  * cols_per_lane 1 or 2, rows_per_wave >= 1, levels_per_launch 1 or 2 (the
  * Born and scattered-field kernels always advance one level; the joint Born
- * kernel prefetches one row) and prefetch_rows 1 or 2 (rows of
- * loads issued ahead by one-level kernels; 0 = 2) force a tiling; all zero
+ * kernel prefetches one row) and prefetch_rows 1 or 2 (rows of loads
+ * issued ahead; 0 = 2 for one level, 1 for two) force a tiling; all zero
  * returns the kernel to the autotuner. Results do not depend on the tiling:
  * every variant computes each cell with the same arithmetic. */
 int fwi_ctx_set_tiling(fwi_ctx *ctx, int kernel, int cols_per_lane, int rows_per_wave,

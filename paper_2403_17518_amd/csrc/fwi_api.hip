@@ -1550,7 +1550,7 @@ const Candidate kTune[] = {
     {1, 8, 1, 1},  {1, 16, 1, 1}, {1, 24, 1, 1}, {1, 32, 1, 1}, {1, 48, 1, 1}, {2, 8, 1, 1},  {2, 16, 1, 1},
     {2, 24, 1, 1}, {2, 32, 1, 1}, {1, 8, 1, 2},  {1, 16, 1, 2}, {1, 24, 1, 2}, {1, 32, 1, 2}, {1, 48, 1, 2},
     {2, 8, 1, 2},  {2, 16, 1, 2}, {2, 24, 1, 2}, {2, 32, 1, 2}, {1, 24, 2, 1}, {1, 48, 2, 1}, {2, 24, 2, 1},
-    {2, 48, 2, 1}};
+    {2, 48, 2, 1}, {1, 24, 2, 2}, {1, 48, 2, 2}, {1, 96, 2, 2}, {2, 24, 2, 2}, {2, 48, 2, 2}, {2, 96, 2, 2}};
 
 constexpr int kTuneLaunches = 10;   // timed launches per candidate and pass
 constexpr int kTunePasses = 2;      // passes over the list; the best time counts
@@ -2153,9 +2153,11 @@ int fwi_ctx_set_tiling(fwi_ctx *c, int kernel, int cols_per_lane, int rows_per_w
             c->force_cw[k] = cols_per_lane;
             c->force_rows[k] = rows_per_wave;
             c->force_tb[k] = one_level(k) && !reset ? 1 : levels_per_launch;
-            // the Born kernel and the two-level kernel prefetch one row ahead
-            c->force_pd[k] =
-                (k == K_BORN || levels_per_launch == 2) ? 1 : (prefetch_rows ? prefetch_rows : kDefaultPd);
+            // the Born kernel prefetches one row ahead; the two-level kernel
+            // one unless told otherwise
+            c->force_pd[k] = k == K_BORN ? 1
+                             : prefetch_rows ? prefetch_rows
+                             : levels_per_launch == 2 ? 1 : kDefaultPd;
             c->tile[k].cw = c->tile[k].rows = c->tile[k].tb = 0;
         }
     return FWI_OK;

@@ -605,8 +605,10 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
 // outside the padded box is zero (the Dirichlet halo), as in the one-level
 // kernel. Per owned cell and two updates the kernel moves u^n, u^{n-1}, v
 // in and u^{n+1}, u^{n+2} out (plus D and G traffic for the adjoint), where
-// two one-level launches would move twice as much.
-template <int FL, int CW>
+// two one-level launches would move twice as much. The loads of the next PD
+// rows are in flight while a row is computed (a ring of PD + 1 statically
+// indexed register buffers, as in k_step).
+template <int FL, int CW, int PD>
 __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs A)
 {
     constexpr int SW = kLanes * CW;           // lane columns
@@ -672,28 +674,32 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 #pragma unroll
         for (int k = 0; k < CW; ++k) cq[r][k] = 0.f;
 
-    float nq[CW], npv[CW], nv[CW], nd1[CW], nd2[CW], ng[CW];
-    float4 nh = make_float4(0.f, 0.f, 0.f, 0.f);
+    // the loads of one level-1 row: u^n four rows below it (and its halo
+    // columns), u^{n-1}, the model, and for the adjoint D and G of row t-4
+    struct Pre2 {
+        float q[CW], pv[CW], v[CW], d1[CW], d2[CW], g[CW];
+        float4 h;
+    };
     const unsigned jc4 = 4u * unsigned(min(max(jl, 0), P - CW));
-    auto prefetch = [&](int t) {
+    auto prefetch = [&](int t, Pre2 &o) {
         const int ro = 4 * ((t + kRowsAbove) * P - kHalo);
-        bld<CW>(run, jl4, ro + 4 * kHalo * P, nq);
-        bld<CW>(rum, jl4, ro, npv);
-        if (lane < 2) nh = bld4(run, hcol4, ro - 4 * kHalo);
+        bld<CW>(run, jl4, ro + 4 * kHalo * P, o.q);
+        bld<CW>(rum, jl4, ro, o.pv);
+        o.h = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lane < 2) o.h = bld4(run, hcol4, ro - 4 * kHalo);
         const int vo = 4 * clampi(t - A.top, 0, A.nz - 1) * A.nx;
 #pragma unroll
-        for (int k = 0; k < CW; ++k) nv[k] = bld1(rv, jm[k], vo);
+        for (int k = 0; k < CW; ++k) o.v[k] = bld1(rv, jm[k], vo);
         if (FL & F_IMAGE) {
             // the imaging terms of both levels are added at level 2 (row t-4)
             const int r2 = t - kHalo;
             if (r2 >= W.z0 && r2 < W.z1) {
-                bld_stream<CW>(rd1, jc4, 4 * r2 * P, nd1);
-                bld_stream<CW>(rd2, jc4, 4 * r2 * P, nd2);
-                bld<CW>(rg, jc4, 4 * r2 * P, ng);
+                bld_stream<CW>(rd1, jc4, 4 * r2 * P, o.d1);
+                bld_stream<CW>(rd2, jc4, 4 * r2 * P, o.d2);
+                bld<CW>(rg, jc4, 4 * r2 * P, o.g);
             }
         }
     };
-    prefetch(t0);
 
     int rr1 = W.rr0, rr2 = W.rr0;
     int rrow1 = kNoRow, rrow2 = kNoRow;
@@ -710,21 +716,20 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
     float sw0[CW], sw1[CW];
     if (FL & F_SRC) source_weights<CW>(S, src_k, sw0, sw1);
 
-    for (int t = t0; t < t1; ++t) {
+    auto do_row = [&](int t, const Pre2 &pf) {
         float cpv[CW], cv[CW], cd1[CW], cd2[CW], cg[CW];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
-            qa[8][k] = nq[k];
-            cpv[k] = npv[k];
-            cv[k] = nv[k];
+            qa[8][k] = pf.q[k];
+            cpv[k] = pf.pv[k];
+            cv[k] = pf.v[k];
             if (FL & F_IMAGE) {
-                cd1[k] = nd1[k];
-                cd2[k] = nd2[k];
-                cg[k] = ng[k];
+                cd1[k] = pf.d1[k];
+                cd2[k] = pf.d2[k];
+                cg[k] = pf.g[k];
             }
         }
-        const float4 ch = nh;
-        if (t + 1 < t1) prefetch(t + 1);
+        const float4 ch = pf.h;
 
         // ---- level 1 at row t ----------------------------------------------
         if constexpr (CW == 1) row0[kHalo + lane] = qa[4][0];
@@ -850,6 +855,21 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int k = 0; k < CW; ++k) cq[r][k] = cq[r + 1][k];
+    };
+
+    Pre2 buf[PD + 1];
+#pragma unroll
+    for (int u = 0; u < PD; ++u)
+        if (t0 + u < t1) prefetch(t0 + u, buf[u]);
+    for (int t = t0; t < t1; t += PD + 1) {
+#pragma unroll
+        for (int u = 0; u <= PD; ++u) {
+            const int tt = t + u;
+            if (tt < t1) {
+                if (tt + PD < t1) prefetch(tt + PD, buf[(u + PD) % (PD + 1)]);
+                do_row(tt, buf[u]);
+            }
+        }
     }
 }
 
@@ -1431,25 +1451,25 @@ hipError_t launch_step(int flags, const StepArgs &a, hipStream_t s)
     return a.pml ? launch_step_pml<true>(flags, a, s) : launch_step_pml<false>(flags, a, s);
 }
 
-template <int CW>
+template <int CW, int PD>
 hipError_t launch_step2_cw(int flags, const StepArgs &a, hipStream_t s)
 {
     const dim3 grid(blocks_for(a.nwaves)), block(kLanes * kWavesPerBlock);
     switch (flags) {
     case F_SRC | F_SAMPLE:
-        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE, CW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE, CW, PD>), grid, block, 0, s, a);
         break;
     case F_SRC:
-        hipLaunchKernelGGL((k_step2<F_SRC, CW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_SRC, CW, PD>), grid, block, 0, s, a);
         break;
     case F_SRC | F_SAMPLE | F_EMIT:
-        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE | F_EMIT, CW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE | F_EMIT, CW, PD>), grid, block, 0, s, a);
         break;
     case F_SRC | F_EMIT:
-        hipLaunchKernelGGL((k_step2<F_SRC | F_EMIT, CW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_SRC | F_EMIT, CW, PD>), grid, block, 0, s, a);
         break;
     case F_INJECT | F_IMAGE:
-        hipLaunchKernelGGL((k_step2<F_INJECT | F_IMAGE, CW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_INJECT | F_IMAGE, CW, PD>), grid, block, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1460,7 +1480,8 @@ hipError_t launch_step2_cw(int flags, const StepArgs &a, hipStream_t s)
 hipError_t launch_step2(int flags, const StepArgs &a, hipStream_t s)
 {
     if (a.nwaves <= 0) return hipSuccess;
-    return a.cw == 2 ? launch_step2_cw<2>(flags, a, s) : launch_step2_cw<1>(flags, a, s);
+    if (a.pd == 2) return a.cw == 2 ? launch_step2_cw<2, 2>(flags, a, s) : launch_step2_cw<1, 2>(flags, a, s);
+    return a.cw == 2 ? launch_step2_cw<2, 1>(flags, a, s) : launch_step2_cw<1, 1>(flags, a, s);
 }
 
 template <bool PML>
