@@ -14,9 +14,12 @@ bf16 tensors:
              convolution, every layer output after its activation, the
              pooled maps and the up-sampled maps; the 1x1 output layer
              reads FP32 weights and writes FP32;
-  backward   the gradient arriving at every stored activation (the data
-             gradient a layer writes), and the gradient after the
-             activation's derivative is applied.
+  backward   the gradient at every convolution's pre-activation output (the
+             library applies the activation's derivative in the kernel that
+             forms the gradient, and stores the product), the gradient of
+             every pooled and up-sampled map, and the skip half of a
+             concatenation's gradient (stored before the pooling adjoint
+             adds the second path to it).
 
 Weight and bias gradients are accumulated without rounding, as the library
 accumulates them in FP32. The parity tests derive their tolerances from the
@@ -86,7 +89,7 @@ def forward(params, x, depth: int, slope: float = 0.0, rounding: bool = True):
 
     def conv_act(h, w, b):
         z = F.conv2d(h, wq(w), b, padding=1)
-        return both(_act(grad(z), slope))
+        return wq(_act(grad(z), slope))
 
     def dconv(h):
         w1, b1, w2, b2 = next(it), next(it), next(it), next(it)
@@ -102,7 +105,7 @@ def forward(params, x, depth: int, slope: float = 0.0, rounding: bool = True):
     for lvl in range(depth - 1, -1, -1):
         wt, bt = next(it), next(it)
         h = both(F.conv_transpose2d(h, wq(wt), bt, stride=2))
-        h = torch.cat([skips[lvl], h], dim=1)
+        h = torch.cat([grad(skips[lvl]), h], dim=1)
         h = dconv(h)
     wo, bo = next(it), next(it)
     return F.conv2d(h, wo, bo)[0, 0]
