@@ -91,8 +91,7 @@ typedef struct {
                            sweeps; 0 = chosen from the memory budget */
     int32_t free_surface; /* 1: the top of the model (physical row 0) is a
                              pressure-free surface - no sponge above it, u = 0
-                             on it, odd mirror above it (image method); the
-                             step kernels then run one level per launch */
+                             on it, odd mirror above it (image method) */
     int32_t relative;   /* perturbation parametrisation of the Born operator
                            (section 2.2, eq. 12: L acts on dm / m_o).
                            0: absolute velocity, J = dF/dv; born_demig takes

@@ -1643,8 +1643,6 @@ int ensure_tilings(fwi_ctx *c, const float *v)
         const int want_cw = forced ? c->force_cw[k] : (c->autotune ? 0 : kDefaultCw);
         const int want_rows = forced ? c->force_rows[k] : (c->autotune ? 0 : kDefaultRows);
         const int want_tb = one_level(k) ? 1 : (forced ? c->force_tb[k] : (c->autotune ? 0 : kDefaultTb));
-        if (want_tb == 2 && p.free_surface)
-            return set_err(c, FWI_EINVAL, "two-level tilings do not support a free surface (force one level)");
         if (want_tb == 2 && p.pml)
             return set_err(c, FWI_EINVAL, "two-level tilings do not support the PML (force one level)");
         const int want_pd = forced ? c->force_pd[k] : kDefaultPd;
@@ -1688,7 +1686,7 @@ int ensure_tilings(fwi_ctx *c, const float *v)
             build_tiling(p, cand.cw, cand.rows, cand.tb, cand.pd, trial);
             if ((rc = upload_tiling(c, trial))) break;
             for (int k = 0; k < kClasses; ++k) {
-                if (c->tile[k].cw != 0 || ((one_level(k) || p.free_surface || p.pml) && cand.tb != 1) ||
+                if (c->tile[k].cw != 0 || ((one_level(k) || p.pml) && cand.tb != 1) ||
                     (k == K_BORN && cand.pd != 1))
                     continue;
                 float ms = 0.f;

@@ -607,7 +607,11 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
 // in and u^{n+1}, u^{n+2} out (plus D and G traffic for the adjoint), where
 // two one-level launches would move twice as much. The loads of the next PD
 // rows are in flight while a row is computed (a ring of PD + 1 statically
-// indexed register buffers, as in k_step).
+// indexed register buffers, as in k_step). Under a free surface both levels
+// are pinned to zero on row 0, and the odd mirror above it is formed inside
+// the launch for level 1: when level-1 row m (1..4) is computed, its negative
+// goes into the window slot of row -m, which level 2 reads only later; both
+// new levels are also stored with their mirrored rows, as k_step stores them.
 template <int FL, int CW, int PD>
 __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs A)
 {
@@ -771,8 +775,21 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
             D1[k] = c * lap;
             const float o = leapfrog(qa[4][k], cpv[k], D1[k], a, sh);
             v1[k] = (row_in && inbox[k]) ? o : 0.0f;
+            if (A.fs && t == 0) v1[k] = 0.0f;   // the pressure-free surface
             qb[8][k] = v1[k];
             cq[4][k] = c;
+        }
+        if (A.fs && t >= 1 && t <= kHalo) {
+            // level 1 above the surface: the odd mirror of rows 1..4, in the
+            // slot of row -t (the window holds rows t-8 .. t)
+#pragma unroll
+            for (int k = 0; k < CW; ++k) {
+                const float m = -v1[k];
+                if (t == 1) qb[6][k] = m;
+                else if (t == 2) qb[4][k] = m;
+                else if (t == 3) qb[2][k] = m;
+                else qb[0][k] = m;
+            }
         }
         const bool own_row1 = t >= W.z0 && t < W.z1;
         if (own_row1) {
@@ -784,6 +801,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                     bst1(ro1, js4 + 4 * k, o, v1[k]);
                     if (FL & F_SAMPLE)
                         if (qi1[k] >= 0) A.samp[qi1[k]] = v1[k];
+                    if (A.fs && t >= 1 && t <= kHalo) bst1(ro1, js4 + 4 * k, 4 * (kRowsAbove - t) * P, -v1[k]);
                 }
             }
         }
@@ -828,9 +846,11 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                     a = sponge_a(sh);
                 }
                 D2[k] = c * lap;
-                const float v2 = leapfrog(qb[4][k], qa[0][k], D2[k], a, sh);
+                float v2 = leapfrog(qb[4][k], qa[0][k], D2[k], a, sh);
+                if (A.fs && r2 == 0) v2 = 0.0f;   // the pressure-free surface
                 if (own[k]) {
                     bst1(ro2, js4 + 4 * k, o, v2);
+                    if (A.fs && r2 >= 1 && r2 <= kHalo) bst1(ro2, js4 + 4 * k, 4 * (kRowsAbove - r2) * P, -v2);
                     if (FL & F_SAMPLE)
                         if (lvl2_ok && qi2[k] >= 0) A.samp2[qi2[k]] = v2;
                     // G after both levels: the fused multiply-adds of two one-level

@@ -240,8 +240,8 @@ def test_step_kernels_in_bounds_every_tiling(emu_driver, tmp_path, geom):
                          "pml_free_surface": pml_free_surface_geometry}[geom]()
     path = str(tmp_path / "geom.txt")
     _write_geom(path, grid, acq, v0, vt)
-    # a free surface or a layer runs one level per launch
-    one = grid.free_surface or grid.pml
+    # the layer runs one level per launch (a free surface alone runs every tiling)
+    one = grid.pml
     specs = [t for t in TILINGS if not one or t == "auto" or t.split(",")[2] == "1"]
     out = _run_parallel(emu_driver, ["fd", path], specs)
     assert out.count("ok ") == len(specs), out
