@@ -607,12 +607,12 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
 // in and u^{n+1}, u^{n+2} out (plus D and G traffic for the adjoint), where
 // two one-level launches would move twice as much. The loads of the next PD
 // rows are in flight while a row is computed (a ring of PD + 1 statically
-// indexed register buffers, as in k_step). Under a free surface both levels
+// indexed register buffers, as in k_step). Under a free surface (FS) both levels
 // are pinned to zero on row 0, and the odd mirror above it is formed inside
 // the launch for level 1: when level-1 row m (1..4) is computed, its negative
 // goes into the window slot of row -m, which level 2 reads only later; both
 // new levels are also stored with their mirrored rows, as k_step stores them.
-template <int FL, int CW, int PD>
+template <int FL, int CW, int PD, bool FS>
 __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs A)
 {
     constexpr int SW = kLanes * CW;           // lane columns
@@ -775,11 +775,11 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
             D1[k] = c * lap;
             const float o = leapfrog(qa[4][k], cpv[k], D1[k], a, sh);
             v1[k] = (row_in && inbox[k]) ? o : 0.0f;
-            if (A.fs && t == 0) v1[k] = 0.0f;   // the pressure-free surface
+            if (FS && t == 0) v1[k] = 0.0f;   // the pressure-free surface
             qb[8][k] = v1[k];
             cq[4][k] = c;
         }
-        if (A.fs && t >= 1 && t <= kHalo) {
+        if (FS && t >= 1 && t <= kHalo) {
             // level 1 above the surface: the odd mirror of rows 1..4, in the
             // slot of row -t (the window holds rows t-8 .. t)
 #pragma unroll
@@ -801,7 +801,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                     bst1(ro1, js4 + 4 * k, o, v1[k]);
                     if (FL & F_SAMPLE)
                         if (qi1[k] >= 0) A.samp[qi1[k]] = v1[k];
-                    if (A.fs && t >= 1 && t <= kHalo) bst1(ro1, js4 + 4 * k, 4 * (kRowsAbove - t) * P, -v1[k]);
+                    if (FS && t >= 1 && t <= kHalo) bst1(ro1, js4 + 4 * k, 4 * (kRowsAbove - t) * P, -v1[k]);
                 }
             }
         }
@@ -847,10 +847,10 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                 }
                 D2[k] = c * lap;
                 float v2 = leapfrog(qb[4][k], qa[0][k], D2[k], a, sh);
-                if (A.fs && r2 == 0) v2 = 0.0f;   // the pressure-free surface
+                if (FS && r2 == 0) v2 = 0.0f;   // the pressure-free surface
                 if (own[k]) {
                     bst1(ro2, js4 + 4 * k, o, v2);
-                    if (A.fs && r2 >= 1 && r2 <= kHalo) bst1(ro2, js4 + 4 * k, 4 * (kRowsAbove - r2) * P, -v2);
+                    if (FS && r2 >= 1 && r2 <= kHalo) bst1(ro2, js4 + 4 * k, 4 * (kRowsAbove - r2) * P, -v2);
                     if (FL & F_SAMPLE)
                         if (lvl2_ok && qi2[k] >= 0) A.samp2[qi2[k]] = v2;
                     // G after both levels: the fused multiply-adds of two one-level
@@ -1471,25 +1471,25 @@ hipError_t launch_step(int flags, const StepArgs &a, hipStream_t s)
     return a.pml ? launch_step_pml<true>(flags, a, s) : launch_step_pml<false>(flags, a, s);
 }
 
-template <int CW, int PD>
+template <int CW, int PD, bool FS>
 hipError_t launch_step2_cw(int flags, const StepArgs &a, hipStream_t s)
 {
     const dim3 grid(blocks_for(a.nwaves)), block(kLanes * kWavesPerBlock);
     switch (flags) {
     case F_SRC | F_SAMPLE:
-        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE, CW, PD>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE, CW, PD, FS>), grid, block, 0, s, a);
         break;
     case F_SRC:
-        hipLaunchKernelGGL((k_step2<F_SRC, CW, PD>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_SRC, CW, PD, FS>), grid, block, 0, s, a);
         break;
     case F_SRC | F_SAMPLE | F_EMIT:
-        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE | F_EMIT, CW, PD>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE | F_EMIT, CW, PD, FS>), grid, block, 0, s, a);
         break;
     case F_SRC | F_EMIT:
-        hipLaunchKernelGGL((k_step2<F_SRC | F_EMIT, CW, PD>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_SRC | F_EMIT, CW, PD, FS>), grid, block, 0, s, a);
         break;
     case F_INJECT | F_IMAGE:
-        hipLaunchKernelGGL((k_step2<F_INJECT | F_IMAGE, CW, PD>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_INJECT | F_IMAGE, CW, PD, FS>), grid, block, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1497,11 +1497,17 @@ hipError_t launch_step2_cw(int flags, const StepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <bool FS>
+hipError_t launch_step2_fs(int flags, const StepArgs &a, hipStream_t s)
+{
+    if (a.pd == 2) return a.cw == 2 ? launch_step2_cw<2, 2, FS>(flags, a, s) : launch_step2_cw<1, 2, FS>(flags, a, s);
+    return a.cw == 2 ? launch_step2_cw<2, 1, FS>(flags, a, s) : launch_step2_cw<1, 1, FS>(flags, a, s);
+}
+
 hipError_t launch_step2(int flags, const StepArgs &a, hipStream_t s)
 {
     if (a.nwaves <= 0) return hipSuccess;
-    if (a.pd == 2) return a.cw == 2 ? launch_step2_cw<2, 2>(flags, a, s) : launch_step2_cw<1, 2>(flags, a, s);
-    return a.cw == 2 ? launch_step2_cw<2, 1>(flags, a, s) : launch_step2_cw<1, 1>(flags, a, s);
+    return a.fs ? launch_step2_fs<true>(flags, a, s) : launch_step2_fs<false>(flags, a, s);
 }
 
 template <bool PML>
