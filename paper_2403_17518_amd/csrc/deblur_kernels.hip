@@ -1050,7 +1050,8 @@ __global__ __launch_bounds__(256) void k_bias_part(const bf16 *dz, int32_t ld, i
 // 3x3 convolution of a one-channel image (the input layer), zero padding 1:
 // out[p][co] = act(b[co] + sum_t w[co][t] x[p + t]) with bf16 weights and
 // inputs and FP32 sums. One thread per pixel and 8 output channels (one
-// 16-byte store); the block's weights are staged in LDS as floats.
+// 16-byte store); the weights are staged in LDS as floats once per block,
+// which then strides over the grid.
 __global__ __launch_bounds__(256) void k_conv1_fwd(const bf16 *x, int32_t H, int32_t W, const bf16 *w,
                                                    const float *b, int32_t C, int32_t act, float slope, bf16 *out,
                                                    int32_t ld, int32_t coff)
@@ -1059,29 +1060,31 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const bf16 *x, int32_t H, int
     for (int e = threadIdx.x; e < C * 9; e += blockDim.x) wl[e] = bf2f(w[e]);
     __syncthreads();
     const int cpp = C / 8;
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= int64_t(H) * W * cpp) return;
-    const int c8 = int(t % cpp);
-    const int p = int(t / cpp);
-    const int i = p / W, j = p - (p / W) * W;
-    float xv[9];
+    const int64_t n = int64_t(H) * W * cpp;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const int c8 = int(t % cpp);
+        const int p = int(t / cpp);
+        const int i = p / W, j = p - (p / W) * W;
+        float xv[9];
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int si = i + tap / 3 - 1, sj = j + tap % 3 - 1;
-        xv[tap] = (si >= 0 && si < H && sj >= 0 && sj < W) ? bf2f(x[si * W + sj]) : 0.f;
+        for (int tap = 0; tap < 9; ++tap) {
+            const int si = i + tap / 3 - 1, sj = j + tap % 3 - 1;
+            xv[tap] = (si >= 0 && si < H && sj >= 0 && sj < W) ? bf2f(x[si * W + sj]) : 0.f;
+        }
+        bf16 o[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int co = c8 * 8 + e;
+            float acc = 0.f;
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) acc = __builtin_fmaf(wl[co * 9 + tap], xv[tap], acc);
+            float v = acc + b[co];
+            if (act) v = v > 0.f ? v : slope * v;
+            o[e] = f2bf(v);
+        }
+        *reinterpret_cast<uint4 *>(out + int64_t(p) * ld + coff + c8 * 8) = *reinterpret_cast<const uint4 *>(o);
     }
-    bf16 o[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int co = c8 * 8 + e;
-        float acc = 0.f;
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap) acc = __builtin_fmaf(wl[co * 9 + tap], xv[tap], acc);
-        float v = acc + b[co];
-        if (act) v = v > 0.f ? v : slope * v;
-        o[e] = f2bf(v);
-    }
-    *reinterpret_cast<uint4 *>(out + int64_t(p) * ld + coff + c8 * 8) = *reinterpret_cast<const uint4 *>(o);
 }
 
 // Weight and bias gradients of the input layer: dW[co][t] = sum_p dz[p][co]
@@ -1347,6 +1350,23 @@ __global__ __launch_bounds__(256) void k_absmax_part(const float *x, int64_t n, 
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// 1x1 output convolution with 16-byte loads (C a multiple of 8): the same
+// sum over the channels in the same order as k_outc_fwd
+__global__ __launch_bounds__(256) void k_outc_fwd8(const bf16 *x, int32_t C, int32_t P, const float *w, const float *b,
+                                                   float *y)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    float s = b[0];
+    for (int c = 0; c < C; c += 8) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(x + int64_t(p) * C + c);
+        const bf16 *xb = reinterpret_cast<const bf16 *>(&v);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += w[c + k] * bf2f(xb[k]);
+    }
+    y[p] = s;
+}
+
 __global__ void k_outc_fwd(const bf16 *x, int32_t C, int32_t P, const float *w, const float *b, float *y)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1584,8 +1604,9 @@ hipError_t conv1_fwd(const bf16 *x, int32_t H, int32_t W, const bf16 *w, const f
     if (C % 8 || C > 1024 || ld % 8 || coff % 8) return hipErrorInvalidValue;   // weights: <= 36 KB of LDS
     const int64_t threads = int64_t(H) * W * (C / 8);
     if (threads == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_conv1_fwd, dim3(unsigned((threads + 255) / 256)), dim3(256), size_t(C) * 9 * sizeof(float),
-                       s, x, H, W, w, b, C, act, slope, out, ld, coff);
+    const int64_t blocks = std::min<int64_t>((threads + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_conv1_fwd, dim3(unsigned(blocks)), dim3(256), size_t(C) * 9 * sizeof(float), s, x, H, W, w,
+                       b, C, act, slope, out, ld, coff);
     return hipGetLastError();
 }
 
@@ -1748,6 +1769,10 @@ hipError_t pool_bwd(const bf16 *dout, int32_t C, int32_t H, int32_t W, bf16 *din
 
 hipError_t outc_fwd(const bf16 *x, int32_t C, int32_t P, const float *w, const float *b, float *y, hipStream_t s)
 {
+    if (C % 8 == 0) {
+        hipLaunchKernelGGL(k_outc_fwd8, dim3(nblocks(P)), dim3(256), 0, s, x, C, P, w, b, y);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_outc_fwd, dim3(nblocks(P)), dim3(256), 0, s, x, C, P, w, b, y);
     return hipGetLastError();
 }
