@@ -951,12 +951,12 @@ __global__ void k_wgrad_finish(const WgradArgs a)
 // bias sums), so the entry is the same for the whole block and is looked up
 // once. The entry's fin_groups G (1, 2, 4 or 8) splits a block's threads into
 // G groups over the splits: thread (g, j) sums the splits z = g, g + G, ...
-// of outputs j, j + 256/G, j + 512/G and j + 768/G of the block's 1024/G
-// (eight loads in flight), and the G sums of an output are added in LDS in
-// a fixed order.
+// of outputs j, j + 256/G, j + 512/G and j + 768/G of the block's 1024/G,
+// all four together (eight loads in flight), and the G sums of an output
+// are added in LDS in a fixed order.
 __global__ __launch_bounds__(256) void k_wgrad_finish_all(const WgradArgs *tab, const int64_t *bbeg, int32_t n)
 {
-    __shared__ float red[256];
+    __shared__ float red[4][256];
     const int64_t blk = blockIdx.x;
     int lo = 0, hi = n;   // the entry holding the block: bbeg[lo] <= blk < bbeg[lo + 1]
     while (hi - lo > 1) {
@@ -971,36 +971,52 @@ __global__ __launch_bounds__(256) void k_wgrad_finish_all(const WgradArgs *tab, 
     const int64_t nw = a.nsplit > 1 ? MN : 0;
     const int64_t nb = a.bias_partial ? (a.bias_from_b ? a.g.Cb : (a.nsplit > 1 ? a.M : 0)) : 0;
     const int64_t k0 = (blk - bbeg[lo]) * (kFinishOutputs / G) + j;
+    // weight sums: two accumulators per output over the group's splits
+    float s0[4] = {0.f, 0.f, 0.f, 0.f}, s1[4] = {0.f, 0.f, 0.f, 0.f};
+    int z = g;
+    for (; z + G < a.nsplit; z += 2 * G) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t k = k0 + int64_t(W) * q;
+            if (k < nw) {
+                s0[q] += a.partial[int64_t(z) * MN + k];
+                s1[q] += a.partial[int64_t(z + G) * MN + k];
+            }
+        }
+    }
+    if (z < a.nsplit) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t k = k0 + int64_t(W) * q;
+            if (k < nw) s0[q] += a.partial[int64_t(z) * MN + k];
+        }
+    }
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int64_t k = k0 + int64_t(W) * q;
-        float t = 0.f;
-        if (k < nw) {
-            float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            const float *p = a.partial + k;
-            int z = g;
-            for (; z + 7 * G < a.nsplit; z += 8 * G)
-#pragma unroll
-                for (int u = 0; u < 8; ++u) s[u] += p[int64_t(z + u * G) * MN];
-            for (; z < a.nsplit; z += G) s[0] += p[int64_t(z) * MN];
-            t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-        } else if (k < nw + nb) {
+        float t = s0[q] + s1[q];
+        if (k >= nw && k < nw + nb) {   // bias sums
             const int c = int(k - nw);
             const int len = a.bias_from_b ? a.N : a.M;
             const int ntap = a.bias_from_b ? a.N / a.g.Cb : 1;
+            t = 0.f;
             for (int tap = 0; tap < ntap; ++tap) {
                 const float *bp = a.bias_partial + tap * (a.bias_from_b ? a.g.Cb : 0) + c;
-                for (int z = g; z < a.nsplit; z += G) t += bp[int64_t(z) * len];
+                for (int zz = g; zz < a.nsplit; zz += G) t += bp[int64_t(zz) * len];
             }
         }
-        red[threadIdx.x] = t;
-        __syncthreads();
-        if (g == 0 && k < nw + nb) {
-            float v = red[j];
-            for (int h = 1; h < G; ++h) v += red[h * W + j];
-            if (k < nw) a.out[(k / a.N) * a.ldm + (k % a.N) * a.ldn] = v;
-            else a.bias_out[k - nw] = v;
-        }
-        __syncthreads();
+        red[q][threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (g != 0) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t k = k0 + int64_t(W) * q;
+        if (k >= nw + nb) continue;
+        float v = red[q][j];
+        for (int h = 1; h < G; ++h) v += red[q][h * W + j];
+        if (k < nw) a.out[(k / a.N) * a.ldm + (k % a.N) * a.ldn] = v;
+        else a.bias_out[k - nw] = v;
     }
 }
 
@@ -1104,6 +1120,7 @@ __global__ __launch_bounds__(256) void k_conv1_wgrad(const bf16 *dz, int32_t ld,
     for (int e = 0; e < 8; ++e)
 #pragma unroll
         for (int k = 0; k < 10; ++k) acc[e][k] = 0.f;
+#pragma unroll 4
     for (int p = p0 + int(threadIdx.x); p < p1; p += blockDim.x) {
         const uint4 v = *reinterpret_cast<const uint4 *>(dz + int64_t(p) * ld + zoff + c8 * 8);
         const bf16 *d = reinterpret_cast<const bf16 *>(&v);
