@@ -108,10 +108,10 @@ typedef struct {
                            symmetric: the adjoint is the same recursion run
                            backward). Two edge fields per propagated field
                            ride along (memory: four more field-sized buffers
-                           per field, snapshots twice as large); the step
-                           kernels run one level per launch (a two-level
-                           tiling forced with fwi_ctx_set_tiling makes the
-                           call fail with FWI_EINVAL). */
+                           per field, snapshots twice as large); every
+                           tiling takes the layer, two-level ones included
+                           (the intermediate level's edge fields stay in
+                           registers). */
 } fwi_grid;
 
 typedef struct {

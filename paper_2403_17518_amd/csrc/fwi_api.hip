@@ -931,7 +931,7 @@ int step_launch(fwi_ctx *c, StepArgs a, int cls, int flags, int levels, int acti
         a.out1 = f.s0;
         a.out2 = f.s1;
         HIPCHK(c, launch_step2(flags, a, c->stream));
-        f = Fields{f.s0, f.s1, f.prev, f.cur, f.px, f.pz, f.qx, f.qz};
+        f = Fields{f.s0, f.s1, f.prev, f.cur, f.qx, f.qz, f.px, f.pz};
     } else {
         HIPCHK(c, launch_step(flags, a, c->stream));
         std::swap(f.prev, f.cur);
@@ -1643,8 +1643,6 @@ int ensure_tilings(fwi_ctx *c, const float *v)
         const int want_cw = forced ? c->force_cw[k] : (c->autotune ? 0 : kDefaultCw);
         const int want_rows = forced ? c->force_rows[k] : (c->autotune ? 0 : kDefaultRows);
         const int want_tb = one_level(k) ? 1 : (forced ? c->force_tb[k] : (c->autotune ? 0 : kDefaultTb));
-        if (want_tb == 2 && p.pml)
-            return set_err(c, FWI_EINVAL, "two-level tilings do not support the PML (force one level)");
         const int want_pd = forced ? c->force_pd[k] : kDefaultPd;
         if (want_cw && want_rows && want_tb) {
             if (t.cw == want_cw && t.rows == want_rows && t.tb == want_tb && t.pd == want_pd) continue;
@@ -1686,7 +1684,7 @@ int ensure_tilings(fwi_ctx *c, const float *v)
             build_tiling(p, cand.cw, cand.rows, cand.tb, cand.pd, trial);
             if ((rc = upload_tiling(c, trial))) break;
             for (int k = 0; k < kClasses; ++k) {
-                if (c->tile[k].cw != 0 || ((one_level(k) || p.pml) && cand.tb != 1) ||
+                if (c->tile[k].cw != 0 || (one_level(k) && cand.tb != 1) ||
                     (k == K_BORN && cand.pd != 1))
                     continue;
                 float ms = 0.f;

@@ -261,7 +261,7 @@ template <int CW>
 struct PmlCols {
     int mxc[CW], mxe[CW], mxl;  // squared half-cell depths: column, right edge, left edge
     float dxc[CW], bxe[CW], gxe[CW];
-    bool xok[CW];               // the right edge lies inside the box
+    bool xok[CW];               // the column and its right edge lie inside the box
     float bxl, gxl;
     bool lok;                   // the left edge lies inside the box
     __device__ __forceinline__ void init(const StepArgs &A, int j0, int NX)
@@ -273,7 +273,7 @@ struct PmlCols {
             mxe[k] = pml_m2(2 * j + 1, NX, A.nb, A.nb);
             dxc[k] = A.hd0 * float(mxc[k]);
             pml_rec(A.hd0 * float(mxe[k]), A.dt, bxe[k], gxe[k]);
-            xok[k] = j + 1 < NX;
+            xok[k] = j >= 0 && j + 1 < NX;
         }
         mxl = pml_m2(2 * j0 - 1, NX, A.nb, A.nb);
         pml_rec(A.hd0 * float(mxl), A.dt, bxl, gxl);
@@ -612,7 +612,15 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
 // the launch for level 1: when level-1 row m (1..4) is computed, its negative
 // goes into the window slot of row -m, which level 2 reads only later; both
 // new levels are also stored with their mirrored rows, as k_step stores them.
-template <int FL, int CW, int PD, bool FS>
+// With the perfectly matched layer (PML) the edge fields of level n are read
+// and those of level n+2 written; the intermediate level's edge fields are
+// formed by level 1 on every lane column and row it computes (edges outside
+// the box are zero) and reach level 2, four rows later, through register
+// rings (the z edges keep one row more: the first level-2 row of a wave also
+// needs the edge above it). Level 2's edge left of lane 0 would need level
+// 1's edge one column further left; that lane's column is never owned, so
+// it is formed from zero.
+template <int FL, int CW, int PD, bool FS, bool PML>
 __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs A)
 {
     constexpr int SW = kLanes * CW;           // lane columns
@@ -666,6 +674,34 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
     if (lane < 2) *reinterpret_cast<float4 *>(&row1[lane == 0 ? 0 : kHalo + SW]) = make_float4(0.f, 0.f, 0.f, 0.f);
 
     const int t0 = W.z0 - kHalo, t1 = W.z1 + kHalo;   // level-1 rows [t0, t1)
+
+    // perfectly matched layer: coefficients of the lane columns, the edge
+    // fields of the row above the current one at each level, and the rings
+    // carrying level 1's edge fields to level 2 (slot 4 / 5: row t)
+    PmlCols<CW> pc;
+    bool pstrip = false;
+    Rsrc rpxi = rv, rpzi = rv, rpxo = rv, rpzo = rv;
+    float pup1[CW], pup1_old[CW], pup2[CW], pxr[5][CW], pzr[6][CW];
+    const unsigned jleft4 = 4u * unsigned(max(cb - 1, 0) + kHalo);
+    if constexpr (PML) {
+        pc.init(A, j0, S.NX);
+        pstrip = pml_strip<CW>(A, cb, S.NX);
+        rpxi = view(A.psx_in + base);
+        rpzi = view(A.psz_in + base);
+        rpxo = view(A.psx_out + base);
+        rpzo = view(A.psz_out + base);
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            pup1[k] = pup1_old[k] = pup2[k] = 0.f;
+#pragma unroll
+            for (int r = 0; r < 5; ++r) pxr[r][k] = 0.f;
+#pragma unroll
+            for (int r = 0; r < 6; ++r) pzr[r][k] = 0.f;
+        }
+        if ((pstrip || pml_row(A, t0)) && t0 >= 1)
+            bld<CW>(rpzi, jl4, 4 * ((t0 - 1 + kRowsAbove) * P - kHalo), pup1_old);
+    }
+
     float qa[9][CW], qb[9][CW], cq[5][CW];
 #pragma unroll
     for (int r = 0; r < 8; ++r) bld<CW>(run, jl4, 4 * ((t0 - kHalo + r + kRowsAbove) * P - kHalo), qa[r]);
@@ -682,6 +718,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
     // columns), u^{n-1}, the model, and for the adjoint D and G of row t-4
     struct Pre2 {
         float q[CW], pv[CW], v[CW], d1[CW], d2[CW], g[CW];
+        float px[CW], pz[CW], pxl;
         float4 h;
     };
     const unsigned jc4 = 4u * unsigned(min(max(jl, 0), P - CW));
@@ -701,6 +738,13 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                 bld_stream<CW>(rd1, jc4, 4 * r2 * P, o.d1);
                 bld_stream<CW>(rd2, jc4, 4 * r2 * P, o.d2);
                 bld<CW>(rg, jc4, 4 * r2 * P, o.g);
+            }
+        }
+        if constexpr (PML) {
+            if (pstrip || pml_row(A, t)) {
+                bld<CW>(rpxi, jl4, ro, o.px);
+                bld<CW>(rpzi, jl4, ro, o.pz);
+                o.pxl = lane == 0 ? bld1(rpxi, jleft4, ro) : 0.f;
             }
         }
     };
@@ -759,10 +803,45 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         const bool row_in = t >= 0 && t < NZ;
         const int ddz1 = max(max(A.top - t, t - (NZ - 1 - nb)), 0);
         const float dz1 = float(ddz1 * ddz1);
+        // layer terms of level 1 (as k_step forms them); edges of rows
+        // outside the box are zero
+        float pdiv1[CW], pnx1[CW], pnz1[CW], fdt1[CW];
+        bool prow1 = false;
+        if constexpr (PML) {
+            prow1 = pstrip || pml_row(A, t);
+            if (prow1) {
+                PmlRow pr;
+                pr.init(A, t);
+                if (t == t0 && t >= 1) {
+                    PmlRow pu;
+                    pu.init(A, t - 1);
+#pragma unroll
+                    for (int k = 0; k < CW; ++k)
+                        pup1[k] = pml_edge(pup1_old[k], pu.bze, pu.gze, A.hd0 * float(pc.mxc[k] - pu.mze),
+                                           qa[4][k] - qa[3][k], A.ih);
+                }
+                pml_row_terms<CW>(A, pc, pr, lane, qa, xr, pf.px, pf.pz, pf.pxl, pnx1, pnz1, pup1, pdiv1);
+#pragma unroll
+                for (int k = 0; k < CW; ++k) {
+                    fdt1[k] = (pc.dxc[k] * pr.dzc) * A.dt2;
+                    if (!row_in) pnx1[k] = pnz1[k] = pup1[k] = 0.f;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < CW; ++k) pnx1[k] = pnz1[k] = pup1[k] = 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < CW; ++k) {
+                pxr[4][k] = pnx1[k];
+                pzr[5][k] = pnz1[k];
+            }
+        }
         float v1[CW], D1[CW];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             float lap = lap8(qa, xr, k, A.w1, A.w2, A.w3, A.w4);
+            if constexpr (PML)
+                if (prow1) lap = __builtin_fmaf(pdiv1[k], A.ih, lap);
             if (FL & F_SRC) lap = add_source<CW>(lap, wsrc1, t, S.src_i, sw0, sw1, k);
             if (FL & F_INJECT)
                 if (qi1[k] >= 0) lap += A.inj[qi1[k]];
@@ -773,7 +852,10 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                 a = sponge_a(sh);
             }
             D1[k] = c * lap;
-            const float o = leapfrog(qa[4][k], cpv[k], D1[k], a, sh);
+            float Du = D1[k];
+            if constexpr (PML)
+                if (prow1) Du = __builtin_fmaf(-fdt1[k], qa[4][k], Du);
+            const float o = leapfrog(qa[4][k], cpv[k], Du, a, sh);
             v1[k] = (row_in && inbox[k]) ? o : 0.0f;
             if (FS && t == 0) v1[k] = 0.0f;   // the pressure-free surface
             qb[8][k] = v1[k];
@@ -832,10 +914,37 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
             const int ddz2 = max(max(A.top - r2, r2 - (NZ - 1 - nb)), 0);
             const float dz2 = float(ddz2 * ddz2);
             const int o = 4 * (r2 + kRowsAbove) * P;
+            // layer terms of level 2 from level 1's edge fields of row r2
+            // (and, for the first row, of the row above it)
+            float pdiv2[CW], pnx2[CW], pnz2[CW], fdt2[CW];
+            bool prow2 = false;
+            if constexpr (PML) {
+                prow2 = pstrip || pml_row(A, r2);
+                if (prow2) {
+                    PmlRow pr;
+                    pr.init(A, r2);
+                    if (r2 == W.z0 && r2 >= 1) {
+                        PmlRow pu;
+                        pu.init(A, r2 - 1);
+#pragma unroll
+                        for (int k = 0; k < CW; ++k)
+                            pup2[k] = pml_edge(pzr[0][k], pu.bze, pu.gze, A.hd0 * float(pc.mxc[k] - pu.mze),
+                                               qb[4][k] - qb[3][k], A.ih);
+                    }
+                    pml_row_terms<CW>(A, pc, pr, lane, qb, yr, pxr[0], pzr[1], 0.f, pnx2, pnz2, pup2, pdiv2);
+#pragma unroll
+                    for (int k = 0; k < CW; ++k) fdt2[k] = (pc.dxc[k] * pr.dzc) * A.dt2;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < CW; ++k) pup2[k] = 0.f;
+                }
+            }
             float D2[CW];
 #pragma unroll
             for (int k = 0; k < CW; ++k) {
                 float lap = lap8(qb, yr, k, A.w1, A.w2, A.w3, A.w4);
+                if constexpr (PML)
+                    if (prow2) lap = __builtin_fmaf(pdiv2[k], A.ih, lap);
                 if (FL & F_SRC) lap = add_source<CW>(lap, wsrc2, r2, S.src_i, sw0, sw1, k);
                 if (FL & F_INJECT)
                     if (qi2[k] >= 0) lap += A.inj2[qi2[k]];
@@ -846,10 +955,19 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                     a = sponge_a(sh);
                 }
                 D2[k] = c * lap;
-                float v2 = leapfrog(qb[4][k], qa[0][k], D2[k], a, sh);
+                float Du = D2[k];
+                if constexpr (PML)
+                    if (prow2) Du = __builtin_fmaf(-fdt2[k], qb[4][k], Du);
+                float v2 = leapfrog(qb[4][k], qa[0][k], Du, a, sh);
                 if (FS && r2 == 0) v2 = 0.0f;   // the pressure-free surface
                 if (own[k]) {
                     bst1(ro2, js4 + 4 * k, o, v2);
+                    if constexpr (PML) {
+                        if (prow2) {
+                            bst1(rpxo, js4 + 4 * k, o, pnx2[k]);
+                            bst1(rpzo, js4 + 4 * k, o, pnz2[k]);
+                        }
+                    }
                     if (FS && r2 >= 1 && r2 <= kHalo) bst1(ro2, js4 + 4 * k, 4 * (kRowsAbove - r2) * P, -v2);
                     if (FL & F_SAMPLE)
                         if (lvl2_ok && qi2[k] >= 0) A.samp2[qi2[k]] = v2;
@@ -875,6 +993,15 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int k = 0; k < CW; ++k) cq[r][k] = cq[r + 1][k];
+        if constexpr (PML) {
+#pragma unroll
+            for (int k = 0; k < CW; ++k) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) pxr[r][k] = pxr[r + 1][k];
+#pragma unroll
+                for (int r = 0; r < 5; ++r) pzr[r][k] = pzr[r + 1][k];
+            }
+        }
     };
 
     Pre2 buf[PD + 1];
@@ -1471,25 +1598,25 @@ hipError_t launch_step(int flags, const StepArgs &a, hipStream_t s)
     return a.pml ? launch_step_pml<true>(flags, a, s) : launch_step_pml<false>(flags, a, s);
 }
 
-template <int CW, int PD, bool FS>
+template <int CW, int PD, bool FS, bool PML>
 hipError_t launch_step2_cw(int flags, const StepArgs &a, hipStream_t s)
 {
     const dim3 grid(blocks_for(a.nwaves)), block(kLanes * kWavesPerBlock);
     switch (flags) {
     case F_SRC | F_SAMPLE:
-        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE, CW, PD, FS>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE, CW, PD, FS, PML>), grid, block, 0, s, a);
         break;
     case F_SRC:
-        hipLaunchKernelGGL((k_step2<F_SRC, CW, PD, FS>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_SRC, CW, PD, FS, PML>), grid, block, 0, s, a);
         break;
     case F_SRC | F_SAMPLE | F_EMIT:
-        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE | F_EMIT, CW, PD, FS>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_SRC | F_SAMPLE | F_EMIT, CW, PD, FS, PML>), grid, block, 0, s, a);
         break;
     case F_SRC | F_EMIT:
-        hipLaunchKernelGGL((k_step2<F_SRC | F_EMIT, CW, PD, FS>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_SRC | F_EMIT, CW, PD, FS, PML>), grid, block, 0, s, a);
         break;
     case F_INJECT | F_IMAGE:
-        hipLaunchKernelGGL((k_step2<F_INJECT | F_IMAGE, CW, PD, FS>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_step2<F_INJECT | F_IMAGE, CW, PD, FS, PML>), grid, block, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1497,17 +1624,19 @@ hipError_t launch_step2_cw(int flags, const StepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool FS>
-hipError_t launch_step2_fs(int flags, const StepArgs &a, hipStream_t s)
+template <bool FS, bool PML>
+hipError_t launch_step2_bnd(int flags, const StepArgs &a, hipStream_t s)
 {
-    if (a.pd == 2) return a.cw == 2 ? launch_step2_cw<2, 2, FS>(flags, a, s) : launch_step2_cw<1, 2, FS>(flags, a, s);
-    return a.cw == 2 ? launch_step2_cw<2, 1, FS>(flags, a, s) : launch_step2_cw<1, 1, FS>(flags, a, s);
+    if (a.pd == 2)
+        return a.cw == 2 ? launch_step2_cw<2, 2, FS, PML>(flags, a, s) : launch_step2_cw<1, 2, FS, PML>(flags, a, s);
+    return a.cw == 2 ? launch_step2_cw<2, 1, FS, PML>(flags, a, s) : launch_step2_cw<1, 1, FS, PML>(flags, a, s);
 }
 
 hipError_t launch_step2(int flags, const StepArgs &a, hipStream_t s)
 {
     if (a.nwaves <= 0) return hipSuccess;
-    return a.fs ? launch_step2_fs<true>(flags, a, s) : launch_step2_fs<false>(flags, a, s);
+    if (a.pml) return a.fs ? launch_step2_bnd<true, true>(flags, a, s) : launch_step2_bnd<false, true>(flags, a, s);
+    return a.fs ? launch_step2_bnd<true, false>(flags, a, s) : launch_step2_bnd<false, false>(flags, a, s);
 }
 
 template <bool PML>

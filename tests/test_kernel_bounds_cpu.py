@@ -240,9 +240,9 @@ def test_step_kernels_in_bounds_every_tiling(emu_driver, tmp_path, geom):
                          "pml_free_surface": pml_free_surface_geometry}[geom]()
     path = str(tmp_path / "geom.txt")
     _write_geom(path, grid, acq, v0, vt)
-    # the layer runs one level per launch (a free surface alone runs every tiling)
-    one = grid.pml
-    specs = [t for t in TILINGS if not one or t == "auto" or t.split(",")[2] == "1"]
+    # every tiling, two levels per launch included, with and without the
+    # layer and the free surface
+    specs = list(TILINGS)
     out = _run_parallel(emu_driver, ["fd", path], specs)
     assert out.count("ok ") == len(specs), out
     # every tiling computes each cell with the same arithmetic: one set of bits
@@ -263,8 +263,6 @@ def test_checkpoint_schedules_give_the_same_bits(emu_driver, tmp_path, pml):
     _write_geom(path, grid, acq, v0, vt)
     groups = {"1,24,1,1": ["0", "3", "1", "1,0", "1,1", "1,3", "2,0"],
               "1,24,2,1": ["0", "3", "1,0", "1,2"]}
-    if pml:
-        del groups["1,24,2,1"]
     specs = [f"{t},{c}" for t, cs in groups.items() for c in cs]
     out = _run_parallel(emu_driver, ["fd", path], specs)
     lines = [l for l in out.splitlines() if l.startswith("ok ")]
@@ -273,6 +271,8 @@ def test_checkpoint_schedules_give_the_same_bits(emu_driver, tmp_path, pml):
     for t, cs in groups.items():
         hashes = {info[f"{t},{c}"]["hash"] for c in cs}
         assert len(hashes) == 1, (t, {c: info[f"{t},{c}"] for c in cs})
+    # and one level per launch gives the bits of two
+    assert len({i["hash"] for i in info.values()}) == 1, info
     # the capped schedules really ran with fewer snapshots and recomputed more
     assert int(info["1,24,1,1,1,0"]["slots"]) == 0
     assert int(info["1,24,1,1,1,0"]["recomputed"]) > int(info["1,24,1,1,1"]["recomputed"])
