@@ -123,8 +123,12 @@ __device__ __forceinline__ void ld(const float *p, float (&o)[CW])
 // base by its descriptor (scalar registers), a per-row byte offset (scalar)
 // and a fixed per-lane byte offset (one vector register), so streaming a row
 // costs no vector address arithmetic. Range checking is left wide open:
-// every offset used is in bounds by construction. The loads and stores are
-// the raw-buffer intrinsics of the AMDGPU backend, bound by name.
+// every offset used is in bounds by construction, except on purpose: a load
+// whose lane offset lies past the range (kNoLoad), or made through a view
+// of range zero (view_none), returns zeros without a memory request. Loads
+// that a lane or a row does not need are made that way instead of being
+// skipped, so that no load sits in a branch. The loads and stores are the
+// raw-buffer intrinsics of the AMDGPU backend, bound by name.
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -147,6 +151,15 @@ __device__ __forceinline__ Rsrc view(const float *base)
     r.w = kRsrcWord3;
     return r;
 }
+
+__device__ __forceinline__ Rsrc view_none(const float *base)
+{
+    Rsrc r = view(base);
+    r.z = 0;
+    return r;
+}
+
+constexpr unsigned kNoLoad = 0x80000000u;   // a lane offset past every view's range
 
 __device__ __forceinline__ float bld1(Rsrc r, unsigned lane_off, int row_off)
 {
@@ -347,6 +360,33 @@ __device__ __forceinline__ void pml_row_terms(const StepArgs &A, const PmlCols<C
     }
 }
 
+// Receiver rows. The entries of a wave's row list are wave-uniform: read
+// through the constant address space they become scalar loads, which the
+// vector-memory counter does not track. The per-lane receiver indices (and
+// the adjoint's injected values) are vector loads made on receiver rows only;
+// the wave waits for them there, so that on every other row the compiler has
+// no outstanding load of unknown position to wait for and the row prefetch
+// stays in flight.
+typedef const __attribute__((address_space(4))) RecRow *RecRowsK;
+__device__ __forceinline__ RecRowsK rec_rows(const RecRow *p) { return (RecRowsK)p; }
+__device__ __forceinline__ void vm_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // vmcnt(0)
+
+template <int CW, bool INJ>
+__device__ __forceinline__ void receiver_row(const StepArgs &A, RecRowsK rrows, const float *inj, int &rr,
+                                             int &rrow, int rr_end, int lane, int (&qi)[CW], float (&iv)[CW])
+{
+    const int mo = rrows[rr].map_off + CW * lane;
+#pragma unroll
+    for (int k = 0; k < CW; ++k) qi[k] = A.rmap[mo + k];
+    if (INJ) {
+#pragma unroll
+        for (int k = 0; k < CW; ++k) iv[k] = qi[k] >= 0 ? inj[qi[k]] : 0.f;
+    }
+    ++rr;
+    rrow = rr < rr_end ? rrows[rr].row : kNoRow;
+    vm_drain();
+}
+
 // One time level of every active shot. Each lane owns CW adjacent columns of
 // a 64*CW-column strip and streams down the rows [z0, z1) of that strip; the
 // loads of rows z+1 .. z+PD are issued before row z is computed so that PD+1
@@ -400,7 +440,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     // columns right of it (a zero column block when past the shot's width)
     // (byte offset shifted up by the 4 halo columns so that it is never
     // negative; the row offset of the load is lowered by as much)
-    const unsigned hcol = 4u * unsigned(lane == 0 ? W.col0 : min(W.col0 + SW, P - kHalo) + kHalo);
+    const unsigned hcol =
+        lane < 2 ? 4u * unsigned(lane == 0 ? W.col0 : min(W.col0 + SW, P - kHalo) + kHalo) : kNoLoad;
 
     // perfectly matched layer: edge fields in the field layout
     PmlCols<CW> pc;
@@ -437,8 +478,10 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
         const int ro = 4 * (z + kRowsAbove) * P;
         bld<CW>(rcur, jl, ro + 4 * kHalo * P, pre.q);
         bld<CW>(rprev, jl, ro, pre.pv);
-        // only lanes 0 and 1 read (and later use) the halo columns
-        if (lane < 2) pre.h = bld4(rcur, hcol, ro - 4 * kHalo);
+        // lanes 0 and 1 read the halo columns; the other lanes' loads return
+        // zeros (kNoLoad), so that no load of the row sits in a branch and
+        // the compiler knows how many are in flight
+        pre.h = bld4(rcur, hcol, ro - 4 * kHalo);
         const int vo = 4 * clampi(z - A.top, 0, A.nz - 1) * A.nx;
 #pragma unroll
         for (int k = 0; k < CW; ++k) pre.v[k] = bld1(rv, jm[k], vo);
@@ -460,9 +503,10 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
         }
     };
 
+    const RecRowsK rrows = rec_rows(A.rrows);
     int rr = W.rr0;
     int rrow = kNoRow;
-    if (FL & (F_SAMPLE | F_INJECT)) rrow = rr < W.rr1 ? A.rrows[rr].row : kNoRow;
+    if (FL & (F_SAMPLE | F_INJECT)) rrow = rr < W.rr1 ? rrows[rr].row : kNoRow;
     const float wsrc = (FL & F_SRC) ? A.wav[S.wav_off + A.n] * A.ih2 : 0.0f;
     const int src_k = S.src_j - j0;          // column of the source in this lane, if 0..CW-1
     float sw0[CW], sw1[CW];
@@ -482,17 +526,14 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
         wave_sync();
 
         int qi[CW];
+        float iv[CW];
 #pragma unroll
-        for (int k = 0; k < CW; ++k) qi[k] = -1;
-        if (FL & (F_SAMPLE | F_INJECT)) {
-            if (z == rrow) {
-                const int mo = A.rrows[rr].map_off + CW * lane;
-#pragma unroll
-                for (int k = 0; k < CW; ++k) qi[k] = A.rmap[mo + k];
-                ++rr;
-                rrow = rr < W.rr1 ? A.rrows[rr].row : kNoRow;
-            }
+        for (int k = 0; k < CW; ++k) {
+            qi[k] = -1;
+            iv[k] = 0.f;
         }
+        if (FL & (F_SAMPLE | F_INJECT))
+            if (z == rrow) receiver_row<CW, (FL & F_INJECT) != 0>(A, rrows, A.inj, rr, rrow, W.rr1, lane, qi, iv);
         const int ddz = max(max(A.top - z, z - (A.NZ - 1 - nb)), 0);
         const float dz2 = float(ddz * ddz);
         // layer terms of this row: edge divergence and d_x d_z dt^2
@@ -528,7 +569,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
                 if (prow) lap = __builtin_fmaf(pdiv[k], A.ih, lap);
             if (FL & F_SRC) lap = add_source<CW>(lap, wsrc, z, S.src_i, sw0, sw1, k);
             if (FL & F_INJECT)
-                if (qi[k] >= 0) lap += A.inj[qi[k]];
+                if (qi[k] >= 0) lap += iv[k];
             const float cc = c.v[k] * c.v[k] * A.dt2;
             float a = ax[k], sh = shx[k];
             if (ddz > 0) {
@@ -578,21 +619,26 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     };
 
     // a ring of PD+1 buffers, statically indexed: the loop is unrolled PD+1
-    // times so that no buffer is copied
+    // times so that no buffer is copied. Every pass of the main loop issues
+    // the same loads (rows past the run's last are fetched as that row again:
+    // cache hits, never used), so the compiler counts the loads in flight
+    // exactly and waits for the current row's only; the last rows (fewer than
+    // PD+1) are in the ring already.
     Pre buf[PD + 1];
+    const int zl = W.z1 - 1;
 #pragma unroll
-    for (int u = 0; u < PD; ++u)
-        if (W.z0 + u < W.z1) prefetch(W.z0 + u, buf[u]);
-    for (int z = W.z0; z < W.z1; z += PD + 1) {
+    for (int u = 0; u < PD; ++u) prefetch(min(W.z0 + u, zl), buf[u]);
+    int z = W.z0;
+    for (; z + PD < W.z1; z += PD + 1) {
 #pragma unroll
         for (int u = 0; u <= PD; ++u) {
-            const int zz = z + u;
-            if (zz < W.z1) {
-                if (zz + PD < W.z1) prefetch(zz + PD, buf[(u + PD) % (PD + 1)]);
-                do_row(zz, buf[u]);
-            }
+            prefetch(min(z + u + PD, zl), buf[(u + PD) % (PD + 1)]);
+            do_row(z + u, buf[u]);
         }
     }
+#pragma unroll
+    for (int u = 0; u < PD; ++u)
+        if (z + u < W.z1) do_row(z + u, buf[u]);
 }
 
 // Two time levels per launch (temporal blocking). With u^{n-1} (prev) and
@@ -653,6 +699,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
     const Rsrc rg = view((FL & F_IMAGE) ? A.G + S.g_off : A.v);
     const Rsrc rd1 = view((FL & (F_IMAGE | F_EMIT)) ? A.dslot + S.g_off : A.v);
     const Rsrc rd2 = view((FL & (F_IMAGE | F_EMIT)) ? A.dslot2 + S.g_off : A.v);
+    const Rsrc rd1n = view_none(A.v), rd2n = rd1n, rgn = rd1n;
 
     bool inbox[CW], own[CW];
     unsigned jm[CW];
@@ -670,7 +717,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         shx[k] = sh;
     }
     // halo columns (byte offset shifted up by 8 columns: cb - 4 >= -8)
-    const unsigned hcol4 = 4u * unsigned((lane == 0 ? cb - kHalo : min(cb + SW, P - kHalo)) + 2 * kHalo);
+    const unsigned hcol4 =
+        lane < 2 ? 4u * unsigned((lane == 0 ? cb - kHalo : min(cb + SW, P - kHalo)) + 2 * kHalo) : kNoLoad;
     if (lane < 2) *reinterpret_cast<float4 *>(&row1[lane == 0 ? 0 : kHalo + SW]) = make_float4(0.f, 0.f, 0.f, 0.f);
 
     const int t0 = W.z0 - kHalo, t1 = W.z1 + kHalo;   // level-1 rows [t0, t1)
@@ -726,19 +774,20 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         const int ro = 4 * ((t + kRowsAbove) * P - kHalo);
         bld<CW>(run, jl4, ro + 4 * kHalo * P, o.q);
         bld<CW>(rum, jl4, ro, o.pv);
-        o.h = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (lane < 2) o.h = bld4(run, hcol4, ro - 4 * kHalo);
+        o.h = bld4(run, hcol4, ro - 4 * kHalo);   // zeros past lane 1
         const int vo = 4 * clampi(t - A.top, 0, A.nz - 1) * A.nx;
 #pragma unroll
         for (int k = 0; k < CW; ++k) o.v[k] = bld1(rv, jm[k], vo);
         if (FL & F_IMAGE) {
-            // the imaging terms of both levels are added at level 2 (row t-4)
-            const int r2 = t - kHalo;
-            if (r2 >= W.z0 && r2 < W.z1) {
-                bld_stream<CW>(rd1, jc4, 4 * r2 * P, o.d1);
-                bld_stream<CW>(rd2, jc4, 4 * r2 * P, o.d2);
-                bld<CW>(rg, jc4, 4 * r2 * P, o.g);
-            }
+            // the imaging terms of both levels are added at level 2 (row t-4,
+            // always below z1); before the first owned row they are loaded
+            // through views of range zero (zeros, no memory request), so that
+            // they sit in no branch
+            const bool own2 = t - kHalo >= W.z0;
+            const int r2 = max(t - kHalo, W.z0);
+            bld_stream<CW>(own2 ? rd1 : rd1n, jc4, 4 * r2 * P, o.d1);
+            bld_stream<CW>(own2 ? rd2 : rd2n, jc4, 4 * r2 * P, o.d2);
+            bld<CW>(own2 ? rg : rgn, jc4, 4 * r2 * P, o.g);
         }
         if constexpr (PML) {
             if (pstrip || pml_row(A, t)) {
@@ -749,12 +798,13 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         }
     };
 
+    const RecRowsK rrows = rec_rows(A.rrows);
     int rr1 = W.rr0, rr2 = W.rr0;
     int rrow1 = kNoRow, rrow2 = kNoRow;
     if (FL & (F_SAMPLE | F_INJECT)) {
         // skip receiver rows above the first level-1 row
-        while (rr1 < W.rr1 && A.rrows[rr1].row < t0) ++rr1;
-        rrow1 = rr1 < W.rr1 ? A.rrows[rr1].row : kNoRow;
+        while (rr1 < W.rr1 && rrows[rr1].row < t0) ++rr1;
+        rrow1 = rr1 < W.rr1 ? rrows[rr1].row : kNoRow;
         rr2 = rr1;
         rrow2 = rrow1;
     }
@@ -789,17 +839,15 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         for (int m = 0; m < CW + 2 * kHalo; ++m) xr[m] = row0[CW * lane + m];
 
         int qi1[CW];
+        float iv1[CW];
 #pragma unroll
-        for (int k = 0; k < CW; ++k) qi1[k] = -1;
-        if (FL & (F_SAMPLE | F_INJECT)) {
-            if (t == rrow1) {
-                const int mo = A.rrows[rr1].map_off + CW * lane;
-#pragma unroll
-                for (int k = 0; k < CW; ++k) qi1[k] = A.rmap[mo + k];
-                ++rr1;
-                rrow1 = rr1 < W.rr1 ? A.rrows[rr1].row : kNoRow;
-            }
+        for (int k = 0; k < CW; ++k) {
+            qi1[k] = -1;
+            iv1[k] = 0.f;
         }
+        if (FL & (F_SAMPLE | F_INJECT))
+            if (t == rrow1)
+                receiver_row<CW, (FL & F_INJECT) != 0>(A, rrows, A.inj, rr1, rrow1, W.rr1, lane, qi1, iv1);
         const bool row_in = t >= 0 && t < NZ;
         const int ddz1 = max(max(A.top - t, t - (NZ - 1 - nb)), 0);
         const float dz1 = float(ddz1 * ddz1);
@@ -844,7 +892,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                 if (prow1) lap = __builtin_fmaf(pdiv1[k], A.ih, lap);
             if (FL & F_SRC) lap = add_source<CW>(lap, wsrc1, t, S.src_i, sw0, sw1, k);
             if (FL & F_INJECT)
-                if (qi1[k] >= 0) lap += A.inj[qi1[k]];
+                if (qi1[k] >= 0) lap += iv1[k];
             const float c = cv[k] * cv[k] * A.dt2;
             float a = ax[k], sh = shx[k];
             if (ddz1 > 0) {
@@ -899,17 +947,15 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         wave_sync();
 
         int qi2[CW];
+        float iv2[CW];
 #pragma unroll
-        for (int k = 0; k < CW; ++k) qi2[k] = -1;
-        if (FL & (F_SAMPLE | F_INJECT)) {
-            if (r2 == rrow2) {
-                const int mo = A.rrows[rr2].map_off + CW * lane;
-#pragma unroll
-                for (int k = 0; k < CW; ++k) qi2[k] = A.rmap[mo + k];
-                ++rr2;
-                rrow2 = rr2 < W.rr1 ? A.rrows[rr2].row : kNoRow;
-            }
+        for (int k = 0; k < CW; ++k) {
+            qi2[k] = -1;
+            iv2[k] = 0.f;
         }
+        if (FL & (F_SAMPLE | F_INJECT))
+            if (r2 == rrow2)
+                receiver_row<CW, (FL & F_INJECT) != 0>(A, rrows, A.inj2, rr2, rrow2, W.rr1, lane, qi2, iv2);
         if (r2 >= W.z0) {   // r2 < z1 always holds
             const int ddz2 = max(max(A.top - r2, r2 - (NZ - 1 - nb)), 0);
             const float dz2 = float(ddz2 * ddz2);
@@ -947,7 +993,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                     if (prow2) lap = __builtin_fmaf(pdiv2[k], A.ih, lap);
                 if (FL & F_SRC) lap = add_source<CW>(lap, wsrc2, r2, S.src_i, sw0, sw1, k);
                 if (FL & F_INJECT)
-                    if (qi2[k] >= 0) lap += A.inj2[qi2[k]];
+                    if (qi2[k] >= 0) lap += iv2[k];
                 const float c = cq[0][k];
                 float a = ax[k], sh = shx[k];
                 if (ddz2 > 0) {
@@ -1004,20 +1050,22 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         }
     };
 
+    // the ring and loop structure of k_step
     Pre2 buf[PD + 1];
+    const int tl = t1 - 1;
 #pragma unroll
-    for (int u = 0; u < PD; ++u)
-        if (t0 + u < t1) prefetch(t0 + u, buf[u]);
-    for (int t = t0; t < t1; t += PD + 1) {
+    for (int u = 0; u < PD; ++u) prefetch(min(t0 + u, tl), buf[u]);
+    int t = t0;
+    for (; t + PD < t1; t += PD + 1) {
 #pragma unroll
         for (int u = 0; u <= PD; ++u) {
-            const int tt = t + u;
-            if (tt < t1) {
-                if (tt + PD < t1) prefetch(tt + PD, buf[(u + PD) % (PD + 1)]);
-                do_row(tt, buf[u]);
-            }
+            prefetch(min(t + u + PD, tl), buf[(u + PD) % (PD + 1)]);
+            do_row(t + u, buf[u]);
         }
     }
+#pragma unroll
+    for (int u = 0; u < PD; ++u)
+        if (t + u < t1) do_row(t + u, buf[u]);
 }
 
 // Born: background u and scattered du advanced together (section 2.2: the
@@ -1068,7 +1116,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
         shx[k] = sh;
     }
     // halo columns (byte offset shifted up by 4 columns, row offset lowered)
-    const unsigned hcol = 4u * unsigned(lane == 0 ? W.col0 : min(W.col0 + SW, P - kHalo) + kHalo);
+    const unsigned hcol =
+        lane < 2 ? 4u * unsigned(lane == 0 ? W.col0 : min(W.col0 + SW, P - kHalo) + kHalo) : kNoLoad;
 
     // perfectly matched layer: edge fields of u (psx, psz) and du (psx2, psz2)
     PmlCols<CW> pc;
@@ -1110,10 +1159,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
         bld<CW>(rcd, jl, ro + 4 * kHalo * P, nr);
         bld<CW>(rpv, jl, ro, npv);
         bld<CW>(rpd, jl, ro, npd);
-        if (lane < 2) {
-            nh = bld4(rcu, hcol, ro - 4 * kHalo);
-            nhd = bld4(rcd, hcol, ro - 4 * kHalo);
-        }
+        nh = bld4(rcu, hcol, ro - 4 * kHalo);     // zeros past lane 1
+        nhd = bld4(rcd, hcol, ro - 4 * kHalo);
         const int vo = 4 * clampi(z - A.top, 0, A.nz - 1) * A.nx;
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
@@ -1133,8 +1180,9 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
     };
     prefetch(W.z0);
 
+    const RecRowsK rrows = rec_rows(A.rrows);
     int rr = W.rr0;
-    int rrow = rr < W.rr1 ? A.rrows[rr].row : kNoRow;
+    int rrow = rr < W.rr1 ? rrows[rr].row : kNoRow;
     const float wsrc = A.wav[S.wav_off + A.n] * A.ih2;
     const int src_k = S.src_j - j0;
     float sw0[CW], sw1[CW];
@@ -1158,7 +1206,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
             cqz[k] = nqz[k];
         }
         const float4 ch = nh, chd = nhd;
-        if (z + 1 < W.z1) prefetch(z + 1);
+        prefetch(min(z + 1, W.z1 - 1));   // past the last row: that row again (unused)
 
         if constexpr (CW == 1) {
             row[kHalo + lane] = q[4][0];
@@ -1181,15 +1229,10 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_born_step(const Step
         wave_sync();
 
         int qi[CW];
+        float iv[CW];
 #pragma unroll
         for (int k = 0; k < CW; ++k) qi[k] = -1;
-        if (z == rrow) {
-            const int mo = A.rrows[rr].map_off + CW * lane;
-#pragma unroll
-            for (int k = 0; k < CW; ++k) qi[k] = A.rmap[mo + k];
-            ++rr;
-            rrow = rr < W.rr1 ? A.rrows[rr].row : kNoRow;
-        }
+        if (z == rrow) receiver_row<CW, false>(A, rrows, nullptr, rr, rrow, W.rr1, lane, qi, iv);
         const int ddz = max(max(A.top - z, z - (A.NZ - 1 - nb)), 0);
         const float dz2 = float(ddz * ddz);
         // layer terms of this row for both fields

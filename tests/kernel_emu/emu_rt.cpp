@@ -259,6 +259,13 @@ static char *emu_buf_addr(i32x4 r, int voff, int soff, size_t bytes)
     return reinterpret_cast<char *>(base + off);
 }
 
+// a raw-buffer load whose lane offset lies at or past the descriptor's range
+// returns zeros and touches no memory (the hardware's range check)
+static bool emu_buf_oob(i32x4 r, int voff, size_t bytes)
+{
+    return uint64_t(uint32_t(voff)) + bytes > uint64_t(uint32_t(r.z));
+}
+
 float emu_raw_ld_f32(i32x4 r, int voff, int soff, int aux) __asm("emu_raw_ld_f32");
 f32x2 emu_raw_ld_v2f32(i32x4 r, int voff, int soff, int aux) __asm("emu_raw_ld_v2f32");
 f32x4 emu_raw_ld_v4f32(i32x4 r, int voff, int soff, int aux) __asm("emu_raw_ld_v4f32");
@@ -267,19 +274,22 @@ void emu_raw_st_v2f32(f32x2 v, i32x4 r, int voff, int soff, int aux) __asm("emu_
 
 float emu_raw_ld_f32(i32x4 r, int voff, int soff, int aux)
 {
-    float v;
+    float v = 0.f;
+    if (emu_buf_oob(r, voff, 4)) return v;
     std::memcpy(&v, emu_buf_addr(r, voff, soff, 4), 4);
     return v;
 }
 f32x2 emu_raw_ld_v2f32(i32x4 r, int voff, int soff, int aux)
 {
-    f32x2 v;
+    f32x2 v = f32x2{0.f, 0.f};
+    if (emu_buf_oob(r, voff, 8)) return v;
     std::memcpy(&v, emu_buf_addr(r, voff, soff, 8), 8);
     return v;
 }
 f32x4 emu_raw_ld_v4f32(i32x4 r, int voff, int soff, int aux)
 {
-    f32x4 v;
+    f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (emu_buf_oob(r, voff, 16)) return v;
     std::memcpy(&v, emu_buf_addr(r, voff, soff, 16), 16);
     return v;
 }

@@ -49,6 +49,7 @@ void *emu_dyn_shared();
 #define __builtin_amdgcn_wave_barrier() emu_wave_barrier()
 #define __builtin_amdgcn_fence(a, b) ((void)0)
 #define __builtin_amdgcn_readfirstlane(x) (x)
+#define __builtin_amdgcn_s_waitcnt(x) ((void)0)
 #define __builtin_amdgcn_rcpf(x) (1.0f / (x))
 inline float cospif(float x) { return float(std::cos(3.14159265358979323846 * double(x))); }
 template <class A, class B, class C>

@@ -55,11 +55,14 @@ pytestmark = pytest.mark.skipif(not os.path.exists(CLANG), reason="ROCm clang++ 
 
 
 def _patch(src: str) -> str:
-    # bind the raw-buffer intrinsics to the emulation and route dynamic LDS
-    # through the runtime; nothing else in the sources changes
+    # bind the raw-buffer intrinsics to the emulation, route dynamic LDS
+    # through the runtime and read the constant address space as ordinary
+    # memory (which the address sanitizer checks); nothing else in the
+    # sources changes
     for kind in ("load.f32", "load.v2f32", "load.v4f32", "store.f32", "store.v2f32"):
         name = "emu_raw_" + ("st_" if kind.startswith("store") else "ld_") + kind.split(".")[1]
         src = src.replace(f"llvm.amdgcn.raw.buffer.{kind}\")", f"{name}\")")
+    src = src.replace("__attribute__((address_space(4)))", "")
     return src.replace("extern __shared__ float wl[];", "float *wl = static_cast<float *>(emu_dyn_shared());")
 
 
