@@ -206,8 +206,8 @@ int fwi_ctx_set_profiling(fwi_ctx *ctx, int enable);
 /* Tiling of the step kernels. kernel: 0 forward, 1 adjoint, 2 joint Born,
  * 3 scattered field driven by a stored history (fwi_gradient_pair), -1 all;
  * cols_per_lane 1 or 2, rows_per_wave >= 1, levels_per_launch 1 or 2 (the
- * Born and scattered-field kernels always advance one level; the joint Born
- * kernel prefetches one row) and prefetch_rows 1 or 2 (rows of loads
+ * joint Born kernel always advances one level and prefetches one row;
+ * levels 2 for it alone is FWI_EINVAL) and prefetch_rows 1 or 2 (rows of loads
  * issued ahead; 0 = 2 for one level, 1 for two) force a tiling; all zero
  * returns the kernel to the autotuner. Results do not depend on the tiling:
  * every variant computes each cell with the same arithmetic. */

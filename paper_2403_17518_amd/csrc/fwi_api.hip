@@ -108,12 +108,12 @@ struct Tiling {
     void release_all();
 };
 
-// tiling classes: forward, adjoint, joint Born, scattered field from a stored
-// history (kScatClass tilings: one level per launch)
+// tiling classes: forward, adjoint, joint Born (one level per launch),
+// scattered field from a stored history
 enum KClass { K_FWD = 0, K_ADJ = 1, K_BORN = 2, K_SCAT = 3, K_OTHER = 4 };
 constexpr int kClasses = 4;
 // classes whose kernels advance one time level per launch
-constexpr bool one_level(int k) { return k == K_BORN || k == K_SCAT; }
+constexpr bool one_level(int k) { return k == K_BORN; }
 
 // The two newest time levels of a sweep and two spare buffers. A one-level
 // launch overwrites `prev` in place; a two-level launch writes the spares.
@@ -795,6 +795,7 @@ double bytes_per_update(int flags)
 double bytes_two_levels(int flags)
 {
     if (flags & F_IMAGE) return 20.0 + 2 * kBytesEmit + 8.0;
+    if (flags & F_SCAT) return 20.0 + 2 * kBytesEmit + 4.0;   // D^n, D^{n+1} and dV in
     return 20.0 + ((flags & F_EMIT) ? 2 * kBytesEmit : 0.0);
 }
 
@@ -940,10 +941,14 @@ int step_launch(fwi_ctx *c, StepArgs a, int cls, int flags, int levels, int acti
     }
     const double cells = step_updates(p, active_n);
     const double upd = levels * cells;
-    const double bytes = levels == 2 ? cells * bytes_two_levels(flags) : cells * bytes_per_update(flags);
+    const double bytes = levels == 2 ? cells * bytes_two_levels(flags)
+                                     : cells * (cls == K_SCAT ? kBytesScat : bytes_per_update(flags));
     c->stats.cell_updates += upd;
     c->stats.stencil_launches += 1;
-    if (cls == K_ADJ) {
+    if (cls == K_SCAT) {
+        c->stats.n_born += 1;
+        c->stats.bytes_born += bytes;
+    } else if (cls == K_ADJ) {
         c->stats.n_adj += 1;
         c->stats.bytes_adj += bytes;
     } else {
@@ -1612,8 +1617,8 @@ int time_class(fwi_ctx *c, int cls, const Tiling &t, const float *v, float *ms_o
             b.dslot = nullptr;   // the Born step of a demigration (no D output)
             return launch_born_step(b, c->stream);
         }
-        if (cls == K_SCAT) return launch_step(F_SAMPLE | F_SCAT, b, c->stream);
-        return t.tb == 2 ? launch_step2(flags, b, c->stream) : launch_step(flags, b, c->stream);
+        const int fl = cls == K_SCAT ? (F_SAMPLE | F_SCAT) : flags;
+        return t.tb == 2 ? launch_step2(fl, b, c->stream) : launch_step(fl, b, c->stream);
     };
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
@@ -1924,7 +1929,7 @@ int pair_core(fwi_ctx *c, const float *v0, const float *dv, float *dd, float *im
 
 // Scattered-field steps lo .. hi-1 with the source (2 dV / V) D^n read from
 // slot n - dlo of dh (the stored background history); du^{n+1} samples to
-// samp + n*Q. One time level per launch on the Born tiling.
+// samp + n*Q. Pairs of levels per launch when the class's tiling runs two.
 int scat_range(fwi_ctx *c, const StepArgs &a, int lo, int hi, float *samp, float *dh, int dlo, Fields &f)
 {
     if (lo >= hi) return FWI_OK;
@@ -1939,28 +1944,20 @@ int scat_range(fwi_ctx *c, const StepArgs &a, int lo, int hi, float *samp, float
     key_put(key, dh);
     key_put(key, dlo);
     key_put(key, f);
+    const bool two = c->tile[K_SCAT].tb == 2;
     return run_loop(c, key, f, [&](Fields &ff) {
         StepArgs b = a;
-        for (int n = lo; n < hi; ++n) {
+        int rc;
+        for (int n = lo; n < hi;) {
+            const int levels = (two && n + 1 < hi) ? 2 : 1;
             b.n = n;
-            b.nwaves = c->tile[K_SCAT].prefix[p.active_slots(n)];
-            b.cur = ff.cur;
-            b.prev = ff.prev;
-            b.psx_in = ff.px;
-            b.psz_in = ff.pz;
-            b.psx_out = ff.qx;
-            b.psz_out = ff.qz;
+            b.n2 = n + 1;
             b.samp = samp + size_t(n) * p.Q;
+            b.samp2 = samp + size_t(n + 1) * p.Q;
             b.dslot = dh + size_t(n - dlo) * gf;
-            HIPCHK(c, launch_step(F_SAMPLE | F_SCAT, b, c->stream));
-            std::swap(ff.prev, ff.cur);
-            std::swap(ff.px, ff.qx);
-            std::swap(ff.pz, ff.qz);
-            const double upd = step_updates(p, n);
-            c->stats.cell_updates += upd;
-            c->stats.stencil_launches += 1;
-            c->stats.n_born += 1;
-            c->stats.bytes_born += upd * kBytesScat;
+            b.dslot2 = dh + size_t(n + 1 - dlo) * gf;
+            if ((rc = step_launch(c, b, K_SCAT, F_SAMPLE | F_SCAT, levels, n, ff))) return rc;
+            n += levels;
         }
         return int(FWI_OK);
     });
@@ -2142,7 +2139,7 @@ int fwi_ctx_set_tiling(fwi_ctx *c, int kernel, int cols_per_lane, int rows_per_w
                     (levels_per_launch == 1 || levels_per_launch == 2) && prefetch_rows >= 0 &&
                     prefetch_rows <= 2))
         return FWI_EINVAL;
-    // the Born and scattered-field kernels run one level per launch
+    // the joint Born kernel runs one level per launch
     if (kernel >= 0 && one_level(kernel) && levels_per_launch == 2) return FWI_EINVAL;
     for (int k = 0; k < kClasses; ++k)
         if (kernel == -1 || kernel == k) {

@@ -643,7 +643,9 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
 
 // Two time levels per launch (temporal blocking). With u^{n-1} (prev) and
 // u^n (cur) it produces u^{n+1} (out1) and u^{n+2} (out2); run backward in
-// time with the residual as source it produces lambda^n and lambda^{n-1}.
+// time with the residual as source it produces lambda^n and lambda^{n-1};
+// with F_SCAT it advances the scattered field driven by the stored D^n and
+// D^{n+1} of the background.
 // The lanes hold the owned columns plus 4 on each side; level 1 is computed
 // on all of them (and on 4 extra rows above and below the owned rows), so
 // level 2 can be computed on the owned cells without exchanging data with
@@ -697,8 +699,9 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
     const Rsrc run = view(A.cur + base), rum = view(A.prev + base), rv = view(A.v);
     const Rsrc ro1 = view(A.out1 + base), ro2 = view(A.out2 + base);
     const Rsrc rg = view((FL & F_IMAGE) ? A.G + S.g_off : A.v);
-    const Rsrc rd1 = view((FL & (F_IMAGE | F_EMIT)) ? A.dslot + S.g_off : A.v);
-    const Rsrc rd2 = view((FL & (F_IMAGE | F_EMIT)) ? A.dslot2 + S.g_off : A.v);
+    const Rsrc rd1 = view((FL & (F_IMAGE | F_EMIT | F_SCAT)) ? A.dslot + S.g_off : A.v);
+    const Rsrc rd2 = view((FL & (F_IMAGE | F_EMIT | F_SCAT)) ? A.dslot2 + S.g_off : A.v);
+    const Rsrc rdv = view((FL & F_SCAT) ? A.dv : A.v);
     const Rsrc rd1n = view_none(A.v), rd2n = rd1n, rgn = rd1n;
 
     bool inbox[CW], own[CW];
@@ -750,7 +753,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
             bld<CW>(rpzi, jl4, 4 * ((t0 - 1 + kRowsAbove) * P - kHalo), pup1_old);
     }
 
-    float qa[9][CW], qb[9][CW], cq[5][CW];
+    float qa[9][CW], qb[9][CW], cq[5][CW], crho[5][CW];
 #pragma unroll
     for (int r = 0; r < 8; ++r) bld<CW>(run, jl4, 4 * ((t0 - kHalo + r + kRowsAbove) * P - kHalo), qa[r]);
 #pragma unroll
@@ -760,12 +763,12 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 #pragma unroll
     for (int r = 0; r < 5; ++r)
 #pragma unroll
-        for (int k = 0; k < CW; ++k) cq[r][k] = 0.f;
+        for (int k = 0; k < CW; ++k) cq[r][k] = crho[r][k] = 0.f;
 
     // the loads of one level-1 row: u^n four rows below it (and its halo
     // columns), u^{n-1}, the model, and for the adjoint D and G of row t-4
     struct Pre2 {
-        float q[CW], pv[CW], v[CW], d1[CW], d2[CW], g[CW];
+        float q[CW], pv[CW], v[CW], d1[CW], d2[CW], g[CW], dv[CW];
         float px[CW], pz[CW], pxl;
         float4 h;
     };
@@ -788,6 +791,17 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
             bld_stream<CW>(own2 ? rd1 : rd1n, jc4, 4 * r2 * P, o.d1);
             bld_stream<CW>(own2 ? rd2 : rd2n, jc4, 4 * r2 * P, o.d2);
             bld<CW>(own2 ? rg : rgn, jc4, 4 * r2 * P, o.g);
+        }
+        if (FL & F_SCAT) {
+            // the scattered field's source: D^n of row t on the lane columns
+            // for level 1 (zeros on rows outside the box, where level 1 is
+            // zero), D^{n+1} of row t-4 for level 2 (owned rows), dV of row t
+            const bool in1 = t >= 0 && t < NZ;
+            bld_stream<CW>(in1 ? rd1 : rd1n, jc4, 4 * clampi(t, 0, NZ - 1) * P, o.d1);
+            const bool own2 = t - kHalo >= W.z0;
+            bld_stream<CW>(own2 ? rd2 : rd2n, jc4, 4 * max(t - kHalo, W.z0) * P, o.d2);
+#pragma unroll
+            for (int k = 0; k < CW; ++k) o.dv[k] = bld1(rdv, jm[k], vo);
         }
         if constexpr (PML) {
             if (pstrip || pml_row(A, t)) {
@@ -900,6 +914,13 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                 a = sponge_a(sh);
             }
             D1[k] = c * lap;
+            // scattered field: the linearised velocity term, as in k_step;
+            // the factor travels to level 2 with the row
+            if (FL & F_SCAT) {
+                const float rho = A.rel ? 2.0f * pf.dv[k] : 2.0f * pf.dv[k] / cv[k];
+                crho[4][k] = rho;
+                D1[k] = __builtin_fmaf(rho, pf.d1[k], D1[k]);
+            }
             float Du = D1[k];
             if constexpr (PML)
                 if (prow1) Du = __builtin_fmaf(-fdt1[k], qa[4][k], Du);
@@ -1001,6 +1022,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                     a = sponge_a(sh);
                 }
                 D2[k] = c * lap;
+                if (FL & F_SCAT) D2[k] = __builtin_fmaf(crho[0][k], pf.d2[k], D2[k]);
                 float Du = D2[k];
                 if constexpr (PML)
                     if (prow2) Du = __builtin_fmaf(-fdt2[k], qb[4][k], Du);
@@ -1038,7 +1060,10 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int k = 0; k < CW; ++k) cq[r][k] = cq[r + 1][k];
+            for (int k = 0; k < CW; ++k) {
+                cq[r][k] = cq[r + 1][k];
+                if (FL & F_SCAT) crho[r][k] = crho[r + 1][k];
+            }
         if constexpr (PML) {
 #pragma unroll
             for (int k = 0; k < CW; ++k) {
@@ -1660,6 +1685,9 @@ hipError_t launch_step2_cw(int flags, const StepArgs &a, hipStream_t s)
         break;
     case F_INJECT | F_IMAGE:
         hipLaunchKernelGGL((k_step2<F_INJECT | F_IMAGE, CW, PD, FS, PML>), grid, block, 0, s, a);
+        break;
+    case F_SAMPLE | F_SCAT:
+        hipLaunchKernelGGL((k_step2<F_SAMPLE | F_SCAT, CW, PD, FS, PML>), grid, block, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;

@@ -71,8 +71,8 @@ class FwiContext:
     def set_tiling(self, kernel: int = -1, cols_per_lane: int = 0, rows_per_wave: int = 0,
                    levels_per_launch: int = 0, prefetch_rows: int = 0):
         """Force the step-kernel tiling (kernel 0 fwd, 1 adj, 2 joint Born, 3
-        scattered field from a stored history, -1 all; the last two keep one
-        level per launch); (0, 0, 0) hands it back to the autotuner."""
+        scattered field from a stored history, -1 all; the joint Born kernel
+        keeps one level per launch); (0, 0, 0) hands it back to the autotuner."""
         _check(self.lib, self.ctx, self.lib.fwi_ctx_set_tiling(self.ctx, kernel, cols_per_lane, rows_per_wave,
                                                                levels_per_launch, prefetch_rows))
 

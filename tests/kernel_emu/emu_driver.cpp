@@ -128,7 +128,7 @@ static int run_fd(int argc, char **argv)
         }
         g.ckpt_every = ck;
         float *v0 = dev<float>(nm), *vt = dev<float>(nm), *grad = dev<float>(nm), *img = dev<float>(nm);
-        float *grad2 = dev<float>(nm), *img2 = dev<float>(nm), *img3 = dev<float>(nm);
+        float *grad2 = dev<float>(nm), *img2 = dev<float>(nm), *img3 = dev<float>(nm), *img4 = dev<float>(nm);
         float *dobs = dev<float>(size_t(ndata)), *dd = dev<float>(size_t(ndata)), *dsyn = dev<float>(size_t(ndata));
         std::memcpy(v0, hv0.data(), nm * 4);
         std::memcpy(vt, hvt.data(), nm * 4);
@@ -140,7 +140,7 @@ static int run_fd(int argc, char **argv)
             std::fprintf(stderr, "FAIL fwi_forward_noalloc differs from fwi_forward (%s)\n", spec.c_str());
             std::exit(1);
         }
-        CK(fwi_gradient_pair(c, &g, &geo, v0, dobs, grad, &phi, -1.f, img, dd));
+        CK(fwi_gradient_pair(c, &g, &geo, v0, dobs, grad, &phi, -1.f, img4, dd));
         CK(fwi_gradient(c, &g, &geo, v0, dobs, grad2, &phi, dsyn));
         CK(born_pair(c, &g, &geo, v0, grad, dd, img3));
         CK(born_demig(c, &g, &geo, v0, grad, dd));
@@ -149,8 +149,9 @@ static int run_fd(int argc, char **argv)
         fwi_stats st{};
         fwi_ctx_get_stats(c, &st);
         CK(fwi_misfit(c, &g, &geo, v0, dobs, &phi));
-        // FNV-1a over the bits of the gradients and the migrated image: the
-        // same for every checkpointing schedule
+        // FNV-1a over the bits of the gradients and the images (migration,
+        // born_pair, the fused gradient + pair): the same for every tiling
+        // and checkpointing schedule
         auto fnv = [&](const float *q) {
             uint64_t h = 1469598103934665603ULL;
             for (size_t i = 0; i < nm; ++i) {
@@ -161,12 +162,12 @@ static int run_fd(int argc, char **argv)
             return (unsigned long long)h;
         };
         std::printf("ok %s tile_fwd=%d,%d,%d,%d segments=%d slots=%d recomputed=%lld "
-                    "hash=%016llx,%016llx,%016llx,%016llx\n",
+                    "hash=%016llx,%016llx,%016llx,%016llx,%016llx\n",
                     spec.c_str(), st.tile_cw[0], st.tile_rows[0], st.tile_levels[0], st.tile_prefetch[0],
                     st.n_segments, st.ckpt_slots, (long long)st.recomputed_steps, fnv(grad), fnv(grad2), fnv(img2),
-                    fnv(img3));
+                    fnv(img3), fnv(img4));
         std::fflush(stdout);
-        for (float *p : {v0, vt, grad, img, grad2, img2, img3, dobs, dd, dsyn}) std::free(p);
+        for (float *p : {v0, vt, grad, img, grad2, img2, img3, img4, dobs, dd, dsyn}) std::free(p);
         fwi_ctx_destroy(c);
         g_ctx = nullptr;
     }
