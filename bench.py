@@ -36,13 +36,33 @@ BF16_PEAK_TFLOPS = 2500.0      # dense bf16 matrix-core peak of MI355X
 # for the kernel source it was measured on: reported as null otherwise.
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 per launch, by the tiling the
-    # class runs with: "columns per lane, levels per launch, rows prefetched"
-    # (two-level launches advance two time levels)
-    "kernels_sha1": "3b107c93de260192abef3413ee61bb5eb9b7efb9",
-    "stencil_adj": {"1,1,1": 268.5e6, "1,1,2": 267.8e6, "2,1,1": 268.2e6, "2,1,2": 268.5e6,
-                    "1,2,1": 383.9e6, "1,2,2": 376.4e6, "2,2,1": 388.6e6, "2,2,2": 367.0e6},
-    "stencil_fwd": {"1,1,1": 178.4e6, "1,1,2": 176.5e6, "2,1,1": 183.5e6, "2,1,2": 181.3e6,
-                    "1,2,1": 288.6e6, "1,2,2": 281.2e6, "2,2,1": 291.6e6, "2,2,2": 276.2e6},
+    # class runs with: "columns per lane, rows per wave, levels per launch,
+    # rows prefetched" (two-level launches advance two time levels)
+    "kernels_sha1": "2348cc1a8c726f30af90576b0b9628f85e50adf8",
+    "stencil_adj": {"1,8,1,1": 260.5e6, "1,8,1,2": 254.9e6, "1,16,1,1": 274.6e6, "1,16,1,2": 274.4e6,
+        "1,16,2,1": 433.1e6, "1,16,2,2": 438.2e6, "1,24,1,1": 265.5e6, "1,24,1,2": 266.5e6,
+        "1,24,2,1": 412.3e6, "1,24,2,2": 412.7e6, "1,32,1,1": 260.8e6, "1,32,1,2": 262.3e6,
+        "1,32,2,2": 403.9e6, "1,48,1,1": 249.5e6, "1,48,1,2": 250.9e6, "1,48,2,1": 373.5e6,
+        "1,48,2,2": 376.9e6, "1,96,2,2": 357.1e6, "2,8,1,1": 272.7e6, "2,8,1,2": 268.6e6, "2,16,1,1": 272.5e6,
+        "2,16,1,2": 273.6e6, "2,16,2,2": 421.7e6, "2,24,1,1": 261.7e6, "2,24,1,2": 263.9e6,
+        "2,24,2,1": 398.2e6, "2,24,2,2": 393.5e6, "2,32,1,1": 256.9e6, "2,32,1,2": 258.3e6,
+        "2,32,2,2": 383.8e6, "2,48,2,1": 362.0e6, "2,48,2,2": 363.6e6, "2,96,2,2": 349.9e6},
+    "stencil_fwd": {"1,8,1,1": 168.6e6, "1,8,1,2": 167.0e6, "1,16,1,1": 184.9e6, "1,16,1,2": 186.9e6,
+        "1,16,2,1": 325.8e6, "1,16,2,2": 326.1e6, "1,24,1,1": 178.8e6, "1,24,1,2": 180.7e6,
+        "1,24,2,1": 305.6e6, "1,24,2,2": 306.6e6, "1,32,1,1": 174.9e6, "1,32,1,2": 175.7e6,
+        "1,32,2,2": 297.3e6, "1,48,1,1": 170.3e6, "1,48,1,2": 170.3e6, "1,48,2,1": 277.9e6,
+        "1,48,2,2": 279.5e6, "1,96,2,2": 270.9e6, "2,8,1,1": 184.6e6, "2,8,1,2": 177.4e6, "2,16,1,1": 187.2e6,
+        "2,16,1,2": 187.7e6, "2,16,2,2": 320.2e6, "2,24,1,1": 177.7e6, "2,24,1,2": 178.0e6,
+        "2,24,2,1": 297.4e6, "2,24,2,2": 297.6e6, "2,32,1,1": 174.3e6, "2,32,1,2": 174.6e6,
+        "2,32,2,2": 286.4e6, "2,48,2,1": 271.7e6, "2,48,2,2": 271.6e6, "2,96,2,2": 263.3e6},
+    "stencil_born": {"1,8,1,1": 170.7e6, "1,8,1,2": 166.9e6, "1,16,1,1": 186.2e6, "1,16,1,2": 186.9e6,
+        "1,16,2,1": 356.3e6, "1,16,2,2": 351.0e6, "1,24,1,1": 179.7e6, "1,24,1,2": 181.7e6,
+        "1,24,2,1": 329.0e6, "1,24,2,2": 335.9e6, "1,32,1,1": 175.3e6, "1,32,1,2": 176.4e6,
+        "1,32,2,2": 312.9e6, "1,48,1,1": 170.4e6, "1,48,1,2": 170.5e6, "1,48,2,1": 289.7e6,
+        "1,48,2,2": 288.0e6, "1,96,2,2": 270.5e6, "2,8,1,1": 178.0e6, "2,8,1,2": 173.0e6, "2,16,1,1": 186.9e6,
+        "2,16,1,2": 186.6e6, "2,16,2,2": 352.4e6, "2,24,1,1": 178.6e6, "2,24,1,2": 179.7e6,
+        "2,24,2,1": 325.2e6, "2,24,2,2": 319.0e6, "2,32,1,1": 175.1e6, "2,32,1,2": 176.0e6,
+        "2,32,2,2": 307.2e6, "2,48,2,1": 282.9e6, "2,48,2,2": 281.6e6, "2,96,2,2": 268.5e6},
 }
 
 
@@ -552,7 +572,7 @@ def main():
     st = st_last
     # the step's Born-class time is the scattered-field pass (tiling class 3)
     cls = {"stencil_fwd": 0, "stencil_adj": 1, "stencil_born": 3}[dom]
-    tkey = f"{st['tile_cw'][cls]},{st['tile_levels'][cls]},{st['tile_prefetch'][cls]}"
+    tkey = f"{st['tile_cw'][cls]},{st['tile_rows'][cls]},{st['tile_levels'][cls]},{st['tile_prefetch'][cls]}"
     table, own = bytes_per_update({"stencil_fwd": "fwd", "stencil_adj": "adj", "stencil_born": "born"}[dom],
                                   st["tile_levels"][cls] or 1)
     achieved = achieved_own * table / own

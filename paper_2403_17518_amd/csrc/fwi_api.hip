@@ -1550,12 +1550,14 @@ struct Candidate {
 };
 // one level per launch: short row runs keep many waves in flight, a deeper
 // prefetch more bytes per wave; two levels per launch recompute 4 rows above
-// and below each run, so runs are longer
+// and below each run, so runs are longer (short runs still pay where a grid
+// holds few waves)
 const Candidate kTune[] = {
     {1, 8, 1, 1},  {1, 16, 1, 1}, {1, 24, 1, 1}, {1, 32, 1, 1}, {1, 48, 1, 1}, {2, 8, 1, 1},  {2, 16, 1, 1},
     {2, 24, 1, 1}, {2, 32, 1, 1}, {1, 8, 1, 2},  {1, 16, 1, 2}, {1, 24, 1, 2}, {1, 32, 1, 2}, {1, 48, 1, 2},
     {2, 8, 1, 2},  {2, 16, 1, 2}, {2, 24, 1, 2}, {2, 32, 1, 2}, {1, 24, 2, 1}, {1, 48, 2, 1}, {2, 24, 2, 1},
-    {2, 48, 2, 1}, {1, 24, 2, 2}, {1, 48, 2, 2}, {1, 96, 2, 2}, {2, 24, 2, 2}, {2, 48, 2, 2}, {2, 96, 2, 2}};
+    {2, 48, 2, 1}, {1, 24, 2, 2}, {1, 48, 2, 2}, {1, 96, 2, 2}, {2, 24, 2, 2}, {2, 48, 2, 2}, {2, 96, 2, 2},
+    {1, 16, 2, 1}, {1, 16, 2, 2}, {2, 16, 2, 2}, {1, 32, 2, 2}, {2, 32, 2, 2}};
 
 constexpr int kTuneLaunches = 10;   // timed launches per candidate and pass
 constexpr int kTunePasses = 2;      // passes over the list; the best time counts

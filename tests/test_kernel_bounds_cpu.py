@@ -46,6 +46,7 @@ TILINGS = [
     "2,24,1,1,0", "2,32,1,1,0", "1,8,1,2,0", "1,16,1,2,0", "1,24,1,2,0", "1,32,1,2,0", "1,48,1,2,0",
     "2,8,1,2,0", "2,16,1,2,0", "2,24,1,2,0", "2,32,1,2,0", "1,24,2,1,0", "1,48,2,1,0", "2,24,2,1,0",
     "2,48,2,1,0", "1,24,2,2,0", "1,48,2,2,0", "1,96,2,2,0", "2,24,2,2,0", "2,48,2,2,0", "2,96,2,2,0",
+    "1,16,2,1,0", "1,16,2,2,0", "2,16,2,2,0", "1,32,2,2,0", "2,32,2,2,0",
     "1,24,1,1,3", "2,16,1,2,3", "1,24,2,1,3", "2,48,2,1,2", "2,24,2,2,3", "auto",
     # binomial checkpointing: a snapshot cap below the uniform schedule's
     "1,24,1,1,1,1", "2,16,1,2,2,0", "1,24,2,1,1,2",
