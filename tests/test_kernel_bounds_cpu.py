@@ -21,6 +21,7 @@ kernels, split K and the direct input-layer kernels.
 from __future__ import annotations
 
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -64,7 +65,7 @@ def _patch(src: str) -> str:
         name = "emu_raw_" + ("st_" if kind.startswith("store") else "ld_") + kind.split(".")[1]
         src = src.replace(f"llvm.amdgcn.raw.buffer.{kind}\")", f"{name}\")")
     src = src.replace("__attribute__((address_space(4)))", "")
-    return src.replace("extern __shared__ float wl[];", "float *wl = static_cast<float *>(emu_dyn_shared());")
+    return re.sub(r"extern __shared__ float (\w+)\[\];", r"float *\1 = static_cast<float *>(emu_dyn_shared());", src)
 
 
 @pytest.fixture(scope="module")
