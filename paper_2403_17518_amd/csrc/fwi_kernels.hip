@@ -124,10 +124,9 @@ __device__ __forceinline__ void ld(const float *p, float (&o)[CW])
 // and a fixed per-lane byte offset (one vector register), so streaming a row
 // costs no vector address arithmetic. Range checking is left wide open:
 // every offset used is in bounds by construction, except on purpose: a load
-// whose lane offset lies past the range (kNoLoad), or made through a view
-// of range zero (view_none), returns zeros without a memory request. Loads
-// that a lane or a row does not need are made that way instead of being
-// skipped, so that no load sits in a branch. The loads and stores are the
+// whose lane offset lies past the range (kNoLoad) returns zeros without a
+// memory request. Loads that a lane or a row does not need are made that way
+// instead of being skipped, so that no load sits in a branch. The loads and stores are the
 // raw-buffer intrinsics of the AMDGPU backend, bound by name.
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -149,13 +148,6 @@ __device__ __forceinline__ Rsrc view(const float *base)
     r.y = int(unsigned(a >> 32) & 0xffffu);   // stride 0
     r.z = 0x7fffffff;                        // byte range
     r.w = kRsrcWord3;
-    return r;
-}
-
-__device__ __forceinline__ Rsrc view_none(const float *base)
-{
-    Rsrc r = view(base);
-    r.z = 0;
     return r;
 }
 
@@ -702,7 +694,6 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
     const Rsrc rd1 = view((FL & (F_IMAGE | F_EMIT | F_SCAT)) ? A.dslot + S.g_off : A.v);
     const Rsrc rd2 = view((FL & (F_IMAGE | F_EMIT | F_SCAT)) ? A.dslot2 + S.g_off : A.v);
     const Rsrc rdv = view((FL & F_SCAT) ? A.dv : A.v);
-    const Rsrc rd1n = view_none(A.v), rd2n = rd1n, rgn = rd1n;
 
     bool inbox[CW], own[CW];
     unsigned jm[CW];
@@ -783,23 +774,21 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         for (int k = 0; k < CW; ++k) o.v[k] = bld1(rv, jm[k], vo);
         if (FL & F_IMAGE) {
             // the imaging terms of both levels are added at level 2 (row t-4,
-            // always below z1); before the first owned row they are loaded
-            // through views of range zero (zeros, no memory request), so that
+            // always below z1); before the first owned row the loads take a
+            // lane offset past the range (zeros, no memory request), so that
             // they sit in no branch
-            const bool own2 = t - kHalo >= W.z0;
+            const unsigned jo = t - kHalo >= W.z0 ? jc4 : kNoLoad;
             const int r2 = max(t - kHalo, W.z0);
-            bld_stream<CW>(own2 ? rd1 : rd1n, jc4, 4 * r2 * P, o.d1);
-            bld_stream<CW>(own2 ? rd2 : rd2n, jc4, 4 * r2 * P, o.d2);
-            bld<CW>(own2 ? rg : rgn, jc4, 4 * r2 * P, o.g);
+            bld_stream<CW>(rd1, jo, 4 * r2 * P, o.d1);
+            bld_stream<CW>(rd2, jo, 4 * r2 * P, o.d2);
+            bld<CW>(rg, jo, 4 * r2 * P, o.g);
         }
         if (FL & F_SCAT) {
             // the scattered field's source: D^n of row t on the lane columns
             // for level 1 (zeros on rows outside the box, where level 1 is
             // zero), D^{n+1} of row t-4 for level 2 (owned rows), dV of row t
-            const bool in1 = t >= 0 && t < NZ;
-            bld_stream<CW>(in1 ? rd1 : rd1n, jc4, 4 * clampi(t, 0, NZ - 1) * P, o.d1);
-            const bool own2 = t - kHalo >= W.z0;
-            bld_stream<CW>(own2 ? rd2 : rd2n, jc4, 4 * max(t - kHalo, W.z0) * P, o.d2);
+            bld_stream<CW>(rd1, t >= 0 && t < NZ ? jc4 : kNoLoad, 4 * clampi(t, 0, NZ - 1) * P, o.d1);
+            bld_stream<CW>(rd2, t - kHalo >= W.z0 ? jc4 : kNoLoad, 4 * max(t - kHalo, W.z0) * P, o.d2);
 #pragma unroll
             for (int k = 0; k < CW; ++k) o.dv[k] = bld1(rdv, jm[k], vo);
         }
