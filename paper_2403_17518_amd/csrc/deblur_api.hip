@@ -215,14 +215,18 @@ void build_layout(deblur_net *n)
 // output tile, pixels per split and split count of a weight-gradient
 // reduction: the tile's height follows M (32, 64 or 128 rows), its width is
 // 128 unless N is narrower; pixel splits (at least 256 pixels each) fill the
-// GPU up to 512 workgroups
+// GPU up to its resident workgroups
 void wsplit(int M, int N, int P, int *nsplit, int *chunk, int *bm, int *bn)
 {
     int tm = M <= 32 ? 32 : (M <= 64 ? 64 : 128);
     int tn = 128;
     if (N <= 64 || (tm == 64 && N < 128)) tm = 64, tn = 64;
     const int tiles = ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
-    int ns = std::max(1, std::min((512 + tiles - 1) / tiles, std::max(1, P / 256)));
+    // as many pixel splits as keep the grid within one round of resident
+    // workgroups (two per CU for the 128-, 64- and 32-row tiles, four for 64 x
+    // 64): a grid just past it leaves a second round of a few workgroups
+    const int cap = tm == 64 && tn == 64 ? 1024 : 512;
+    int ns = std::max(1, std::min(cap / tiles, std::max(1, P / 256)));
     int ch = (P + ns - 1) / ns;
     ch = ((ch + 63) / 64) * 64;
     ns = (P + ch - 1) / ch;
