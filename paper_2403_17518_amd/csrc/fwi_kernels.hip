@@ -125,8 +125,11 @@ __device__ __forceinline__ void ld(const float *p, float (&o)[CW])
 // costs no vector address arithmetic. Range checking is left wide open:
 // every offset used is in bounds by construction, except on purpose: a load
 // whose lane offset lies past the range (kNoLoad) returns zeros without a
-// memory request. Loads that a lane or a row does not need are made that way
-// instead of being skipped, so that no load sits in a branch. The loads and stores are the
+// memory request, and such a store is dropped. Loads that a lane or a row
+// does not need are made that way instead of being skipped, so that no load
+// sits in a branch; the step kernels store their columns that way too (lanes
+// past the shot's width, columns a two-level wave does not own), without a
+// per-lane branch. The loads and stores are the
 // raw-buffer intrinsics of the AMDGPU backend, bound by name.
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -415,12 +418,15 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
     const Rsrc rdv = view((FL & F_SCAT) ? A.dv : A.v);
 
     bool valid[CW];
-    unsigned jm[CW];
+    unsigned jm[CW], jsv[CW];
     float dx2[CW], ax[CW], shx[CW];
 #pragma unroll
     for (int k = 0; k < CW; ++k) {
         const int j = j0 + k;
         valid[k] = j < S.NX;
+        // store offset of the column: past the range (stores dropped) when the
+        // column lies past the shot's width, so that no store sits in a branch
+        jsv[k] = valid[k] ? 4u * unsigned(j) : kNoLoad;
         jm[k] = 4u * unsigned(S.x0 + clampi(j - nb, 0, S.wnx - 1));
         const int ddx = max(max(nb - j, j - (S.NX - 1 - nb)), 0);
         dx2[k] = float(ddx * ddx);
@@ -586,23 +592,20 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step(const StepArgs 
         if constexpr (PML) {
             if (prow) {
 #pragma unroll
-                for (int k = 0; k < CW; ++k)
-                    if (valid[k]) {
-                        bst1(rpxo, js + 4 * k, ro, pnx[k]);
-                        bst1(rpzo, js + 4 * k, ro, pnz[k]);
-                    }
+                for (int k = 0; k < CW; ++k) {
+                    bst1(rpxo, jsv[k], ro, pnx[k]);
+                    bst1(rpzo, jsv[k], ro, pnz[k]);
+                }
             }
         }
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
-            if (valid[k]) {
-                bst1(rprev, js + 4 * k, ro, out[k]);
-                if (FL & F_IMAGE) bst1(rg, js + 4 * k, go, __builtin_fmaf(out[k], c.d[k], c.g[k]));
-                if (FL & F_SAMPLE)
-                    if (qi[k] >= 0) A.samp[qi[k]] = out[k];
-                // odd mirror above the free surface: rows -1..-4 of the new level
-                if (A.fs && z >= 1 && z <= kHalo) bst1(rprev, js + 4 * k, 4 * (kRowsAbove - z) * P, -out[k]);
-            }
+            bst1(rprev, jsv[k], ro, out[k]);
+            if (FL & F_IMAGE) bst1(rg, jsv[k], go, __builtin_fmaf(out[k], c.d[k], c.g[k]));
+            if (FL & F_SAMPLE)
+                if (valid[k] && qi[k] >= 0) A.samp[qi[k]] = out[k];
+            // odd mirror above the free surface: rows -1..-4 of the new level
+            if (A.fs && z >= 1 && z <= kHalo) bst1(rprev, jsv[k], 4 * (kRowsAbove - z) * P, -out[k]);
         }
 #pragma unroll
         for (int r = 0; r < 8; ++r)
@@ -696,6 +699,7 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
     const Rsrc rdv = view((FL & F_SCAT) ? A.dv : A.v);
 
     bool inbox[CW], own[CW];
+    unsigned jso[CW];
     unsigned jm[CW];
     float dx2[CW], ax[CW], shx[CW];
 #pragma unroll
@@ -703,6 +707,8 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
         const int j = j0 + k;
         inbox[k] = j >= 0 && j < S.NX;
         own[k] = j >= W.col0 && j < own_hi;
+        // store offset of the column: past the range (stores dropped) unless owned
+        jso[k] = own[k] ? 4u * unsigned(j) : kNoLoad;
         jm[k] = 4u * unsigned(S.x0 + clampi(j - nb, 0, S.wnx - 1));
         const int ddx = max(max(nb - j, j - (S.NX - 1 - nb)), 0);
         dx2[k] = float(ddx * ddx);
@@ -937,12 +943,10 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
             if (FL & F_EMIT) bst_stream<CW>(rd1, js4, 4 * t * P, D1, own);
 #pragma unroll
             for (int k = 0; k < CW; ++k) {
-                if (own[k]) {
-                    bst1(ro1, js4 + 4 * k, o, v1[k]);
-                    if (FL & F_SAMPLE)
-                        if (qi1[k] >= 0) A.samp[qi1[k]] = v1[k];
-                    if (FS && t >= 1 && t <= kHalo) bst1(ro1, js4 + 4 * k, 4 * (kRowsAbove - t) * P, -v1[k]);
-                }
+                bst1(ro1, jso[k], o, v1[k]);
+                if (FS && t >= 1 && t <= kHalo) bst1(ro1, jso[k], 4 * (kRowsAbove - t) * P, -v1[k]);
+                if (FL & F_SAMPLE)
+                    if (own[k] && qi1[k] >= 0) A.samp[qi1[k]] = v1[k];
             }
         }
 
@@ -1017,23 +1021,21 @@ __global__ __launch_bounds__(kLanes *kWavesPerBlock) void k_step2(const StepArgs
                     if (prow2) Du = __builtin_fmaf(-fdt2[k], qb[4][k], Du);
                 float v2 = leapfrog(qb[4][k], qa[0][k], Du, a, sh);
                 if (FS && r2 == 0) v2 = 0.0f;   // the pressure-free surface
-                if (own[k]) {
-                    bst1(ro2, js4 + 4 * k, o, v2);
-                    if constexpr (PML) {
-                        if (prow2) {
-                            bst1(rpxo, js4 + 4 * k, o, pnx2[k]);
-                            bst1(rpzo, js4 + 4 * k, o, pnz2[k]);
-                        }
+                bst1(ro2, jso[k], o, v2);
+                if constexpr (PML) {
+                    if (prow2) {
+                        bst1(rpxo, jso[k], o, pnx2[k]);
+                        bst1(rpzo, jso[k], o, pnz2[k]);
                     }
-                    if (FS && r2 >= 1 && r2 <= kHalo) bst1(ro2, js4 + 4 * k, 4 * (kRowsAbove - r2) * P, -v2);
-                    if (FL & F_SAMPLE)
-                        if (lvl2_ok && qi2[k] >= 0) A.samp2[qi2[k]] = v2;
-                    // G after both levels: the fused multiply-adds of two one-level
-                    // steps, in their order (qb[4] is the level-1 value of this row)
-                    if (FL & F_IMAGE) {
-                        const float g1 = lvl1_ok ? __builtin_fmaf(qb[4][k], cd1[k], cg[k]) : cg[k];
-                        bst1(rg, js4 + 4 * k, 4 * r2 * P, __builtin_fmaf(v2, cd2[k], g1));
-                    }
+                }
+                if (FS && r2 >= 1 && r2 <= kHalo) bst1(ro2, jso[k], 4 * (kRowsAbove - r2) * P, -v2);
+                if (FL & F_SAMPLE)
+                    if (own[k] && lvl2_ok && qi2[k] >= 0) A.samp2[qi2[k]] = v2;
+                // G after both levels: the fused multiply-adds of two one-level
+                // steps, in their order (qb[4] is the level-1 value of this row)
+                if (FL & F_IMAGE) {
+                    const float g1 = lvl1_ok ? __builtin_fmaf(qb[4][k], cd1[k], cg[k]) : cg[k];
+                    bst1(rg, jso[k], 4 * r2 * P, __builtin_fmaf(v2, cd2[k], g1));
                 }
             }
             if (FL & F_EMIT)

@@ -259,8 +259,9 @@ static char *emu_buf_addr(i32x4 r, int voff, int soff, size_t bytes)
     return reinterpret_cast<char *>(base + off);
 }
 
-// a raw-buffer load whose lane offset lies at or past the descriptor's range
-// returns zeros and touches no memory (the hardware's range check)
+// a raw-buffer access whose lane offset lies at or past the descriptor's
+// range touches no memory: a load returns zeros, a store is dropped (the
+// hardware's range check)
 static bool emu_buf_oob(i32x4 r, int voff, size_t bytes)
 {
     return uint64_t(uint32_t(voff)) + bytes > uint64_t(uint32_t(r.z));
@@ -295,10 +296,12 @@ f32x4 emu_raw_ld_v4f32(i32x4 r, int voff, int soff, int aux)
 }
 void emu_raw_st_f32(float v, i32x4 r, int voff, int soff, int aux)
 {
+    if (emu_buf_oob(r, voff, 4)) return;   // dropped, as the hardware drops it
     std::memcpy(emu_buf_addr(r, voff, soff, 4), &v, 4);
 }
 void emu_raw_st_v2f32(f32x2 v, i32x4 r, int voff, int soff, int aux)
 {
+    if (emu_buf_oob(r, voff, 8)) return;
     std::memcpy(emu_buf_addr(r, voff, soff, 8), &v, 8);
 }
 
